@@ -1,0 +1,254 @@
+"""Seeded synthetic inputs: array geometries, candidate grids and multichannel
+STFT frames.
+
+This module generates the inputs of the SRP-map hot path and holds none of
+its arithmetic (no cross-spectra, steering, sampling or interpolation).  Both
+the HIP path and the FP64 oracle consume what it produces.
+
+The paper evaluates on speech, babble noise and simulated or measured room
+impulse responses (Sec. V), none of which ship here.  The scenes below are
+synthetic stand-ins with the paper's structure: a band-limited coloured
+source, free-field or image-source propagation with exact fractional delays
+and 1/(4 pi r) spreading, sensor or diffuse noise at a stated SNR, and an
+STFT with hop N/2 (Sec. V-B1).
+
+All randomness comes from numpy.random.default_rng(2306085140 + index) in a
+fixed draw order, so every consumer sees bit-identical frames.
+"""
+
+import numpy as np
+
+SEED_BASE = 2306085140
+C_SOUND = 343.0
+
+
+# --------------------------------------------------------------- geometry --
+
+def uca(M, diameter, center=(0.0, 0.0, 0.0)):
+    """Uniform circular array in a horizontal plane, quoted by diameter."""
+    a = 2.0 * np.pi * np.arange(M) / M
+    c = np.asarray(center, dtype=np.float64)
+    return np.stack([c[0] + diameter / 2 * np.cos(a),
+                     c[1] + diameter / 2 * np.sin(a),
+                     np.full(M, c[2])], axis=1)
+
+
+def square_array(half=0.1):
+    """Four microphones on a square in the plane z = 0, in the order
+    (-,-), (+,-), (+,+), (-,+)."""
+    return np.array([[-half, -half, 0.0], [half, -half, 0.0],
+                     [half, half, 0.0], [-half, half, 0.0]])
+
+
+def random_disc_array(rng, M, radius, z, min_spacing):
+    """M microphones uniform in a horizontal disc, rejection-sampled so that
+    no two are closer than min_spacing."""
+    pts = []
+    while len(pts) < M:
+        r = radius * np.sqrt(rng.uniform())
+        a = rng.uniform(0, 2 * np.pi)
+        p = np.array([r * np.cos(a), r * np.sin(a), z])
+        if all(np.linalg.norm(p - q) >= min_spacing for q in pts):
+            pts.append(p)
+    return np.array(pts)
+
+
+def box_grid(xs, ys, zs):
+    """Cartesian candidate grid, x-major, z-minor (inclusive linspaces)."""
+    X, Y, Z = np.meshgrid(xs, ys, zs, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+# ---------------------------------------------------------------- signals --
+
+def one_over_f_noise(rng, n, pole=0.95):
+    """White Gaussian noise through the one-pole filter s[n] = a s[n-1] + w[n]."""
+    w = rng.standard_normal(n)
+    # closed-form IIR by FFT-free recursion in blocks would be faster; lfilter
+    # from scipy is fine and deterministic
+    from scipy.signal import lfilter
+    return lfilter([1.0], [1.0, -pole], w)
+
+
+def _delay_sum(spec, nfft, delays, gains):
+    """Sum of delayed, scaled copies of a signal given by its rfft spectrum:
+    sum_i g_i s(t - tau_i), delays in samples, by a phase shift."""
+    w = 2.0 * np.pi * np.arange(nfft // 2 + 1) / nfft
+    acc = np.zeros_like(spec)
+    for d, g in zip(delays, gains):
+        acc += g * np.exp(-1j * w * d)
+    return np.fft.irfft(spec * acc, n=nfft)
+
+
+def image_sources(src, room, max_order, beta):
+    """Image sources of a shoebox [0, room] up to total reflection order
+    max_order, each with amplitude beta^(reflections)."""
+    out = []
+    opts = []
+    for ax in range(3):
+        L = room[ax]
+        x = src[ax]
+        # (coordinate, reflection count) for n in {-1, 0, 1}
+        axis_opts = []
+        for n in (-1, 0, 1):
+            axis_opts.append((2 * n * L + x, abs(2 * n)))
+            axis_opts.append((2 * n * L - x, abs(2 * n - 1)))
+        opts.append([o for o in axis_opts if o[1] <= max_order])
+    for ox in opts[0]:
+        for oy in opts[1]:
+            for oz in opts[2]:
+                order = ox[1] + oy[1] + oz[1]
+                if order <= max_order:
+                    out.append((np.array([ox[0], oy[0], oz[0]]), beta ** order))
+    return out
+
+
+def stft_frames(x, N, hop, L):
+    """STFT with a periodic Hann window of length N and the given hop.
+    x: [M, T] real.  Returns complex128 [L, M, N/2 + 1]."""
+    n = np.arange(N)
+    win = 0.5 - 0.5 * np.cos(2.0 * np.pi * n / N)
+    M = x.shape[0]
+    out = np.empty((L, M, N // 2 + 1), dtype=np.complex128)
+    for l in range(L):
+        seg = x[:, l * hop:l * hop + N] * win[None, :]
+        out[l] = np.fft.rfft(seg, axis=1)
+    return out
+
+
+def _scale_to_snr(sig, noise, snr_db):
+    ps = np.mean(np.var(sig, axis=1))
+    pn = np.mean(np.var(noise, axis=1))
+    return noise * np.sqrt(ps / (pn * 10.0 ** (snr_db / 10.0)))
+
+
+def render(rng, mics, sources, fs, T, snr_db, noise="white", room=None,
+           max_order=0, beta=0.7, n_diffuse=64, c=C_SOUND):
+    """Microphone signals [M, T] for independent 1/f sources at the given
+    positions, with exact fractional delays, 1/(4 pi r) spreading, optional
+    image sources, and white sensor or diffuse noise at snr_db."""
+    M = mics.shape[0]
+    paths = []
+    for s in sources:
+        if max_order > 0:
+            paths.append(image_sources(s, room, max_order, beta))
+        else:
+            paths.append([(np.asarray(s, dtype=np.float64), 1.0)])
+    maxdist = max(np.linalg.norm(p - m) for ps in paths for (p, _) in ps for m in mics)
+    dmax = int(np.ceil(maxdist / c * fs)) + 2
+    nfft = 1 << int(np.ceil(np.log2(T + dmax + 1)))
+    sig = np.zeros((M, T))
+    for ps in paths:
+        spec = np.fft.rfft(one_over_f_noise(rng, nfft))
+        for m in range(M):
+            dl = [np.linalg.norm(p - mics[m]) / c * fs for (p, _) in ps]
+            gl = [g / (4 * np.pi * np.linalg.norm(p - mics[m])) for (p, g) in ps]
+            sig[m] = _delay_sum(spec, nfft, dl, gl)[dmax:dmax + T]
+    if noise == "white":
+        nz = rng.standard_normal((M, T))
+    elif noise == "diffuse":
+        # independent 1/f plane waves from directions uniform on the sphere
+        v = rng.standard_normal((n_diffuse, 3))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        nz_full = np.zeros((M, nfft // 2 + 1), dtype=np.complex128)
+        w = 2.0 * np.pi * np.arange(nfft // 2 + 1) / nfft
+        ctr = mics.mean(0)
+        for i in range(n_diffuse):
+            spec = np.fft.rfft(one_over_f_noise(rng, nfft))
+            for m in range(M):
+                # a plane wave arriving from direction v reaches a microphone
+                # displaced towards v earlier
+                d = -((mics[m] - ctr) @ v[i]) / c * fs + dmax / 2
+                nz_full[m] += spec * np.exp(-1j * w * d)
+        nz = np.fft.irfft(nz_full, n=nfft, axis=1)[:, dmax:dmax + T]
+    else:
+        raise ValueError(noise)
+    return sig + _scale_to_snr(sig, nz, snr_db)
+
+
+# --------------------------------------------------------------- configs --
+
+def _n_samples(L, N, hop):
+    return (L - 1) * hop + N
+
+
+def config(index, L=None, grid_stride=1):
+    """Geometry and sizes of the benchmark configurations (0-based index):
+
+    0: M = 4 square (0.2 m) in z = 0; planar 32 x 32 grid over [-2, 2]^2;
+       fs 16 kHz, N = 512, L = 100; one free-field source in the plane at
+       >= 0.5 m from the centre; white sensor noise at 10 dB.
+    1: M = 8 UCA, diameter 0.3 m, ceiling-mounted at (2.5, 2.5, 2.4) in a
+       5 x 5 x 2.5 m room; 50 x 50 x 50 grid over the room (J = 125,000);
+       fs 16 kHz, N = 1024, L = 1000; one source >= 0.5 m from walls and
+       array, z <= 2.0; image sources of order <= 2 with wall reflection
+       0.7; diffuse 1/f noise at 5 dB.
+    2: the frames and geometry of 0 (precision sweep).
+    3: M = 32 uniform in a disc of radius 1 m at z = 3.0 (>= 5 cm spacing);
+       100 x 100 x 20 grid over [-5, 5]^2 x [0.5, 2.5] (J = 200,000);
+       fs 48 kHz, N = 2048, L = 256; two free-field sources in the grid box;
+       white sensor noise at 10 dB.
+
+    Returns a dict with mics, grid, fs, N, hop, L, c and the drawing recipe;
+    frames are produced by make_frames().  grid_stride subsamples every grid
+    axis (for small test cases)."""
+    rng = np.random.default_rng(SEED_BASE + index)
+    if index in (0, 2):
+        rng = np.random.default_rng(SEED_BASE + 0)
+        mics = square_array(0.1)
+        g = np.linspace(-2.0, 2.0, 32)[::grid_stride]
+        grid = box_grid(g, g, np.array([0.0]))
+        while True:
+            s = np.array([rng.uniform(-2, 2), rng.uniform(-2, 2), 0.0])
+            if np.linalg.norm(s) >= 0.5:
+                break
+        cfg = dict(mics=mics, grid=grid, fs=16000.0, N=512, hop=256, L=L or 100,
+                   sources=[s], snr_db=10.0, noise="white", room=None, max_order=0)
+    elif index == 1:
+        mics = uca(8, 0.3, (2.5, 2.5, 2.4))
+        gx = np.linspace(0.0, 5.0, 50)[::grid_stride]
+        gz = np.linspace(0.0, 2.5, 50)[::grid_stride]
+        grid = box_grid(gx, gx, gz)
+        room = np.array([5.0, 5.0, 2.5])
+        while True:
+            s = rng.uniform([0.5, 0.5, 0.5], [4.5, 4.5, 2.0])
+            if np.min(np.linalg.norm(mics - s, axis=1)) >= 0.5:
+                break
+        cfg = dict(mics=mics, grid=grid, fs=16000.0, N=1024, hop=512, L=L or 1000,
+                   sources=[s], snr_db=5.0, noise="diffuse", room=room, max_order=2)
+    elif index == 3:
+        mics = random_disc_array(rng, 32, 1.0, 3.0, 0.05)
+        gx = np.linspace(-5.0, 5.0, 100)[::grid_stride]
+        gz = np.linspace(0.5, 2.5, 20)[::grid_stride]
+        grid = box_grid(gx, gx, gz)
+        srcs = [rng.uniform([-5, -5, 0.5], [5, 5, 2.5]) for _ in range(2)]
+        cfg = dict(mics=mics, grid=grid, fs=48000.0, N=2048, hop=1024, L=L or 256,
+                   sources=srcs, snr_db=10.0, noise="white", room=None, max_order=0)
+    else:
+        raise ValueError(f"no configuration {index}")
+    cfg["c"] = C_SOUND
+    cfg["index"] = index
+    cfg["_rng"] = rng
+    return cfg
+
+
+def make_frames(cfg):
+    """Render the configuration's signals and return complex64 STFT frames
+    [L, M, N/2 + 1] (computed in FP64, then rounded once)."""
+    rng = cfg["_rng"]
+    T = _n_samples(cfg["L"], cfg["N"], cfg["hop"])
+    x = render(rng, cfg["mics"], cfg["sources"], cfg["fs"], T, cfg["snr_db"],
+               noise=cfg["noise"], room=cfg["room"], max_order=cfg["max_order"],
+               c=cfg["c"])
+    return stft_frames(x, cfg["N"], cfg["hop"], cfg["L"]).astype(np.complex64)
+
+
+def random_frames(seed, L, M, N, zero_fraction=0.0):
+    """Unstructured complex64 frames [L, M, N/2 + 1] (unit-variance complex
+    Gaussian), optionally with a fraction of exact zeros, for edge-case
+    tests."""
+    rng = np.random.default_rng(SEED_BASE + 1000 + seed)
+    Y = (rng.standard_normal((L, M, N // 2 + 1)) + 1j * rng.standard_normal((L, M, N // 2 + 1)))
+    if zero_fraction > 0:
+        Y[rng.uniform(size=Y.shape) < zero_fraction] = 0.0
+    return Y.astype(np.complex64)

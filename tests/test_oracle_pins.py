@@ -1,0 +1,418 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks an oracle function against something other than itself:
+values the paper prints (Table 1, Fig. 12, Sec. V-B1), closed forms derived
+from the paper's definitions, brute force, or textbook identities.  A
+plausible mistake (a dropped factor 2, a flipped sign, a transposed index, a
+wrong lag order) fails at least one of them.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle as o
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_table(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append(line.split())
+    return rows
+
+
+def _uca(M, diameter, z=0.0):
+    a = 2 * np.pi * np.arange(M) / M
+    return np.stack([diameter / 2 * np.cos(a), diameter / 2 * np.sin(a), np.full(M, z)], 1)
+
+
+NF_CORNERS = np.array([[0.4, 0.4, 3.0], [0.4, 5.4, 3.0], [4.4, 5.4, 3.0], [4.4, 0.4, 3.0]])
+
+
+def _measured_array():
+    xy = np.array([[float(v) for v in r] for r in _read_table("paper_measured_array.txt")])
+    return np.concatenate([xy, np.zeros((len(xy), 1))], 1)
+
+
+def _random_frames(rng, L, M, K):
+    return rng.standard_normal((L, M, K + 1)) + 1j * rng.standard_normal((L, M, K + 1))
+
+
+# ---------------------------------------------------------------- P1 TDOA ---
+
+def test_tdoa_pair_relation_antisymmetry_and_range():
+    """Delta t_{m,m'} = Delta t_{m,1} - Delta t_{m',1} (used for (8)); swapping
+    the microphones flips the sign; |Delta t_p| <= d_p / c (4), with equality
+    for candidates on the microphones' line outside the segment."""
+    rng = np.random.default_rng(1)
+    mics = rng.uniform(-1, 1, (5, 3))
+    grid = rng.uniform(-3, 3, (200, 3))
+    fs, c = 16000.0, 343.0
+    x = o.tdoa_samples(mics, grid, fs, c)
+    dist = np.linalg.norm(grid[None] - mics[:, None], axis=-1)
+    x1 = (dist - dist[0]) * fs / c          # relative to microphone 1
+    for p, (m, mp) in enumerate(o.pairs(5)):
+        np.testing.assert_allclose(x[p], x1[m] - x1[mp], atol=1e-12)
+        d = np.linalg.norm(mics[m] - mics[mp]) * fs / c
+        assert np.all(np.abs(x[p]) <= d + 1e-9)
+    swapped = o.tdoa_samples(mics[::-1], grid, fs, c)
+    # pair (m, m') of the reversed array is (M-1-m, M-1-m') of the original
+    for p, (m, mp) in enumerate(o.pairs(5)):
+        q = o.pairs(5).index((4 - mp, 4 - m))
+        np.testing.assert_allclose(swapped[p], -x[q], atol=1e-12)
+    # collinear candidate beyond microphone m' of pair 0 -> x = -d (closer to m')
+    m, mp = o.pairs(5)[0]
+    far = mics[mp] + 2.5 * (mics[mp] - mics[m])
+    xc = o.tdoa_samples(mics, far[None], fs, c)[0, 0]
+    np.testing.assert_allclose(xc, np.linalg.norm(mics[m] - mics[mp]) * fs / c, rtol=1e-12)
+
+
+def test_pair_order_is_sum_order_of_eq8():
+    assert o.pairs(4) == [(1, 0), (2, 0), (3, 0), (2, 1), (3, 1), (3, 2)]
+    assert len(o.pairs(32)) == 496
+
+
+# -------------------------------------------------------- P2 lag counts ----
+
+@pytest.mark.parametrize("row", _read_table("paper_lag_counts.txt"))
+def test_mean_lags_match_table1(row):
+    """N printed in Table 1 / Sec. V-B1 follows from (33) and (35)."""
+    name, fs, c, n_aux, printed = row
+    if name == "nf_corners":
+        mics = NF_CORNERS
+    else:
+        mics = _uca(6, float(name.split("_d")[1]))
+    Np = o.max_lags(mics, float(fs), float(c), int(n_aux))
+    N = o.mean_lags(Np)
+    assert round(N, 1) == float(printed)
+
+
+def test_table1_complexities():
+    """C of (24) and C_rel of SI-SRP (50) reproduce Table 1's printed values."""
+    t = {r[0]: r[1:] for r in _read_table("paper_table1.txt")}
+    # NF
+    Np = o.max_lags(NF_CORNERS, 4000.0, 340.0, 2)
+    c = o.complexity(J=73084, P=6, K=256, N=o.mean_lags(Np))
+    assert round(c["C"] / 2 / 1e6, 1) == float(t["C_printed_e6"][0])
+    assert round(c["C_si"] / c["C"], 2) == float(t["C_rel_SI_NF"][0])
+    # FF, 30 cm for C; all four diameters for C_rel
+    c30 = o.complexity(J=8101, P=15, K=512)
+    assert round(c30["C"] / 2 / 1e6, 1) == float(t["C_printed_e6"][1])
+    for d, printed in zip([0.1, 0.2, 0.3, 0.4], t["C_rel_SI_FF"]):
+        Np = o.max_lags(_uca(6, d), 16000.0, 340.0, 2)
+        cc = o.complexity(J=8101, P=15, K=512, N=o.mean_lags(Np))
+        assert round(cc["C_si"] / cc["C"], 3) == pytest.approx(float(printed), abs=1.01e-3)
+
+
+def test_fig12_complexities_to_13_digits():
+    """The measured-array geometry (Fig. 10), (33)-(35) and the complexity
+    model (24), (25), (30), (49), (50), (61), (62) reproduce every relative
+    complexity printed in Fig. 12."""
+    g = {r[0]: float(r[1]) for r in _read_table("paper_fig12_complexity.txt")}
+    mics = _measured_array()[:9]
+    Np = o.max_lags(mics, 4000.0, 340.0, 2)
+    J, P, K = 73 * 73 * 4, 36, 128
+    N = o.mean_lags(Np)
+    c = o.complexity(J=J, P=P, K=K, N=N, R_lambda=int(g["R_lambda"]),
+                     Q_lambda=J * P, R_H=int(g["R_H"]))
+    C = c["C"]
+    for key, ck in [("C_samp_rel", "C_samp"), ("C_td_rel", "C_td"), ("C_lr_rel", "C_lr"),
+                    ("C_si_rel", "C_si"), ("C_slri_rel", "C_slri"), ("C_sspi_rel", "C_sspi")]:
+        assert c[ck] / C == pytest.approx(g[key], rel=5e-12), key
+
+
+# --------------------------------------------------------------- P4 PHAT ---
+
+def test_phat_unit_modulus_conjugate_symmetry_and_zero():
+    rng = np.random.default_rng(2)
+    Y = _random_frames(rng, 3, 4, 16)
+    Y[0, 2, 5] = 0.0
+    psi = o.phat(Y)
+    assert psi.shape == (3, 6, 15)
+    mag = np.abs(psi)
+    zero = np.zeros_like(mag, dtype=bool)
+    for p, (m, mp) in enumerate(o.pairs(4)):
+        if 2 in (m, mp):
+            zero[0, p, 4] = True            # bin 5 is psi index 4
+    np.testing.assert_allclose(mag[~zero], 1.0, atol=1e-14)
+    assert np.all(psi[zero] == 0)
+    # psi_{m',m} = conj(psi_{m,m'}): reverse the channel order
+    psi_r = o.phat(Y[:, ::-1, :])
+    for p, (m, mp) in enumerate(o.pairs(4)):
+        q = o.pairs(4).index((3 - mp, 3 - m))
+        np.testing.assert_allclose(psi_r[:, q], np.conj(psi[:, p]), atol=1e-14)
+    # the phase of psi is the phase difference of the two channels
+    for p, (m, mp) in enumerate(o.pairs(4)):
+        d = np.angle(Y[1, m, 1:16]) - np.angle(Y[1, mp, 1:16])
+        np.testing.assert_allclose(psi[1, p], np.exp(1j * d), atol=1e-13)
+
+
+# -------------------------------------------------- P5 integer-delay GCC ---
+
+@pytest.mark.parametrize("D", [0, 3, -5, 7])
+def test_gcc_of_integer_circular_delay(D):
+    """Microphone m hears microphone m' delayed by D samples (circularly).
+    With the forward DFT exp(-j 2 pi k n / 2K), psi_p[k] = exp(-j pi k D / K)
+    and, DC and Nyquist zeroed, xi_p[n] = 2K delta[(n - D) mod 2K] - 1 -
+    (-1)^(n - D).  Checks the sign convention end to end on real signals."""
+    K = 32
+    N = 2 * K
+    rng = np.random.default_rng(3)
+    s = rng.standard_normal(N)
+    y0 = np.fft.rfft(s)
+    y1 = np.fft.rfft(np.roll(s, D))                   # m = 1 hears s delayed by D
+    Y = np.stack([y0, y1])[None]                      # [1, 2, K+1]
+    psi = o.phat(Y)
+    np.testing.assert_allclose(psi[0, 0], np.exp(-1j * np.pi * np.arange(1, K) * D / K), atol=1e-12)
+    n_p = 9
+    n = np.arange(-n_p, n_p + 1)
+    expect = N * (np.mod(n - D, N) == 0) - 1.0 - (-1.0) ** (n - D)
+    for xi in (o.gcc_samples_ifft(psi, [n_p], K), o.gcc_samples_direct(psi, [n_p], K)):
+        np.testing.assert_allclose(xi[0][0], expect, atol=1e-10)
+
+
+# ----------------------------------------------------------- P6 sampling ---
+
+def test_sampling_ifft_equals_direct_and_parseval_identity():
+    """The iFFT route (46)-(48) equals xi = 2 Re[S psi] (40); the rows of the
+    two-sided S-bar are orthogonal with S-bar S-bar^H = 2K I (Appendix); and
+    the cost simplification behind (53): for real Delta,
+    ||Delta S||_F^2 = K ||Delta||_F^2 - (||Delta 1||^2 + ||Delta (-1)^n||^2)/2,
+    the correction being the DC and Nyquist columns missing from S."""
+    rng = np.random.default_rng(4)
+    K = 24
+    Y = _random_frames(rng, 5, 3, K)
+    psi = o.phat(Y)
+    Np = [4, 7, 11]
+    a = o.gcc_samples_ifft(psi, Np, K)
+    b = o.gcc_samples_direct(psi, Np, K)
+    for u, v in zip(a, b):
+        np.testing.assert_allclose(u, v, atol=1e-11)
+    n_p = 7
+    n = np.arange(-n_p, n_p + 1)
+    k2 = np.arange(-K + 1, K + 1)
+    Sbar = np.exp(1j * np.pi * np.outer(n, k2) / K)
+    np.testing.assert_allclose(Sbar @ Sbar.conj().T, 2 * K * np.eye(2 * n_p + 1), atol=1e-10)
+    S = np.exp(1j * np.pi * np.outer(n, np.arange(1, K)) / K)
+    Delta = rng.standard_normal((6, 2 * n_p + 1))
+    lhs = np.sum(np.abs(Delta @ S) ** 2)
+    rhs = K * np.sum(Delta ** 2) - 0.5 * (np.sum((Delta @ np.ones(2 * n_p + 1)) ** 2)
+                                          + np.sum((Delta @ (-1.0) ** n) ** 2))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+# ----------------------------------------------------- P7 DSB brute force ---
+
+def test_fd_map_equals_delay_and_sum_output_power():
+    """z of (22) equals the broadband DSB output power minus the trace, the
+    first line of (8) summed over bins, computed without any pair algebra."""
+    rng = np.random.default_rng(5)
+    K = 16
+    mics = rng.uniform(-0.3, 0.3, (4, 3))
+    grid = rng.uniform(-2, 2, (40, 3))
+    fs, c = 8000.0, 343.0
+    Y = _random_frames(rng, 3, 4, K)
+    z = o.fd_map(o.phat(Y), o.tdoa_samples(mics, grid, fs, c), K)
+    z_dsb = o.dsb_power_map(Y, mics, grid, fs, c)
+    np.testing.assert_allclose(z, z_dsb, rtol=1e-11, atol=1e-10)
+
+
+# ---------------------------------------------- P8 Dirichlet closed form ---
+
+def test_fd_map_single_pure_delay_source_is_dirichlet_sum():
+    """psi_p[k] = exp(-j pi k x_p(s) / K) gives z(j) = sum_p [sin((K-1/2)
+    theta_p) / sin(theta_p / 2) - 1], theta_p = pi (x_p(j) - x_p(s)) / K, with
+    the global maximum P (2K - 2) at the source."""
+    rng = np.random.default_rng(6)
+    K = 64
+    fs, c = 16000.0, 343.0
+    mics = _uca(6, 0.2)
+    grid = np.concatenate([rng.uniform(-2, 2, (300, 3)), [[1.1, -0.7, 0.4]]])
+    src = grid[-1]
+    x = o.tdoa_samples(mics, grid, fs, c)
+    xs = x[:, -1]
+    k = np.arange(1, K)
+    psi = np.exp(-1j * np.pi * np.outer(xs, k) / K)[None]    # [1, P, K-1]
+    z = o.fd_map(psi, x, K)[0]
+    theta = np.pi * (x - xs[:, None]) / K
+    with np.errstate(invalid="ignore", divide="ignore"):
+        dk = np.sin((K - 0.5) * theta) / np.sin(theta / 2)
+    dk[np.abs(theta) < 1e-15] = 2 * K - 1
+    expect = (dk - 1).sum(0)
+    np.testing.assert_allclose(z, expect, rtol=1e-10, atol=1e-9)
+    P = x.shape[0]
+    assert z[-1] == pytest.approx(P * (2 * K - 2), rel=1e-12)
+    assert o.argmax_map(z) == len(grid) - 1
+    del src
+
+
+def test_fd_map_equals_exact_periodic_interpolation():
+    """With DC and Nyquist zero, the 2K GCC samples determine xi(tau) exactly
+    through the periodic interpolator D(t); interpolating all 2K samples at
+    the TDOAs reproduces (22).  Pins the sampling scale and the map scale."""
+    rng = np.random.default_rng(7)
+    K = 20
+    mics = rng.uniform(-0.2, 0.2, (4, 3))
+    grid = rng.uniform(-2, 2, (60, 3))
+    x = o.tdoa_samples(mics, grid, 8000.0, 343.0)
+    psi = o.phat(_random_frames(rng, 4, 4, K))
+    full = np.stack([np.fft.ifft(o.two_sided(psi[:, p], K), axis=1).real * 2 * K
+                     for p in range(psi.shape[1])], axis=1)        # [L, P, 2K]
+    z = o.fd_map(psi, x, K)
+    np.testing.assert_allclose(o.periodic_interp_map(full, x, K), z, rtol=1e-10, atol=1e-9)
+
+
+# ----------------------------------------- P9 integer TDOAs: SI = TD = FD ---
+
+def test_integer_tdoas_si_td_fd_agree():
+    """If every x_p(j) is an integer, the rows of Lambda_p are unit vectors
+    (42), so SI (44), TD (23) and FD (22) coincide (Sec. III-B2)."""
+    rng = np.random.default_rng(8)
+    K = 32
+    P, J = 5, 50
+    Np = np.array([6, 8, 5, 9, 7])
+    x = np.stack([rng.integers(-n + 2, n - 1, J).astype(float) for n in Np])
+    psi = np.exp(1j * rng.uniform(0, 2 * np.pi, (3, P, K - 1)))
+    xi = o.gcc_samples_ifft(psi, Np, K)
+    z_fd = o.fd_map(psi, x, K)
+    np.testing.assert_allclose(o.si_map(xi, x, Np), z_fd, atol=1e-9)
+    np.testing.assert_allclose(o.td_map(xi, x, Np), z_fd, atol=1e-9)
+    # SSPI with one tap per (location, pair) at integer TDOAs is FD too
+    sel = [o.sspi_select(x[p], Np[p], 1) for p in range(P)]
+    np.testing.assert_allclose(o.sspi_map(xi, sel, Np), z_fd, atol=1e-9)
+
+
+def test_td_map_rounds_to_nearest_lag():
+    K = 16
+    Np = [5]
+    x = np.array([[0.4, 0.6, -1.6, 2.49, -2.51]])
+    xi = [np.arange(-5, 6, dtype=float)[None] * 10.0]      # xi[n] = 10 n
+    np.testing.assert_allclose(o.td_map(xi, x, Np)[0], [0, 10, -20, 20, -30])
+    del K
+
+
+# ------------------------------------------------------------ P10 SLRI ---
+
+def _real_geometry(rng, J=300, M=5):
+    mics = _uca(M, 0.3)
+    grid = rng.uniform([-2, -2, 0.5], [2, 2, 2.0], (J, 3))
+    fs, c = 16000.0, 343.0
+    return o.tdoa_samples(mics, grid, fs, c), o.max_lags(mics, fs, c, 2)
+
+
+def test_slri_full_rank_is_si_and_truncation_error_is_eckart_young():
+    rng = np.random.default_rng(9)
+    K = 64
+    x, Np = _real_geometry(rng)
+    psi = o.phat(_random_frames(rng, 4, 5, K))
+    xi = o.gcc_samples_ifft(psi, Np, K)
+    z_si = o.si_map(xi, x, Np)
+    full = o.slri_factors(x, Np, R=10 ** 6)
+    np.testing.assert_allclose(o.slri_map(xi, full), z_si, rtol=1e-10, atol=1e-8)
+    R = 4
+    fac = o.slri_factors(x, Np, R)
+    prev = None
+    for p, (U, V, s) in enumerate(fac):
+        lam = o.interp_matrix(x[p], Np[p])
+        err = np.sum((lam - U @ V.T) ** 2)
+        assert err == pytest.approx(np.sum(s[R:] ** 2), rel=1e-8, abs=1e-18)
+        # no other rank-R approximation of the same matrix does better:
+        # projections onto random R-dimensional row spaces
+        for t in range(5):
+            B = np.linalg.qr(rng.standard_normal((lam.shape[1], R)))[0]
+            assert np.sum((lam - lam @ B @ B.T) ** 2) >= err - 1e-9
+        # error decreases with the rank
+        errs = [np.sum(s[r:] ** 2) for r in range(1, len(s) + 1)]
+        assert all(a >= b for a, b in zip(errs, errs[1:]))
+        prev = err
+    assert prev is not None
+
+
+def test_slri_global_full_rank_is_si():
+    rng = np.random.default_rng(10)
+    K = 64
+    x, Np = _real_geometry(rng, J=250, M=4)
+    psi = o.phat(_random_frames(rng, 3, 4, K))
+    xi = o.gcc_samples_ifft(psi, Np, K)
+    PN = int(np.sum(2 * Np + 1))
+    tall, fat = o.slri_global_factors(x, Np, PN)
+    np.testing.assert_allclose(o.slri_global_map(xi, tall, fat), o.si_map(xi, x, Np),
+                               rtol=1e-10, atol=1e-8)
+    # rank-R global error equals the discarded singular energy
+    lam = np.concatenate([o.interp_matrix(x[p], n) for p, n in enumerate(Np)], 1)
+    s = np.linalg.svd(lam, compute_uv=False)
+    tall, fat = o.slri_global_factors(x, Np, 12)
+    assert np.sum((lam - tall @ fat) ** 2) == pytest.approx(np.sum(s[12:] ** 2), rel=1e-8)
+
+
+# ------------------------------------------------------------ P11 SSPI ---
+
+def test_sspi_dense_is_si_and_window_is_closed_form():
+    """Q_p = 2N_p + 1 keeps all of Lambda_p, so SSPI = SI.  The top-Q
+    selection by sorting equals the window of the Q integers nearest to x,
+    s = clamp(ceil(x - Q/2), -N_p, N_p - Q + 1), because |sinc(x - n)| =
+    |sin(pi x)| / (pi |x - n|) decreases with |x - n|."""
+    rng = np.random.default_rng(11)
+    K = 64
+    x, Np = _real_geometry(rng)
+    psi = o.phat(_random_frames(rng, 4, 5, K))
+    xi = o.gcc_samples_ifft(psi, Np, K)
+    dense = [o.sspi_select(x[p], Np[p], 10 ** 6) for p in range(len(Np))]
+    np.testing.assert_allclose(o.sspi_map(xi, dense, Np), o.si_map(xi, x, Np), rtol=1e-11, atol=1e-9)
+    for Q in (1, 2, 3, 4, 7):
+        for p, n_p in enumerate(Np):
+            lags, w = o.sspi_select(x[p], n_p, Q)
+            q = min(Q, 2 * n_p + 1)
+            s = np.clip(np.ceil(x[p] - q / 2.0), -n_p, n_p - q + 1).astype(int)
+            np.testing.assert_array_equal(lags, s[:, None] + np.arange(q)[None])
+            np.testing.assert_allclose(w, np.sinc(x[p][:, None] - lags), atol=0)
+            # discarded energy is the part of the row outside the window
+            lam = o.interp_matrix(x[p], n_p)
+            kept = np.sum(w ** 2)
+            assert np.sum(lam ** 2) - kept >= -1e-12
+
+
+def test_sspi_window_at_half_integers_and_clamp():
+    # x = 0.5, Q = 3: candidates 0 and 1 (dist .5), then -1 and 2 tie at 1.5:
+    # the smaller n wins
+    lags, _ = o.sspi_select(np.array([0.5, 2.9, -2.9, 0.0]), 3, 3)
+    np.testing.assert_array_equal(lags[0], [-1, 0, 1])
+    np.testing.assert_array_equal(lags[1], [1, 2, 3])       # clamped at N_p = 3
+    np.testing.assert_array_equal(lags[2], [-3, -2, -1])
+    np.testing.assert_array_equal(lags[3], [-1, 0, 1])
+
+
+def test_sspi_global_selection():
+    """Global top-Q_Lambda of (55): with Q_Lambda = J P N every entry is kept
+    (SI); with smaller Q the kept entries are the largest in magnitude."""
+    rng = np.random.default_rng(12)
+    K = 64
+    x, Np = _real_geometry(rng, J=120, M=4)
+    psi = o.phat(_random_frames(rng, 2, 4, K))
+    xi = o.gcc_samples_ifft(psi, Np, K)
+    J = x.shape[1]
+    PN = int(np.sum(2 * Np + 1))
+    np.testing.assert_allclose(o.sspi_global_map(xi, o.sspi_global_select(x, Np, J * PN)),
+                               o.si_map(xi, x, Np), rtol=1e-11, atol=1e-9)
+    Qt = J * len(Np) * 2
+    sp = o.sspi_global_select(x, Np, Qt)
+    assert np.count_nonzero(sp) == Qt
+    lam = np.concatenate([o.interp_matrix(x[p], n) for p, n in enumerate(Np)], 1)
+    assert np.min(np.abs(sp[sp != 0])) >= np.max(np.abs(lam[sp == 0])) - 1e-15
+
+
+# ------------------------------------------------------- argmax / errors ---
+
+def test_argmax_ties_and_error_measures():
+    z = np.array([[1.0, 3.0, 3.0, 2.0], [5.0, 0.0, 5.0, 5.0]])
+    np.testing.assert_array_equal(o.argmax_map(z), [1, 0])
+    ref = np.array([[3.0, 4.0]])
+    np.testing.assert_allclose(o.rel_error(ref * 1.01, ref), [0.01])
+    np.testing.assert_allclose(o.eps_z_db(ref * 1.1, ref), [-20.0])
+    assert o.eps_h_db(2 * np.eye(3), np.eye(3)) == pytest.approx(0.0)
