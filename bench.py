@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""SRP-map benchmark on one MI355X.
+
+Workload: M = 8 microphones (0.3 m UCA), J = 125,000 candidates (50 x 50 x 50
+over a 5 x 5 x 2.5 m room), fs = 16 kHz, N = 1024, L = 1000 STFT frames of a
+reverberant 1/f-noise scene (seeded synthetic frames, resident in HBM before
+timing starts).
+
+One step is one pass of the whole hot path over the 1000 frames: PHAT
+cross-spectra, conv. FD-SRP with FP32 operands (the reference form),
+GCC sampling, SLRI (R = 8 per pair, BF16 tall factor) and SSPI (Q = 4 per
+location and pair, BF16 weights); every form writes its 1000 maps.  `value`
+counts every map the step writes (3 L per step).  Per-form rates, p50/p99
+call latencies and each form's speed-up over FP32 FD are reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32_mfma_tflops": 157.3, "bf16_mfma_tflops": 2500.0, "hbm_gbs": 8000.0,
+        "fp32_valu_tflops_nonpacked": 78.6}
+METRIC = "SRP maps/sec (M=8, J=125k) vs FP32 conv FD-SRP at fixed error; p50/p99 ms"
+
+FORMS = [("fd", 0, "f32"), ("slri", 8, "bf16"), ("sspi", 4, "bf16")]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=None, help="override L (default 1000)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--forms", default="fd,slri,sspi")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for HBM counter calibration)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_rooflines(cfg, prof, L, P, K, PN):
+    """Achieved rates of the main kernels from live HIP-event spans.
+    Algorithmic work per launch (one launch covers L frames):
+      gemm_fd      2 J P (K-1) MACs per map            (eq. (24))
+      gemm_tall    J R P MACs per map; HBM bytes = 4 J (map write)
+                   + 2 J P R (BF16 U) per launch
+      sspi_gather  J P Q FMAs per map; HBM bytes = 4 J (map write)
+                   + J P (4 + 2 Q) (starts + BF16 weights) per launch
+    """
+    J = cfg["grid"].shape[0]
+    out = {}
+    fd = prof.get("fd", {}).get("gemm_fd")
+    if fd:
+        t = fd[0] / fd[1] / 1e3
+        flops = 2.0 * 2.0 * J * P * (K - 1) * L
+        out["gemm_fd"] = {"bound": "mfma", "avg_ms": t * 1e3, "achieved": flops / t / 1e12,
+                          "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
+                          "frac": flops / t / 1e12 / PEAK["fp32_mfma_tflops"]}
+    tall = prof.get("slri", {}).get("gemm_tall")
+    if tall:
+        t = tall[0] / tall[1] / 1e3
+        byts = 4.0 * J * L + 2.0 * J * P * 8
+        out["gemm_tall"] = {"bound": "hbm", "avg_ms": t * 1e3, "achieved": byts / t / 1e9,
+                            "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": byts / t / 1e9 / PEAK["hbm_gbs"],
+                            "mfma_tflops": 2.0 * J * P * 8 * L / t / 1e12}
+    sg = prof.get("sspi", {}).get("sspi_gather")
+    if sg:
+        t = sg[0] / sg[1] / 1e3
+        fl = 2.0 * J * P * 4 * L
+        out["sspi_gather"] = {"bound": "alu", "avg_ms": t * 1e3, "achieved": fl / t / 1e12,
+                              "peak": PEAK["fp32_valu_tflops_nonpacked"], "unit": "TFLOP/s",
+                              "frac": fl / t / 1e12 / PEAK["fp32_valu_tflops_nonpacked"],
+                              "hbm_gbs": (4.0 * J * L + J * P * (4 + 2 * 4)) / t / 1e9}
+    return out
+
+
+def cpu_baseline(cfg, Y, forms):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload:
+    50 frames at 4096 of the 125,000 candidates per form (plan-time work such
+    as the SVD and window selection excluded); per-map time scaled by J/4096."""
+    import oracle as o
+    threads = len(os.sched_getaffinity(0))
+    J = cfg["grid"].shape[0]
+    rng = np.random.default_rng(11)
+    cols = np.sort(rng.choice(J, 4096, replace=False))
+    Ls = 50
+    Ys = Y[:Ls]
+    x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+    K = cfg["N"] // 2
+    per_map = {}
+    for form, rq, _ in forms:
+        if form == "slri":
+            fac = o.slri_factors(x, Np, rq)
+            fac = [(U[cols], V, s) for (U, V, s) in fac]
+        elif form == "sspi":
+            xs = x[:, cols]
+            sel = [o.sspi_select(xs[p], Np[p], rq) for p in range(len(Np))]
+        t0 = time.perf_counter()
+        psi = o.phat(Ys)
+        if form == "fd":
+            o.fd_map(psi, x[:, cols], K)
+        else:
+            xi = o.gcc_samples_ifft(psi, Np, K)
+            if form == "slri":
+                o.slri_map(xi, fac)
+            else:
+                o.sspi_map(xi, sel, Np)
+        dt = time.perf_counter() - t0
+        per_map[form] = dt * (J / len(cols)) / Ls
+    total = sum(per_map.values())
+    try:
+        model = [ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")][0]
+    except Exception:
+        model = "unknown"
+    return {"value": len(per_map) / total, "unit": "maps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{Ls} frames x {len(cols)} of {J} candidates per form, per-map time scaled by "
+                      f"J/{len(cols)}; one map per form per frame",
+            "per_form_maps_per_s": {k: 1.0 / v for k, v in per_map.items()},
+            "cpu_model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1",
+                          "n_gpus_requested": args.gpus}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    from paper_2306_08514_amd import native, scenes
+    native.lib()  # fails loudly when the HIP library is missing
+
+    forms = [f for f in FORMS if f[0] in args.forms.split(",")]
+    t0 = time.time()
+    cfg = scenes.config(1, L=args.frames)
+    Y = scenes.make_frames(cfg)
+    log(f"scene generated in {time.time() - t0:.1f} s: frames {Y.shape}")
+    L, M, _ = Y.shape
+    J = cfg["grid"].shape[0]
+    dev = torch.device("cuda:0")
+    Yt = torch.from_numpy(Y).to(dev)
+
+    plans, outs, wss, plan_s = {}, {}, {}, {}
+    for form, rq, dt in forms:
+        t1 = time.time()
+        plans[form] = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], form, rq, dtype=dt,
+                                  c=cfg["c"], device=0)
+        plan_s[form] = time.time() - t1
+        outs[form] = torch.empty((L, J), dtype=torch.float32, device=dev)
+        wss[form] = torch.empty(plans[form].workspace_size(L), dtype=torch.uint8, device=dev)
+        log(f"plan {form}/{dt} built in {plan_s[form]:.2f} s, resident "
+            f"{plans[form].info()['device_bytes'] / 2**30:.2f} GiB")
+    info = plans[forms[0][0]].info()
+    P, K = info["P"], info["K"]
+    PN = info["PN"]
+
+    def step(ev=None):
+        for form, _, _ in forms:
+            if ev is not None:
+                ev[form][0].record()
+            plans[form].compute(Yt, maps=outs[form], workspace=wss[form])
+            if ev is not None:
+                ev[form][1].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    for form in plans:
+        plans[form].profile(True)
+    events = [{f: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for f in plans} for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    log(f"timed {args.steps} steps in {wall:.3f} s")
+
+    prof = {}
+    for form in plans:
+        prof[form] = plans[form].profile_collect()
+        plans[form].profile(False)
+
+    lat = {f: np.array([events[k][f][0].elapsed_time(events[k][f][1]) for k in range(args.steps)]) for f in plans}
+    ms_per_step = wall / args.steps * 1e3
+    maps_per_step = L * len(plans)
+    value = maps_per_step / (ms_per_step / 1e3)
+    per_form = {}
+    for form, rq, dt in forms:
+        ms = float(np.mean(lat[form]))
+        per_form[form] = {"operands": dt, "rank_or_q": rq, "maps_per_s": L / (ms / 1e3),
+                          "ms_per_call": ms, "p50_ms": float(np.percentile(lat[form], 50)),
+                          "p99_ms": float(np.percentile(lat[form], 99)),
+                          "plan_seconds": plan_s[form],
+                          "resident_gib": plans[form].info()["device_bytes"] / 2 ** 30,
+                          "kernels_ms_per_call": {k: v[0] / v[1] for k, v in prof[form].items()}}
+    if "fd" in per_form:
+        for form in per_form:
+            per_form[form]["speedup_vs_fd_f32"] = per_form[form]["maps_per_s"] / per_form["fd"]["maps_per_s"]
+
+    # accuracy at the configured R, Q: epsilon_z against the FP64 FD oracle on
+    # 8 frames x 2000 sampled candidates; argmax agreement with FP32 FD over
+    # every frame and the full grid
+    accuracy = None
+    if not args.no_accuracy and "fd" in plans:
+        import oracle as o
+        rng = np.random.default_rng(5)
+        fr = np.sort(rng.choice(L, 8, replace=False))
+        cols = np.sort(rng.choice(J, 2000, replace=False))
+        x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+        ref = o.fd_map(o.phat(Y[fr]), x[:, cols], cfg["N"] // 2)
+        am_fd = torch.argmax(outs["fd"], dim=1)
+        accuracy = {}
+        for form in plans:
+            zs = outs[form][torch.from_numpy(fr).to(dev)][:, torch.from_numpy(cols).to(dev)].cpu().numpy()
+            eps = o.eps_z_db(zs, ref)
+            agree = float((torch.argmax(outs[form], dim=1) == am_fd).float().mean())
+            accuracy[form] = {"eps_z_db_vs_fp64_fd_median": float(np.median(eps)),
+                              "argmax_agreement_with_fd_f32": agree}
+
+    rl = kernel_rooflines(cfg, prof, L, P, K, PN)
+    dom = rl.get("gemm_fd") or next(iter(rl.values()), None)
+    roofline = None
+    if dom:
+        roofline = {"bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
+                    "unit": dom["unit"], "frac": dom["frac"], "traffic": None,
+                    "kernel": [k for k, v in rl.items() if v is dom][0], "avg_ms": dom["avg_ms"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t2 = time.time()
+        cpu = cpu_baseline(cfg, Y, forms)
+        log(f"cpu baseline in {time.time() - t2:.1f} s")
+
+    if args.copy_calibration:
+        a = torch.empty(2 ** 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    rec = {
+        "metric": METRIC, "value": value, "unit": "maps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"config 2: M=8 UCA 0.3 m, J={J} (50x50x50 over 5x5x2.5 m), "
+                               f"fs=16 kHz, N=1024, L={L} frames per step; forms "
+                               + ", ".join(f"{f}({dt}{'' if not rq else ', ' + ('R' if f == 'slri' else 'Q') + '=' + str(rq)})"
+                                           for f, rq, dt in forms),
+                   "maps_per_step": maps_per_step, "accumulate": "f32"},
+        "forms": per_form,
+        "kernels": rl,
+        "accuracy": accuracy,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

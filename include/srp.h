@@ -1,0 +1,202 @@
+/*
+ * srp.h -- C ABI of the MI355X (gfx950) SRP-map library.
+ *
+ * Computes steered response power (SRP) maps from multichannel STFT frames,
+ * following Dietzen, De Sena and van Waterschoot, "Scalable-Complexity
+ * Steered Response Power based on Low-Rank and Sparse Interpolation"
+ * (arXiv 2306.08514), in three forms:
+ *
+ *   SRP_FD    conv. FD-SRP, the dense transform z = 2 Re[H psi]
+ *             (Sec. II-D, eq. (22));
+ *   SRP_SLRI  sampling of each pair's GCC (Sec. III-B3, eqs. (40), (46)-(48))
+ *             followed by low-rank interpolation z = sum_p U_p (V_p^T xi_p),
+ *             the rank-R truncated SVD of each pair's sinc interpolation
+ *             matrix Lambda_p (Sec. IV-A, eqs. (54), (56), (57));
+ *   SRP_SSPI  the same sampling followed by sparse interpolation keeping the Q
+ *             largest-magnitude entries of every row of every Lambda_p
+ *             (Sec. IV-A, eqs. (55), (58)).
+ *
+ * Conventions used by every entry point:
+ *   - N is the DFT length 2K of the STFT; frames hold bins 0..K; the map uses
+ *     bins 1..K-1 and treats DC and Nyquist as zero (Sec. II-D).
+ *   - Pairs p <-> (m, m'), m > m', are enumerated with m' in the outer and m
+ *     in the inner loop (the double sum of eq. (8)).
+ *   - PHAT weighting psi = y_m y_m'^* / |y_m y_m'^*| (eq. (2)), 0 where the
+ *     product vanishes.
+ *   - TDOAs are near-field (eq. (3)), in samples x_p(j) = Delta t_p(j) fs,
+ *     computed in FP64 on the host; N_p = floor(d_p fs / c) + N_aux (eq. (33)).
+ *   - sinc is the normalised sinc of Whittaker-Shannon interpolation
+ *     (eq. (31), (42)).
+ *   - Map scale: z = 2 Re[H psi] exactly as in eq. (22); the GCC samples are
+ *     the unnormalised inverse DFT xi_p[n] = 2 Re sum_k psi_p[k] e^{j pi k n/K}
+ *     (eq. (40)).
+ *
+ * Memory: host pointers are read during the call and copied; device pointers
+ * must stay valid until the work enqueued on the given stream completes.
+ * A plan owns its device memory until srp_destroy.  No entry point
+ * synchronises the stream except where stated.
+ *
+ * Errors: every entry point returns an srp_status; on failure
+ * srp_last_error() returns a message for the calling thread.  A failed
+ * srp_plan leaves *out == NULL and leaks nothing.  No C++ exception crosses
+ * the ABI.
+ */
+#ifndef SRP_H_
+#define SRP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct srp_plan_s* srp_plan_t;
+
+typedef enum {
+  SRP_OK = 0,
+  SRP_E_INVALID = -1,     /* bad argument or geometry */
+  SRP_E_NOMEM = -2,       /* host or device allocation failed */
+  SRP_E_UNSUPPORTED = -3, /* variant/dtype combination not built */
+  SRP_E_HIP = -4,         /* a HIP runtime call failed */
+  SRP_E_BUDGET = -5       /* plan or workspace exceeds opts.hbm_budget */
+} srp_status;
+
+typedef enum { SRP_FD = 0, SRP_SLRI = 1, SRP_SSPI = 2 } srp_variant;
+
+/* Operand precision of the dominant contraction (steering matrix for FD, the
+ * tall factor U for SLRI, the interpolation weights for SSPI).  Accumulation
+ * is FP32 (FP64 for SRP_F64); cross-spectra, GCC samples and the SLRI fat
+ * stage are FP32 for every dtype except SRP_F64.  FP8 is OCP E4M3 with
+ * per-pair scales folded into the activations (SLRI) or weights (SSPI). */
+typedef enum {
+  SRP_F32 = 0,
+  SRP_BF16 = 1,
+  SRP_F16 = 2,
+  SRP_FP8_E4M3 = 3,
+  SRP_F64 = 4
+} srp_dtype;
+
+typedef struct {
+  double c;              /* speed of sound in m/s (default 343.0) */
+  int n_aux;             /* auxiliary lags N_aux of eq. (33) (default 2) */
+  srp_dtype dtype;       /* operand precision (default SRP_F32) */
+  int device;            /* HIP device ordinal; -1 builds the host plan only
+                            (no device memory; srp_compute is then invalid) */
+  int64_t frame_tile;    /* frames per internal tile (default 1024) */
+  size_t hbm_budget;     /* max device bytes for the plan, 0 = unlimited */
+} srp_opts;
+
+typedef struct {
+  int M, P, K;           /* microphones, pairs, half DFT length */
+  int64_t J;             /* candidate locations */
+  int PN;                /* stacked GCC samples sum_p (2 N_p + 1) */
+  int max_np;            /* max_p N_p */
+  int rank_or_q;         /* effective R (SLRI) or Q (SSPI), 0 for FD */
+  srp_variant variant;
+  srp_dtype dtype;
+  double mean_n;         /* N of eq. (35) */
+  double macs_per_map;   /* run-time MACs per map: C (24), C_slri (61) or
+                            C_sspi (62), sampling counted as 2PN(K-1) */
+  size_t device_bytes;   /* resident device memory owned by the plan */
+  double plan_seconds;   /* wall time of plan construction */
+} srp_plan_info;
+
+/* Fills *opts with the defaults listed above. */
+void srp_default_opts(srp_opts* opts);
+
+/* Builds a plan (Sec. IV-B: everything that depends only on geometry and
+ * frequency resolution is computed upfront, in FP64).
+ *   mics      host, M x 3 row-major, metres (M >= 2)
+ *   grid      host, J x 3 row-major, metres (J >= 1), near-field candidates
+ *   fs        sampling rate in Hz (> 0)
+ *   N         DFT length 2K (even, >= 8); requires 2 N_p + 1 <= N for every
+ *             pair (lag aliasing, Sec. III-B2 footnote)
+ *   variant   SRP_FD, SRP_SLRI or SRP_SSPI
+ *   rank_or_q R per pair (SLRI) or Q per (location, pair) (SSPI), >= 1;
+ *             clamped per pair to 2 N_p + 1; ignored for SRP_FD
+ *   opts      NULL for defaults
+ *   out       receives the plan, NULL on failure
+ * Returns SRP_E_INVALID for bad geometry or arguments, SRP_E_UNSUPPORTED for
+ * a dtype the variant does not offer, SRP_E_BUDGET when the resident operands
+ * exceed opts->hbm_budget, SRP_E_NOMEM / SRP_E_HIP on allocation or runtime
+ * failures. */
+srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J,
+                    double fs, int N, srp_variant variant, int rank_or_q,
+                    const srp_opts* opts, srp_plan_t* out);
+
+/* Bytes of device workspace srp_compute needs for L frames. */
+srp_status srp_workspace_size(srp_plan_t plan, int64_t L, size_t* bytes);
+
+/* Computes one SRP map per frame.
+ *   frames    device, complex64 [L][M][N/2 + 1] (interleaved re, im float32)
+ *   L         number of frames (>= 0; 0 is a no-op)
+ *   maps      device, float32 [L][J] (float64 [L][J] for SRP_F64 plans)
+ *   workspace device, >= srp_workspace_size(L) bytes, 256-byte aligned; NULL
+ *             uses a plan-owned buffer (then at most one call per plan may be
+ *             in flight at a time)
+ *   stream    hipStream_t to enqueue on (NULL = the null stream)
+ * Asynchronous: returns after enqueueing. */
+srp_status srp_compute(srp_plan_t plan, const void* frames, int64_t L,
+                       void* maps, void* workspace, size_t ws_bytes,
+                       void* stream);
+
+/* Stage entry point: PHAT-weighted cross-spectra (eq. (2)) of L frames.
+ *   psi  device, complex64 [L][P][K-1] */
+srp_status srp_crossspec(srp_plan_t plan, const void* frames, int64_t L,
+                         void* psi, void* stream);
+
+/* Stage entry point: GCC samples xi_p[n], n = -N_p..N_p, of L frames
+ * (eq. (40)), pairs stacked in order, lags in natural order.
+ *   xi   device, float32 [L][PN]
+ * Only for SLRI and SSPI plans (the sampling stage exists only there). */
+srp_status srp_gcc_samples(srp_plan_t plan, const void* frames, int64_t L,
+                           float* xi, void* stream);
+
+srp_status srp_plan_info_get(srp_plan_t plan, srp_plan_info* info);
+
+/* Host-side plan data, for inspection (no device access):
+ *   what = "tdoa"     double [P][J]   x_p(j) in samples
+ *          "np"       int32  [P]      N_p
+ *          "pairs"    int32  [P][2]   (m, m')
+ *          "slri_u"   double [P][J][R]  U_p = Lambda_p V_p (FP64, before cast)
+ *          "slri_v"   double [P][maxlag][R] V_p, rows n = -N_p..N_p, padded
+ *                                      to 2 max_np + 1 rows with zeros
+ *          "slri_s"   double [P][2 max_np + 1] singular values, descending
+ *          "sspi_start" int32 [J][P]  first lag s of the window (-N_p..)
+ *          "sspi_w"   double [J][P][Q] weights sinc(x - s - q)
+ * bytes: size of dst; *needed receives the required size.  dst may be NULL
+ * to query the size.  SRP_E_INVALID if the plan has no such data. */
+srp_status srp_plan_export(srp_plan_t plan, const char* what, void* dst,
+                           size_t bytes, size_t* needed);
+
+/* Per-kernel timing.  While enabled, srp_compute, srp_crossspec and
+ * srp_gcc_samples record a pair of HIP events around every kernel they
+ * launch, on the caller's stream.  srp_profile_collect waits for the
+ * recorded events and returns, per kernel name, the total time in ms and the
+ * number of launches since the previous collect, then clears them.  A plan
+ * with profiling enabled must be driven from one host thread at a time.
+ *   out       host array of `capacity` entries; *count receives the number of
+ *             kernel names (entries beyond capacity are dropped). */
+typedef struct {
+  char name[32];
+  double total_ms;
+  int64_t launches;
+} srp_kernel_time;
+
+srp_status srp_profile_enable(srp_plan_t plan, int enable);
+srp_status srp_profile_collect(srp_plan_t plan, srp_kernel_time* out, int capacity,
+                               int* count);
+
+/* Frees the plan and all device memory it owns; safe on NULL.  The caller
+ * must make sure no work using the plan is still in flight. */
+void srp_destroy(srp_plan_t plan);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* srp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRP_H_ */

@@ -1,0 +1,1112 @@
+// HIP kernels for gfx950 (MI355X) and the hot-path launch sequence.
+//
+// Hot path per frame tile (one map per STFT frame):
+//   phat_kernel      PHAT-weighted cross-spectra psi_p[l, k]          eq. (2)
+//   gemm_nt (FD)     z = 2 Re[H psi] as a real MFMA GEMM              eq. (22)
+//   gemm_nt (samp.)  xi_p = 2 Re[S_p psi_p], S_p rows of the iDFT      eq. (40)
+//   slri_fat         g_p = V_p^T xi_p                                   eq. (57)
+//   gemm_nt (tall)   z = sum_p U_p g_p                                  eq. (57)
+//   sspi_gather      z = sum_p sum_q w[j,p,q] xi_p[s(j,p) + q]          eq. (58)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/srp.h"
+#include "device.hpp"
+
+namespace srp {
+
+// ------------------------------------------------------------------ types --
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// OCP FP8 E4M3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits, max
+// 448, no infinities, S.1111.111 is NaN).
+struct fp8 {
+  uint8_t bits;
+};
+
+__host__ __device__ inline uint8_t e4m3_encode(float x) {
+  const uint8_t sign = std::signbit(x) ? 0x80 : 0x00;
+  const float a = std::fabs(x);
+  if (!(a == a)) return static_cast<uint8_t>(0x7F | sign);
+  if (a >= 448.0f) return static_cast<uint8_t>(0x7E | sign);  // saturate
+  if (a < 0.015625f) {
+    // subnormal grid m * 2^-9; rounding to 8 lands on the smallest normal
+    return static_cast<uint8_t>(static_cast<int>(std::rint(a * 512.0f)) | sign);
+  }
+  int e;
+  const float f = std::frexp(a, &e);  // a = f 2^e, f in [1/2, 1)
+  int q = static_cast<int>(std::rint((2.0f * f - 1.0f) * 8.0f));  // ties to even
+  int E = e - 1 + 7;
+  if (q == 8) {
+    q = 0;
+    E += 1;
+  }
+  int code = (E << 3) | q;
+  if (code > 0x7E) code = 0x7E;
+  return static_cast<uint8_t>(code | sign);
+}
+
+__host__ __device__ inline float e4m3_decode(uint8_t c) {
+  const int E = (c >> 3) & 15, m = c & 7;
+  if ((c & 0x7F) == 0x7F) return NAN;
+  const float v = E ? std::ldexp(1.0f + m / 8.0f, E - 7) : std::ldexp(static_cast<float>(m), -9);
+  return (c & 0x80) ? -v : v;
+}
+
+template <typename T>
+__device__ inline T cvt(float v);
+template <>
+__device__ inline float cvt<float>(float v) { return v; }
+template <>
+__device__ inline __bf16 cvt<__bf16>(float v) { return static_cast<__bf16>(v); }
+template <>
+__device__ inline _Float16 cvt<_Float16>(float v) { return static_cast<_Float16>(v); }
+template <>
+__device__ inline fp8 cvt<fp8>(float v) { return fp8{e4m3_encode(v)}; }
+
+template <typename T>
+__device__ inline T cvt64(double v) { return cvt<T>(static_cast<float>(v)); }
+template <>
+__device__ inline double cvt64<double>(double v) { return v; }
+
+// ------------------------------------------------------------ error check --
+
+#define HIP_OK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw Error{e_ == hipErrorOutOfMemory ? SRP_E_NOMEM : SRP_E_HIP,                   \
+                  std::string(#expr) + ": " + hipGetErrorString(e_)};                    \
+  } while (0)
+
+static void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error{SRP_E_HIP, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+static inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+static inline size_t align256(size_t a) { return (a + 255) & ~static_cast<size_t>(255); }
+
+static hipEvent_t take_event(DevicePlan& dp) {
+  if (!dp.event_pool.empty()) {
+    hipEvent_t e = dp.event_pool.back();
+    dp.event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  HIP_OK(hipEventCreate(&e));
+  return e;
+}
+
+// Launches `launch` and, while profiling is enabled, brackets it with a pair
+// of events recorded on the same stream.
+#define TRACED(dp, kname, st, launch)                     \
+  do {                                                    \
+    hipEvent_t a_ = nullptr;                              \
+    if ((dp).profiling) {                                 \
+      a_ = take_event(dp);                                \
+      HIP_OK(hipEventRecord(a_, st));                     \
+    }                                                     \
+    launch;                                               \
+    if (a_) {                                             \
+      hipEvent_t b_ = take_event(dp);                     \
+      HIP_OK(hipEventRecord(b_, st));                     \
+      (dp).spans.push_back(DevicePlan::Span{kname, a_, b_}); \
+    }                                                     \
+  } while (0)
+
+// ============================================================ PHAT kernel ==
+//
+// One wave per block; a thread owns one single-sided bin k = 1 + slot of one
+// frame.  u_m = y_m / |y_m| is formed once per microphone and staged in LDS,
+// then psi_p = u_m conj(u_m') for every pair, which equals
+// y_m y_m'^* / |y_m y_m'^*| of eq. (2), and 0 where either bin is 0.
+// Output layout: out[l * ld_l + p * ld_p + 2 * slot + {re, im}]; slots in
+// [K-1, kslots) are written as zeros (row padding).
+
+template <typename TO, typename TC>
+__global__ __launch_bounds__(64) void phat_kernel(const float2* __restrict__ Y, int M, int K,
+                                                  int P, const int32_t* __restrict__ pm,
+                                                  const int32_t* __restrict__ pmp,
+                                                  TO* __restrict__ out, int64_t ld_l,
+                                                  int64_t ld_p, int kslots) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char phat_lds[];
+  TC* ur = reinterpret_cast<TC*>(phat_lds);  // [M][64] real
+  TC* ui = ur + M * 64;                      // [M][64] imag
+  const int tid = threadIdx.x;
+  const int slot = blockIdx.x * 64 + tid;
+  const int64_t l = blockIdx.y;
+  const bool live = slot < K - 1;
+  if (live) {
+    const float2* yl = Y + l * M * (K + 1) + (slot + 1);
+    for (int m = 0; m < M; ++m) {
+      const float2 y = yl[static_cast<int64_t>(m) * (K + 1)];
+      TC a = y.x, b = y.y;
+      const TC s = std::max(std::fabs(a), std::fabs(b));
+      if (s > 0) {
+        a /= s;
+        b /= s;
+        const TC r = TC(1) / std::sqrt(a * a + b * b);
+        a *= r;
+        b *= r;
+      } else {
+        a = 0;
+        b = 0;
+      }
+      ur[m * 64 + tid] = a;
+      ui[m * 64 + tid] = b;
+    }
+  }
+  // same wave wrote and reads its own column: no barrier needed across waves
+  if (slot >= kslots) return;
+  TO* o = out + l * ld_l + 2 * static_cast<int64_t>(slot);
+  for (int p = 0; p < P; ++p) {
+    TC re = 0, im = 0;
+    if (live) {
+      const int m = pm[p], mq = pmp[p];
+      const TC ar = ur[m * 64 + tid], ai = ui[m * 64 + tid];
+      const TC br = ur[mq * 64 + tid], bi = ui[mq * 64 + tid];
+      re = ar * br + ai * bi;  // u_m conj(u_m')
+      im = ai * br - ar * bi;
+    }
+    o[p * ld_p] = cvt64<TO>(re);
+    o[p * ld_p + 1] = cvt64<TO>(im);
+  }
+}
+
+// ============================================================ MFMA GEMM ====
+//
+// C[r][c] = alpha * sum_k X[r][k] W[c][k] with both operands row-major and
+// K-contiguous.  A block of 256 threads (4 waves) computes a BX x BW tile of
+// C; waves are arranged WGX (along r) x 4/WGX (along c); each wave covers
+// 32 x 32 MFMA blocks.  The MFMA A-operand is X (rows of C), the B-operand
+// is W (columns of C), so consecutive lanes hold consecutive columns of C
+// and the stores are coalesced along c.  K is staged through LDS in BKB-byte
+// slices with a one-slice register prefetch.
+//
+// Per-lane operand layout: for a 32 x 32 block, lane i supplies row i % 32
+// and the K-half (i / 32) of each MFMA step; X and W use the same lane -> k
+// assignment, so each MFMA step accumulates every k of its slice exactly
+// once whatever the instruction's internal k order.
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<float> {  // v_mfma_f32_32x32x2_f32, 4 per 32-byte step
+  static constexpr int STEP = 32;
+  __device__ static inline void run(const i32x4* a, const i32x4* b, f32x16& c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(a[0].x), __int_as_float(b[0].x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(a[0].y), __int_as_float(b[0].y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(a[0].z), __int_as_float(b[0].z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(a[0].w), __int_as_float(b[0].w), c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<__bf16> {  // v_mfma_f32_32x32x16_bf16
+  static constexpr int STEP = 32;
+  __device__ static inline void run(const i32x4* a, const i32x4* b, f32x16& c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[0]),
+                                                __builtin_bit_cast(bf16x8, b[0]), c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<_Float16> {  // v_mfma_f32_32x32x16_f16
+  static constexpr int STEP = 32;
+  __device__ static inline void run(const i32x4* a, const i32x4* b, f32x16& c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a[0]),
+                                               __builtin_bit_cast(f16x8, b[0]), c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<fp8> {  // v_mfma_f32_32x32x64_f8f6f4, both operands E4M3, unit scales
+  static constexpr int STEP = 64;
+  __device__ static inline void run(const i32x4* a, const i32x4* b, f32x16& c) {
+    const i32x8 av = __builtin_shufflevector(a[0], a[1], 0, 1, 2, 3, 4, 5, 6, 7);
+    const i32x8 bv = __builtin_shufflevector(b[0], b[1], 0, 1, 2, 3, 4, 5, 6, 7);
+    // format 0 = E4M3 for A and B; E8M0 scale 127 = 2^0
+    c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, c, 0, 0, 0, 127, 0, 127);
+  }
+};
+
+template <typename T, int BX, int BW, int WGX, int BKB>
+__global__ __launch_bounds__(256) void gemm_nt(const GemmBatch* __restrict__ batches,
+                                               const T* __restrict__ X, int64_t ldx,
+                                               const T* __restrict__ W, int64_t ldw,
+                                               float* __restrict__ C, int64_t ldc, int nw,
+                                               int kdim, float alpha, int nx_single) {
+  constexpr int STEP = Mfma<T>::STEP;
+  constexpr int LB = STEP / 2;   // bytes per lane per step
+  constexpr int NV = LB / 16;    // 16-byte vectors per lane per step
+  constexpr int ROWB = BKB + 16; // padded LDS row
+  constexpr int WGW = 4 / WGX;
+  constexpr int WX = BX / WGX, WW = BW / WGW;
+  constexpr int NBX = WX / 32, NBW = WW / 32;
+  static_assert(NBX >= 1 && NBW >= 1, "tile too small");
+  static_assert(BKB % STEP == 0, "slice must hold whole steps");
+  constexpr int CPR = BKB / 16;  // 16-byte chunks per row per slice
+  constexpr int NCH = (BX + BW) * CPR;
+  constexpr int PER = (NCH + 255) / 256;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[(BX + BW) * ROWB];
+
+  // batched (one entry per blockIdx.z) or a single product with nx rows
+  const GemmBatch bt = batches ? batches[blockIdx.z] : GemmBatch{0, 0, 0, nx_single, 0};
+  const int nx = bt.nx;
+  const int x0 = blockIdx.y * BX;
+  const int w0 = blockIdx.x * BW;
+  if (x0 >= nx) return;  // uniform over the block
+  const unsigned char* Xb = reinterpret_cast<const unsigned char*>(X + bt.x_off);
+  const unsigned char* Wb = reinterpret_cast<const unsigned char*>(W + bt.w_off);
+  C += bt.c_off * ldc;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wx = (wave / WGW) * WX, ww = (wave % WGW) * WW;
+  const int r32 = lane & 31, g = lane >> 5;
+
+  const int64_t xrow = ldx * static_cast<int64_t>(sizeof(T));
+  const int64_t wrow = ldw * static_cast<int64_t>(sizeof(T));
+  i32x4 pre[PER];
+  auto gload = [&](int kb) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int c = tid + i * 256;
+      if (NCH % 256 == 0 || c < NCH) {
+        const int row = c / CPR, col = c % CPR;
+        const unsigned char* src =
+            row < BX ? Xb + (x0 + row) * xrow + kb + col * 16
+                     : Wb + static_cast<int64_t>(w0 + row - BX) * wrow + kb + col * 16;
+        pre[i] = *reinterpret_cast<const i32x4*>(src);
+      }
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int c = tid + i * 256;
+      if (NCH % 256 == 0 || c < NCH) {
+        const int row = c / CPR, col = c % CPR;
+        *reinterpret_cast<i32x4*>(lds + row * ROWB + col * 16) = pre[i];
+      }
+    }
+  };
+
+  f32x16 acc[NBX][NBW];
+#pragma unroll
+  for (int a = 0; a < NBX; ++a)
+#pragma unroll
+    for (int b = 0; b < NBW; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
+
+  const int kbytes = kdim * static_cast<int>(sizeof(T));
+  gload(0);
+  for (int kb = 0; kb < kbytes; kb += BKB) {
+    __syncthreads();
+    lstore();
+    __syncthreads();
+    if (kb + BKB < kbytes) gload(kb + BKB);
+#pragma unroll
+    for (int s = 0; s < BKB; s += STEP) {
+      i32x4 fa[NBX][NV], fb[NBW][NV];
+#pragma unroll
+      for (int a = 0; a < NBX; ++a) {
+        const unsigned char* p = lds + (wx + a * 32 + r32) * ROWB + s + g * LB;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fa[a][v] = *reinterpret_cast<const i32x4*>(p + 16 * v);
+      }
+#pragma unroll
+      for (int b = 0; b < NBW; ++b) {
+        const unsigned char* p = lds + (BX + ww + b * 32 + r32) * ROWB + s + g * LB;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fb[b][v] = *reinterpret_cast<const i32x4*>(p + 16 * v);
+      }
+#pragma unroll
+      for (int a = 0; a < NBX; ++a)
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) Mfma<T>::run(fa[a], fb[b], acc[a][b]);
+    }
+  }
+
+  // 32 x 32 accumulator layout: register v of lane i holds row
+  // 8 (v / 4) + 4 (i / 32) + v % 4 and column i % 32
+#pragma unroll
+  for (int a = 0; a < NBX; ++a)
+#pragma unroll
+    for (int b = 0; b < NBW; ++b) {
+      const int col = w0 + ww + b * 32 + r32;
+      if (col >= nw) continue;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = x0 + wx + a * 32 + 8 * (v / 4) + 4 * g + (v % 4);
+        if (row < nx) C[static_cast<int64_t>(row) * ldc + col] = alpha * acc[a][b][v];
+      }
+    }
+}
+
+// FP64 variant on v_mfma_f64_16x16x4_f64: 64 x 64 tile, 4 waves of 32 x 32,
+// each 2 x 2 blocks of 16 x 16.  Lane i supplies row i % 16 and k slot i / 16
+// of each 4-deep step; accumulator register v of lane i holds row
+// 4 v + i / 16, column i % 16 (the FP64 accumulator interleaves rows across
+// lane groups, unlike the FP32 32 x 32 layout).
+__global__ __launch_bounds__(256) void gemm_nt_f64(const double* __restrict__ X, int64_t ldx,
+                                                   const double* __restrict__ W, int64_t ldw,
+                                                   double* __restrict__ C, int64_t ldc, int nx,
+                                                   int nw, int kdim, double alpha) {
+  constexpr int BX = 64, BW = 64, BK = 16, ROW = BK + 1;
+  __shared__ double xs[BX * ROW];
+  __shared__ double ws[BW * ROW];
+  const int x0 = blockIdx.y * BX, w0 = blockIdx.x * BW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wx = (wave >> 1) * 32, ww = (wave & 1) * 32;
+  const int r16 = lane & 15, g = lane >> 4;
+  f64x4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.0;
+  for (int k0 = 0; k0 < kdim; k0 += BK) {
+    __syncthreads();
+    for (int e = tid; e < (BX + BW) * BK; e += 256) {
+      const int row = e / BK, col = e % BK;
+      if (row < BX)
+        xs[row * ROW + col] = X[static_cast<int64_t>(x0 + row) * ldx + k0 + col];
+      else
+        ws[(row - BX) * ROW + col] = W[static_cast<int64_t>(w0 + row - BX) * ldw + k0 + col];
+    }
+    __syncthreads();
+    for (int s = 0; s < BK; s += 4) {
+      double fa[2], fb[2];
+      for (int a = 0; a < 2; ++a) fa[a] = xs[(wx + a * 16 + r16) * ROW + s + g];
+      for (int b = 0; b < 2; ++b) fb[b] = ws[(ww + b * 16 + r16) * ROW + s + g];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int col = w0 + ww + b * 16 + r16;
+      if (col >= nw) continue;
+      for (int v = 0; v < 4; ++v) {
+        const int row = x0 + wx + a * 16 + 4 * v + g;
+        if (row < nx) C[static_cast<int64_t>(row) * ldc + col] = alpha * acc[a][b][v];
+      }
+    }
+}
+
+// ======================================================== SLRI fat stage ===
+//
+// g[l][p R + r] = gscale_p * sum_n V_p[n][r] xi_p[l][n], one thread per frame,
+// blockIdx.y = pair (the extra index P zero-fills the padding columns).
+
+template <typename T, int RMAX>
+__global__ __launch_bounds__(64) void slri_fat(const float* __restrict__ xiT, int64_t ldxi,
+                                               const int32_t* __restrict__ np,
+                                               const int32_t* __restrict__ off,
+                                               const float* __restrict__ V, int vrows, int R,
+                                               const float* __restrict__ gscale, int P, int Kc,
+                                               T* __restrict__ g) {
+  const int64_t l = blockIdx.x * 64 + threadIdx.x;
+  const int p = blockIdx.y;
+  T* gl = g + l * Kc;
+  if (p == P) {
+    for (int c = P * R; c < Kc; ++c) gl[c] = cvt<T>(0.0f);
+    return;
+  }
+  float acc[RMAX];
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) acc[r] = 0.0f;
+  const int n = 2 * np[p] + 1;
+  const float* xs = xiT + static_cast<int64_t>(off[p]) * ldxi + l;
+  const float* Vp = V + static_cast<int64_t>(p) * vrows * R;
+  for (int i = 0; i < n; ++i) {
+    const float xv = xs[static_cast<int64_t>(i) * ldxi];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+      if (r < R) acc[r] += Vp[i * R + r] * xv;
+  }
+  const float sc = gscale[p];
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r)
+    if (r < R) gl[p * R + r] = cvt<T>(acc[r] * sc);
+}
+
+// ========================================================= SSPI gather ===
+//
+// z[l][j] = sum_p sum_{q < Q} w[j][p][q] xi[start(j, p) + q][l].
+// A block of 4 waves owns 64 frames (one per lane) and 4 * JW locations
+// (JW consecutive locations per wave).  The GCC samples of the frame tile
+// are staged in LDS, lag-major ([lag][64 frames]), one chunk of pairs at a
+// time; the location and pair loops are wave-uniform, so tap starts and
+// weights come through scalar loads and every LDS read is a conflict-free
+// row read.
+
+template <typename TW>
+__device__ inline float wdecode(TW w);
+template <>
+__device__ inline float wdecode<float>(float w) { return w; }
+template <>
+__device__ inline float wdecode<__bf16>(__bf16 w) { return static_cast<float>(w); }
+template <>
+__device__ inline float wdecode<_Float16>(_Float16 w) { return static_cast<float>(w); }
+template <>
+__device__ inline float wdecode<fp8>(fp8 w) {
+  // E4M3 -> FP32: exponent bias 7 -> 127; subnormals m * 2^-9
+  const uint32_t c = w.bits;
+  const uint32_t s = (c & 0x80u) << 24;
+  const uint32_t em = c & 0x7Fu;
+  const float mag = (em >> 3) ? __uint_as_float(((em << 20) + (120u << 23))) : static_cast<float>(em) * 0x1p-9f;
+  return __uint_as_float(__float_as_uint(mag) | s);
+}
+
+template <typename TW, int Q, int JW>
+__global__ __launch_bounds__(256) void sspi_gather(const float* __restrict__ xiT, int64_t ldxi,
+                                                   int PN, const int32_t* __restrict__ start,
+                                                   const TW* __restrict__ w, int Qs,
+                                                   const int32_t* __restrict__ chunk_p0,
+                                                   int nchunks,
+                                                   const int32_t* __restrict__ off, int P,
+                                                   int64_t J, int L, float* __restrict__ z,
+                                                   int64_t ldz) {
+  extern __shared__ __attribute__((aligned(16))) float xs[];  // [rows][64]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t l0 = static_cast<int64_t>(blockIdx.y) * 64;
+  const int64_t jb = static_cast<int64_t>(blockIdx.x) * (4 * JW) + wave * JW;
+  float acc[JW];
+#pragma unroll
+  for (int i = 0; i < JW; ++i) acc[i] = 0.0f;
+
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int p0 = chunk_p0[ch], p1 = chunk_p0[ch + 1];
+    const int r0 = off[p0];
+    const int r1 = (p1 < P ? off[p1] : PN) + Q - 1;  // taps may run Q-1 past
+    const int rows = r1 - r0;
+    __syncthreads();
+    for (int e = tid; e < rows * 16; e += 256) {
+      const int row = e >> 4, c4 = e & 15;
+      f32x4 v = {0.f, 0.f, 0.f, 0.f};
+      if (r0 + row < PN) v = *reinterpret_cast<const f32x4*>(xiT + static_cast<int64_t>(r0 + row) * ldxi + l0 + c4 * 4);
+      *reinterpret_cast<f32x4*>(xs + row * 64 + c4 * 4) = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < JW; ++i) {
+      const int64_t j = jb + i;
+      if (j >= J) break;
+      const int32_t* st = start + j * P;
+      const TW* wj = w + j * P * Qs;
+      float a = acc[i];
+      for (int p = p0; p < p1; ++p) {
+        const int s = st[p] - r0;
+        const float* xr = xs + s * 64 + lane;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) a += wdecode<TW>(wj[p * Qs + q]) * xr[q * 64];
+      }
+      acc[i] = a;
+    }
+  }
+  const int64_t l = l0 + lane;
+  if (l >= L) return;
+  float* zl = z + l * ldz;
+#pragma unroll
+  for (int i = 0; i < JW; ++i) {
+    const int64_t j = jb + i;
+    if (j < J) zl[j] = acc[i];
+  }
+}
+
+// ================================================== plan-time kernels =====
+
+// Steering operand of conv. FD-SRP: H[j][p Kp + 2 (k-1) + {0,1}] =
+// (cos theta, -sin theta), theta = pi k x_p(j) / K (eq. (19) with (14)).  The
+// phase is reduced in FP64: theta = 2 pi (t - rint(t)), t = k x / (2K), and
+// sin/cos come from the FP64 sincospi.  Rows j >= J and slots k >= K are 0.
+template <typename T>
+__global__ void build_steering(const double* __restrict__ x, int P, int64_t J, int K, int Kp,
+                               T* __restrict__ H) {
+  const int64_t j = blockIdx.x;
+  const int slots = Kp / 2;
+  const int e = blockIdx.y * 256 + threadIdx.x;
+  if (e >= P * slots) return;
+  const int p = e / slots, kk = e % slots;
+  const int k = kk + 1;
+  double c = 0.0, s = 0.0;
+  if (j < J && k <= K - 1) {
+    const double t = static_cast<double>(k) * x[static_cast<int64_t>(p) * J + j] / (2.0 * K);
+    const double r = t - rint(t);
+    sincospi(2.0 * r, &s, &c);
+  }
+  T* h = H + j * static_cast<int64_t>(P) * Kp + static_cast<int64_t>(p) * Kp + 2 * kk;
+  h[0] = cvt64<T>(c);
+  h[1] = cvt64<T>(-s);
+}
+
+template <typename T>
+__global__ void convert_f32(const float* __restrict__ src, T* __restrict__ dst, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) dst[i] = cvt<T>(src[i]);
+}
+
+// xi^T [PN][ld] -> xi [L][PN]
+__global__ void transpose_xi(const float* __restrict__ xiT, int64_t ld, int PN, int L,
+                             float* __restrict__ xi) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= static_cast<int64_t>(PN) * L) return;
+  const int64_t l = i / PN, n = i % PN;
+  xi[i] = xiT[n * ld + l];
+}
+
+// ================================================================ host ====
+
+namespace {
+
+size_t dsize(int dtype) {
+  switch (dtype) {
+    case SRP_F32: return 4;
+    case SRP_BF16: return 2;
+    case SRP_F16: return 2;
+    case SRP_FP8_E4M3: return 1;
+    case SRP_F64: return 8;
+  }
+  return 4;
+}
+
+template <typename T>
+void launch_steering(const double* d_x, const HostPlan& hp, int Kp, int64_t Jpad, void* H) {
+  dim3 grid(static_cast<unsigned>(Jpad), (hp.P * (Kp / 2) + 255) / 256);
+  hipLaunchKernelGGL(build_steering<T>, grid, dim3(256), 0, 0, d_x, hp.P, hp.J, hp.K, Kp,
+                     static_cast<T*>(H));
+  check_launch("build_steering");
+}
+
+template <typename T>
+void launch_convert(const float* src, void* dst, int64_t n) {
+  hipLaunchKernelGGL(convert_f32<T>, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, 0,
+                     src, static_cast<T*>(dst), n);
+  check_launch("convert_f32");
+}
+
+void convert_dtype(int dtype, const float* src, void* dst, int64_t n) {
+  switch (dtype) {
+    case SRP_F32: HIP_OK(hipMemcpy(dst, src, n * 4, hipMemcpyDeviceToDevice)); break;
+    case SRP_BF16: launch_convert<__bf16>(src, dst, n); break;
+    case SRP_F16: launch_convert<_Float16>(src, dst, n); break;
+    case SRP_FP8_E4M3: launch_convert<fp8>(src, dst, n); break;
+    default: throw Error{SRP_E_UNSUPPORTED, "dtype not supported here"};
+  }
+}
+
+struct Alloc {
+  DevicePlan& dp;
+  size_t budget;
+  void* get(size_t bytes) {
+    if (budget && dp.resident_bytes + bytes > budget)
+      throw Error{SRP_E_BUDGET, "plan exceeds the HBM budget (" + std::to_string(dp.resident_bytes + bytes) +
+                                    " > " + std::to_string(budget) + " bytes)"};
+    void* p = nullptr;
+    HIP_OK(hipMalloc(&p, std::max<size_t>(bytes, 256)));
+    dp.resident_bytes += bytes;
+    return p;
+  }
+};
+
+template <typename T>
+void upload(void* dst, const std::vector<T>& v) {
+  HIP_OK(hipMemcpy(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// tile shapes of the launch configurations
+constexpr int BIG_BX = 256, BIG_BW = 128, BIG_WGX = 2, BIG_BKB = 128;
+constexpr int SMP_BX = 32, SMP_BW = 256, SMP_WGX = 1, SMP_BKB = 128;
+constexpr int SSPI_JW = 16;
+constexpr int SSPI_ROWS = 192;  // max LDS rows (lags) per pair chunk: 48 KB
+
+}  // namespace
+
+void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budget) {
+  (void)frame_tile;
+  dp.device = -1;
+  HIP_OK(hipGetDevice(&dp.device));
+  Alloc A{dp, budget};
+  const int P = hp.P;
+  // per-pair cross-spectrum slot: 2 (K - 1) reals padded to 128 elements
+  dp.Kp = static_cast<int>(round_up(2 * (hp.K - 1), 128));
+  dp.Jpad = round_up(hp.J, BIG_BW);
+  dp.d_pm = static_cast<int32_t*>(A.get(P * 4));
+  dp.d_pmp = static_cast<int32_t*>(A.get(P * 4));
+  dp.d_np = static_cast<int32_t*>(A.get(P * 4));
+  dp.d_off = static_cast<int32_t*>(A.get(P * 4));
+  upload(dp.d_pm, hp.pair_m);
+  upload(dp.d_pmp, hp.pair_mp);
+  upload(dp.d_np, hp.np);
+  upload(dp.d_off, hp.off);
+
+  if (hp.variant == SRP_FD) {
+    const size_t es = dsize(hp.dtype);
+    const size_t hbytes = static_cast<size_t>(dp.Jpad) * P * dp.Kp * es;
+    dp.d_H = A.get(hbytes);
+    double* d_x = nullptr;
+    HIP_OK(hipMalloc(&d_x, hp.x.size() * sizeof(double)));
+    try {
+      upload(d_x, hp.x);
+      switch (hp.dtype) {
+        case SRP_F32: launch_steering<float>(d_x, hp, dp.Kp, dp.Jpad, dp.d_H); break;
+        case SRP_BF16: launch_steering<__bf16>(d_x, hp, dp.Kp, dp.Jpad, dp.d_H); break;
+        case SRP_F16: launch_steering<_Float16>(d_x, hp, dp.Kp, dp.Jpad, dp.d_H); break;
+        case SRP_FP8_E4M3: launch_steering<fp8>(d_x, hp, dp.Kp, dp.Jpad, dp.d_H); break;
+        case SRP_F64: launch_steering<double>(d_x, hp, dp.Kp, dp.Jpad, dp.d_H); break;
+      }
+      HIP_OK(hipDeviceSynchronize());
+    } catch (...) {
+      hipFree(d_x);
+      throw;
+    }
+    HIP_OK(hipFree(d_x));
+    return;
+  }
+
+  // sampling table: row n + max_np holds 2 cos(pi k n / K), -2 sin(pi k n / K)
+  // in slots 2 (k - 1), 2 (k - 1) + 1; the angle pi (k n mod 2K) / K is
+  // reduced exactly in integers, then evaluated in FP64
+  dp.samp_rows = 2 * hp.max_np + 1;
+  {
+    const int rows = dp.samp_rows + SMP_BX;
+    std::vector<float> S(static_cast<size_t>(rows) * dp.Kp, 0.0f);
+    for (int i = 0; i < dp.samp_rows; ++i) {
+      const int64_t n = i - hp.max_np;
+      for (int k = 1; k < hp.K; ++k) {
+        int64_t m = (static_cast<int64_t>(k) * n) % (2 * hp.K);
+        if (m < 0) m += 2 * hp.K;
+        const double ang = M_PI * static_cast<double>(m) / hp.K;
+        S[static_cast<size_t>(i) * dp.Kp + 2 * (k - 1)] = static_cast<float>(2.0 * std::cos(ang));
+        S[static_cast<size_t>(i) * dp.Kp + 2 * (k - 1) + 1] = static_cast<float>(-2.0 * std::sin(ang));
+      }
+    }
+    dp.d_S = static_cast<float*>(A.get(S.size() * 4));
+    upload(dp.d_S, S);
+    std::vector<GemmBatch> sb(P);
+    for (int p = 0; p < P; ++p) {
+      sb[p].x_off = static_cast<int64_t>(hp.max_np - hp.np[p]) * dp.Kp;
+      sb[p].w_off = static_cast<int64_t>(p) * dp.Kp;
+      sb[p].c_off = hp.off[p];
+      sb[p].nx = 2 * hp.np[p] + 1;
+      sb[p].pad = 0;
+    }
+    dp.d_samp_batch = static_cast<GemmBatch*>(A.get(sizeof(GemmBatch) * P));
+    upload(dp.d_samp_batch, sb);
+  }
+
+  if (hp.variant == SRP_SLRI) {
+    if (hp.dtype == SRP_F64) throw Error{SRP_E_UNSUPPORTED, "SLRI has no FP64 path"};
+    const int R = hp.R;
+    const int vrows = 2 * hp.max_np + 1;
+    const int elem_per_slice = BIG_BKB / static_cast<int>(dsize(hp.dtype));
+    dp.Kc = static_cast<int>(round_up(static_cast<int64_t>(P) * R, elem_per_slice));
+    // per-pair weight scale (FP8 only) and a power-of-two activation scale
+    // bounding |g| by the format's range: |xi| <= 2 (K - 1) since |psi| <= 1
+    std::vector<float> sigma(P, 1.0f), gscale(P, 1.0f);
+    double amax_act = 0;
+    for (int p = 0; p < P; ++p) {
+      double umax = 0, vl1 = 0;
+      const double* Up = &hp.U[static_cast<size_t>(p) * hp.J * R];
+      for (size_t i = 0; i < static_cast<size_t>(hp.J) * R; ++i) umax = std::max(umax, std::fabs(Up[i]));
+      for (int r = 0; r < R; ++r) {
+        double s = 0;
+        for (int i = 0; i < vrows; ++i) s += std::fabs(hp.V[(static_cast<size_t>(p) * vrows + i) * R + r]);
+        vl1 = std::max(vl1, s);
+      }
+      if (hp.dtype == SRP_FP8_E4M3 && umax > 0) sigma[p] = static_cast<float>(std::exp2(std::ceil(std::log2(umax / 448.0))));
+      amax_act = std::max(amax_act, sigma[p] * vl1 * 2.0 * (hp.K - 1));
+    }
+    double act = 1.0;
+    if (hp.dtype == SRP_FP8_E4M3) act = std::exp2(std::ceil(std::log2(amax_act / 448.0)));
+    if (hp.dtype == SRP_F16 && amax_act > 60000.0) act = std::exp2(std::ceil(std::log2(amax_act / 60000.0)));
+    for (int p = 0; p < P; ++p) gscale[p] = static_cast<float>(sigma[p] / act);
+    dp.tall_alpha = static_cast<float>(act);
+
+    // U staged in FP32 as [Jpad][Kc], pair-major columns p R + r
+    std::vector<float> Us(static_cast<size_t>(dp.Jpad) * dp.Kc, 0.0f);
+    for (int p = 0; p < P; ++p) {
+      const double* Up = &hp.U[static_cast<size_t>(p) * hp.J * R];
+      const double inv = 1.0 / sigma[p];
+      for (int64_t j = 0; j < hp.J; ++j)
+        for (int r = 0; r < R; ++r)
+          Us[static_cast<size_t>(j) * dp.Kc + p * R + r] = static_cast<float>(Up[static_cast<size_t>(j) * R + r] * inv);
+    }
+    float* d_stage = nullptr;
+    HIP_OK(hipMalloc(&d_stage, Us.size() * 4));
+    try {
+      upload(d_stage, Us);
+      dp.d_U = A.get(Us.size() * dsize(hp.dtype));
+      convert_dtype(hp.dtype, d_stage, dp.d_U, static_cast<int64_t>(Us.size()));
+      HIP_OK(hipDeviceSynchronize());
+    } catch (...) {
+      hipFree(d_stage);
+      throw;
+    }
+    HIP_OK(hipFree(d_stage));
+    std::vector<float> Vf(hp.V.begin(), hp.V.end());
+    dp.d_V = static_cast<float*>(A.get(Vf.size() * 4));
+    upload(dp.d_V, Vf);
+    dp.d_gscale = static_cast<float*>(A.get(P * 4));
+    upload(dp.d_gscale, gscale);
+    return;
+  }
+
+  // SSPI
+  if (hp.dtype == SRP_F64) throw Error{SRP_E_UNSUPPORTED, "SSPI has no FP64 path"};
+  {
+    const int Q = hp.Q;
+    const int es = static_cast<int>(dsize(hp.dtype));
+    const int Qs = static_cast<int>(round_up(Q * es, 4) / es);
+    std::vector<int32_t> st(static_cast<size_t>(hp.J) * P);
+    std::vector<float> ws(static_cast<size_t>(hp.J) * P * Qs, 0.0f);
+    for (int64_t j = 0; j < hp.J; ++j)
+      for (int p = 0; p < P; ++p) {
+        const size_t jp = static_cast<size_t>(j) * P + p;
+        st[jp] = hp.off[p] + hp.start[jp] + hp.np[p];
+        for (int q = 0; q < hp.qp[p]; ++q) ws[jp * Qs + q] = static_cast<float>(hp.w[jp * Q + q]);
+      }
+    dp.d_start = static_cast<int32_t*>(A.get(st.size() * 4));
+    upload(dp.d_start, st);
+    float* d_stage = nullptr;
+    HIP_OK(hipMalloc(&d_stage, ws.size() * 4));
+    try {
+      upload(d_stage, ws);
+      dp.d_w = A.get(ws.size() * es);
+      convert_dtype(hp.dtype, d_stage, dp.d_w, static_cast<int64_t>(ws.size()));
+      HIP_OK(hipDeviceSynchronize());
+    } catch (...) {
+      hipFree(d_stage);
+      throw;
+    }
+    HIP_OK(hipFree(d_stage));
+    // pair chunks whose lags (plus Q - 1 spill rows) fit the LDS tile
+    dp.chunk_p0.clear();
+    int p = 0;
+    while (p < P) {
+      dp.chunk_p0.push_back(p);
+      int rows = 0;
+      int q = p;
+      while (q < P && (rows + 2 * hp.np[q] + 1 + Q - 1 <= SSPI_ROWS || q == p)) {
+        rows += 2 * hp.np[q] + 1;
+        ++q;
+      }
+      // one pair alone must fit the 160 KB of LDS: 64 frames x 4 B per lag row
+      if (rows + Q - 1 > 640) throw Error{SRP_E_UNSUPPORTED, "a pair has too many lags for the SSPI tile"};
+      p = q;
+    }
+    dp.chunk_p0.push_back(P);
+    dp.nchunks = static_cast<int>(dp.chunk_p0.size()) - 1;
+    dp.d_chunk_p0 = static_cast<int32_t*>(A.get(dp.chunk_p0.size() * 4));
+    upload(dp.d_chunk_p0, dp.chunk_p0);
+  }
+}
+
+void device_profile_collect(DevicePlan& dp,
+                            std::vector<std::pair<std::string, std::pair<double, int64_t>>>& out) {
+  out.clear();
+  for (const auto& sp : dp.spans) {
+    HIP_OK(hipEventSynchronize(sp.stop));
+    float ms = 0.0f;
+    HIP_OK(hipEventElapsedTime(&ms, sp.start, sp.stop));
+    auto it = std::find_if(out.begin(), out.end(), [&](const auto& e) { return e.first == sp.name; });
+    if (it == out.end()) {
+      out.push_back({sp.name, {0.0, 0}});
+      it = out.end() - 1;
+    }
+    it->second.first += ms;
+    it->second.second += 1;
+    dp.event_pool.push_back(sp.start);
+    dp.event_pool.push_back(sp.stop);
+  }
+  dp.spans.clear();
+}
+
+void device_free(DevicePlan& dp) {
+  for (const auto& sp : dp.spans) {
+    hipEventDestroy(sp.start);
+    hipEventDestroy(sp.stop);
+  }
+  for (hipEvent_t e : dp.event_pool) hipEventDestroy(e);
+  void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_samp_batch,
+                  dp.d_U, dp.d_V, dp.d_gscale, dp.d_start, dp.d_w, dp.d_chunk_p0,
+                  dp.ws};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  dp = DevicePlan{};
+}
+
+namespace {
+
+struct WsLayout {
+  int64_t Lc = 0, Lpad = 0;
+  size_t psi = 0, xi = 0, g = 0, total = 0;
+};
+
+WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t frame_tile) {
+  WsLayout w;
+  w.Lc = std::max<int64_t>(1, std::min(L, frame_tile));
+  w.Lpad = round_up(w.Lc, BIG_BX);
+  size_t psi_es = hp.variant == SRP_FD ? dsize(hp.dtype) : 4;
+  size_t off = 0;
+  w.psi = off;
+  off = align256(off + static_cast<size_t>(w.Lpad) * hp.P * dp.Kp * psi_es);
+  if (hp.variant != SRP_FD) {
+    w.xi = off;
+    off = align256(off + static_cast<size_t>(hp.PN) * w.Lpad * 4);
+  }
+  if (hp.variant == SRP_SLRI) {
+    w.g = off;
+    off = align256(off + static_cast<size_t>(w.Lpad) * dp.Kc * dsize(hp.dtype));
+  }
+  w.total = off;
+  return w;
+}
+
+template <typename TO, typename TC>
+void launch_phat(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L, TO* out,
+                 int64_t ld_l, int64_t ld_p, int kslots, hipStream_t st) {
+  if (L == 0) return;
+  dim3 grid((kslots + 63) / 64, static_cast<unsigned>(L));
+  const size_t lds = 2 * static_cast<size_t>(hp.M) * 64 * sizeof(TC);
+  TRACED(dp, "phat", st,
+         hipLaunchKernelGGL((phat_kernel<TO, TC>), grid, dim3(64), lds, st,
+                            static_cast<const float2*>(frames), hp.M, hp.K, hp.P, dp.d_pm, dp.d_pmp, out,
+                            ld_l, ld_p, kslots));
+  check_launch("phat_kernel");
+}
+
+void phat_dispatch(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L,
+                   void* out, int dtype, hipStream_t st) {
+  const int64_t ld_l = static_cast<int64_t>(hp.P) * dp.Kp;
+  const int kslots = dp.Kp / 2;
+  switch (dtype) {
+    case SRP_F32: launch_phat<float, float>(hp, dp, frames, L, static_cast<float*>(out), ld_l, dp.Kp, kslots, st); break;
+    case SRP_BF16: launch_phat<__bf16, float>(hp, dp, frames, L, static_cast<__bf16*>(out), ld_l, dp.Kp, kslots, st); break;
+    case SRP_F16: launch_phat<_Float16, float>(hp, dp, frames, L, static_cast<_Float16*>(out), ld_l, dp.Kp, kslots, st); break;
+    case SRP_FP8_E4M3: launch_phat<fp8, float>(hp, dp, frames, L, static_cast<fp8*>(out), ld_l, dp.Kp, kslots, st); break;
+    case SRP_F64: launch_phat<double, double>(hp, dp, frames, L, static_cast<double*>(out), ld_l, dp.Kp, kslots, st); break;
+  }
+}
+
+template <typename T>
+void launch_big_gemm(DevicePlan& dp, const char* kname, const void* X, int64_t ldx, const void* W, int64_t ldw,
+                     float* C, int64_t ldc, int nx, int nw, int kdim, float alpha, int64_t Lpad,
+                     hipStream_t st) {
+  dim3 grid(static_cast<unsigned>(dp.Jpad / BIG_BW), static_cast<unsigned>(Lpad / BIG_BX), 1);
+  TRACED(dp, kname, st,
+         hipLaunchKernelGGL((gemm_nt<T, BIG_BX, BIG_BW, BIG_WGX, BIG_BKB>), grid, dim3(256), 0, st,
+                            static_cast<const GemmBatch*>(nullptr), static_cast<const T*>(X), ldx,
+                            static_cast<const T*>(W), ldw, C, ldc, nw, kdim, alpha, nx));
+  check_launch("gemm_nt");
+}
+
+void launch_sampling(const HostPlan& hp, DevicePlan& dp, const float* psi, float* xiT,
+                     int64_t Lpad, hipStream_t st) {
+  dim3 grid(static_cast<unsigned>(Lpad / SMP_BW), static_cast<unsigned>((dp.samp_rows + SMP_BX - 1) / SMP_BX),
+            static_cast<unsigned>(hp.P));
+  TRACED(dp, "gemm_sampling", st,
+         hipLaunchKernelGGL((gemm_nt<float, SMP_BX, SMP_BW, SMP_WGX, SMP_BKB>), grid, dim3(256), 0, st,
+                            dp.d_samp_batch, dp.d_S, static_cast<int64_t>(dp.Kp), psi,
+                            static_cast<int64_t>(hp.P) * dp.Kp, xiT, Lpad, static_cast<int>(Lpad), dp.Kp, 1.0f,
+                            0));
+  check_launch("gemm_nt(sampling)");
+}
+
+template <typename T>
+void launch_fat(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t Lpad, void* g,
+                hipStream_t st) {
+  dim3 grid(static_cast<unsigned>(Lpad / 64), static_cast<unsigned>(hp.P + 1));
+  const int vrows = 2 * hp.max_np + 1;
+  if (hp.R <= 8)
+    TRACED(dp, "slri_fat", st,
+           hipLaunchKernelGGL((slri_fat<T, 8>), grid, dim3(64), 0, st, xiT, Lpad, dp.d_np, dp.d_off, dp.d_V,
+                              vrows, hp.R, dp.d_gscale, hp.P, dp.Kc, static_cast<T*>(g)));
+  else if (hp.R <= 16)
+    TRACED(dp, "slri_fat", st,
+           hipLaunchKernelGGL((slri_fat<T, 16>), grid, dim3(64), 0, st, xiT, Lpad, dp.d_np, dp.d_off, dp.d_V,
+                              vrows, hp.R, dp.d_gscale, hp.P, dp.Kc, static_cast<T*>(g)));
+  else if (hp.R <= 32)
+    TRACED(dp, "slri_fat", st,
+           hipLaunchKernelGGL((slri_fat<T, 32>), grid, dim3(64), 0, st, xiT, Lpad, dp.d_np, dp.d_off, dp.d_V,
+                              vrows, hp.R, dp.d_gscale, hp.P, dp.Kc, static_cast<T*>(g)));
+  else
+    throw Error{SRP_E_UNSUPPORTED, "SLRI rank per pair above 32 is not built"};
+  check_launch("slri_fat");
+}
+
+template <typename TW, int Q>
+void launch_sspi_q(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t Lpad,
+                   int64_t Lc, float* z, hipStream_t st) {
+  const int es = static_cast<int>(sizeof(TW));
+  const int Qs = static_cast<int>(round_up(Q * es, 4) / es);
+  int maxrows = 0;
+  for (int c = 0; c < dp.nchunks; ++c) {
+    const int p0 = dp.chunk_p0[c], p1 = dp.chunk_p0[c + 1];
+    const int r1 = p1 < hp.P ? hp.off[p1] : hp.PN;
+    maxrows = std::max(maxrows, r1 - hp.off[p0] + Q - 1);
+  }
+  const size_t lds = static_cast<size_t>(maxrows) * 64 * 4;
+  if (lds > 65536)
+    HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&sspi_gather<TW, Q, SSPI_JW>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  dim3 grid(static_cast<unsigned>((hp.J + 4 * SSPI_JW - 1) / (4 * SSPI_JW)), static_cast<unsigned>(Lpad / 64));
+  TRACED(dp, "sspi_gather", st,
+         hipLaunchKernelGGL((sspi_gather<TW, Q, SSPI_JW>), grid, dim3(256), lds, st, xiT, Lpad, hp.PN,
+                            dp.d_start, static_cast<const TW*>(dp.d_w), Qs, dp.d_chunk_p0, dp.nchunks, dp.d_off,
+                            hp.P, hp.J, static_cast<int>(Lc), z, hp.J));
+  check_launch("sspi_gather");
+}
+
+template <typename TW>
+void launch_sspi(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t Lpad, int64_t Lc,
+                 float* z, hipStream_t st) {
+  switch (hp.Q) {
+    case 1: launch_sspi_q<TW, 1>(hp, dp, xiT, Lpad, Lc, z, st); break;
+    case 2: launch_sspi_q<TW, 2>(hp, dp, xiT, Lpad, Lc, z, st); break;
+    case 3: launch_sspi_q<TW, 3>(hp, dp, xiT, Lpad, Lc, z, st); break;
+    case 4: launch_sspi_q<TW, 4>(hp, dp, xiT, Lpad, Lc, z, st); break;
+    case 5: launch_sspi_q<TW, 5>(hp, dp, xiT, Lpad, Lc, z, st); break;
+    case 6: launch_sspi_q<TW, 6>(hp, dp, xiT, Lpad, Lc, z, st); break;
+    case 7: launch_sspi_q<TW, 7>(hp, dp, xiT, Lpad, Lc, z, st); break;
+    case 8: launch_sspi_q<TW, 8>(hp, dp, xiT, Lpad, Lc, z, st); break;
+    default: throw Error{SRP_E_UNSUPPORTED, "SSPI with Q above 8 is not built"};
+  }
+}
+
+}  // namespace
+
+size_t workspace_bytes(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t frame_tile) {
+  return ws_layout(hp, dp, L, frame_tile).total;
+}
+
+static void* ensure_ws(DevicePlan& dp, void* ws, size_t ws_bytes, size_t need) {
+  if (ws) {
+    if (ws_bytes < need)
+      throw Error{SRP_E_INVALID, "workspace too small: " + std::to_string(ws_bytes) + " < " + std::to_string(need)};
+    if (reinterpret_cast<uintptr_t>(ws) & 255) throw Error{SRP_E_INVALID, "workspace must be 256-byte aligned"};
+    return ws;
+  }
+  if (dp.ws_bytes < need) {
+    if (dp.ws) HIP_OK(hipFree(dp.ws));
+    dp.ws = nullptr;
+    dp.ws_bytes = 0;
+    HIP_OK(hipMalloc(&dp.ws, need));
+    dp.ws_bytes = need;
+  }
+  return dp.ws;
+}
+
+void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L, void* maps,
+                    void* ws, size_t ws_bytes, int64_t frame_tile, hipStream_t st) {
+  if (L <= 0) return;
+  const WsLayout lay = ws_layout(hp, dp, L, frame_tile);
+  unsigned char* base = static_cast<unsigned char*>(ensure_ws(dp, ws, ws_bytes, lay.total));
+  const int64_t frame_elems = static_cast<int64_t>(hp.M) * (hp.K + 1);  // complex per frame
+  const int64_t ldpsi = static_cast<int64_t>(hp.P) * dp.Kp;
+  for (int64_t l0 = 0; l0 < L; l0 += lay.Lc) {
+    const int64_t Lc = std::min(lay.Lc, L - l0);
+    const void* fr = static_cast<const float2*>(frames) + l0 * frame_elems;
+    void* psi = base + lay.psi;
+    if (hp.variant == SRP_FD) {
+      phat_dispatch(hp, dp, fr, Lc, psi, hp.dtype, st);
+      if (hp.dtype == SRP_F64) {
+        double* z = static_cast<double*>(maps) + l0 * hp.J;
+        dim3 grid(static_cast<unsigned>((hp.J + 63) / 64), static_cast<unsigned>((Lc + 63) / 64));
+        TRACED(dp, "gemm_fd_f64", st,
+               hipLaunchKernelGGL(gemm_nt_f64, grid, dim3(256), 0, st, static_cast<const double*>(psi), ldpsi,
+                                  static_cast<const double*>(dp.d_H), ldpsi, z, hp.J, static_cast<int>(Lc),
+                                  static_cast<int>(hp.J), static_cast<int>(ldpsi), 2.0));
+        check_launch("gemm_nt_f64");
+        continue;
+      }
+      float* z = static_cast<float*>(maps) + l0 * hp.J;
+      switch (hp.dtype) {
+        case SRP_F32: launch_big_gemm<float>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, hp.J, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
+        case SRP_BF16: launch_big_gemm<__bf16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, hp.J, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
+        case SRP_F16: launch_big_gemm<_Float16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, hp.J, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
+        case SRP_FP8_E4M3: launch_big_gemm<fp8>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, hp.J, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
+      }
+      continue;
+    }
+    // sampling (SLRI, SSPI)
+    phat_dispatch(hp, dp, fr, Lc, psi, SRP_F32, st);
+    float* xiT = reinterpret_cast<float*>(base + lay.xi);
+    launch_sampling(hp, dp, static_cast<const float*>(psi), xiT, lay.Lpad, st);
+    float* z = static_cast<float*>(maps) + l0 * hp.J;
+    if (hp.variant == SRP_SLRI) {
+      void* g = base + lay.g;
+      switch (hp.dtype) {
+        case SRP_F32:
+          launch_fat<float>(hp, dp, xiT, lay.Lpad, g, st);
+          launch_big_gemm<float>(dp, "gemm_tall", g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          break;
+        case SRP_BF16:
+          launch_fat<__bf16>(hp, dp, xiT, lay.Lpad, g, st);
+          launch_big_gemm<__bf16>(dp, "gemm_tall", g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          break;
+        case SRP_F16:
+          launch_fat<_Float16>(hp, dp, xiT, lay.Lpad, g, st);
+          launch_big_gemm<_Float16>(dp, "gemm_tall", g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          break;
+        case SRP_FP8_E4M3:
+          launch_fat<fp8>(hp, dp, xiT, lay.Lpad, g, st);
+          launch_big_gemm<fp8>(dp, "gemm_tall", g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          break;
+      }
+    } else {
+      switch (hp.dtype) {
+        case SRP_F32: launch_sspi<float>(hp, dp, xiT, lay.Lpad, Lc, z, st); break;
+        case SRP_BF16: launch_sspi<__bf16>(hp, dp, xiT, lay.Lpad, Lc, z, st); break;
+        case SRP_F16: launch_sspi<_Float16>(hp, dp, xiT, lay.Lpad, Lc, z, st); break;
+        case SRP_FP8_E4M3: launch_sspi<fp8>(hp, dp, xiT, lay.Lpad, Lc, z, st); break;
+      }
+    }
+  }
+}
+
+void device_crossspec(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L, void* psi,
+                      hipStream_t st) {
+  const int64_t ld_p = 2 * (hp.K - 1);
+  launch_phat<float, float>(hp, dp, frames, L, static_cast<float*>(psi), hp.P * ld_p, ld_p, hp.K - 1, st);
+}
+
+void device_gcc_samples(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L, float* xi,
+                        void* ws, size_t ws_bytes, int64_t frame_tile, hipStream_t st) {
+  if (L <= 0) return;
+  const WsLayout lay = ws_layout(hp, dp, L, frame_tile);
+  unsigned char* base = static_cast<unsigned char*>(ensure_ws(dp, ws, ws_bytes, lay.total));
+  const int64_t frame_elems = static_cast<int64_t>(hp.M) * (hp.K + 1);
+  for (int64_t l0 = 0; l0 < L; l0 += lay.Lc) {
+    const int64_t Lc = std::min(lay.Lc, L - l0);
+    const void* fr = static_cast<const float2*>(frames) + l0 * frame_elems;
+    void* psi = base + lay.psi;
+    phat_dispatch(hp, dp, fr, Lc, psi, SRP_F32, st);
+    float* xiT = reinterpret_cast<float*>(base + lay.xi);
+    launch_sampling(hp, dp, static_cast<const float*>(psi), xiT, lay.Lpad, st);
+    const int64_t n = static_cast<int64_t>(hp.PN) * Lc;
+    TRACED(dp, "transpose_xi", st,
+           hipLaunchKernelGGL(transpose_xi, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
+                              xiT, lay.Lpad, hp.PN, static_cast<int>(Lc), xi + l0 * hp.PN));
+    check_launch("transpose_xi");
+  }
+}
+
+}  // namespace srp

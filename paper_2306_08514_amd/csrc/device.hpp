@@ -1,0 +1,85 @@
+// Device-resident plan operands and the hot-path launch sequence.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace srp {
+
+// One entry of a batched GEMM: element offsets of the three operands and the
+// number of valid output rows of that batch.
+struct GemmBatch {
+  int64_t x_off, w_off, c_off;
+  int nx;
+  int pad;
+};
+
+struct DevicePlan {
+  int device = -1;
+  // common
+  int Kp = 0;        // per-pair slot width of the cross-spectrum rows (elements)
+  int64_t Jpad = 0;  // rows of the resident weight operands
+  int32_t* d_pm = nullptr;   // pair tables
+  int32_t* d_pmp = nullptr;
+  int32_t* d_np = nullptr;
+  int32_t* d_off = nullptr;
+  // FD
+  void* d_H = nullptr;       // [Jpad][P*Kp] steering (cos, -sin) in dtype
+  // sampling (SLRI, SSPI)
+  float* d_S = nullptr;      // [2 max_np + 1 + 64][Kp] rows 2cos / -2sin
+  GemmBatch* d_samp_batch = nullptr;  // [P]
+  int samp_rows = 0;         // 2 max_np + 1
+  // SLRI
+  int Kc = 0;                // columns of the tall GEMM (P*R padded)
+  void* d_U = nullptr;       // [Jpad][Kc] in dtype
+  float* d_V = nullptr;      // [P][2 max_np + 1][R]
+  float* d_gscale = nullptr; // [P] activation scale of pair p in the fat stage
+  float tall_alpha = 1.0f;   // undoes the activation scale in the tall GEMM
+  // SSPI
+  int32_t* d_start = nullptr;  // [J][P] absolute stacked lag index of tap 0
+  void* d_w = nullptr;         // [J][P][Q] in dtype (f32, bf16, f16 or fp8)
+  std::vector<int32_t> chunk_p0;  // pair ranges whose lags fit one LDS tile
+  int32_t* d_chunk_p0 = nullptr;  // [nchunks + 1]
+  int nchunks = 0;
+  // per-kernel timing (see srp_profile_enable)
+  struct Span {
+    const char* name;
+    hipEvent_t start, stop;
+  };
+  bool profiling = false;
+  std::vector<Span> spans;
+  std::vector<hipEvent_t> event_pool;
+  // plan-owned workspace when the caller passes none
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t resident_bytes = 0;
+};
+
+// Allocates and fills the device operands of a plan.  Throws srp::Error.
+void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budget);
+void device_free(DevicePlan& dp);
+
+size_t workspace_bytes(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t frame_tile);
+
+// Enqueues the map computation for L frames on `stream`.
+void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L,
+                    void* maps, void* ws, size_t ws_bytes, int64_t frame_tile,
+                    hipStream_t stream);
+
+// Waits for the recorded spans and accumulates them per kernel name.
+void device_profile_collect(DevicePlan& dp, std::vector<std::pair<std::string, std::pair<double, int64_t>>>& out);
+
+void device_crossspec(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L,
+                      void* psi, hipStream_t stream);
+
+void device_gcc_samples(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L,
+                        float* xi, void* ws, size_t ws_bytes, int64_t frame_tile,
+                        hipStream_t stream);
+
+}  // namespace srp

@@ -1,0 +1,282 @@
+// Host-side FP64 plan construction.  See plan.hpp.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <functional>
+#include <thread>
+
+#include "../../include/srp.h"
+
+namespace srp {
+
+namespace {
+
+void fail(const std::string& msg) { throw Error{SRP_E_INVALID, msg}; }
+
+// Runs body(i) for i in [0, n) on up to `threads` threads.
+void parallel_for(int n, int threads, const std::function<void(int)>& body) {
+  threads = std::max(1, std::min(threads, n));
+  if (threads == 1) {
+    for (int i = 0; i < n; ++i) body(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::thread> pool;
+  std::vector<Error> errs(threads, Error{0, ""});
+  for (int t = 0; t < threads; ++t) {
+    pool.emplace_back([&, t] {
+      try {
+        for (int i = next++; i < n; i = next++) body(i);
+      } catch (const Error& e) {
+        errs[t] = e;
+      } catch (...) {
+        errs[t] = Error{SRP_E_NOMEM, "host allocation failed during plan build"};
+      }
+    });
+  }
+  for (auto& th : pool) th.join();
+  for (auto& e : errs)
+    if (e.code != 0) throw e;
+}
+
+}  // namespace
+
+double sinc_shift(double x, int n) {
+  // sin(pi (x - n)) = (-1)^(n + k0) sin(pi r) with x = k0 + r, |r| <= 1/2;
+  // the reduction x - rint(x) is exact in FP64.
+  const double d = x - static_cast<double>(n);
+  if (d == 0.0) return 1.0;
+  const double k0 = std::rint(x);
+  const double r = x - k0;
+  const double s = std::sin(M_PI * r);
+  const long long parity = (static_cast<long long>(k0) + n) & 1LL;
+  const double num = parity ? -s : s;
+  return num / (M_PI * d);
+}
+
+void build_geometry(HostPlan& hp, const double* mics, int M, const double* grid,
+                    int64_t J, double fs, int N, double c, int n_aux) {
+  if (!mics || !grid) fail("mics and grid must be non-NULL host pointers");
+  if (M < 2) fail("need at least 2 microphones");
+  if (M > 64) fail("at most 64 microphones are supported");
+  if (J < 1) fail("need at least one candidate location");
+  if (!(fs > 0) || !std::isfinite(fs)) fail("fs must be positive and finite");
+  if (N < 8 || (N & 1)) fail("N must be even and >= 8");
+  if (N > 16384) fail("N above 16384 is not supported");
+  if (!(c > 0) || !std::isfinite(c)) fail("speed of sound must be positive");
+  if (n_aux < 0) fail("n_aux must be >= 0");
+  for (int i = 0; i < 3 * M; ++i)
+    if (!std::isfinite(mics[i])) fail("non-finite microphone coordinate");
+  for (int64_t i = 0; i < 3 * J; ++i)
+    if (!std::isfinite(grid[i])) fail("non-finite grid coordinate");
+
+  hp.M = M;
+  hp.J = J;
+  hp.fs = fs;
+  hp.N = N;
+  hp.K = N / 2;
+  hp.c = c;
+  hp.n_aux = n_aux;
+  hp.P = M * (M - 1) / 2;
+  hp.mics.assign(mics, mics + 3 * M);
+  hp.grid.assign(grid, grid + 3 * J);
+
+  // pairs (m, m'), m > m', m' outer (the double sum of eq. (8))
+  hp.pair_m.clear();
+  hp.pair_mp.clear();
+  for (int mp = 0; mp < M - 1; ++mp)
+    for (int m = mp + 1; m < M; ++m) {
+      hp.pair_m.push_back(m);
+      hp.pair_mp.push_back(mp);
+    }
+
+  // N_p = floor(d_p fs / c) + N_aux, eq. (33)
+  hp.np.resize(hp.P);
+  hp.off.resize(hp.P);
+  hp.PN = 0;
+  hp.max_np = 0;
+  for (int p = 0; p < hp.P; ++p) {
+    const double* a = &mics[3 * hp.pair_m[p]];
+    const double* b = &mics[3 * hp.pair_mp[p]];
+    const double d = std::sqrt((a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]) +
+                               (a[2] - b[2]) * (a[2] - b[2]));
+    const int n_p = static_cast<int>(std::floor(d * fs / c)) + n_aux;
+    if (2 * n_p + 1 > N)
+      fail("frame too short: 2 N_p + 1 > N for a pair (lags would alias)");
+    hp.np[p] = n_p;
+    hp.off[p] = hp.PN;
+    hp.PN += 2 * n_p + 1;
+    hp.max_np = std::max(hp.max_np, n_p);
+  }
+  hp.mean_n = static_cast<double>(hp.PN) / hp.P;
+
+  // TDOA in samples, near field, eq. (3)
+  hp.x.assign(static_cast<size_t>(hp.P) * J, 0.0);
+  std::vector<double> dist(static_cast<size_t>(M));
+  for (int64_t j = 0; j < J; ++j) {
+    const double* q = &grid[3 * j];
+    for (int m = 0; m < M; ++m) {
+      const double* r = &mics[3 * m];
+      dist[m] = std::sqrt((r[0] - q[0]) * (r[0] - q[0]) + (r[1] - q[1]) * (r[1] - q[1]) +
+                          (r[2] - q[2]) * (r[2] - q[2]));
+    }
+    for (int p = 0; p < hp.P; ++p)
+      hp.x[static_cast<size_t>(p) * J + j] = (dist[hp.pair_m[p]] - dist[hp.pair_mp[p]]) * fs / c;
+  }
+}
+
+void sym_eig(std::vector<double>& a, int n, std::vector<double>& evals,
+             std::vector<double>& evecs) {
+  evecs.assign(static_cast<size_t>(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) evecs[static_cast<size_t>(i) * n + i] = 1.0;
+  auto A = [&](int i, int j) -> double& { return a[static_cast<size_t>(i) * n + j]; };
+  auto V = [&](int i, int j) -> double& { return evecs[static_cast<size_t>(i) * n + j]; };
+  double scale = 0;
+  for (int i = 0; i < n; ++i) scale = std::max(scale, std::fabs(A(i, i)));
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += A(i, j) * A(i, j);
+    if (off <= 1e-30 * scale * scale || off == 0) break;
+    for (int p = 0; p < n; ++p) {
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A(p, q);
+        if (std::fabs(apq) <= 1e-300) continue;
+        // rotation angle: t = tan(phi) solves t^2 + 2 theta t - 1 = 0 with
+        // theta = (a_qq - a_pp) / (2 a_pq); the smaller root is stable
+        const double theta = (A(q, q) - A(p, p)) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0);
+        const double sn = t * cs;
+        for (int k = 0; k < n; ++k) {  // columns p, q of A
+          const double akp = A(k, p), akq = A(k, q);
+          A(k, p) = cs * akp - sn * akq;
+          A(k, q) = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q of A
+          const double apk = A(p, k), aqk = A(q, k);
+          A(p, k) = cs * apk - sn * aqk;
+          A(q, k) = sn * apk + cs * aqk;
+        }
+        A(p, q) = A(q, p) = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V(k, p), vkq = V(k, q);
+          V(k, p) = cs * vkp - sn * vkq;
+          V(k, q) = sn * vkp + cs * vkq;
+        }
+      }
+    }
+  }
+  // sort descending
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int u, int v) { return A(u, u) > A(v, v); });
+  evals.resize(n);
+  std::vector<double> sorted(static_cast<size_t>(n) * n);
+  for (int c = 0; c < n; ++c) {
+    evals[c] = A(idx[c], idx[c]);
+    for (int r = 0; r < n; ++r) sorted[static_cast<size_t>(r) * n + c] = V(r, idx[c]);
+  }
+  evecs.swap(sorted);
+}
+
+void build_slri(HostPlan& hp, int R, int threads) {
+  if (R < 1) fail("rank must be >= 1");
+  const int nmax = 2 * hp.max_np + 1;
+  hp.R = std::min(R, nmax);
+  hp.rp.resize(hp.P);
+  const int64_t J = hp.J;
+  hp.U.assign(static_cast<size_t>(hp.P) * J * hp.R, 0.0);
+  hp.V.assign(static_cast<size_t>(hp.P) * nmax * hp.R, 0.0);
+  hp.sv.assign(static_cast<size_t>(hp.P) * nmax, 0.0);
+  parallel_for(hp.P, threads, [&](int p) {
+    const int n_p = hp.np[p];
+    const int n = 2 * n_p + 1;
+    const int r_p = std::min(R, n);
+    hp.rp[p] = r_p;
+    const double* x = &hp.x[static_cast<size_t>(p) * J];
+    // Gram matrix G = Lambda_p^T Lambda_p accumulated row by row in FP64
+    std::vector<double> G(static_cast<size_t>(n) * n, 0.0), lam(n);
+    for (int64_t j = 0; j < J; ++j) {
+      for (int i = 0; i < n; ++i) lam[i] = sinc_shift(x[j], i - n_p);
+      for (int a = 0; a < n; ++a) {
+        const double la = lam[a];
+        double* g = &G[static_cast<size_t>(a) * n];
+        for (int b = a; b < n; ++b) g[b] += la * lam[b];
+      }
+    }
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < a; ++b) G[static_cast<size_t>(a) * n + b] = G[static_cast<size_t>(b) * n + a];
+    // eigenvectors of G are the right singular vectors of Lambda_p,
+    // eigenvalues the squared singular values
+    std::vector<double> ev, vec;
+    sym_eig(G, n, ev, vec);
+    for (int i = 0; i < n; ++i) hp.sv[static_cast<size_t>(p) * nmax + i] = std::sqrt(std::max(0.0, ev[i]));
+    double* Vp = &hp.V[static_cast<size_t>(p) * nmax * hp.R];
+    for (int i = 0; i < n; ++i)
+      for (int r = 0; r < r_p; ++r) Vp[static_cast<size_t>(i) * hp.R + r] = vec[static_cast<size_t>(i) * n + r];
+    // U_p = Lambda_p V_p (= left singular vectors times singular values)
+    double* Up = &hp.U[static_cast<size_t>(p) * J * hp.R];
+    for (int64_t j = 0; j < J; ++j) {
+      for (int i = 0; i < n; ++i) lam[i] = sinc_shift(x[j], i - n_p);
+      for (int r = 0; r < r_p; ++r) {
+        double s = 0;
+        for (int i = 0; i < n; ++i) s += lam[i] * Vp[static_cast<size_t>(i) * hp.R + r];
+        Up[static_cast<size_t>(j) * hp.R + r] = s;
+      }
+    }
+  });
+}
+
+void build_sspi(HostPlan& hp, int Q, int threads) {
+  if (Q < 1) fail("Q must be >= 1");
+  const int nmax = 2 * hp.max_np + 1;
+  hp.Q = std::min(Q, nmax);
+  hp.qp.resize(hp.P);
+  for (int p = 0; p < hp.P; ++p) hp.qp[p] = std::min(Q, 2 * hp.np[p] + 1);
+  const int64_t J = hp.J;
+  hp.start.assign(static_cast<size_t>(J) * hp.P, 0);
+  hp.w.assign(static_cast<size_t>(J) * hp.P * hp.Q, 0.0);
+  const int chunks = 64;
+  parallel_for(chunks, threads, [&](int ch) {
+    const int64_t j0 = J * ch / chunks, j1 = J * (ch + 1) / chunks;
+    for (int64_t j = j0; j < j1; ++j) {
+      for (int p = 0; p < hp.P; ++p) {
+        const int n_p = hp.np[p];
+        const int q = hp.qp[p];
+        const double x = hp.x[static_cast<size_t>(p) * J + j];
+        // the q integers nearest to x, clamped to [-N_p, N_p]; |sinc(x - n)|
+        // decreases with |x - n|, so these are the q largest entries
+        double s = std::ceil(x - 0.5 * q);
+        s = std::min(std::max(s, static_cast<double>(-n_p)), static_cast<double>(n_p - q + 1));
+        const int si = static_cast<int>(s);
+        hp.start[static_cast<size_t>(j) * hp.P + p] = si;
+        double* w = &hp.w[(static_cast<size_t>(j) * hp.P + p) * hp.Q];
+        for (int t = 0; t < q; ++t) w[t] = sinc_shift(x, si + t);
+      }
+    }
+  });
+}
+
+void count_macs(HostPlan& hp) {
+  const double J = static_cast<double>(hp.J);
+  const double samp = 2.0 * hp.PN * (hp.K - 1);
+  if (hp.variant == SRP_FD) {
+    hp.macs_per_map = 2.0 * J * hp.P * (hp.K - 1);
+  } else if (hp.variant == SRP_SLRI) {
+    double tall = 0, fat = 0;
+    for (int p = 0; p < hp.P; ++p) {
+      tall += J * hp.rp[p];
+      fat += static_cast<double>(hp.rp[p]) * (2 * hp.np[p] + 1);
+    }
+    hp.macs_per_map = tall + fat + samp;
+  } else {
+    double nnz = 0;
+    for (int p = 0; p < hp.P; ++p) nnz += J * hp.qp[p];
+    hp.macs_per_map = nnz + samp;
+  }
+}
+
+}  // namespace srp

@@ -1,0 +1,82 @@
+// Host-side FP64 plan construction for the SRP-map library.
+//
+// Everything here depends only on the array geometry, the candidate grid and
+// the frequency resolution, so it is computed once, upfront (Sec. IV-B), in
+// FP64: pair enumeration, TDOAs, lag ranges, the per-pair low-rank factors of
+// the sinc interpolation matrices and the sparse interpolation windows.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace srp {
+
+struct HostPlan {
+  // geometry and sizes
+  int M = 0, P = 0, K = 0, N = 0;
+  int64_t J = 0;
+  double fs = 0, c = 0;
+  int n_aux = 0;
+  int variant = 0;  // srp_variant
+  int dtype = 0;    // srp_dtype
+  int requested = 0;
+
+  std::vector<double> mics;  // [M][3]
+  std::vector<double> grid;  // [J][3]
+  std::vector<int32_t> pair_m, pair_mp;  // [P]
+  std::vector<int32_t> np;               // N_p
+  std::vector<int32_t> off;              // stacked lag offset of pair p
+  int PN = 0;
+  int max_np = 0;
+  double mean_n = 0;
+
+  std::vector<double> x;  // [P][J] TDOA in samples
+
+  // SLRI (per-pair truncated SVD of Lambda_p)
+  int R = 0;                 // columns per pair in U (max_p R_p)
+  std::vector<int32_t> rp;   // R_p
+  std::vector<double> U;     // [P][J][R], zero for r >= R_p
+  std::vector<double> V;     // [P][2 max_np + 1][R], rows n + N_p, zero-padded
+  std::vector<double> sv;    // [P][2 max_np + 1] singular values, descending
+
+  // SSPI (Q largest-magnitude taps per (location, pair))
+  int Q = 0;                    // taps stored per (j, p) (max_p Q_p)
+  std::vector<int32_t> qp;      // Q_p
+  std::vector<int32_t> start;   // [J][P] first lag s (in -N_p..N_p)
+  std::vector<double> w;        // [J][P][Q], zero for q >= Q_p
+
+  double macs_per_map = 0;
+};
+
+// Validates the arguments and fills geometry, pairs, TDOAs and lag ranges.
+// Throws srp::Error on invalid input.
+void build_geometry(HostPlan& hp, const double* mics, int M, const double* grid,
+                    int64_t J, double fs, int N, double c, int n_aux);
+
+// Per-pair rank-R truncated SVD of Lambda_p (Sec. IV-A, eq. (54) per pair).
+void build_slri(HostPlan& hp, int R, int threads);
+
+// Per-(location, pair) Q-tap windows (Sec. IV-A, eq. (55) per row and pair).
+void build_sspi(HostPlan& hp, int Q, int threads);
+
+// Run-time MAC counts per map (eqs. (24), (61), (62); sampling by the
+// direct product, 2 PN (K-1)).
+void count_macs(HostPlan& hp);
+
+// sinc(x - n) for integer n, accurate for large |x| (argument reduced
+// exactly in FP64).
+double sinc_shift(double x, int n);
+
+// Symmetric eigendecomposition by cyclic Jacobi rotations.  a: n x n
+// row-major (destroyed), evals: n (descending), evecs: n x n row-major with
+// eigenvector i in column i.
+void sym_eig(std::vector<double>& a, int n, std::vector<double>& evals,
+             std::vector<double>& evecs);
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+}  // namespace srp

@@ -1,0 +1,226 @@
+"""ctypes binding of libsrp.so (the C ABI declared in include/srp.h).
+
+Argument marshalling only: every step of the SRP-map computation runs in the
+library's HIP kernels.  torch tensors provide device memory and streams; the
+library never sees a torch type.  If the library is missing this module
+raises at import of the binding, there is no fallback.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsrp.so")
+
+VARIANTS = {"fd": 0, "slri": 1, "sspi": 2}
+DTYPES = {"f32": 0, "bf16": 1, "f16": 2, "fp8": 3, "f64": 4}
+STATUS = {0: "SRP_OK", -1: "SRP_E_INVALID", -2: "SRP_E_NOMEM", -3: "SRP_E_UNSUPPORTED",
+          -4: "SRP_E_HIP", -5: "SRP_E_BUDGET"}
+
+# every function declared in include/srp.h
+EXPORTS = ["srp_default_opts", "srp_plan", "srp_workspace_size", "srp_compute",
+           "srp_crossspec", "srp_gcc_samples", "srp_plan_info_get", "srp_plan_export",
+           "srp_profile_enable", "srp_profile_collect", "srp_destroy", "srp_last_error"]
+
+
+class SrpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double), ("n_aux", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("device", ctypes.c_int), ("frame_tile", ctypes.c_int64),
+                ("hbm_budget", ctypes.c_size_t)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int), ("P", ctypes.c_int), ("K", ctypes.c_int),
+                ("J", ctypes.c_int64), ("PN", ctypes.c_int), ("max_np", ctypes.c_int),
+                ("rank_or_q", ctypes.c_int), ("variant", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("mean_n", ctypes.c_double), ("macs_per_map", ctypes.c_double),
+                ("device_bytes", ctypes.c_size_t), ("plan_seconds", ctypes.c_double)]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("total_ms", ctypes.c_double),
+                ("launches", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libsrp.so once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2306_08514_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    L.srp_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    L.srp_default_opts.restype = None
+    L.srp_plan.argtypes = [dp, ctypes.c_int, dp, i64, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                           ctypes.c_int, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+    L.srp_plan.restype = ctypes.c_int
+    L.srp_workspace_size.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_size_t)]
+    L.srp_workspace_size.restype = ctypes.c_int
+    L.srp_compute.argtypes = [vp, vp, i64, vp, vp, ctypes.c_size_t, vp]
+    L.srp_compute.restype = ctypes.c_int
+    L.srp_crossspec.argtypes = [vp, vp, i64, vp, vp]
+    L.srp_crossspec.restype = ctypes.c_int
+    L.srp_gcc_samples.argtypes = [vp, vp, i64, vp, vp]
+    L.srp_gcc_samples.restype = ctypes.c_int
+    L.srp_plan_info_get.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    L.srp_plan_info_get.restype = ctypes.c_int
+    L.srp_plan_export.argtypes = [vp, ctypes.c_char_p, vp, ctypes.c_size_t,
+                                  ctypes.POINTER(ctypes.c_size_t)]
+    L.srp_plan_export.restype = ctypes.c_int
+    L.srp_profile_enable.argtypes = [vp, ctypes.c_int]
+    L.srp_profile_enable.restype = ctypes.c_int
+    L.srp_profile_collect.argtypes = [vp, ctypes.POINTER(KernelTime), ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int)]
+    L.srp_profile_collect.restype = ctypes.c_int
+    L.srp_destroy.argtypes = [vp]
+    L.srp_destroy.restype = None
+    L.srp_last_error.argtypes = []
+    L.srp_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code != 0:
+        raise SrpError(code, lib().srp_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """An SRP-map plan: geometry-dependent operands resident on one device.
+
+    mics [M, 3], grid [J, 3] in metres (host arrays, copied); fs in Hz; N the
+    DFT length; variant in {"fd", "slri", "sspi"}; rank_or_q = R per pair
+    (SLRI) or Q per (location, pair) (SSPI); dtype in {"f32", "bf16", "f16",
+    "fp8", "f64"}; device = -1 builds the host-side plan only."""
+
+    def __init__(self, mics, grid, fs, N, variant, rank_or_q=0, dtype="f32", c=343.0, n_aux=2,
+                 device=0, frame_tile=1024, hbm_budget=0):
+        L = lib()
+        mics = np.ascontiguousarray(mics, dtype=np.float64)
+        grid = np.ascontiguousarray(grid, dtype=np.float64)
+        o = Opts()
+        L.srp_default_opts(ctypes.byref(o))
+        o.c, o.n_aux, o.dtype, o.device = float(c), int(n_aux), DTYPES[dtype], int(device)
+        o.frame_tile, o.hbm_budget = int(frame_tile), int(hbm_budget)
+        h = ctypes.c_void_p()
+        self._h = None
+        self._mics_ref = mics
+        _check(L.srp_plan(mics.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), mics.shape[0],
+                          grid.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), grid.shape[0],
+                          float(fs), int(N), VARIANTS[variant], int(rank_or_q), ctypes.byref(o),
+                          ctypes.byref(h)))
+        self._h = h
+        self.variant, self.dtype, self.device = variant, dtype, int(device)
+        self.N, self.K = int(N), int(N) // 2
+        i = self.info()
+        self.M, self.P, self.J, self.PN = i["M"], i["P"], i["J"], i["PN"]
+
+    # ---------------------------------------------------------------- info --
+    def info(self):
+        pi = PlanInfo()
+        _check(lib().srp_plan_info_get(self._h, ctypes.byref(pi)))
+        return {f: getattr(pi, f) for f, _ in PlanInfo._fields_}
+
+    def export(self, what):
+        need = ctypes.c_size_t()
+        _check(lib().srp_plan_export(self._h, what.encode(), None, 0, ctypes.byref(need)))
+        dt = np.int32 if what in ("np", "pairs", "sspi_start") else np.float64
+        buf = np.empty(need.value // np.dtype(dt).itemsize, dtype=dt)
+        _check(lib().srp_plan_export(self._h, what.encode(), buf.ctypes.data_as(ctypes.c_void_p),
+                                     buf.nbytes, ctypes.byref(need)))
+        return buf
+
+    def workspace_size(self, L):
+        b = ctypes.c_size_t()
+        _check(lib().srp_workspace_size(self._h, int(L), ctypes.byref(b)))
+        return b.value
+
+    # ------------------------------------------------------------- compute --
+    def _check_frames(self, frames):
+        import torch
+        if frames.dtype != torch.complex64 or not frames.is_cuda or not frames.is_contiguous():
+            raise ValueError("frames must be a contiguous complex64 CUDA tensor")
+        if frames.dim() != 3 or frames.shape[1] != self.M or frames.shape[2] != self.K + 1:
+            raise ValueError(f"frames must have shape [L, {self.M}, {self.K + 1}]")
+
+    def compute(self, frames, maps=None, workspace=None, stream=None):
+        """Enqueues one map per frame; returns maps [L, J] (float32, float64
+        for f64 plans).  frames: complex64 CUDA tensor [L, M, N/2 + 1]."""
+        import torch
+        self._check_frames(frames)
+        L = frames.shape[0]
+        odt = torch.float64 if self.dtype == "f64" else torch.float32
+        if maps is None:
+            maps = torch.empty((L, self.J), dtype=odt, device=frames.device)
+        elif maps.dtype != odt or maps.shape != (L, self.J) or not maps.is_contiguous():
+            raise ValueError("maps must be a contiguous [L, J] tensor of the plan's output dtype")
+        ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+        _check(lib().srp_compute(self._h, _ptr(frames), L, _ptr(maps), _ptr(workspace), ws_bytes,
+                                 _stream_handle(stream)))
+        return maps
+
+    def crossspec(self, frames, stream=None):
+        import torch
+        self._check_frames(frames)
+        out = torch.empty((frames.shape[0], self.P, self.K - 1), dtype=torch.complex64,
+                          device=frames.device)
+        _check(lib().srp_crossspec(self._h, _ptr(frames), frames.shape[0], _ptr(out),
+                                   _stream_handle(stream)))
+        return out
+
+    def gcc_samples(self, frames, stream=None):
+        import torch
+        self._check_frames(frames)
+        out = torch.empty((frames.shape[0], self.PN), dtype=torch.float32, device=frames.device)
+        _check(lib().srp_gcc_samples(self._h, _ptr(frames), frames.shape[0], _ptr(out),
+                                     _stream_handle(stream)))
+        return out
+
+    def profile(self, enable=True):
+        """Turns per-kernel event timing on or off (see srp_profile_enable)."""
+        _check(lib().srp_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_collect(self):
+        """{kernel name: (total ms, launches)} since the previous collect."""
+        arr = (KernelTime * 32)()
+        n = ctypes.c_int()
+        _check(lib().srp_profile_collect(self._h, arr, 32, ctypes.byref(n)))
+        return {arr[i].name.decode(): (arr[i].total_ms, arr[i].launches) for i in range(min(n.value, 32))}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().srp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

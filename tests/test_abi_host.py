@@ -1,0 +1,152 @@
+"""CPU tests of the C ABI: the library loads, exports every declared symbol,
+validates its arguments, and its FP64 host plan (pairs, TDOAs, lag ranges,
+SLRI factors, SSPI windows) agrees with the oracle.  No device calls."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as o
+from paper_2306_08514_amd import native, scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_or_skip():
+    if not os.path.exists(native.LIB_PATH):
+        pytest.skip("libsrp.so not built")
+    return native.lib()
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib_or_skip()
+    hdr = open(os.path.join(ROOT, "include", "srp.h")).read()
+    declared = set(re.findall(r"^\s*(?:srp_status|void|const char\*)\s+(srp_\w+)\s*\(", hdr, re.M))
+    assert declared == set(native.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def _host_plan(variant, rq, cfg_index=0, stride=4, **kw):
+    cfg = scenes.config(cfg_index, grid_stride=stride)
+    p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, rq, device=-1, **kw)
+    return p, cfg
+
+
+def test_host_plan_geometry_matches_oracle():
+    _lib_or_skip()
+    p, cfg = _host_plan("sspi", 4, cfg_index=1, stride=7)
+    x_ref = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    x = p.export("tdoa").reshape(x_ref.shape)
+    np.testing.assert_allclose(x, x_ref, rtol=0, atol=1e-11)
+    np.testing.assert_array_equal(p.export("np"), o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2))
+    np.testing.assert_array_equal(p.export("pairs").reshape(-1, 2), np.array(o.pairs(8)))
+    info = p.info()
+    assert info["PN"] == 660 and info["P"] == 28 and info["K"] == 512
+    assert info["mean_n"] == pytest.approx(660 / 28)
+    assert info["device_bytes"] == 0
+
+
+def test_host_plan_slri_factors_match_oracle_svd():
+    """U_p V_p^T (the rank-R truncation, unique when sigma_R > sigma_{R+1})
+    agrees with numpy's SVD; singular values agree."""
+    _lib_or_skip()
+    R = 5
+    p, cfg = _host_plan("slri", R, cfg_index=1, stride=5)
+    x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+    fac = o.slri_factors(x, Np, R)
+    P, J = x.shape
+    nmax = 2 * Np.max() + 1
+    U = p.export("slri_u").reshape(P, J, R)
+    V = p.export("slri_v").reshape(P, nmax, R)
+    S = p.export("slri_s").reshape(P, nmax)
+    for q in range(P):
+        n = 2 * Np[q] + 1
+        Uo, Vo, so = fac[q]
+        np.testing.assert_allclose(S[q, :n], so, rtol=1e-9, atol=1e-12 * so[0])
+        prod = U[q] @ V[q, :n].T
+        ref = Uo @ Vo.T
+        assert np.linalg.norm(prod - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_host_plan_sspi_windows_match_oracle_selection():
+    _lib_or_skip()
+    Q = 4
+    p, cfg = _host_plan("sspi", Q, cfg_index=1, stride=5)
+    x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+    P, J = x.shape
+    st = p.export("sspi_start").reshape(J, P)
+    w = p.export("sspi_w").reshape(J, P, Q)
+    for q in range(P):
+        lags, wts = o.sspi_select(x[q], Np[q], Q)
+        np.testing.assert_array_equal(st[:, q], lags[:, 0])
+        np.testing.assert_allclose(w[:, q, :], wts, rtol=0, atol=1e-14)
+
+
+def test_mac_counts_follow_complexity_model():
+    _lib_or_skip()
+    cfg = scenes.config(1, grid_stride=5)
+    J = cfg["grid"].shape[0]
+    fd = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], "fd", device=-1)
+    assert fd.info()["macs_per_map"] == 2 * J * 28 * 511
+    sl = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], "slri", 8, device=-1)
+    c = o.complexity(J=J, P=28, K=512, N=660 / 28, R_lambda=28 * 8, sampling="direct")
+    # per-pair rank R is a block-diagonal fat factor: R PN_p per pair
+    assert sl.info()["macs_per_map"] == pytest.approx(J * 28 * 8 + 8 * 660 + 2 * 660 * 511)
+    assert c["C_samp"] == 2 * 660 * 511
+    sp = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], "sspi", 4, device=-1)
+    assert sp.info()["macs_per_map"] == pytest.approx(J * 28 * 4 + 2 * 660 * 511)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(N=511), -1),                          # odd N
+    (dict(N=16), -1),                           # 2 N_p + 1 = 31 > N (lags alias)
+    (dict(fs=-1.0), -1),
+    (dict(variant="slri", rq=0), -1),
+    (dict(variant="slri", rq=33), -3),
+    (dict(variant="sspi", rq=9), -3),
+    (dict(variant="slri", rq=4, dtype="f64"), -3),
+    (dict(M=1), -1),
+])
+def test_invalid_arguments_return_error_codes(kw, code):
+    _lib_or_skip()
+    cfg = scenes.config(0, grid_stride=8)
+    mics = cfg["mics"][: kw.get("M", 4)]
+    with pytest.raises(native.SrpError) as ei:
+        native.Plan(mics, cfg["grid"], kw.get("fs", cfg["fs"]), kw.get("N", cfg["N"]),
+                    kw.get("variant", "fd"), kw.get("rq", 0), dtype=kw.get("dtype", "f32"),
+                    device=-1)
+    assert ei.value.code == code
+    assert native.lib().srp_last_error().decode() != ""
+
+
+def test_non_finite_geometry_and_null_out():
+    L = _lib_or_skip()
+    cfg = scenes.config(0, grid_stride=8)
+    grid = cfg["grid"].copy()
+    grid[3, 1] = np.nan
+    with pytest.raises(native.SrpError) as ei:
+        native.Plan(cfg["mics"], grid, cfg["fs"], cfg["N"], "fd", device=-1)
+    assert ei.value.code == -1
+    # NULL out pointer
+    m = np.ascontiguousarray(cfg["mics"])
+    g = np.ascontiguousarray(cfg["grid"])
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = L.srp_plan(m.ctypes.data_as(dp), 4, g.ctypes.data_as(dp), g.shape[0], 16000.0, 512, 0, 0, None, None)
+    assert rc == -1
+
+
+def test_host_only_plan_refuses_compute_and_export_of_missing_data():
+    L = _lib_or_skip()
+    p, _ = _host_plan("fd", 0)
+    rc = L.srp_compute(p._h, ctypes.c_void_p(16), 4, ctypes.c_void_p(16), None, 0, None)
+    assert rc == -1
+    assert L.srp_compute(p._h, None, 0, None, None, 0, None) == 0   # L = 0 is a no-op
+    with pytest.raises(native.SrpError):
+        p.export("slri_u")
+    L.srp_destroy(None)   # safe on NULL

@@ -1,0 +1,243 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, on the
+same seeded inputs.
+
+Tolerances (per map, relative L2 error against the same-variant FP64
+oracle): 1e-5 for FP32 operands and 1e-2 for BF16/FP16 operands, the bounds
+the path is built to; FP64 FD 1e-12; FP8 is reported against 6e-2 (E4M3
+has a 2^-4 relative step).  Argmax must agree except on near-tie frames,
+where the GPU's pick must lie within the error band of the oracle's maximum.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as o
+from paper_2306_08514_amd import scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "bf16": 1e-2, "f16": 1e-2, "fp8": 6e-2, "f64": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def native():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_08514_amd import native as nat
+    nat.lib()
+    return nat
+
+
+def _announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _oracle_maps(variant, Y, cfg, rq, cols=None):
+    """FP64 oracle maps for the variant, at the grid columns `cols`."""
+    x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+    K = cfg["N"] // 2
+    psi = o.phat(Y)
+    if variant == "fd":
+        xs = x if cols is None else x[:, cols]
+        return o.fd_map(psi, xs, K)
+    xi = o.gcc_samples_ifft(psi, Np, K)
+    if variant == "slri":
+        fac = o.slri_factors(x, Np, rq)
+        if cols is not None:
+            fac = [(U[cols], V, s) for (U, V, s) in fac]
+        return o.slri_map(xi, fac)
+    xs = x if cols is None else x[:, cols]
+    sel = [o.sspi_select(xs[p], Np[p], rq) for p in range(len(Np))]
+    return o.sspi_map(xi, sel, Np)
+
+
+def _check_maps(z, z_ref, tol, label):
+    z = np.asarray(z, dtype=np.float64)
+    rel = o.rel_error(z, z_ref)
+    worst = float(rel.max())
+    assert np.all(np.isfinite(z)), label
+    assert worst <= tol, f"{label}: max rel error {worst:.3e} > {tol:.1e} (median {np.median(rel):.3e})"
+    # argmax up to near ties
+    a_gpu = o.argmax_map(z)
+    a_ref = o.argmax_map(z_ref)
+    err = np.abs(z - z_ref).max(axis=1)
+    top = z_ref.max(axis=1)
+    picked = z_ref[np.arange(len(z_ref)), a_gpu]
+    bad = (a_gpu != a_ref) & (picked < top - 2 * err - 1e-12 * np.abs(top))
+    assert not bad.any(), f"{label}: argmax disagrees beyond the error band on frames {np.nonzero(bad)[0][:10]}"
+    return worst
+
+
+def _plan(native, cfg, variant, rq=0, dtype="f32", **kw):
+    return native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, rq, dtype=dtype, **kw)
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    cfg = scenes.config(0)
+    Y = scenes.make_frames(cfg)
+    return cfg, Y
+
+
+@pytest.fixture(scope="module")
+def cfg1_small():
+    # config-2 geometry on a 17 x 17 x 17 subgrid (J = 4913, not a tile
+    # multiple), 37 frames (ragged)
+    cfg = scenes.config(1, L=37, grid_stride=3)
+    Y = scenes.make_frames(cfg)
+    return cfg, Y
+
+
+# ----------------------------------------------------------- stages -------
+
+def test_crossspec_matches_phat(native, cfg0):
+    cfg, Y = cfg0
+    _announce("crossspec config0")
+    p = _plan(native, cfg, "fd")
+    psi = p.crossspec(torch.from_numpy(Y).cuda()).cpu().numpy()
+    torch.cuda.synchronize()
+    ref = o.phat(Y)
+    assert np.abs(psi - ref).max() <= 2e-6
+    # zeros in the input give zero cross-spectra
+    Z = scenes.random_frames(3, 9, 4, cfg["N"], zero_fraction=0.2)
+    psi = p.crossspec(torch.from_numpy(Z).cuda()).cpu().numpy()
+    ref = o.phat(Z)
+    assert np.abs(psi - ref).max() <= 2e-6
+    assert np.all(psi[ref == 0] == 0)
+
+
+def test_gcc_samples_match_ifft(native, cfg0, cfg1_small):
+    for cfg, Y in (cfg0, cfg1_small):
+        _announce(f"gcc_samples config{cfg['index']}")
+        p = _plan(native, cfg, "sspi", 4)
+        xi = p.gcc_samples(torch.from_numpy(Y).cuda()).cpu().numpy()
+        Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+        ref = o.stack_samples(o.gcc_samples_ifft(o.phat(Y), Np, cfg["N"] // 2))
+        scale = np.abs(ref).max(axis=1, keepdims=True)
+        assert (np.abs(xi - ref) / scale).max() <= 1e-5
+
+
+# ------------------------------------------------------------ maps --------
+
+@pytest.mark.parametrize("variant,rq", [("fd", 0), ("slri", 8), ("sspi", 4)])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16", "fp8"])
+def test_maps_config0(native, cfg0, variant, rq, dtype):
+    cfg, Y = cfg0
+    _announce(f"maps config0 {variant} {dtype}")
+    p = _plan(native, cfg, variant, rq, dtype)
+    z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
+    ref = _oracle_maps(variant, Y, cfg, rq)
+    worst = _check_maps(z, ref, TOL[dtype], f"config0 {variant} {dtype}")
+    print(f"config0 {variant} {dtype}: max rel {worst:.2e}")
+
+
+def test_fd_f64_config0(native, cfg0):
+    cfg, Y = cfg0
+    _announce("maps config0 fd f64")
+    p = _plan(native, cfg, "fd", 0, "f64")
+    z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
+    assert z.dtype == np.float64
+    _check_maps(z, _oracle_maps("fd", Y, cfg, 0), TOL["f64"], "config0 fd f64")
+
+
+@pytest.mark.parametrize("variant,rq", [("fd", 0), ("slri", 8), ("slri", 31), ("sspi", 4),
+                                        ("sspi", 1), ("sspi", 8)])
+def test_maps_ragged_config1_geometry(native, cfg1_small, variant, rq):
+    cfg, Y = cfg1_small
+    _announce(f"maps config1-small {variant} {rq}")
+    p = _plan(native, cfg, variant, rq)
+    z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
+    _check_maps(z, _oracle_maps(variant, Y, cfg, rq), TOL["f32"], f"ragged {variant} {rq}")
+
+
+def test_full_rank_slri_and_dense_sspi_agree_on_gpu(native, cfg1_small):
+    """R_p = Q_p = 2 N_p + 1 for every pair (max lag count 31) reproduce SI."""
+    cfg, Y = cfg1_small
+    _announce("full-rank slri / dense sspi")
+    Yt = torch.from_numpy(Y).cuda()
+    zs = _plan(native, cfg, "slri", 31).compute(Yt).cpu().numpy()
+    x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+    z_si = o.si_map(o.gcc_samples_ifft(o.phat(Y), Np, cfg["N"] // 2), x, Np)
+    _check_maps(zs, z_si, 1e-5, "slri full rank vs SI")
+
+
+# ---------------------------------------------------------- edge cases ----
+
+def test_edge_cases(native, cfg0):
+    cfg, Y = cfg0
+    _announce("edge cases")
+    p = _plan(native, cfg, "sspi", 3)
+    empty = torch.empty((0, 4, cfg["N"] // 2 + 1), dtype=torch.complex64, device="cuda")
+    assert p.compute(empty).shape == (0, cfg["grid"].shape[0])
+    one = p.compute(torch.from_numpy(Y[:1]).cuda()).cpu().numpy()
+    _check_maps(one, _oracle_maps("sspi", Y[:1], cfg, 3), 1e-5, "L=1")
+    # two microphones (one pair), a single candidate
+    cfg2 = dict(cfg)
+    cfg2["mics"] = cfg["mics"][:2]
+    cfg2["grid"] = cfg["grid"][5:6]
+    Y2 = np.ascontiguousarray(Y[:5, :2])
+    for variant, rq in (("fd", 0), ("slri", 2), ("sspi", 2)):
+        q = _plan(native, cfg2, variant, rq)
+        z = q.compute(torch.from_numpy(Y2).cuda()).cpu().numpy()
+        ref = _oracle_maps(variant, Y2, cfg2, rq)
+        assert np.abs(z - ref).max() <= 1e-5 * np.abs(ref).max() + 1e-6
+    # frames with exact zeros
+    Z = scenes.random_frames(5, 7, 4, cfg["N"], zero_fraction=0.3)
+    z = p.compute(torch.from_numpy(Z).cuda()).cpu().numpy()
+    _check_maps(z, _oracle_maps("sspi", Z, cfg, 3), 1e-5, "zeros")
+
+
+def test_batch_invariance_and_workspace(native, cfg1_small):
+    """A frame's map does not depend on the other frames of the batch
+    (bitwise), nor on whether the caller passes a workspace or which
+    stream runs it."""
+    cfg, Y = cfg1_small
+    _announce("batch invariance")
+    Yt = torch.from_numpy(Y).cuda()
+    for variant, rq in (("fd", 0), ("slri", 8), ("sspi", 4)):
+        p = _plan(native, cfg, variant, rq, "bf16" if variant != "fd" else "f32")
+        full = p.compute(Yt)
+        part = p.compute(Yt[5:9].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(full[5:9], part), variant
+        ws = torch.empty(p.workspace_size(Y.shape[0]), dtype=torch.uint8, device="cuda")
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            again = p.compute(Yt, workspace=ws, stream=s)
+        s.synchronize()
+        assert torch.equal(full, again), variant
+
+
+# ------------------------------------------------- full-size config 2 -----
+
+@pytest.fixture(scope="module")
+def cfg1_full():
+    cfg = scenes.config(1)
+    Y = scenes.make_frames(cfg)
+    return cfg, Y
+
+
+@pytest.mark.parametrize("variant,rq,dtype", [("fd", 0, "f32"), ("slri", 8, "f32"), ("sspi", 4, "f32"),
+                                              ("slri", 8, "bf16"), ("sspi", 4, "bf16"),
+                                              ("fd", 0, "bf16")])
+def test_full_size_config1_sampled(native, cfg1_full, variant, rq, dtype):
+    """J = 125,000 and L = 1000 in the benchmark's launch configuration;
+    the oracle evaluates 12 frames at 3000 sampled candidates."""
+    cfg, Y = cfg1_full
+    _announce(f"full config1 {variant} {dtype}")
+    p = _plan(native, cfg, variant, rq, dtype)
+    z = p.compute(torch.from_numpy(Y).cuda())
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    frames = np.sort(rng.choice(Y.shape[0], 12, replace=False))
+    cols = np.sort(rng.choice(cfg["grid"].shape[0], 3000, replace=False))
+    zs = z[torch.from_numpy(frames).cuda()][:, torch.from_numpy(cols).cuda()].cpu().numpy()
+    ref = _oracle_maps(variant, Y[frames], cfg, rq, cols=cols)
+    rel = o.rel_error(zs, ref)
+    assert np.all(np.isfinite(zs))
+    assert rel.max() <= TOL[dtype], f"max rel {rel.max():.3e}"
+    del z, p
+    torch.cuda.empty_cache()
