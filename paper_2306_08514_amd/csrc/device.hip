@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/srp.h"
@@ -448,13 +449,25 @@ __global__ __launch_bounds__(64) void slri_fat(const float* __restrict__ xiT, in
 
 // ========================================================= SSPI gather ===
 //
-// z[l][j] = sum_p sum_{q < Q} w[j][p][q] xi[start(j, p) + q][l].
-// A block of 4 waves owns 64 frames (one per lane) and 4 * JW locations
-// (JW consecutive locations per wave).  The GCC samples of the frame tile
-// are staged in LDS, lag-major ([lag][64 frames]), one chunk of pairs at a
-// time; the location and pair loops are wave-uniform, so tap starts and
-// weights come through scalar loads and every LDS read is a conflict-free
-// row read.
+// z[l][j] = sum_p sum_{q < Q} w[p][j][q] xi[start(p, j) + q][l].
+// One lane per candidate location j (256 per block) and FT frames per block,
+// accumulated in registers.  The GCC samples of the frame tile are staged in
+// LDS lag-major ([lag][FT frames], rows padded by 4 words so that lanes
+// reading nearby lags hit different banks), one chunk of pairs at a time;
+// each lane gathers the rows of its own Q-tap windows with 16-byte reads
+// (4 frames each).  Starts and weights are per-lane coalesced vector loads.
+//
+// PAIRS = true (16-bit and FP8 weights): LDS holds packed FP16 "sliding
+// pairs" E[n][l] = (xi[n][l], xi[n+1][l]) and two taps are applied by one
+// v_dot2_f32_f16 with FP32 accumulation, halving LDS bytes per FMA.
+//
+// Blocks are ordered for the 8 XCDs (workgroups are dispatched round-robin
+// over XCDs): XCD x walks a contiguous range of location tiles with the
+// frame tiles innermost, so a tile's starts and weights stay in that XCD's
+// L2 across all frame tiles.
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename TW>
 __device__ inline float wdecode(TW w);
@@ -468,66 +481,154 @@ template <>
 __device__ inline float wdecode<fp8>(fp8 w) {
   // E4M3 -> FP32: exponent bias 7 -> 127; subnormals m * 2^-9
   const uint32_t c = w.bits;
-  const uint32_t s = (c & 0x80u) << 24;
+  const uint32_t sg = (c & 0x80u) << 24;
   const uint32_t em = c & 0x7Fu;
   const float mag = (em >> 3) ? __uint_as_float(((em << 20) + (120u << 23))) : static_cast<float>(em) * 0x1p-9f;
-  return __uint_as_float(__float_as_uint(mag) | s);
+  return __uint_as_float(__float_as_uint(mag) | sg);
 }
 
-template <typename TW, int Q, int JW>
+// Tap i of a weight record held as 32-bit words (no type punning through
+// pointers: the element is extracted by shifts and bit casts).
+template <typename TW>
+__device__ inline float tap(const uint32_t* wv, int i) {
+  if constexpr (sizeof(TW) == 4) {
+    return __uint_as_float(wv[i]);
+  } else if constexpr (sizeof(TW) == 2) {
+    const uint16_t b = static_cast<uint16_t>(wv[i / 2] >> (16 * (i % 2)));
+    return wdecode<TW>(__builtin_bit_cast(TW, b));
+  } else {
+    const uint8_t b = static_cast<uint8_t>(wv[i / 4] >> (8 * (i % 4)));
+    return wdecode<TW>(fp8{b});
+  }
+}
+
+__device__ inline uint32_t pack_h2(float a, float b) {
+  const h2 v = {static_cast<_Float16>(a), static_cast<_Float16>(b)};
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+// Maps a linear block id to (location tile, frame tile) so that the blocks an
+// XCD receives (ids x, x + 8, x + 16, ...) cover consecutive pairs of a
+// location-major, frame-minor enumeration.
+__device__ inline bool xcd_tile(int nj, int nf, int& jt, int& ft) {
+  const int b = blockIdx.x;
+  const int per = static_cast<int>(gridDim.x) / 8;  // grid is a multiple of 8
+  const int g = (b % 8) * per + b / 8;
+  if (g >= nj * nf) return false;
+  jt = g / nf;
+  ft = g % nf;
+  return true;
+}
+
+template <typename TW, int Q, int FT, bool PAIRS>
 __global__ __launch_bounds__(256) void sspi_gather(const float* __restrict__ xiT, int64_t ldxi,
                                                    int PN, const int32_t* __restrict__ start,
                                                    const TW* __restrict__ w, int Qs,
                                                    const int32_t* __restrict__ chunk_p0,
-                                                   int nchunks,
-                                                   const int32_t* __restrict__ off, int P,
-                                                   int64_t J, int L, float* __restrict__ z,
-                                                   int64_t ldz) {
-  extern __shared__ __attribute__((aligned(16))) float xs[];  // [rows][64]
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t l0 = static_cast<int64_t>(blockIdx.y) * 64;
-  const int64_t jb = static_cast<int64_t>(blockIdx.x) * (4 * JW) + wave * JW;
-  float acc[JW];
+                                                   int nchunks, const int32_t* __restrict__ off,
+                                                   int P, int64_t J, int L, int nftiles,
+                                                   float* __restrict__ z, int64_t ldz) {
+  constexpr int STRIDE = FT + 4;  // LDS row stride in 32-bit words
+  constexpr int QP = PAIRS ? (Q + 1) / 2 : Q;
+  extern __shared__ __attribute__((aligned(16))) uint32_t xs[];
+  const int nj = static_cast<int>((J + 255) / 256);
+  int jt, ft;
+  if (!xcd_tile(nj, nftiles, jt, ft)) return;
+  const int tid = threadIdx.x;
+  const int64_t j = static_cast<int64_t>(jt) * 256 + tid;
+  const bool live = j < J;
+  const int64_t jc = live ? j : J - 1;  // dead lanes read a valid record
+  const int64_t l0 = static_cast<int64_t>(ft) * FT;
+  constexpr int WORDS = (Q * static_cast<int>(sizeof(TW)) + 3) / 4;
+
+  float acc[FT];
 #pragma unroll
-  for (int i = 0; i < JW; ++i) acc[i] = 0.0f;
+  for (int f = 0; f < FT; ++f) acc[f] = 0.0f;
 
   for (int ch = 0; ch < nchunks; ++ch) {
     const int p0 = chunk_p0[ch], p1 = chunk_p0[ch + 1];
     const int r0 = off[p0];
-    const int r1 = (p1 < P ? off[p1] : PN) + Q - 1;  // taps may run Q-1 past
-    const int rows = r1 - r0;
+    const int rows = (p1 < P ? off[p1] : PN) + Q - r0;  // taps may run Q-1 past
     __syncthreads();
-    for (int e = tid; e < rows * 16; e += 256) {
-      const int row = e >> 4, c4 = e & 15;
-      f32x4 v = {0.f, 0.f, 0.f, 0.f};
-      if (r0 + row < PN) v = *reinterpret_cast<const f32x4*>(xiT + static_cast<int64_t>(r0 + row) * ldxi + l0 + c4 * 4);
-      *reinterpret_cast<f32x4*>(xs + row * 64 + c4 * 4) = v;
+    for (int e = tid; e < rows * (FT / 4); e += 256) {
+      const int row = e / (FT / 4), c4 = e % (FT / 4);
+      const int n = r0 + row;
+      const float* src = xiT + static_cast<int64_t>(n) * ldxi + l0 + 4 * c4;
+      f32x4 a = {0.f, 0.f, 0.f, 0.f};
+      if (n < PN) a = *reinterpret_cast<const f32x4*>(src);
+      u32x4 v;
+      if (PAIRS) {
+        f32x4 b = {0.f, 0.f, 0.f, 0.f};
+        if (n + 1 < PN) b = *reinterpret_cast<const f32x4*>(src + ldxi);
+        v.x = pack_h2(a.x, b.x);
+        v.y = pack_h2(a.y, b.y);
+        v.z = pack_h2(a.z, b.z);
+        v.w = pack_h2(a.w, b.w);
+      } else {
+        v = __builtin_bit_cast(u32x4, a);
+      }
+      *reinterpret_cast<u32x4*>(xs + row * STRIDE + 4 * c4) = v;
     }
     __syncthreads();
+    // the next pair's start and weights are loaded one iteration ahead
+    int s_next = 0;
+    uint32_t w_next[WORDS];
+    auto fetch = [&](int p) {
+      const int64_t rec = static_cast<int64_t>(p) * J + jc;
+      s_next = start[rec];
+      const uint32_t* wsrc = reinterpret_cast<const uint32_t*>(w + rec * Qs);
 #pragma unroll
-    for (int i = 0; i < JW; ++i) {
-      const int64_t j = jb + i;
-      if (j >= J) break;
-      const int32_t* st = start + j * P;
-      const TW* wj = w + j * P * Qs;
-      float a = acc[i];
-      for (int p = p0; p < p1; ++p) {
-        const int s = st[p] - r0;
-        const float* xr = xs + s * 64 + lane;
+      for (int i = 0; i < WORDS; ++i) w_next[i] = wsrc[i];
+    };
+    fetch(p0);
+    for (int p = p0; p < p1; ++p) {
+      const int s = s_next - r0;
+      uint32_t wv[WORDS];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) a += wdecode<TW>(wj[p * Qs + q]) * xr[q * 64];
+      for (int i = 0; i < WORDS; ++i) wv[i] = w_next[i];
+      if (p + 1 < p1) fetch(p + 1);
+      const uint32_t* rowp = xs + s * STRIDE;
+      if (PAIRS) {
+#pragma unroll
+        for (int q2 = 0; q2 < QP; ++q2) {
+          const float wa = tap<TW>(wv, 2 * q2);
+          const float wb = 2 * q2 + 1 < Q ? tap<TW>(wv, 2 * q2 + 1) : 0.0f;
+          const h2 wp = __builtin_bit_cast(h2, pack_h2(wa, wb));
+          const uint32_t* r = rowp + 2 * q2 * STRIDE;
+#pragma unroll
+          for (int f4 = 0; f4 < FT / 4; ++f4) {
+            const u32x4 e4 = *reinterpret_cast<const u32x4*>(r + 4 * f4);
+            // elements are copied to scalars before the bit cast: hipcc 7.2
+            // lowers __builtin_bit_cast of a vector swizzle (e4.y) to e4.x
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const uint32_t word = e4[i];
+              acc[4 * f4 + i] = __builtin_amdgcn_fdot2(wp, __builtin_bit_cast(h2, word), acc[4 * f4 + i], false);
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const float wq = tap<TW>(wv, q);
+          const uint32_t* r = rowp + q * STRIDE;
+#pragma unroll
+          for (int f4 = 0; f4 < FT / 4; ++f4) {
+            const f32x4 e4 = *reinterpret_cast<const f32x4*>(r + 4 * f4);
+            acc[4 * f4 + 0] += wq * e4.x;
+            acc[4 * f4 + 1] += wq * e4.y;
+            acc[4 * f4 + 2] += wq * e4.z;
+            acc[4 * f4 + 3] += wq * e4.w;
+          }
+        }
       }
-      acc[i] = a;
     }
   }
-  const int64_t l = l0 + lane;
-  if (l >= L) return;
-  float* zl = z + l * ldz;
+  if (!live) return;
 #pragma unroll
-  for (int i = 0; i < JW; ++i) {
-    const int64_t j = jb + i;
-    if (j < J) zl[j] = acc[i];
+  for (int f = 0; f < FT; ++f) {
+    const int64_t l = l0 + f;
+    if (l < L) z[l * ldz + j] = acc[f];
   }
 }
 
@@ -634,8 +735,8 @@ void upload(void* dst, const std::vector<T>& v) {
 // tile shapes of the launch configurations
 constexpr int BIG_BX = 256, BIG_BW = 128, BIG_WGX = 2, BIG_BKB = 128;
 constexpr int SMP_BX = 32, SMP_BW = 256, SMP_WGX = 1, SMP_BKB = 128;
-constexpr int SSPI_JW = 16;
-constexpr int SSPI_ROWS = 192;  // max LDS rows (lags) per pair chunk: 48 KB
+constexpr int SSPI_FT = 32;                       // frames per SSPI block
+constexpr int SSPI_ROWS = 48 * 1024 / ((SSPI_FT + 4) * 4);  // lag rows per LDS chunk (48 KB)
 
 }  // namespace
 
@@ -775,13 +876,16 @@ void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t
     const int Q = hp.Q;
     const int es = static_cast<int>(dsize(hp.dtype));
     const int Qs = static_cast<int>(round_up(Q * es, 4) / es);
+    // device layouts are pair-major ([P][J] and [P][J][Qs]) so that lanes
+    // (consecutive locations) load consecutive records
     std::vector<int32_t> st(static_cast<size_t>(hp.J) * P);
     std::vector<float> ws(static_cast<size_t>(hp.J) * P * Qs, 0.0f);
     for (int64_t j = 0; j < hp.J; ++j)
       for (int p = 0; p < P; ++p) {
         const size_t jp = static_cast<size_t>(j) * P + p;
-        st[jp] = hp.off[p] + hp.start[jp] + hp.np[p];
-        for (int q = 0; q < hp.qp[p]; ++q) ws[jp * Qs + q] = static_cast<float>(hp.w[jp * Q + q]);
+        const size_t pj = static_cast<size_t>(p) * hp.J + j;
+        st[pj] = hp.off[p] + hp.start[jp] + hp.np[p];
+        for (int q = 0; q < hp.qp[p]; ++q) ws[pj * Qs + q] = static_cast<float>(hp.w[jp * Q + q]);
       }
     dp.d_start = static_cast<int32_t*>(A.get(st.size() * 4));
     upload(dp.d_start, st);
@@ -804,12 +908,13 @@ void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t
       dp.chunk_p0.push_back(p);
       int rows = 0;
       int q = p;
-      while (q < P && (rows + 2 * hp.np[q] + 1 + Q - 1 <= SSPI_ROWS || q == p)) {
+      while (q < P && (rows + 2 * hp.np[q] + 1 + Q <= SSPI_ROWS || q == p)) {
         rows += 2 * hp.np[q] + 1;
         ++q;
       }
-      // one pair alone must fit the 160 KB of LDS: 64 frames x 4 B per lag row
-      if (rows + Q - 1 > 640) throw Error{SRP_E_UNSUPPORTED, "a pair has too many lags for the SSPI tile"};
+      // one pair alone must fit the 160 KB of LDS
+      if ((rows + Q) * (SSPI_FT + 4) * 4 > 160 * 1024)
+        throw Error{SRP_E_UNSUPPORTED, "a pair has too many lags for the SSPI tile"};
       p = q;
     }
     dp.chunk_p0.push_back(P);
@@ -955,24 +1060,28 @@ void launch_fat(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t Lp
 template <typename TW, int Q>
 void launch_sspi_q(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t Lpad,
                    int64_t Lc, float* z, hipStream_t st) {
+  constexpr bool PAIRS = !std::is_same<TW, float>::value;
   const int es = static_cast<int>(sizeof(TW));
   const int Qs = static_cast<int>(round_up(Q * es, 4) / es);
   int maxrows = 0;
   for (int c = 0; c < dp.nchunks; ++c) {
     const int p0 = dp.chunk_p0[c], p1 = dp.chunk_p0[c + 1];
     const int r1 = p1 < hp.P ? hp.off[p1] : hp.PN;
-    maxrows = std::max(maxrows, r1 - hp.off[p0] + Q - 1);
+    maxrows = std::max(maxrows, r1 + Q - hp.off[p0]);
   }
-  const size_t lds = static_cast<size_t>(maxrows) * 64 * 4;
+  const size_t lds = static_cast<size_t>(maxrows) * (SSPI_FT + 4) * 4;
+  auto kern = &sspi_gather<TW, Q, SSPI_FT, PAIRS>;
   if (lds > 65536)
-    HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&sspi_gather<TW, Q, SSPI_JW>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  dim3 grid(static_cast<unsigned>((hp.J + 4 * SSPI_JW - 1) / (4 * SSPI_JW)), static_cast<unsigned>(Lpad / 64));
+    HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               static_cast<int>(lds)));
+  const int nj = static_cast<int>((hp.J + 255) / 256);
+  const int nf = static_cast<int>((Lc + SSPI_FT - 1) / SSPI_FT);
+  const int blocks = static_cast<int>(round_up(static_cast<int64_t>(nj) * nf, 8));
+  (void)Lpad;
   TRACED(dp, "sspi_gather", st,
-         hipLaunchKernelGGL((sspi_gather<TW, Q, SSPI_JW>), grid, dim3(256), lds, st, xiT, Lpad, hp.PN,
-                            dp.d_start, static_cast<const TW*>(dp.d_w), Qs, dp.d_chunk_p0, dp.nchunks, dp.d_off,
-                            hp.P, hp.J, static_cast<int>(Lc), z, hp.J));
-  check_launch("sspi_gather");
+         hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, xiT, Lpad, hp.PN, dp.d_start,
+                            static_cast<const TW*>(dp.d_w), Qs, dp.d_chunk_p0, dp.nchunks, dp.d_off, hp.P,
+                            hp.J, static_cast<int>(Lc), nf, z, hp.J));
 }
 
 template <typename TW>
