@@ -1,10 +1,9 @@
 // HIP kernels for gfx950 (MI355X) and the hot-path launch sequence.
 //
 // Hot path per frame tile (one map per STFT frame):
-//   phat_kernel      PHAT-weighted cross-spectra psi_p[l, k]          eq. (2)
+//   phat_kernel      PHAT-weighted cross-spectra psi_p[l, k] (FD)      eq. (2)
 //   gemm_nt (FD)     z = 2 Re[H psi] as a real MFMA GEMM              eq. (22)
-//   gemm_nt (samp.)  xi_p = 2 Re[S_p psi_p], S_p rows of the iDFT      eq. (40)
-//   slri_fat         g_p = V_p^T xi_p                                   eq. (57)
+//   front_fused      PHAT + xi_p = 2 Re[S_p psi_p] (+ g_p = V_p^T xi_p)  eqs. (2), (40), (57)
 //   gemm_nt (tall)   z = sum_p U_p g_p                                  eq. (57)
 //   sspi_gather      z = sum_p sum_q w[j,p,q] xi_p[s(j,p) + q]          eq. (58)
 #include <hip/hip_runtime.h>
@@ -245,12 +244,28 @@ struct Mfma<fp8> {  // v_mfma_f32_32x32x64_f8f6f4, both operands E4M3, unit scal
   }
 };
 
-template <typename T, int BX, int BW, int WGX, int BKB>
+// Maps a linear block id to (W tile, X tile) so that the blocks one XCD
+// receives (workgroups are dispatched round-robin over the 8 XCDs: ids x,
+// x + 8, ...) walk a contiguous range of W tiles with the X tiles innermost;
+// a W tile is then fetched from HBM once into that XCD's L2 and reused by
+// every X tile.  The grid holds a multiple of 8 blocks.
+__device__ inline bool xcd_tile(int nw_tiles, int nx_tiles, int& wt, int& xt) {
+  const int b = blockIdx.x;
+  const int per = static_cast<int>(gridDim.x) / 8;
+  const int gidx = (b % 8) * per + b / 8;
+  if (gidx >= nw_tiles * nx_tiles) return false;
+  wt = gidx / nx_tiles;
+  xt = gidx % nx_tiles;
+  return true;
+}
+
+template <typename T, int BX, int BW, int WGX, int BKB, bool NT>
 __global__ __launch_bounds__(256) void gemm_nt(const GemmBatch* __restrict__ batches,
                                                const T* __restrict__ X, int64_t ldx,
                                                const T* __restrict__ W, int64_t ldw,
                                                float* __restrict__ C, int64_t ldc, int nw,
-                                               int kdim, float alpha, int nx_single) {
+                                               int kdim, float alpha, int nx_single,
+                                               int nw_tiles, int nx_tiles) {
   constexpr int STEP = Mfma<T>::STEP;
   constexpr int LB = STEP / 2;   // bytes per lane per step
   constexpr int NV = LB / 16;    // 16-byte vectors per lane per step
@@ -268,9 +283,11 @@ __global__ __launch_bounds__(256) void gemm_nt(const GemmBatch* __restrict__ bat
   // batched (one entry per blockIdx.z) or a single product with nx rows
   const GemmBatch bt = batches ? batches[blockIdx.z] : GemmBatch{0, 0, 0, nx_single, 0};
   const int nx = bt.nx;
-  const int x0 = blockIdx.y * BX;
-  const int w0 = blockIdx.x * BW;
-  if (x0 >= nx) return;  // uniform over the block
+  int wt, xt;
+  if (!xcd_tile(nw_tiles, nx_tiles, wt, xt)) return;  // uniform over the block
+  const int x0 = xt * BX;
+  const int w0 = wt * BW;
+  if (x0 >= nx) return;
   const unsigned char* Xb = reinterpret_cast<const unsigned char*>(X + bt.x_off);
   const unsigned char* Wb = reinterpret_cast<const unsigned char*>(W + bt.w_off);
   C += bt.c_off * ldc;
@@ -355,7 +372,13 @@ __global__ __launch_bounds__(256) void gemm_nt(const GemmBatch* __restrict__ bat
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int row = x0 + wx + a * 32 + 8 * (v / 4) + 4 * g + (v % 4);
-        if (row < nx) C[static_cast<int64_t>(row) * ldc + col] = alpha * acc[a][b][v];
+        if (row < nx) {
+          float* dst = C + static_cast<int64_t>(row) * ldc + col;
+          if (NT)
+            __builtin_nontemporal_store(alpha * acc[a][b][v], dst);
+          else
+            *dst = alpha * acc[a][b][v];
+        }
       }
     }
 }
@@ -410,41 +433,289 @@ __global__ __launch_bounds__(256) void gemm_nt_f64(const double* __restrict__ X,
     }
 }
 
-// ======================================================== SLRI fat stage ===
+// ================================================ fused front end ========
 //
-// g[l][p R + r] = gscale_p * sum_n V_p[n][r] xi_p[l][n], one thread per frame,
-// blockIdx.y = pair (the extra index P zero-fills the padding columns).
+// PHAT cross-spectra (eq. (2)), GCC sampling (eq. (40)) and, for SLRI, the
+// fat stage g_p = V_p^T xi_p (eq. (57)) in one kernel.  A block owns one
+// pair and 32 frames and computes the 32-lag x 32-frame tile
+// xi_p[n][l] = sum_k S[n][k] psi_p[l][k] on v_mfma_f32_32x32x2_f32; the four
+// waves split the spectrum into quarters and their partial tiles are summed
+// through LDS.  The A-operand is the shared iDFT table S (rows
+// 2 cos / -2 sin (pi k n / K)); the B-operand is psi_p, formed once per
+// (frame, bin) while a wave stages its chunk of both microphones' bins from
+// HBM (coalesced along bins) into wave-private LDS, psi = u_m conj(u_m'),
+// u = y / |y|.  psi never touches HBM.
+// MODE 0 writes xi^T [lag][frame] (SSPI); MODE 1 reduces the tile against
+// V_p (both lane halves of a frame, then a cross-half shuffle) and writes
+// g[frame][p R + r] in TG with the pair's activation scale.
 
-template <typename T, int RMAX>
-__global__ __launch_bounds__(64) void slri_fat(const float* __restrict__ xiT, int64_t ldxi,
-                                               const int32_t* __restrict__ np,
-                                               const int32_t* __restrict__ off,
-                                               const float* __restrict__ V, int vrows, int R,
-                                               const float* __restrict__ gscale, int P, int Kc,
-                                               T* __restrict__ g) {
-  const int64_t l = blockIdx.x * 64 + threadIdx.x;
+// y / |y| (0 for y = 0) with the hardware reciprocal square root; squared
+// magnitudes outside [2^-100, 2^100] are rescaled first so that neither
+// underflow nor overflow can occur.
+__device__ inline float2 unit_phase(float2 y) {
+  float a = y.x, b = y.y;
+  float n2 = a * a + b * b;
+  if (!(n2 >= 0x1p-100f && n2 <= 0x1p100f)) {
+    const float s = std::max(std::fabs(a), std::fabs(b));
+    if (!(s > 0.0f)) return make_float2(0.0f, 0.0f);
+    a /= s;
+    b /= s;
+    n2 = a * a + b * b;
+  }
+  const float r = __builtin_amdgcn_rsqf(n2);
+  return make_float2(a * r, b * r);
+}
+
+template <int MODE, typename TG, int RMAX>
+__global__ __launch_bounds__(256) void front_fused(
+    const float2* __restrict__ Y, int M, int K, int L, const int32_t* __restrict__ pm,
+    const int32_t* __restrict__ pmp, const int32_t* __restrict__ np,
+    const int32_t* __restrict__ off, int max_np, const float* __restrict__ S, int Kp,
+    float* __restrict__ xiT, int64_t ldxi, const float* __restrict__ V, int vrows, int R,
+    const float* __restrict__ gscale, int P, TG* __restrict__ g, int Kc) {
+  constexpr int KC = 16;           // bins per chunk
+  constexpr int ROW = 2 * KC + 4;  // psi floats per frame row (padded)
+  constexpr int WBUF = 32 * ROW;   // one wave's chunk buffer (floats)
+  __shared__ __attribute__((aligned(16))) float lds[4 * 2 * WBUF];  // [wave][buf]; reused for the reduction
   const int p = blockIdx.y;
-  T* gl = g + l * Kc;
-  if (p == P) {
-    for (int c = P * R; c < Kc; ++c) gl[c] = cvt<T>(0.0f);
-    return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r32 = lane & 31, gq = lane >> 5;
+  const int64_t fbase = static_cast<int64_t>(blockIdx.x) * 32;
+  const int64_t frame = fbase + r32;
+  const bool fvalid = frame < L;
+  const int m = pm[p], mq = pmp[p];
+  const int n_p = np[p], nrows = 2 * n_p + 1;
+  // this wave's quarter of the single-sided bins 1..K-1, in whole chunks
+  const int cpw = ((K - 1 + 3) / 4 + KC - 1) / KC;  // chunks per wave
+  const int c0 = wave * cpw;
+  float* wb = lds + wave * 2 * WBUF;
+
+  // staging: lane handles frames lane / 8 + 8 it (it < 4), bin pair lane % 8
+  float2 pre[4][4];  // [item][y_m k, y_m k+1, y_m' k, y_m' k+1]
+  auto gload = [&](int c) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int64_t f = std::min<int64_t>(fbase + lane / 8 + 8 * it, L - 1);
+      const int k0 = c * KC + 2 * (lane % 8) + 1;
+      const float2* a = Y + (f * M + m) * (K + 1);
+      const float2* b = Y + (f * M + mq) * (K + 1);
+      const float2 zero = make_float2(0.f, 0.f);
+      pre[it][0] = k0 <= K - 1 ? a[k0] : zero;
+      pre[it][1] = k0 + 1 <= K - 1 ? a[k0 + 1] : zero;
+      pre[it][2] = k0 <= K - 1 ? b[k0] : zero;
+      pre[it][3] = k0 + 1 <= K - 1 ? b[k0 + 1] : zero;
+    }
+  };
+  auto lstore = [&](float* buf) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int fl = lane / 8 + 8 * it;
+      const float2 u0 = unit_phase(pre[it][0]), v0 = unit_phase(pre[it][2]);
+      const float2 u1 = unit_phase(pre[it][1]), v1 = unit_phase(pre[it][3]);
+      f32x4 q;  // psi = u_m conj(u_m') for the two bins
+      q.x = u0.x * v0.x + u0.y * v0.y;
+      q.y = u0.y * v0.x - u0.x * v0.y;
+      q.z = u1.x * v1.x + u1.y * v1.y;
+      q.w = u1.y * v1.x - u1.x * v1.y;
+      *reinterpret_cast<f32x4*>(buf + fl * ROW + 4 * (lane % 8)) = q;
+    }
+  };
+
+  float gacc[RMAX];
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) gacc[r] = 0.0f;
+
+  for (int t0 = 0; t0 < nrows; t0 += 32) {
+    // lane's A row: lag n = -N_p + t0 + r32 -> table row max_np - N_p + t0 + r32
+    const float* srow = S + static_cast<int64_t>(max_np - n_p + t0 + r32) * Kp + 4 * gq;
+    f32x16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    __syncthreads();  // previous tile's reduction is done with the buffers
+    gload(c0);
+    lstore(wb);
+    for (int c = 0; c < cpw; ++c) {
+      float* cur = wb + (c & 1) * WBUF;
+      if (c + 1 < cpw) gload(c0 + c + 1);
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS stores landed
+      __builtin_amdgcn_wave_barrier();
+      const float* prow = cur + r32 * ROW + 4 * gq;
+      const float* sc = srow + (c0 + c) * 2 * KC;
+#pragma unroll
+      for (int st = 0; st < KC / 4; ++st) {
+        const f32x4 a = *reinterpret_cast<const f32x4*>(sc + 8 * st);
+        const f32x4 bq = *reinterpret_cast<const f32x4*>(prow + 8 * st);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, bq.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, bq.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, bq.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, bq.w, acc, 0, 0, 0);
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (c + 1 < cpw) lstore(wb + ((c + 1) & 1) * WBUF);
+    }
+    // sum the four waves' partial tiles
+    __syncthreads();
+    float* red = lds;  // [wave][v][lane]
+#pragma unroll
+    for (int v = 0; v < 16; ++v) red[(wave * 16 + v) * 64 + lane] = acc[v];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v)
+        acc[v] = red[v * 64 + lane] + red[(16 + v) * 64 + lane] + red[(32 + v) * 64 + lane] +
+                 red[(48 + v) * 64 + lane];
+      // accumulator layout: register v of lane i holds lag row
+      // t0 + 8 (v / 4) + 4 (i / 32) + v % 4 of frame column i % 32
+      if (MODE == 0) {
+        if (fvalid) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int lag = t0 + 8 * (v / 4) + 4 * gq + (v % 4);
+            if (lag < nrows) xiT[static_cast<int64_t>(off[p] + lag) * ldxi + frame] = acc[v];
+          }
+        }
+      } else {
+        const float* Vp = V + static_cast<int64_t>(p) * vrows * R;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int lag = t0 + 8 * (v / 4) + 4 * gq + (v % 4);
+          if (lag < nrows) {
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r)
+              if (r < R) gacc[r] += Vp[lag * R + r] * acc[v];
+          }
+        }
+      }
+    }
   }
-  float acc[RMAX];
+  if (MODE == 1 && wave == 0) {
+    const float sc = gscale[p];
 #pragma unroll
-  for (int r = 0; r < RMAX; ++r) acc[r] = 0.0f;
-  const int n = 2 * np[p] + 1;
-  const float* xs = xiT + static_cast<int64_t>(off[p]) * ldxi + l;
-  const float* Vp = V + static_cast<int64_t>(p) * vrows * R;
-  for (int i = 0; i < n; ++i) {
-    const float xv = xs[static_cast<int64_t>(i) * ldxi];
+    for (int r = 0; r < RMAX; ++r) gacc[r] += __shfl_xor(gacc[r], 32);
+    if (gq == 0 && fvalid) {
+      TG* gl = g + frame * Kc;
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r)
-      if (r < R) acc[r] += Vp[i * R + r] * xv;
+      for (int r = 0; r < RMAX; ++r)
+        if (r < R) gl[p * R + r] = cvt<TG>(gacc[r] * sc);
+      if (p == P - 1)
+        for (int c = P * R; c < Kc; ++c) gl[c] = cvt<TG>(0.0f);
+    }
   }
-  const float sc = gscale[p];
+}
+
+// ====================================================== SLRI tall stream ===
+//
+// z[l][j] = alpha * sum_c g[l][c] U[j][c] for the 16-bit and FP8 operands
+// with a short contraction (P R padded, at most 1 KB per row).  A block owns
+// 128 candidates: each wave keeps its 32 rows of U in registers for the whole
+// kernel (U is read from HBM exactly once), and all frames stream past in
+// groups of 32 whose g rows are staged in LDS (double-buffered, prefetched
+// one group ahead).  The kernel is bound by the map stores.
+
+template <typename T, int MAXS, bool WIDE>
+__global__ __launch_bounds__(256) void tall_stream(const T* __restrict__ g, int64_t ldg,
+                                                   const T* __restrict__ U, int64_t ldu, int nsteps,
+                                                   float* __restrict__ z, int64_t ldz, int L, int64_t J,
+                                                   float alpha) {
+  constexpr int STEP = Mfma<T>::STEP;  // bytes of a row per MFMA step
+  constexpr int LB = STEP / 2;         // bytes per lane per step
+  constexpr int NV = LB / 16;
+  constexpr int ROWMAX = MAXS * STEP + 16;  // padded LDS row (bytes)
+  __shared__ __attribute__((aligned(16))) unsigned char gs[2][32 * ROWMAX];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r32 = lane & 31, gq = lane >> 5;
+  const int64_t j0 = static_cast<int64_t>(blockIdx.x) * 128 + wave * 32;
+  const int rowb = nsteps * STEP;  // bytes of a g / U row
+  const int rowp = rowb + 16;      // padded LDS row
+
+  // this lane's U fragments: row j0 + r32, K-half gq of every step
+  i32x4 uf[MAXS][NV];
+  {
+    const unsigned char* ur =
+        reinterpret_cast<const unsigned char*>(U) + (j0 + r32) * ldu * static_cast<int64_t>(sizeof(T)) + gq * LB;
 #pragma unroll
-  for (int r = 0; r < RMAX; ++r)
-    if (r < R) gl[p * R + r] = cvt<T>(acc[r] * sc);
+    for (int s = 0; s < MAXS; ++s)
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (s < nsteps) uf[s][v] = *reinterpret_cast<const i32x4*>(ur + s * STEP + 16 * v);
+  }
+  // g group staging: 32 rows x rowb bytes in 16-byte chunks
+  const int chunks = 32 * (rowb / 16);
+  constexpr int PER = (32 * MAXS * STEP / 16 + 255) / 256;
+  i32x4 pre[PER];
+  const unsigned char* gb = reinterpret_cast<const unsigned char*>(g);
+  auto gload = [&](int grp) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int c = tid + 256 * i;
+      if (c < chunks) {
+        const int row = c / (rowb / 16), col = c % (rowb / 16);
+        pre[i] = *reinterpret_cast<const i32x4*>(gb + (static_cast<int64_t>(grp) * 32 + row) * ldg * sizeof(T) + 16 * col);
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int c = tid + 256 * i;
+      if (c < chunks) {
+        const int row = c / (rowb / 16), col = c % (rowb / 16);
+        *reinterpret_cast<i32x4*>(&gs[buf][row * rowp + 16 * col]) = pre[i];
+      }
+    }
+  };
+  const int ngroups = (L + 31) / 32;
+  const int64_t jcol = j0 + r32;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int grp = 0; grp < ngroups; ++grp) {
+    const int buf = grp & 1;
+    if (grp + 1 < ngroups) gload(grp + 1);
+    f32x16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    const unsigned char* ar = &gs[buf][r32 * rowp + gq * LB];
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s) {
+      if (s < nsteps) {
+        i32x4 af[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) af[v] = *reinterpret_cast<const i32x4*>(ar + s * STEP + 16 * v);
+        if (WIDE)
+          Mfma<T>::run(uf[s], af, acc);
+        else
+          Mfma<T>::run(af, uf[s], acc);
+      }
+    }
+    if (WIDE) {
+      // rows are candidates j0 + 8 (v / 4) + 4 gq + v % 4, the column is
+      // frame grp * 32 + r32: four consecutive candidates per 16-byte store
+      const int64_t l = static_cast<int64_t>(grp) * 32 + r32;
+      if (l < L) {
+#pragma unroll
+        for (int v4 = 0; v4 < 4; ++v4) {
+          const int64_t jj = j0 + 8 * v4 + 4 * gq;
+          f32x4 o = {alpha * acc[4 * v4], alpha * acc[4 * v4 + 1], alpha * acc[4 * v4 + 2], alpha * acc[4 * v4 + 3]};
+          if (jj + 3 < J) {
+            *reinterpret_cast<f32x4*>(z + l * ldz + jj) = o;
+          } else {
+            for (int e = 0; e < 4; ++e)
+              if (jj + e < J) z[l * ldz + jj + e] = o[e];
+          }
+        }
+      }
+    } else if (jcol < J) {
+      // rows (frames) 8 (v / 4) + 4 gq + v % 4 of the group, column jcol
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t l = static_cast<int64_t>(grp) * 32 + 8 * (v / 4) + 4 * gq + (v % 4);
+        if (l < L) z[l * ldz + jcol] = alpha * acc[v];
+      }
+    }
+    if (grp + 1 < ngroups) lstore(buf ^ 1);
+    __syncthreads();
+  }
 }
 
 // ========================================================= SSPI gather ===
@@ -505,19 +776,6 @@ __device__ inline float tap(const uint32_t* wv, int i) {
 __device__ inline uint32_t pack_h2(float a, float b) {
   const h2 v = {static_cast<_Float16>(a), static_cast<_Float16>(b)};
   return __builtin_bit_cast(uint32_t, v);
-}
-
-// Maps a linear block id to (location tile, frame tile) so that the blocks an
-// XCD receives (ids x, x + 8, x + 16, ...) cover consecutive pairs of a
-// location-major, frame-minor enumeration.
-__device__ inline bool xcd_tile(int nj, int nf, int& jt, int& ft) {
-  const int b = blockIdx.x;
-  const int per = static_cast<int>(gridDim.x) / 8;  // grid is a multiple of 8
-  const int g = (b % 8) * per + b / 8;
-  if (g >= nj * nf) return false;
-  jt = g / nf;
-  ft = g % nf;
-  return true;
 }
 
 template <typename TW, int Q, int FT, bool PAIRS>
@@ -733,10 +991,11 @@ void upload(void* dst, const std::vector<T>& v) {
 }
 
 // tile shapes of the launch configurations
-constexpr int BIG_BX = 256, BIG_BW = 128, BIG_WGX = 2, BIG_BKB = 128;
-constexpr int SMP_BX = 32, SMP_BW = 256, SMP_WGX = 1, SMP_BKB = 128;
+constexpr int BIG_BX = 256, BIG_BW = 128, BIG_WGX = 2, BIG_BKB = 128;   // FD
+constexpr int TALL_BX = 256, TALL_BW = 128, TALL_WGX = 2, TALL_BKB = 128; // SLRI tall (FP32)
+constexpr bool TALL_WIDE = false;  // 16-byte map stores in tall_stream
 constexpr int SSPI_FT = 32;                       // frames per SSPI block
-constexpr int SSPI_ROWS = 48 * 1024 / ((SSPI_FT + 4) * 4);  // lag rows per LDS chunk (48 KB)
+constexpr int SSPI_ROWS = 32 * 1024 / ((SSPI_FT + 4) * 4);  // lag rows per LDS chunk (32 KB)
 
 }  // namespace
 
@@ -787,7 +1046,7 @@ void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t
   // reduced exactly in integers, then evaluated in FP64
   dp.samp_rows = 2 * hp.max_np + 1;
   {
-    const int rows = dp.samp_rows + SMP_BX;
+    const int rows = dp.samp_rows + 32;  // zero rows past the last lag tile
     std::vector<float> S(static_cast<size_t>(rows) * dp.Kp, 0.0f);
     for (int i = 0; i < dp.samp_rows; ++i) {
       const int64_t n = i - hp.max_np;
@@ -801,16 +1060,6 @@ void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t
     }
     dp.d_S = static_cast<float*>(A.get(S.size() * 4));
     upload(dp.d_S, S);
-    std::vector<GemmBatch> sb(P);
-    for (int p = 0; p < P; ++p) {
-      sb[p].x_off = static_cast<int64_t>(hp.max_np - hp.np[p]) * dp.Kp;
-      sb[p].w_off = static_cast<int64_t>(p) * dp.Kp;
-      sb[p].c_off = hp.off[p];
-      sb[p].nx = 2 * hp.np[p] + 1;
-      sb[p].pad = 0;
-    }
-    dp.d_samp_batch = static_cast<GemmBatch*>(A.get(sizeof(GemmBatch) * P));
-    upload(dp.d_samp_batch, sb);
   }
 
   if (hp.variant == SRP_SLRI) {
@@ -950,7 +1199,7 @@ void device_free(DevicePlan& dp) {
     hipEventDestroy(sp.stop);
   }
   for (hipEvent_t e : dp.event_pool) hipEventDestroy(e);
-  void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_samp_batch,
+  void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S,
                   dp.d_U, dp.d_V, dp.d_gscale, dp.d_start, dp.d_w, dp.d_chunk_p0,
                   dp.ws};
   for (void* p : ptrs)
@@ -969,10 +1218,9 @@ WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t 
   WsLayout w;
   w.Lc = std::max<int64_t>(1, std::min(L, frame_tile));
   w.Lpad = round_up(w.Lc, BIG_BX);
-  size_t psi_es = hp.variant == SRP_FD ? dsize(hp.dtype) : 4;
   size_t off = 0;
   w.psi = off;
-  off = align256(off + static_cast<size_t>(w.Lpad) * hp.P * dp.Kp * psi_es);
+  if (hp.variant == SRP_FD) off = align256(off + static_cast<size_t>(w.Lpad) * hp.P * dp.Kp * dsize(hp.dtype));
   if (hp.variant != SRP_FD) {
     w.xi = off;
     off = align256(off + static_cast<size_t>(hp.PN) * w.Lpad * 4);
@@ -1011,50 +1259,73 @@ void phat_dispatch(const HostPlan& hp, DevicePlan& dp, const void* frames, int64
   }
 }
 
+template <typename T, int BX, int BW, int WGX, int BKB>
+void launch_gemm(DevicePlan& dp, const char* kname, const void* X, int64_t ldx, const void* W, int64_t ldw,
+                 float* C, int64_t ldc, int nx, int nw, int kdim, float alpha, int64_t Lpad, hipStream_t st) {
+  const int nwt = static_cast<int>(dp.Jpad / BW);
+  const int nxt = static_cast<int>(Lpad / BX);
+  const int blocks = static_cast<int>(round_up(static_cast<int64_t>(nwt) * nxt, 8));
+  TRACED(dp, kname, st,
+         hipLaunchKernelGGL((gemm_nt<T, BX, BW, WGX, BKB, false>), dim3(blocks), dim3(256), 0, st,
+                            static_cast<const GemmBatch*>(nullptr), static_cast<const T*>(X), ldx,
+                            static_cast<const T*>(W), ldw, C, ldc, nw, kdim, alpha, nx, nwt, nxt));
+}
+
 template <typename T>
 void launch_big_gemm(DevicePlan& dp, const char* kname, const void* X, int64_t ldx, const void* W, int64_t ldw,
                      float* C, int64_t ldc, int nx, int nw, int kdim, float alpha, int64_t Lpad,
                      hipStream_t st) {
-  dim3 grid(static_cast<unsigned>(dp.Jpad / BIG_BW), static_cast<unsigned>(Lpad / BIG_BX), 1);
-  TRACED(dp, kname, st,
-         hipLaunchKernelGGL((gemm_nt<T, BIG_BX, BIG_BW, BIG_WGX, BIG_BKB>), grid, dim3(256), 0, st,
-                            static_cast<const GemmBatch*>(nullptr), static_cast<const T*>(X), ldx,
-                            static_cast<const T*>(W), ldw, C, ldc, nw, kdim, alpha, nx));
-  check_launch("gemm_nt");
-}
-
-void launch_sampling(const HostPlan& hp, DevicePlan& dp, const float* psi, float* xiT,
-                     int64_t Lpad, hipStream_t st) {
-  dim3 grid(static_cast<unsigned>(Lpad / SMP_BW), static_cast<unsigned>((dp.samp_rows + SMP_BX - 1) / SMP_BX),
-            static_cast<unsigned>(hp.P));
-  TRACED(dp, "gemm_sampling", st,
-         hipLaunchKernelGGL((gemm_nt<float, SMP_BX, SMP_BW, SMP_WGX, SMP_BKB>), grid, dim3(256), 0, st,
-                            dp.d_samp_batch, dp.d_S, static_cast<int64_t>(dp.Kp), psi,
-                            static_cast<int64_t>(hp.P) * dp.Kp, xiT, Lpad, static_cast<int>(Lpad), dp.Kp, 1.0f,
-                            0));
-  check_launch("gemm_nt(sampling)");
+  launch_gemm<T, BIG_BX, BIG_BW, BIG_WGX, BIG_BKB>(dp, kname, X, ldx, W, ldw, C, ldc, nx, nw, kdim, alpha, Lpad, st);
 }
 
 template <typename T>
-void launch_fat(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t Lpad, void* g,
-                hipStream_t st) {
-  dim3 grid(static_cast<unsigned>(Lpad / 64), static_cast<unsigned>(hp.P + 1));
+void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W, int64_t ldw, float* C,
+                      int64_t ldc, int nx, int nw, int kdim, float alpha, int64_t Lpad, hipStream_t st) {
+  const int steps = kdim * static_cast<int>(sizeof(T)) / Mfma<T>::STEP;
+  // 16-byte map stores need 16-byte aligned rows
+  if (!std::is_same<T, float>::value && steps <= 32 && kdim * static_cast<int>(sizeof(T)) <= 1024 &&
+      (!TALL_WIDE || ldc % 4 == 0)) {
+    // U rows of the block stay in registers; frames stream past
+    const unsigned blocks = static_cast<unsigned>(dp.Jpad / 128);
+#define SRP_TALL(MS)                                                                                         \
+  TRACED(dp, "gemm_tall", st,                                                                              \
+         hipLaunchKernelGGL((tall_stream<T, MS, TALL_WIDE>), dim3(blocks), dim3(256), 0, st,                \
+                            static_cast<const T*>(X),                                                        \
+                            ldx, static_cast<const T*>(W), ldw, steps, C, ldc, nx, static_cast<int64_t>(nw),   \
+                            alpha))
+    if (steps <= 8)
+      SRP_TALL(8);
+    else if (steps <= 16)
+      SRP_TALL(16);
+    else
+      SRP_TALL(32);
+#undef SRP_TALL
+    return;
+  }
+  launch_gemm<T, TALL_BX, TALL_BW, TALL_WGX, TALL_BKB>(dp, "gemm_tall", X, ldx, W, ldw, C, ldc, nx, nw, kdim, alpha,
+                                                      Lpad, st);
+}
+
+// Fused PHAT + sampling (+ fat stage for SLRI) straight from the frames.
+template <int MODE, typename TG>
+void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t Lc, float* xiT, int64_t ldxi,
+                  void* g, hipStream_t st) {
+  dim3 grid(static_cast<unsigned>((Lc + 31) / 32), static_cast<unsigned>(hp.P));
   const int vrows = 2 * hp.max_np + 1;
-  if (hp.R <= 8)
-    TRACED(dp, "slri_fat", st,
-           hipLaunchKernelGGL((slri_fat<T, 8>), grid, dim3(64), 0, st, xiT, Lpad, dp.d_np, dp.d_off, dp.d_V,
-                              vrows, hp.R, dp.d_gscale, hp.P, dp.Kc, static_cast<T*>(g)));
+  const char* kname = MODE == 0 ? "front_sampling" : "front_sampling_fat";
+#define SRP_FRONT(RM)                                                                                       \
+  TRACED(dp, kname, st,                                                                                     \
+         hipLaunchKernelGGL((front_fused<MODE, TG, RM>), grid, dim3(256), 0, st,                            \
+                            static_cast<const float2*>(frames), hp.M, hp.K, static_cast<int>(Lc), dp.d_pm, \
+                            dp.d_pmp, dp.d_np, dp.d_off, hp.max_np, dp.d_S, dp.Kp, xiT, ldxi, dp.d_V,      \
+                            vrows, hp.R, dp.d_gscale, hp.P, static_cast<TG*>(g), dp.Kc))
+  if (MODE == 0 || hp.R <= 8)
+    SRP_FRONT(8);
   else if (hp.R <= 16)
-    TRACED(dp, "slri_fat", st,
-           hipLaunchKernelGGL((slri_fat<T, 16>), grid, dim3(64), 0, st, xiT, Lpad, dp.d_np, dp.d_off, dp.d_V,
-                              vrows, hp.R, dp.d_gscale, hp.P, dp.Kc, static_cast<T*>(g)));
-  else if (hp.R <= 32)
-    TRACED(dp, "slri_fat", st,
-           hipLaunchKernelGGL((slri_fat<T, 32>), grid, dim3(64), 0, st, xiT, Lpad, dp.d_np, dp.d_off, dp.d_V,
-                              vrows, hp.R, dp.d_gscale, hp.P, dp.Kc, static_cast<T*>(g)));
+    SRP_FRONT(16);
   else
-    throw Error{SRP_E_UNSUPPORTED, "SLRI rank per pair above 32 is not built"};
-  check_launch("slri_fat");
+    SRP_FRONT(32);
+#undef SRP_FRONT
 }
 
 template <typename TW, int Q>
@@ -1155,32 +1426,31 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
       }
       continue;
     }
-    // sampling (SLRI, SSPI)
-    phat_dispatch(hp, dp, fr, Lc, psi, SRP_F32, st);
+    // SLRI and SSPI: fused PHAT + sampling (+ fat stage) from the frames
     float* xiT = reinterpret_cast<float*>(base + lay.xi);
-    launch_sampling(hp, dp, static_cast<const float*>(psi), xiT, lay.Lpad, st);
     float* z = static_cast<float*>(maps) + l0 * hp.J;
     if (hp.variant == SRP_SLRI) {
       void* g = base + lay.g;
       switch (hp.dtype) {
         case SRP_F32:
-          launch_fat<float>(hp, dp, xiT, lay.Lpad, g, st);
-          launch_big_gemm<float>(dp, "gemm_tall", g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          launch_front<1, float>(hp, dp, fr, Lc, nullptr, 0, g, st);
+          launch_tall_gemm<float>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
           break;
         case SRP_BF16:
-          launch_fat<__bf16>(hp, dp, xiT, lay.Lpad, g, st);
-          launch_big_gemm<__bf16>(dp, "gemm_tall", g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          launch_front<1, __bf16>(hp, dp, fr, Lc, nullptr, 0, g, st);
+          launch_tall_gemm<__bf16>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
           break;
         case SRP_F16:
-          launch_fat<_Float16>(hp, dp, xiT, lay.Lpad, g, st);
-          launch_big_gemm<_Float16>(dp, "gemm_tall", g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          launch_front<1, _Float16>(hp, dp, fr, Lc, nullptr, 0, g, st);
+          launch_tall_gemm<_Float16>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
           break;
         case SRP_FP8_E4M3:
-          launch_fat<fp8>(hp, dp, xiT, lay.Lpad, g, st);
-          launch_big_gemm<fp8>(dp, "gemm_tall", g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          launch_front<1, fp8>(hp, dp, fr, Lc, nullptr, 0, g, st);
+          launch_tall_gemm<fp8>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
           break;
       }
     } else {
+      launch_front<0, float>(hp, dp, fr, Lc, xiT, lay.Lpad, nullptr, st);
       switch (hp.dtype) {
         case SRP_F32: launch_sspi<float>(hp, dp, xiT, lay.Lpad, Lc, z, st); break;
         case SRP_BF16: launch_sspi<__bf16>(hp, dp, xiT, lay.Lpad, Lc, z, st); break;
@@ -1206,10 +1476,8 @@ void device_gcc_samples(const HostPlan& hp, DevicePlan& dp, const void* frames, 
   for (int64_t l0 = 0; l0 < L; l0 += lay.Lc) {
     const int64_t Lc = std::min(lay.Lc, L - l0);
     const void* fr = static_cast<const float2*>(frames) + l0 * frame_elems;
-    void* psi = base + lay.psi;
-    phat_dispatch(hp, dp, fr, Lc, psi, SRP_F32, st);
     float* xiT = reinterpret_cast<float*>(base + lay.xi);
-    launch_sampling(hp, dp, static_cast<const float*>(psi), xiT, lay.Lpad, st);
+    launch_front<0, float>(hp, dp, fr, Lc, xiT, lay.Lpad, nullptr, st);
     const int64_t n = static_cast<int64_t>(hp.PN) * Lc;
     TRACED(dp, "transpose_xi", st,
            hipLaunchKernelGGL(transpose_xi, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,

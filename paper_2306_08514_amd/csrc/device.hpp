@@ -32,8 +32,7 @@ struct DevicePlan {
   // FD
   void* d_H = nullptr;       // [Jpad][P*Kp] steering (cos, -sin) in dtype
   // sampling (SLRI, SSPI)
-  float* d_S = nullptr;      // [2 max_np + 1 + 64][Kp] rows 2cos / -2sin
-  GemmBatch* d_samp_batch = nullptr;  // [P]
+  float* d_S = nullptr;      // [2 max_np + 1 + 32][Kp] rows 2cos / -2sin
   int samp_rows = 0;         // 2 max_np + 1
   // SLRI
   int Kc = 0;                // columns of the tall GEMM (P*R padded)
