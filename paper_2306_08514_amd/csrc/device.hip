@@ -3,7 +3,8 @@
 // Hot path per frame tile (one map per STFT frame):
 //   phat_kernel      PHAT-weighted cross-spectra psi_p[l, k] (FD)      eq. (2)
 //   gemm_nt (FD)     z = 2 Re[H psi] as a real MFMA GEMM              eq. (22)
-//   front_fused      PHAT + xi_p = 2 Re[S_p psi_p] (+ g_p = V_p^T xi_p)  eqs. (2), (40), (57)
+//   spectral_slices  PHAT + xi_p = 2 Re[S_p psi_p] per spectral slice    eqs. (2), (40)
+//   slice_reduce     sum of slices (+ g_p = V_p^T xi_p for SLRI)        eq. (57)
 //   gemm_nt (tall)   z = sum_p U_p g_p                                  eq. (57)
 //   sspi_gather      z = sum_p sum_q w[j,p,q] xi_p[s(j,p) + q]          eq. (58)
 #include <hip/hip_runtime.h>
@@ -433,21 +434,20 @@ __global__ __launch_bounds__(256) void gemm_nt_f64(const double* __restrict__ X,
     }
 }
 
-// ================================================ fused front end ========
+// =============================================== sampling front end ======
 //
-// PHAT cross-spectra (eq. (2)), GCC sampling (eq. (40)) and, for SLRI, the
-// fat stage g_p = V_p^T xi_p (eq. (57)) in one kernel.  A block owns one
-// pair and 32 frames and computes the 32-lag x 32-frame tile
-// xi_p[n][l] = sum_k S[n][k] psi_p[l][k] on v_mfma_f32_32x32x2_f32; the four
-// waves split the spectrum into quarters and their partial tiles are summed
-// through LDS.  The A-operand is the shared iDFT table S (rows
-// 2 cos / -2 sin (pi k n / K)); the B-operand is psi_p, formed once per
-// (frame, bin) while a wave stages its chunk of both microphones' bins from
-// HBM (coalesced along bins) into wave-private LDS, psi = u_m conj(u_m'),
-// u = y / |y|.  psi never touches HBM.
-// MODE 0 writes xi^T [lag][frame] (SSPI); MODE 1 reduces the tile against
-// V_p (both lane halves of a frame, then a cross-half shuffle) and writes
-// g[frame][p R + r] in TG with the pair's activation scale.
+// PHAT cross-spectra (eq. (2)) and GCC sampling xi_p[n] = sum_k S[n][k]
+// psi_p[k] (eq. (40)) for every pair, straight from the frames.
+// spectral_slices: a block owns 32 frames and one 64-bin slice of the
+// single-sided spectrum.  It stages u_m = y_m / |y_m| of every microphone
+// for chunks of CB bins in LDS (normalised once per (frame, mic, bin),
+// loaded coalesced along bins), and each wave accumulates up to 8 tasks
+// (pair, 32-lag tile) on v_mfma_f32_32x32x2_f32: the A-operand is the
+// shared iDFT table S (rows 2 cos / -2 sin (pi k n / K)), the B-operand is
+// psi_p = u_m conj(u_m') formed in registers.  The slice's partial tiles go
+// to part[slice][stacked lag][frame]; slice_reduce sums the slices in a
+// fixed order (deterministic) and writes xi^T (SSPI) or applies the SLRI fat
+// stage g_p = V_p^T xi_p (eq. (57)) and writes g in the tall operand type.
 
 // y / |y| (0 for y = 0) with the hardware reciprocal square root; squared
 // magnitudes outside [2^-100, 2^100] are rescaled first so that neither
@@ -466,140 +466,204 @@ __device__ inline float2 unit_phase(float2 y) {
   return make_float2(a * r, b * r);
 }
 
-template <int MODE, typename TG, int RMAX>
-__global__ __launch_bounds__(256) void front_fused(
+constexpr int SLICE_BINS = 64;  // bins per spectral slice
+constexpr int SLICE_TPW = 8;    // tasks per wave per pass
+
+// LDS layout of one chunk buffer: u [M][32 frames][CB complex] rows padded to
+// CB * 8 + 16 bytes, then the S-table columns of the chunk [srows][2 CB]
+// padded to 2 CB + 4 floats.
+template <int CB>
+__device__ __host__ inline int slice_buf_bytes(int M, int srows) {
+  return M * 32 * (CB * 8 + 16) + srows * (2 * CB + 4) * 4;
+}
+
+template <int MODE, int CB, int RMAX>
+__global__ __launch_bounds__(256) void spectral_slices(
     const float2* __restrict__ Y, int M, int K, int L, const int32_t* __restrict__ pm,
     const int32_t* __restrict__ pmp, const int32_t* __restrict__ np,
-    const int32_t* __restrict__ off, int max_np, const float* __restrict__ S, int Kp,
-    float* __restrict__ xiT, int64_t ldxi, const float* __restrict__ V, int vrows, int R,
-    const float* __restrict__ gscale, int P, TG* __restrict__ g, int Kc) {
-  constexpr int KC = 16;           // bins per chunk
-  constexpr int ROW = 2 * KC + 4;  // psi floats per frame row (padded)
-  constexpr int WBUF = 32 * ROW;   // one wave's chunk buffer (floats)
-  __shared__ __attribute__((aligned(16))) float lds[4 * 2 * WBUF];  // [wave][buf]; reused for the reduction
-  const int p = blockIdx.y;
+    const int32_t* __restrict__ off, int max_np, const float* __restrict__ S, int Kp, int srows,
+    const int2* __restrict__ tasks, int ntasks, float* __restrict__ part, int64_t ldp, int PN,
+    const float* __restrict__ V, int vrows, int R) {
+  constexpr int RB = CB * 8 + 16;  // bytes per (mic, frame) row of u
+  constexpr int SR = 2 * CB + 4;   // floats per S row in LDS
+  // CB is chosen so that M * 32 * CB <= 4096 (CB = 16, 8, 4 for M <= 8, 16, 32)
+  constexpr int UPER = 4096 / 256;  // u items per thread
+  extern __shared__ __attribute__((aligned(16))) unsigned char slds[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r32 = lane & 31, gq = lane >> 5;
   const int64_t fbase = static_cast<int64_t>(blockIdx.x) * 32;
-  const int64_t frame = fbase + r32;
-  const bool fvalid = frame < L;
-  const int m = pm[p], mq = pmp[p];
-  const int n_p = np[p], nrows = 2 * n_p + 1;
-  // this wave's quarter of the single-sided bins 1..K-1, in whole chunks
-  const int cpw = ((K - 1 + 3) / 4 + KC - 1) / KC;  // chunks per wave
-  const int c0 = wave * cpw;
-  float* wb = lds + wave * 2 * WBUF;
+  const int ks = blockIdx.y;
+  const int kb0 = ks * SLICE_BINS + 1;                           // first bin of the slice
+  const int nb = std::min(SLICE_BINS, K - 1 - ks * SLICE_BINS);  // bins in the slice
+  const int nch = (nb + CB - 1) / CB;
+  const int bufb = slice_buf_bytes<CB>(M, srows);
+  const int uitems = M * 32 * CB;          // complex values of u per chunk
+  const int sitems = srows * (CB / 2);     // 16-byte pieces of S per chunk
 
-  // staging: lane handles frames lane / 8 + 8 it (it < 4), bin pair lane % 8
-  float2 pre[4][4];  // [item][y_m k, y_m k+1, y_m' k, y_m' k+1]
+  float2 pu[UPER];
+  f32x4 psv[4];  // S pieces per thread (the host checks srows * CB / 2 <= 1024)
   auto gload = [&](int c) {
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int64_t f = std::min<int64_t>(fbase + lane / 8 + 8 * it, L - 1);
-      const int k0 = c * KC + 2 * (lane % 8) + 1;
-      const float2* a = Y + (f * M + m) * (K + 1);
-      const float2* b = Y + (f * M + mq) * (K + 1);
-      const float2 zero = make_float2(0.f, 0.f);
-      pre[it][0] = k0 <= K - 1 ? a[k0] : zero;
-      pre[it][1] = k0 + 1 <= K - 1 ? a[k0 + 1] : zero;
-      pre[it][2] = k0 <= K - 1 ? b[k0] : zero;
-      pre[it][3] = k0 + 1 <= K - 1 ? b[k0 + 1] : zero;
-    }
-  };
-  auto lstore = [&](float* buf) {
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int fl = lane / 8 + 8 * it;
-      const float2 u0 = unit_phase(pre[it][0]), v0 = unit_phase(pre[it][2]);
-      const float2 u1 = unit_phase(pre[it][1]), v1 = unit_phase(pre[it][3]);
-      f32x4 q;  // psi = u_m conj(u_m') for the two bins
-      q.x = u0.x * v0.x + u0.y * v0.y;
-      q.y = u0.y * v0.x - u0.x * v0.y;
-      q.z = u1.x * v1.x + u1.y * v1.y;
-      q.w = u1.y * v1.x - u1.x * v1.y;
-      *reinterpret_cast<f32x4*>(buf + fl * ROW + 4 * (lane % 8)) = q;
-    }
-  };
-
-  float gacc[RMAX];
-#pragma unroll
-  for (int r = 0; r < RMAX; ++r) gacc[r] = 0.0f;
-
-  for (int t0 = 0; t0 < nrows; t0 += 32) {
-    // lane's A row: lag n = -N_p + t0 + r32 -> table row max_np - N_p + t0 + r32
-    const float* srow = S + static_cast<int64_t>(max_np - n_p + t0 + r32) * Kp + 4 * gq;
-    f32x16 acc;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-    __syncthreads();  // previous tile's reduction is done with the buffers
-    gload(c0);
-    lstore(wb);
-    for (int c = 0; c < cpw; ++c) {
-      float* cur = wb + (c & 1) * WBUF;
-      if (c + 1 < cpw) gload(c0 + c + 1);
-      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS stores landed
-      __builtin_amdgcn_wave_barrier();
-      const float* prow = cur + r32 * ROW + 4 * gq;
-      const float* sc = srow + (c0 + c) * 2 * KC;
-#pragma unroll
-      for (int st = 0; st < KC / 4; ++st) {
-        const f32x4 a = *reinterpret_cast<const f32x4*>(sc + 8 * st);
-        const f32x4 bq = *reinterpret_cast<const f32x4*>(prow + 8 * st);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, bq.x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, bq.y, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, bq.z, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, bq.w, acc, 0, 0, 0);
+    for (int i = 0; i < UPER; ++i) {
+      const int e = tid + 256 * i;
+      pu[i] = make_float2(0.f, 0.f);
+      if (e < uitems) {
+        const int b = e % CB, row = e / CB;
+        const int mic = row / 32, fl = row % 32;
+        const int k = kb0 + c * CB + b;
+        const int64_t f = std::min<int64_t>(fbase + fl, L - 1);
+        if (k <= K - 1) pu[i] = Y[(f * M + mic) * (K + 1) + k];
       }
-      __builtin_amdgcn_wave_barrier();
-      if (c + 1 < cpw) lstore(wb + ((c + 1) & 1) * WBUF);
     }
-    // sum the four waves' partial tiles
-    __syncthreads();
-    float* red = lds;  // [wave][v][lane]
 #pragma unroll
-    for (int v = 0; v < 16; ++v) red[(wave * 16 + v) * 64 + lane] = acc[v];
-    __syncthreads();
-    if (wave == 0) {
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + 256 * i;
+      if (e < sitems) {
+        const int row = e / (CB / 2), q = e % (CB / 2);
+        psv[i] = *reinterpret_cast<const f32x4*>(S + static_cast<int64_t>(row) * Kp + 2 * (kb0 - 1 + c * CB) + 4 * q);
+      }
+    }
+  };
+  auto lstore = [&](unsigned char* buf) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v)
-        acc[v] = red[v * 64 + lane] + red[(16 + v) * 64 + lane] + red[(32 + v) * 64 + lane] +
-                 red[(48 + v) * 64 + lane];
-      // accumulator layout: register v of lane i holds lag row
-      // t0 + 8 (v / 4) + 4 (i / 32) + v % 4 of frame column i % 32
+    for (int i = 0; i < UPER; ++i) {
+      const int e = tid + 256 * i;
+      if (e < uitems) {
+        const int b = e % CB, row = e / CB;
+        *reinterpret_cast<float2*>(buf + row * RB + 8 * b) = unit_phase(pu[i]);
+      }
+    }
+    float* sb = reinterpret_cast<float*>(buf + M * 32 * RB);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + 256 * i;
+      if (e < sitems) {
+        const int row = e / (CB / 2), q = e % (CB / 2);
+        *reinterpret_cast<f32x4*>(sb + row * SR + 4 * q) = psv[i];
+      }
+    }
+  };
+
+  for (int pass = 0; pass * 4 * SLICE_TPW < ntasks; ++pass) {
+    f32x16 acc[SLICE_TPW];
+    int tp[SLICE_TPW], tt[SLICE_TPW];
+#pragma unroll
+    for (int i = 0; i < SLICE_TPW; ++i) {
+      const int id = pass * 4 * SLICE_TPW + wave + 4 * i;
+      tp[i] = id < ntasks ? tasks[id].x : -1;
+      tt[i] = id < ntasks ? tasks[id].y : 0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][v] = 0.0f;
+    }
+    __syncthreads();
+    gload(0);
+    lstore(slds);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+      const unsigned char* cur = slds + (c & 1) * bufb;
+      const float* sb = reinterpret_cast<const float*>(cur + M * 32 * RB);
+      if (c + 1 < nch) gload(c + 1);
+#pragma unroll
+      for (int i = 0; i < SLICE_TPW; ++i) {
+        if (tp[i] < 0) continue;  // wave-uniform
+        const int p = tp[i];
+        const unsigned char* um = cur + (pm[p] * 32 + r32) * RB + 16 * gq;
+        const unsigned char* uq = cur + (pmp[p] * 32 + r32) * RB + 16 * gq;
+        const float* srow = sb + (max_np - np[p] + 32 * tt[i] + r32) * SR + 4 * gq;
+#pragma unroll
+        for (int st = 0; st < CB / 4; ++st) {
+          const f32x4 a = *reinterpret_cast<const f32x4*>(srow + 8 * st);
+          const f32x4 x = *reinterpret_cast<const f32x4*>(um + 32 * st);  // u_m bins 2gq, 2gq+1
+          const f32x4 y = *reinterpret_cast<const f32x4*>(uq + 32 * st);  // u_m'
+          // psi = u_m conj(u_m')
+          const float b0 = x.x * y.x + x.y * y.y, b1 = x.y * y.x - x.x * y.y;
+          const float b2 = x.z * y.z + x.w * y.w, b3 = x.w * y.z - x.z * y.w;
+          acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b0, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b1, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b2, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b3, acc[i], 0, 0, 0);
+        }
+      }
+      if (c + 1 < nch) lstore(slds + ((c + 1) & 1) * bufb);
+      __syncthreads();
+    }
+    // accumulator layout: register v of lane i holds lag row
+    // 32 t + 8 (v / 4) + 4 (i / 32) + v % 4 of frame column i % 32
+    const int64_t frame = fbase + r32;
+#pragma unroll
+    for (int i = 0; i < SLICE_TPW; ++i) {
+      if (tp[i] < 0) continue;
+      const int nrows = 2 * np[tp[i]] + 1;
       if (MODE == 0) {
-        if (fvalid) {
+        if (frame < L) {
+          float* dst = part + (static_cast<int64_t>(ks) * PN + off[tp[i]]) * ldp + frame;
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
-            const int lag = t0 + 8 * (v / 4) + 4 * gq + (v % 4);
-            if (lag < nrows) xiT[static_cast<int64_t>(off[p] + lag) * ldxi + frame] = acc[v];
+            const int lag = 32 * tt[i] + 8 * (v / 4) + 4 * gq + (v % 4);
+            if (lag < nrows) dst[static_cast<int64_t>(lag) * ldp] = acc[i][v];
           }
         }
       } else {
-        const float* Vp = V + static_cast<int64_t>(p) * vrows * R;
+        // this slice's share of the fat stage: g_p[r] += V_p[n][r] xi_p[n]
+        const float* Vp = V + static_cast<int64_t>(tp[i]) * vrows * R;
+        float gp[RMAX];
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) gp[r] = 0.0f;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-          const int lag = t0 + 8 * (v / 4) + 4 * gq + (v % 4);
+          const int lag = 32 * tt[i] + 8 * (v / 4) + 4 * gq + (v % 4);
           if (lag < nrows) {
 #pragma unroll
             for (int r = 0; r < RMAX; ++r)
-              if (r < R) gacc[r] += Vp[lag * R + r] * acc[v];
+              if (r < R) gp[r] += Vp[lag * R + r] * acc[i][v];
           }
+        }
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) gp[r] += __shfl_xor(gp[r], 32);
+        if (gq == 0 && frame < L) {
+          // part[slice][task][r][frame]
+          const int id = pass * 4 * SLICE_TPW + wave + 4 * i;
+          float* dst = part + ((static_cast<int64_t>(ks) * ntasks + id) * R) * ldp + frame;
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r)
+            if (r < R) dst[static_cast<int64_t>(r) * ldp] = gp[r];
         }
       }
     }
   }
-  if (MODE == 1 && wave == 0) {
-    const float sc = gscale[p];
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) gacc[r] += __shfl_xor(gacc[r], 32);
-    if (gq == 0 && fvalid) {
-      TG* gl = g + frame * Kc;
-#pragma unroll
-      for (int r = 0; r < RMAX; ++r)
-        if (r < R) gl[p * R + r] = cvt<TG>(gacc[r] * sc);
-      if (p == P - 1)
-        for (int c = P * R; c < Kc; ++c) gl[c] = cvt<TG>(0.0f);
+}
+
+// MODE 0: xi^T[n][l] = sum over slices.  MODE 1: g[l][p R + r] = gscale_p *
+// sum over slices and the pair's lag tiles of the partial fat-stage sums
+// (one thread per (frame, column); columns past P R are zero padding).
+template <int MODE, typename TG>
+__global__ __launch_bounds__(256) void slice_reduce(const float* __restrict__ part, int nslices,
+                                                    int64_t ldp, int PN, int L,
+                                                    float* __restrict__ xiT,
+                                                    const int32_t* __restrict__ task0,
+                                                    const int32_t* __restrict__ ntiles, int ntasks,
+                                                    int R, const float* __restrict__ gscale, int P,
+                                                    TG* __restrict__ g, int Kc) {
+  if (MODE == 0) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t n = i / L, l = i % L;
+    if (n >= PN) return;
+    float s = 0.0f;
+    for (int k = 0; k < nslices; ++k) s += part[(static_cast<int64_t>(k) * PN + n) * ldp + l];
+    xiT[n * ldp + l] = s;
+  } else {
+    const int64_t l = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (l >= L) return;
+    float x = 0.0f;
+    if (c < P * R) {
+      const int p = c / R, r = c % R;
+      for (int k = 0; k < nslices; ++k)
+        for (int t = 0; t < ntiles[p]; ++t)
+          x += part[((static_cast<int64_t>(k) * ntasks + task0[p] + t) * R + r) * ldp + l];
+      x *= gscale[p];
     }
+    g[l * Kc + c] = cvt<TG>(x);
   }
 }
 
@@ -1034,7 +1098,7 @@ void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t
       }
       HIP_OK(hipDeviceSynchronize());
     } catch (...) {
-      hipFree(d_x);
+      (void)hipFree(d_x);
       throw;
     }
     HIP_OK(hipFree(d_x));
@@ -1060,6 +1124,26 @@ void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t
     }
     dp.d_S = static_cast<float*>(A.get(S.size() * 4));
     upload(dp.d_S, S);
+    // sampling tasks: (pair, 32-lag tile)
+    std::vector<int32_t> tk;
+    for (int p = 0; p < P; ++p)
+      for (int t = 0; 32 * t < 2 * hp.np[p] + 1; ++t) {
+        tk.push_back(p);
+        tk.push_back(t);
+      }
+    dp.ntasks = static_cast<int>(tk.size() / 2);
+    dp.d_tasks = static_cast<int32_t*>(A.get(tk.size() * 4));
+    upload(dp.d_tasks, tk);
+    std::vector<int32_t> t0(P), nt(P);
+    for (int p = 0, id = 0; p < P; ++p) {
+      t0[p] = id;
+      nt[p] = (2 * hp.np[p] + 1 + 31) / 32;
+      id += nt[p];
+    }
+    dp.d_task0 = static_cast<int32_t*>(A.get(P * 4));
+    dp.d_ntiles = static_cast<int32_t*>(A.get(P * 4));
+    upload(dp.d_task0, t0);
+    upload(dp.d_ntiles, nt);
   }
 
   if (hp.variant == SRP_SLRI) {
@@ -1107,7 +1191,7 @@ void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t
       convert_dtype(hp.dtype, d_stage, dp.d_U, static_cast<int64_t>(Us.size()));
       HIP_OK(hipDeviceSynchronize());
     } catch (...) {
-      hipFree(d_stage);
+      (void)hipFree(d_stage);
       throw;
     }
     HIP_OK(hipFree(d_stage));
@@ -1146,7 +1230,7 @@ void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t
       convert_dtype(hp.dtype, d_stage, dp.d_w, static_cast<int64_t>(ws.size()));
       HIP_OK(hipDeviceSynchronize());
     } catch (...) {
-      hipFree(d_stage);
+      (void)hipFree(d_stage);
       throw;
     }
     HIP_OK(hipFree(d_stage));
@@ -1195,15 +1279,15 @@ void device_profile_collect(DevicePlan& dp,
 
 void device_free(DevicePlan& dp) {
   for (const auto& sp : dp.spans) {
-    hipEventDestroy(sp.start);
-    hipEventDestroy(sp.stop);
+    (void)hipEventDestroy(sp.start);
+    (void)hipEventDestroy(sp.stop);
   }
-  for (hipEvent_t e : dp.event_pool) hipEventDestroy(e);
-  void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S,
+  for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
+  void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_tasks, dp.d_task0, dp.d_ntiles,
                   dp.d_U, dp.d_V, dp.d_gscale, dp.d_start, dp.d_w, dp.d_chunk_p0,
                   dp.ws};
   for (void* p : ptrs)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   dp = DevicePlan{};
 }
 
@@ -1211,7 +1295,7 @@ namespace {
 
 struct WsLayout {
   int64_t Lc = 0, Lpad = 0;
-  size_t psi = 0, xi = 0, g = 0, total = 0;
+  size_t psi = 0, xi = 0, part = 0, g = 0, total = 0;
 };
 
 WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t frame_tile) {
@@ -1224,6 +1308,10 @@ WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t 
   if (hp.variant != SRP_FD) {
     w.xi = off;
     off = align256(off + static_cast<size_t>(hp.PN) * w.Lpad * 4);
+    w.part = off;
+    const size_t nsl = static_cast<size_t>((hp.K - 1 + SLICE_BINS - 1) / SLICE_BINS);
+    const size_t rows = hp.variant == SRP_SLRI ? static_cast<size_t>(dp.ntasks) * hp.R : static_cast<size_t>(hp.PN);
+    off = align256(off + nsl * rows * w.Lpad * 4);
   }
   if (hp.variant == SRP_SLRI) {
     w.g = off;
@@ -1306,26 +1394,62 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
                                                       Lpad, st);
 }
 
-// Fused PHAT + sampling (+ fat stage for SLRI) straight from the frames.
+// Sampling front end straight from the frames: spectral slices, then the
+// slice reduction (MODE 0: xi^T, MODE 1: SLRI fat stage into g).
 template <int MODE, typename TG>
 void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t Lc, float* xiT, int64_t ldxi,
-                  void* g, hipStream_t st) {
-  dim3 grid(static_cast<unsigned>((Lc + 31) / 32), static_cast<unsigned>(hp.P));
+                  float* part, void* g, hipStream_t st) {
+  const int nslices = (hp.K - 1 + SLICE_BINS - 1) / SLICE_BINS;
+  dim3 grid(static_cast<unsigned>((Lc + 31) / 32), static_cast<unsigned>(nslices));
+  const int CB = hp.M <= 8 ? 16 : (hp.M <= 16 ? 8 : 4);
+  const int srows = dp.samp_rows + 32;  // every S row a task can touch
+  if (srows * (CB / 2) > 1024) throw Error{SRP_E_UNSUPPORTED, "too many lags for the sampling tile"};
   const int vrows = 2 * hp.max_np + 1;
-  const char* kname = MODE == 0 ? "front_sampling" : "front_sampling_fat";
-#define SRP_FRONT(RM)                                                                                       \
-  TRACED(dp, kname, st,                                                                                     \
-         hipLaunchKernelGGL((front_fused<MODE, TG, RM>), grid, dim3(256), 0, st,                            \
-                            static_cast<const float2*>(frames), hp.M, hp.K, static_cast<int>(Lc), dp.d_pm, \
-                            dp.d_pmp, dp.d_np, dp.d_off, hp.max_np, dp.d_S, dp.Kp, xiT, ldxi, dp.d_V,      \
-                            vrows, hp.R, dp.d_gscale, hp.P, static_cast<TG*>(g), dp.Kc))
-  if (MODE == 0 || hp.R <= 8)
-    SRP_FRONT(8);
-  else if (hp.R <= 16)
-    SRP_FRONT(16);
+  const int rmax = MODE == 0 || hp.R <= 8 ? 8 : (hp.R <= 16 ? 16 : 32);
+#define SRP_SLICES(CBV, RM)                                                                                   \
+  do {                                                                                                        \
+    auto kern = &spectral_slices<MODE, CBV, RM>;                                                              \
+    const size_t lds = 2 * static_cast<size_t>(slice_buf_bytes<CBV>(hp.M, srows));                            \
+    if (lds > 160 * 1024) throw Error{SRP_E_UNSUPPORTED, "sampling tile exceeds the LDS"};                    \
+    if (lds > 65536)                                                                                          \
+      HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),                                         \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));         \
+    TRACED(dp, "spectral_slices", st,                                                                         \
+           hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, static_cast<const float2*>(frames), hp.M, hp.K,  \
+                              static_cast<int>(Lc), dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, hp.max_np, dp.d_S,  \
+                              dp.Kp, srows, reinterpret_cast<const int2*>(dp.d_tasks), dp.ntasks, part, ldxi, \
+                              hp.PN, dp.d_V, vrows, hp.R));                                                   \
+  } while (0)
+#define SRP_SLICES_CB(RM)  \
+  do {                     \
+    if (CB == 16)          \
+      SRP_SLICES(16, RM);  \
+    else if (CB == 8)      \
+      SRP_SLICES(8, RM);   \
+    else                   \
+      SRP_SLICES(4, RM);   \
+  } while (0)
+  if (rmax == 8)
+    SRP_SLICES_CB(8);
+  else if (rmax == 16)
+    SRP_SLICES_CB(16);
   else
-    SRP_FRONT(32);
-#undef SRP_FRONT
+    SRP_SLICES_CB(32);
+#undef SRP_SLICES_CB
+#undef SRP_SLICES
+  if constexpr (MODE == 0) {
+    const int64_t n = static_cast<int64_t>(hp.PN) * Lc;
+    TRACED(dp, "slice_reduce", st,
+           hipLaunchKernelGGL((slice_reduce<0, float>), dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                              st, part, nslices, ldxi, hp.PN, static_cast<int>(Lc), xiT, dp.d_task0, dp.d_ntiles,
+                              dp.ntasks, hp.R, dp.d_gscale, hp.P, static_cast<float*>(nullptr), dp.Kc));
+  } else {
+    dim3 g2(static_cast<unsigned>((Lc + 255) / 256), static_cast<unsigned>(dp.Kc));
+    TRACED(dp, "slice_reduce_fat", st,
+           hipLaunchKernelGGL((slice_reduce<1, TG>), g2, dim3(256), 0, st, part, nslices, ldxi, hp.PN,
+                              static_cast<int>(Lc), xiT, dp.d_task0, dp.d_ntiles, dp.ntasks, hp.R, dp.d_gscale,
+                              hp.P, static_cast<TG*>(g), dp.Kc));
+  }
 }
 
 template <typename TW, int Q>
@@ -1426,31 +1550,32 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
       }
       continue;
     }
-    // SLRI and SSPI: fused PHAT + sampling (+ fat stage) from the frames
+    // SLRI and SSPI: PHAT + sampling (+ fat stage) straight from the frames
     float* xiT = reinterpret_cast<float*>(base + lay.xi);
+    float* part = reinterpret_cast<float*>(base + lay.part);
     float* z = static_cast<float*>(maps) + l0 * hp.J;
     if (hp.variant == SRP_SLRI) {
       void* g = base + lay.g;
       switch (hp.dtype) {
         case SRP_F32:
-          launch_front<1, float>(hp, dp, fr, Lc, nullptr, 0, g, st);
+          launch_front<1, float>(hp, dp, fr, Lc, xiT, lay.Lpad, part, g, st);
           launch_tall_gemm<float>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
           break;
         case SRP_BF16:
-          launch_front<1, __bf16>(hp, dp, fr, Lc, nullptr, 0, g, st);
+          launch_front<1, __bf16>(hp, dp, fr, Lc, xiT, lay.Lpad, part, g, st);
           launch_tall_gemm<__bf16>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
           break;
         case SRP_F16:
-          launch_front<1, _Float16>(hp, dp, fr, Lc, nullptr, 0, g, st);
+          launch_front<1, _Float16>(hp, dp, fr, Lc, xiT, lay.Lpad, part, g, st);
           launch_tall_gemm<_Float16>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
           break;
         case SRP_FP8_E4M3:
-          launch_front<1, fp8>(hp, dp, fr, Lc, nullptr, 0, g, st);
+          launch_front<1, fp8>(hp, dp, fr, Lc, xiT, lay.Lpad, part, g, st);
           launch_tall_gemm<fp8>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
           break;
       }
     } else {
-      launch_front<0, float>(hp, dp, fr, Lc, xiT, lay.Lpad, nullptr, st);
+      launch_front<0, float>(hp, dp, fr, Lc, xiT, lay.Lpad, part, nullptr, st);
       switch (hp.dtype) {
         case SRP_F32: launch_sspi<float>(hp, dp, xiT, lay.Lpad, Lc, z, st); break;
         case SRP_BF16: launch_sspi<__bf16>(hp, dp, xiT, lay.Lpad, Lc, z, st); break;
@@ -1477,7 +1602,8 @@ void device_gcc_samples(const HostPlan& hp, DevicePlan& dp, const void* frames, 
     const int64_t Lc = std::min(lay.Lc, L - l0);
     const void* fr = static_cast<const float2*>(frames) + l0 * frame_elems;
     float* xiT = reinterpret_cast<float*>(base + lay.xi);
-    launch_front<0, float>(hp, dp, fr, Lc, xiT, lay.Lpad, nullptr, st);
+    float* part = reinterpret_cast<float*>(base + lay.part);
+    launch_front<0, float>(hp, dp, fr, Lc, xiT, lay.Lpad, part, nullptr, st);
     const int64_t n = static_cast<int64_t>(hp.PN) * Lc;
     TRACED(dp, "transpose_xi", st,
            hipLaunchKernelGGL(transpose_xi, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
