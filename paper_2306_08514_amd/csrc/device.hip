@@ -4,7 +4,8 @@
 //   phat_kernel      PHAT-weighted cross-spectra psi_p[l, k] (FD)      eq. (2)
 //   gemm_nt (FD)     z = 2 Re[H psi] as a real MFMA GEMM              eq. (22)
 //   spectral_slices  PHAT + xi_p = 2 Re[S_p psi_p] per spectral slice    eqs. (2), (40)
-//   slice_reduce     sum of slices (+ g_p = V_p^T xi_p for SLRI)        eq. (57)
+//   slice_reduce     sum of the slices' partial GCC samples
+//   slri_fat         g_p = V_p^T xi_p                                   eq. (57)
 //   gemm_nt (tall)   z = sum_p U_p g_p                                  eq. (57)
 //   sspi_gather      z = sum_p sum_q w[j,p,q] xi_p[s(j,p) + q]          eq. (58)
 #include <hip/hip_runtime.h>
@@ -477,13 +478,12 @@ __device__ __host__ inline int slice_buf_bytes(int M, int srows) {
   return M * 32 * (CB * 8 + 16) + srows * (2 * CB + 4) * 4;
 }
 
-template <int MODE, int CB, int RMAX>
+template <int CB>
 __global__ __launch_bounds__(256) void spectral_slices(
     const float2* __restrict__ Y, int M, int K, int L, const int32_t* __restrict__ pm,
     const int32_t* __restrict__ pmp, const int32_t* __restrict__ np,
     const int32_t* __restrict__ off, int max_np, const float* __restrict__ S, int Kp, int srows,
-    const int2* __restrict__ tasks, int ntasks, float* __restrict__ part, int64_t ldp, int PN,
-    const float* __restrict__ V, int vrows, int R) {
+    const int2* __restrict__ tasks, int ntasks, float* __restrict__ part, int64_t ldp, int PN) {
   constexpr int RB = CB * 8 + 16;  // bytes per (mic, frame) row of u
   constexpr int SR = 2 * CB + 4;   // floats per S row in LDS
   // CB is chosen so that M * 32 * CB <= 4096 (CB = 16, 8, 4 for M <= 8, 16, 32)
@@ -590,81 +590,70 @@ __global__ __launch_bounds__(256) void spectral_slices(
     // accumulator layout: register v of lane i holds lag row
     // 32 t + 8 (v / 4) + 4 (i / 32) + v % 4 of frame column i % 32
     const int64_t frame = fbase + r32;
+    if (frame < L) {
 #pragma unroll
-    for (int i = 0; i < SLICE_TPW; ++i) {
-      if (tp[i] < 0) continue;
-      const int nrows = 2 * np[tp[i]] + 1;
-      if (MODE == 0) {
-        if (frame < L) {
-          float* dst = part + (static_cast<int64_t>(ks) * PN + off[tp[i]]) * ldp + frame;
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const int lag = 32 * tt[i] + 8 * (v / 4) + 4 * gq + (v % 4);
-            if (lag < nrows) dst[static_cast<int64_t>(lag) * ldp] = acc[i][v];
-          }
-        }
-      } else {
-        // this slice's share of the fat stage: g_p[r] += V_p[n][r] xi_p[n]
-        const float* Vp = V + static_cast<int64_t>(tp[i]) * vrows * R;
-        float gp[RMAX];
-#pragma unroll
-        for (int r = 0; r < RMAX; ++r) gp[r] = 0.0f;
+      for (int i = 0; i < SLICE_TPW; ++i) {
+        if (tp[i] < 0) continue;
+        const int nrows = 2 * np[tp[i]] + 1;
+        float* dst = part + (static_cast<int64_t>(ks) * PN + off[tp[i]]) * ldp + frame;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int lag = 32 * tt[i] + 8 * (v / 4) + 4 * gq + (v % 4);
-          if (lag < nrows) {
-#pragma unroll
-            for (int r = 0; r < RMAX; ++r)
-              if (r < R) gp[r] += Vp[lag * R + r] * acc[i][v];
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < RMAX; ++r) gp[r] += __shfl_xor(gp[r], 32);
-        if (gq == 0 && frame < L) {
-          // part[slice][task][r][frame]
-          const int id = pass * 4 * SLICE_TPW + wave + 4 * i;
-          float* dst = part + ((static_cast<int64_t>(ks) * ntasks + id) * R) * ldp + frame;
-#pragma unroll
-          for (int r = 0; r < RMAX; ++r)
-            if (r < R) dst[static_cast<int64_t>(r) * ldp] = gp[r];
+          if (lag < nrows) dst[static_cast<int64_t>(lag) * ldp] = acc[i][v];
         }
       }
     }
   }
 }
 
-// MODE 0: xi^T[n][l] = sum over slices.  MODE 1: g[l][p R + r] = gscale_p *
-// sum over slices and the pair's lag tiles of the partial fat-stage sums
-// (one thread per (frame, column); columns past P R are zero padding).
-template <int MODE, typename TG>
+// xi^T[n][l] = sum of the slices' partial samples, in slice order.
 __global__ __launch_bounds__(256) void slice_reduce(const float* __restrict__ part, int nslices,
                                                     int64_t ldp, int PN, int L,
-                                                    float* __restrict__ xiT,
-                                                    const int32_t* __restrict__ task0,
-                                                    const int32_t* __restrict__ ntiles, int ntasks,
-                                                    int R, const float* __restrict__ gscale, int P,
-                                                    TG* __restrict__ g, int Kc) {
-  if (MODE == 0) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    const int64_t n = i / L, l = i % L;
-    if (n >= PN) return;
-    float s = 0.0f;
-    for (int k = 0; k < nslices; ++k) s += part[(static_cast<int64_t>(k) * PN + n) * ldp + l];
-    xiT[n * ldp + l] = s;
-  } else {
-    const int64_t l = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    const int c = blockIdx.y;
-    if (l >= L) return;
-    float x = 0.0f;
-    if (c < P * R) {
-      const int p = c / R, r = c % R;
-      for (int k = 0; k < nslices; ++k)
-        for (int t = 0; t < ntiles[p]; ++t)
-          x += part[((static_cast<int64_t>(k) * ntasks + task0[p] + t) * R + r) * ldp + l];
-      x *= gscale[p];
-    }
-    g[l * Kc + c] = cvt<TG>(x);
+                                                    float* __restrict__ xiT) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t n = i / L, l = i % L;
+  if (n >= PN) return;
+  float s = 0.0f;
+  for (int k = 0; k < nslices; ++k) s += part[(static_cast<int64_t>(k) * PN + n) * ldp + l];
+  xiT[n * ldp + l] = s;
+}
+
+// SLRI fat stage g[l][p R + r] = gscale_p sum_n V_p[n][r] xi_p[l][n]
+// (eq. (57)): one thread per frame of pair blockIdx.y; V_p is wave-uniform
+// (scalar loads) and the xi^T reads are coalesced along frames.  Pair index
+// P zero-fills g's padding columns.
+template <typename TG, int RMAX>
+__global__ __launch_bounds__(256) void slri_fat(const float* __restrict__ xiT, int64_t ldxi, int L,
+                                                const int32_t* __restrict__ np,
+                                                const int32_t* __restrict__ off,
+                                                const float* __restrict__ V, int vrows, int R,
+                                                const float* __restrict__ gscale, int P,
+                                                TG* __restrict__ g, int Kc) {
+  const int64_t l = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int p = blockIdx.y;
+  if (l >= L) return;
+  TG* gl = g + l * Kc;
+  if (p == P) {
+    for (int c = P * R; c < Kc; ++c) gl[c] = cvt<TG>(0.0f);
+    return;
   }
+  float acc[RMAX];
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) acc[r] = 0.0f;
+  const int nrows = 2 * np[p] + 1;
+  const float* xs = xiT + static_cast<int64_t>(off[p]) * ldxi + l;
+  const float* Vp = V + static_cast<int64_t>(p) * vrows * R;
+#pragma unroll 4
+  for (int n = 0; n < nrows; ++n) {
+    const float x = xs[static_cast<int64_t>(n) * ldxi];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+      if (r < R) acc[r] += Vp[n * R + r] * x;
+  }
+  const float sc = gscale[p];
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r)
+    if (r < R) gl[p * R + r] = cvt<TG>(acc[r] * sc);
 }
 
 // ====================================================== SLRI tall stream ===
@@ -1134,16 +1123,6 @@ void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t
     dp.ntasks = static_cast<int>(tk.size() / 2);
     dp.d_tasks = static_cast<int32_t*>(A.get(tk.size() * 4));
     upload(dp.d_tasks, tk);
-    std::vector<int32_t> t0(P), nt(P);
-    for (int p = 0, id = 0; p < P; ++p) {
-      t0[p] = id;
-      nt[p] = (2 * hp.np[p] + 1 + 31) / 32;
-      id += nt[p];
-    }
-    dp.d_task0 = static_cast<int32_t*>(A.get(P * 4));
-    dp.d_ntiles = static_cast<int32_t*>(A.get(P * 4));
-    upload(dp.d_task0, t0);
-    upload(dp.d_ntiles, nt);
   }
 
   if (hp.variant == SRP_SLRI) {
@@ -1283,7 +1262,7 @@ void device_free(DevicePlan& dp) {
     (void)hipEventDestroy(sp.stop);
   }
   for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
-  void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_tasks, dp.d_task0, dp.d_ntiles,
+  void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_tasks,
                   dp.d_U, dp.d_V, dp.d_gscale, dp.d_start, dp.d_w, dp.d_chunk_p0,
                   dp.ws};
   for (void* p : ptrs)
@@ -1310,8 +1289,7 @@ WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t 
     off = align256(off + static_cast<size_t>(hp.PN) * w.Lpad * 4);
     w.part = off;
     const size_t nsl = static_cast<size_t>((hp.K - 1 + SLICE_BINS - 1) / SLICE_BINS);
-    const size_t rows = hp.variant == SRP_SLRI ? static_cast<size_t>(dp.ntasks) * hp.R : static_cast<size_t>(hp.PN);
-    off = align256(off + nsl * rows * w.Lpad * 4);
+    off = align256(off + nsl * static_cast<size_t>(hp.PN) * w.Lpad * 4);
   }
   if (hp.variant == SRP_SLRI) {
     w.g = off;
@@ -1394,8 +1372,8 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
                                                       Lpad, st);
 }
 
-// Sampling front end straight from the frames: spectral slices, then the
-// slice reduction (MODE 0: xi^T, MODE 1: SLRI fat stage into g).
+// Sampling front end straight from the frames: spectral slices, the slice
+// reduction into xi^T, and for SLRI (MODE 1) the fat stage into g.
 template <int MODE, typename TG>
 void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t Lc, float* xiT, int64_t ldxi,
                   float* part, void* g, hipStream_t st) {
@@ -1404,11 +1382,9 @@ void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_
   const int CB = hp.M <= 8 ? 16 : (hp.M <= 16 ? 8 : 4);
   const int srows = dp.samp_rows + 32;  // every S row a task can touch
   if (srows * (CB / 2) > 1024) throw Error{SRP_E_UNSUPPORTED, "too many lags for the sampling tile"};
-  const int vrows = 2 * hp.max_np + 1;
-  const int rmax = MODE == 0 || hp.R <= 8 ? 8 : (hp.R <= 16 ? 16 : 32);
-#define SRP_SLICES(CBV, RM)                                                                                   \
+#define SRP_SLICES(CBV)                                                                                       \
   do {                                                                                                        \
-    auto kern = &spectral_slices<MODE, CBV, RM>;                                                              \
+    auto kern = &spectral_slices<CBV>;                                                                        \
     const size_t lds = 2 * static_cast<size_t>(slice_buf_bytes<CBV>(hp.M, srows));                            \
     if (lds > 160 * 1024) throw Error{SRP_E_UNSUPPORTED, "sampling tile exceeds the LDS"};                    \
     if (lds > 65536)                                                                                          \
@@ -1418,37 +1394,34 @@ void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_
            hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, static_cast<const float2*>(frames), hp.M, hp.K,  \
                               static_cast<int>(Lc), dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, hp.max_np, dp.d_S,  \
                               dp.Kp, srows, reinterpret_cast<const int2*>(dp.d_tasks), dp.ntasks, part, ldxi, \
-                              hp.PN, dp.d_V, vrows, hp.R));                                                   \
+                              hp.PN));                                                                        \
   } while (0)
-#define SRP_SLICES_CB(RM)  \
-  do {                     \
-    if (CB == 16)          \
-      SRP_SLICES(16, RM);  \
-    else if (CB == 8)      \
-      SRP_SLICES(8, RM);   \
-    else                   \
-      SRP_SLICES(4, RM);   \
-  } while (0)
-  if (rmax == 8)
-    SRP_SLICES_CB(8);
-  else if (rmax == 16)
-    SRP_SLICES_CB(16);
+  if (CB == 16)
+    SRP_SLICES(16);
+  else if (CB == 8)
+    SRP_SLICES(8);
   else
-    SRP_SLICES_CB(32);
-#undef SRP_SLICES_CB
+    SRP_SLICES(4);
 #undef SRP_SLICES
-  if constexpr (MODE == 0) {
-    const int64_t n = static_cast<int64_t>(hp.PN) * Lc;
-    TRACED(dp, "slice_reduce", st,
-           hipLaunchKernelGGL((slice_reduce<0, float>), dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
-                              st, part, nslices, ldxi, hp.PN, static_cast<int>(Lc), xiT, dp.d_task0, dp.d_ntiles,
-                              dp.ntasks, hp.R, dp.d_gscale, hp.P, static_cast<float*>(nullptr), dp.Kc));
-  } else {
-    dim3 g2(static_cast<unsigned>((Lc + 255) / 256), static_cast<unsigned>(dp.Kc));
-    TRACED(dp, "slice_reduce_fat", st,
-           hipLaunchKernelGGL((slice_reduce<1, TG>), g2, dim3(256), 0, st, part, nslices, ldxi, hp.PN,
-                              static_cast<int>(Lc), xiT, dp.d_task0, dp.d_ntiles, dp.ntasks, hp.R, dp.d_gscale,
-                              hp.P, static_cast<TG*>(g), dp.Kc));
+  const int64_t n = static_cast<int64_t>(hp.PN) * Lc;
+  TRACED(dp, "slice_reduce", st,
+         hipLaunchKernelGGL(slice_reduce, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, part,
+                            nslices, ldxi, hp.PN, static_cast<int>(Lc), xiT));
+  if constexpr (MODE == 1) {
+    const int vrows = 2 * hp.max_np + 1;
+    dim3 g2(static_cast<unsigned>((Lc + 255) / 256), static_cast<unsigned>(hp.P + 1));
+#define SRP_FAT(RM)                                                                                       \
+  TRACED(dp, "slri_fat", st,                                                                              \
+         hipLaunchKernelGGL((slri_fat<TG, RM>), g2, dim3(256), 0, st, xiT, ldxi, static_cast<int>(Lc),      \
+                            dp.d_np, dp.d_off, dp.d_V, vrows, hp.R, dp.d_gscale, hp.P, static_cast<TG*>(g), \
+                            dp.Kc))
+    if (hp.R <= 8)
+      SRP_FAT(8);
+    else if (hp.R <= 16)
+      SRP_FAT(16);
+    else
+      SRP_FAT(32);
+#undef SRP_FAT
   }
 }
 

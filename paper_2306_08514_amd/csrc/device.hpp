@@ -35,8 +35,6 @@ struct DevicePlan {
   float* d_S = nullptr;      // [2 max_np + 1 + 32][Kp] rows 2cos / -2sin
   int samp_rows = 0;         // 2 max_np + 1
   int32_t* d_tasks = nullptr;  // sampling tasks (pair, 32-lag tile)
-  int32_t* d_task0 = nullptr;  // [P] first task of the pair
-  int32_t* d_ntiles = nullptr; // [P] lag tiles of the pair
   int ntasks = 0;
   // SLRI
   int Kc = 0;                // columns of the tall GEMM (P*R padded)
