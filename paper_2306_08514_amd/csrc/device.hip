@@ -160,7 +160,7 @@ __global__ __launch_bounds__(64) void phat_kernel(const float2* __restrict__ Y, 
       if (s > 0) {
         a /= s;
         b /= s;
-        const TC r = TC(1) / std::sqrt(a * a + b * b);
+        const TC r = TC(1) / std::sqrt(std::fma(a, a, b * b));
         a *= r;
         b *= r;
       } else {
@@ -180,8 +180,8 @@ __global__ __launch_bounds__(64) void phat_kernel(const float2* __restrict__ Y, 
       const int m = pm[p], mq = pmp[p];
       const TC ar = ur[m * 64 + tid], ai = ui[m * 64 + tid];
       const TC br = ur[mq * 64 + tid], bi = ui[mq * 64 + tid];
-      re = ar * br + ai * bi;  // u_m conj(u_m')
-      im = ai * br - ar * bi;
+      re = std::fma(ar, br, ai * bi);  // u_m conj(u_m')
+      im = std::fma(ai, br, -(ar * bi));
     }
     o[p * ld_p] = cvt64<TO>(re);
     o[p * ld_p + 1] = cvt64<TO>(im);
@@ -453,15 +453,18 @@ __global__ __launch_bounds__(256) void gemm_nt_f64(const double* __restrict__ X,
 // y / |y| (0 for y = 0) with the hardware reciprocal square root; squared
 // magnitudes outside [2^-100, 2^100] are rescaled first so that neither
 // underflow nor overflow can occur.
+// Every contraction is spelled out with fmaf: left to the compiler, a * a +
+// b * b is contracted one way in some unrolled copies and the other way in
+// others, and a frame's result would then depend on its slot in the tile.
 __device__ inline float2 unit_phase(float2 y) {
   float a = y.x, b = y.y;
-  float n2 = a * a + b * b;
+  float n2 = __builtin_fmaf(a, a, b * b);
   if (!(n2 >= 0x1p-100f && n2 <= 0x1p100f)) {
     const float s = std::max(std::fabs(a), std::fabs(b));
     if (!(s > 0.0f)) return make_float2(0.0f, 0.0f);
     a /= s;
     b /= s;
-    n2 = a * a + b * b;
+    n2 = __builtin_fmaf(a, a, b * b);
   }
   const float r = __builtin_amdgcn_rsqf(n2);
   return make_float2(a * r, b * r);
@@ -576,8 +579,8 @@ __global__ __launch_bounds__(256) void spectral_slices(
           const f32x4 x = *reinterpret_cast<const f32x4*>(um + 32 * st);  // u_m bins 2gq, 2gq+1
           const f32x4 y = *reinterpret_cast<const f32x4*>(uq + 32 * st);  // u_m'
           // psi = u_m conj(u_m')
-          const float b0 = x.x * y.x + x.y * y.y, b1 = x.y * y.x - x.x * y.y;
-          const float b2 = x.z * y.z + x.w * y.w, b3 = x.w * y.z - x.z * y.w;
+          const float b0 = __builtin_fmaf(x.x, y.x, x.y * y.y), b1 = __builtin_fmaf(x.y, y.x, -(x.x * y.y));
+          const float b2 = __builtin_fmaf(x.z, y.z, x.w * y.w), b3 = __builtin_fmaf(x.w, y.z, -(x.z * y.w));
           acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b0, acc[i], 0, 0, 0);
           acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b1, acc[i], 0, 0, 0);
           acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b2, acc[i], 0, 0, 0);
@@ -648,7 +651,7 @@ __global__ __launch_bounds__(256) void slri_fat(const float* __restrict__ xiT, i
     const float x = xs[static_cast<int64_t>(n) * ldxi];
 #pragma unroll
     for (int r = 0; r < RMAX; ++r)
-      if (r < R) acc[r] += Vp[n * R + r] * x;
+      if (r < R) acc[r] = __builtin_fmaf(Vp[n * R + r], x, acc[r]);
   }
   const float sc = gscale[p];
 #pragma unroll
@@ -926,10 +929,10 @@ __global__ __launch_bounds__(256) void sspi_gather(const float* __restrict__ xiT
 #pragma unroll
           for (int f4 = 0; f4 < FT / 4; ++f4) {
             const f32x4 e4 = *reinterpret_cast<const f32x4*>(r + 4 * f4);
-            acc[4 * f4 + 0] += wq * e4.x;
-            acc[4 * f4 + 1] += wq * e4.y;
-            acc[4 * f4 + 2] += wq * e4.z;
-            acc[4 * f4 + 3] += wq * e4.w;
+            acc[4 * f4 + 0] = __builtin_fmaf(wq, e4.x, acc[4 * f4 + 0]);
+            acc[4 * f4 + 1] = __builtin_fmaf(wq, e4.y, acc[4 * f4 + 1]);
+            acc[4 * f4 + 2] = __builtin_fmaf(wq, e4.z, acc[4 * f4 + 2]);
+            acc[4 * f4 + 3] = __builtin_fmaf(wq, e4.w, acc[4 * f4 + 3]);
           }
         }
       }

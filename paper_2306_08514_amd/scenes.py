@@ -252,3 +252,58 @@ def random_frames(seed, L, M, N, zero_fraction=0.0):
     if zero_fraction > 0:
         Y[rng.uniform(size=Y.shape) < zero_fraction] = 0.0
     return Y.astype(np.complex64)
+
+
+# ------------------------------------------------------------ serving mix --
+
+SERVING_M = (4, 8, 16, 32)
+SERVING_J = (1024, 16384, 125000, 200000)
+
+
+def serving_array(M):
+    """Array and sampling of the serving mix for M microphones: M = 4 is the
+    0.2 m square (16 kHz, N = 512), M = 8 the 0.3 m UCA (16 kHz, N = 1024),
+    M = 16 a 0.5 m UCA (16 kHz, N = 1024), M = 32 the 2 m-aperture random
+    disc array (48 kHz, N = 2048).  Arrays are centred at the origin in the
+    plane z = 0."""
+    if M == 4:
+        return square_array(0.1), 16000.0, 512
+    if M == 8:
+        return uca(8, 0.3), 16000.0, 1024
+    if M == 16:
+        return uca(16, 0.5), 16000.0, 1024
+    if M == 32:
+        rng = np.random.default_rng(SEED_BASE + 3)
+        return random_disc_array(rng, 32, 1.0, 0.0, 0.05), 48000.0, 2048
+    raise ValueError(M)
+
+
+def serving_grid(J):
+    """Candidate grids of the serving mix, relative to an array at the origin
+    in the plane z = 0: 1k = 32 x 32 and 16k = 128 x 128 points in the array
+    plane (over 4 x 4 m and 8 x 8 m); 125k = 50^3 over 5 x 5 x 2.5 m and
+    200k = 100 x 100 x 20 over 10 x 10 x 2 m, both entirely below the array
+    (z in [-3, -0.5] and [-2.5, -0.5]) so that no point has a mirror twin."""
+    if J == 1024:
+        g = np.linspace(-2.0, 2.0, 32)
+        return box_grid(g, g, np.array([0.0]))
+    if J == 16384:
+        g = np.linspace(-4.0, 4.0, 128)
+        return box_grid(g, g, np.array([0.0]))
+    if J == 125000:
+        return box_grid(np.linspace(-2.5, 2.5, 50), np.linspace(-2.5, 2.5, 50), np.linspace(-3.0, -0.5, 50))
+    if J == 200000:
+        return box_grid(np.linspace(-5.0, 5.0, 100), np.linspace(-5.0, 5.0, 100), np.linspace(-2.5, -0.5, 20))
+    raise ValueError(J)
+
+
+def serving_frames(M, L=256):
+    """A pool of L seeded STFT frames for the M-microphone serving array: one
+    free-field 1/f source 2 m below the array plane plus white sensor noise at
+    10 dB."""
+    mics, fs, N = serving_array(M)
+    rng = np.random.default_rng(SEED_BASE + 100 + M)
+    src = np.array([rng.uniform(-1.5, 1.5), rng.uniform(-1.5, 1.5), -2.0])
+    T = _n_samples(L, N, N // 2)
+    x = render(rng, mics, [src], fs, T, 10.0, noise="white")
+    return stft_frames(x, N, N // 2, L).astype(np.complex64)
