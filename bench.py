@@ -150,7 +150,7 @@ def main():
 
     forms = [f for f in FORMS if f[0] in args.forms.split(",")]
     t0 = time.time()
-    cfg = scenes.config(1, L=args.frames)
+    cfg = scenes.workload("uca8_room125k", L=args.frames)
     Y = scenes.make_frames(cfg)
     log(f"scene generated in {time.time() - t0:.1f} s: frames {Y.shape}")
     L, M, _ = Y.shape
@@ -264,7 +264,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "maps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"config 2: M=8 UCA 0.3 m, J={J} (50x50x50 over 5x5x2.5 m), "
+        "config": {"workload": f"uca8_room125k: M=8 UCA 0.3 m, J={J} (50x50x50 over 5x5x2.5 m), "
                                f"fs=16 kHz, N=1024, L={L} frames per step; forms "
                                + ", ".join(f"{f}({dt}{'' if not rq else ', ' + ('R' if f == 'slri' else 'Q') + '=' + str(rq)})"
                                            for f, rq, dt in forms),

@@ -166,35 +166,40 @@ def render(rng, mics, sources, fs, T, snr_db, noise="white", room=None,
     return sig + _scale_to_snr(sig, nz, snr_db)
 
 
-# --------------------------------------------------------------- configs --
+# -------------------------------------------------------------- workloads --
 
 def _n_samples(L, N, hop):
     return (L - 1) * hop + N
 
 
-def config(index, L=None, grid_stride=1):
-    """Geometry and sizes of the benchmark configurations (0-based index):
+WORKLOADS = ("square4_plane1k", "uca8_room125k", "disc32_box200k")
+_SEED_OFFSET = {"square4_plane1k": 0, "uca8_room125k": 1, "disc32_box200k": 3}
 
-    0: M = 4 square (0.2 m) in z = 0; planar 32 x 32 grid over [-2, 2]^2;
-       fs 16 kHz, N = 512, L = 100; one free-field source in the plane at
-       >= 0.5 m from the centre; white sensor noise at 10 dB.
-    1: M = 8 UCA, diameter 0.3 m, ceiling-mounted at (2.5, 2.5, 2.4) in a
-       5 x 5 x 2.5 m room; 50 x 50 x 50 grid over the room (J = 125,000);
-       fs 16 kHz, N = 1024, L = 1000; one source >= 0.5 m from walls and
-       array, z <= 2.0; image sources of order <= 2 with wall reflection
-       0.7; diffuse 1/f noise at 5 dB.
-    2: the frames and geometry of 0 (precision sweep).
-    3: M = 32 uniform in a disc of radius 1 m at z = 3.0 (>= 5 cm spacing);
-       100 x 100 x 20 grid over [-5, 5]^2 x [0.5, 2.5] (J = 200,000);
-       fs 48 kHz, N = 2048, L = 256; two free-field sources in the grid box;
-       white sensor noise at 10 dB.
+
+def workload(name, L=None, grid_stride=1):
+    """Geometry and sizes of the named workloads:
+
+    square4_plane1k: M = 4 square (0.2 m) in z = 0; planar 32 x 32 grid over
+       [-2, 2]^2 (J = 1024); fs 16 kHz, N = 512, L = 100; one free-field
+       source in the plane at >= 0.5 m from the centre; white sensor noise
+       at 10 dB.  (Also the inputs of the precision sweep.)
+    uca8_room125k: M = 8 UCA, diameter 0.3 m, ceiling-mounted at
+       (2.5, 2.5, 2.4) in a 5 x 5 x 2.5 m room; 50 x 50 x 50 grid over the
+       room (J = 125,000); fs 16 kHz, N = 1024, L = 1000; one source >= 0.5 m
+       from walls and array, z <= 2.0; image sources of order <= 2 with wall
+       reflection 0.7; diffuse 1/f noise at 5 dB.
+    disc32_box200k: M = 32 uniform in a disc of radius 1 m at z = 3.0
+       (>= 5 cm spacing); 100 x 100 x 20 grid over [-5, 5]^2 x [0.5, 2.5]
+       (J = 200,000); fs 48 kHz, N = 2048, L = 256; two free-field sources
+       in the grid box; white sensor noise at 10 dB.
 
     Returns a dict with mics, grid, fs, N, hop, L, c and the drawing recipe;
     frames are produced by make_frames().  grid_stride subsamples every grid
     axis (for small test cases)."""
-    rng = np.random.default_rng(SEED_BASE + index)
-    if index in (0, 2):
-        rng = np.random.default_rng(SEED_BASE + 0)
+    if name not in _SEED_OFFSET:
+        raise ValueError(f"no workload {name!r}; known: {WORKLOADS}")
+    rng = np.random.default_rng(SEED_BASE + _SEED_OFFSET[name])
+    if name == "square4_plane1k":
         mics = square_array(0.1)
         g = np.linspace(-2.0, 2.0, 32)[::grid_stride]
         grid = box_grid(g, g, np.array([0.0]))
@@ -204,7 +209,7 @@ def config(index, L=None, grid_stride=1):
                 break
         cfg = dict(mics=mics, grid=grid, fs=16000.0, N=512, hop=256, L=L or 100,
                    sources=[s], snr_db=10.0, noise="white", room=None, max_order=0)
-    elif index == 1:
+    elif name == "uca8_room125k":
         mics = uca(8, 0.3, (2.5, 2.5, 2.4))
         gx = np.linspace(0.0, 5.0, 50)[::grid_stride]
         gz = np.linspace(0.0, 2.5, 50)[::grid_stride]
@@ -216,7 +221,7 @@ def config(index, L=None, grid_stride=1):
                 break
         cfg = dict(mics=mics, grid=grid, fs=16000.0, N=1024, hop=512, L=L or 1000,
                    sources=[s], snr_db=5.0, noise="diffuse", room=room, max_order=2)
-    elif index == 3:
+    else:
         mics = random_disc_array(rng, 32, 1.0, 3.0, 0.05)
         gx = np.linspace(-5.0, 5.0, 100)[::grid_stride]
         gz = np.linspace(0.5, 2.5, 20)[::grid_stride]
@@ -224,16 +229,14 @@ def config(index, L=None, grid_stride=1):
         srcs = [rng.uniform([-5, -5, 0.5], [5, 5, 2.5]) for _ in range(2)]
         cfg = dict(mics=mics, grid=grid, fs=48000.0, N=2048, hop=1024, L=L or 256,
                    sources=srcs, snr_db=10.0, noise="white", room=None, max_order=0)
-    else:
-        raise ValueError(f"no configuration {index}")
     cfg["c"] = C_SOUND
-    cfg["index"] = index
+    cfg["name"] = name
     cfg["_rng"] = rng
     return cfg
 
 
 def make_frames(cfg):
-    """Render the configuration's signals and return complex64 STFT frames
+    """Render the workload's signals and return complex64 STFT frames
     [L, M, N/2 + 1] (computed in FP64, then rounded once)."""
     rng = cfg["_rng"]
     T = _n_samples(cfg["L"], cfg["N"], cfg["hop"])

@@ -30,15 +30,15 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
-def _host_plan(variant, rq, cfg_index=0, stride=4, **kw):
-    cfg = scenes.config(cfg_index, grid_stride=stride)
+def _host_plan(variant, rq, name="square4_plane1k", stride=4, **kw):
+    cfg = scenes.workload(name, grid_stride=stride)
     p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, rq, device=-1, **kw)
     return p, cfg
 
 
 def test_host_plan_geometry_matches_oracle():
     _lib_or_skip()
-    p, cfg = _host_plan("sspi", 4, cfg_index=1, stride=7)
+    p, cfg = _host_plan("sspi", 4, name="uca8_room125k", stride=7)
     x_ref = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
     x = p.export("tdoa").reshape(x_ref.shape)
     np.testing.assert_allclose(x, x_ref, rtol=0, atol=1e-11)
@@ -55,7 +55,7 @@ def test_host_plan_slri_factors_match_oracle_svd():
     agrees with numpy's SVD; singular values agree."""
     _lib_or_skip()
     R = 5
-    p, cfg = _host_plan("slri", R, cfg_index=1, stride=5)
+    p, cfg = _host_plan("slri", R, name="uca8_room125k", stride=5)
     x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
     Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
     fac = o.slri_factors(x, Np, R)
@@ -76,7 +76,7 @@ def test_host_plan_slri_factors_match_oracle_svd():
 def test_host_plan_sspi_windows_match_oracle_selection():
     _lib_or_skip()
     Q = 4
-    p, cfg = _host_plan("sspi", Q, cfg_index=1, stride=5)
+    p, cfg = _host_plan("sspi", Q, name="uca8_room125k", stride=5)
     x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
     Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
     P, J = x.shape
@@ -90,7 +90,7 @@ def test_host_plan_sspi_windows_match_oracle_selection():
 
 def test_mac_counts_follow_complexity_model():
     _lib_or_skip()
-    cfg = scenes.config(1, grid_stride=5)
+    cfg = scenes.workload("uca8_room125k", grid_stride=5)
     J = cfg["grid"].shape[0]
     fd = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], "fd", device=-1)
     assert fd.info()["macs_per_map"] == 2 * J * 28 * 511
@@ -115,7 +115,7 @@ def test_mac_counts_follow_complexity_model():
 ])
 def test_invalid_arguments_return_error_codes(kw, code):
     _lib_or_skip()
-    cfg = scenes.config(0, grid_stride=8)
+    cfg = scenes.workload("square4_plane1k", grid_stride=8)
     mics = cfg["mics"][: kw.get("M", 4)]
     with pytest.raises(native.SrpError) as ei:
         native.Plan(mics, cfg["grid"], kw.get("fs", cfg["fs"]), kw.get("N", cfg["N"]),
@@ -127,7 +127,7 @@ def test_invalid_arguments_return_error_codes(kw, code):
 
 def test_non_finite_geometry_and_null_out():
     L = _lib_or_skip()
-    cfg = scenes.config(0, grid_stride=8)
+    cfg = scenes.workload("square4_plane1k", grid_stride=8)
     grid = cfg["grid"].copy()
     grid[3, 1] = np.nan
     with pytest.raises(native.SrpError) as ei:

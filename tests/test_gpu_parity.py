@@ -75,26 +75,26 @@ def _plan(native, cfg, variant, rq=0, dtype="f32", **kw):
 
 
 @pytest.fixture(scope="module")
-def cfg0():
-    cfg = scenes.config(0)
+def sq4():
+    cfg = scenes.workload("square4_plane1k")
     Y = scenes.make_frames(cfg)
     return cfg, Y
 
 
 @pytest.fixture(scope="module")
-def cfg1_small():
-    # config-2 geometry on a 17 x 17 x 17 subgrid (J = 4913, not a tile
+def room_small():
+    # room-125k geometry on a 17 x 17 x 17 subgrid (J = 4913, not a tile
     # multiple), 37 frames (ragged)
-    cfg = scenes.config(1, L=37, grid_stride=3)
+    cfg = scenes.workload("uca8_room125k", L=37, grid_stride=3)
     Y = scenes.make_frames(cfg)
     return cfg, Y
 
 
 # ----------------------------------------------------------- stages -------
 
-def test_crossspec_matches_phat(native, cfg0):
-    cfg, Y = cfg0
-    _announce("crossspec config0")
+def test_crossspec_matches_phat(native, sq4):
+    cfg, Y = sq4
+    _announce("crossspec square4")
     p = _plan(native, cfg, "fd")
     psi = p.crossspec(torch.from_numpy(Y).cuda()).cpu().numpy()
     torch.cuda.synchronize()
@@ -108,9 +108,9 @@ def test_crossspec_matches_phat(native, cfg0):
     assert np.all(psi[ref == 0] == 0)
 
 
-def test_gcc_samples_match_ifft(native, cfg0, cfg1_small):
-    for cfg, Y in (cfg0, cfg1_small):
-        _announce(f"gcc_samples config{cfg['index']}")
+def test_gcc_samples_match_ifft(native, sq4, room_small):
+    for cfg, Y in (sq4, room_small):
+        _announce(f"gcc_samples {cfg['name']}")
         p = _plan(native, cfg, "sspi", 4)
         xi = p.gcc_samples(torch.from_numpy(Y).cuda()).cpu().numpy()
         Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
@@ -123,38 +123,38 @@ def test_gcc_samples_match_ifft(native, cfg0, cfg1_small):
 
 @pytest.mark.parametrize("variant,rq", [("fd", 0), ("slri", 8), ("sspi", 4)])
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f16", "fp8"])
-def test_maps_config0(native, cfg0, variant, rq, dtype):
-    cfg, Y = cfg0
-    _announce(f"maps config0 {variant} {dtype}")
+def test_maps_square4(native, sq4, variant, rq, dtype):
+    cfg, Y = sq4
+    _announce(f"maps square4 {variant} {dtype}")
     p = _plan(native, cfg, variant, rq, dtype)
     z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
     ref = _oracle_maps(variant, Y, cfg, rq)
-    worst = _check_maps(z, ref, TOL[dtype], f"config0 {variant} {dtype}")
-    print(f"config0 {variant} {dtype}: max rel {worst:.2e}")
+    worst = _check_maps(z, ref, TOL[dtype], f"square4 {variant} {dtype}")
+    print(f"square4 {variant} {dtype}: max rel {worst:.2e}")
 
 
-def test_fd_f64_config0(native, cfg0):
-    cfg, Y = cfg0
-    _announce("maps config0 fd f64")
+def test_fd_f64_square4(native, sq4):
+    cfg, Y = sq4
+    _announce("maps square4 fd f64")
     p = _plan(native, cfg, "fd", 0, "f64")
     z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
     assert z.dtype == np.float64
-    _check_maps(z, _oracle_maps("fd", Y, cfg, 0), TOL["f64"], "config0 fd f64")
+    _check_maps(z, _oracle_maps("fd", Y, cfg, 0), TOL["f64"], "square4 fd f64")
 
 
 @pytest.mark.parametrize("variant,rq", [("fd", 0), ("slri", 8), ("slri", 31), ("sspi", 4),
                                         ("sspi", 1), ("sspi", 8)])
-def test_maps_ragged_config1_geometry(native, cfg1_small, variant, rq):
-    cfg, Y = cfg1_small
-    _announce(f"maps config1-small {variant} {rq}")
+def test_maps_ragged_room125k_geometry(native, room_small, variant, rq):
+    cfg, Y = room_small
+    _announce(f"maps room125k-small {variant} {rq}")
     p = _plan(native, cfg, variant, rq)
     z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
     _check_maps(z, _oracle_maps(variant, Y, cfg, rq), TOL["f32"], f"ragged {variant} {rq}")
 
 
-def test_full_rank_slri_and_dense_sspi_agree_on_gpu(native, cfg1_small):
+def test_full_rank_slri_and_dense_sspi_agree_on_gpu(native, room_small):
     """R_p = Q_p = 2 N_p + 1 for every pair (max lag count 31) reproduce SI."""
-    cfg, Y = cfg1_small
+    cfg, Y = room_small
     _announce("full-rank slri / dense sspi")
     Yt = torch.from_numpy(Y).cuda()
     zs = _plan(native, cfg, "slri", 31).compute(Yt).cpu().numpy()
@@ -166,8 +166,8 @@ def test_full_rank_slri_and_dense_sspi_agree_on_gpu(native, cfg1_small):
 
 # ---------------------------------------------------------- edge cases ----
 
-def test_edge_cases(native, cfg0):
-    cfg, Y = cfg0
+def test_edge_cases(native, sq4):
+    cfg, Y = sq4
     _announce("edge cases")
     p = _plan(native, cfg, "sspi", 3)
     empty = torch.empty((0, 4, cfg["N"] // 2 + 1), dtype=torch.complex64, device="cuda")
@@ -190,11 +190,11 @@ def test_edge_cases(native, cfg0):
     _check_maps(z, _oracle_maps("sspi", Z, cfg, 3), 1e-5, "zeros")
 
 
-def test_batch_invariance_and_workspace(native, cfg1_small):
+def test_batch_invariance_and_workspace(native, room_small):
     """A frame's map does not depend on the other frames of the batch
     (bitwise), nor on whether the caller passes a workspace or which
     stream runs it."""
-    cfg, Y = cfg1_small
+    cfg, Y = room_small
     _announce("batch invariance")
     Yt = torch.from_numpy(Y).cuda()
     for variant, rq in (("fd", 0), ("slri", 8), ("sspi", 4)):
@@ -211,11 +211,11 @@ def test_batch_invariance_and_workspace(native, cfg1_small):
         assert torch.equal(full, again), variant
 
 
-# ------------------------------------------------- full-size config 2 -----
+# ------------------------------------- full-size M=8, J=125k room workload --
 
 @pytest.fixture(scope="module")
-def cfg1_full():
-    cfg = scenes.config(1)
+def room_full():
+    cfg = scenes.workload("uca8_room125k")
     Y = scenes.make_frames(cfg)
     return cfg, Y
 
@@ -223,11 +223,11 @@ def cfg1_full():
 @pytest.mark.parametrize("variant,rq,dtype", [("fd", 0, "f32"), ("slri", 8, "f32"), ("sspi", 4, "f32"),
                                               ("slri", 8, "bf16"), ("sspi", 4, "bf16"),
                                               ("fd", 0, "bf16")])
-def test_full_size_config1_sampled(native, cfg1_full, variant, rq, dtype):
+def test_full_size_room125k_sampled(native, room_full, variant, rq, dtype):
     """J = 125,000 and L = 1000 in the benchmark's launch configuration;
     the oracle evaluates 12 frames at 3000 sampled candidates."""
-    cfg, Y = cfg1_full
-    _announce(f"full config1 {variant} {dtype}")
+    cfg, Y = room_full
+    _announce(f"full room125k {variant} {dtype}")
     p = _plan(native, cfg, variant, rq, dtype)
     z = p.compute(torch.from_numpy(Y).cuda())
     torch.cuda.synchronize()

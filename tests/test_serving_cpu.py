@@ -80,7 +80,7 @@ class FakeExecutor:
 
 
 def _cfg(stride=8):
-    return scenes.config(0, L=40, grid_stride=stride)
+    return scenes.workload("square4_plane1k", L=40, grid_stride=stride)
 
 
 @pytest.fixture(scope="module")
