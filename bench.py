@@ -164,7 +164,9 @@ def main():
         plans[form] = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], form, rq, dtype=dt,
                                   c=cfg["c"], device=0)
         plan_s[form] = time.time() - t1
-        outs[form] = torch.empty((L, J), dtype=torch.float32, device=dev)
+        # maps at the plan's row pitch (J rounded up to 128: rows on 512-byte
+        # boundaries); the dense pitch J is timed separately below
+        outs[form] = plans[form].empty_maps(L, dev)
         wss[form] = torch.empty(plans[form].workspace_size(L), dtype=torch.uint8, device=dev)
         log(f"plan {form}/{dt} built in {plan_s[form]:.2f} s, resident "
             f"{plans[form].info()['device_bytes'] / 2**30:.2f} GiB")
@@ -202,6 +204,24 @@ def main():
         prof[form] = plans[form].profile_collect()
         plans[form].profile(False)
 
+    # the same calls writing dense [L][J] maps (row pitch J), timed the same
+    # way (events around each call)
+    dense_ms = {}
+    for form in plans:
+        zd = torch.empty((L, J), dtype=torch.float32, device=dev)
+        n = 2 if form == "fd" else 10
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        plans[form].compute(Yt, maps=zd, workspace=wss[form])
+        for e0, e1 in evs:
+            e0.record()
+            plans[form].compute(Yt, maps=zd, workspace=wss[form])
+            e1.record()
+        torch.cuda.synchronize()
+        dense_ms[form] = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+        if not torch.equal(zd, outs[form]):
+            raise RuntimeError(f"{form}: maps at pitch J differ from maps at the padded pitch")
+        del zd
+
     lat = {f: np.array([events[k][f][0].elapsed_time(events[k][f][1]) for k in range(args.steps)]) for f in plans}
     ms_per_step = wall / args.steps * 1e3
     maps_per_step = L * len(plans)
@@ -212,6 +232,8 @@ def main():
         per_form[form] = {"operands": dt, "rank_or_q": rq, "maps_per_s": L / (ms / 1e3),
                           "ms_per_call": ms, "p50_ms": float(np.percentile(lat[form], 50)),
                           "p99_ms": float(np.percentile(lat[form], 99)),
+                          "ms_per_call_dense_pitch": dense_ms[form],
+                          "maps_per_s_dense_pitch": L / (dense_ms[form] / 1e3),
                           "plan_seconds": plan_s[form],
                           "resident_gib": plans[form].info()["device_bytes"] / 2 ** 30,
                           "kernels_ms_per_call": {k: v[0] / v[1] for k, v in prof[form].items()}}
@@ -240,12 +262,21 @@ def main():
                               "argmax_agreement_with_fd_f32": agree}
 
     rl = kernel_rooflines(cfg, prof, L, P, K, PN)
-    dom = rl.get("gemm_fd") or next(iter(rl.values()), None)
+    # measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-
+    # calibrated), valid only while the kernel source is the one profiled
+    from paper_2306_08514_amd import rocprof_summary as rs
+    rec = rs.read_traffic_record(os.path.join(ROOT, "profiles", "hbm_traffic_uca8_room125k.md"))
+    traffic_ok = rec is not None and rec.get("source_sha256") == rs.source_sha256()
+    for kname, k in rl.items():
+        t = rec["kernels"].get(kname, {}).get("bytes_per_launch") if traffic_ok else None
+        k["traffic"] = t
+    dom_name = "gemm_fd" if "gemm_fd" in rl else next(iter(rl), None)
     roofline = None
-    if dom:
+    if dom_name:
+        dom = rl[dom_name]
         roofline = {"bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
-                    "unit": dom["unit"], "frac": dom["frac"], "traffic": None,
-                    "kernel": [k for k, v in rl.items() if v is dom][0], "avg_ms": dom["avg_ms"]}
+                    "unit": dom["unit"], "frac": dom["frac"], "traffic": dom["traffic"],
+                    "kernel": dom_name, "avg_ms": dom["avg_ms"]}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -268,7 +299,8 @@ def main():
                                f"fs=16 kHz, N=1024, L={L} frames per step; forms "
                                + ", ".join(f"{f}({dt}{'' if not rq else ', ' + ('R' if f == 'slri' else 'Q') + '=' + str(rq)})"
                                            for f, rq, dt in forms),
-                   "maps_per_step": maps_per_step, "accumulate": "f32"},
+                   "maps_per_step": maps_per_step, "accumulate": "f32",
+                   "map_row_pitch": plans[forms[0][0]].map_pitch},
         "forms": per_form,
         "kernels": rl,
         "accuracy": accuracy,

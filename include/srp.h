@@ -100,6 +100,10 @@ typedef struct {
                             C_sspi (62), sampling counted as 2PN(K-1) */
   size_t device_bytes;   /* resident device memory owned by the plan */
   double plan_seconds;   /* wall time of plan construction */
+  int64_t map_pitch;     /* recommended row pitch of the maps in elements:
+                            J rounded up to 128, so that every row starts on
+                            a 512-byte boundary and the map stores write
+                            whole cache lines */
 } srp_plan_info;
 
 /* Fills *opts with the defaults listed above. */
@@ -131,15 +135,21 @@ srp_status srp_workspace_size(srp_plan_t plan, int64_t L, size_t* bytes);
 /* Computes one SRP map per frame.
  *   frames    device, complex64 [L][M][N/2 + 1] (interleaved re, im float32)
  *   L         number of frames (>= 0; 0 is a no-op)
- *   maps      device, float32 [L][J] (float64 [L][J] for SRP_F64 plans)
+ *   maps      device, float32 (float64 for SRP_F64 plans): map l occupies
+ *             elements [l * ld_maps, l * ld_maps + J); the elements past J
+ *             in each row are not written
+ *   ld_maps   row pitch of maps in elements, >= J; 0 means J (dense
+ *             [L][J]).  srp_plan_info.map_pitch gives the pitch at which
+ *             the map stores run fastest (rows on 512-byte boundaries)
  *   workspace device, >= srp_workspace_size(L) bytes, 256-byte aligned; NULL
  *             uses a plan-owned buffer (then at most one call per plan may be
  *             in flight at a time)
  *   stream    hipStream_t to enqueue on (NULL = the null stream)
- * Asynchronous: returns after enqueueing. */
+ * Returns SRP_E_INVALID for ld_maps in (0, J).  Asynchronous: returns after
+ * enqueueing. */
 srp_status srp_compute(srp_plan_t plan, const void* frames, int64_t L,
-                       void* maps, void* workspace, size_t ws_bytes,
-                       void* stream);
+                       void* maps, int64_t ld_maps, void* workspace,
+                       size_t ws_bytes, void* stream);
 
 /* Stage entry point: PHAT-weighted cross-spectra (eq. (2)) of L frames.
  *   psi  device, complex64 [L][P][K-1] */

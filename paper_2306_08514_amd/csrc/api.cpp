@@ -148,17 +148,19 @@ srp_status srp_workspace_size(srp_plan_t plan, int64_t L, size_t* bytes) {
   })
 }
 
-srp_status srp_compute(srp_plan_t plan, const void* frames, int64_t L, void* maps, void* workspace,
-                       size_t ws_bytes, void* stream) {
+srp_status srp_compute(srp_plan_t plan, const void* frames, int64_t L, void* maps, int64_t ld_maps,
+                       void* workspace, size_t ws_bytes, void* stream) {
   if (!plan) return fail(SRP_E_INVALID, "NULL plan");
   if (L < 0) return fail(SRP_E_INVALID, "L must be >= 0");
+  if (ld_maps == 0) ld_maps = plan->hp.J;
+  if (ld_maps < plan->hp.J) return fail(SRP_E_INVALID, "ld_maps must be 0 or >= J");
   if (L == 0) return SRP_OK;
   if (!frames || !maps) return fail(SRP_E_INVALID, "frames and maps must be device pointers");
   if (!plan->has_device) return fail(SRP_E_INVALID, "host-only plan cannot compute");
   SRP_GUARD({
     DeviceGuard g(plan->dp.device);
-    srp::device_compute(plan->hp, plan->dp, frames, L, maps, workspace, ws_bytes, plan->opts.frame_tile,
-                        static_cast<hipStream_t>(stream));
+    srp::device_compute(plan->hp, plan->dp, frames, L, maps, ld_maps, workspace, ws_bytes,
+                        plan->opts.frame_tile, static_cast<hipStream_t>(stream));
     return SRP_OK;
   })
 }
@@ -208,6 +210,7 @@ srp_status srp_plan_info_get(srp_plan_t plan, srp_plan_info* info) {
   info->macs_per_map = hp.macs_per_map;
   info->device_bytes = plan->dp.resident_bytes;
   info->plan_seconds = plan->plan_seconds;
+  info->map_pitch = (hp.J + 127) / 128 * 128;
   return SRP_OK;
 }
 

@@ -6,7 +6,7 @@
 //   spectral_slices  PHAT + xi_p = 2 Re[S_p psi_p] per spectral slice    eqs. (2), (40)
 //   slice_reduce     sum of the slices' partial GCC samples
 //   slri_fat         g_p = V_p^T xi_p                                   eq. (57)
-//   gemm_nt (tall)   z = sum_p U_p g_p                                  eq. (57)
+//   tall_ws          z = sum_p U_p g_p                                  eq. (57)
 //   sspi_gather      z = sum_p sum_q w[j,p,q] xi_p[s(j,p) + q]          eq. (58)
 #include <hip/hip_runtime.h>
 
@@ -661,115 +661,116 @@ __global__ __launch_bounds__(256) void slri_fat(const float* __restrict__ xiT, i
 
 // ====================================================== SLRI tall stream ===
 //
-// z[l][j] = alpha * sum_c g[l][c] U[j][c] for the 16-bit and FP8 operands
-// with a short contraction (P R padded, at most 1 KB per row).  A block owns
-// 128 candidates: each wave keeps its 32 rows of U in registers for the whole
-// kernel (U is read from HBM exactly once), and all frames stream past in
-// groups of 32 whose g rows are staged in LDS (double-buffered, prefetched
-// one group ahead).  The kernel is bound by the map stores.
-
-template <typename T, int MAXS, bool WIDE>
-__global__ __launch_bounds__(256) void tall_stream(const T* __restrict__ g, int64_t ldg,
-                                                   const T* __restrict__ U, int64_t ldu, int nsteps,
-                                                   float* __restrict__ z, int64_t ldz, int L, int64_t J,
-                                                   float alpha) {
-  constexpr int STEP = Mfma<T>::STEP;  // bytes of a row per MFMA step
-  constexpr int LB = STEP / 2;         // bytes per lane per step
+// z[l][j] = alpha * sum_c g[l][c] U[j][c] (the tall stage of eq. (57)) for the
+// 16-bit and FP8 operands with rows of at most 1 KB.  Warp-specialised
+// streaming: one loader wave stages the g rows of the
+// next groups of 32 frames into LDS (three buffers, two groups ahead) while
+// CW compute waves (32 candidates each) multiply the current group and store
+// it.  vmcnt is
+// per wave and counts stores as well as loads, so keeping every global load
+// out of the compute waves means they never wait for their own map stores,
+// and the loader only ever waits for its loads.  The loads still queue
+// behind the CU's map stores, so a block covers 32 CW candidates to read
+// each g row as few times as possible.  Block b owns 32 CW candidates and
+// one of nsplit contiguous ranges of frame groups; the splits of a
+// candidate tile run back to back on one XCD (xcd_tile), so the U rows they
+// share are fetched from HBM once.
+template <typename T, int NS, int CW>
+__global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g, int64_t ldg, int grows,
+                                               const T* __restrict__ U, int64_t ldu,
+                                               float* __restrict__ z, int64_t ldz, int L, int64_t J,
+                                               float alpha, int njt, int nsplit, int gps) {
+  constexpr int STEP = Mfma<T>::STEP;
+  constexpr int LB = STEP / 2;
   constexpr int NV = LB / 16;
-  constexpr int ROWMAX = MAXS * STEP + 16;  // padded LDS row (bytes)
-  __shared__ __attribute__((aligned(16))) unsigned char gs[2][32 * ROWMAX];
+  constexpr int ROWP = NS * STEP + 16;  // padded LDS row (bytes)
+  constexpr int CPR = NS * STEP / 16;   // 16-byte chunks per g row
+  constexpr int PERL = 32 * CPR / 64;   // chunks per loader lane and group
+  constexpr int NBUF = 3;
+  __shared__ __attribute__((aligned(16))) unsigned char gs[NBUF][32 * ROWP];
+  int jt, sp;
+  if (!xcd_tile(njt, nsplit, jt, sp)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r32 = lane & 31, gq = lane >> 5;
-  const int64_t j0 = static_cast<int64_t>(blockIdx.x) * 128 + wave * 32;
-  const int rowb = nsteps * STEP;  // bytes of a g / U row
-  const int rowp = rowb + 16;      // padded LDS row
+  const int g0 = sp * gps;
+  const int ng = std::min((L + 31) / 32, g0 + gps) - g0;  // groups of this block
+  if (ng <= 0) return;  // block-uniform
 
-  // this lane's U fragments: row j0 + r32, K-half gq of every step
-  i32x4 uf[MAXS][NV];
+  if (wave == CW) {
+    // loader: all of a group's loads in flight, then the LDS writes
+    const unsigned char* gb = reinterpret_cast<const unsigned char*>(g);
+    auto stage = [&](int i) {
+      i32x4 v[PERL];
+#pragma unroll
+      for (int k = 0; k < PERL; ++k) {
+        const int c = lane + 64 * k;
+        const int row = (g0 + i) * 32 + c / CPR;
+        v[k] = i32x4{0, 0, 0, 0};
+        if (row < grows)
+          v[k] = *reinterpret_cast<const i32x4*>(gb + static_cast<int64_t>(row) * ldg * sizeof(T) + 16 * (c % CPR));
+      }
+#pragma unroll
+      for (int k = 0; k < PERL; ++k) {
+        const int c = lane + 64 * k;
+        *reinterpret_cast<i32x4*>(&gs[i % NBUF][(c / CPR) * ROWP + 16 * (c % CPR)]) = v[k];
+      }
+    };
+    stage(0);
+    if (ng > 1) stage(1);
+    __syncthreads();
+    for (int i = 0; i < ng; ++i) {
+      if (i + 2 < ng) stage(i + 2);
+      __syncthreads();
+    }
+    return;
+  }
+
+  const int r32 = lane & 31, gq = lane >> 5;
+  const int64_t j0 = static_cast<int64_t>(jt) * (32 * CW) + wave * 32;
+  // U rows of this lane's candidate (zeros past J: the last tile may reach
+  // beyond the padded rows of U)
+  const bool jok = j0 + r32 < J;
+  i32x4 uf[NS][NV];
   {
     const unsigned char* ur =
-        reinterpret_cast<const unsigned char*>(U) + (j0 + r32) * ldu * static_cast<int64_t>(sizeof(T)) + gq * LB;
+        reinterpret_cast<const unsigned char*>(U) + (jok ? j0 + r32 : 0) * ldu * static_cast<int64_t>(sizeof(T)) + gq * LB;
 #pragma unroll
-    for (int s = 0; s < MAXS; ++s)
+    for (int s = 0; s < NS; ++s)
 #pragma unroll
       for (int v = 0; v < NV; ++v)
-        if (s < nsteps) uf[s][v] = *reinterpret_cast<const i32x4*>(ur + s * STEP + 16 * v);
+        uf[s][v] = jok ? *reinterpret_cast<const i32x4*>(ur + s * STEP + 16 * v) : i32x4{0, 0, 0, 0};
   }
-  // g group staging: 32 rows x rowb bytes in 16-byte chunks
-  const int chunks = 32 * (rowb / 16);
-  constexpr int PER = (32 * MAXS * STEP / 16 + 255) / 256;
-  i32x4 pre[PER];
-  const unsigned char* gb = reinterpret_cast<const unsigned char*>(g);
-  auto gload = [&](int grp) {
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int c = tid + 256 * i;
-      if (c < chunks) {
-        const int row = c / (rowb / 16), col = c % (rowb / 16);
-        pre[i] = *reinterpret_cast<const i32x4*>(gb + (static_cast<int64_t>(grp) * 32 + row) * ldg * sizeof(T) + 16 * col);
-      }
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int c = tid + 256 * i;
-      if (c < chunks) {
-        const int row = c / (rowb / 16), col = c % (rowb / 16);
-        *reinterpret_cast<i32x4*>(&gs[buf][row * rowp + 16 * col]) = pre[i];
-      }
-    }
-  };
-  const int ngroups = (L + 31) / 32;
-  const int64_t jcol = j0 + r32;
-  gload(0);
-  lstore(0);
   __syncthreads();
-  for (int grp = 0; grp < ngroups; ++grp) {
-    const int buf = grp & 1;
-    if (grp + 1 < ngroups) gload(grp + 1);
+  // element offset of this lane inside a group's rows: row 4 gq, column r32
+  // (the host keeps 36 ldz below 2^31)
+  const uint32_t loff = static_cast<uint32_t>(4 * gq * ldz + r32);
+  for (int i = 0; i < ng; ++i) {
+    const int grp = g0 + i;
     f32x16 acc;
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-    const unsigned char* ar = &gs[buf][r32 * rowp + gq * LB];
+    const unsigned char* ar = &gs[i % NBUF][r32 * ROWP + gq * LB];
+    i32x4 af[NS][NV];
 #pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-      if (s < nsteps) {
-        i32x4 af[NV];
+    for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int v = 0; v < NV; ++v) af[v] = *reinterpret_cast<const i32x4*>(ar + s * STEP + 16 * v);
-        if (WIDE)
-          Mfma<T>::run(uf[s], af, acc);
-        else
-          Mfma<T>::run(af, uf[s], acc);
+      for (int v = 0; v < NV; ++v) af[s][v] = *reinterpret_cast<const i32x4*>(ar + s * STEP + 16 * v);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Mfma<T>::run(af[s], uf[s], acc);
+    // rows (frames) 8 (v / 4) + 4 gq + v % 4 of the group, column j0 + r32:
+    // a uniform row pointer plus the lane's 32-bit offset
+    float* zg = z + static_cast<int64_t>(grp) * 32 * ldz + j0;
+    if (grp * 32 + 32 <= L) {
+      if (jok) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) zg[(8 * (v / 4) + (v % 4)) * ldz + loff] = alpha * acc[v];
       }
-    }
-    if (WIDE) {
-      // rows are candidates j0 + 8 (v / 4) + 4 gq + v % 4, the column is
-      // frame grp * 32 + r32: four consecutive candidates per 16-byte store
-      const int64_t l = static_cast<int64_t>(grp) * 32 + r32;
-      if (l < L) {
-#pragma unroll
-        for (int v4 = 0; v4 < 4; ++v4) {
-          const int64_t jj = j0 + 8 * v4 + 4 * gq;
-          f32x4 o = {alpha * acc[4 * v4], alpha * acc[4 * v4 + 1], alpha * acc[4 * v4 + 2], alpha * acc[4 * v4 + 3]};
-          if (jj + 3 < J) {
-            *reinterpret_cast<f32x4*>(z + l * ldz + jj) = o;
-          } else {
-            for (int e = 0; e < 4; ++e)
-              if (jj + e < J) z[l * ldz + jj + e] = o[e];
-          }
-        }
-      }
-    } else if (jcol < J) {
-      // rows (frames) 8 (v / 4) + 4 gq + v % 4 of the group, column jcol
+    } else if (jok) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int64_t l = static_cast<int64_t>(grp) * 32 + 8 * (v / 4) + 4 * gq + (v % 4);
-        if (l < L) z[l * ldz + jcol] = alpha * acc[v];
+        const int l = grp * 32 + 8 * (v / 4) + 4 * gq + (v % 4);
+        if (l < L) zg[(8 * (v / 4) + (v % 4)) * ldz + loff] = alpha * acc[v];
       }
     }
-    if (grp + 1 < ngroups) lstore(buf ^ 1);
     __syncthreads();
   }
 }
@@ -1049,7 +1050,8 @@ void upload(void* dst, const std::vector<T>& v) {
 // tile shapes of the launch configurations
 constexpr int BIG_BX = 256, BIG_BW = 128, BIG_WGX = 2, BIG_BKB = 128;   // FD
 constexpr int TALL_BX = 256, TALL_BW = 128, TALL_WGX = 2, TALL_BKB = 128; // SLRI tall (FP32)
-constexpr bool TALL_WIDE = false;  // 16-byte map stores in tall_stream
+constexpr int TALL_STEP_BYTES(int dtype) { return dtype == SRP_FP8_E4M3 ? 64 : 32; }  // Mfma<T>::STEP
+constexpr int TALL_CW = 8;  // compute waves per block of the tall kernel (256 candidates)
 constexpr int SSPI_FT = 32;                       // frames per SSPI block
 constexpr int SSPI_ROWS = 32 * 1024 / ((SSPI_FT + 4) * 4);  // lag rows per LDS chunk (32 KB)
 
@@ -1132,7 +1134,10 @@ void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t
     if (hp.dtype == SRP_F64) throw Error{SRP_E_UNSUPPORTED, "SLRI has no FP64 path"};
     const int R = hp.R;
     const int vrows = 2 * hp.max_np + 1;
-    const int elem_per_slice = BIG_BKB / static_cast<int>(dsize(hp.dtype));
+    // padded to a whole K slice of the FP32 GEMM and, for the 16-bit and
+    // FP8 operands, to a multiple of four MFMA steps of the tall kernel
+    const int es = static_cast<int>(dsize(hp.dtype));
+    const int elem_per_slice = std::max(BIG_BKB / es, hp.dtype == SRP_F32 ? 0 : 4 * TALL_STEP_BYTES(hp.dtype) / es);
     dp.Kc = static_cast<int>(round_up(static_cast<int64_t>(P) * R, elem_per_slice));
     // per-pair weight scale (FP8 only) and a power-of-two activation scale
     // bounding |g| by the format's range: |xi| <= 2 (K - 1) since |psi| <= 1
@@ -1347,29 +1352,65 @@ void launch_big_gemm(DevicePlan& dp, const char* kname, const void* X, int64_t l
   launch_gemm<T, BIG_BX, BIG_BW, BIG_WGX, BIG_BKB>(dp, kname, X, ldx, W, ldw, C, ldc, nx, nw, kdim, alpha, Lpad, st);
 }
 
+// Frame splits of the tall kernel: the number of ranges per candidate tile
+// (1..8, at least four groups each) that minimises rounds x (groups per
+// block + 2), where rounds = blocks / resident block slots rounded up (the
+// last, partial round leaves slots idle) and the 2 stands for a block's
+// fixed cost (its U rows and the first staged groups).
+void tall_split(DevicePlan& dp, const void* kern, int threads, int njt, int ngroups, int& nsplit, int& gps) {
+  if (dp.tall_slots == 0) {
+    int per_cu = 0, cus = 0;
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0));
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dp.device));
+    dp.tall_slots = std::max(1, per_cu) * std::max(1, cus);
+  }
+  const int slots = dp.tall_slots;
+  nsplit = 1;
+  int64_t best = -1;
+  for (int s = 1; s <= 8 && (s == 1 || ngroups / s >= 4); ++s) {
+    const int64_t rounds = (static_cast<int64_t>(njt) * s + slots - 1) / slots;
+    const int64_t cost = rounds * ((ngroups + s - 1) / s + 2);
+    if (best < 0 || cost < best) {
+      best = cost;
+      nsplit = s;
+    }
+  }
+  gps = (ngroups + nsplit - 1) / nsplit;
+  nsplit = (ngroups + gps - 1) / gps;
+}
+
 template <typename T>
 void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W, int64_t ldw, float* C,
                       int64_t ldc, int nx, int nw, int kdim, float alpha, int64_t Lpad, hipStream_t st) {
   const int steps = kdim * static_cast<int>(sizeof(T)) / Mfma<T>::STEP;
-  // 16-byte map stores need 16-byte aligned rows
-  if (!std::is_same<T, float>::value && steps <= 32 && kdim * static_cast<int>(sizeof(T)) <= 1024 &&
-      (!TALL_WIDE || ldc % 4 == 0)) {
-    // U rows of the block stay in registers; frames stream past
-    const unsigned blocks = static_cast<unsigned>(dp.Jpad / 128);
-#define SRP_TALL(MS)                                                                                         \
-  TRACED(dp, "gemm_tall", st,                                                                              \
-         hipLaunchKernelGGL((tall_stream<T, MS, TALL_WIDE>), dim3(blocks), dim3(256), 0, st,                \
-                            static_cast<const T*>(X),                                                        \
-                            ldx, static_cast<const T*>(W), ldw, steps, C, ldc, nx, static_cast<int64_t>(nw),   \
-                            alpha))
-    if (steps <= 8)
-      SRP_TALL(8);
-    else if (steps <= 16)
-      SRP_TALL(16);
-    else
-      SRP_TALL(32);
-#undef SRP_TALL
-    return;
+  // 16-bit and FP8 operands with rows of at most 1 KB: U rows in registers,
+  // g streamed through LDS by the loader wave; anything else takes the
+  // general MFMA GEMM
+  if (!std::is_same<T, float>::value && steps <= 32 && kdim * static_cast<int>(sizeof(T)) <= 1024) {
+    if (steps % 4 == 0 && 36 * ldc < (int64_t(1) << 31)) {
+      constexpr int CW = TALL_CW;
+      const int njt = static_cast<int>((nw + 32 * CW - 1) / (32 * CW));
+      const int ngroups = (nx + 31) / 32;
+#define SRP_WS(NSV)                                                                                           \
+  case NSV:                                                                                                   \
+    if constexpr (NSV * Mfma<T>::STEP <= 1024) {                                                              \
+    auto kern = &tall_ws<T, NSV, CW>;                                                                         \
+    int nsplit, gps;                                                                                          \
+    tall_split(dp, reinterpret_cast<const void*>(kern), 64 * (CW + 1), njt, ngroups, nsplit, gps);            \
+    const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(njt) * nsplit, 8));          \
+    TRACED(dp, "gemm_tall", st,                                                                               \
+           hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * (CW + 1)), 0, st, static_cast<const T*>(X), ldx,  \
+                              static_cast<int>(Lpad), static_cast<const T*>(W), ldw, C, ldc, nx,               \
+                              static_cast<int64_t>(nw), alpha, njt, nsplit, gps));                             \
+    return;                                                                                                   \
+    }                                                                                                         \
+    break;
+      switch (steps) {
+        SRP_WS(4) SRP_WS(8) SRP_WS(12) SRP_WS(16) SRP_WS(20) SRP_WS(24) SRP_WS(28) SRP_WS(32)
+        default: break;
+      }
+#undef SRP_WS
+    }
   }
   launch_gemm<T, TALL_BX, TALL_BW, TALL_WGX, TALL_BKB>(dp, "gemm_tall", X, ldx, W, ldw, C, ldc, nx, nw, kdim, alpha,
                                                       Lpad, st);
@@ -1430,7 +1471,7 @@ void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_
 
 template <typename TW, int Q>
 void launch_sspi_q(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t Lpad,
-                   int64_t Lc, float* z, hipStream_t st) {
+                   int64_t Lc, float* z, int64_t ldz, hipStream_t st) {
   constexpr bool PAIRS = !std::is_same<TW, float>::value;
   const int es = static_cast<int>(sizeof(TW));
   const int Qs = static_cast<int>(round_up(Q * es, 4) / es);
@@ -1452,21 +1493,21 @@ void launch_sspi_q(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t
   TRACED(dp, "sspi_gather", st,
          hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, xiT, Lpad, hp.PN, dp.d_start,
                             static_cast<const TW*>(dp.d_w), Qs, dp.d_chunk_p0, dp.nchunks, dp.d_off, hp.P,
-                            hp.J, static_cast<int>(Lc), nf, z, hp.J));
+                            hp.J, static_cast<int>(Lc), nf, z, ldz));
 }
 
 template <typename TW>
 void launch_sspi(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t Lpad, int64_t Lc,
-                 float* z, hipStream_t st) {
+                 float* z, int64_t ldz, hipStream_t st) {
   switch (hp.Q) {
-    case 1: launch_sspi_q<TW, 1>(hp, dp, xiT, Lpad, Lc, z, st); break;
-    case 2: launch_sspi_q<TW, 2>(hp, dp, xiT, Lpad, Lc, z, st); break;
-    case 3: launch_sspi_q<TW, 3>(hp, dp, xiT, Lpad, Lc, z, st); break;
-    case 4: launch_sspi_q<TW, 4>(hp, dp, xiT, Lpad, Lc, z, st); break;
-    case 5: launch_sspi_q<TW, 5>(hp, dp, xiT, Lpad, Lc, z, st); break;
-    case 6: launch_sspi_q<TW, 6>(hp, dp, xiT, Lpad, Lc, z, st); break;
-    case 7: launch_sspi_q<TW, 7>(hp, dp, xiT, Lpad, Lc, z, st); break;
-    case 8: launch_sspi_q<TW, 8>(hp, dp, xiT, Lpad, Lc, z, st); break;
+    case 1: launch_sspi_q<TW, 1>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
+    case 2: launch_sspi_q<TW, 2>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
+    case 3: launch_sspi_q<TW, 3>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
+    case 4: launch_sspi_q<TW, 4>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
+    case 5: launch_sspi_q<TW, 5>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
+    case 6: launch_sspi_q<TW, 6>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
+    case 7: launch_sspi_q<TW, 7>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
+    case 8: launch_sspi_q<TW, 8>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
     default: throw Error{SRP_E_UNSUPPORTED, "SSPI with Q above 8 is not built"};
   }
 }
@@ -1495,7 +1536,7 @@ static void* ensure_ws(DevicePlan& dp, void* ws, size_t ws_bytes, size_t need) {
 }
 
 void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L, void* maps,
-                    void* ws, size_t ws_bytes, int64_t frame_tile, hipStream_t st) {
+                    int64_t ldm, void* ws, size_t ws_bytes, int64_t frame_tile, hipStream_t st) {
   if (L <= 0) return;
   const WsLayout lay = ws_layout(hp, dp, L, frame_tile);
   unsigned char* base = static_cast<unsigned char*>(ensure_ws(dp, ws, ws_bytes, lay.total));
@@ -1508,55 +1549,55 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
     if (hp.variant == SRP_FD) {
       phat_dispatch(hp, dp, fr, Lc, psi, hp.dtype, st);
       if (hp.dtype == SRP_F64) {
-        double* z = static_cast<double*>(maps) + l0 * hp.J;
+        double* z = static_cast<double*>(maps) + l0 * ldm;
         dim3 grid(static_cast<unsigned>((hp.J + 63) / 64), static_cast<unsigned>((Lc + 63) / 64));
         TRACED(dp, "gemm_fd_f64", st,
                hipLaunchKernelGGL(gemm_nt_f64, grid, dim3(256), 0, st, static_cast<const double*>(psi), ldpsi,
-                                  static_cast<const double*>(dp.d_H), ldpsi, z, hp.J, static_cast<int>(Lc),
+                                  static_cast<const double*>(dp.d_H), ldpsi, z, ldm, static_cast<int>(Lc),
                                   static_cast<int>(hp.J), static_cast<int>(ldpsi), 2.0));
         check_launch("gemm_nt_f64");
         continue;
       }
-      float* z = static_cast<float*>(maps) + l0 * hp.J;
+      float* z = static_cast<float*>(maps) + l0 * ldm;
       switch (hp.dtype) {
-        case SRP_F32: launch_big_gemm<float>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, hp.J, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
-        case SRP_BF16: launch_big_gemm<__bf16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, hp.J, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
-        case SRP_F16: launch_big_gemm<_Float16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, hp.J, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
-        case SRP_FP8_E4M3: launch_big_gemm<fp8>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, hp.J, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
+        case SRP_F32: launch_big_gemm<float>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
+        case SRP_BF16: launch_big_gemm<__bf16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
+        case SRP_F16: launch_big_gemm<_Float16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
+        case SRP_FP8_E4M3: launch_big_gemm<fp8>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
       }
       continue;
     }
     // SLRI and SSPI: PHAT + sampling (+ fat stage) straight from the frames
     float* xiT = reinterpret_cast<float*>(base + lay.xi);
     float* part = reinterpret_cast<float*>(base + lay.part);
-    float* z = static_cast<float*>(maps) + l0 * hp.J;
+    float* z = static_cast<float*>(maps) + l0 * ldm;
     if (hp.variant == SRP_SLRI) {
       void* g = base + lay.g;
       switch (hp.dtype) {
         case SRP_F32:
           launch_front<1, float>(hp, dp, fr, Lc, xiT, lay.Lpad, part, g, st);
-          launch_tall_gemm<float>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          launch_tall_gemm<float>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, ldm, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
           break;
         case SRP_BF16:
           launch_front<1, __bf16>(hp, dp, fr, Lc, xiT, lay.Lpad, part, g, st);
-          launch_tall_gemm<__bf16>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          launch_tall_gemm<__bf16>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, ldm, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
           break;
         case SRP_F16:
           launch_front<1, _Float16>(hp, dp, fr, Lc, xiT, lay.Lpad, part, g, st);
-          launch_tall_gemm<_Float16>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          launch_tall_gemm<_Float16>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, ldm, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
           break;
         case SRP_FP8_E4M3:
           launch_front<1, fp8>(hp, dp, fr, Lc, xiT, lay.Lpad, part, g, st);
-          launch_tall_gemm<fp8>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, hp.J, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          launch_tall_gemm<fp8>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, ldm, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
           break;
       }
     } else {
       launch_front<0, float>(hp, dp, fr, Lc, xiT, lay.Lpad, part, nullptr, st);
       switch (hp.dtype) {
-        case SRP_F32: launch_sspi<float>(hp, dp, xiT, lay.Lpad, Lc, z, st); break;
-        case SRP_BF16: launch_sspi<__bf16>(hp, dp, xiT, lay.Lpad, Lc, z, st); break;
-        case SRP_F16: launch_sspi<_Float16>(hp, dp, xiT, lay.Lpad, Lc, z, st); break;
-        case SRP_FP8_E4M3: launch_sspi<fp8>(hp, dp, xiT, lay.Lpad, Lc, z, st); break;
+        case SRP_F32: launch_sspi<float>(hp, dp, xiT, lay.Lpad, Lc, z, ldm, st); break;
+        case SRP_BF16: launch_sspi<__bf16>(hp, dp, xiT, lay.Lpad, Lc, z, ldm, st); break;
+        case SRP_F16: launch_sspi<_Float16>(hp, dp, xiT, lay.Lpad, Lc, z, ldm, st); break;
+        case SRP_FP8_E4M3: launch_sspi<fp8>(hp, dp, xiT, lay.Lpad, Lc, z, ldm, st); break;
       }
     }
   }

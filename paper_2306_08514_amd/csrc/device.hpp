@@ -42,6 +42,7 @@ struct DevicePlan {
   float* d_V = nullptr;      // [P][2 max_np + 1][R]
   float* d_gscale = nullptr; // [P] activation scale of pair p in the fat stage
   float tall_alpha = 1.0f;   // undoes the activation scale in the tall GEMM
+  int tall_slots = 0;        // resident blocks of the tall kernel on the device (0 = not yet queried)
   // SSPI
   int32_t* d_start = nullptr;  // [J][P] absolute stacked lag index of tap 0
   void* d_w = nullptr;         // [J][P][Q] in dtype (f32, bf16, f16 or fp8)
@@ -70,7 +71,7 @@ size_t workspace_bytes(const HostPlan& hp, const DevicePlan& dp, int64_t L, int6
 
 // Enqueues the map computation for L frames on `stream`.
 void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L,
-                    void* maps, void* ws, size_t ws_bytes, int64_t frame_tile,
+                    void* maps, int64_t ld_maps, void* ws, size_t ws_bytes, int64_t frame_tile,
                     hipStream_t stream);
 
 // Waits for the recorded spans and accumulates them per kernel name.

@@ -42,7 +42,8 @@ class PlanInfo(ctypes.Structure):
                 ("J", ctypes.c_int64), ("PN", ctypes.c_int), ("max_np", ctypes.c_int),
                 ("rank_or_q", ctypes.c_int), ("variant", ctypes.c_int), ("dtype", ctypes.c_int),
                 ("mean_n", ctypes.c_double), ("macs_per_map", ctypes.c_double),
-                ("device_bytes", ctypes.c_size_t), ("plan_seconds", ctypes.c_double)]
+                ("device_bytes", ctypes.c_size_t), ("plan_seconds", ctypes.c_double),
+                ("map_pitch", ctypes.c_int64)]
 
 
 class KernelTime(ctypes.Structure):
@@ -70,7 +71,7 @@ def lib():
     L.srp_plan.restype = ctypes.c_int
     L.srp_workspace_size.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_size_t)]
     L.srp_workspace_size.restype = ctypes.c_int
-    L.srp_compute.argtypes = [vp, vp, i64, vp, vp, ctypes.c_size_t, vp]
+    L.srp_compute.argtypes = [vp, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
     L.srp_compute.restype = ctypes.c_int
     L.srp_crossspec.argtypes = [vp, vp, i64, vp, vp]
     L.srp_crossspec.restype = ctypes.c_int
@@ -141,6 +142,7 @@ class Plan:
         self.N, self.K = int(N), int(N) // 2
         i = self.info()
         self.M, self.P, self.J, self.PN = i["M"], i["P"], i["J"], i["PN"]
+        self.map_pitch = int(i["map_pitch"])
 
     # ---------------------------------------------------------------- info --
     def info(self):
@@ -170,19 +172,33 @@ class Plan:
         if frames.dim() != 3 or frames.shape[1] != self.M or frames.shape[2] != self.K + 1:
             raise ValueError(f"frames must have shape [L, {self.M}, {self.K + 1}]")
 
+    def empty_maps(self, L, device=None):
+        """An [L, J] output view over rows of map_pitch elements (the pitch at
+        which the map stores run fastest)."""
+        import torch
+        odt = torch.float64 if self.dtype == "f64" else torch.float32
+        buf = torch.empty((L, self.map_pitch), dtype=odt, device=device or torch.device("cuda", max(self.device, 0)))
+        return buf[:, :self.J]
+
     def compute(self, frames, maps=None, workspace=None, stream=None):
         """Enqueues one map per frame; returns maps [L, J] (float32, float64
-        for f64 plans).  frames: complex64 CUDA tensor [L, M, N/2 + 1]."""
+        for f64 plans).  frames: complex64 CUDA tensor [L, M, N/2 + 1].  maps
+        may be any [L, J] view with unit column stride and row stride >= J
+        (the row stride is passed as the pitch); by default a view at the
+        plan's map_pitch is allocated."""
         import torch
         self._check_frames(frames)
         L = frames.shape[0]
         odt = torch.float64 if self.dtype == "f64" else torch.float32
         if maps is None:
-            maps = torch.empty((L, self.J), dtype=odt, device=frames.device)
-        elif maps.dtype != odt or maps.shape != (L, self.J) or not maps.is_contiguous():
-            raise ValueError("maps must be a contiguous [L, J] tensor of the plan's output dtype")
+            maps = self.empty_maps(L, frames.device)
+        elif (maps.dtype != odt or tuple(maps.shape) != (L, self.J) or not maps.is_cuda
+              or (L > 0 and self.J > 1 and maps.stride(1) != 1) or (L > 1 and maps.stride(0) < self.J)):
+            raise ValueError("maps must be an [L, J] CUDA tensor of the plan's output dtype with unit "
+                             "column stride and row stride >= J")
+        ld = maps.stride(0) if L > 1 else self.J
         ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
-        _check(lib().srp_compute(self._h, _ptr(frames), L, _ptr(maps), _ptr(workspace), ws_bytes,
+        _check(lib().srp_compute(self._h, _ptr(frames), L, _ptr(maps), ld, _ptr(workspace), ws_bytes,
                                  _stream_handle(stream)))
         return maps
 

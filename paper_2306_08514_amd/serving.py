@@ -310,7 +310,7 @@ class TorchExecutor:
         p = self.plans[key]
         esz = 8 if p.dtype == "f64" else 4
         frames_bytes = n * p.M * (p.K + 1) * 8
-        return p.workspace_size(n) + n * p.J * esz + frames_bytes
+        return p.workspace_size(n) + n * p.map_pitch * esz + frames_bytes
 
     def mark_ready(self, frames):
         ev = self.torch.cuda.Event()
@@ -329,8 +329,7 @@ class TorchExecutor:
             fr = frames_list[0] if len(frames_list) == 1 else torch.cat(frames_list, 0)
             L = fr.shape[0]
             ws = torch.empty(max(1, p.workspace_size(L)), dtype=torch.uint8, device=self.device)
-            out = torch.empty((L, p.J), dtype=torch.float64 if p.dtype == "f64" else torch.float32,
-                              device=self.device)
+            out = p.empty_maps(L, self.device)
             p.compute(fr, maps=out, workspace=ws, stream=s)
             done = torch.cuda.Event()
             done.record(s)

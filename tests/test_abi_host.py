@@ -144,9 +144,13 @@ def test_non_finite_geometry_and_null_out():
 def test_host_only_plan_refuses_compute_and_export_of_missing_data():
     L = _lib_or_skip()
     p, _ = _host_plan("fd", 0)
-    rc = L.srp_compute(p._h, ctypes.c_void_p(16), 4, ctypes.c_void_p(16), None, 0, None)
+    rc = L.srp_compute(p._h, ctypes.c_void_p(16), 4, ctypes.c_void_p(16), 0, None, 0, None)
     assert rc == -1
-    assert L.srp_compute(p._h, None, 0, None, None, 0, None) == 0   # L = 0 is a no-op
+    assert L.srp_compute(p._h, None, 0, None, 0, None, 0, None) == 0   # L = 0 is a no-op
+    # a row pitch below J is rejected before any device access
+    rc = L.srp_compute(p._h, ctypes.c_void_p(16), 4, ctypes.c_void_p(16), p.J - 1, None, 0, None)
+    assert rc == -1 and b"ld_maps" in L.srp_last_error()
+    assert p.info()["map_pitch"] == (p.J + 127) // 128 * 128
     with pytest.raises(native.SrpError):
         p.export("slri_u")
     L.srp_destroy(None)   # safe on NULL

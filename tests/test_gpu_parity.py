@@ -211,6 +211,29 @@ def test_batch_invariance_and_workspace(native, room_small):
         assert torch.equal(full, again), variant
 
 
+def test_map_row_pitch(native, room_small):
+    """Maps written at a row pitch above J hold the same values as dense
+    maps, and the padding elements of every row are left untouched."""
+    cfg, Y = room_small
+    _announce("map row pitch")
+    Yt = torch.from_numpy(Y).cuda()
+    J = cfg["grid"].shape[0]
+    for variant, rq, dt in (("fd", 0, "f32"), ("fd", 0, "bf16"), ("fd", 0, "f64"), ("slri", 8, "bf16"),
+                            ("slri", 8, "f32"), ("sspi", 4, "bf16")):
+        p = _plan(native, cfg, variant, rq, dt)
+        odt = torch.float64 if dt == "f64" else torch.float32
+        dense = torch.empty((Y.shape[0], J), dtype=odt, device="cuda")
+        p.compute(Yt, maps=dense)
+        for pitch in (J + 37, p.map_pitch + 128):
+            buf = torch.full((Y.shape[0], pitch), float("nan"), dtype=odt, device="cuda")
+            p.compute(Yt, maps=buf[:, :J])
+            torch.cuda.synchronize()
+            assert torch.equal(buf[:, :J], dense), (variant, dt, pitch)
+            assert torch.isnan(buf[:, J:]).all(), (variant, dt, pitch)
+        with pytest.raises(ValueError):
+            p.compute(Yt, maps=torch.empty((Y.shape[0], J), dtype=odt, device="cuda").t().contiguous().t())
+
+
 # ------------------------------------- full-size M=8, J=125k room workload --
 
 @pytest.fixture(scope="module")
