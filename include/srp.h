@@ -85,6 +85,11 @@ typedef struct {
                             (no device memory; srp_compute is then invalid) */
   int64_t frame_tile;    /* frames per internal tile (default 1024) */
   size_t hbm_budget;     /* max device bytes for the plan, 0 = unlimited */
+  int sampling;          /* GCC sampling of SLRI/SSPI (Sec. III-B2, eq. (49)):
+                            0 = whichever of the two forms costs fewer
+                            operations by (49), 1 = the direct product
+                            2 Re[S_p psi_p] of (40), 2 = the iFFT of (46)
+                            (N must be a power of two, at most 4096) */
 } srp_opts;
 
 typedef struct {
@@ -104,6 +109,8 @@ typedef struct {
                             J rounded up to 128, so that every row starts on
                             a 512-byte boundary and the map stores write
                             whole cache lines */
+  int sampling_fft;      /* 1 if SLRI/SSPI sample the GCCs by the iFFT of
+                            (46), 0 for the direct product of (40) */
 } srp_plan_info;
 
 /* Fills *opts with the defaults listed above. */

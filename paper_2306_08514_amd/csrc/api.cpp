@@ -90,6 +90,7 @@ void srp_default_opts(srp_opts* o) {
   o->device = 0;
   o->frame_tile = 1024;
   o->hbm_budget = 0;
+  o->sampling = 0;
 }
 
 const char* srp_last_error(void) { return g_err.c_str(); }
@@ -107,6 +108,7 @@ srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J, do
   if (!dtype_ok(variant, o.dtype)) return fail(SRP_E_UNSUPPORTED, "dtype not offered for this variant");
   if (variant != SRP_FD && rank_or_q < 1) return fail(SRP_E_INVALID, "rank_or_q must be >= 1");
   if (o.frame_tile < 1) return fail(SRP_E_INVALID, "frame_tile must be >= 1");
+  if (o.sampling < 0 || o.sampling > 2) return fail(SRP_E_INVALID, "sampling must be 0, 1 or 2");
   if (variant == SRP_SLRI && rank_or_q > 32) return fail(SRP_E_UNSUPPORTED, "SLRI rank per pair above 32 is not built");
   if (variant == SRP_SSPI && rank_or_q > 8) return fail(SRP_E_UNSUPPORTED, "SSPI with Q above 8 is not built");
   SRP_GUARD({
@@ -118,6 +120,7 @@ srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J, do
     hp.dtype = o.dtype;
     hp.requested = rank_or_q;
     srp::build_geometry(hp, mics, M, grid, J, fs, N, o.c, o.n_aux);
+    srp::choose_sampling(hp, o.sampling);
     if (variant == SRP_SLRI) srp::build_slri(hp, rank_or_q, plan_threads());
     if (variant == SRP_SSPI) srp::build_sspi(hp, rank_or_q, plan_threads());
     srp::count_macs(hp);
@@ -211,6 +214,7 @@ srp_status srp_plan_info_get(srp_plan_t plan, srp_plan_info* info) {
   info->device_bytes = plan->dp.resident_bytes;
   info->plan_seconds = plan->plan_seconds;
   info->map_pitch = (hp.J + 127) / 128 * 128;
+  info->sampling_fft = hp.fft ? 1 : 0;
   return SRP_OK;
 }
 

@@ -609,6 +609,92 @@ __global__ __launch_bounds__(256) void spectral_slices(
   }
 }
 
+// iFFT sampling (46): xi_p[n] for n = -N_p..N_p as samples of the unscaled
+// length-2K inverse DFT of the Hermitian spectrum psi_p (zero at DC and
+// Nyquist).  A block owns one (frame, pair): psi = u_m conj(u_m') with
+// u = y/|y| is formed in LDS, the real length-2K transform is folded into one
+// complex length-K transform (z[i] = x[2i] + j x[2i+1] is the inverse DFT of
+// E[k] + j O[k], E[k] = psi[k] + conj psi[K-k], O[k] = (psi[k] - conj
+// psi[K-k]) exp(i pi k / K)), which runs as a radix-2 Stockham transform in
+// LDS.  The 2 N_p + 1 wanted samples go to xi [L][PN] (frame-major, written
+// contiguously); transpose_lp then forms xi^T.  Every block runs the same
+// instruction sequence, so a frame's samples do not depend on its batch.
+__device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
+}
+
+template <int LOGK>
+__global__ __launch_bounds__(256) void gcc_fft(const float2* __restrict__ Y, int M, int P,
+                                               const int32_t* __restrict__ pm, const int32_t* __restrict__ pmp,
+                                               const int32_t* __restrict__ np, const int32_t* __restrict__ off,
+                                               const float2* __restrict__ tw, const float2* __restrict__ w2,
+                                               float* __restrict__ xi, int64_t ldx) {
+  constexpr int K = 1 << LOGK;
+  __shared__ float2 bufA[K], bufB[K];
+  const int tid = threadIdx.x;
+  const int64_t l = blockIdx.x / P;
+  const int p = blockIdx.x % P;
+  const float2* ym = Y + (l * M + pm[p]) * (K + 1);
+  const float2* yq = Y + (l * M + pmp[p]) * (K + 1);
+  for (int k = tid; k < K; k += 256) {
+    float2 v = make_float2(0.0f, 0.0f);
+    if (k >= 1) {
+      const float2 a = unit_phase(ym[k]), b = unit_phase(yq[k]);
+      v = make_float2(__builtin_fmaf(a.x, b.x, a.y * b.y), __builtin_fmaf(a.y, b.x, -(a.x * b.y)));
+    }
+    bufA[k] = v;
+  }
+  __syncthreads();
+  for (int k = tid; k < K; k += 256) {
+    const float2 a = bufA[k];
+    const float2 c = k == 0 ? make_float2(0.0f, 0.0f) : bufA[K - k];
+    const float2 e = make_float2(a.x + c.x, a.y - c.y);
+    const float2 o = cmul(make_float2(a.x - c.x, a.y + c.y), w2[k]);
+    bufB[k] = make_float2(e.x - o.y, e.y + o.x);
+  }
+  __syncthreads();
+  float2* src = bufB;
+  float2* dst = bufA;
+#pragma unroll
+  for (int s = 0; s < LOGK; ++s) {
+    const int mm = 1 << s, half = (K >> (s + 1)) << s;  // butterfly span l * m = K / 2
+    for (int b = tid; b < K / 2; b += 256) {
+      const int j = b >> s, k = b & (mm - 1);
+      const float2 c0 = src[k + j * mm], c1 = src[k + j * mm + half];
+      dst[k + 2 * j * mm] = make_float2(c0.x + c1.x, c0.y + c1.y);
+      dst[k + 2 * j * mm + mm] = cmul(tw[j * mm], make_float2(c0.x - c1.x, c0.y - c1.y));
+    }
+    __syncthreads();
+    float2* t = src;
+    src = dst;
+    dst = t;
+  }
+  const int npp = np[p];
+  float* out = xi + l * ldx + off[p];
+  for (int i = tid; i < 2 * npp + 1; i += 256) {
+    const int t = (i - npp + 2 * K) & (2 * K - 1);
+    const float2 z = src[t >> 1];
+    out[i] = (t & 1) ? z.y : z.x;
+  }
+}
+
+// xi [L][ldx] -> xi^T [PN][ldt] through a 32 x 32 LDS tile.
+__global__ __launch_bounds__(256) void transpose_lp(const float* __restrict__ xi, int64_t ldx, int L, int PN,
+                                                    float* __restrict__ xiT, int64_t ldt) {
+  __shared__ float t[32][33];
+  const int n0 = blockIdx.x * 32, l0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int l = l0 + r, n = n0 + tx;
+    t[r][tx] = (l < L && n < PN) ? xi[static_cast<int64_t>(l) * ldx + n] : 0.0f;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int n = n0 + r, l = l0 + tx;
+    if (n < PN && l < L) xiT[static_cast<int64_t>(n) * ldt + l] = t[tx][r];
+  }
+}
+
 // xi^T[n][l] = sum of the slices' partial samples, in slice order.
 __global__ __launch_bounds__(256) void slice_reduce(const float* __restrict__ part, int nslices,
                                                     int64_t ldp, int PN, int L,
@@ -1103,7 +1189,24 @@ void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t
   // in slots 2 (k - 1), 2 (k - 1) + 1; the angle pi (k n mod 2K) / K is
   // reduced exactly in integers, then evaluated in FP64
   dp.samp_rows = 2 * hp.max_np + 1;
-  {
+  if (hp.fft) {
+    // iFFT sampling (46): twiddles of the length-K complex inverse FFT and
+    // the factors exp(i pi k / K) that fold the length-2K real transform
+    // into it, evaluated in FP64 and rounded once
+    dp.logk = 0;
+    while ((1 << dp.logk) < hp.K) ++dp.logk;
+    std::vector<float2> tw(hp.K / 2), w2(hp.K);
+    for (int t = 0; t < hp.K / 2; ++t)
+      tw[t] = make_float2(static_cast<float>(std::cos(2.0 * M_PI * t / hp.K)),
+                          static_cast<float>(std::sin(2.0 * M_PI * t / hp.K)));
+    for (int k = 0; k < hp.K; ++k)
+      w2[k] = make_float2(static_cast<float>(std::cos(M_PI * k / hp.K)),
+                          static_cast<float>(std::sin(M_PI * k / hp.K)));
+    dp.d_tw = static_cast<float2*>(A.get(tw.size() * sizeof(float2)));
+    upload(dp.d_tw, tw);
+    dp.d_w2 = static_cast<float2*>(A.get(w2.size() * sizeof(float2)));
+    upload(dp.d_w2, w2);
+  } else {
     const int rows = dp.samp_rows + 32;  // zero rows past the last lag tile
     std::vector<float> S(static_cast<size_t>(rows) * dp.Kp, 0.0f);
     for (int i = 0; i < dp.samp_rows; ++i) {
@@ -1296,8 +1399,13 @@ WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t 
     w.xi = off;
     off = align256(off + static_cast<size_t>(hp.PN) * w.Lpad * 4);
     w.part = off;
-    const size_t nsl = static_cast<size_t>((hp.K - 1 + SLICE_BINS - 1) / SLICE_BINS);
-    off = align256(off + nsl * static_cast<size_t>(hp.PN) * w.Lpad * 4);
+    if (hp.fft) {
+      // frame-major samples of the iFFT kernel, [Lc][PN]
+      off = align256(off + static_cast<size_t>(w.Lc) * hp.PN * 4);
+    } else {
+      const size_t nsl = static_cast<size_t>((hp.K - 1 + SLICE_BINS - 1) / SLICE_BINS);
+      off = align256(off + nsl * static_cast<size_t>(hp.PN) * w.Lpad * 4);
+    }
   }
   if (hp.variant == SRP_SLRI) {
     w.g = off;
@@ -1418,9 +1526,8 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
 
 // Sampling front end straight from the frames: spectral slices, the slice
 // reduction into xi^T, and for SLRI (MODE 1) the fat stage into g.
-template <int MODE, typename TG>
-void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t Lc, float* xiT, int64_t ldxi,
-                  float* part, void* g, hipStream_t st) {
+void launch_slices(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t Lc, float* xiT, int64_t ldxi,
+                   float* part, hipStream_t st) {
   const int nslices = (hp.K - 1 + SLICE_BINS - 1) / SLICE_BINS;
   dim3 grid(static_cast<unsigned>((Lc + 31) / 32), static_cast<unsigned>(nslices));
   const int CB = hp.M <= 8 ? 16 : (hp.M <= 16 ? 8 : 4);
@@ -1451,7 +1558,13 @@ void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_
   TRACED(dp, "slice_reduce", st,
          hipLaunchKernelGGL(slice_reduce, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, part,
                             nslices, ldxi, hp.PN, static_cast<int>(Lc), xiT));
-  if constexpr (MODE == 1) {
+}
+
+// SLRI fat stage g_p = V_p^T xi_p (eq. (57)) for every frame of the tile.
+template <typename TG>
+void launch_fat(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t ldxi, int64_t Lc, void* g,
+                hipStream_t st) {
+  {
     const int vrows = 2 * hp.max_np + 1;
     dim3 g2(static_cast<unsigned>((Lc + 255) / 256), static_cast<unsigned>(hp.P + 1));
 #define SRP_FAT(RM)                                                                                       \
@@ -1468,6 +1581,35 @@ void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_
 #undef SRP_FAT
   }
 }
+
+template <int MODE, typename TG>
+void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t Lc, float* xiT, int64_t ldxi,
+                  float* part, void* g, hipStream_t st) {
+  if (hp.fft) {
+    const dim3 grid(static_cast<unsigned>(Lc * hp.P));
+#define SRP_FFT(LK)                                                                                           \
+  case LK:                                                                                                    \
+    TRACED(dp, "gcc_fft", st,                                                                                 \
+           hipLaunchKernelGGL(gcc_fft<LK>, grid, dim3(256), 0, st, static_cast<const float2*>(frames), hp.M,  \
+                              hp.P, dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_tw, dp.d_w2, part,             \
+                              static_cast<int64_t>(hp.PN)));                                                  \
+    break;
+    switch (dp.logk) {
+      SRP_FFT(2) SRP_FFT(3) SRP_FFT(4) SRP_FFT(5) SRP_FFT(6) SRP_FFT(7) SRP_FFT(8) SRP_FFT(9) SRP_FFT(10)
+      SRP_FFT(11)
+      default: throw Error{SRP_E_UNSUPPORTED, "iFFT sampling needs N a power of two, at most 4096"};
+    }
+#undef SRP_FFT
+    const dim3 tgrid(static_cast<unsigned>((hp.PN + 31) / 32), static_cast<unsigned>((Lc + 31) / 32));
+    TRACED(dp, "transpose_lp", st,
+           hipLaunchKernelGGL(transpose_lp, tgrid, dim3(256), 0, st, part, static_cast<int64_t>(hp.PN),
+                              static_cast<int>(Lc), hp.PN, xiT, ldxi));
+  } else {
+    launch_slices(hp, dp, frames, Lc, xiT, ldxi, part, st);
+  }
+  if constexpr (MODE == 1) launch_fat<TG>(hp, dp, xiT, ldxi, Lc, g, st);
+}
+
 
 template <typename TW, int Q>
 void launch_sspi_q(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t Lpad,

@@ -36,6 +36,9 @@ struct DevicePlan {
   int samp_rows = 0;         // 2 max_np + 1
   int32_t* d_tasks = nullptr;  // sampling tasks (pair, 32-lag tile)
   int ntasks = 0;
+  float2* d_tw = nullptr;      // iFFT sampling: exp(+2 pi i t / K), t < K/2
+  float2* d_w2 = nullptr;      // iFFT sampling: exp(+i pi k / K), k < K
+  int logk = 0;                // log2 K
   // SLRI
   int Kc = 0;                // columns of the tall GEMM (P*R padded)
   void* d_U = nullptr;       // [Jpad][Kc] in dtype

@@ -260,9 +260,27 @@ void build_sspi(HostPlan& hp, int Q, int threads) {
   });
 }
 
+void choose_sampling(HostPlan& hp, int mode) {
+  const bool pow2 = hp.N >= 8 && hp.N <= 4096 && (hp.N & (hp.N - 1)) == 0;
+  const double direct = 2.0 * hp.PN * (hp.K - 1);
+  const double ifft = 8.0 * hp.P * hp.K * std::log2(2.0 * hp.K);
+  if (mode == 2 && !pow2)
+    throw Error{SRP_E_UNSUPPORTED, "iFFT sampling needs N a power of two, at most 4096"};
+  // the direct kernel stages the table rows of every lag a 32-lag tile can
+  // touch in LDS; past its capacity only the iFFT form runs
+  const int cb = hp.M <= 8 ? 16 : (hp.M <= 16 ? 8 : 4);
+  const bool direct_fits = (2 * hp.max_np + 1 + 32) * (cb / 2) <= 1024;
+  if (mode == 1 && !direct_fits)
+    throw Error{SRP_E_UNSUPPORTED, "too many lags for the direct sampling kernel; use the iFFT form"};
+  hp.fft = mode == 2 || (mode == 0 && pow2 && (ifft < direct || !direct_fits));
+  if (mode == 0 && !direct_fits && !pow2)
+    throw Error{SRP_E_UNSUPPORTED, "too many lags for the direct sampling kernel and N is not a power of two"};
+}
+
 void count_macs(HostPlan& hp) {
   const double J = static_cast<double>(hp.J);
-  const double samp = 2.0 * hp.PN * (hp.K - 1);
+  // sampling by (49): the direct product or the iFFT, whichever runs
+  const double samp = hp.fft ? 8.0 * hp.P * hp.K * std::log2(2.0 * hp.K) : 2.0 * hp.PN * (hp.K - 1);
   if (hp.variant == SRP_FD) {
     hp.macs_per_map = 2.0 * J * hp.P * (hp.K - 1);
   } else if (hp.variant == SRP_SLRI) {

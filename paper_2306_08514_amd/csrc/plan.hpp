@@ -46,6 +46,8 @@ struct HostPlan {
   std::vector<int32_t> start;   // [J][P] first lag s (in -N_p..N_p)
   std::vector<double> w;        // [J][P][Q], zero for q >= Q_p
 
+  bool fft = false;  // GCC sampling by the iFFT of (46) instead of the direct product of (40)
+
   double macs_per_map = 0;
 };
 
@@ -53,6 +55,11 @@ struct HostPlan {
 // Throws srp::Error on invalid input.
 void build_geometry(HostPlan& hp, const double* mics, int M, const double* grid,
                     int64_t J, double fs, int N, double c, int n_aux);
+
+// Chooses the GCC sampling form: mode 1 = direct product (40), 2 = iFFT
+// (46), 0 = the cheaper of the two operation counts of (49), 2 PN (K-1)
+// against 8 P K log2(2K); the iFFT needs N a power of two up to 4096.
+void choose_sampling(HostPlan& hp, int mode);
 
 // Per-pair rank-R truncated SVD of Lambda_p (Sec. IV-A, eq. (54) per pair).
 void build_slri(HostPlan& hp, int R, int threads);

@@ -164,6 +164,30 @@ def test_full_rank_slri_and_dense_sspi_agree_on_gpu(native, room_small):
     _check_maps(zs, z_si, 1e-5, "slri full rank vs SI")
 
 
+@pytest.mark.parametrize("variant,rq,dtype", [("slri", 8, "f32"), ("slri", 8, "bf16"), ("sspi", 4, "f32"),
+                                              ("sspi", 3, "bf16")])
+def test_fft_sampling(native, sq4, room_small, variant, rq, dtype):
+    """The iFFT form of the GCC sampling (46) against the oracle's iFFT
+    samples and maps, on both small workloads (forced on), and the automatic
+    choice of the form by the operation counts of (49)."""
+    for cfg, Y in (sq4, room_small):
+        _announce(f"fft sampling {cfg['name']} {variant} {rq} {dtype}")
+        p = _plan(native, cfg, variant, rq, dtype, sampling="fft")
+        assert p.info()["sampling_fft"] == 1
+        Yt = torch.from_numpy(Y).cuda()
+        K = cfg["N"] // 2
+        Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+        ref_xi = o.stack_samples(o.gcc_samples_ifft(o.phat(Y), Np, K))
+        xi = p.gcc_samples(Yt).cpu().numpy()
+        scale = np.abs(ref_xi).max(axis=1, keepdims=True)
+        assert (np.abs(xi - ref_xi) / scale).max() <= 1e-5
+        z = p.compute(Yt).cpu().numpy()
+        _check_maps(z, _oracle_maps(variant, Y, cfg, rq), TOL[dtype], f"fft {cfg['name']} {variant} {dtype}")
+        # the automatic choice: both small workloads have few lags, so the
+        # direct product is cheaper by (49)
+        assert _plan(native, cfg, variant, rq, dtype).info()["sampling_fft"] == 0
+
+
 # ---------------------------------------------------------- edge cases ----
 
 def test_edge_cases(native, sq4):
