@@ -121,6 +121,7 @@ srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J, do
     hp.requested = rank_or_q;
     srp::build_geometry(hp, mics, M, grid, J, fs, N, o.c, o.n_aux);
     srp::choose_sampling(hp, o.sampling);
+    hp.device_fit = o.device >= 0;
     if (variant == SRP_SLRI) srp::build_slri(hp, rank_or_q, plan_threads());
     if (variant == SRP_SSPI) srp::build_sspi(hp, rank_or_q, plan_threads());
     srp::count_macs(hp);

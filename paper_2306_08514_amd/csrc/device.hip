@@ -15,6 +15,7 @@
 #include <cstring>
 #include <string>
 #include <type_traits>
+#include <thread>
 #include <vector>
 
 #include "../../include/srp.h"
@@ -1035,6 +1036,165 @@ __global__ __launch_bounds__(256) void sspi_gather(const float* __restrict__ xiT
 
 // ================================================== plan-time kernels =====
 
+// sinc(x - n) for integer n with the argument reduced exactly: x = k0 + r,
+// |r| <= 1/2, sin(pi (x - n)) = (-1)^(k0 + n) sin(pi r).  sr = sin(pi r)
+// is shared by every n of one x.
+__device__ inline double sinc_red(double x, double k0, double sr, int n) {
+  const double d = x - static_cast<double>(n);
+  if (d == 0.0) return 1.0;
+  const long long par = (static_cast<long long>(k0) + n) & 1LL;
+  return (par ? -sr : sr) / (M_PI * d);
+}
+
+// Gram matrices G_p = Lambda_p^T Lambda_p (eq. (54) per pair: its right
+// singular vectors are the eigenvectors of G_p) in FP64 on
+// v_mfma_f64_16x16x4_f64, Lambda_p[j][a] = sinc(x_p(j) - (a - N_p))
+// generated in registers.  Block = one 64 x 64 tile (ta <= tb) of one pair,
+// looping over all J; both the tile and its mirror are written to
+// G [P][nmax][nmax].  Lane i supplies row i % 16 and k slot (candidate)
+// i / 16 of each 4-candidate step; accumulator register v of lane i holds
+// row 4 v + i / 16, column i % 16.
+__global__ __launch_bounds__(256) void gram_f64(const double* __restrict__ x, int64_t J,
+                                                const int32_t* __restrict__ np, int nmax, int ntile,
+                                                double* __restrict__ G) {
+  int t = blockIdx.x, ta = 0;
+  while (t >= ntile - ta) {
+    t -= ntile - ta;
+    ++ta;
+  }
+  const int tb = ta + t;
+  const int p = blockIdx.y;
+  const int npp = np[p], n = 2 * npp + 1;
+  if (tb * 64 >= n) return;  // block-uniform
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wx = (wave >> 1) * 32, ww = (wave & 1) * 32;
+  const int r16 = lane & 15, g = lane >> 4;
+  int ra[2], cb[2];
+  for (int a = 0; a < 2; ++a) ra[a] = ta * 64 + wx + a * 16 + r16;
+  for (int b = 0; b < 2; ++b) cb[b] = tb * 64 + ww + b * 16 + r16;
+  f64x4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.0;
+  const double* xp = x + static_cast<int64_t>(p) * J;
+  for (int64_t j0 = 0; j0 < J; j0 += 4) {
+    const int64_t j = j0 + g;
+    const bool ok = j < J;
+    const double xv = ok ? xp[j] : 0.0;
+    const double k0 = rint(xv), sr = sin(M_PI * (xv - k0));
+    double fa[2], fb[2];
+    for (int a = 0; a < 2; ++a) fa[a] = (ok && ra[a] < n) ? sinc_red(xv, k0, sr, ra[a] - npp) : 0.0;
+    for (int b = 0; b < 2; ++b) fb[b] = (ok && cb[b] < n) ? sinc_red(xv, k0, sr, cb[b] - npp) : 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+  }
+  double* Gp = G + static_cast<int64_t>(p) * nmax * nmax;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int col = cb[b];
+      if (col >= n) continue;
+      for (int v = 0; v < 4; ++v) {
+        const int row = ta * 64 + wx + a * 16 + 4 * v + g;
+        if (row >= n) continue;
+        Gp[static_cast<int64_t>(row) * nmax + col] = acc[a][b][v];
+        Gp[static_cast<int64_t>(col) * nmax + row] = acc[a][b][v];
+      }
+    }
+}
+
+// U_p = Lambda_p V_p (eq. (54): left singular vectors times singular values)
+// into the FP32 staging matrix Us [Jpad][Kc] at columns p R + r.  One thread
+// per candidate; V_p is staged in LDS 512 rows x 8 columns at a time; FP64
+// sums.
+__global__ __launch_bounds__(256) void slri_u_f64(const double* __restrict__ x, int64_t J,
+                                                  const int32_t* __restrict__ np, int nmax, int R,
+                                                  const double* __restrict__ V, float* __restrict__ Us, int Kc) {
+  constexpr int AR = 512;
+  __shared__ double vs[AR * 8];
+  const int p = blockIdx.y;
+  const int npp = np[p], n = 2 * npp + 1;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const double xv = j < J ? x[static_cast<int64_t>(p) * J + j] : 0.0;
+  const double k0 = rint(xv), sr = sin(M_PI * (xv - k0));
+  const double* Vp = V + static_cast<int64_t>(p) * nmax * R;
+  for (int r0 = 0; r0 < R; r0 += 8) {
+    const int rc = min(8, R - r0);
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int a0 = 0; a0 < n; a0 += AR) {
+      const int an = min(AR, n - a0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < an * 8; e += 256) {
+        const int a = e / 8, c = e % 8;
+        vs[e] = c < rc ? Vp[static_cast<int64_t>(a0 + a) * R + r0 + c] : 0.0;
+      }
+      __syncthreads();
+      if (j < J) {
+        for (int a = 0; a < an; ++a) {
+          const double lam = sinc_red(xv, k0, sr, a0 + a - npp);
+#pragma unroll
+          for (int c = 0; c < 8; ++c) acc[c] = fma(lam, vs[a * 8 + c], acc[c]);
+        }
+      }
+    }
+    if (j < J) {
+      float* dst = Us + j * Kc + p * R + r0;
+      for (int c = 0; c < rc; ++c) dst[c] = static_cast<float>(acc[c]);
+    }
+  }
+}
+
+// max |U_p| over the staged columns of pair p (per-pair FP8 scale).
+__global__ __launch_bounds__(256) void pair_absmax(const float* __restrict__ Us, int64_t J, int Kc, int R,
+                                                   float* __restrict__ out) {
+  __shared__ float red[256];
+  const int p = blockIdx.x;
+  float m = 0.0f;
+  for (int64_t e = threadIdx.x; e < J * R; e += 256)
+    m = fmaxf(m, fabsf(Us[(e / R) * Kc + p * R + e % R]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s2]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[p] = red[0];
+}
+
+// Us[:, p R .. p R + R) *= inv_sigma[p]
+__global__ void scale_pairs(float* __restrict__ Us, int64_t rows, int Kc, int R, int P,
+                            const float* __restrict__ inv_sigma) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= rows * Kc) return;
+  const int col = static_cast<int>(i % Kc);
+  if (col < P * R) Us[i] *= inv_sigma[col / R];
+}
+
+// SSPI windows (eq. (55) per row and pair): the Q_p integers nearest to x,
+// clamped to [-N_p, N_p], start = clamp(ceil(x - Q_p / 2), -N_p,
+// N_p - Q_p + 1), weights sinc(x - n) in FP64 rounded once to FP32 and then
+// to the weight type; records [P][J] (absolute stacked lag) and [P][J][Qs].
+template <typename TW>
+__global__ void sspi_windows(const double* __restrict__ x, int64_t J, const int32_t* __restrict__ np,
+                             const int32_t* __restrict__ off, int Q, int Qs, int32_t* __restrict__ start,
+                             TW* __restrict__ w) {
+  const int p = blockIdx.y;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (j >= J) return;
+  const int npp = np[p];
+  const int q = min(Q, 2 * npp + 1);
+  const double xv = x[static_cast<int64_t>(p) * J + j];
+  double s = ceil(xv - 0.5 * q);
+  s = fmin(fmax(s, static_cast<double>(-npp)), static_cast<double>(npp - q + 1));
+  const int si = static_cast<int>(s);
+  const int64_t rec = static_cast<int64_t>(p) * J + j;
+  start[rec] = off[p] + si + npp;
+  const double k0 = rint(xv), sr = sin(M_PI * (xv - k0));
+  for (int t2 = 0; t2 < Qs; ++t2) {
+    const float v = t2 < q ? static_cast<float>(sinc_red(xv, k0, sr, si + t2)) : 0.0f;
+    w[rec * Qs + t2] = cvt<TW>(v);
+  }
+}
+
 // Steering operand of conv. FD-SRP: H[j][p Kp + 2 (k-1) + {0,1}] =
 // (cos theta, -sin theta), theta = pi k x_p(j) / K (eq. (19) with (14)).  The
 // phase is reduced in FP64: theta = 2 pi (t - rint(t)), t = k x / (2K), and
@@ -1143,7 +1303,27 @@ constexpr int SSPI_ROWS = 32 * 1024 / ((SSPI_FT + 4) * 4);  // lag rows per LDS 
 
 }  // namespace
 
-void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budget) {
+// Plan-time device temporary, freed on every exit path.
+struct TmpBuf {
+  void* p = nullptr;
+  explicit TmpBuf(size_t bytes) { HIP_OK(hipMalloc(&p, std::max<size_t>(bytes, 1))); }
+  ~TmpBuf() {
+    if (p) (void)hipFree(p);
+  }
+  TmpBuf(const TmpBuf&) = delete;
+  TmpBuf& operator=(const TmpBuf&) = delete;
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+int host_threads() {
+  const unsigned n = std::thread::hardware_concurrency();
+  return static_cast<int>(std::min(std::max(n, 1u), 16u));
+}
+
+void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budget) {
   (void)frame_tile;
   dp.device = -1;
   HIP_OK(hipGetDevice(&dp.device));
@@ -1242,20 +1422,68 @@ void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t
     const int es = static_cast<int>(dsize(hp.dtype));
     const int elem_per_slice = std::max(BIG_BKB / es, hp.dtype == SRP_F32 ? 0 : 4 * TALL_STEP_BYTES(hp.dtype) / es);
     dp.Kc = static_cast<int>(round_up(static_cast<int64_t>(P) * R, elem_per_slice));
+    TmpBuf dx(hp.x.size() * sizeof(double));
+    upload(dx.p, hp.x);
+    // Gram matrices on the device (FP64 MFMA), eigenvectors on the host
+    {
+      const int ntile = (vrows + 63) / 64;
+      const size_t gn = static_cast<size_t>(P) * vrows * vrows;
+      TmpBuf dg(gn * sizeof(double));
+      HIP_OK(hipMemset(dg.p, 0, gn * sizeof(double)));
+      hipLaunchKernelGGL(gram_f64, dim3(static_cast<unsigned>(ntile * (ntile + 1) / 2), static_cast<unsigned>(P)),
+                         dim3(256), 0, 0, dx.as<double>(), hp.J, dp.d_np, vrows, ntile, dg.as<double>());
+      check_launch("gram_f64");
+      std::vector<double> gall(gn);
+      HIP_OK(hipMemcpy(gall.data(), dg.p, gn * sizeof(double), hipMemcpyDeviceToHost));
+      parallel_for(P, host_threads(), [&](int p) {
+        const int n = 2 * hp.np[p] + 1;
+        std::vector<double> gp(static_cast<size_t>(n) * n);
+        const double* src = &gall[static_cast<size_t>(p) * vrows * vrows];
+        for (int a = 0; a < n; ++a)
+          std::copy(src + static_cast<size_t>(a) * vrows, src + static_cast<size_t>(a) * vrows + n,
+                    gp.begin() + static_cast<size_t>(a) * n);
+        slri_fit_pair(hp, p, gp);
+      });
+    }
+    // U = Lambda V on the device, staged in FP32 as [Jpad][Kc]
+    const size_t ucount = static_cast<size_t>(dp.Jpad) * dp.Kc;
+    TmpBuf dv(hp.V.size() * sizeof(double));
+    upload(dv.p, hp.V);
+    TmpBuf us(ucount * sizeof(float));
+    HIP_OK(hipMemset(us.p, 0, ucount * sizeof(float)));
+    hipLaunchKernelGGL(slri_u_f64, dim3(static_cast<unsigned>((hp.J + 255) / 256), static_cast<unsigned>(P)),
+                       dim3(256), 0, 0, dx.as<double>(), hp.J, dp.d_np, vrows, R, dv.as<double>(), us.as<float>(),
+                       dp.Kc);
+    check_launch("slri_u_f64");
     // per-pair weight scale (FP8 only) and a power-of-two activation scale
     // bounding |g| by the format's range: |xi| <= 2 (K - 1) since |psi| <= 1
     std::vector<float> sigma(P, 1.0f), gscale(P, 1.0f);
+    if (hp.dtype == SRP_FP8_E4M3) {
+      TmpBuf um(P * sizeof(float));
+      hipLaunchKernelGGL(pair_absmax, dim3(P), dim3(256), 0, 0, us.as<float>(), hp.J, dp.Kc, R, um.as<float>());
+      check_launch("pair_absmax");
+      std::vector<float> umax(P);
+      HIP_OK(hipMemcpy(umax.data(), um.p, P * sizeof(float), hipMemcpyDeviceToHost));
+      std::vector<float> inv(P, 1.0f);
+      for (int p = 0; p < P; ++p) {
+        if (umax[p] > 0) sigma[p] = static_cast<float>(std::exp2(std::ceil(std::log2(umax[p] / 448.0))));
+        inv[p] = 1.0f / sigma[p];
+      }
+      TmpBuf di(P * sizeof(float));
+      upload(di.p, inv);
+      hipLaunchKernelGGL(scale_pairs, dim3(static_cast<unsigned>((ucount + 255) / 256)), dim3(256), 0, 0,
+                         us.as<float>(), dp.Jpad, dp.Kc, R, P, di.as<float>());
+      check_launch("scale_pairs");
+      HIP_OK(hipDeviceSynchronize());
+    }
     double amax_act = 0;
     for (int p = 0; p < P; ++p) {
-      double umax = 0, vl1 = 0;
-      const double* Up = &hp.U[static_cast<size_t>(p) * hp.J * R];
-      for (size_t i = 0; i < static_cast<size_t>(hp.J) * R; ++i) umax = std::max(umax, std::fabs(Up[i]));
+      double vl1 = 0;
       for (int r = 0; r < R; ++r) {
-        double s = 0;
-        for (int i = 0; i < vrows; ++i) s += std::fabs(hp.V[(static_cast<size_t>(p) * vrows + i) * R + r]);
-        vl1 = std::max(vl1, s);
+        double sum = 0;
+        for (int i = 0; i < vrows; ++i) sum += std::fabs(hp.V[(static_cast<size_t>(p) * vrows + i) * R + r]);
+        vl1 = std::max(vl1, sum);
       }
-      if (hp.dtype == SRP_FP8_E4M3 && umax > 0) sigma[p] = static_cast<float>(std::exp2(std::ceil(std::log2(umax / 448.0))));
       amax_act = std::max(amax_act, sigma[p] * vl1 * 2.0 * (hp.K - 1));
     }
     double act = 1.0;
@@ -1263,28 +1491,9 @@ void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t
     if (hp.dtype == SRP_F16 && amax_act > 60000.0) act = std::exp2(std::ceil(std::log2(amax_act / 60000.0)));
     for (int p = 0; p < P; ++p) gscale[p] = static_cast<float>(sigma[p] / act);
     dp.tall_alpha = static_cast<float>(act);
-
-    // U staged in FP32 as [Jpad][Kc], pair-major columns p R + r
-    std::vector<float> Us(static_cast<size_t>(dp.Jpad) * dp.Kc, 0.0f);
-    for (int p = 0; p < P; ++p) {
-      const double* Up = &hp.U[static_cast<size_t>(p) * hp.J * R];
-      const double inv = 1.0 / sigma[p];
-      for (int64_t j = 0; j < hp.J; ++j)
-        for (int r = 0; r < R; ++r)
-          Us[static_cast<size_t>(j) * dp.Kc + p * R + r] = static_cast<float>(Up[static_cast<size_t>(j) * R + r] * inv);
-    }
-    float* d_stage = nullptr;
-    HIP_OK(hipMalloc(&d_stage, Us.size() * 4));
-    try {
-      upload(d_stage, Us);
-      dp.d_U = A.get(Us.size() * dsize(hp.dtype));
-      convert_dtype(hp.dtype, d_stage, dp.d_U, static_cast<int64_t>(Us.size()));
-      HIP_OK(hipDeviceSynchronize());
-    } catch (...) {
-      (void)hipFree(d_stage);
-      throw;
-    }
-    HIP_OK(hipFree(d_stage));
+    dp.d_U = A.get(ucount * dsize(hp.dtype));
+    convert_dtype(hp.dtype, us.as<float>(), dp.d_U, static_cast<int64_t>(ucount));
+    HIP_OK(hipDeviceSynchronize());
     std::vector<float> Vf(hp.V.begin(), hp.V.end());
     dp.d_V = static_cast<float*>(A.get(Vf.size() * 4));
     upload(dp.d_V, Vf);
@@ -1301,29 +1510,23 @@ void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t
     const int Qs = static_cast<int>(round_up(Q * es, 4) / es);
     // device layouts are pair-major ([P][J] and [P][J][Qs]) so that lanes
     // (consecutive locations) load consecutive records
-    std::vector<int32_t> st(static_cast<size_t>(hp.J) * P);
-    std::vector<float> ws(static_cast<size_t>(hp.J) * P * Qs, 0.0f);
-    for (int64_t j = 0; j < hp.J; ++j)
-      for (int p = 0; p < P; ++p) {
-        const size_t jp = static_cast<size_t>(j) * P + p;
-        const size_t pj = static_cast<size_t>(p) * hp.J + j;
-        st[pj] = hp.off[p] + hp.start[jp] + hp.np[p];
-        for (int q = 0; q < hp.qp[p]; ++q) ws[pj * Qs + q] = static_cast<float>(hp.w[jp * Q + q]);
-      }
-    dp.d_start = static_cast<int32_t*>(A.get(st.size() * 4));
-    upload(dp.d_start, st);
-    float* d_stage = nullptr;
-    HIP_OK(hipMalloc(&d_stage, ws.size() * 4));
-    try {
-      upload(d_stage, ws);
-      dp.d_w = A.get(ws.size() * es);
-      convert_dtype(hp.dtype, d_stage, dp.d_w, static_cast<int64_t>(ws.size()));
-      HIP_OK(hipDeviceSynchronize());
-    } catch (...) {
-      (void)hipFree(d_stage);
-      throw;
+    TmpBuf dx(hp.x.size() * sizeof(double));
+    upload(dx.p, hp.x);
+    dp.d_start = static_cast<int32_t*>(A.get(static_cast<size_t>(hp.J) * P * 4));
+    dp.d_w = A.get(static_cast<size_t>(hp.J) * P * Qs * es);
+    const dim3 gw(static_cast<unsigned>((hp.J + 255) / 256), static_cast<unsigned>(P));
+#define SRP_WIN(TW)                                                                                           \
+  hipLaunchKernelGGL(sspi_windows<TW>, gw, dim3(256), 0, 0, dx.as<double>(), hp.J, dp.d_np, dp.d_off, Q, Qs,   \
+                     dp.d_start, static_cast<TW*>(dp.d_w))
+    switch (hp.dtype) {
+      case SRP_F32: SRP_WIN(float); break;
+      case SRP_BF16: SRP_WIN(__bf16); break;
+      case SRP_F16: SRP_WIN(_Float16); break;
+      case SRP_FP8_E4M3: SRP_WIN(fp8); break;
     }
-    HIP_OK(hipFree(d_stage));
+#undef SRP_WIN
+    check_launch("sspi_windows");
+    HIP_OK(hipDeviceSynchronize());
     // pair chunks whose lags (plus Q - 1 spill rows) fit the LDS tile
     dp.chunk_p0.clear();
     int p = 0;

@@ -67,7 +67,7 @@ struct DevicePlan {
 };
 
 // Allocates and fills the device operands of a plan.  Throws srp::Error.
-void device_build(const HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budget);
+void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budget);
 void device_free(DevicePlan& dp);
 
 size_t workspace_bytes(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t frame_tile);

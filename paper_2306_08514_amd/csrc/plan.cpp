@@ -5,6 +5,7 @@
 #include <atomic>
 #include <cmath>
 #include <functional>
+#include <limits>
 #include <thread>
 
 #include "../../include/srp.h"
@@ -14,6 +15,8 @@ namespace srp {
 namespace {
 
 void fail(const std::string& msg) { throw Error{SRP_E_INVALID, msg}; }
+
+}  // namespace
 
 // Runs body(i) for i in [0, n) on up to `threads` threads.
 void parallel_for(int n, int threads, const std::function<void(int)>& body) {
@@ -41,7 +44,6 @@ void parallel_for(int n, int threads, const std::function<void(int)>& body) {
     if (e.code != 0) throw e;
 }
 
-}  // namespace
 
 double sinc_shift(double x, int n) {
   // sin(pi (x - n)) = (-1)^(n + k0) sin(pi r) with x = k0 + r, |r| <= 1/2;
@@ -182,20 +184,160 @@ void sym_eig(std::vector<double>& a, int n, std::vector<double>& evals,
   evecs.swap(sorted);
 }
 
+// Symmetric eigendecomposition by Householder reduction to tridiagonal form
+// followed by the implicitly shifted QL iteration; same interface as sym_eig.
+// The orthogonal factor is accumulated transposed (row i = i-th basis
+// vector) so that both the reduction and the QL rotations touch contiguous
+// rows.
+void sym_eig_tridiag(std::vector<double>& a, int n, std::vector<double>& evals,
+                     std::vector<double>& evecs) {
+  auto A = [&](int i, int j) -> double& { return a[static_cast<size_t>(i) * n + j]; };
+  std::vector<double> zt(static_cast<size_t>(n) * n, 0.0);  // Q^T, later Z^T
+  auto Z = [&](int i, int j) -> double& { return zt[static_cast<size_t>(i) * n + j]; };
+  for (int i = 0; i < n; ++i) Z(i, i) = 1.0;
+  std::vector<double> v(n), p(n), w(n), r(n);
+  // reduction: step k annihilates column k below the subdiagonal with the
+  // reflector H = I - 2 v v^T, v supported on k+1..n-1; A <- H A H and
+  // Q^T <- H Q^T
+  for (int k = 0; k + 2 < n; ++k) {
+    double alpha = 0.0;
+    for (int i = k + 1; i < n; ++i) alpha += A(i, k) * A(i, k);
+    alpha = std::sqrt(alpha);
+    if (alpha == 0.0) continue;
+    if (A(k + 1, k) > 0) alpha = -alpha;
+    std::fill(v.begin(), v.end(), 0.0);
+    for (int i = k + 1; i < n; ++i) v[i] = A(i, k);
+    v[k + 1] -= alpha;
+    double vn = 0.0;
+    for (int i = k + 1; i < n; ++i) vn += v[i] * v[i];
+    vn = std::sqrt(vn);
+    if (vn == 0.0) continue;
+    for (int i = k + 1; i < n; ++i) v[i] /= vn;
+    // H A H = A - v w^T - w v^T with p = A v, w = 2 (p - (v^T p) v)
+    for (int i = k; i < n; ++i) {
+      double s = 0.0;
+      for (int j = k + 1; j < n; ++j) s += A(i, j) * v[j];
+      p[i] = s;
+    }
+    double kv = 0.0;
+    for (int i = k + 1; i < n; ++i) kv += v[i] * p[i];
+    for (int i = k; i < n; ++i) w[i] = 2.0 * (p[i] - kv * v[i]);
+    for (int i = k; i < n; ++i) {
+      double* ai = &A(i, 0);
+      const double vi = v[i], wi = w[i];
+      for (int j = k; j < n; ++j) ai[j] -= vi * w[j] + wi * v[j];
+    }
+    // Q^T <- H Q^T: rows k+1.. change by -2 v (v^T Q^T)
+    std::fill(r.begin(), r.end(), 0.0);
+    for (int i = k + 1; i < n; ++i) {
+      const double vi = v[i];
+      const double* zi = &Z(i, 0);
+      for (int c = 0; c < n; ++c) r[c] += vi * zi[c];
+    }
+    for (int i = k + 1; i < n; ++i) {
+      const double f = 2.0 * v[i];
+      double* zi = &Z(i, 0);
+      for (int c = 0; c < n; ++c) zi[c] -= f * r[c];
+    }
+  }
+  std::vector<double> d(n), e(n, 0.0);
+  for (int i = 0; i < n; ++i) d[i] = A(i, i);
+  for (int i = 0; i + 1 < n; ++i) e[i] = A(i + 1, i);
+  // implicit QL with shifts from the trailing 2 x 2 block: e[i] couples
+  // d[i] and d[i + 1]; a chase from m - 1 down to l applies plane rotations
+  // to rows i, i + 1 of Z^T.  An off-diagonal counts as negligible against
+  // the largest |d| + |e| met so far, so blocks of (near-)zero eigenvalues
+  // of a rank-deficient Gram matrix deflate too.
+  double tst = 0.0;
+  for (int l = 0; l < n; ++l) {
+    tst = std::max(tst, std::fabs(d[l]) + std::fabs(e[l]));
+    for (int iter = 0;; ++iter) {
+      int m = l;
+      for (; m + 1 < n; ++m) {
+        if (std::fabs(e[m]) <= std::numeric_limits<double>::epsilon() * tst) break;
+      }
+      if (m == l) break;
+      if (iter == 100) throw Error{SRP_E_INVALID, "eigensolver did not converge"};
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double rr = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + std::copysign(rr, g));
+      double s = 1.0, c = 1.0, pp = 0.0;
+      bool early = false;
+      for (int i = m - 1; i >= l; --i) {
+        const double f = s * e[i], b = c * e[i];
+        rr = std::hypot(f, g);
+        e[i + 1] = rr;
+        if (rr == 0.0) {
+          d[i + 1] -= pp;
+          e[m] = 0.0;
+          early = true;
+          break;
+        }
+        s = f / rr;
+        c = g / rr;
+        g = d[i + 1] - pp;
+        rr = (d[i] - g) * s + 2.0 * c * b;
+        pp = s * rr;
+        d[i + 1] = g + pp;
+        g = c * rr - b;
+        double* zi = &Z(i, 0);
+        double* zi1 = &Z(i + 1, 0);
+        for (int k = 0; k < n; ++k) {
+          const double a0 = zi[k], a1 = zi1[k];
+          zi1[k] = s * a0 + c * a1;
+          zi[k] = c * a0 - s * a1;
+        }
+      }
+      if (early) continue;
+      d[l] -= pp;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int u, int w2) { return d[u] > d[w2]; });
+  evals.resize(n);
+  evecs.assign(static_cast<size_t>(n) * n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    evals[c] = d[idx[c]];
+    const double* zc = &Z(idx[c], 0);
+    for (int rrow = 0; rrow < n; ++rrow) evecs[static_cast<size_t>(rrow) * n + c] = zc[rrow];
+  }
+}
+
+void slri_fit_pair(HostPlan& hp, int p, std::vector<double>& G) {
+  const int nmax = 2 * hp.max_np + 1;
+  const int n = 2 * hp.np[p] + 1;
+  const int r_p = hp.rp[p];
+  // eigenvectors of G are the right singular vectors of Lambda_p,
+  // eigenvalues the squared singular values
+  std::vector<double> ev, vec;
+  if (n <= 64)
+    sym_eig(G, n, ev, vec);
+  else
+    sym_eig_tridiag(G, n, ev, vec);
+  for (int i = 0; i < n; ++i) hp.sv[static_cast<size_t>(p) * nmax + i] = std::sqrt(std::max(0.0, ev[i]));
+  double* Vp = &hp.V[static_cast<size_t>(p) * nmax * hp.R];
+  for (int i = 0; i < n; ++i)
+    for (int r = 0; r < r_p; ++r) Vp[static_cast<size_t>(i) * hp.R + r] = vec[static_cast<size_t>(i) * n + r];
+}
+
 void build_slri(HostPlan& hp, int R, int threads) {
   if (R < 1) fail("rank must be >= 1");
   const int nmax = 2 * hp.max_np + 1;
   hp.R = std::min(R, nmax);
   hp.rp.resize(hp.P);
-  const int64_t J = hp.J;
-  hp.U.assign(static_cast<size_t>(hp.P) * J * hp.R, 0.0);
+  for (int p = 0; p < hp.P; ++p) hp.rp[p] = std::min(R, 2 * hp.np[p] + 1);
   hp.V.assign(static_cast<size_t>(hp.P) * nmax * hp.R, 0.0);
   hp.sv.assign(static_cast<size_t>(hp.P) * nmax, 0.0);
+  if (hp.device_fit) return;  // Gram matrices and U come from the device
+  const int64_t J = hp.J;
+  hp.U.assign(static_cast<size_t>(hp.P) * J * hp.R, 0.0);
   parallel_for(hp.P, threads, [&](int p) {
     const int n_p = hp.np[p];
     const int n = 2 * n_p + 1;
-    const int r_p = std::min(R, n);
-    hp.rp[p] = r_p;
+    const int r_p = hp.rp[p];
     const double* x = &hp.x[static_cast<size_t>(p) * J];
     // Gram matrix G = Lambda_p^T Lambda_p accumulated row by row in FP64
     std::vector<double> G(static_cast<size_t>(n) * n, 0.0), lam(n);
@@ -209,15 +351,9 @@ void build_slri(HostPlan& hp, int R, int threads) {
     }
     for (int a = 0; a < n; ++a)
       for (int b = 0; b < a; ++b) G[static_cast<size_t>(a) * n + b] = G[static_cast<size_t>(b) * n + a];
-    // eigenvectors of G are the right singular vectors of Lambda_p,
-    // eigenvalues the squared singular values
-    std::vector<double> ev, vec;
-    sym_eig(G, n, ev, vec);
-    for (int i = 0; i < n; ++i) hp.sv[static_cast<size_t>(p) * nmax + i] = std::sqrt(std::max(0.0, ev[i]));
-    double* Vp = &hp.V[static_cast<size_t>(p) * nmax * hp.R];
-    for (int i = 0; i < n; ++i)
-      for (int r = 0; r < r_p; ++r) Vp[static_cast<size_t>(i) * hp.R + r] = vec[static_cast<size_t>(i) * n + r];
+    slri_fit_pair(hp, p, G);
     // U_p = Lambda_p V_p (= left singular vectors times singular values)
+    const double* Vp = &hp.V[static_cast<size_t>(p) * nmax * hp.R];
     double* Up = &hp.U[static_cast<size_t>(p) * J * hp.R];
     for (int64_t j = 0; j < J; ++j) {
       for (int i = 0; i < n; ++i) lam[i] = sinc_shift(x[j], i - n_p);
@@ -236,6 +372,7 @@ void build_sspi(HostPlan& hp, int Q, int threads) {
   hp.Q = std::min(Q, nmax);
   hp.qp.resize(hp.P);
   for (int p = 0; p < hp.P; ++p) hp.qp[p] = std::min(Q, 2 * hp.np[p] + 1);
+  if (hp.device_fit) return;  // windows and weights come from the device
   const int64_t J = hp.J;
   hp.start.assign(static_cast<size_t>(J) * hp.P, 0);
   hp.w.assign(static_cast<size_t>(J) * hp.P * hp.Q, 0.0);

@@ -7,6 +7,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -47,6 +48,7 @@ struct HostPlan {
   std::vector<double> w;        // [J][P][Q], zero for q >= Q_p
 
   bool fft = false;  // GCC sampling by the iFFT of (46) instead of the direct product of (40)
+  bool device_fit = false;  // SLRI Gram matrices and U, SSPI windows are computed on the device
 
   double macs_per_map = 0;
 };
@@ -62,7 +64,15 @@ void build_geometry(HostPlan& hp, const double* mics, int M, const double* grid,
 void choose_sampling(HostPlan& hp, int mode);
 
 // Per-pair rank-R truncated SVD of Lambda_p (Sec. IV-A, eq. (54) per pair).
+// With device_fit only the ranks and the V / sv storage are set up; the
+// device builds the Gram matrices and U.
 void build_slri(HostPlan& hp, int R, int threads);
+
+// V_p and the singular values of pair p from its Gram matrix
+// G = Lambda_p^T Lambda_p (n x n row-major, destroyed).
+void slri_fit_pair(HostPlan& hp, int p, std::vector<double>& G);
+
+void parallel_for(int n, int threads, const std::function<void(int)>& body);
 
 // Per-(location, pair) Q-tap windows (Sec. IV-A, eq. (55) per row and pair).
 void build_sspi(HostPlan& hp, int Q, int threads);
@@ -80,6 +90,10 @@ double sinc_shift(double x, int n);
 // eigenvector i in column i.
 void sym_eig(std::vector<double>& a, int n, std::vector<double>& evals,
              std::vector<double>& evecs);
+
+// The same by Householder tridiagonalisation and implicit QL (large n).
+void sym_eig_tridiag(std::vector<double>& a, int n, std::vector<double>& evals,
+                     std::vector<double>& evecs);
 
 struct Error {
   int code;

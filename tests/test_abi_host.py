@@ -73,6 +73,37 @@ def test_host_plan_slri_factors_match_oracle_svd():
         assert np.linalg.norm(prod - ref) <= 1e-9 * np.linalg.norm(ref)
 
 
+def test_host_plan_slri_large_lag_counts_match_oracle_svd():
+    """Pairs with up to 499 lags take the tridiagonal + QL eigensolver: the
+    first eight microphones of the 2 m disc array at 48 kHz on a 200-point
+    subgrid (rank-deficient Lambda_p, J < 2 N_p + 1)."""
+    _lib_or_skip()
+    R = 8
+    cfg = scenes.workload("disc32_box200k", grid_stride=10)
+    mics = cfg["mics"][:8]
+    p = native.Plan(mics, cfg["grid"], cfg["fs"], cfg["N"], "slri", R, device=-1)
+    x = o.tdoa_samples(mics, cfg["grid"], cfg["fs"], cfg["c"])
+    Np = o.max_lags(mics, cfg["fs"], cfg["c"], 2)
+    assert (2 * Np + 1).max() > 200
+    fac = o.slri_factors(x, Np, R)
+    P, J = x.shape
+    nmax = 2 * Np.max() + 1
+    U = p.export("slri_u").reshape(P, J, R)
+    V = p.export("slri_v").reshape(P, nmax, R)
+    S = p.export("slri_s").reshape(P, nmax)
+    for q in range(P):
+        n = 2 * Np[q] + 1
+        Uo, Vo, so = fac[q]
+        np.testing.assert_allclose(S[q, :R], so[:R], rtol=1e-9)
+        # the remaining singular values come from the squared spectrum of
+        # the Gram matrix: absolute accuracy ~ sqrt(eps) sigma_1
+        k = min(n, J)
+        np.testing.assert_allclose(S[q, :k], so[:k], atol=1e-6 * so[0])
+        prod = U[q] @ V[q, :n].T
+        ref = Uo @ Vo.T
+        assert np.linalg.norm(prod - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
 def test_host_plan_sspi_windows_match_oracle_selection():
     _lib_or_skip()
     Q = 4
