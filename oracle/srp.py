@@ -34,7 +34,10 @@ Parity status: every function below is pinned by the CPU tests in
 ``tests/test_oracle_pins.py`` against values printed in the paper (Table 1,
 Fig. 12, the measured-array layout), closed forms (integer-delay GCC, the
 Dirichlet-kernel map of a single pure-delay source, the exact periodic
-interpolator) and brute force (delay-and-sum output power).  The
+interpolator) and brute force (delay-and-sum output power).
+``slri_factors_gram`` (the same truncation through the Gram matrix, for
+very tall Lambda_p) is pinned against ``slri_factors``, which the
+Eckart-Young and full-rank checks pin.  The
 far-field TDOA (3) and the LR-SRP form are pinned only by the complexity
 values of Fig. 12 and by construction checks; they are off the hot path.
 """
@@ -45,7 +48,7 @@ __all__ = [
     "pairs", "tdoa_samples", "tdoa_samples_far_field", "max_lags",
     "mean_lags", "phat", "steering", "fd_map", "two_sided",
     "gcc_samples_ifft", "gcc_samples_direct", "interp_matrix", "si_map",
-    "td_map", "slri_factors", "slri_map", "slri_global_factors",
+    "td_map", "slri_factors", "slri_factors_gram", "slri_map", "slri_global_factors",
     "slri_global_map", "sspi_select", "sspi_map", "sspi_global_select",
     "sspi_global_map", "dsb_power_map", "argmax_map", "rel_error",
     "eps_z_db", "eps_h_db", "complexity", "periodic_interp_map",
@@ -280,6 +283,32 @@ def slri_factors(x, Np, R):
         U, s, Vt = np.linalg.svd(lam, full_matrices=False)
         r = min(int(R), 2 * int(n_p) + 1)
         out.append((U[:, :r] * s[:r], Vt[:r].T.copy(), s))
+    return out
+
+
+def slri_factors_gram(x, Np, R, cols, chunk=16384):
+    """The same per-pair rank-R_p truncation computed through the Gram
+    matrix: the right singular vectors of Lambda_p are the eigenvectors of
+    Lambda_p^T Lambda_p and its eigenvalues the squared singular values (the
+    SVD of (54) written as an eigenproblem), so V_p needs only the
+    (2N_p+1)^2 Gram matrix, accumulated over candidates in chunks.  U_p =
+    Lambda_p V_p is returned for the candidates `cols` only.  For problems
+    whose Lambda_p is too tall to decompose directly."""
+    out = []
+    J = x.shape[1]
+    for p, n_p in enumerate(Np):
+        n = 2 * int(n_p) + 1
+        G = np.zeros((n, n))
+        for j0 in range(0, J, chunk):
+            lam = interp_matrix(x[p, j0:j0 + chunk], n_p)
+            G += lam.T @ lam
+        w, v = np.linalg.eigh(G)
+        order = np.argsort(w)[::-1]
+        w, v = w[order], v[:, order]
+        r = min(int(R), n)
+        V = v[:, :r]
+        U = interp_matrix(x[p, cols], n_p) @ V
+        out.append((U, V, np.sqrt(np.maximum(w, 0.0))))
     return out
 
 

@@ -246,11 +246,13 @@ void sym_eig_tridiag(std::vector<double>& a, int n, std::vector<double>& evals,
   // implicit QL with shifts from the trailing 2 x 2 block: e[i] couples
   // d[i] and d[i + 1]; a chase from m - 1 down to l applies plane rotations
   // to rows i, i + 1 of Z^T.  An off-diagonal counts as negligible against
-  // the largest |d| + |e| met so far, so blocks of (near-)zero eigenvalues
-  // of a rank-deficient Gram matrix deflate too.
+  // the norm of the whole tridiagonal matrix, so blocks of (near-)zero
+  // eigenvalues of a rank-deficient Gram matrix deflate too; the small
+  // eigenvalues are then accurate to eps |T|, the accuracy the Gram route
+  // gives them anyway.
   double tst = 0.0;
+  for (int i = 0; i < n; ++i) tst = std::max(tst, std::fabs(d[i]) + std::fabs(e[i]) + (i ? std::fabs(e[i - 1]) : 0.0));
   for (int l = 0; l < n; ++l) {
-    tst = std::max(tst, std::fabs(d[l]) + std::fabs(e[l]));
     for (int iter = 0;; ++iter) {
       int m = l;
       for (; m + 1 < n; ++m) {

@@ -104,6 +104,30 @@ def test_host_plan_slri_large_lag_counts_match_oracle_svd():
         assert np.linalg.norm(prod - ref) <= 1e-9 * np.linalg.norm(ref)
 
 
+def test_host_plan_slri_rank_deficient_grams_all_converge():
+    """All 496 pairs of the 32-microphone disc array on a 200-candidate
+    subgrid: Gram matrices of rank 200 with up to 499 lags, hundreds of
+    (near-)zero eigenvalues.  Pairs whose QL iteration once failed to
+    deflate are checked against numpy's SVD."""
+    _lib_or_skip()
+    R = 8
+    cfg = scenes.workload("disc32_box200k", grid_stride=10)
+    p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], "slri", R, device=-1)
+    x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+    P, J = x.shape
+    nmax = 2 * Np.max() + 1
+    U = p.export("slri_u").reshape(P, J, R)
+    V = p.export("slri_v").reshape(P, nmax, R)
+    for q in (0, 381, 434, 456, 459, P - 1):
+        n = 2 * Np[q] + 1
+        lam = o.interp_matrix(x[q], Np[q])
+        Uo, so, Vt = np.linalg.svd(lam, full_matrices=False)
+        ref = (Uo[:, :R] * so[:R]) @ Vt[:R]
+        prod = U[q] @ V[q, :n].T
+        assert np.linalg.norm(prod - ref) <= 1e-9 * np.linalg.norm(ref), q
+
+
 def test_host_plan_sspi_windows_match_oracle_selection():
     _lib_or_skip()
     Q = 4

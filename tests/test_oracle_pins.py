@@ -334,6 +334,27 @@ def test_slri_full_rank_is_si_and_truncation_error_is_eckart_young():
     assert prev is not None
 
 
+def test_slri_gram_route_equals_svd_route():
+    """The Gram-matrix route (eigenvectors of Lambda_p^T Lambda_p, summed over
+    candidate chunks) gives the truncated SVD's rank-R products and leading
+    singular values; on a wide-aperture array with up to ~300 lags per pair
+    and with chunks that do not divide J."""
+    rng = np.random.default_rng(12)
+    mics = rng.uniform([-1, -1, 0], [1, 1, 0], (4, 3))
+    grid = rng.uniform([-3, -3, -2.0], [3, 3, -0.5], (1500, 3))
+    fs, c = 48000.0, 343.0
+    x, Np = o.tdoa_samples(mics, grid, fs, c), o.max_lags(mics, fs, c, 2)
+    assert (2 * Np + 1).max() > 200
+    R = 6
+    cols = np.sort(rng.choice(x.shape[1], 200, replace=False))
+    ref = o.slri_factors(x, Np, R)
+    got = o.slri_factors_gram(x, Np, R, cols, chunk=256)
+    for (Ur, Vr, sr), (Ug, Vg, sg) in zip(ref, got):
+        np.testing.assert_allclose(sg[:R], sr[:R], rtol=1e-9)
+        a, b = Ur[cols] @ Vr.T, Ug @ Vg.T
+        assert np.linalg.norm(a - b) <= 1e-8 * np.linalg.norm(a)
+
+
 def test_slri_global_full_rank_is_si():
     rng = np.random.default_rng(10)
     K = 64
