@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--forms", default="fd,slri,sspi")
+    ap.add_argument("--no-disc32", action="store_true", help="skip the large-aperture leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
     return ap.parse_args()
@@ -135,6 +136,51 @@ def cpu_baseline(cfg, Y, forms):
             "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
+def bench_disc32(steps):
+    """Large-aperture leg: disc32_box200k (M = 32, 496 pairs, up to 499 lags,
+    J = 200,000, fs 48 kHz, N = 2048, L = 256), SLRI R = 8 and SSPI Q = 4
+    with BF16 operands; maps at the recommended pitch, frames resident."""
+    import torch
+    from paper_2306_08514_amd import native, scenes
+    t0 = time.time()
+    cfg = scenes.workload("disc32_box200k")
+    Y = scenes.make_frames(cfg)
+    Yt = torch.from_numpy(Y).cuda()
+    L, J = Y.shape[0], cfg["grid"].shape[0]
+    log(f"disc32 frames in {time.time() - t0:.1f} s")
+    out = {"workload": f"disc32_box200k: M=32 disc 2 m aperture, J={J}, fs=48 kHz, N=2048, L={L}", "forms": {}}
+    for form, rq, dt in (("slri", 8, "bf16"), ("sspi", 4, "bf16")):
+        t1 = time.time()
+        p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], form, rq, dtype=dt, c=cfg["c"])
+        plan_s = time.time() - t1
+        z = p.empty_maps(L)
+        ws = torch.empty(p.workspace_size(L), dtype=torch.uint8, device="cuda")
+        for _ in range(2):
+            p.compute(Yt, maps=z, workspace=ws)
+        torch.cuda.synchronize()
+        p.profile(True)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for e0, e1 in evs:
+            e0.record()
+            p.compute(Yt, maps=z, workspace=ws)
+            e1.record()
+        torch.cuda.synchronize()
+        prof = p.profile_collect()
+        p.profile(False)
+        lat = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+        info = p.info()
+        out["forms"][form] = {"operands": dt, "rank_or_q": rq, "maps_per_s": L / (lat.mean() / 1e3),
+                              "ms_per_call": float(lat.mean()), "p50_ms": float(np.percentile(lat, 50)),
+                              "p99_ms": float(np.percentile(lat, 99)), "plan_seconds": plan_s,
+                              "resident_gib": info["device_bytes"] / 2 ** 30,
+                              "sampling": "ifft" if info["sampling_fft"] else "direct",
+                              "kernels_ms_per_call": {k: v[0] / v[1] for k, v in prof.items()}}
+        log(f"disc32 {form}/{dt}: plan {plan_s:.1f} s, {lat.mean():.3f} ms per {L} maps")
+        del p, z, ws
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -171,6 +217,7 @@ def main():
         log(f"plan {form}/{dt} built in {plan_s[form]:.2f} s, resident "
             f"{plans[form].info()['device_bytes'] / 2**30:.2f} GiB")
     info = plans[forms[0][0]].info()
+    map_pitch = plans[forms[0][0]].map_pitch
     P, K = info["P"], info["K"]
     PN = info["PN"]
 
@@ -278,6 +325,12 @@ def main():
                     "unit": dom["unit"], "frac": dom["frac"], "traffic": dom["traffic"],
                     "kernel": dom_name, "avg_ms": dom["avg_ms"]}
 
+    disc32 = None
+    if not args.no_disc32:
+        del plans, outs, wss
+        torch.cuda.empty_cache()
+        disc32 = bench_disc32(max(5, min(args.steps, 20)))
+
     cpu = None
     if not args.no_cpu_baseline:
         t2 = time.time()
@@ -300,12 +353,13 @@ def main():
                                + ", ".join(f"{f}({dt}{'' if not rq else ', ' + ('R' if f == 'slri' else 'Q') + '=' + str(rq)})"
                                            for f, rq, dt in forms),
                    "maps_per_step": maps_per_step, "accumulate": "f32",
-                   "map_row_pitch": plans[forms[0][0]].map_pitch},
+                   "map_row_pitch": map_pitch},
         "forms": per_form,
         "kernels": rl,
         "accuracy": accuracy,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "large_aperture": disc32,
     }
     print(json.dumps(rec), flush=True)
 

@@ -882,6 +882,7 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
 // L2 across all frame tiles.
 
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+constexpr int SSPI_MAX_CHUNK = 512;  // pairs per staged chunk of the SSPI gather
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename TW>
@@ -926,105 +927,159 @@ template <typename TW, int Q, int FT, bool PAIRS>
 __global__ __launch_bounds__(256) void sspi_gather(const float* __restrict__ xiT, int64_t ldxi,
                                                    int PN, const int32_t* __restrict__ start,
                                                    const TW* __restrict__ w, int Qs,
-                                                   const int32_t* __restrict__ chunk_p0,
-                                                   int nchunks, const int32_t* __restrict__ off,
-                                                   int P, int64_t J, int L, int nftiles,
+                                                   const int2* __restrict__ win, int cap, int P,
+                                                   int64_t J, int L, int nftiles,
                                                    float* __restrict__ z, int64_t ldz) {
   constexpr int STRIDE = FT + 4;  // LDS row stride in 32-bit words
   constexpr int QP = PAIRS ? (Q + 1) / 2 : Q;
+  constexpr int C4 = FT / 4;      // 16-byte pieces per staged row
   extern __shared__ __attribute__((aligned(16))) uint32_t xs[];
+  __shared__ int pbase[SSPI_MAX_CHUNK + 1];
   const int nj = static_cast<int>((J + 255) / 256);
   int jt, ft;
   if (!xcd_tile(nj, nftiles, jt, ft)) return;
   const int tid = threadIdx.x;
   const int64_t j = static_cast<int64_t>(jt) * 256 + tid;
   const bool live = j < J;
-  const int64_t jc = live ? j : J - 1;  // dead lanes read a valid record
+  const int64_t jc = live ? j : J - 1;  // dead lanes read a valid record of this tile
   const int64_t l0 = static_cast<int64_t>(ft) * FT;
   constexpr int WORDS = (Q * static_cast<int>(sizeof(TW)) + 3) / 4;
+  const int2* wt = win + static_cast<int64_t>(jt) * P;  // (first row, rows) per pair
 
   float acc[FT];
 #pragma unroll
   for (int f = 0; f < FT; ++f) acc[f] = 0.0f;
 
-  for (int ch = 0; ch < nchunks; ++ch) {
-    const int p0 = chunk_p0[ch], p1 = chunk_p0[ch + 1];
-    const int r0 = off[p0];
-    const int rows = (p1 < P ? off[p1] : PN) + Q - r0;  // taps may run Q-1 past
-    __syncthreads();
-    for (int e = tid; e < rows * (FT / 4); e += 256) {
-      const int row = e / (FT / 4), c4 = e % (FT / 4);
-      const int n = r0 + row;
-      const float* src = xiT + static_cast<int64_t>(n) * ldxi + l0 + 4 * c4;
-      f32x4 a = {0.f, 0.f, 0.f, 0.f};
-      if (n < PN) a = *reinterpret_cast<const f32x4*>(src);
-      u32x4 v;
-      if (PAIRS) {
-        f32x4 b = {0.f, 0.f, 0.f, 0.f};
-        if (n + 1 < PN) b = *reinterpret_cast<const f32x4*>(src + ldxi);
-        v.x = pack_h2(a.x, b.x);
-        v.y = pack_h2(a.y, b.y);
-        v.z = pack_h2(a.z, b.z);
-        v.w = pack_h2(a.w, b.w);
-      } else {
-        v = __builtin_bit_cast(u32x4, a);
-      }
-      *reinterpret_cast<u32x4*>(xs + row * STRIDE + 4 * c4) = v;
+  for (int p0 = 0; p0 < P;) {
+    // chunk: consecutive pairs whose windows fit `cap` rows (one always fits)
+    int rows = 0, p1 = p0;
+    while (p1 < P && p1 - p0 < SSPI_MAX_CHUNK) {
+      const int c = wt[p1].y;
+      if (p1 > p0 && rows + c > cap) break;
+      rows += c;
+      ++p1;
     }
     __syncthreads();
-    // the next pair's start and weights are loaded one iteration ahead
-    int s_next = 0;
-    uint32_t w_next[WORDS];
-    auto fetch = [&](int p) {
-      const int64_t rec = static_cast<int64_t>(p) * J + jc;
-      s_next = start[rec];
-      const uint32_t* wsrc = reinterpret_cast<const uint32_t*>(w + rec * Qs);
+    if (tid == 0) {
+      int b = 0;
+      for (int q = p0; q < p1; ++q) {
+        pbase[q - p0] = b;
+        b += wt[q].y;
+      }
+      pbase[p1 - p0] = b;
+    }
+    __syncthreads();
+    // stage the windows, four 16-byte pieces in flight per thread; a row's
+    // pair is found by bisection over the window offsets
+    const int items = rows * C4;
+    for (int e0 = 0; e0 < items; e0 += 4 * 256) {
+      f32x4 a[4], bb[4];
+      int dst[4];
 #pragma unroll
-      for (int i = 0; i < WORDS; ++i) w_next[i] = wsrc[i];
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * 256 + tid;
+        a[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        bb[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        dst[u] = -1;
+        if (e < items) {
+          const int row = e / C4, c4 = e % C4;
+          int lo = 0, hi = p1 - p0;  // pbase[lo] <= row < pbase[hi]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pbase[mid] <= row) lo = mid; else hi = mid;
+          }
+          const int n = wt[p0 + lo].x + (row - pbase[lo]);
+          const float* src = xiT + static_cast<int64_t>(n) * ldxi + l0 + 4 * c4;
+          if (n < PN) a[u] = *reinterpret_cast<const f32x4*>(src);
+          if (PAIRS && n + 1 < PN) bb[u] = *reinterpret_cast<const f32x4*>(src + ldxi);
+          dst[u] = row * STRIDE + 4 * c4;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (dst[u] < 0) continue;
+        u32x4 v;
+        if (PAIRS) {
+          v.x = pack_h2(a[u].x, bb[u].x);
+          v.y = pack_h2(a[u].y, bb[u].y);
+          v.z = pack_h2(a[u].z, bb[u].z);
+          v.w = pack_h2(a[u].w, bb[u].w);
+        } else {
+          v = __builtin_bit_cast(u32x4, a[u]);
+        }
+        *reinterpret_cast<u32x4*>(xs + dst[u]) = v;
+      }
+    }
+    __syncthreads();
+    // starts and weights of the next group of GP pairs are loaded while the
+    // current group is applied
+    constexpr int GP = 4;
+    int s_cur[GP], s_nxt[GP];
+    uint32_t w_cur[GP][WORDS], w_nxt[GP][WORDS];
+    auto fetch = [&](int pg, int (&sv)[GP], uint32_t (&wv)[GP][WORDS]) {
+#pragma unroll
+      for (int u = 0; u < GP; ++u) {
+        const int p = min(pg + u, p1 - 1);  // past the chunk: a valid record, not applied
+        const int64_t rec = static_cast<int64_t>(p) * J + jc;
+        sv[u] = start[rec];
+        const uint32_t* wsrc = reinterpret_cast<const uint32_t*>(w + rec * Qs);
+#pragma unroll
+        for (int i = 0; i < WORDS; ++i) wv[u][i] = wsrc[i];
+      }
     };
-    fetch(p0);
-    for (int p = p0; p < p1; ++p) {
-      const int s = s_next - r0;
-      uint32_t wv[WORDS];
+    fetch(p0, s_cur, w_cur);
+    for (int pg = p0; pg < p1; pg += GP) {
+      if (pg + GP < p1) fetch(pg + GP, s_nxt, w_nxt);
 #pragma unroll
-      for (int i = 0; i < WORDS; ++i) wv[i] = w_next[i];
-      if (p + 1 < p1) fetch(p + 1);
-      const uint32_t* rowp = xs + s * STRIDE;
-      if (PAIRS) {
+      for (int u = 0; u < GP; ++u) {
+        const int p = pg + u;
+        if (p >= p1) break;  // uniform
+        const int s = s_cur[u] - wt[p].x + pbase[p - p0];  // LDS row of tap 0
+        const uint32_t* wv = w_cur[u];
+        const uint32_t* rowp = xs + s * STRIDE;
+        if (PAIRS) {
 #pragma unroll
-        for (int q2 = 0; q2 < QP; ++q2) {
-          const float wa = tap<TW>(wv, 2 * q2);
-          const float wb = 2 * q2 + 1 < Q ? tap<TW>(wv, 2 * q2 + 1) : 0.0f;
-          const h2 wp = __builtin_bit_cast(h2, pack_h2(wa, wb));
-          const uint32_t* r = rowp + 2 * q2 * STRIDE;
+          for (int q2 = 0; q2 < QP; ++q2) {
+            const float wa = tap<TW>(wv, 2 * q2);
+            const float wb = 2 * q2 + 1 < Q ? tap<TW>(wv, 2 * q2 + 1) : 0.0f;
+            const h2 wp = __builtin_bit_cast(h2, pack_h2(wa, wb));
+            const uint32_t* r = rowp + 2 * q2 * STRIDE;
 #pragma unroll
-          for (int f4 = 0; f4 < FT / 4; ++f4) {
-            const u32x4 e4 = *reinterpret_cast<const u32x4*>(r + 4 * f4);
-            // elements are copied to scalars before the bit cast: hipcc 7.2
-            // lowers __builtin_bit_cast of a vector swizzle (e4.y) to e4.x
+            for (int f4 = 0; f4 < FT / 4; ++f4) {
+              const u32x4 e4 = *reinterpret_cast<const u32x4*>(r + 4 * f4);
+              // elements are copied to scalars before the bit cast: hipcc 7.2
+              // lowers __builtin_bit_cast of a vector swizzle (e4.y) to e4.x
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const uint32_t word = e4[i];
-              acc[4 * f4 + i] = __builtin_amdgcn_fdot2(wp, __builtin_bit_cast(h2, word), acc[4 * f4 + i], false);
+              for (int i = 0; i < 4; ++i) {
+                const uint32_t word = e4[i];
+                acc[4 * f4 + i] = __builtin_amdgcn_fdot2(wp, __builtin_bit_cast(h2, word), acc[4 * f4 + i], false);
+              }
+            }
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const float wq = tap<TW>(wv, q);
+            const uint32_t* r = rowp + q * STRIDE;
+#pragma unroll
+            for (int f4 = 0; f4 < FT / 4; ++f4) {
+              const f32x4 e4 = *reinterpret_cast<const f32x4*>(r + 4 * f4);
+              acc[4 * f4 + 0] = __builtin_fmaf(wq, e4.x, acc[4 * f4 + 0]);
+              acc[4 * f4 + 1] = __builtin_fmaf(wq, e4.y, acc[4 * f4 + 1]);
+              acc[4 * f4 + 2] = __builtin_fmaf(wq, e4.z, acc[4 * f4 + 2]);
+              acc[4 * f4 + 3] = __builtin_fmaf(wq, e4.w, acc[4 * f4 + 3]);
             }
           }
         }
-      } else {
+      }
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const float wq = tap<TW>(wv, q);
-          const uint32_t* r = rowp + q * STRIDE;
+      for (int u = 0; u < GP; ++u) {
+        s_cur[u] = s_nxt[u];
 #pragma unroll
-          for (int f4 = 0; f4 < FT / 4; ++f4) {
-            const f32x4 e4 = *reinterpret_cast<const f32x4*>(r + 4 * f4);
-            acc[4 * f4 + 0] = __builtin_fmaf(wq, e4.x, acc[4 * f4 + 0]);
-            acc[4 * f4 + 1] = __builtin_fmaf(wq, e4.y, acc[4 * f4 + 1]);
-            acc[4 * f4 + 2] = __builtin_fmaf(wq, e4.z, acc[4 * f4 + 2]);
-            acc[4 * f4 + 3] = __builtin_fmaf(wq, e4.w, acc[4 * f4 + 3]);
-          }
-        }
+        for (int i = 0; i < WORDS; ++i) w_cur[u][i] = w_nxt[u][i];
       }
     }
+    p0 = p1;
   }
   if (!live) return;
 #pragma unroll
@@ -1173,26 +1228,46 @@ __global__ void scale_pairs(float* __restrict__ Us, int64_t rows, int Kc, int R,
 // clamped to [-N_p, N_p], start = clamp(ceil(x - Q_p / 2), -N_p,
 // N_p - Q_p + 1), weights sinc(x - n) in FP64 rounded once to FP32 and then
 // to the weight type; records [P][J] (absolute stacked lag) and [P][J][Qs].
+// A block covers the 256 candidates of one gather tile and one pair and also
+// writes the tile's lag window win[tile][p] = (first row, rows): every row a
+// candidate of the tile reads.
 template <typename TW>
-__global__ void sspi_windows(const double* __restrict__ x, int64_t J, const int32_t* __restrict__ np,
-                             const int32_t* __restrict__ off, int Q, int Qs, int32_t* __restrict__ start,
-                             TW* __restrict__ w) {
+__global__ __launch_bounds__(256) void sspi_windows(const double* __restrict__ x, int64_t J,
+                                                    const int32_t* __restrict__ np, const int32_t* __restrict__ off,
+                                                    int Q, int Qs, int P, int32_t* __restrict__ start,
+                                                    TW* __restrict__ w, int2* __restrict__ win) {
+  __shared__ int rlo[256], rhi[256];
   const int p = blockIdx.y;
   const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (j >= J) return;
   const int npp = np[p];
   const int q = min(Q, 2 * npp + 1);
-  const double xv = x[static_cast<int64_t>(p) * J + j];
-  double s = ceil(xv - 0.5 * q);
-  s = fmin(fmax(s, static_cast<double>(-npp)), static_cast<double>(npp - q + 1));
-  const int si = static_cast<int>(s);
-  const int64_t rec = static_cast<int64_t>(p) * J + j;
-  start[rec] = off[p] + si + npp;
-  const double k0 = rint(xv), sr = sin(M_PI * (xv - k0));
-  for (int t2 = 0; t2 < Qs; ++t2) {
-    const float v = t2 < q ? static_cast<float>(sinc_red(xv, k0, sr, si + t2)) : 0.0f;
-    w[rec * Qs + t2] = cvt<TW>(v);
+  int sabs_lo = 0x7fffffff, sabs_hi = -0x7fffffff;
+  if (j < J) {
+    const double xv = x[static_cast<int64_t>(p) * J + j];
+    double s = ceil(xv - 0.5 * q);
+    s = fmin(fmax(s, static_cast<double>(-npp)), static_cast<double>(npp - q + 1));
+    const int si = static_cast<int>(s);
+    const int64_t rec = static_cast<int64_t>(p) * J + j;
+    const int sabs = off[p] + si + npp;
+    start[rec] = sabs;
+    sabs_lo = sabs_hi = sabs;
+    const double k0 = rint(xv), sr = sin(M_PI * (xv - k0));
+    for (int t2 = 0; t2 < Qs; ++t2) {
+      const float v = t2 < q ? static_cast<float>(sinc_red(xv, k0, sr, si + t2)) : 0.0f;
+      w[rec * Qs + t2] = cvt<TW>(v);
+    }
   }
+  rlo[threadIdx.x] = sabs_lo;
+  rhi[threadIdx.x] = sabs_hi;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      rlo[threadIdx.x] = min(rlo[threadIdx.x], rlo[threadIdx.x + h]);
+      rhi[threadIdx.x] = max(rhi[threadIdx.x], rhi[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) win[static_cast<int64_t>(blockIdx.x) * P + p] = make_int2(rlo[0], rhi[0] + q - rlo[0]);
 }
 
 // Steering operand of conv. FD-SRP: H[j][p Kp + 2 (k-1) + {0,1}] =
@@ -1299,7 +1374,6 @@ constexpr int TALL_BX = 256, TALL_BW = 128, TALL_WGX = 2, TALL_BKB = 128; // SLR
 constexpr int TALL_STEP_BYTES(int dtype) { return dtype == SRP_FP8_E4M3 ? 64 : 32; }  // Mfma<T>::STEP
 constexpr int TALL_CW = 8;  // compute waves per block of the tall kernel (256 candidates)
 constexpr int SSPI_FT = 32;                       // frames per SSPI block
-constexpr int SSPI_ROWS = 32 * 1024 / ((SSPI_FT + 4) * 4);  // lag rows per LDS chunk (32 KB)
 
 }  // namespace
 
@@ -1514,10 +1588,12 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     upload(dx.p, hp.x);
     dp.d_start = static_cast<int32_t*>(A.get(static_cast<size_t>(hp.J) * P * 4));
     dp.d_w = A.get(static_cast<size_t>(hp.J) * P * Qs * es);
-    const dim3 gw(static_cast<unsigned>((hp.J + 255) / 256), static_cast<unsigned>(P));
+    const int njt = static_cast<int>((hp.J + 255) / 256);
+    dp.d_win = static_cast<int2*>(A.get(static_cast<size_t>(njt) * P * sizeof(int2)));
+    const dim3 gw(static_cast<unsigned>(njt), static_cast<unsigned>(P));
 #define SRP_WIN(TW)                                                                                           \
   hipLaunchKernelGGL(sspi_windows<TW>, gw, dim3(256), 0, 0, dx.as<double>(), hp.J, dp.d_np, dp.d_off, Q, Qs,   \
-                     dp.d_start, static_cast<TW*>(dp.d_w))
+                     P, dp.d_start, static_cast<TW*>(dp.d_w), dp.d_win)
     switch (hp.dtype) {
       case SRP_F32: SRP_WIN(float); break;
       case SRP_BF16: SRP_WIN(__bf16); break;
@@ -1526,27 +1602,15 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     }
 #undef SRP_WIN
     check_launch("sspi_windows");
-    HIP_OK(hipDeviceSynchronize());
-    // pair chunks whose lags (plus Q - 1 spill rows) fit the LDS tile
-    dp.chunk_p0.clear();
-    int p = 0;
-    while (p < P) {
-      dp.chunk_p0.push_back(p);
-      int rows = 0;
-      int q = p;
-      while (q < P && (rows + 2 * hp.np[q] + 1 + Q <= SSPI_ROWS || q == p)) {
-        rows += 2 * hp.np[q] + 1;
-        ++q;
-      }
-      // one pair alone must fit the 160 KB of LDS
-      if ((rows + Q) * (SSPI_FT + 4) * 4 > 160 * 1024)
-        throw Error{SRP_E_UNSUPPORTED, "a pair has too many lags for the SSPI tile"};
-      p = q;
-    }
-    dp.chunk_p0.push_back(P);
-    dp.nchunks = static_cast<int>(dp.chunk_p0.size()) - 1;
-    dp.d_chunk_p0 = static_cast<int32_t*>(A.get(dp.chunk_p0.size() * 4));
-    upload(dp.d_chunk_p0, dp.chunk_p0);
+    // LDS rows per staged chunk: 32 KB worth (five blocks per CU), or the
+    // widest window
+    std::vector<int2> wins(static_cast<size_t>(njt) * P);
+    HIP_OK(hipMemcpy(wins.data(), dp.d_win, wins.size() * sizeof(int2), hipMemcpyDeviceToHost));
+    int widest = 0;
+    for (const int2& v : wins) widest = std::max(widest, v.y);
+    dp.sspi_cap = std::max(widest, 32 * 1024 / ((SSPI_FT + 4) * 4));
+    if (static_cast<size_t>(dp.sspi_cap) * (SSPI_FT + 4) * 4 > 150 * 1024)
+      throw Error{SRP_E_UNSUPPORTED, "a candidate tile spans too many lags of one pair for the SSPI tile"};
   }
 }
 
@@ -1576,9 +1640,8 @@ void device_free(DevicePlan& dp) {
     (void)hipEventDestroy(sp.stop);
   }
   for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
-  void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_tasks,
-                  dp.d_U, dp.d_V, dp.d_gscale, dp.d_start, dp.d_w, dp.d_chunk_p0,
-                  dp.ws};
+  void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_tasks, dp.d_tw, dp.d_w2,
+                  dp.d_U, dp.d_V, dp.d_gscale, dp.d_start, dp.d_w, dp.d_win, dp.ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   dp = DevicePlan{};
@@ -1820,25 +1883,18 @@ void launch_sspi_q(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t
   constexpr bool PAIRS = !std::is_same<TW, float>::value;
   const int es = static_cast<int>(sizeof(TW));
   const int Qs = static_cast<int>(round_up(Q * es, 4) / es);
-  int maxrows = 0;
-  for (int c = 0; c < dp.nchunks; ++c) {
-    const int p0 = dp.chunk_p0[c], p1 = dp.chunk_p0[c + 1];
-    const int r1 = p1 < hp.P ? hp.off[p1] : hp.PN;
-    maxrows = std::max(maxrows, r1 + Q - hp.off[p0]);
-  }
-  const size_t lds = static_cast<size_t>(maxrows) * (SSPI_FT + 4) * 4;
+  const size_t lds = static_cast<size_t>(dp.sspi_cap) * (SSPI_FT + 4) * 4;
   auto kern = &sspi_gather<TW, Q, SSPI_FT, PAIRS>;
-  if (lds > 65536)
+  if (lds > 60 * 1024)
     HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                static_cast<int>(lds)));
   const int nj = static_cast<int>((hp.J + 255) / 256);
   const int nf = static_cast<int>((Lc + SSPI_FT - 1) / SSPI_FT);
   const int blocks = static_cast<int>(round_up(static_cast<int64_t>(nj) * nf, 8));
-  (void)Lpad;
   TRACED(dp, "sspi_gather", st,
          hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, xiT, Lpad, hp.PN, dp.d_start,
-                            static_cast<const TW*>(dp.d_w), Qs, dp.d_chunk_p0, dp.nchunks, dp.d_off, hp.P,
-                            hp.J, static_cast<int>(Lc), nf, z, ldz));
+                            static_cast<const TW*>(dp.d_w), Qs, dp.d_win, dp.sspi_cap, hp.P, hp.J,
+                            static_cast<int>(Lc), nf, z, ldz));
 }
 
 template <typename TW>

@@ -49,9 +49,8 @@ struct DevicePlan {
   // SSPI
   int32_t* d_start = nullptr;  // [J][P] absolute stacked lag index of tap 0
   void* d_w = nullptr;         // [J][P][Q] in dtype (f32, bf16, f16 or fp8)
-  std::vector<int32_t> chunk_p0;  // pair ranges whose lags fit one LDS tile
-  int32_t* d_chunk_p0 = nullptr;  // [nchunks + 1]
-  int nchunks = 0;
+  int2* d_win = nullptr;          // [J / 256 tiles][P] (first row, rows) lag window of a tile
+  int sspi_cap = 0;               // LDS rows per staged chunk of the gather
   // per-kernel timing (see srp_profile_enable)
   struct Span {
     const char* name;
