@@ -90,6 +90,12 @@ typedef struct {
                             operations by (49), 1 = the direct product
                             2 Re[S_p psi_p] of (40), 2 = the iFFT of (46)
                             (N must be a power of two, at most 4096) */
+  int fd_steering;       /* steering operand of conv. FD-SRP (eq. (22)):
+                            0 = resident when it takes at most 16 GiB and
+                            fits the budget, else generated; 1 = resident
+                            J x 2P(K-1) matrix; 2 = generated on the fly
+                            from the FP64 TDOAs inside the product (not for
+                            SRP_F64) */
 } srp_opts;
 
 typedef struct {
@@ -111,6 +117,7 @@ typedef struct {
                             whole cache lines */
   int sampling_fft;      /* 1 if SLRI/SSPI sample the GCCs by the iFFT of
                             (46), 0 for the direct product of (40) */
+  int fd_generated;      /* 1 if the FD steering is generated on the fly */
 } srp_plan_info;
 
 /* Fills *opts with the defaults listed above. */
@@ -182,8 +189,11 @@ srp_status srp_plan_info_get(srp_plan_t plan, srp_plan_info* info);
  *          "slri_s"   double [P][2 max_np + 1] singular values, descending
  *          "sspi_start" int32 [J][P]  first lag s of the window (-N_p..)
  *          "sspi_w"   double [J][P][Q] weights sinc(x - s - q)
- * bytes: size of dst; *needed receives the required size.  dst may be NULL
- * to query the size.  SRP_E_INVALID if the plan has no such data. */
+ * "tdoa", "slri_u", "sspi_start" and "sspi_w" are kept only by host-only
+ * plans (device = -1): a device plan fits these on the device and frees the
+ * host copies.  bytes: size of dst; *needed receives the required size.  dst
+ * may be NULL to query the size.  SRP_E_INVALID if the plan has no such
+ * data. */
 srp_status srp_plan_export(srp_plan_t plan, const char* what, void* dst,
                            size_t bytes, size_t* needed);
 

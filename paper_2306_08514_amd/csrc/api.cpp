@@ -91,6 +91,7 @@ void srp_default_opts(srp_opts* o) {
   o->frame_tile = 1024;
   o->hbm_budget = 0;
   o->sampling = 0;
+  o->fd_steering = 0;
 }
 
 const char* srp_last_error(void) { return g_err.c_str(); }
@@ -109,6 +110,7 @@ srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J, do
   if (variant != SRP_FD && rank_or_q < 1) return fail(SRP_E_INVALID, "rank_or_q must be >= 1");
   if (o.frame_tile < 1) return fail(SRP_E_INVALID, "frame_tile must be >= 1");
   if (o.sampling < 0 || o.sampling > 2) return fail(SRP_E_INVALID, "sampling must be 0, 1 or 2");
+  if (o.fd_steering < 0 || o.fd_steering > 2) return fail(SRP_E_INVALID, "fd_steering must be 0, 1 or 2");
   if (variant == SRP_SLRI && rank_or_q > 32) return fail(SRP_E_UNSUPPORTED, "SLRI rank per pair above 32 is not built");
   if (variant == SRP_SSPI && rank_or_q > 8) return fail(SRP_E_UNSUPPORTED, "SSPI with Q above 8 is not built");
   SRP_GUARD({
@@ -122,6 +124,7 @@ srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J, do
     srp::build_geometry(hp, mics, M, grid, J, fs, N, o.c, o.n_aux);
     srp::choose_sampling(hp, o.sampling);
     hp.device_fit = o.device >= 0;
+    hp.fd_steering = o.fd_steering;
     if (variant == SRP_SLRI) srp::build_slri(hp, rank_or_q, plan_threads());
     if (variant == SRP_SSPI) srp::build_sspi(hp, rank_or_q, plan_threads());
     srp::count_macs(hp);
@@ -134,6 +137,12 @@ srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J, do
         throw;
       }
       plan->has_device = true;
+      // the device holds everything compute needs; drop the host copies of
+      // the TDOAs and fits (srp_plan_export serves host-only plans)
+      std::vector<double>().swap(hp.x);
+      std::vector<double>().swap(hp.U);
+      std::vector<double>().swap(hp.w);
+      std::vector<int32_t>().swap(hp.start);
     }
     plan->plan_seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -216,6 +225,7 @@ srp_status srp_plan_info_get(srp_plan_t plan, srp_plan_info* info) {
   info->plan_seconds = plan->plan_seconds;
   info->map_pitch = (hp.J + 127) / 128 * 128;
   info->sampling_fft = hp.fft ? 1 : 0;
+  info->fd_generated = plan->dp.fd_gen ? 1 : 0;
   return SRP_OK;
 }
 
@@ -226,6 +236,8 @@ srp_status srp_plan_export(srp_plan_t plan, const char* what, void* dst, size_t 
   size_t n = 0;
   std::vector<int32_t> tmp;
   const std::string w(what);
+  if (plan->has_device && (w == "tdoa" || w == "slri_u" || w == "sspi_start" || w == "sspi_w"))
+    return fail(SRP_E_INVALID, "'" + w + "' is kept only by host-only plans");
   if (w == "tdoa") {
     src = hp.x.data();
     n = hp.x.size() * sizeof(double);

@@ -386,6 +386,160 @@ __global__ __launch_bounds__(256) void gemm_nt(const GemmBatch* __restrict__ bat
     }
 }
 
+// conv. FD-SRP with the steering operand generated on the fly (plans whose
+// H would not fit in HBM): z = alpha (psi H^T) as in gemm_nt, but each
+// 128-byte K slice of the BW = 128 rows of H is computed into LDS instead of
+// read: slots 2 (k - 1), 2 (k - 1) + 1 of pair p hold cos theta, -sin theta,
+// theta = pi k x_p(j) / K (eq. (19) with (14)).  A thread fills up to
+// BINS consecutive bins of one row: the first angle is reduced in FP64
+// (t = k x / 2K, theta = 2 pi (t - rint t)) and evaluated by sincospi, the
+// rest follow by FP32 rotation by exp(+i pi x / K), itself from an FP64
+// reduction; the rotation chain is at most BINS - 1 steps long.
+template <typename T, int BX, int WGX>
+__global__ __launch_bounds__(256) void fd_gen(const T* __restrict__ X, int64_t ldx,
+                                              const double* __restrict__ xg, int64_t J, int K, int Kp,
+                                              float* __restrict__ C, int64_t ldc, int nx, int kdim, float alpha,
+                                              int nw_tiles, int nx_tiles) {
+  constexpr int BW = 128, BKB = 128;
+  constexpr int STEP = Mfma<T>::STEP;
+  constexpr int LB = STEP / 2;
+  constexpr int NV = LB / 16;
+  constexpr int ROWB = BKB + 16;
+  constexpr int WGW = 4 / WGX;
+  constexpr int WX = BX / WGX, WW = BW / WGW;
+  constexpr int NBX = WX / 32, NBW = WW / 32;
+  static_assert(NBX >= 1 && NBW >= 1, "tile too small");
+  constexpr int CPR = BKB / 16;                         // 16-byte chunks per row per slice
+  constexpr int XCH = BX * CPR;                         // X chunks per slice
+  constexpr int PER = (XCH + 255) / 256;
+  constexpr int EPS = BKB / static_cast<int>(sizeof(T));  // elements per row per slice
+  constexpr int BPS = EPS / 2;                          // bins per row per slice
+  constexpr int TPR = 256 / BW;                         // threads per row (2)
+  constexpr int BINS = BPS / TPR;                       // bins per thread
+  __shared__ __attribute__((aligned(16))) unsigned char lds[(BX + BW) * ROWB];
+
+  int wt, xt;
+  if (!xcd_tile(nw_tiles, nx_tiles, wt, xt)) return;
+  const int x0 = xt * BX;
+  const int w0 = wt * BW;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wx = (wave / WGW) * WX, ww = (wave % WGW) * WW;
+  const int r32 = lane & 31, g = lane >> 5;
+  const unsigned char* Xb = reinterpret_cast<const unsigned char*>(X);
+  const int64_t xrow = ldx * static_cast<int64_t>(sizeof(T));
+
+  // generator: row gr of the tile, bins gb0 .. gb0 + BINS - 1 of the slice
+  const int gr = tid / TPR, gpart = tid % TPR;
+  const int64_t gj = w0 + gr;
+  const bool glive = gj < J;
+
+  i32x4 pre[PER];
+  auto gload = [&](int kb) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int c = tid + i * 256;
+      if (XCH % 256 == 0 || c < XCH) {
+        const int row = c / CPR, col = c % CPR;
+        pre[i] = i32x4{0, 0, 0, 0};
+        if (x0 + row < nx) pre[i] = *reinterpret_cast<const i32x4*>(Xb + (x0 + row) * xrow + kb + col * 16);
+      }
+    }
+  };
+
+  f32x16 acc[NBX][NBW];
+#pragma unroll
+  for (int a = 0; a < NBX; ++a)
+#pragma unroll
+    for (int b = 0; b < NBW; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
+
+  const int kbytes = kdim * static_cast<int>(sizeof(T));
+  gload(0);
+  for (int kb = 0; kb < kbytes; kb += BKB) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int c = tid + i * 256;
+      if (XCH % 256 == 0 || c < XCH) {
+        const int row = c / CPR, col = c % CPR;
+        *reinterpret_cast<i32x4*>(lds + row * ROWB + col * 16) = pre[i];
+      }
+    }
+    // generate this slice's BW rows of H
+    {
+      const int e0 = kb / static_cast<int>(sizeof(T));  // first element of the slice in the row
+      const int p = e0 / Kp;
+      const int k0 = (e0 % Kp) / 2 + 1 + gpart * BINS;  // first bin of this thread
+      T* dst = reinterpret_cast<T*>(lds + (BX + gr) * ROWB) + 2 * gpart * BINS;
+      if (glive && k0 <= K - 1) {
+        const double xv = xg[static_cast<int64_t>(p) * J + gj];
+        const double t = static_cast<double>(k0) * xv / (2.0 * K);
+        double sd, cd;
+        sincospi(2.0 * (t - rint(t)), &sd, &cd);
+        const double u = xv / (2.0 * K);
+        double su, cu;
+        sincospi(2.0 * (u - rint(u)), &su, &cu);
+        float c = static_cast<float>(cd), sn = static_cast<float>(sd);
+        const float cs = static_cast<float>(cu), ss = static_cast<float>(su);
+#pragma unroll
+        for (int b = 0; b < BINS; ++b) {
+          const bool ok = k0 + b <= K - 1;
+          dst[2 * b] = cvt<T>(ok ? c : 0.0f);
+          dst[2 * b + 1] = cvt<T>(ok ? -sn : 0.0f);
+          // (c + i s) <- (c + i s)(cs + i ss)
+          const float cn = __builtin_fmaf(c, cs, -(sn * ss));
+          sn = __builtin_fmaf(c, ss, sn * cs);
+          c = cn;
+        }
+      } else {
+#pragma unroll
+        for (int b = 0; b < BINS; ++b) {
+          dst[2 * b] = cvt<T>(0.0f);
+          dst[2 * b + 1] = cvt<T>(0.0f);
+        }
+      }
+    }
+    __syncthreads();
+    if (kb + BKB < kbytes) gload(kb + BKB);
+#pragma unroll
+    for (int s = 0; s < BKB; s += STEP) {
+      i32x4 fa[NBX][NV], fb[NBW][NV];
+#pragma unroll
+      for (int a = 0; a < NBX; ++a) {
+        const unsigned char* q = lds + (wx + a * 32 + r32) * ROWB + s + g * LB;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fa[a][v] = *reinterpret_cast<const i32x4*>(q + 16 * v);
+      }
+#pragma unroll
+      for (int b = 0; b < NBW; ++b) {
+        const unsigned char* q = lds + (BX + ww + b * 32 + r32) * ROWB + s + g * LB;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fb[b][v] = *reinterpret_cast<const i32x4*>(q + 16 * v);
+      }
+#pragma unroll
+      for (int a = 0; a < NBX; ++a)
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) Mfma<T>::run(fa[a], fb[b], acc[a][b]);
+    }
+  }
+  // 32 x 32 accumulator layout: register v of lane i holds row
+  // 8 (v / 4) + 4 (i / 32) + v % 4 and column i % 32
+#pragma unroll
+  for (int a = 0; a < NBX; ++a)
+#pragma unroll
+    for (int b = 0; b < NBW; ++b) {
+      const int64_t col = w0 + ww + b * 32 + r32;
+      if (col >= J) continue;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = x0 + wx + a * 32 + 8 * (v / 4) + 4 * g + (v % 4);
+        if (row < nx) C[static_cast<int64_t>(row) * ldc + col] = alpha * acc[a][b][v];
+      }
+    }
+}
+
 // FP64 variant on v_mfma_f64_16x16x4_f64: 64 x 64 tile, 4 waves of 32 x 32,
 // each 2 x 2 blocks of 16 x 16.  Lane i supplies row i % 16 and k slot i / 16
 // of each 4-deep step; accumulator register v of lane i holds row
@@ -1418,6 +1572,16 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
   if (hp.variant == SRP_FD) {
     const size_t es = dsize(hp.dtype);
     const size_t hbytes = static_cast<size_t>(dp.Jpad) * P * dp.Kp * es;
+    // resident H up to 16 GiB (and within the budget); beyond, the steering
+    // is generated on the fly from the FP64 TDOAs
+    const bool fits = hbytes <= (size_t(16) << 30) && (budget == 0 || hbytes + dp.resident_bytes <= budget);
+    dp.fd_gen = hp.fd_steering == 2 || (hp.fd_steering == 0 && !fits);
+    if (dp.fd_gen) {
+      if (hp.dtype == SRP_F64) throw Error{SRP_E_UNSUPPORTED, "FP64 FD needs the resident steering operand"};
+      dp.d_xg = static_cast<double*>(A.get(hp.x.size() * sizeof(double)));
+      upload(dp.d_xg, hp.x);
+      return;
+    }
     dp.d_H = A.get(hbytes);
     double* d_x = nullptr;
     HIP_OK(hipMalloc(&d_x, hp.x.size() * sizeof(double)));
@@ -1641,7 +1805,7 @@ void device_free(DevicePlan& dp) {
   }
   for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
   void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_tasks, dp.d_tw, dp.d_w2,
-                  dp.d_U, dp.d_V, dp.d_gscale, dp.d_start, dp.d_w, dp.d_win, dp.ws};
+                  dp.d_U, dp.d_V, dp.d_gscale, dp.d_start, dp.d_w, dp.d_win, dp.d_xg, dp.ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   dp = DevicePlan{};
@@ -1751,6 +1915,28 @@ void tall_split(DevicePlan& dp, const void* kern, int threads, int njt, int ngro
   }
   gps = (ngroups + nsplit - 1) / nsplit;
   nsplit = (ngroups + gps - 1) / gps;
+}
+
+// FD with generated steering: 256-frame tiles (waves 2 x 2) for large
+// batches, 64-frame tiles (waves 1 x 4) for small ones.
+template <typename T>
+void launch_fd_gen(const HostPlan& hp, DevicePlan& dp, const void* psi, int64_t ldpsi, float* z, int64_t ldz,
+                   int64_t Lc, hipStream_t st) {
+  const int nw = static_cast<int>((hp.J + 127) / 128);
+  const int kdim = static_cast<int>(ldpsi);
+  if (Lc > 128) {
+    const int nxt = static_cast<int>((Lc + 255) / 256);
+    const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(nw) * nxt, 8));
+    TRACED(dp, "fd_gen", st,
+           hipLaunchKernelGGL((fd_gen<T, 256, 2>), dim3(blocks), dim3(256), 0, st, static_cast<const T*>(psi), ldpsi,
+                              dp.d_xg, hp.J, hp.K, dp.Kp, z, ldz, static_cast<int>(Lc), kdim, 2.0f, nw, nxt));
+  } else {
+    const int nxt = static_cast<int>((Lc + 63) / 64);
+    const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(nw) * nxt, 8));
+    TRACED(dp, "fd_gen", st,
+           hipLaunchKernelGGL((fd_gen<T, 64, 1>), dim3(blocks), dim3(256), 0, st, static_cast<const T*>(psi), ldpsi,
+                              dp.d_xg, hp.J, hp.K, dp.Kp, z, ldz, static_cast<int>(Lc), kdim, 2.0f, nw, nxt));
+  }
 }
 
 template <typename T>
@@ -1960,6 +2146,15 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
         continue;
       }
       float* z = static_cast<float*>(maps) + l0 * ldm;
+      if (dp.fd_gen) {
+        switch (hp.dtype) {
+          case SRP_F32: launch_fd_gen<float>(hp, dp, psi, ldpsi, z, ldm, Lc, st); break;
+          case SRP_BF16: launch_fd_gen<__bf16>(hp, dp, psi, ldpsi, z, ldm, Lc, st); break;
+          case SRP_F16: launch_fd_gen<_Float16>(hp, dp, psi, ldpsi, z, ldm, Lc, st); break;
+          case SRP_FP8_E4M3: launch_fd_gen<fp8>(hp, dp, psi, ldpsi, z, ldm, Lc, st); break;
+        }
+        continue;
+      }
       switch (hp.dtype) {
         case SRP_F32: launch_big_gemm<float>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
         case SRP_BF16: launch_big_gemm<__bf16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;

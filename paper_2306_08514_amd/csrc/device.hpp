@@ -31,6 +31,8 @@ struct DevicePlan {
   int32_t* d_off = nullptr;
   // FD
   void* d_H = nullptr;       // [Jpad][P*Kp] steering (cos, -sin) in dtype
+  bool fd_gen = false;       // steering generated on the fly from d_xg
+  double* d_xg = nullptr;    // [P][J] TDOAs in samples (generated steering)
   // sampling (SLRI, SSPI)
   float* d_S = nullptr;      // [2 max_np + 1 + 32][Kp] rows 2cos / -2sin
   int samp_rows = 0;         // 2 max_np + 1

@@ -116,17 +116,21 @@ void build_geometry(HostPlan& hp, const double* mics, int M, const double* grid,
 
   // TDOA in samples, near field, eq. (3)
   hp.x.assign(static_cast<size_t>(hp.P) * J, 0.0);
-  std::vector<double> dist(static_cast<size_t>(M));
-  for (int64_t j = 0; j < J; ++j) {
-    const double* q = &grid[3 * j];
-    for (int m = 0; m < M; ++m) {
-      const double* r = &mics[3 * m];
-      dist[m] = std::sqrt((r[0] - q[0]) * (r[0] - q[0]) + (r[1] - q[1]) * (r[1] - q[1]) +
-                          (r[2] - q[2]) * (r[2] - q[2]));
+  const int chunks = static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, J / 4096)));
+  const unsigned hw = std::thread::hardware_concurrency();
+  parallel_for(chunks, static_cast<int>(std::min(std::max(hw, 1u), 16u)), [&](int ch) {
+    std::vector<double> dist(static_cast<size_t>(M));
+    for (int64_t j = J * ch / chunks; j < J * (ch + 1) / chunks; ++j) {
+      const double* q = &grid[3 * j];
+      for (int m = 0; m < M; ++m) {
+        const double* r = &mics[3 * m];
+        dist[m] = std::sqrt((r[0] - q[0]) * (r[0] - q[0]) + (r[1] - q[1]) * (r[1] - q[1]) +
+                            (r[2] - q[2]) * (r[2] - q[2]));
+      }
+      for (int p = 0; p < hp.P; ++p)
+        hp.x[static_cast<size_t>(p) * J + j] = (dist[hp.pair_m[p]] - dist[hp.pair_mp[p]]) * fs / c;
     }
-    for (int p = 0; p < hp.P; ++p)
-      hp.x[static_cast<size_t>(p) * J + j] = (dist[hp.pair_m[p]] - dist[hp.pair_mp[p]]) * fs / c;
-  }
+  });
 }
 
 void sym_eig(std::vector<double>& a, int n, std::vector<double>& evals,

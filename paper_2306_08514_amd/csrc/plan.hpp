@@ -48,7 +48,8 @@ struct HostPlan {
   std::vector<double> w;        // [J][P][Q], zero for q >= Q_p
 
   bool fft = false;  // GCC sampling by the iFFT of (46) instead of the direct product of (40)
-  bool device_fit = false;  // SLRI Gram matrices and U, SSPI windows are computed on the device
+  bool device_fit = false;
+  int fd_steering = 0;  // FD steering operand: 0 auto, 1 resident, 2 generated  // SLRI Gram matrices and U, SSPI windows are computed on the device
 
   double macs_per_map = 0;
 };

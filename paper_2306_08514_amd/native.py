@@ -34,7 +34,8 @@ class SrpError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("n_aux", ctypes.c_int), ("dtype", ctypes.c_int),
                 ("device", ctypes.c_int), ("frame_tile", ctypes.c_int64),
-                ("hbm_budget", ctypes.c_size_t), ("sampling", ctypes.c_int)]
+                ("hbm_budget", ctypes.c_size_t), ("sampling", ctypes.c_int),
+                ("fd_steering", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -43,7 +44,8 @@ class PlanInfo(ctypes.Structure):
                 ("rank_or_q", ctypes.c_int), ("variant", ctypes.c_int), ("dtype", ctypes.c_int),
                 ("mean_n", ctypes.c_double), ("macs_per_map", ctypes.c_double),
                 ("device_bytes", ctypes.c_size_t), ("plan_seconds", ctypes.c_double),
-                ("map_pitch", ctypes.c_int64), ("sampling_fft", ctypes.c_int)]
+                ("map_pitch", ctypes.c_int64), ("sampling_fft", ctypes.c_int),
+                ("fd_generated", ctypes.c_int)]
 
 
 class KernelTime(ctypes.Structure):
@@ -120,12 +122,14 @@ class Plan:
     DFT length; variant in {"fd", "slri", "sspi"}; rank_or_q = R per pair
     (SLRI) or Q per (location, pair) (SSPI); dtype in {"f32", "bf16", "f16",
     "fp8", "f64"}; device = -1 builds the host-side plan only; sampling in
-    {"auto", "direct", "fft"} selects the GCC sampling form of SLRI/SSPI."""
+    {"auto", "direct", "fft"} selects the GCC sampling form of SLRI/SSPI;
+    fd_steering in {"auto", "resident", "generated"} the FD steering operand."""
 
     SAMPLING = {"auto": 0, "direct": 1, "fft": 2}
+    STEERING = {"auto": 0, "resident": 1, "generated": 2}
 
     def __init__(self, mics, grid, fs, N, variant, rank_or_q=0, dtype="f32", c=343.0, n_aux=2,
-                 device=0, frame_tile=1024, hbm_budget=0, sampling="auto"):
+                 device=0, frame_tile=1024, hbm_budget=0, sampling="auto", fd_steering="auto"):
         L = lib()
         mics = np.ascontiguousarray(mics, dtype=np.float64)
         grid = np.ascontiguousarray(grid, dtype=np.float64)
@@ -134,6 +138,7 @@ class Plan:
         o.c, o.n_aux, o.dtype, o.device = float(c), int(n_aux), DTYPES[dtype], int(device)
         o.frame_tile, o.hbm_budget = int(frame_tile), int(hbm_budget)
         o.sampling = self.SAMPLING[sampling]
+        o.fd_steering = self.STEERING[fd_steering]
         h = ctypes.c_void_p()
         self._h = None
         self._mics_ref = mics

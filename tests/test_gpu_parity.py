@@ -188,6 +188,23 @@ def test_fft_sampling(native, sq4, room_small, variant, rq, dtype):
         assert _plan(native, cfg, variant, rq, dtype).info()["sampling_fft"] == 0
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16", "fp8"])
+def test_fd_generated_steering(native, sq4, room_small, dtype):
+    """conv. FD-SRP with the steering operand generated inside the product
+    (FP64-reduced seed angles, short FP32 rotation chains) against the FP64
+    oracle, and against the resident-operand maps."""
+    for cfg, Y in (sq4, room_small):
+        _announce(f"fd generated {cfg['name']} {dtype}")
+        p = _plan(native, cfg, "fd", 0, dtype, fd_steering="generated")
+        assert p.info()["fd_generated"] == 1
+        Yt = torch.from_numpy(Y).cuda()
+        z = p.compute(Yt).cpu().numpy()
+        _check_maps(z, _oracle_maps("fd", Y, cfg, 0), TOL[dtype], f"fd gen {cfg['name']} {dtype}")
+        if dtype == "f32":
+            zr = _plan(native, cfg, "fd", 0, dtype).compute(Yt).cpu().numpy()
+            assert (np.linalg.norm(z - zr, axis=1) / np.linalg.norm(zr, axis=1)).max() <= 1e-5
+
+
 # ---------------------------------------------------------- edge cases ----
 
 def test_edge_cases(native, sq4):
