@@ -390,11 +390,13 @@ __global__ __launch_bounds__(256) void gemm_nt(const GemmBatch* __restrict__ bat
 // H would not fit in HBM): z = alpha (psi H^T) as in gemm_nt, but each
 // 128-byte K slice of the BW = 128 rows of H is computed into LDS instead of
 // read: slots 2 (k - 1), 2 (k - 1) + 1 of pair p hold cos theta, -sin theta,
-// theta = pi k x_p(j) / K (eq. (19) with (14)).  A thread fills up to
-// BINS consecutive bins of one row: the first angle is reduced in FP64
-// (t = k x / 2K, theta = 2 pi (t - rint t)) and evaluated by sincospi, the
-// rest follow by FP32 rotation by exp(+i pi x / K), itself from an FP64
-// reduction; the rotation chain is at most BINS - 1 steps long.
+// theta = pi k x_p(j) / K (eq. (19) with (14)).  A thread fills BINS
+// consecutive bins of one row per slice: at the first slice of a pair its
+// first angle is reduced in FP64 (t = k x / 2K, theta = 2 pi (t - rint t))
+// and evaluated by sincospi; each further slice of the pair advances that
+// FP64 value by one rotation of BPS bins (at most K / BPS rotations, error
+// ~1e-15); within a slice the bins follow by FP32 rotation by
+// exp(+i pi x / K), a chain of at most BINS - 1 steps.
 template <typename T, int BX, int WGX>
 __global__ __launch_bounds__(256) void fd_gen(const T* __restrict__ X, int64_t ldx,
                                               const double* __restrict__ xg, int64_t J, int K, int Kp,
@@ -456,6 +458,8 @@ __global__ __launch_bounds__(256) void fd_gen(const T* __restrict__ X, int64_t l
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
 
   const int kbytes = kdim * static_cast<int>(sizeof(T));
+  double gx = 0.0, gs_c = 1.0, gs_s = 0.0, gadv_c = 1.0, gadv_s = 0.0;  // generator state
+  float gstep_c = 1.0f, gstep_s = 0.0f;
   gload(0);
   for (int kb = 0; kb < kbytes; kb += BKB) {
     __syncthreads();
@@ -467,38 +471,48 @@ __global__ __launch_bounds__(256) void fd_gen(const T* __restrict__ X, int64_t l
         *reinterpret_cast<i32x4*>(lds + row * ROWB + col * 16) = pre[i];
       }
     }
-    // generate this slice's BW rows of H
+    // generate this slice's BW rows of H: the thread's first angle of the
+    // slice comes from an FP64 seed, exact at the first slice of each pair
+    // and advanced by one FP64 rotation per further slice; its BINS bins by
+    // FP32 rotation; 64 bytes per thread go to LDS as four 16-byte stores
     {
       const int e0 = kb / static_cast<int>(sizeof(T));  // first element of the slice in the row
       const int p = e0 / Kp;
-      const int k0 = (e0 % Kp) / 2 + 1 + gpart * BINS;  // first bin of this thread
-      T* dst = reinterpret_cast<T*>(lds + (BX + gr) * ROWB) + 2 * gpart * BINS;
-      if (glive && k0 <= K - 1) {
-        const double xv = xg[static_cast<int64_t>(p) * J + gj];
-        const double t = static_cast<double>(k0) * xv / (2.0 * K);
-        double sd, cd;
-        sincospi(2.0 * (t - rint(t)), &sd, &cd);
-        const double u = xv / (2.0 * K);
+      const int kfirst = (e0 % Kp) / 2 + 1 + gpart * BINS;  // first bin of this thread
+      if (glive && e0 % Kp == 0) {
+        gx = xg[static_cast<int64_t>(p) * J + gj];
+        const double t = static_cast<double>(kfirst) * gx / (2.0 * K);
+        sincospi(2.0 * (t - rint(t)), &gs_s, &gs_c);
+        const double u = gx / (2.0 * K);
         double su, cu;
         sincospi(2.0 * (u - rint(u)), &su, &cu);
-        float c = static_cast<float>(cd), sn = static_cast<float>(sd);
-        const float cs = static_cast<float>(cu), ss = static_cast<float>(su);
+        gstep_c = static_cast<float>(cu);
+        gstep_s = static_cast<float>(su);
+        const double v = static_cast<double>(BPS) * gx / (2.0 * K);
+        sincospi(2.0 * (v - rint(v)), &gadv_s, &gadv_c);
+      } else if (glive) {
+        const double cn = gs_c * gadv_c - gs_s * gadv_s;
+        gs_s = gs_c * gadv_s + gs_s * gadv_c;
+        gs_c = cn;
+      }
+      T vals[2 * BINS];
+      float c = static_cast<float>(gs_c), sn = static_cast<float>(gs_s);
 #pragma unroll
-        for (int b = 0; b < BINS; ++b) {
-          const bool ok = k0 + b <= K - 1;
-          dst[2 * b] = cvt<T>(ok ? c : 0.0f);
-          dst[2 * b + 1] = cvt<T>(ok ? -sn : 0.0f);
-          // (c + i s) <- (c + i s)(cs + i ss)
-          const float cn = __builtin_fmaf(c, cs, -(sn * ss));
-          sn = __builtin_fmaf(c, ss, sn * cs);
-          c = cn;
-        }
-      } else {
+      for (int b = 0; b < BINS; ++b) {
+        const bool ok = glive && kfirst + b <= K - 1;
+        vals[2 * b] = cvt<T>(ok ? c : 0.0f);
+        vals[2 * b + 1] = cvt<T>(ok ? -sn : 0.0f);
+        // (c + i s) <- (c + i s)(step_c + i step_s)
+        const float cn = __builtin_fmaf(c, gstep_c, -(sn * gstep_s));
+        sn = __builtin_fmaf(c, gstep_s, sn * gstep_c);
+        c = cn;
+      }
+      unsigned char* dst = lds + (BX + gr) * ROWB + gpart * (BKB / TPR);
 #pragma unroll
-        for (int b = 0; b < BINS; ++b) {
-          dst[2 * b] = cvt<T>(0.0f);
-          dst[2 * b + 1] = cvt<T>(0.0f);
-        }
+      for (int i = 0; i < BKB / TPR / 16; ++i) {
+        i32x4 w4;
+        __builtin_memcpy(&w4, reinterpret_cast<const unsigned char*>(vals) + 16 * i, 16);
+        *reinterpret_cast<i32x4*>(dst + 16 * i) = w4;
       }
     }
     __syncthreads();

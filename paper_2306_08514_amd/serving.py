@@ -51,12 +51,16 @@ class Server:
     hbm_budget     bytes available to plans plus in-flight work (None: the
                    executor's default)
     max_batch_frames  cap on the frames coalesced into one batch
+    max_queue      requests that may wait; beyond it submit() fails fast with
+                   AdmissionError (backpressure: every waiting request holds
+                   device resources such as its ready event)
     """
 
     def __init__(self, executor, n_slots=4, hbm_budget=None, max_batch_frames=1024,
-                 poll_interval=20e-6):
+                 poll_interval=20e-6, max_queue=1024):
         self.ex = executor
         self.n_slots = int(n_slots)
+        self.max_queue = int(max_queue)
         self.budget = int(hbm_budget if hbm_budget is not None else executor.default_budget())
         self.max_batch_frames = int(max_batch_frames)
         self.poll_interval = poll_interval
@@ -75,6 +79,7 @@ class Server:
         self._coalesced = 0
         self._max_inflight = 0
         self._failed = 0
+        self._rejected = 0
         self.error = None
 
     # --------------------------------------------------------------- plans --
@@ -104,6 +109,13 @@ class Server:
         fut = concurrent.futures.Future()
         if key not in self._plans:
             fut.set_exception(KeyError(f"unknown plan {key!r}"))
+            return fut
+        with self._lock:
+            full = len(self._queue) >= self.max_queue
+        if full:
+            with self._lock:
+                self._rejected += 1
+            fut.set_exception(AdmissionError(f"queue full ({self.max_queue} requests waiting)"))
             return fut
         n = self.ex.frames_len(frames)
         need = self.ex.footprint(key, n)
@@ -251,6 +263,19 @@ class Server:
                         r.future.set_exception(e)
 
     # ---------------------------------------------------------------- stats --
+    def reset_stats(self):
+        """Starts a new measurement window (in-flight work is not affected)."""
+        with self._lock:
+            self._lat = []
+            self._maps_done = 0
+            self._t0 = None
+            self._t_last = None
+            self._batches = 0
+            self._coalesced = 0
+            self._max_inflight = len(self._inflight)
+            self._failed = 0
+            self._rejected = 0
+
     def stats(self):
         lat = np.array(self._lat) * 1e3
         span = (self._t_last - self._t0) if self._t0 is not None and self._t_last is not None else 0.0
@@ -261,6 +286,7 @@ class Server:
             "requests_per_batch": self._coalesced / max(1, self._batches),
             "max_inflight": int(self._max_inflight),
             "failed_requests": int(self._failed),
+            "rejected_requests": int(self._rejected),
             "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
             "mean_ms": float(lat.mean()) if lat.size else None,
@@ -277,10 +303,12 @@ class TorchExecutor:
     ready event), the library computes into a fresh output, and an event on
     the slot's stream marks completion."""
 
-    def __init__(self, device=0, n_slots=4):
+    def __init__(self, device=0, n_slots=4, timing=False):
         import torch
         from . import native
         self.torch, self.native = torch, native
+        self.timing = bool(timing)
+        self.busy = {}  # (variant, M, J) -> (device ms, batches, frames) when timing
         self.device = torch.device("cuda", device)
         self.dev_index = device
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_slots)]
@@ -321,6 +349,7 @@ class TorchExecutor:
         torch = self.torch
         p = self.plans[key]
         s = self.streams[slot]
+        t0 = None
         with torch.cuda.stream(s):
             for ev in ready:
                 s.wait_event(ev)
@@ -330,17 +359,20 @@ class TorchExecutor:
             L = fr.shape[0]
             ws = torch.empty(max(1, p.workspace_size(L)), dtype=torch.uint8, device=self.device)
             out = p.empty_maps(L, self.device)
+            if self.timing:
+                t0 = torch.cuda.Event(enable_timing=True)
+                t0.record(s)
             p.compute(fr, maps=out, workspace=ws, stream=s)
-            done = torch.cuda.Event()
+            done = torch.cuda.Event(enable_timing=self.timing)
             done.record(s)
         sizes = [f.shape[0] for f in frames_list]
-        return (done, out, sizes, fr, ws)
+        return (done, out, sizes, fr, ws, t0, key)
 
     def poll(self, handle):
         return handle[0].query()
 
     def results(self, handle):
-        _, out, sizes, _, _ = handle
+        out, sizes = handle[1], handle[2]
         res, o = [], 0
         for n in sizes:
             res.append(out[o:o + n])
@@ -348,4 +380,10 @@ class TorchExecutor:
         return res
 
     def release(self, handle):
-        pass  # the caching allocator reclaims ws / frames once unreferenced
+        # the caching allocator reclaims ws / frames once unreferenced
+        if self.timing and handle[5] is not None:
+            key = handle[6]
+            cls = (key[2], key[0], key[1]) if isinstance(key, tuple) and len(key) >= 3 else key
+            ms = handle[5].elapsed_time(handle[0])
+            tot, n, frames = self.busy.get(cls, (0.0, 0, 0))
+            self.busy[cls] = (tot + ms, n + 1, frames + sum(handle[2]))

@@ -187,3 +187,24 @@ def test_executor_failure_fails_its_batch_and_the_server_keeps_serving(frames):
     assert srv.drain(timeout=10)
     assert srv.stats()["failed_requests"] == 1
     srv.stop()
+
+
+def test_queue_bound_rejects_fast_and_recovers(frames):
+    """Backpressure: with the device busy and the queue at its bound, a new
+    request fails at once with AdmissionError; once the queue drains, new
+    requests are served again."""
+    cfg, Y = frames
+    ex = FakeExecutor(per_frame_s=5e-3, fixed_s=20e-3)
+    srv = Server(ex, n_slots=1, max_batch_frames=1, max_queue=3).start()
+    srv.register("a", cfg=cfg)
+    first = srv.submit("a", Y[:1])
+    time.sleep(0.005)                        # the first batch is on the device
+    queued = [srv.submit("a", Y[i:i + 1]) for i in range(1, 4)]
+    over = srv.submit("a", Y[5:6])
+    with pytest.raises(AdmissionError):
+        over.result(timeout=1)
+    assert srv.drain(timeout=30)
+    assert first.result().shape[0] == 1 and all(f.result().shape[0] == 1 for f in queued)
+    assert srv.stats()["rejected_requests"] == 1
+    assert srv.submit("a", Y[:2]).result(timeout=10).shape[0] == 2
+    srv.stop()
