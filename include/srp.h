@@ -62,7 +62,16 @@ typedef enum {
   SRP_E_BUDGET = -5       /* plan or workspace exceeds opts.hbm_budget */
 } srp_status;
 
-typedef enum { SRP_FD = 0, SRP_SLRI = 1, SRP_SSPI = 2 } srp_variant;
+typedef enum {
+  SRP_FD = 0,    /* conv. FD-SRP, eq. (22) */
+  SRP_SLRI = 1,  /* SLRI-SRP, eq. (57) */
+  SRP_SSPI = 2,  /* SSPI-SRP, eq. (58) */
+  SRP_SI = 3,    /* SI-SRP, eq. (44): every lag of every pair interpolated;
+                    rank_or_q ignored (at most 32 lags per pair) */
+  SRP_TD = 4     /* conv. TD-SRP, eq. (23): the GCC read at the TDOA rounded
+                    to the nearest sample (half away from zero); rank_or_q
+                    ignored */
+} srp_variant;
 
 /* Operand precision of the dominant contraction (steering matrix for FD, the
  * tall factor U for SLRI, the interpolation weights for SSPI).  Accumulation
@@ -96,6 +105,10 @@ typedef struct {
                             J x 2P(K-1) matrix; 2 = generated on the fly
                             from the FP64 TDOAs inside the product (not for
                             SRP_F64) */
+  int far_field;         /* 1: grid rows are unit directions u pointing from
+                            the array towards the source (Sec. II-A, the far
+                            limit of (3)): x_p = -(r_m - r_m')^T u fs / c;
+                            rows must have unit length (|1 - |u|| <= 1e-6) */
 } srp_opts;
 
 typedef struct {
@@ -164,6 +177,18 @@ srp_status srp_workspace_size(srp_plan_t plan, int64_t L, size_t* bytes);
 srp_status srp_compute(srp_plan_t plan, const void* frames, int64_t L,
                        void* maps, int64_t ld_maps, void* workspace,
                        size_t ws_bytes, void* stream);
+
+/* Peak picking of (10)-(11) on the device: for each of L maps (row pitch
+ * ld_maps >= J elements, float32 or float64 as given by dtype = SRP_F32 or
+ * SRP_F64), the candidate with the largest value, ties to the smallest
+ * index; NaN never wins.
+ *   maps  device, as written by srp_compute
+ *   idx   device, int64 [L]: the candidate index (-1 if every value is NaN)
+ *   val   device, float64 [L]: its value
+ * Asynchronous on `stream`.  SRP_E_INVALID for J < 1, ld_maps < J or another
+ * dtype. */
+srp_status srp_argmax(const void* maps, srp_dtype dtype, int64_t L, int64_t J, int64_t ld_maps,
+                      int64_t* idx, double* val, void* stream);
 
 /* Stage entry point: PHAT-weighted cross-spectra (eq. (2)) of L frames.
  *   psi  device, complex64 [L][P][K-1] */

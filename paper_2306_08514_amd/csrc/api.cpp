@@ -92,6 +92,7 @@ void srp_default_opts(srp_opts* o) {
   o->hbm_budget = 0;
   o->sampling = 0;
   o->fd_steering = 0;
+  o->far_field = 0;
 }
 
 const char* srp_last_error(void) { return g_err.c_str(); }
@@ -103,11 +104,11 @@ srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J, do
   srp_opts o;
   srp_default_opts(&o);
   if (opts) o = *opts;
-  if (variant != SRP_FD && variant != SRP_SLRI && variant != SRP_SSPI)
-    return fail(SRP_E_INVALID, "unknown variant");
+  if (variant < SRP_FD || variant > SRP_TD) return fail(SRP_E_INVALID, "unknown variant");
+  const bool fixed = variant == SRP_FD || variant == SRP_SI || variant == SRP_TD;  // rank_or_q ignored
   if (o.dtype < SRP_F32 || o.dtype > SRP_F64) return fail(SRP_E_INVALID, "unknown dtype");
   if (!dtype_ok(variant, o.dtype)) return fail(SRP_E_UNSUPPORTED, "dtype not offered for this variant");
-  if (variant != SRP_FD && rank_or_q < 1) return fail(SRP_E_INVALID, "rank_or_q must be >= 1");
+  if (!fixed && rank_or_q < 1) return fail(SRP_E_INVALID, "rank_or_q must be >= 1");
   if (o.frame_tile < 1) return fail(SRP_E_INVALID, "frame_tile must be >= 1");
   if (o.sampling < 0 || o.sampling > 2) return fail(SRP_E_INVALID, "sampling must be 0, 1 or 2");
   if (o.fd_steering < 0 || o.fd_steering > 2) return fail(SRP_E_INVALID, "fd_steering must be 0, 1 or 2");
@@ -118,15 +119,19 @@ srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J, do
     std::unique_ptr<srp_plan_s> plan(new srp_plan_s());
     plan->opts = o;
     srp::HostPlan& hp = plan->hp;
-    hp.variant = variant;
+    hp.form = variant;
+    hp.variant = variant == SRP_SI ? SRP_SLRI : (variant == SRP_TD ? SRP_SSPI : variant);
     hp.dtype = o.dtype;
     hp.requested = rank_or_q;
-    srp::build_geometry(hp, mics, M, grid, J, fs, N, o.c, o.n_aux);
+    srp::build_geometry(hp, mics, M, grid, J, fs, N, o.c, o.n_aux, o.far_field != 0);
     srp::choose_sampling(hp, o.sampling);
     hp.device_fit = o.device >= 0;
     hp.fd_steering = o.fd_steering;
     if (variant == SRP_SLRI) srp::build_slri(hp, rank_or_q, plan_threads());
+    if (variant == SRP_SI) srp::build_slri(hp, 2 * hp.max_np + 1, plan_threads());
     if (variant == SRP_SSPI) srp::build_sspi(hp, rank_or_q, plan_threads());
+    if (variant == SRP_TD) srp::build_sspi(hp, 1, plan_threads());
+    if (variant == SRP_SI && hp.R > 32) throw srp::Error{SRP_E_UNSUPPORTED, "SI with more than 32 lags per pair is not built"};
     srp::count_macs(hp);
     if (o.device >= 0) {
       DeviceGuard g(o.device);
@@ -178,6 +183,19 @@ srp_status srp_compute(srp_plan_t plan, const void* frames, int64_t L, void* map
   })
 }
 
+srp_status srp_argmax(const void* maps, srp_dtype dtype, int64_t L, int64_t J, int64_t ld_maps,
+                      int64_t* idx, double* val, void* stream) {
+  if (L < 0 || J < 1) return fail(SRP_E_INVALID, "need L >= 0 and J >= 1");
+  if (ld_maps < J) return fail(SRP_E_INVALID, "ld_maps must be >= J");
+  if (dtype != SRP_F32 && dtype != SRP_F64) return fail(SRP_E_INVALID, "maps must be float32 or float64");
+  if (L == 0) return SRP_OK;
+  if (!maps || !idx || !val) return fail(SRP_E_INVALID, "maps, idx and val must be device pointers");
+  SRP_GUARD({
+    srp::device_argmax(maps, dtype == SRP_F64, L, J, ld_maps, idx, val, static_cast<hipStream_t>(stream));
+    return SRP_OK;
+  })
+}
+
 srp_status srp_crossspec(srp_plan_t plan, const void* frames, int64_t L, void* psi, void* stream) {
   if (!plan) return fail(SRP_E_INVALID, "NULL plan");
   if (L < 0) return fail(SRP_E_INVALID, "L must be >= 0");
@@ -217,7 +235,7 @@ srp_status srp_plan_info_get(srp_plan_t plan, srp_plan_info* info) {
   info->PN = hp.PN;
   info->max_np = hp.max_np;
   info->rank_or_q = hp.variant == SRP_SLRI ? hp.R : (hp.variant == SRP_SSPI ? hp.Q : 0);
-  info->variant = static_cast<srp_variant>(hp.variant);
+  info->variant = static_cast<srp_variant>(hp.form);
   info->dtype = static_cast<srp_dtype>(hp.dtype);
   info->mean_n = hp.mean_n;
   info->macs_per_map = hp.macs_per_map;

@@ -1402,7 +1402,7 @@ __global__ void scale_pairs(float* __restrict__ Us, int64_t rows, int Kc, int R,
 template <typename TW>
 __global__ __launch_bounds__(256) void sspi_windows(const double* __restrict__ x, int64_t J,
                                                     const int32_t* __restrict__ np, const int32_t* __restrict__ off,
-                                                    int Q, int Qs, int P, int32_t* __restrict__ start,
+                                                    int Q, int Qs, int P, int td, int32_t* __restrict__ start,
                                                     TW* __restrict__ w, int2* __restrict__ win) {
   __shared__ int rlo[256], rhi[256];
   const int p = blockIdx.y;
@@ -1414,6 +1414,8 @@ __global__ __launch_bounds__(256) void sspi_windows(const double* __restrict__ x
     const double xv = x[static_cast<int64_t>(p) * J + j];
     double s = ceil(xv - 0.5 * q);
     s = fmin(fmax(s, static_cast<double>(-npp)), static_cast<double>(npp - q + 1));
+    // conv. TD-SRP (23): the lag nearest to x, half away from zero
+    if (td) s = copysign(floor(fabs(xv) + 0.5), xv);
     const int si = static_cast<int>(s);
     const int64_t rec = static_cast<int64_t>(p) * J + j;
     const int sabs = off[p] + si + npp;
@@ -1421,7 +1423,8 @@ __global__ __launch_bounds__(256) void sspi_windows(const double* __restrict__ x
     sabs_lo = sabs_hi = sabs;
     const double k0 = rint(xv), sr = sin(M_PI * (xv - k0));
     for (int t2 = 0; t2 < Qs; ++t2) {
-      const float v = t2 < q ? static_cast<float>(sinc_red(xv, k0, sr, si + t2)) : 0.0f;
+      float v = t2 < q ? static_cast<float>(sinc_red(xv, k0, sr, si + t2)) : 0.0f;
+      if (td) v = t2 == 0 ? 1.0f : 0.0f;
       w[rec * Qs + t2] = cvt<TW>(v);
     }
   }
@@ -1677,7 +1680,8 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     TmpBuf dx(hp.x.size() * sizeof(double));
     upload(dx.p, hp.x);
     // Gram matrices on the device (FP64 MFMA), eigenvectors on the host
-    {
+    // (SI keeps every lag: V = I from the host plan, no fit)
+    if (hp.form != SRP_SI) {
       const int ntile = (vrows + 63) / 64;
       const size_t gn = static_cast<size_t>(P) * vrows * vrows;
       TmpBuf dg(gn * sizeof(double));
@@ -1771,7 +1775,7 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     const dim3 gw(static_cast<unsigned>(njt), static_cast<unsigned>(P));
 #define SRP_WIN(TW)                                                                                           \
   hipLaunchKernelGGL(sspi_windows<TW>, gw, dim3(256), 0, 0, dx.as<double>(), hp.J, dp.d_np, dp.d_off, Q, Qs,   \
-                     P, dp.d_start, static_cast<TW*>(dp.d_w), dp.d_win)
+                     P, hp.form == SRP_TD ? 1 : 0, dp.d_start, static_cast<TW*>(dp.d_w), dp.d_win)
     switch (hp.dtype) {
       case SRP_F32: SRP_WIN(float); break;
       case SRP_BF16: SRP_WIN(__bf16); break;
@@ -1810,6 +1814,56 @@ void device_profile_collect(DevicePlan& dp,
     dp.event_pool.push_back(sp.stop);
   }
   dp.spans.clear();
+}
+
+// Peak picking (10)-(11): one block per map; each thread keeps its best
+// (value, index) over a strided sweep (the first index wins among equal
+// values), then a tree reduction with the same order.
+template <typename T>
+__global__ __launch_bounds__(256) void argmax_rows(const T* __restrict__ z, int64_t J, int64_t ld,
+                                                   int64_t* __restrict__ idx, double* __restrict__ val) {
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  const T* row = z + static_cast<int64_t>(blockIdx.x) * ld;
+  double best = 0.0;
+  int64_t bj = -1;
+  for (int64_t j = threadIdx.x; j < J; j += 256) {
+    const double v = static_cast<double>(row[j]);
+    if (v == v && (bj < 0 || v > best)) {
+      best = v;
+      bj = j;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = bj;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      const double v2 = bv[threadIdx.x + h];
+      const int64_t j2 = bi[threadIdx.x + h];
+      const int64_t j1 = bi[threadIdx.x];
+      if (j2 >= 0 && (j1 < 0 || v2 > bv[threadIdx.x] || (v2 == bv[threadIdx.x] && j2 < j1))) {
+        bv[threadIdx.x] = v2;
+        bi[threadIdx.x] = j2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    idx[blockIdx.x] = bi[0];
+    val[blockIdx.x] = bi[0] >= 0 ? bv[0] : 0.0;
+  }
+}
+
+void device_argmax(const void* maps, bool f64, int64_t L, int64_t J, int64_t ld, int64_t* idx, double* val,
+                   hipStream_t st) {
+  if (f64)
+    hipLaunchKernelGGL(argmax_rows<double>, dim3(static_cast<unsigned>(L)), dim3(256), 0, st,
+                       static_cast<const double*>(maps), J, ld, idx, val);
+  else
+    hipLaunchKernelGGL(argmax_rows<float>, dim3(static_cast<unsigned>(L)), dim3(256), 0, st,
+                       static_cast<const float*>(maps), J, ld, idx, val);
+  check_launch("argmax_rows");
 }
 
 void device_free(DevicePlan& dp) {

@@ -71,6 +71,10 @@ struct DevicePlan {
 void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budget);
 void device_free(DevicePlan& dp);
 
+// per-map argmax (ties to the smallest index, NaN never wins)
+void device_argmax(const void* maps, bool f64, int64_t L, int64_t J, int64_t ld, int64_t* idx, double* val,
+                   hipStream_t st);
+
 size_t workspace_bytes(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t frame_tile);
 
 // Enqueues the map computation for L frames on `stream`.

@@ -59,7 +59,7 @@ double sinc_shift(double x, int n) {
 }
 
 void build_geometry(HostPlan& hp, const double* mics, int M, const double* grid,
-                    int64_t J, double fs, int N, double c, int n_aux) {
+                    int64_t J, double fs, int N, double c, int n_aux, bool far_field) {
   if (!mics || !grid) fail("mics and grid must be non-NULL host pointers");
   if (M < 2) fail("need at least 2 microphones");
   if (M > 64) fail("at most 64 microphones are supported");
@@ -115,6 +115,27 @@ void build_geometry(HostPlan& hp, const double* mics, int M, const double* grid,
   hp.mean_n = static_cast<double>(hp.PN) / hp.P;
 
   // TDOA in samples, near field, eq. (3)
+  hp.far_field = far_field;
+  if (far_field) {
+    // far-field TDOA, the far limit of (3): x_p = -(r_m - r_m')^T u fs / c
+    for (int64_t j = 0; j < J; ++j) {
+      const double* u = &grid[3 * j];
+      const double len = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      if (!(std::fabs(1.0 - len) <= 1e-6)) fail("far-field grid rows must be unit vectors");
+    }
+    hp.x.assign(static_cast<size_t>(hp.P) * J, 0.0);
+    for (int p = 0; p < hp.P; ++p) {
+      const double* rm = &mics[3 * hp.pair_m[p]];
+      const double* rq = &mics[3 * hp.pair_mp[p]];
+      const double d0 = rm[0] - rq[0], d1 = rm[1] - rq[1], d2 = rm[2] - rq[2];
+      double* xp = &hp.x[static_cast<size_t>(p) * J];
+      for (int64_t j = 0; j < J; ++j) {
+        const double* u = &grid[3 * j];
+        xp[j] = -(d0 * u[0] + d1 * u[1] + d2 * u[2]) * fs / c;
+      }
+    }
+    return;
+  }
   hp.x.assign(static_cast<size_t>(hp.P) * J, 0.0);
   const int chunks = static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, J / 4096)));
   const unsigned hw = std::thread::hardware_concurrency();
@@ -337,6 +358,15 @@ void build_slri(HostPlan& hp, int R, int threads) {
   for (int p = 0; p < hp.P; ++p) hp.rp[p] = std::min(R, 2 * hp.np[p] + 1);
   hp.V.assign(static_cast<size_t>(hp.P) * nmax * hp.R, 0.0);
   hp.sv.assign(static_cast<size_t>(hp.P) * nmax, 0.0);
+  const bool si = hp.form == SRP_SI;
+  if (si) {
+    // SI-SRP (44): U_p = Lambda_p, V_p = I (every lag kept, no fit)
+    for (int p = 0; p < hp.P; ++p)
+      for (int i = 0; i < 2 * hp.np[p] + 1; ++i) {
+        hp.V[(static_cast<size_t>(p) * nmax + i) * hp.R + i] = 1.0;
+        hp.sv[static_cast<size_t>(p) * nmax + i] = 1.0;
+      }
+  }
   if (hp.device_fit) return;  // Gram matrices and U come from the device
   const int64_t J = hp.J;
   hp.U.assign(static_cast<size_t>(hp.P) * J * hp.R, 0.0);
@@ -357,7 +387,7 @@ void build_slri(HostPlan& hp, int R, int threads) {
     }
     for (int a = 0; a < n; ++a)
       for (int b = 0; b < a; ++b) G[static_cast<size_t>(a) * n + b] = G[static_cast<size_t>(b) * n + a];
-    slri_fit_pair(hp, p, G);
+    if (!si) slri_fit_pair(hp, p, G);
     // U_p = Lambda_p V_p (= left singular vectors times singular values)
     const double* Vp = &hp.V[static_cast<size_t>(p) * nmax * hp.R];
     double* Up = &hp.U[static_cast<size_t>(p) * J * hp.R];
@@ -390,13 +420,21 @@ void build_sspi(HostPlan& hp, int Q, int threads) {
         const int n_p = hp.np[p];
         const int q = hp.qp[p];
         const double x = hp.x[static_cast<size_t>(p) * J + j];
+        double* w = &hp.w[(static_cast<size_t>(j) * hp.P + p) * hp.Q];
+        if (hp.form == SRP_TD) {
+          // conv. TD-SRP (23): the lag nearest to x (half away from zero),
+          // unit weight
+          const double r = std::copysign(std::floor(std::fabs(x) + 0.5), x);
+          hp.start[static_cast<size_t>(j) * hp.P + p] = static_cast<int>(r);
+          w[0] = 1.0;
+          continue;
+        }
         // the q integers nearest to x, clamped to [-N_p, N_p]; |sinc(x - n)|
         // decreases with |x - n|, so these are the q largest entries
         double s = std::ceil(x - 0.5 * q);
         s = std::min(std::max(s, static_cast<double>(-n_p)), static_cast<double>(n_p - q + 1));
         const int si = static_cast<int>(s);
         hp.start[static_cast<size_t>(j) * hp.P + p] = si;
-        double* w = &hp.w[(static_cast<size_t>(j) * hp.P + p) * hp.Q];
         for (int t = 0; t < q; ++t) w[t] = sinc_shift(x, si + t);
       }
     }
@@ -430,7 +468,7 @@ void count_macs(HostPlan& hp) {
     double tall = 0, fat = 0;
     for (int p = 0; p < hp.P; ++p) {
       tall += J * hp.rp[p];
-      fat += static_cast<double>(hp.rp[p]) * (2 * hp.np[p] + 1);
+      if (hp.form != SRP_SI) fat += static_cast<double>(hp.rp[p]) * (2 * hp.np[p] + 1);  // SI: V = I
     }
     hp.macs_per_map = tall + fat + samp;
   } else {

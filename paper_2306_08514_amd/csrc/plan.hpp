@@ -19,7 +19,8 @@ struct HostPlan {
   int64_t J = 0;
   double fs = 0, c = 0;
   int n_aux = 0;
-  int variant = 0;  // srp_variant
+  int variant = 0;  // machinery: SRP_FD, SRP_SLRI (also SI) or SRP_SSPI (also TD)
+  int form = 0;     // the srp_variant requested (SI and TD run on the SLRI / SSPI machinery)
   int dtype = 0;    // srp_dtype
   int requested = 0;
 
@@ -49,7 +50,8 @@ struct HostPlan {
 
   bool fft = false;  // GCC sampling by the iFFT of (46) instead of the direct product of (40)
   bool device_fit = false;
-  int fd_steering = 0;  // FD steering operand: 0 auto, 1 resident, 2 generated  // SLRI Gram matrices and U, SSPI windows are computed on the device
+  int fd_steering = 0;
+  bool far_field = false;  // grid rows are unit directions (far-field TDOAs)  // FD steering operand: 0 auto, 1 resident, 2 generated  // SLRI Gram matrices and U, SSPI windows are computed on the device
 
   double macs_per_map = 0;
 };
@@ -57,7 +59,7 @@ struct HostPlan {
 // Validates the arguments and fills geometry, pairs, TDOAs and lag ranges.
 // Throws srp::Error on invalid input.
 void build_geometry(HostPlan& hp, const double* mics, int M, const double* grid,
-                    int64_t J, double fs, int N, double c, int n_aux);
+                    int64_t J, double fs, int N, double c, int n_aux, bool far_field = false);
 
 // Chooses the GCC sampling form: mode 1 = direct product (40), 2 = iFFT
 // (46), 0 = the cheaper of the two operation counts of (49), 2 PN (K-1)

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsrp.so")
 
-VARIANTS = {"fd": 0, "slri": 1, "sspi": 2}
+VARIANTS = {"fd": 0, "slri": 1, "sspi": 2, "si": 3, "td": 4}
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2, "fp8": 3, "f64": 4}
 STATUS = {0: "SRP_OK", -1: "SRP_E_INVALID", -2: "SRP_E_NOMEM", -3: "SRP_E_UNSUPPORTED",
           -4: "SRP_E_HIP", -5: "SRP_E_BUDGET"}
@@ -22,7 +22,7 @@ STATUS = {0: "SRP_OK", -1: "SRP_E_INVALID", -2: "SRP_E_NOMEM", -3: "SRP_E_UNSUPP
 # every function declared in include/srp.h
 EXPORTS = ["srp_default_opts", "srp_plan", "srp_workspace_size", "srp_compute",
            "srp_crossspec", "srp_gcc_samples", "srp_plan_info_get", "srp_plan_export",
-           "srp_profile_enable", "srp_profile_collect", "srp_destroy", "srp_last_error"]
+           "srp_profile_enable", "srp_profile_collect", "srp_destroy", "srp_last_error", "srp_argmax"]
 
 
 class SrpError(RuntimeError):
@@ -35,7 +35,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("n_aux", ctypes.c_int), ("dtype", ctypes.c_int),
                 ("device", ctypes.c_int), ("frame_tile", ctypes.c_int64),
                 ("hbm_budget", ctypes.c_size_t), ("sampling", ctypes.c_int),
-                ("fd_steering", ctypes.c_int)]
+                ("fd_steering", ctypes.c_int), ("far_field", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -91,6 +91,8 @@ def lib():
     L.srp_profile_collect.restype = ctypes.c_int
     L.srp_destroy.argtypes = [vp]
     L.srp_destroy.restype = None
+    L.srp_argmax.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, vp, vp]
+    L.srp_argmax.restype = ctypes.c_int
     L.srp_last_error.argtypes = []
     L.srp_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -115,6 +117,24 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def argmax(maps, stream=None):
+    """Per-map peak (10)-(11) on the device: (idx int64 [L], val float64 [L])
+    for an [L, J] float32/float64 CUDA tensor with unit column stride; ties go
+    to the smallest index, NaN never wins (idx -1 if a row is all NaN)."""
+    import torch
+    if maps.dim() != 2 or not maps.is_cuda or maps.dtype not in (torch.float32, torch.float64):
+        raise ValueError("maps must be a 2-D float32/float64 CUDA tensor")
+    L, J = maps.shape
+    if J > 1 and maps.stride(1) != 1:
+        raise ValueError("maps must have unit column stride")
+    idx = torch.empty(L, dtype=torch.int64, device=maps.device)
+    val = torch.empty(L, dtype=torch.float64, device=maps.device)
+    ld = maps.stride(0) if L > 1 else J
+    _check(lib().srp_argmax(_ptr(maps), DTYPES["f64" if maps.dtype == torch.float64 else "f32"], L, J, ld,
+                            _ptr(idx), _ptr(val), _stream_handle(stream)))
+    return idx, val
+
+
 class Plan:
     """An SRP-map plan: geometry-dependent operands resident on one device.
 
@@ -123,13 +143,15 @@ class Plan:
     (SLRI) or Q per (location, pair) (SSPI); dtype in {"f32", "bf16", "f16",
     "fp8", "f64"}; device = -1 builds the host-side plan only; sampling in
     {"auto", "direct", "fft"} selects the GCC sampling form of SLRI/SSPI;
-    fd_steering in {"auto", "resident", "generated"} the FD steering operand."""
+    fd_steering in {"auto", "resident", "generated"} the FD steering operand;
+    far_field=True reads the grid rows as unit source directions."""
 
     SAMPLING = {"auto": 0, "direct": 1, "fft": 2}
     STEERING = {"auto": 0, "resident": 1, "generated": 2}
 
     def __init__(self, mics, grid, fs, N, variant, rank_or_q=0, dtype="f32", c=343.0, n_aux=2,
-                 device=0, frame_tile=1024, hbm_budget=0, sampling="auto", fd_steering="auto"):
+                 device=0, frame_tile=1024, hbm_budget=0, sampling="auto", fd_steering="auto",
+                 far_field=False):
         L = lib()
         mics = np.ascontiguousarray(mics, dtype=np.float64)
         grid = np.ascontiguousarray(grid, dtype=np.float64)
@@ -139,6 +161,7 @@ class Plan:
         o.frame_tile, o.hbm_budget = int(frame_tile), int(hbm_budget)
         o.sampling = self.SAMPLING[sampling]
         o.fd_steering = self.STEERING[fd_steering]
+        o.far_field = 1 if far_field else 0
         h = ctypes.c_void_p()
         self._h = None
         self._mics_ref = mics

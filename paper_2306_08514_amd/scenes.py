@@ -59,6 +59,19 @@ def box_grid(xs, ys, zs):
     return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
 
 
+def half_sphere_directions(step_deg=2.0):
+    """Far-field candidate directions (unit vectors from the array towards
+    the source) on the lower half sphere z <= 0 at step_deg resolution in
+    azimuth and elevation: rings at depression 0, step, ..., < 90 degrees,
+    azimuth-minor, followed by the nadir.  2 degrees gives 45 x 180 + 1 =
+    8,101 directions."""
+    el = np.deg2rad(np.arange(0.0, 90.0 - 1e-9, step_deg))
+    az = np.deg2rad(np.arange(0.0, 360.0 - 1e-9, step_deg))
+    E, A = np.meshgrid(el, az, indexing="ij")
+    u = np.stack([np.cos(E) * np.cos(A), np.cos(E) * np.sin(A), -np.sin(E)], axis=-1).reshape(-1, 3)
+    return np.concatenate([u, [[0.0, 0.0, -1.0]]], axis=0)
+
+
 # ---------------------------------------------------------------- signals --
 
 def one_over_f_noise(rng, n, pole=0.95):

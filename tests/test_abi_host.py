@@ -50,6 +50,19 @@ def test_host_plan_geometry_matches_oracle():
     assert info["device_bytes"] == 0
 
 
+def test_host_plan_far_field_geometry_matches_oracle():
+    _lib_or_skip()
+    mics = scenes.uca(8, 0.3)
+    u = scenes.half_sphere_directions(4.0)
+    p = native.Plan(mics, u, 16000.0, 1024, "sspi", 4, device=-1, far_field=True)
+    x_ref = o.tdoa_samples_far_field(mics, u, 16000.0, 343.0)
+    np.testing.assert_allclose(p.export("tdoa").reshape(x_ref.shape), x_ref, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(p.export("np"), o.max_lags(mics, 16000.0, 343.0, 2))
+    p.close()
+    with pytest.raises(native.SrpError):
+        native.Plan(mics, 1.5 * u, 16000.0, 1024, "fd", device=-1, far_field=True)
+
+
 def test_host_plan_slri_factors_match_oracle_svd():
     """U_p V_p^T (the rank-R truncation, unique when sigma_R > sigma_{R+1})
     agrees with numpy's SVD; singular values agree."""
@@ -141,6 +154,27 @@ def test_host_plan_sspi_windows_match_oracle_selection():
         lags, wts = o.sspi_select(x[q], Np[q], Q)
         np.testing.assert_array_equal(st[:, q], lags[:, 0])
         np.testing.assert_allclose(w[:, q, :], wts, rtol=0, atol=1e-14)
+
+
+def test_host_plans_of_si_and_td():
+    """TD keeps one unit-weight tap at the TDOA rounded half away from zero;
+    SI keeps every lag (U_p = Lambda_p)."""
+    _lib_or_skip()
+    cfg = scenes.workload("uca8_room125k", grid_stride=7)
+    x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+    P, J = x.shape
+    td = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], "td", device=-1)
+    st = td.export("sspi_start").reshape(J, P)
+    np.testing.assert_array_equal(st.T, np.sign(x) * np.floor(np.abs(x) + 0.5))
+    np.testing.assert_array_equal(td.export("sspi_w"), 1.0)
+    si = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], "si", device=-1)
+    R = si.info()["rank_or_q"]
+    assert R == 2 * Np.max() + 1
+    U = si.export("slri_u").reshape(P, J, R)
+    for q in range(P):
+        lam = o.interp_matrix(x[q], Np[q])
+        np.testing.assert_allclose(U[q][:, :lam.shape[1]], lam, rtol=0, atol=1e-12)
 
 
 def test_mac_counts_follow_complexity_model():

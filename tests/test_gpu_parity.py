@@ -43,6 +43,9 @@ def _oracle_maps(variant, Y, cfg, rq, cols=None):
         xs = x if cols is None else x[:, cols]
         return o.fd_map(psi, xs, K)
     xi = o.gcc_samples_ifft(psi, Np, K)
+    if variant in ("si", "td"):
+        xs = x if cols is None else x[:, cols]
+        return (o.si_map if variant == "si" else o.td_map)(xi, xs, Np)
     if variant == "slri":
         fac = o.slri_factors(x, Np, rq)
         if cols is not None:
@@ -203,6 +206,19 @@ def test_fd_generated_steering(native, sq4, room_small, dtype):
         if dtype == "f32":
             zr = _plan(native, cfg, "fd", 0, dtype).compute(Yt).cpu().numpy()
             assert (np.linalg.norm(z - zr, axis=1) / np.linalg.norm(zr, axis=1)).max() <= 1e-5
+
+
+@pytest.mark.parametrize("variant", ["si", "td"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_si_and_td_variants(native, sq4, room_small, variant, dtype):
+    """SI-SRP (44), every lag interpolated, and conv. TD-SRP (23), the GCC at
+    the rounded TDOA, against their FP64 oracles."""
+    for cfg, Y in (sq4, room_small):
+        _announce(f"{variant} {cfg['name']} {dtype}")
+        p = _plan(native, cfg, variant, 0, dtype)
+        assert p.info()["variant"] == native.VARIANTS[variant]
+        z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
+        _check_maps(z, _oracle_maps(variant, Y, cfg, 0), TOL[dtype], f"{variant} {cfg['name']} {dtype}")
 
 
 # ---------------------------------------------------------- edge cases ----

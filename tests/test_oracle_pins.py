@@ -73,6 +73,31 @@ def test_tdoa_pair_relation_antisymmetry_and_range():
     np.testing.assert_allclose(xc, np.linalg.norm(mics[m] - mics[mp]) * fs / c, rtol=1e-12)
 
 
+def test_far_field_tdoa_is_the_far_limit_of_the_near_field_model():
+    """Sec. II-A: for a source at distance R along u the near-field TDOA
+    tends to -(r_m - r_m')^T u fs / c, with an error below d^2 / (2 R)
+    samples; a direction along r_m - r_m' (source on m's side) gives -d, the
+    opposite direction +d, a direction orthogonal to the pair 0."""
+    from paper_2306_08514_amd import scenes
+    rng = np.random.default_rng(7)
+    mics = rng.uniform(-0.3, 0.3, (6, 3))
+    u = scenes.half_sphere_directions(6.0)
+    fs, c, R = 16000.0, 343.0, 1e6
+    assert np.allclose(np.linalg.norm(u, axis=1), 1.0, atol=1e-15)
+    x_ff = o.tdoa_samples_far_field(mics, u, fs, c)
+    x_nf = o.tdoa_samples(mics, R * u, fs, c)
+    dmax = max(np.linalg.norm(mics[m] - mics[mp]) for m, mp in o.pairs(6))
+    np.testing.assert_allclose(x_ff, x_nf, rtol=0, atol=dmax ** 2 / (2 * R) * fs / c + 1e-8)
+    m, mp = o.pairs(6)[3]
+    dv = mics[m] - mics[mp]
+    d = np.linalg.norm(dv)
+    orth = np.cross(dv, [0.0, 0.0, 1.0])
+    dirs = np.stack([dv / d, -dv / d, orth / np.linalg.norm(orth)])
+    np.testing.assert_allclose(o.tdoa_samples_far_field(mics, dirs, fs, c)[3], [-d * fs / c, d * fs / c, 0.0],
+                               atol=1e-12)
+    assert len(scenes.half_sphere_directions(2.0)) == 45 * 180 + 1
+
+
 def test_pair_order_is_sum_order_of_eq8():
     assert o.pairs(4) == [(1, 0), (2, 0), (3, 0), (2, 1), (3, 1), (3, 2)]
     assert len(o.pairs(32)) == 496
