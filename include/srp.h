@@ -109,6 +109,11 @@ typedef struct {
                             the array towards the source (Sec. II-A, the far
                             limit of (3)): x_p = -(r_m - r_m')^T u fs / c;
                             rows must have unit length (|1 - |u|| <= 1e-6) */
+  int global_fit;        /* SLRI only, 1: the paper's global form of (54),
+                            one rank-R truncated SVD of the stacked J x PN
+                            Lambda of (43) (rank_or_q = R_Lambda, the total
+                            rank, R_Lambda <= PN <= 4096) instead of one
+                            rank-R fit per pair; 0 (default): per pair */
 } srp_opts;
 
 typedef struct {

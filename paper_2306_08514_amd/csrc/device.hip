@@ -914,6 +914,34 @@ __global__ __launch_bounds__(256) void slri_fat(const float* __restrict__ xiT, i
     if (r < R) gl[p * R + r] = cvt<TG>(acc[r] * sc);
 }
 
+// Global SLRI fat stage g = Lambda_fat xi (eq. (57) with the stacked fit of
+// (54)): g[l][c] = scale * sum_a V[a][c] xi[l][a] over all PN stacked
+// samples, 32 columns per block row (V zero-padded to Kc columns, so the
+// padding columns come out zero).
+template <typename TG>
+__global__ __launch_bounds__(256) void slri_fat_global(const float* __restrict__ xiT, int64_t ldxi, int L,
+                                                       int PN, const float* __restrict__ V, int Kc,
+                                                       const float* __restrict__ gscale, TG* __restrict__ g) {
+  const int64_t l = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int c0 = blockIdx.y * 32;
+  if (l >= L) return;
+  float acc[32];
+#pragma unroll
+  for (int r = 0; r < 32; ++r) acc[r] = 0.0f;
+  const float* xs = xiT + l;
+#pragma unroll 2
+  for (int a = 0; a < PN; ++a) {
+    const float xv = xs[static_cast<int64_t>(a) * ldxi];
+    const float* va = V + static_cast<int64_t>(a) * Kc + c0;
+#pragma unroll
+    for (int r = 0; r < 32; ++r) acc[r] = __builtin_fmaf(va[r], xv, acc[r]);
+  }
+  const float sc = gscale[0];
+  TG* gl = g + l * Kc + c0;
+#pragma unroll
+  for (int r = 0; r < 32; ++r) gl[r] = cvt<TG>(acc[r] * sc);
+}
+
 // ====================================================== SLRI tall stream ===
 //
 // z[l][j] = alpha * sum_c g[l][c] U[j][c] (the tall stage of eq. (57)) for the
@@ -1366,6 +1394,117 @@ __global__ __launch_bounds__(256) void slri_u_f64(const double* __restrict__ x, 
   }
 }
 
+// Gram matrix G = Lambda^T Lambda of the stacked J x PN interpolation
+// matrix (43) for the global fit of (54).  Same tiling and MFMA lane layout
+// as gram_f64; stacked column a belongs to pair pa[a] at lag la[a], so every
+// lane evaluates its own rows' sinc from that pair's TDOA.  Block = one
+// 64 x 64 tile (ta <= tb) over candidates [j0, j1) of split blockIdx.y;
+// partial tiles go to G [split][PN][PN] (summed on the host).
+__global__ __launch_bounds__(256) void gram_global_f64(const double* __restrict__ x, int64_t J,
+                                                       const int32_t* __restrict__ pa,
+                                                       const int32_t* __restrict__ la, int PN, int ntile,
+                                                       int64_t jchunk, double* __restrict__ G) {
+  int t = blockIdx.x, ta = 0;
+  while (t >= ntile - ta) {
+    t -= ntile - ta;
+    ++ta;
+  }
+  const int tb = ta + t;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wx = (wave >> 1) * 32, ww = (wave & 1) * 32;
+  const int r16 = lane & 15, g = lane >> 4;
+  int ra[2], cb[2];
+  const double* xa[2];
+  const double* xb[2];
+  int na[2], nb[2];
+  for (int a = 0; a < 2; ++a) {
+    ra[a] = ta * 64 + wx + a * 16 + r16;
+    const int rr = min(ra[a], PN - 1);
+    xa[a] = x + static_cast<int64_t>(pa[rr]) * J;
+    na[a] = la[rr];
+  }
+  for (int b = 0; b < 2; ++b) {
+    cb[b] = tb * 64 + ww + b * 16 + r16;
+    const int cc = min(cb[b], PN - 1);
+    xb[b] = x + static_cast<int64_t>(pa[cc]) * J;
+    nb[b] = la[cc];
+  }
+  f64x4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.0;
+  const int64_t j0 = static_cast<int64_t>(blockIdx.y) * jchunk;
+  const int64_t j1 = min(J, j0 + jchunk);
+  for (int64_t jb = j0; jb < j1; jb += 4) {
+    const int64_t j = jb + g;
+    const bool ok = j < j1;
+    double fa[2], fb[2];
+    for (int a = 0; a < 2; ++a) {
+      const double xv = ok ? xa[a][j] : 0.0;
+      const double k0 = rint(xv), sr = sin(M_PI * (xv - k0));
+      fa[a] = (ok && ra[a] < PN) ? sinc_red(xv, k0, sr, na[a]) : 0.0;
+    }
+    for (int b = 0; b < 2; ++b) {
+      const double xv = ok ? xb[b][j] : 0.0;
+      const double k0 = rint(xv), sr = sin(M_PI * (xv - k0));
+      fb[b] = (ok && cb[b] < PN) ? sinc_red(xv, k0, sr, nb[b]) : 0.0;
+    }
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+  }
+  double* Gs = G + static_cast<int64_t>(blockIdx.y) * PN * PN;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int col = cb[b];
+      if (col >= PN) continue;
+      for (int v = 0; v < 4; ++v) {
+        const int row = ta * 64 + wx + a * 16 + 4 * v + g;
+        if (row >= PN) continue;
+        Gs[static_cast<int64_t>(row) * PN + col] = acc[a][b][v];
+        Gs[static_cast<int64_t>(col) * PN + row] = acc[a][b][v];
+      }
+    }
+}
+
+// U = Lambda V for the global fit (left singular vectors times singular
+// values) into the FP32 staging matrix Us [Jpad][Kc], columns 0..R-1.  One
+// thread per candidate and 8 columns per pass; pair by pair, the TDOA and
+// its reduced sine are formed once and V's rows of that pair staged in LDS.
+__global__ __launch_bounds__(256) void slri_u_global_f64(const double* __restrict__ x, int64_t J,
+                                                         const int32_t* __restrict__ np,
+                                                         const int32_t* __restrict__ off, int P, int R,
+                                                         const double* __restrict__ V, float* __restrict__ Us,
+                                                         int Kc) {
+  constexpr int AR = 576;  // >= 2 N_p + 1 of every pair (checked on the host)
+  __shared__ double vs[AR * 8];
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int r0 = blockIdx.y * 8;
+  const int rc = min(8, R - r0);
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int p = 0; p < P; ++p) {
+    const int npp = np[p], n = 2 * npp + 1;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * 8; e += 256) {
+      const int a = e / 8, c = e % 8;
+      vs[e] = c < rc ? V[static_cast<int64_t>(off[p] + a) * R + r0 + c] : 0.0;
+    }
+    __syncthreads();
+    if (j < J) {
+      const double xv = x[static_cast<int64_t>(p) * J + j];
+      const double k0 = rint(xv), sr = sin(M_PI * (xv - k0));
+      for (int a = 0; a < n; ++a) {
+        const double lam = sinc_red(xv, k0, sr, a - npp);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = fma(lam, vs[a * 8 + c], acc[c]);
+      }
+    }
+  }
+  if (j < J) {
+    float* dst = Us + j * Kc + r0;
+    for (int c = 0; c < rc; ++c) dst[c] = static_cast<float>(acc[c]);
+  }
+}
+
 // max |U_p| over the staged columns of pair p (per-pair FP8 scale).
 __global__ __launch_bounds__(256) void pair_absmax(const float* __restrict__ Us, int64_t J, int Kc, int R,
                                                    float* __restrict__ out) {
@@ -1438,7 +1577,10 @@ __global__ __launch_bounds__(256) void sspi_windows(const double* __restrict__ x
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) win[static_cast<int64_t>(blockIdx.x) * P + p] = make_int2(rlo[0], rhi[0] + q - rlo[0]);
+  // the gather reads Q taps from every start (taps past q_p carry zero
+  // weight), so the staged window covers Q rows past the last start; rows
+  // past PN are staged as zeros
+  if (threadIdx.x == 0) win[static_cast<int64_t>(blockIdx.x) * P + p] = make_int2(rlo[0], rhi[0] + Q - rlo[0]);
 }
 
 // Steering operand of conv. FD-SRP: H[j][p Kp + 2 (k-1) + {0,1}] =
@@ -1568,6 +1710,97 @@ int host_threads() {
   return static_cast<int>(std::min(std::max(n, 1u), 16u));
 }
 
+// Global SLRI operands (eq. (54) over the stacked Lambda): the PN x PN Gram
+// matrix on the device in FP64 (candidate range split across blocks, the
+// partial sums added on the host), its eigenvectors on the host, then
+// U = Lambda V on the device; a single FP8 weight scale and activation
+// scale, as for one pair.
+static void build_slri_global_device(HostPlan& hp, DevicePlan& dp, Alloc& A, const double* dx) {
+  const int PN = hp.PN, R = hp.R, P = hp.P;
+  if (2 * hp.max_np + 1 > 576) throw Error{SRP_E_UNSUPPORTED, "global SLRI stages at most 576 lags per pair"};
+  std::vector<int32_t> pa(PN), la(PN);
+  for (int p = 0; p < P; ++p)
+    for (int i = 0; i < 2 * hp.np[p] + 1; ++i) {
+      pa[hp.off[p] + i] = p;
+      la[hp.off[p] + i] = i - hp.np[p];
+    }
+  TmpBuf dpa(PN * 4), dla(PN * 4);
+  upload(static_cast<int32_t*>(dpa.p), pa);
+  upload(static_cast<int32_t*>(dla.p), la);
+  const int ntile = (PN + 63) / 64;
+  const int tiles = ntile * (ntile + 1) / 2;
+  // enough candidate splits to give every CU a few blocks, within ~1 GB of partials
+  int splits = std::max(1, std::min<int>(static_cast<int>((hp.J + 4095) / 4096), (1024 + tiles - 1) / tiles));
+  while (splits > 1 && static_cast<double>(splits) * PN * PN * 8 > 1e9) --splits;
+  const int64_t jchunk = round_up((hp.J + splits - 1) / splits, 4);
+  const size_t gn = static_cast<size_t>(splits) * PN * PN;
+  TmpBuf dg(gn * sizeof(double));
+  hipLaunchKernelGGL(gram_global_f64, dim3(static_cast<unsigned>(tiles), static_cast<unsigned>(splits)), dim3(256), 0,
+                     0, dx, hp.J, dpa.as<int32_t>(), dla.as<int32_t>(), PN, ntile, jchunk, dg.as<double>());
+  check_launch("gram_global_f64");
+  std::vector<double> gall(gn);
+  HIP_OK(hipMemcpy(gall.data(), dg.p, gn * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> G(static_cast<size_t>(PN) * PN, 0.0);
+  parallel_for(PN, host_threads(), [&](int a) {
+    for (int sidx = 0; sidx < splits; ++sidx) {
+      const double* src = &gall[(static_cast<size_t>(sidx) * PN + a) * PN];
+      double* dst = &G[static_cast<size_t>(a) * PN];
+      for (int b = 0; b < PN; ++b) dst[b] += src[b];
+    }
+  });
+  std::vector<double>().swap(gall);
+  slri_fit_global(hp, G);
+  // U = Lambda V, staged in FP32 as [Jpad][Kc]
+  const size_t ucount = static_cast<size_t>(dp.Jpad) * dp.Kc;
+  TmpBuf dv(hp.V.size() * sizeof(double));
+  upload(dv.p, hp.V);
+  TmpBuf us(ucount * sizeof(float));
+  HIP_OK(hipMemset(us.p, 0, ucount * sizeof(float)));
+  hipLaunchKernelGGL(slri_u_global_f64, dim3(static_cast<unsigned>((hp.J + 255) / 256), static_cast<unsigned>((R + 7) / 8)),
+                     dim3(256), 0, 0, dx, hp.J, dp.d_np, dp.d_off, P, R, dv.as<double>(), us.as<float>(), dp.Kc);
+  check_launch("slri_u_global_f64");
+  float sigma = 1.0f;
+  if (hp.dtype == SRP_FP8_E4M3) {
+    TmpBuf um(sizeof(float));
+    hipLaunchKernelGGL(pair_absmax, dim3(1), dim3(256), 0, 0, us.as<float>(), hp.J, dp.Kc, R, um.as<float>());
+    check_launch("pair_absmax");
+    float umax = 0.0f;
+    HIP_OK(hipMemcpy(&umax, um.p, sizeof(float), hipMemcpyDeviceToHost));
+    if (umax > 0) sigma = static_cast<float>(std::exp2(std::ceil(std::log2(umax / 448.0))));
+    std::vector<float> inv(1, 1.0f / sigma);
+    TmpBuf di(sizeof(float));
+    upload(di.as<float>(), inv);
+    hipLaunchKernelGGL(scale_pairs, dim3(static_cast<unsigned>((ucount + 255) / 256)), dim3(256), 0, 0,
+                       us.as<float>(), dp.Jpad, dp.Kc, R, 1, di.as<float>());
+    check_launch("scale_pairs");
+    HIP_OK(hipDeviceSynchronize());
+  }
+  // activation bound: |g_c| <= sigma * sum_a |V[a][c]| * 2 (K - 1)
+  double vl1 = 0;
+  for (int r = 0; r < R; ++r) {
+    double sum = 0;
+    for (int a = 0; a < PN; ++a) sum += std::fabs(hp.V[static_cast<size_t>(a) * R + r]);
+    vl1 = std::max(vl1, sum);
+  }
+  const double amax_act = sigma * vl1 * 2.0 * (hp.K - 1);
+  double act = 1.0;
+  if (hp.dtype == SRP_FP8_E4M3) act = std::exp2(std::ceil(std::log2(amax_act / 448.0)));
+  if (hp.dtype == SRP_F16 && amax_act > 60000.0) act = std::exp2(std::ceil(std::log2(amax_act / 60000.0)));
+  std::vector<float> gscale(1, static_cast<float>(sigma / act));
+  dp.tall_alpha = static_cast<float>(act);
+  dp.d_U = A.get(ucount * dsize(hp.dtype));
+  convert_dtype(hp.dtype, us.as<float>(), dp.d_U, static_cast<int64_t>(ucount));
+  HIP_OK(hipDeviceSynchronize());
+  // V as FP32 [PN][Kc], zero past column R
+  std::vector<float> Vf(static_cast<size_t>(PN) * dp.Kc, 0.0f);
+  for (int a = 0; a < PN; ++a)
+    for (int r = 0; r < R; ++r) Vf[static_cast<size_t>(a) * dp.Kc + r] = static_cast<float>(hp.V[static_cast<size_t>(a) * R + r]);
+  dp.d_V = static_cast<float*>(A.get(Vf.size() * 4));
+  upload(dp.d_V, Vf);
+  dp.d_gscale = static_cast<float*>(A.get(4));
+  upload(dp.d_gscale, gscale);
+}
+
 void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budget) {
   (void)frame_tile;
   dp.device = -1;
@@ -1676,9 +1909,13 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     // FP8 operands, to a multiple of four MFMA steps of the tall kernel
     const int es = static_cast<int>(dsize(hp.dtype));
     const int elem_per_slice = std::max(BIG_BKB / es, hp.dtype == SRP_F32 ? 0 : 4 * TALL_STEP_BYTES(hp.dtype) / es);
-    dp.Kc = static_cast<int>(round_up(static_cast<int64_t>(P) * R, elem_per_slice));
+    dp.Kc = static_cast<int>(round_up(static_cast<int64_t>(hp.global_fit ? 1 : P) * R, elem_per_slice));
     TmpBuf dx(hp.x.size() * sizeof(double));
     upload(dx.p, hp.x);
+    if (hp.global_fit) {
+      build_slri_global_device(hp, dp, A, dx.as<double>());
+      return;
+    }
     // Gram matrices on the device (FP64 MFMA), eigenvectors on the host
     // (SI keeps every lag: V = I from the host plan, no fit)
     if (hp.form != SRP_SI) {
@@ -2084,6 +2321,13 @@ void launch_slices(const HostPlan& hp, DevicePlan& dp, const void* frames, int64
 template <typename TG>
 void launch_fat(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t ldxi, int64_t Lc, void* g,
                 hipStream_t st) {
+  if (hp.global_fit) {
+    dim3 g2(static_cast<unsigned>((Lc + 255) / 256), static_cast<unsigned>(dp.Kc / 32));
+    TRACED(dp, "slri_fat", st,
+           hipLaunchKernelGGL(slri_fat_global<TG>, g2, dim3(256), 0, st, xiT, ldxi, static_cast<int>(Lc), hp.PN,
+                              dp.d_V, dp.Kc, dp.d_gscale, static_cast<TG*>(g)));
+    return;
+  }
   {
     const int vrows = 2 * hp.max_np + 1;
     dim3 g2(static_cast<unsigned>((Lc + 255) / 256), static_cast<unsigned>(hp.P + 1));

@@ -402,6 +402,77 @@ void build_slri(HostPlan& hp, int R, int threads) {
   });
 }
 
+void slri_fit_global(HostPlan& hp, std::vector<double>& G) {
+  const int n = hp.PN;
+  std::vector<double> ev, vec;
+  if (n <= 64)
+    sym_eig(G, n, ev, vec);
+  else
+    sym_eig_tridiag(G, n, ev, vec);
+  for (int i = 0; i < n; ++i) hp.sv[i] = std::sqrt(std::max(0.0, ev[i]));
+  for (int a = 0; a < n; ++a)
+    for (int r = 0; r < hp.R; ++r) hp.V[static_cast<size_t>(a) * hp.R + r] = vec[static_cast<size_t>(a) * n + r];
+}
+
+void build_slri_global(HostPlan& hp, int R, int threads) {
+  if (R < 1) fail("rank must be >= 1");
+  const int n = hp.PN;
+  if (n > 4096)
+    throw Error{SRP_E_UNSUPPORTED, "global SLRI decomposes the PN x PN Gram matrix; PN above 4096 is not built"};
+  hp.R = std::min(R, n);
+  hp.rp.assign(hp.P, 0);
+  hp.V.assign(static_cast<size_t>(n) * hp.R, 0.0);
+  hp.sv.assign(n, 0.0);
+  if (hp.device_fit) return;  // Gram matrix and U come from the device
+  const int64_t J = hp.J;
+  // stacked column a <-> (pair, lag)
+  std::vector<int> pa(n), la(n);
+  for (int p = 0; p < hp.P; ++p)
+    for (int i = 0; i < 2 * hp.np[p] + 1; ++i) {
+      pa[hp.off[p] + i] = p;
+      la[hp.off[p] + i] = i - hp.np[p];
+    }
+  const int64_t CH = 512;
+  std::vector<double> lam(static_cast<size_t>(CH) * n);
+  auto fill = [&](int64_t j0, int64_t rows) {
+    parallel_for(static_cast<int>(rows), threads, [&](int r) {
+      double* row = &lam[static_cast<size_t>(r) * n];
+      for (int a = 0; a < n; ++a) row[a] = sinc_shift(hp.x[static_cast<size_t>(pa[a]) * J + j0 + r], la[a]);
+    });
+  };
+  std::vector<double> G(static_cast<size_t>(n) * n, 0.0);
+  for (int64_t j0 = 0; j0 < J; j0 += CH) {
+    const int64_t rows = std::min(CH, J - j0);
+    fill(j0, rows);
+    parallel_for(n, threads, [&](int a) {
+      double* g = &G[static_cast<size_t>(a) * n];
+      for (int64_t r = 0; r < rows; ++r) {
+        const double* row = &lam[static_cast<size_t>(r) * n];
+        const double va = row[a];
+        for (int b = a; b < n; ++b) g[b] += va * row[b];
+      }
+    });
+  }
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < a; ++b) G[static_cast<size_t>(a) * n + b] = G[static_cast<size_t>(b) * n + a];
+  slri_fit_global(hp, G);
+  // U = Lambda V (left singular vectors times singular values)
+  hp.U.assign(static_cast<size_t>(J) * hp.R, 0.0);
+  for (int64_t j0 = 0; j0 < J; j0 += CH) {
+    const int64_t rows = std::min(CH, J - j0);
+    fill(j0, rows);
+    parallel_for(static_cast<int>(rows), threads, [&](int r) {
+      const double* row = &lam[static_cast<size_t>(r) * n];
+      double* u = &hp.U[static_cast<size_t>(j0 + r) * hp.R];
+      for (int a = 0; a < n; ++a) {
+        const double v = row[a];
+        const double* Va = &hp.V[static_cast<size_t>(a) * hp.R];
+        for (int c = 0; c < hp.R; ++c) u[c] += v * Va[c];
+      }
+    });
+  }
+}
+
 void build_sspi(HostPlan& hp, int Q, int threads) {
   if (Q < 1) fail("Q must be >= 1");
   const int nmax = 2 * hp.max_np + 1;
@@ -464,6 +535,8 @@ void count_macs(HostPlan& hp) {
   const double samp = hp.fft ? 8.0 * hp.P * hp.K * std::log2(2.0 * hp.K) : 2.0 * hp.PN * (hp.K - 1);
   if (hp.variant == SRP_FD) {
     hp.macs_per_map = 2.0 * J * hp.P * (hp.K - 1);
+  } else if (hp.variant == SRP_SLRI && hp.global_fit) {
+    hp.macs_per_map = J * hp.R + static_cast<double>(hp.R) * hp.PN + samp;  // (61)
   } else if (hp.variant == SRP_SLRI) {
     double tall = 0, fat = 0;
     for (int p = 0; p < hp.P; ++p) {

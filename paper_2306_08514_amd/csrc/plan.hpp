@@ -49,9 +49,10 @@ struct HostPlan {
   std::vector<double> w;        // [J][P][Q], zero for q >= Q_p
 
   bool fft = false;  // GCC sampling by the iFFT of (46) instead of the direct product of (40)
-  bool device_fit = false;
-  int fd_steering = 0;
-  bool far_field = false;  // grid rows are unit directions (far-field TDOAs)  // FD steering operand: 0 auto, 1 resident, 2 generated  // SLRI Gram matrices and U, SSPI windows are computed on the device
+  bool device_fit = false;  // SLRI Gram matrices and U, SSPI windows are computed on the device
+  int fd_steering = 0;      // FD steering operand: 0 auto, 1 resident, 2 generated
+  bool far_field = false;   // grid rows are unit directions (far-field TDOAs)
+  bool global_fit = false;  // SLRI: one rank-R fit of the stacked Lambda (54); SSPI: global top-Q_Lambda (55)
 
   double macs_per_map = 0;
 };
@@ -70,6 +71,16 @@ void choose_sampling(HostPlan& hp, int mode);
 // With device_fit only the ranks and the V / sv storage are set up; the
 // device builds the Gram matrices and U.
 void build_slri(HostPlan& hp, int R, int threads);
+
+// Global low-rank interpolation (Sec. IV-A, eq. (54) over the stacked
+// Lambda of (43)): the rank-R truncated SVD of the J x PN matrix, through
+// its PN x PN Gram matrix.  V [PN][R], sv [PN], U [J][R] (host plans).
+// With device_fit only the sizes are set up.
+void build_slri_global(HostPlan& hp, int R, int threads);
+
+// V and the singular values of the global fit from G = Lambda^T Lambda
+// (PN x PN row-major, destroyed).
+void slri_fit_global(HostPlan& hp, std::vector<double>& G);
 
 // V_p and the singular values of pair p from its Gram matrix
 // G = Lambda_p^T Lambda_p (n x n row-major, destroyed).

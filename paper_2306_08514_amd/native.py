@@ -35,7 +35,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("n_aux", ctypes.c_int), ("dtype", ctypes.c_int),
                 ("device", ctypes.c_int), ("frame_tile", ctypes.c_int64),
                 ("hbm_budget", ctypes.c_size_t), ("sampling", ctypes.c_int),
-                ("fd_steering", ctypes.c_int), ("far_field", ctypes.c_int)]
+                ("fd_steering", ctypes.c_int), ("far_field", ctypes.c_int),
+                ("global_fit", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -144,14 +145,15 @@ class Plan:
     "fp8", "f64"}; device = -1 builds the host-side plan only; sampling in
     {"auto", "direct", "fft"} selects the GCC sampling form of SLRI/SSPI;
     fd_steering in {"auto", "resident", "generated"} the FD steering operand;
-    far_field=True reads the grid rows as unit source directions."""
+    far_field=True reads the grid rows as unit source directions;
+    global_fit=True fits SLRI globally (rank_or_q = the total rank R_Lambda)."""
 
     SAMPLING = {"auto": 0, "direct": 1, "fft": 2}
     STEERING = {"auto": 0, "resident": 1, "generated": 2}
 
     def __init__(self, mics, grid, fs, N, variant, rank_or_q=0, dtype="f32", c=343.0, n_aux=2,
                  device=0, frame_tile=1024, hbm_budget=0, sampling="auto", fd_steering="auto",
-                 far_field=False):
+                 far_field=False, global_fit=False):
         L = lib()
         mics = np.ascontiguousarray(mics, dtype=np.float64)
         grid = np.ascontiguousarray(grid, dtype=np.float64)
@@ -162,6 +164,7 @@ class Plan:
         o.sampling = self.SAMPLING[sampling]
         o.fd_steering = self.STEERING[fd_steering]
         o.far_field = 1 if far_field else 0
+        o.global_fit = 1 if global_fit else 0
         h = ctypes.c_void_p()
         self._h = None
         self._mics_ref = mics

@@ -41,6 +41,14 @@ _TAGS = [
     (r"slri_fat", "slri_fat"),
     (r"phat_kernel", "phat"),
     (r"build_steering", "build_steering (plan)"),
+    (r"gram_f64", "gram_f64 (plan)"),
+    (r"slri_u_f64", "slri_u_f64 (plan)"),
+    (r"sspi_windows", "sspi_windows (plan)"),
+    (r"pair_absmax|scale_pairs", "scale (plan)"),
+    (r"fd_gen", "gemm_fd_gen"),
+    (r"gcc_fft", "gcc_fft"),
+    (r"transpose_lp", "transpose_lp"),
+    (r"argmax_rows", "argmax"),
     (r"convert_f32", "convert_f32 (plan)"),
     (r"transpose_xi", "transpose_xi"),
     (r"copyBuffer", "copy"),

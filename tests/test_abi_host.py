@@ -86,6 +86,40 @@ def test_host_plan_slri_factors_match_oracle_svd():
         assert np.linalg.norm(prod - ref) <= 1e-9 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("R", [8, 40, 154])
+def test_host_plan_global_slri_matches_oracle_svd(R):
+    """Global fit of (54): singular values and the rank-R product U V^T of
+    the stacked Lambda against numpy's SVD (factors are unique only up to
+    signs and rotations within equal singular values, so products are
+    compared); R = PN reproduces Lambda itself."""
+    _lib_or_skip()
+    p, cfg = _host_plan("slri", R, stride=2, global_fit=True)
+    x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+    PN, J = int(sum(2 * Np + 1)), x.shape[1]
+    assert p.info()["rank_or_q"] == min(R, PN)
+    tall, fat = o.slri_global_factors(x, Np, R)
+    U = p.export("slri_u").reshape(J, -1)
+    V = p.export("slri_v").reshape(PN, -1)
+    sv = p.export("slri_s")
+    lam = np.concatenate([o.interp_matrix(x[q], n) for q, n in enumerate(Np)], axis=1)
+    s_ref = np.linalg.svd(lam, compute_uv=False)
+    k = min(R, len(s_ref))
+    np.testing.assert_allclose(sv[:k], s_ref[:k], rtol=1e-9, atol=1e-9 * s_ref[0])
+    np.testing.assert_allclose(U @ V.T, tall @ fat, rtol=0, atol=1e-9 * s_ref[0])
+    if R >= PN:
+        np.testing.assert_allclose(U @ V.T, lam, rtol=0, atol=1e-9)
+    p.close()
+
+
+def test_global_fit_is_refused_for_other_forms():
+    _lib_or_skip()
+    cfg = scenes.workload("square4_plane1k", grid_stride=4)
+    for variant in ("fd", "sspi", "si", "td"):
+        with pytest.raises(native.SrpError):
+            native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, 4, device=-1, global_fit=True)
+
+
 def test_host_plan_slri_large_lag_counts_match_oracle_svd():
     """Pairs with up to 499 lags take the tridiagonal + QL eigensolver: the
     first eight microphones of the 2 m disc array at 48 kHz on a 200-point

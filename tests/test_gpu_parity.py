@@ -223,6 +223,26 @@ def test_si_and_td_variants(native, sq4, room_small, variant, dtype):
 
 # ---------------------------------------------------------- edge cases ----
 
+@pytest.mark.parametrize("R,dtype", [(8, "f32"), (64, "f32"), (224, "f32"), (224, "bf16"), (224, "f16"),
+                                     (224, "fp8"), (660, "f32")])
+def test_global_slri(native, sq4, room_small, R, dtype):
+    """Global fit of (54) (one rank-R_Lambda SVD of the stacked Lambda)
+    against the oracle's SVD of the same matrix; R = PN is SI itself."""
+    for cfg, Y in (sq4, room_small):
+        _announce(f"global slri R={R} {dtype} {cfg['name']} J={len(cfg['grid'])}")
+        x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+        Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+        xi = o.gcc_samples_ifft(o.phat(Y), Np, cfg["N"] // 2)
+        tall, fat = o.slri_global_factors(x, Np, R)
+        ref = o.slri_global_map(xi, tall, fat)
+        p = _plan(native, cfg, "slri", R, dtype=dtype, global_fit=True)
+        z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
+        _check_maps(z, ref, TOL[dtype], f"global slri R={R} {dtype} {cfg['name']}")
+        if R >= int(sum(2 * Np + 1)):
+            _check_maps(z, o.si_map(xi, x, Np), TOL[dtype], "global slri at full rank = SI")
+        p.close()
+
+
 def test_edge_cases(native, sq4):
     cfg, Y = sq4
     _announce("edge cases")
