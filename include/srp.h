@@ -109,11 +109,16 @@ typedef struct {
                             the array towards the source (Sec. II-A, the far
                             limit of (3)): x_p = -(r_m - r_m')^T u fs / c;
                             rows must have unit length (|1 - |u|| <= 1e-6) */
-  int global_fit;        /* SLRI only, 1: the paper's global form of (54),
-                            one rank-R truncated SVD of the stacked J x PN
-                            Lambda of (43) (rank_or_q = R_Lambda, the total
-                            rank, R_Lambda <= PN <= 4096) instead of one
-                            rank-R fit per pair; 0 (default): per pair */
+  int global_fit;        /* 1: the paper's global forms over the stacked
+                            J x PN Lambda of (43) instead of one fit per
+                            pair (0, the default).  SLRI (54): one rank-R
+                            truncated SVD, rank_or_q = R_Lambda, the total
+                            rank (PN <= 4096).  SSPI (55): the Q_Lambda =
+                            rank_or_q * J * P largest-magnitude entries
+                            (rank_or_q = mean taps per location and pair;
+                            every entry at or above the Q_Lambda-th largest
+                            magnitude is kept; at most 16 per location and
+                            pair).  Other variants: SRP_E_INVALID */
 } srp_opts;
 
 typedef struct {
@@ -144,13 +149,16 @@ void srp_default_opts(srp_opts* opts);
 /* Builds a plan (Sec. IV-B: everything that depends only on geometry and
  * frequency resolution is computed upfront, in FP64).
  *   mics      host, M x 3 row-major, metres (M >= 2)
- *   grid      host, J x 3 row-major, metres (J >= 1), near-field candidates
+ *   grid      host, J x 3 row-major (J >= 1): candidate positions in metres,
+ *             or unit source directions with opts->far_field
  *   fs        sampling rate in Hz (> 0)
  *   N         DFT length 2K (even, >= 8); requires 2 N_p + 1 <= N for every
  *             pair (lag aliasing, Sec. III-B2 footnote)
- *   variant   SRP_FD, SRP_SLRI or SRP_SSPI
- *   rank_or_q R per pair (SLRI) or Q per (location, pair) (SSPI), >= 1;
- *             clamped per pair to 2 N_p + 1; ignored for SRP_FD
+ *   variant   SRP_FD, SRP_SLRI, SRP_SSPI, SRP_SI or SRP_TD
+ *   rank_or_q R per pair (SLRI, <= 32) or Q per (location, pair) (SSPI,
+ *             <= 16), >= 1, clamped per pair to 2 N_p + 1; with
+ *             opts->global_fit the total rank R_Lambda (SLRI) or the mean
+ *             taps per (location, pair) (SSPI); ignored for FD, SI and TD
  *   opts      NULL for defaults
  *   out       receives the plan, NULL on failure
  * Returns SRP_E_INVALID for bad geometry or arguments, SRP_E_UNSUPPORTED for

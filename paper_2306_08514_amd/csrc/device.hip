@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -1541,22 +1542,29 @@ __global__ void scale_pairs(float* __restrict__ Us, int64_t rows, int Kc, int R,
 template <typename TW>
 __global__ __launch_bounds__(256) void sspi_windows(const double* __restrict__ x, int64_t J,
                                                     const int32_t* __restrict__ np, const int32_t* __restrict__ off,
-                                                    int Q, int Qs, int P, int td, int32_t* __restrict__ start,
+                                                    int Qsel, int Q, int Qs, int P, int td,
+                                                    const int32_t* __restrict__ gstart,
+                                                    const int32_t* __restrict__ gcount, int32_t* __restrict__ start,
                                                     TW* __restrict__ w, int2* __restrict__ win) {
   __shared__ int rlo[256], rhi[256];
   const int p = blockIdx.y;
   const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   const int npp = np[p];
-  const int q = min(Q, 2 * npp + 1);
+  int q = min(Qsel, 2 * npp + 1);
   int sabs_lo = 0x7fffffff, sabs_hi = -0x7fffffff;
   if (j < J) {
     const double xv = x[static_cast<int64_t>(p) * J + j];
+    const int64_t rec = static_cast<int64_t>(p) * J + j;
     double s = ceil(xv - 0.5 * q);
     s = fmin(fmax(s, static_cast<double>(-npp)), static_cast<double>(npp - q + 1));
     // conv. TD-SRP (23): the lag nearest to x, half away from zero
     if (td) s = copysign(floor(fabs(xv) + 0.5), xv);
+    // global selection: the window chosen on the host
+    if (gstart) {
+      s = gstart[rec];
+      q = gcount[rec];
+    }
     const int si = static_cast<int>(s);
-    const int64_t rec = static_cast<int64_t>(p) * J + j;
     const int sabs = off[p] + si + npp;
     start[rec] = sabs;
     sabs_lo = sabs_hi = sabs;
@@ -1691,6 +1699,17 @@ constexpr int SSPI_FT = 32;                       // frames per SSPI block
 }  // namespace
 
 // Plan-time device temporary, freed on every exit path.
+// The gather is instantiated for Q = 1..8, 10, 12 and 16 taps; a selection
+// of q taps runs on the smallest instance with at least q (the extra taps
+// carry zero weight).
+int gather_q(int q) {
+  if (q <= 8) return std::max(q, 1);
+  if (q <= 10) return 10;
+  if (q <= 12) return 12;
+  if (q <= 16) return 16;
+  throw Error{SRP_E_UNSUPPORTED, "SSPI with more than 16 taps per (location, pair) is not built"};
+}
+
 struct TmpBuf {
   void* p = nullptr;
   explicit TmpBuf(size_t bytes) { HIP_OK(hipMalloc(&p, std::max<size_t>(bytes, 1))); }
@@ -1998,9 +2017,17 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
   // SSPI
   if (hp.dtype == SRP_F64) throw Error{SRP_E_UNSUPPORTED, "SSPI has no FP64 path"};
   {
-    const int Q = hp.Q;
+    const int Q = gather_q(hp.Q);  // taps the gather kernel reads (zero-weighted past the selection)
+    dp.sspi_q = Q;
     const int es = static_cast<int>(dsize(hp.dtype));
     const int Qs = static_cast<int>(round_up(Q * es, 4) / es);
+    std::unique_ptr<TmpBuf> dgs, dgc;
+    if (hp.global_fit) {
+      dgs.reset(new TmpBuf(hp.gstart.size() * 4));
+      dgc.reset(new TmpBuf(hp.gcount.size() * 4));
+      upload(dgs->p, hp.gstart);
+      upload(dgc->p, hp.gcount);
+    }
     // device layouts are pair-major ([P][J] and [P][J][Qs]) so that lanes
     // (consecutive locations) load consecutive records
     TmpBuf dx(hp.x.size() * sizeof(double));
@@ -2011,8 +2038,9 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     dp.d_win = static_cast<int2*>(A.get(static_cast<size_t>(njt) * P * sizeof(int2)));
     const dim3 gw(static_cast<unsigned>(njt), static_cast<unsigned>(P));
 #define SRP_WIN(TW)                                                                                           \
-  hipLaunchKernelGGL(sspi_windows<TW>, gw, dim3(256), 0, 0, dx.as<double>(), hp.J, dp.d_np, dp.d_off, Q, Qs,   \
-                     P, hp.form == SRP_TD ? 1 : 0, dp.d_start, static_cast<TW*>(dp.d_w), dp.d_win)
+  hipLaunchKernelGGL(sspi_windows<TW>, gw, dim3(256), 0, 0, dx.as<double>(), hp.J, dp.d_np, dp.d_off, hp.Q, Q, \
+                     Qs, P, hp.form == SRP_TD ? 1 : 0, dgs ? dgs->as<int32_t>() : nullptr,                     \
+                     dgc ? dgc->as<int32_t>() : nullptr, dp.d_start, static_cast<TW*>(dp.d_w), dp.d_win)
     switch (hp.dtype) {
       case SRP_F32: SRP_WIN(float); break;
       case SRP_BF16: SRP_WIN(__bf16); break;
@@ -2398,7 +2426,7 @@ void launch_sspi_q(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t
 template <typename TW>
 void launch_sspi(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t Lpad, int64_t Lc,
                  float* z, int64_t ldz, hipStream_t st) {
-  switch (hp.Q) {
+  switch (dp.sspi_q) {
     case 1: launch_sspi_q<TW, 1>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
     case 2: launch_sspi_q<TW, 2>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
     case 3: launch_sspi_q<TW, 3>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
@@ -2407,7 +2435,10 @@ void launch_sspi(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t L
     case 6: launch_sspi_q<TW, 6>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
     case 7: launch_sspi_q<TW, 7>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
     case 8: launch_sspi_q<TW, 8>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
-    default: throw Error{SRP_E_UNSUPPORTED, "SSPI with Q above 8 is not built"};
+    case 10: launch_sspi_q<TW, 10>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
+    case 12: launch_sspi_q<TW, 12>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
+    case 16: launch_sspi_q<TW, 16>(hp, dp, xiT, Lpad, Lc, z, ldz, st); break;
+    default: throw Error{SRP_E_UNSUPPORTED, "SSPI gather with this Q is not built"};
   }
 }
 

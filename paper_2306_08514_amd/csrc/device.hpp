@@ -53,6 +53,7 @@ struct DevicePlan {
   void* d_w = nullptr;         // [J][P][Q] in dtype (f32, bf16, f16 or fp8)
   int2* d_win = nullptr;          // [J / 256 tiles][P] (first row, rows) lag window of a tile
   int sspi_cap = 0;               // LDS rows per staged chunk of the gather
+  int sspi_q = 0;                 // taps per record read by the gather (>= the selection's Q)
   // per-kernel timing (see srp_profile_enable)
   struct Span {
     const char* name;

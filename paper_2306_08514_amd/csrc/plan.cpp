@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstring>
 #include <functional>
 #include <limits>
 #include <thread>
@@ -512,6 +513,140 @@ void build_sspi(HostPlan& hp, int Q, int threads) {
   });
 }
 
+namespace {
+
+// Lags n in [-N, N] with |sinc(x - n)| >= tau, x = k0 + r with the reduced
+// sine sr = |sin(pi r)|: |sinc(x - n)| = sr / (pi |x - n|) for n != x, so
+// they are the lags within sr / (pi tau) of x, a contiguous run [lo, hi].
+// At integer x only n = x (value 1) is nonzero.
+inline void kept_window(double x, double sr, int N, double tau, int& lo, int& hi) {
+  if (tau > 1.0) {
+    lo = 0;
+    hi = -1;
+    return;
+  }
+  if (sr == 0.0) {
+    lo = hi = static_cast<int>(x);
+    return;
+  }
+  const double d = sr / (M_PI * tau);
+  lo = static_cast<int>(std::max(std::ceil(x - d), static_cast<double>(-N)));
+  hi = static_cast<int>(std::min(std::floor(x + d), static_cast<double>(N)));
+}
+
+}  // namespace
+
+void build_sspi_global(HostPlan& hp, int qbar, int threads) {
+  if (qbar < 1) fail("Q must be >= 1");
+  const int64_t J = hp.J;
+  const int P = hp.P;
+  const double target = static_cast<double>(qbar) * J * P;  // Q_Lambda
+  if (target > static_cast<double>(J) * hp.PN) fail("Q_Lambda = Q J P exceeds the J x PN entries of Lambda");
+  // reduced sines, pair-major
+  std::vector<double> sr(static_cast<size_t>(P) * J);
+  const int chunks = 64;
+  parallel_for(chunks, threads, [&](int ch) {
+    const size_t e0 = sr.size() * ch / chunks, e1 = sr.size() * (ch + 1) / chunks;
+    for (size_t e = e0; e < e1; ++e) {
+      const double x = hp.x[e];
+      sr[e] = std::fabs(std::sin(M_PI * (x - std::nearbyint(x))));
+    }
+  });
+  auto count = [&](double tau) {
+    std::vector<double> part(chunks, 0.0);
+    parallel_for(chunks, threads, [&](int ch) {
+      const size_t e0 = sr.size() * ch / chunks, e1 = sr.size() * (ch + 1) / chunks;
+      double c = 0;
+      for (size_t e = e0; e < e1; ++e) {
+        int lo, hi;
+        kept_window(hp.x[e], sr[e], hp.np[e / J], tau, lo, hi);
+        c += std::max(0, hi - lo + 1);
+      }
+      part[ch] = c;
+    });
+    double c = 0;
+    for (double v : part) c += v;
+    return c;
+  };
+  // largest tau with count(tau) >= Q_Lambda, by bisection over the bit
+  // patterns of positive doubles (ordered like their values)
+  uint64_t lo = 1, hi;  // lo: the smallest subnormal; count(hi) < target
+  const double above = std::nextafter(1.0, 2.0);
+  std::memcpy(&hi, &above, 8);
+  while (hi - lo > 1) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    double t;
+    std::memcpy(&t, &mid, 8);
+    if (count(t) >= target) lo = mid; else hi = mid;
+  }
+  std::memcpy(&hp.tau, &lo, 8);
+  double tau_above;  // the next magnitude up: count(tau_above) < Q_Lambda
+  std::memcpy(&tau_above, &hi, 8);
+  // every entry strictly above tau ...
+  hp.gstart.assign(static_cast<size_t>(P) * J, 0);
+  hp.gcount.assign(static_cast<size_t>(P) * J, 0);
+  std::vector<double> nnz(chunks, 0.0);
+  parallel_for(chunks, threads, [&](int ch) {
+    const size_t e0 = sr.size() * ch / chunks, e1 = sr.size() * (ch + 1) / chunks;
+    for (size_t e = e0; e < e1; ++e) {
+      const int N = hp.np[e / J];
+      int a, b;
+      kept_window(hp.x[e], sr[e], N, tau_above, a, b);
+      const int c = std::max(0, b - a + 1);
+      // an empty window still needs a start inside the pair's lags
+      hp.gstart[e] = c > 0 ? a : std::min(std::max(static_cast<int>(std::nearbyint(hp.x[e])), -N), N);
+      hp.gcount[e] = c;
+      nnz[ch] += c;
+    }
+  });
+  double kept = 0;
+  for (double v : nnz) kept += v;
+  // ... then entries equal to tau, in the order of the stacked matrix
+  // (candidate-major, then pair and lag), until exactly Q_Lambda are kept.
+  // A tie lies at the threshold distance from x, so it extends a window at
+  // one of its ends and the kept lags stay contiguous.
+  for (int64_t j = 0; j < J && kept < target; ++j)
+    for (int p = 0; p < P && kept < target; ++p) {
+      const size_t e = static_cast<size_t>(p) * J + j;
+      int a, b;
+      kept_window(hp.x[e], sr[e], hp.np[p], hp.tau, a, b);
+      int s0 = hp.gstart[e], c0 = hp.gcount[e];
+      if (b - a + 1 <= c0) continue;
+      for (int n = a; n <= b && kept < target; ++n) {
+        if (c0 > 0 && n >= s0 && n < s0 + c0) continue;  // already kept
+        if (c0 == 0) {
+          s0 = n;
+        } else if (n < s0) {
+          s0 = n;
+        } else if (n != s0 + c0) {
+          continue;  // not adjacent: cannot happen for a tie, kept contiguous
+        }
+        ++c0;
+        kept += 1;
+      }
+      hp.gstart[e] = s0;
+      hp.gcount[e] = c0;
+    }
+  hp.nnz = kept;
+  hp.Q = 0;
+  for (int32_t c : hp.gcount) hp.Q = std::max(hp.Q, static_cast<int>(c));
+  hp.Q = std::max(hp.Q, 1);
+  hp.qp.assign(P, hp.Q);
+  if (hp.device_fit) return;  // the device forms the weights from the windows
+  hp.start.assign(static_cast<size_t>(J) * P, 0);
+  hp.w.assign(static_cast<size_t>(J) * P * hp.Q, 0.0);
+  parallel_for(chunks, threads, [&](int ch) {
+    const int64_t j0 = J * ch / chunks, j1 = J * (ch + 1) / chunks;
+    for (int64_t j = j0; j < j1; ++j)
+      for (int p = 0; p < P; ++p) {
+        const size_t e = static_cast<size_t>(p) * J + j;
+        hp.start[static_cast<size_t>(j) * P + p] = hp.gstart[e];
+        double* w = &hp.w[(static_cast<size_t>(j) * P + p) * hp.Q];
+        for (int t = 0; t < hp.gcount[e]; ++t) w[t] = sinc_shift(hp.x[e], hp.gstart[e] + t);
+      }
+  });
+}
+
 void choose_sampling(HostPlan& hp, int mode) {
   const bool pow2 = hp.N >= 8 && hp.N <= 4096 && (hp.N & (hp.N - 1)) == 0;
   const double direct = 2.0 * hp.PN * (hp.K - 1);
@@ -544,6 +679,8 @@ void count_macs(HostPlan& hp) {
       if (hp.form != SRP_SI) fat += static_cast<double>(hp.rp[p]) * (2 * hp.np[p] + 1);  // SI: V = I
     }
     hp.macs_per_map = tall + fat + samp;
+  } else if (hp.global_fit) {
+    hp.macs_per_map = hp.nnz + samp;  // (62) with the kept entries Q_Lambda
   } else {
     double nnz = 0;
     for (int p = 0; p < hp.P; ++p) nnz += J * hp.qp[p];

@@ -47,6 +47,12 @@ struct HostPlan {
   std::vector<int32_t> qp;      // Q_p
   std::vector<int32_t> start;   // [J][P] first lag s (in -N_p..N_p)
   std::vector<double> w;        // [J][P][Q], zero for q >= Q_p
+  // global SSPI (55): every entry of the stacked Lambda with |Lambda| >= tau,
+  // tau the Q_Lambda-th largest magnitude; per (j, p) a window of gcount
+  // nearest lags from gstart (pair-major [P][J])
+  double tau = 0;
+  double nnz = 0;                 // entries kept
+  std::vector<int32_t> gstart, gcount;
 
   bool fft = false;  // GCC sampling by the iFFT of (46) instead of the direct product of (40)
   bool device_fit = false;  // SLRI Gram matrices and U, SSPI windows are computed on the device
@@ -90,6 +96,10 @@ void parallel_for(int n, int threads, const std::function<void(int)>& body);
 
 // Per-(location, pair) Q-tap windows (Sec. IV-A, eq. (55) per row and pair).
 void build_sspi(HostPlan& hp, int Q, int threads);
+
+// Global sparse interpolation (Sec. IV-A, eq. (55) over the stacked
+// Lambda): keep the Q_Lambda = qbar J P largest-magnitude entries.
+void build_sspi_global(HostPlan& hp, int qbar, int threads);
 
 // Run-time MAC counts per map (eqs. (24), (61), (62); sampling by the
 // direct product, 2 PN (K-1)).

@@ -146,7 +146,8 @@ class Plan:
     {"auto", "direct", "fft"} selects the GCC sampling form of SLRI/SSPI;
     fd_steering in {"auto", "resident", "generated"} the FD steering operand;
     far_field=True reads the grid rows as unit source directions;
-    global_fit=True fits SLRI globally (rank_or_q = the total rank R_Lambda)."""
+    global_fit=True selects the global forms: SLRI with rank_or_q = the
+    total rank R_Lambda, SSPI with Q_Lambda = rank_or_q J P kept entries."""
 
     SAMPLING = {"auto": 0, "direct": 1, "fft": 2}
     STEERING = {"auto": 0, "resident": 1, "generated": 2}

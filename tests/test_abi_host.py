@@ -112,10 +112,40 @@ def test_host_plan_global_slri_matches_oracle_svd(R):
     p.close()
 
 
+@pytest.mark.parametrize("name,stride", [("square4_plane1k", 2), ("uca8_room125k", 3)])
+@pytest.mark.parametrize("qbar", [1, 2, 4])
+def test_host_plan_global_sspi_matches_oracle_selection(qbar, name, stride):
+    """Global selection of (55): the kept entries of the stacked Lambda are
+    the oracle's Q_Lambda = qbar J P largest magnitudes, with their values,
+    exactly Q_Lambda of them (the room grid has exact magnitude ties at the
+    threshold for qbar = 2 and 4, settled in the stacked matrix's order)."""
+    _lib_or_skip()
+    p, cfg = _host_plan("sspi", qbar, name=name, stride=stride, global_fit=True)
+    x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+    J, P = x.shape[1], len(Np)
+    ref = o.sspi_global_select(x, Np, qbar * J * P)
+    Q = p.info()["rank_or_q"]
+    start = p.export("sspi_start").reshape(J, P)
+    w = p.export("sspi_w").reshape(J, P, Q)
+    off = np.concatenate([[0], np.cumsum(2 * Np + 1)])
+    dense = np.zeros_like(ref)
+    for q in range(P):
+        for t in range(Q):
+            nz = w[:, q, t] != 0
+            cols = off[q] + start[nz, q] + t + Np[q]
+            dense[np.nonzero(nz)[0], cols] = w[nz, q, t]
+    assert np.count_nonzero(dense) == np.count_nonzero(ref) == qbar * J * P
+    np.testing.assert_array_equal(dense != 0, ref != 0)
+    np.testing.assert_allclose(dense, ref, rtol=0, atol=1e-14)
+    assert 1 <= Q <= 16
+    p.close()
+
+
 def test_global_fit_is_refused_for_other_forms():
     _lib_or_skip()
     cfg = scenes.workload("square4_plane1k", grid_stride=4)
-    for variant in ("fd", "sspi", "si", "td"):
+    for variant in ("fd", "si", "td"):
         with pytest.raises(native.SrpError):
             native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, 4, device=-1, global_fit=True)
 
@@ -232,7 +262,7 @@ def test_mac_counts_follow_complexity_model():
     (dict(fs=-1.0), -1),
     (dict(variant="slri", rq=0), -1),
     (dict(variant="slri", rq=33), -3),
-    (dict(variant="sspi", rq=9), -3),
+    (dict(variant="sspi", rq=17), -3),
     (dict(variant="slri", rq=4, dtype="f64"), -3),
     (dict(M=1), -1),
 ])

@@ -243,6 +243,34 @@ def test_global_slri(native, sq4, room_small, R, dtype):
         p.close()
 
 
+@pytest.mark.parametrize("qbar,dtype", [(1, "f32"), (2, "f32"), (4, "f32"), (8, "f32"), (4, "bf16"), (4, "fp8"),
+                                        (8, "bf16")])
+def test_global_sspi(native, sq4, room_small, qbar, dtype):
+    """Global selection of (55) (the qbar J P largest entries of the stacked
+    Lambda, a variable number per location and pair) against the oracle's
+    dense selection."""
+    for cfg, Y in (sq4, room_small):
+        _announce(f"global sspi qbar={qbar} {dtype} {cfg['name']} J={len(cfg['grid'])}")
+        x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+        Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+        xi = o.gcc_samples_ifft(o.phat(Y), Np, cfg["N"] // 2)
+        ref = o.sspi_global_map(xi, o.sspi_global_select(x, Np, qbar * x.shape[1] * len(Np)))
+        p = _plan(native, cfg, "sspi", qbar, dtype=dtype, global_fit=True)
+        z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
+        _check_maps(z, ref, TOL[dtype], f"global sspi qbar={qbar} {dtype} {cfg['name']}")
+        p.close()
+
+
+@pytest.mark.parametrize("Q", [9, 12, 16])
+def test_sspi_more_than_eight_taps(native, sq4, Q):
+    cfg, Y = sq4
+    _announce(f"sspi Q={Q} f32 square4")
+    p = _plan(native, cfg, "sspi", Q)
+    z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
+    _check_maps(z, _oracle_maps("sspi", Y, cfg, Q), TOL["f32"], f"sspi Q={Q}")
+    p.close()
+
+
 def test_edge_cases(native, sq4):
     cfg, Y = sq4
     _announce("edge cases")
