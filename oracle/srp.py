@@ -37,9 +37,9 @@ Dirichlet-kernel map of a single pure-delay source, the exact periodic
 interpolator) and brute force (delay-and-sum output power).
 ``slri_factors_gram`` (the same truncation through the Gram matrix, for
 very tall Lambda_p) is pinned against ``slri_factors``, which the
-Eckart-Young and full-rank checks pin.  The
-far-field TDOA (3) and the LR-SRP form are pinned only by the complexity
-values of Fig. 12 and by construction checks; they are off the hot path.
+Eckart-Young and full-rank checks pin.  The far-field TDOA is pinned as the
+far limit of the near-field model; LR-SRP by full rank (= conv. FD-SRP),
+Eckart-Young optimality and its complexity (30) in Fig. 12.
 """
 
 import numpy as np
@@ -52,7 +52,7 @@ __all__ = [
     "slri_global_map", "sspi_select", "sspi_map", "sspi_global_select",
     "sspi_global_map", "dsb_power_map", "argmax_map", "rel_error",
     "eps_z_db", "eps_h_db", "complexity", "periodic_interp_map",
-    "stack_samples",
+    "stack_samples", "steering_matrix", "lr_factors", "lr_map",
 ]
 
 
@@ -159,6 +159,29 @@ def fd_map(psi, x, K, chunk=4096):
             acc += psi[:, p, :] @ H.T               # sum_k H[j,k] psi[l,k]
         z[:, j0:j1] = 2.0 * acc.real
     return z
+
+
+def steering_matrix(x, K):
+    """The single-sided SRP matrix H = [H_1 ... H_P] of (19)-(21), J x P(K-1),
+    columns ordered by pair, then bin k = 1..K-1."""
+    return np.concatenate([steering(x[p], K) for p in range(x.shape[0])], axis=1)
+
+
+def lr_factors(x, K, R):
+    """LR-SRP (Sec. II-E): the minimiser of (26) under the rank constraint
+    (27), the rank-R truncated SVD of H written as (28).  Returns
+    (H_tall = U Sigma [J, R], H_fat = V^H [R, P(K-1)], all singular values)."""
+    H = steering_matrix(x, K)
+    U, s, Vh = np.linalg.svd(H, full_matrices=False)
+    return U[:, :R] * s[:R], Vh[:R].copy(), s
+
+
+def lr_map(psi, tall, fat):
+    """LR-SRP map (29): z = 2 Re[H_tall (H_fat psi)], psi [L, P, K-1]."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    v = psi.reshape(psi.shape[0], -1)              # stacked (p, k)
+    g = v @ fat.T                                  # fat stage [L, R]
+    return 2.0 * (g @ tall.T).real                 # tall stage [L, J]
 
 
 def dsb_power_map(Y, mics, grid, fs, c):

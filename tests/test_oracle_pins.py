@@ -453,6 +453,36 @@ def test_sspi_global_selection():
     assert np.min(np.abs(sp[sp != 0])) >= np.max(np.abs(lam[sp == 0])) - 1e-15
 
 
+# ------------------------------------------------------------- LR-SRP ---
+
+def test_lr_full_rank_is_fd_and_truncation_is_eckart_young():
+    """(26)-(29): at full rank H_tall H_fat = H, so the LR map is the
+    conv. FD-SRP map (22); below it the Frobenius error of the truncation is
+    the energy of the discarded singular values, no random rank-R subspace
+    does better, and eps_H of (64) falls with R."""
+    rng = np.random.default_rng(12)
+    mics = _uca(4, 0.2)
+    grid = rng.uniform(-2, 2, (48, 3))
+    K, fs, c = 32, 8000.0, 343.0
+    x = o.tdoa_samples(mics, grid, fs, c)
+    H = o.steering_matrix(x, K)
+    assert H.shape == (48, 6 * 31)
+    np.testing.assert_allclose(H[:, 31 + 4], np.exp(1j * np.pi * 5 * x[1] / K), atol=1e-14)
+    psi = o.phat(_random_frames(rng, 5, 4, K))
+    tall, fat, sv = o.lr_factors(x, K, 48)
+    np.testing.assert_allclose(o.lr_map(psi, tall, fat), o.fd_map(psi, x, K), rtol=0, atol=1e-10)
+    prev = np.inf
+    for R in (2, 8, 20, 40):
+        tall, fat, sv = o.lr_factors(x, K, R)
+        err = np.sum(np.abs(H - tall @ fat) ** 2)
+        np.testing.assert_allclose(err, np.sum(sv[R:] ** 2), rtol=1e-9)
+        Q, _ = np.linalg.qr(rng.standard_normal((H.shape[1], R)) + 1j * rng.standard_normal((H.shape[1], R)))
+        assert np.sum(np.abs(H - H @ Q @ Q.conj().T) ** 2) >= err
+        eh = o.eps_h_db(tall @ fat, H)
+        assert eh < prev
+        prev = eh
+
+
 # ------------------------------------------------------- argmax / errors ---
 
 def test_argmax_ties_and_error_measures():
