@@ -68,9 +68,15 @@ typedef enum {
   SRP_SSPI = 2,  /* SSPI-SRP, eq. (58) */
   SRP_SI = 3,    /* SI-SRP, eq. (44): every lag of every pair interpolated;
                     rank_or_q ignored (at most 32 lags per pair) */
-  SRP_TD = 4     /* conv. TD-SRP, eq. (23): the GCC read at the TDOA rounded
+  SRP_TD = 4,    /* conv. TD-SRP, eq. (23): the GCC read at the TDOA rounded
                     to the nearest sample (half away from zero); rank_or_q
                     ignored */
+  SRP_LR = 5     /* LR-SRP, eqs. (26)-(29): z = 2 Re[H_tall (H_fat psi)]
+                    from the rank-R_H truncated SVD of the steering matrix H
+                    (J x P(K-1)); rank_or_q = R_H <= min(J, P(K-1), 1024).
+                    The fit runs on the device (FP64, through the smaller
+                    Gram matrix of H, min(J, P(K-1)) <= 16384); no host-only
+                    plans */
 } srp_variant;
 
 /* Operand precision of the dominant contraction (steering matrix for FD, the
@@ -154,11 +160,12 @@ void srp_default_opts(srp_opts* opts);
  *   fs        sampling rate in Hz (> 0)
  *   N         DFT length 2K (even, >= 8); requires 2 N_p + 1 <= N for every
  *             pair (lag aliasing, Sec. III-B2 footnote)
- *   variant   SRP_FD, SRP_SLRI, SRP_SSPI, SRP_SI or SRP_TD
+ *   variant   SRP_FD, SRP_SLRI, SRP_SSPI, SRP_SI, SRP_TD or SRP_LR
  *   rank_or_q R per pair (SLRI, <= 32) or Q per (location, pair) (SSPI,
  *             <= 16), >= 1, clamped per pair to 2 N_p + 1; with
  *             opts->global_fit the total rank R_Lambda (SLRI) or the mean
- *             taps per (location, pair) (SSPI); ignored for FD, SI and TD
+ *             taps per (location, pair) (SSPI); R_H for LR; ignored for
+ *             FD, SI and TD
  *   opts      NULL for defaults
  *   out       receives the plan, NULL on failure
  * Returns SRP_E_INVALID for bad geometry or arguments, SRP_E_UNSUPPORTED for

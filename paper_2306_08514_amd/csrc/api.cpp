@@ -105,7 +105,7 @@ srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J, do
   srp_opts o;
   srp_default_opts(&o);
   if (opts) o = *opts;
-  if (variant < SRP_FD || variant > SRP_TD) return fail(SRP_E_INVALID, "unknown variant");
+  if (variant < SRP_FD || variant > SRP_LR) return fail(SRP_E_INVALID, "unknown variant");
   const bool fixed = variant == SRP_FD || variant == SRP_SI || variant == SRP_TD;  // rank_or_q ignored
   if (o.dtype < SRP_F32 || o.dtype > SRP_F64) return fail(SRP_E_INVALID, "unknown dtype");
   if (!dtype_ok(variant, o.dtype)) return fail(SRP_E_UNSUPPORTED, "dtype not offered for this variant");
@@ -119,6 +119,9 @@ srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J, do
   if (variant == SRP_SLRI && !o.global_fit && rank_or_q > 32)
     return fail(SRP_E_UNSUPPORTED, "SLRI rank per pair above 32 is not built");
   if (variant == SRP_SSPI && rank_or_q > 16) return fail(SRP_E_UNSUPPORTED, "SSPI with Q above 16 is not built");
+  if (variant == SRP_LR && rank_or_q > 1024) return fail(SRP_E_UNSUPPORTED, "LR-SRP with R_H above 1024 is not built");
+  if (variant == SRP_LR && o.device < 0)
+    return fail(SRP_E_UNSUPPORTED, "LR-SRP fits on the device; host-only plans are not offered");
   SRP_GUARD({
     const auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<srp_plan_s> plan(new srp_plan_s());
@@ -139,6 +142,11 @@ srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J, do
     if (variant == SRP_SSPI && hp.global_fit) srp::build_sspi_global(hp, rank_or_q, plan_threads());
     if (variant == SRP_SSPI && !hp.global_fit) srp::build_sspi(hp, rank_or_q, plan_threads());
     if (variant == SRP_TD) srp::build_sspi(hp, 1, plan_threads());
+    if (variant == SRP_LR) {
+      const int64_t n = static_cast<int64_t>(hp.P) * (hp.K - 1);
+      if (rank_or_q > std::min<int64_t>(hp.J, n)) throw srp::Error{SRP_E_INVALID, "R_H exceeds min(J, P (K - 1))"};
+      hp.RH = rank_or_q;
+    }
     if (variant == SRP_SI && hp.R > 32) throw srp::Error{SRP_E_UNSUPPORTED, "SI with more than 32 lags per pair is not built"};
     srp::count_macs(hp);
     if (o.device >= 0) {
@@ -242,7 +250,7 @@ srp_status srp_plan_info_get(srp_plan_t plan, srp_plan_info* info) {
   info->J = hp.J;
   info->PN = hp.PN;
   info->max_np = hp.max_np;
-  info->rank_or_q = hp.variant == SRP_SLRI ? hp.R : (hp.variant == SRP_SSPI ? hp.Q : 0);
+  info->rank_or_q = hp.variant == SRP_SLRI ? hp.R : (hp.variant == SRP_SSPI ? hp.Q : (hp.variant == SRP_LR ? hp.RH : 0));
   info->variant = static_cast<srp_variant>(hp.form);
   info->dtype = static_cast<srp_dtype>(hp.dtype);
   info->mean_n = hp.mean_n;
@@ -287,6 +295,9 @@ srp_status srp_plan_export(srp_plan_t plan, const char* what, void* dst, size_t 
   } else if (w == "slri_s" && hp.variant == SRP_SLRI) {
     src = hp.sv.data();
     n = hp.sv.size() * sizeof(double);
+  } else if (w == "lr_s" && hp.variant == SRP_LR) {
+    src = hp.lr_s.data();
+    n = hp.lr_s.size() * sizeof(double);
   } else if (w == "sspi_start" && hp.variant == SRP_SSPI) {
     src = hp.start.data();
     n = hp.start.size() * 4;

@@ -19,6 +19,9 @@
 #include <thread>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include "../../include/srp.h"
 #include "device.hpp"
 
@@ -1615,6 +1618,30 @@ __global__ void build_steering(const double* __restrict__ x, int P, int64_t J, i
   h[1] = cvt64<T>(-s);
 }
 
+// The complex steering matrix of LR-SRP in FP64, H[j][p (K-1) + k - 1] =
+// exp(i theta), theta = pi k x_p(j) / K (eq. (19)), reduced as in
+// build_steering; row-major [J][P (K-1)] (a column-major P (K-1) x J matrix
+// for the BLAS calls of the fit).
+__global__ void build_h_c64(const double* __restrict__ x, int P, int64_t J, int K, double2* __restrict__ H) {
+  const int64_t j = blockIdx.x;
+  const int n = P * (K - 1);
+  const int e = blockIdx.y * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int p = e / (K - 1), k = e % (K - 1) + 1;
+  const double t = static_cast<double>(k) * x[static_cast<int64_t>(p) * J + j] / (2.0 * K);
+  const double r = t - rint(t);
+  double sn, cs;
+  sincospi(2.0 * r, &sn, &cs);
+  H[j * n + e] = make_double2(cs, sn);
+}
+
+// dst = src * s, narrowed to the operand type (the LR fat-stage output).
+template <typename T>
+__global__ void scale_convert(const float* __restrict__ src, T* __restrict__ dst, int64_t n, float s) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) dst[i] = cvt<T>(src[i] * s);
+}
+
 template <typename T>
 __global__ void convert_f32(const float* __restrict__ src, T* __restrict__ dst, int64_t n) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
@@ -1820,6 +1847,175 @@ static void build_slri_global_device(HostPlan& hp, DevicePlan& dp, Alloc& A, con
   upload(dp.d_gscale, gscale);
 }
 
+// LR-SRP operands (eqs. (26)-(29)).  The truncated SVD of the complex
+// steering matrix H (J x n, n = P (K-1)) is taken through the smaller of
+// its two Gram matrices, in FP64 on the device: H is materialised
+// (build_h_c64), the Gram matrix formed by rocBLAS zherk and decomposed by
+// rocSOLVER zheevd.  Viewing H's row-major storage as the column-major
+// n x J matrix X = H^T:
+//   n <= J: X X^H = conj(H^H H); its eigenvectors z give V = conj(z), and
+//           H_tall = H V (zgemm: T^T = V^T X);
+//   J <  n: X^H X = conj(H H^H); U = conj(z), H_tall = U Sigma, and
+//           conj(H^H U) = X conj(U) = X z (zgemm), V = H^H U / sigma.
+// Runtime operands: F (rows 2r, 2r+1 hold (Re V, Im V) and (-Im V, Re V) in
+// the interleaved (Re, Im) slots of psi, so psi F^T gives Re and Im of
+// (V^H psi)_r) and the tall operand (columns 2 Re T, -2 Im T), so that the
+// tall product is 2 Re[T g].
+struct Blas {
+  rocblas_handle h = nullptr;
+  Blas() {
+    if (rocblas_create_handle(&h) != rocblas_status_success) throw Error{SRP_E_HIP, "rocblas_create_handle failed"};
+  }
+  ~Blas() {
+    if (h) (void)rocblas_destroy_handle(h);
+  }
+  Blas(const Blas&) = delete;
+  Blas& operator=(const Blas&) = delete;
+};
+
+static void blas_ok(rocblas_status st, const char* what) {
+  if (st != rocblas_status_success)
+    throw Error{SRP_E_HIP, std::string(what) + " failed: " + rocblas_status_to_string(st)};
+}
+
+static void build_lr_device(HostPlan& hp, DevicePlan& dp, Alloc& A, const double* dx) {
+  const int P = hp.P, K = hp.K, R = hp.RH;
+  const int64_t J = hp.J, n = static_cast<int64_t>(P) * (K - 1);
+  const int64_t m = std::min(J, n);
+  if (m > 16384) throw Error{SRP_E_UNSUPPORTED, "LR-SRP needs min(J, P (K - 1)) <= 16384 for its Gram matrix"};
+  if (static_cast<double>(J) * n * 16 > 48e9) throw Error{SRP_E_UNSUPPORTED, "LR-SRP fit: H above 48 GB"};
+  TmpBuf dh(static_cast<size_t>(J) * n * sizeof(double2));
+  hipLaunchKernelGGL(build_h_c64, dim3(static_cast<unsigned>(J), static_cast<unsigned>((n + 255) / 256)), dim3(256),
+                     0, 0, dx, P, J, K, dh.as<double2>());
+  check_launch("build_h_c64");
+  HIP_OK(hipDeviceSynchronize());
+  Blas blas;
+  auto* X = reinterpret_cast<rocblas_double_complex*>(dh.p);
+  const bool nroute = n <= J;
+  TmpBuf dg(static_cast<size_t>(m) * m * sizeof(double2));
+  auto* G = reinterpret_cast<rocblas_double_complex*>(dg.p);
+  const double one = 1.0, zero = 0.0;
+  blas_ok(rocblas_zherk(blas.h, rocblas_fill_lower, nroute ? rocblas_operation_none : rocblas_operation_conjugate_transpose,
+                        static_cast<rocblas_int>(m), static_cast<rocblas_int>(nroute ? J : n), &one, X,
+                        static_cast<rocblas_int>(n), &zero, G, static_cast<rocblas_int>(m)),
+          "rocblas_zherk");
+  TmpBuf dd(m * sizeof(double)), de(m * sizeof(double)), dinfo(sizeof(rocblas_int));
+  blas_ok(rocsolver_zheevd(blas.h, rocblas_evect_original, rocblas_fill_lower, static_cast<rocblas_int>(m), G,
+                           static_cast<rocblas_int>(m), dd.as<double>(), de.as<double>(), dinfo.as<rocblas_int>()),
+          "rocsolver_zheevd");
+  HIP_OK(hipDeviceSynchronize());
+  rocblas_int info = 0;
+  HIP_OK(hipMemcpy(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost));
+  if (info != 0) throw Error{SRP_E_HIP, "rocsolver_zheevd did not converge (info " + std::to_string(info) + ")"};
+  std::vector<double> lam(m);
+  HIP_OK(hipMemcpy(lam.data(), dd.p, m * sizeof(double), hipMemcpyDeviceToHost));
+  // eigenvalues ascending: the R largest are the last R columns of z
+  const double2* zR = reinterpret_cast<const double2*>(dg.p) + static_cast<int64_t>(m - R) * m;
+  hp.lr_s.assign(R, 0.0);
+  for (int r = 0; r < R; ++r) hp.lr_s[r] = std::sqrt(std::max(0.0, lam[m - 1 - r]));
+  const double smin = 1e-12 * (hp.lr_s.empty() ? 0.0 : hp.lr_s[0]);
+  // T [J][R] and V [n][R] on the host, column r = the r-th largest
+  std::vector<double2> T(static_cast<size_t>(J) * R), V(static_cast<size_t>(n) * R);
+  const rocblas_double_complex c1{1.0, 0.0}, c0{0.0, 0.0};
+  if (nroute) {
+    std::vector<double2> zh(static_cast<size_t>(m) * R);
+    HIP_OK(hipMemcpy(zh.data(), zR, zh.size() * sizeof(double2), hipMemcpyDeviceToHost));
+    std::vector<double2> vcm(static_cast<size_t>(n) * R);  // column-major n x R, V = conj(z)
+    for (int r = 0; r < R; ++r)
+      for (int64_t i = 0; i < n; ++i) {
+        const double2 z = zh[static_cast<size_t>(R - 1 - r) * m + i];
+        vcm[static_cast<size_t>(r) * n + i] = make_double2(z.x, -z.y);
+        V[static_cast<size_t>(i) * R + r] = make_double2(z.x, -z.y);
+      }
+    TmpBuf dv(vcm.size() * sizeof(double2)), dt(T.size() * sizeof(double2));
+    upload(dv.p, vcm);
+    blas_ok(rocblas_zgemm(blas.h, rocblas_operation_transpose, rocblas_operation_none, R, static_cast<rocblas_int>(J),
+                          static_cast<rocblas_int>(n), &c1, dv.as<rocblas_double_complex>(), static_cast<rocblas_int>(n),
+                          X, static_cast<rocblas_int>(n), &c0, dt.as<rocblas_double_complex>(), R),
+            "rocblas_zgemm");
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipMemcpy(T.data(), dt.p, T.size() * sizeof(double2), hipMemcpyDeviceToHost));
+  } else {
+    std::vector<double2> zh(static_cast<size_t>(m) * R);
+    HIP_OK(hipMemcpy(zh.data(), zR, zh.size() * sizeof(double2), hipMemcpyDeviceToHost));
+    for (int r = 0; r < R; ++r) {
+      const double sg = hp.lr_s[r] > smin ? hp.lr_s[r] : 0.0;
+      for (int64_t j = 0; j < J; ++j) {
+        const double2 z = zh[static_cast<size_t>(R - 1 - r) * m + j];
+        T[static_cast<size_t>(j) * R + r] = make_double2(z.x * sg, -z.y * sg);  // U sigma, U = conj(z)
+      }
+    }
+    // conj(H^H U) = X z, for the R columns of z (ascending order)
+    TmpBuf dw(static_cast<size_t>(n) * R * sizeof(double2));
+    blas_ok(rocblas_zgemm(blas.h, rocblas_operation_none, rocblas_operation_none, static_cast<rocblas_int>(n), R,
+                          static_cast<rocblas_int>(J), &c1, X, static_cast<rocblas_int>(n),
+                          reinterpret_cast<const rocblas_double_complex*>(zR), static_cast<rocblas_int>(m), &c0,
+                          dw.as<rocblas_double_complex>(), static_cast<rocblas_int>(n)),
+            "rocblas_zgemm");
+    HIP_OK(hipDeviceSynchronize());
+    std::vector<double2> w(static_cast<size_t>(n) * R);
+    HIP_OK(hipMemcpy(w.data(), dw.p, w.size() * sizeof(double2), hipMemcpyDeviceToHost));
+    for (int r = 0; r < R; ++r) {
+      const double inv = hp.lr_s[r] > smin ? 1.0 / hp.lr_s[r] : 0.0;
+      for (int64_t i = 0; i < n; ++i) {
+        const double2 c = w[static_cast<size_t>(R - 1 - r) * n + i];
+        V[static_cast<size_t>(i) * R + r] = make_double2(c.x * inv, -c.y * inv);
+      }
+    }
+  }
+  // runtime operands
+  const int es = static_cast<int>(dsize(hp.dtype));
+  const int elem_per_slice = std::max(BIG_BKB / es, hp.dtype == SRP_F32 ? 0 : 4 * TALL_STEP_BYTES(hp.dtype) / es);
+  dp.Kc = static_cast<int>(round_up(2 * R, std::max(elem_per_slice, 32)));
+  dp.Fpad = static_cast<int>(round_up(dp.Kc, BIG_BW));
+  const int64_t ldf = static_cast<int64_t>(P) * dp.Kp;
+  std::vector<float> F(static_cast<size_t>(dp.Fpad) * ldf, 0.0f);
+  double act_max = 0;
+  for (int r = 0; r < R; ++r) {
+    float* f0 = &F[static_cast<size_t>(2 * r) * ldf];
+    float* f1 = &F[static_cast<size_t>(2 * r + 1) * ldf];
+    double l1a = 0, l1b = 0;
+    for (int p = 0; p < P; ++p)
+      for (int k = 1; k < K; ++k) {
+        const double2 v = V[static_cast<size_t>(p * (K - 1) + k - 1) * R + r];
+        const size_t e = static_cast<size_t>(p) * dp.Kp + 2 * (k - 1);
+        f0[e] = static_cast<float>(v.x);
+        f0[e + 1] = static_cast<float>(v.y);
+        f1[e] = static_cast<float>(-v.y);
+        f1[e + 1] = static_cast<float>(v.x);
+        l1a += std::fabs(v.x) + std::fabs(v.y);
+      }
+    l1b = l1a;
+    act_max = std::max(act_max, std::max(l1a, l1b));  // |Re g|, |Im g| <= sum |V| since |psi| <= 1
+  }
+  dp.d_F = static_cast<float*>(A.get(F.size() * 4));
+  upload(dp.d_F, F);
+  const size_t ucount = static_cast<size_t>(dp.Jpad) * dp.Kc;
+  std::vector<float> Us(ucount, 0.0f);
+  double umax = 0;
+  for (int64_t j = 0; j < J; ++j)
+    for (int r = 0; r < R; ++r) {
+      const double2 t = T[static_cast<size_t>(j) * R + r];
+      Us[static_cast<size_t>(j) * dp.Kc + 2 * r] = static_cast<float>(2.0 * t.x);
+      Us[static_cast<size_t>(j) * dp.Kc + 2 * r + 1] = static_cast<float>(-2.0 * t.y);
+      umax = std::max(umax, 2.0 * std::max(std::fabs(t.x), std::fabs(t.y)));
+    }
+  double sigma = 1.0, act = 1.0;
+  if (hp.dtype == SRP_FP8_E4M3) {
+    if (umax > 0) sigma = std::exp2(std::ceil(std::log2(umax / 448.0)));
+    if (act_max > 0) act = std::exp2(std::ceil(std::log2(act_max / 448.0)));
+    for (float& u : Us) u = static_cast<float>(u / sigma);
+  }
+  if (hp.dtype == SRP_F16 && act_max > 60000.0) act = std::exp2(std::ceil(std::log2(act_max / 60000.0)));
+  dp.lr_gscale = static_cast<float>(1.0 / act);
+  dp.tall_alpha = static_cast<float>(act * sigma);
+  TmpBuf us(ucount * 4);
+  upload(us.p, Us);
+  dp.d_U = A.get(ucount * dsize(hp.dtype));
+  convert_dtype(hp.dtype, us.as<float>(), dp.d_U, static_cast<int64_t>(ucount));
+  HIP_OK(hipDeviceSynchronize());
+}
+
 void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budget) {
   (void)frame_tile;
   dp.device = -1;
@@ -1837,6 +2033,14 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
   upload(dp.d_pmp, hp.pair_mp);
   upload(dp.d_np, hp.np);
   upload(dp.d_off, hp.off);
+
+  if (hp.variant == SRP_LR) {
+    if (hp.dtype == SRP_F64) throw Error{SRP_E_UNSUPPORTED, "LR-SRP has no FP64 path"};
+    TmpBuf dx(hp.x.size() * sizeof(double));
+    upload(dx.p, hp.x);
+    build_lr_device(hp, dp, A, dx.as<double>());
+    return;
+  }
 
   if (hp.variant == SRP_FD) {
     const size_t es = dsize(hp.dtype);
@@ -2138,7 +2342,7 @@ void device_free(DevicePlan& dp) {
   }
   for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
   void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_tasks, dp.d_tw, dp.d_w2,
-                  dp.d_U, dp.d_V, dp.d_gscale, dp.d_start, dp.d_w, dp.d_win, dp.d_xg, dp.ws};
+                  dp.d_U, dp.d_V, dp.d_gscale, dp.d_F, dp.d_start, dp.d_w, dp.d_win, dp.d_xg, dp.ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   dp = DevicePlan{};
@@ -2148,7 +2352,7 @@ namespace {
 
 struct WsLayout {
   int64_t Lc = 0, Lpad = 0;
-  size_t psi = 0, xi = 0, part = 0, g = 0, total = 0;
+  size_t psi = 0, xi = 0, part = 0, g = 0, g32 = 0, total = 0;
 };
 
 WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t frame_tile) {
@@ -2158,7 +2362,15 @@ WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t 
   size_t off = 0;
   w.psi = off;
   if (hp.variant == SRP_FD) off = align256(off + static_cast<size_t>(w.Lpad) * hp.P * dp.Kp * dsize(hp.dtype));
-  if (hp.variant != SRP_FD) {
+  if (hp.variant == SRP_LR) {
+    // FP32 cross-spectra, the FP32 fat-stage output and its narrowed copy
+    off = align256(off + static_cast<size_t>(w.Lpad) * hp.P * dp.Kp * 4);
+    w.g32 = off;
+    off = align256(off + static_cast<size_t>(w.Lpad) * dp.Kc * 4);
+    w.g = off;
+    off = align256(off + static_cast<size_t>(w.Lpad) * dp.Kc * dsize(hp.dtype));
+  }
+  if (hp.variant != SRP_FD && hp.variant != SRP_LR) {
     w.xi = off;
     off = align256(off + static_cast<size_t>(hp.PN) * w.Lpad * 4);
     w.part = off;
@@ -2206,8 +2418,9 @@ void phat_dispatch(const HostPlan& hp, DevicePlan& dp, const void* frames, int64
 
 template <typename T, int BX, int BW, int WGX, int BKB>
 void launch_gemm(DevicePlan& dp, const char* kname, const void* X, int64_t ldx, const void* W, int64_t ldw,
-                 float* C, int64_t ldc, int nx, int nw, int kdim, float alpha, int64_t Lpad, hipStream_t st) {
-  const int nwt = static_cast<int>(dp.Jpad / BW);
+                 float* C, int64_t ldc, int nx, int nw, int kdim, float alpha, int64_t Lpad, hipStream_t st,
+                 int64_t wrows = 0) {
+  const int nwt = static_cast<int>((wrows ? wrows : dp.Jpad) / BW);
   const int nxt = static_cast<int>(Lpad / BX);
   const int blocks = static_cast<int>(round_up(static_cast<int64_t>(nwt) * nxt, 8));
   TRACED(dp, kname, st,
@@ -2476,6 +2689,36 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
     const int64_t Lc = std::min(lay.Lc, L - l0);
     const void* fr = static_cast<const float2*>(frames) + l0 * frame_elems;
     void* psi = base + lay.psi;
+    if (hp.variant == SRP_LR) {
+      // eq. (29): g = H_fat psi as the real product psi F^T (FP32 operands,
+      // MFMA), narrowed to the operand type, then z = 2 Re[H_tall g]
+      phat_dispatch(hp, dp, fr, Lc, psi, SRP_F32, st);
+      float* g32 = reinterpret_cast<float*>(base + lay.g32);
+      float* z = static_cast<float*>(maps) + l0 * ldm;
+      launch_gemm<float, BIG_BX, BIG_BW, BIG_WGX, BIG_BKB>(dp, "lr_fat", psi, ldpsi, dp.d_F, ldpsi, g32, dp.Kc,
+                                                           (int)Lc, dp.Kc, (int)ldpsi, 1.0f, lay.Lpad, st, dp.Fpad);
+      void* g = base + lay.g;
+      const int64_t ng = Lc * dp.Kc;
+      const dim3 cg(static_cast<unsigned>((ng + 255) / 256));
+      switch (hp.dtype) {
+        case SRP_F32:
+          launch_tall_gemm<float>(dp, g32, dp.Kc, dp.d_U, dp.Kc, z, ldm, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          break;
+        case SRP_BF16:
+          TRACED(dp, "lr_narrow", st, hipLaunchKernelGGL(scale_convert<__bf16>, cg, dim3(256), 0, st, g32, static_cast<__bf16*>(g), ng, dp.lr_gscale));
+          launch_tall_gemm<__bf16>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, ldm, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          break;
+        case SRP_F16:
+          TRACED(dp, "lr_narrow", st, hipLaunchKernelGGL(scale_convert<_Float16>, cg, dim3(256), 0, st, g32, static_cast<_Float16*>(g), ng, dp.lr_gscale));
+          launch_tall_gemm<_Float16>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, ldm, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          break;
+        case SRP_FP8_E4M3:
+          TRACED(dp, "lr_narrow", st, hipLaunchKernelGGL(scale_convert<fp8>, cg, dim3(256), 0, st, g32, static_cast<fp8*>(g), ng, dp.lr_gscale));
+          launch_tall_gemm<fp8>(dp, g, dp.Kc, dp.d_U, dp.Kc, z, ldm, (int)Lc, (int)hp.J, dp.Kc, dp.tall_alpha, lay.Lpad, st);
+          break;
+      }
+      continue;
+    }
     if (hp.variant == SRP_FD) {
       phat_dispatch(hp, dp, fr, Lc, psi, hp.dtype, st);
       if (hp.dtype == SRP_F64) {

@@ -48,6 +48,11 @@ struct DevicePlan {
   float* d_gscale = nullptr; // [P] activation scale of pair p in the fat stage
   float tall_alpha = 1.0f;   // undoes the activation scale in the tall GEMM
   int tall_slots = 0;        // resident blocks of the tall kernel on the device (0 = not yet queried)
+  // LR-SRP: fat operand F [Fpad][P*Kp] FP32 (rows 2r, 2r+1 give Re, Im of
+  // (H_fat psi)_r), tall operand in d_U (columns 2 Re T, -2 Im T)
+  float* d_F = nullptr;
+  int Fpad = 0;
+  float lr_gscale = 1.0f;    // activation scale applied when g is narrowed
   // SSPI
   int32_t* d_start = nullptr;  // [J][P] absolute stacked lag index of tap 0
   void* d_w = nullptr;         // [J][P][Q] in dtype (f32, bf16, f16 or fp8)

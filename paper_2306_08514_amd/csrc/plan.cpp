@@ -670,6 +670,8 @@ void count_macs(HostPlan& hp) {
   const double samp = hp.fft ? 8.0 * hp.P * hp.K * std::log2(2.0 * hp.K) : 2.0 * hp.PN * (hp.K - 1);
   if (hp.variant == SRP_FD) {
     hp.macs_per_map = 2.0 * J * hp.P * (hp.K - 1);
+  } else if (hp.variant == SRP_LR) {
+    hp.macs_per_map = 2.0 * J * hp.RH + 4.0 * hp.RH * hp.P * (hp.K - 1);  // (30)
   } else if (hp.variant == SRP_SLRI && hp.global_fit) {
     hp.macs_per_map = J * hp.R + static_cast<double>(hp.R) * hp.PN + samp;  // (61)
   } else if (hp.variant == SRP_SLRI) {

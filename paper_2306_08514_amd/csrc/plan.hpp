@@ -54,6 +54,10 @@ struct HostPlan {
   double nnz = 0;                 // entries kept
   std::vector<int32_t> gstart, gcount;
 
+  // LR-SRP (eqs. (26)-(29)): rank R_H of the truncated SVD of H
+  int RH = 0;
+  std::vector<double> lr_s;  // the R_H largest singular values of H
+
   bool fft = false;  // GCC sampling by the iFFT of (46) instead of the direct product of (40)
   bool device_fit = false;  // SLRI Gram matrices and U, SSPI windows are computed on the device
   int fd_steering = 0;      // FD steering operand: 0 auto, 1 resident, 2 generated

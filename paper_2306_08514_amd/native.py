@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsrp.so")
 
-VARIANTS = {"fd": 0, "slri": 1, "sspi": 2, "si": 3, "td": 4}
+VARIANTS = {"fd": 0, "slri": 1, "sspi": 2, "si": 3, "td": 4, "lr": 5}
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2, "fp8": 3, "f64": 4}
 STATUS = {0: "SRP_OK", -1: "SRP_E_INVALID", -2: "SRP_E_NOMEM", -3: "SRP_E_UNSUPPORTED",
           -4: "SRP_E_HIP", -5: "SRP_E_BUDGET"}

@@ -265,6 +265,7 @@ def test_mac_counts_follow_complexity_model():
     (dict(variant="sspi", rq=17), -3),
     (dict(variant="slri", rq=4, dtype="f64"), -3),
     (dict(M=1), -1),
+    (dict(variant="lr", rq=8), -3),             # LR-SRP fits on the device only
 ])
 def test_invalid_arguments_return_error_codes(kw, code):
     _lib_or_skip()

@@ -271,6 +271,44 @@ def test_sspi_more_than_eight_taps(native, sq4, Q):
     p.close()
 
 
+def _lr_case(native, cfg, Y, R, dtype, label):
+    x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    K = cfg["N"] // 2
+    psi = o.phat(Y)
+    tall, fat, sv = o.lr_factors(x, K, R)
+    ref = o.lr_map(psi, tall, fat)
+    p = _plan(native, cfg, "lr", R, dtype=dtype)
+    z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
+    # the FP64 fit's singular values are the oracle's; through the Gram
+    # matrix they carry an absolute error of about sqrt(eps) sigma_1
+    np.testing.assert_allclose(p.export("lr_s"), sv[:R], rtol=1e-9, atol=1e-7 * sv[0])
+    _check_maps(z, ref, TOL[dtype], label)
+    if R >= min(x.shape[1], x.shape[0] * (K - 1)):
+        _check_maps(z, o.fd_map(psi, x, K), TOL[dtype], label + " at full rank = FD")
+    p.close()
+
+
+@pytest.mark.parametrize("R,dtype", [(8, "f32"), (64, "f32"), (256, "f32"), (256, "bf16"), (256, "f16"),
+                                     (256, "fp8"), (1024, "f32")])
+def test_lr_srp_wide_h(native, sq4, R, dtype):
+    """LR-SRP (26)-(29) with J = 1024 < P (K-1) = 1530 (fit through H H^H);
+    R = J is full rank and must give the FD map."""
+    cfg, Y = sq4
+    _announce(f"lr R={R} {dtype} square4 (J < n)")
+    _lr_case(native, cfg, Y, R, dtype, f"lr R={R} {dtype}")
+
+
+@pytest.mark.parametrize("R,dtype", [(16, "f32"), (378, "f32"), (64, "bf16")])
+def test_lr_srp_tall_h(native, sq4, R, dtype):
+    """LR-SRP with N = 128 on the 1024-point plane: P (K-1) = 378 < J (fit
+    through H^H H); R = 378 is full rank."""
+    cfg = dict(sq4[0])
+    cfg["N"] = 128
+    Y = scenes.random_frames(7, 19, 4, 128)
+    _announce(f"lr R={R} {dtype} square4 N=128 (n < J)")
+    _lr_case(native, cfg, Y, R, dtype, f"lr N=128 R={R} {dtype}")
+
+
 def test_edge_cases(native, sq4):
     cfg, Y = sq4
     _announce("edge cases")
