@@ -270,6 +270,100 @@ def random_frames(seed, L, M, N, zero_fraction=0.0):
     return Y.astype(np.complex64)
 
 
+# ------------------------------------------------------- evaluation scenes --
+
+def evaluation_scene(kind, n_sources=16, frames_per_source=8, snr_db=12.0, max_order=0, beta=0.7,
+                     grid_stride=2, seed=0):
+    """Seeded scenes for the localisation and map-error sweeps, one source
+    position per group of frames_per_source consecutive frames.
+
+    room: the uca8_room125k array and grid (axes subsampled by grid_stride);
+      sources uniform in the room >= 0.5 m from walls and array, z <= 2 m;
+      image sources up to max_order (reflection beta); white noise at snr_db.
+    square: the square4_plane1k array and 32 x 32 plane; sources in the
+      plane >= 0.5 m from the centre.
+    farfield: 8-mic UCA (0.3 m) at the origin, the 2-degree lower
+      half-sphere of directions; 1/f plane waves (sources 300 m away) from
+      uniformly drawn grid directions of depression 5..85 degrees.
+    nf4: the paper's near-field scenario (Sec. V-B1, Table 1): M = 4
+      microphones near the corners of a 4.9 x 5.9 x 3.5 m room at 3 m
+      height, a 4 x 5 x 0.1 m grid at 3.33 cm around 1.5 m height (121 x
+      151 x 4, J = 73,084), fs 4 kHz, 2K = 512, c = 340 m/s; sources
+      uniform inside the grid volume.
+    ff6: the paper's far-field scenario: a 6-mic UCA (diameter 0.3 m) 10 cm
+      below the ceiling of a 6.5 x 9 x 4.5 m room, the 2-degree lower
+      half-sphere (J = 8,101), fs 16 kHz, 2K = 1024, c = 340 m/s; sources
+      inside the room at least 2 m from the array centre, their directions
+      the truth.
+
+    Returns (cfg, frames [n_sources * frames_per_source, M, N/2 + 1]
+    complex64, truth [n_sources * frames_per_source, 3]) where truth holds
+    source positions (room, square) or unit directions (farfield)."""
+    rng = np.random.default_rng(SEED_BASE + 200 + seed)
+    if kind == "room":
+        cfg = workload("uca8_room125k", L=frames_per_source, grid_stride=grid_stride)
+        room = np.array([5.0, 5.0, 2.5])
+        far = False
+    elif kind == "square":
+        cfg = workload("square4_plane1k", L=frames_per_source)
+        room, far = None, False
+    elif kind == "farfield":
+        cfg = dict(mics=uca(8, 0.3), grid=half_sphere_directions(2.0), fs=16000.0, N=1024, hop=512,
+                   L=frames_per_source, c=C_SOUND, name="uca8_farfield8k")
+        room, far = None, True
+    elif kind == "nf4":
+        mics = np.array([[0.4, 0.4, 3.0], [0.4, 5.4, 3.0], [4.4, 5.4, 3.0], [4.4, 0.4, 3.0]])
+        grid = box_grid(np.linspace(0.4, 4.4, 121), np.linspace(0.4, 5.4, 151), np.linspace(1.45, 1.55, 4))
+        cfg = dict(mics=mics, grid=grid, fs=4000.0, N=512, hop=256, L=frames_per_source, c=340.0,
+                   name="nf4_paper73k")
+        room, far = np.array([4.9, 5.9, 3.5]), False
+    elif kind == "ff6":
+        centre = np.array([3.25, 4.5, 4.4])
+        cfg = dict(mics=uca(6, 0.3, centre), grid=half_sphere_directions(2.0), fs=16000.0, N=1024, hop=512,
+                   L=frames_per_source, c=340.0, name="ff6_paper8k")
+        room, far = np.array([6.5, 9.0, 4.5]), True
+    else:
+        raise ValueError(kind)
+    N, hop = cfg["N"], cfg["hop"]
+    T = _n_samples(frames_per_source, N, hop)
+    frames, truth = [], []
+    for _ in range(n_sources):
+        if kind == "room":
+            while True:
+                s = rng.uniform([0.5, 0.5, 0.5], [4.5, 4.5, 2.0])
+                if np.min(np.linalg.norm(cfg["mics"] - s, axis=1)) >= 0.5:
+                    break
+            src, t = s, s
+        elif kind == "square":
+            while True:
+                s = np.array([rng.uniform(-2, 2), rng.uniform(-2, 2), 0.0])
+                if np.linalg.norm(s) >= 0.5:
+                    break
+            src, t = s, s
+        elif kind == "nf4":
+            s = rng.uniform([0.4, 0.4, 1.45], [4.4, 5.4, 1.55])
+            src, t = s, s
+        elif kind == "ff6":
+            ctr = cfg["mics"].mean(0)
+            while True:
+                s = rng.uniform([0.3, 0.3, 0.3], [6.2, 8.7, 4.0])
+                if np.linalg.norm(s - ctr) >= 2.0:
+                    break
+            src, t = s, (s - ctr) / np.linalg.norm(s - ctr)
+        else:
+            g = cfg["grid"]
+            dep = np.degrees(np.arcsin(-g[:, 2]))
+            cand = np.nonzero((dep >= 5.0) & (dep <= 85.0))[0]
+            t = g[cand[rng.integers(len(cand))]]
+            src = 300.0 * t
+        x = render(rng, cfg["mics"], [src], cfg["fs"], T, snr_db, noise="white", room=room,
+                   max_order=max_order if room is not None else 0, beta=beta, c=cfg["c"])
+        frames.append(stft_frames(x, N, hop, frames_per_source))
+        truth.append(np.repeat(np.asarray(t, dtype=np.float64)[None], frames_per_source, axis=0))
+    cfg["far_field"] = far
+    return cfg, np.concatenate(frames).astype(np.complex64), np.concatenate(truth)
+
+
 # ------------------------------------------------------------ serving mix --
 
 SERVING_M = (4, 8, 16, 32)
