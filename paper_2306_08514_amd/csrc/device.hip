@@ -1594,12 +1594,12 @@ __global__ __launch_bounds__(256) void sspi_windows(const double* __restrict__ x
   if (threadIdx.x == 0) win[static_cast<int64_t>(blockIdx.x) * P + p] = make_int2(rlo[0], rhi[0] + Q - rlo[0]);
 }
 
-// Steering operand of conv. FD-SRP: H[j][p Kp + 2 (k-1) + {0,1}] =
+// Steering operand of conv. FD-SRP: H[j * ldh + p Kp + 2 (k-1) + {0,1}] =
 // (cos theta, -sin theta), theta = pi k x_p(j) / K (eq. (19) with (14)).  The
 // phase is reduced in FP64: theta = 2 pi (t - rint(t)), t = k x / (2K), and
 // sin/cos come from the FP64 sincospi.  Rows j >= J and slots k >= K are 0.
 template <typename T>
-__global__ void build_steering(const double* __restrict__ x, int P, int64_t J, int K, int Kp,
+__global__ void build_steering(const double* __restrict__ x, int P, int64_t J, int K, int Kp, int64_t ldh,
                                T* __restrict__ H) {
   const int64_t j = blockIdx.x;
   const int slots = Kp / 2;
@@ -1613,7 +1613,7 @@ __global__ void build_steering(const double* __restrict__ x, int P, int64_t J, i
     const double r = t - rint(t);
     sincospi(2.0 * r, &s, &c);
   }
-  T* h = H + j * static_cast<int64_t>(P) * Kp + static_cast<int64_t>(p) * Kp + 2 * kk;
+  T* h = H + j * ldh + static_cast<int64_t>(p) * Kp + 2 * kk;
   h[0] = cvt64<T>(c);
   h[1] = cvt64<T>(-s);
 }
@@ -1673,9 +1673,9 @@ size_t dsize(int dtype) {
 }
 
 template <typename T>
-void launch_steering(const double* d_x, const HostPlan& hp, int Kp, int64_t Jpad, void* H) {
+void launch_steering(const double* d_x, const HostPlan& hp, int Kp, int64_t Jpad, int64_t ldh, void* H) {
   dim3 grid(static_cast<unsigned>(Jpad), (hp.P * (Kp / 2) + 255) / 256);
-  hipLaunchKernelGGL(build_steering<T>, grid, dim3(256), 0, 0, d_x, hp.P, hp.J, hp.K, Kp,
+  hipLaunchKernelGGL(build_steering<T>, grid, dim3(256), 0, 0, d_x, hp.P, hp.J, hp.K, Kp, ldh,
                      static_cast<T*>(H));
   check_launch("build_steering");
 }
@@ -1717,7 +1717,31 @@ void upload(void* dst, const std::vector<T>& v) {
 }
 
 // tile shapes of the launch configurations
-constexpr int BIG_BX = 256, BIG_BW = 128, BIG_WGX = 2, BIG_BKB = 128;   // FD
+// FD GEMM: 128 frames x 128 candidates per block, 2 x 2 waves, 256-byte K
+// slices (128 bytes for FP8, whose rows are only a multiple of 128 bytes).
+// Measured against 256 x 128 tiles with 128-byte slices: 55.0 vs 58.6 ms at
+// 125,000 candidates and 1000 frames (fewer barriers per MAC, two blocks
+// per CU, and twice the blocks for the last partial round of the grid).
+// The price is L2 reuse: 12 % of the reads hit L2 against 82 % with
+// 256-frame tiles, so the kernel reads ~200 GB from HBM per 1000 maps
+// instead of ~31 GB (3.7 TB/s, under half the HBM peak; the kernel stays
+// MFMA-bound).  Block order (row-major, frame-major, XCD-grouped) and row
+// padding did not restore it.
+constexpr int BIG_BX = 128, BIG_BW = 128, BIG_WGX = 2;
+template <typename T>
+constexpr int big_bkb() {
+  return sizeof(T) == 1 ? 128 : 256;
+}
+// workspace frame rows are padded to whole 256-frame tiles, the largest
+// frame tile any kernel reads (fd_gen)
+constexpr int LPAD_ROWS = 256;
+// Row pitch of the FD operands (steering H and the cross-spectra psi): P Kp
+// elements plus FD_ROW_PAD_BYTES.  Padding by 128 or 256 bytes changed
+// neither the time nor the L2 hit rate of the 128 x 128 tiles, so it is 0.
+constexpr int FD_ROW_PAD_BYTES = 0;
+inline int64_t fd_ld(const HostPlan& hp, const DevicePlan& dp, size_t es) {
+  return static_cast<int64_t>(hp.P) * dp.Kp + FD_ROW_PAD_BYTES / static_cast<int64_t>(es);
+}
 constexpr int TALL_BX = 256, TALL_BW = 128, TALL_WGX = 2, TALL_BKB = 128; // SLRI tall (FP32)
 constexpr int TALL_STEP_BYTES(int dtype) { return dtype == SRP_FP8_E4M3 ? 64 : 32; }  // Mfma<T>::STEP
 constexpr int TALL_CW = 8;  // compute waves per block of the tall kernel (256 candidates)
@@ -1965,7 +1989,7 @@ static void build_lr_device(HostPlan& hp, DevicePlan& dp, Alloc& A, const double
   }
   // runtime operands
   const int es = static_cast<int>(dsize(hp.dtype));
-  const int elem_per_slice = std::max(BIG_BKB / es, hp.dtype == SRP_F32 ? 0 : 4 * TALL_STEP_BYTES(hp.dtype) / es);
+  const int elem_per_slice = std::max(TALL_BKB / es, hp.dtype == SRP_F32 ? 0 : 4 * TALL_STEP_BYTES(hp.dtype) / es);
   dp.Kc = static_cast<int>(round_up(2 * R, std::max(elem_per_slice, 32)));
   dp.Fpad = static_cast<int>(round_up(dp.Kc, BIG_BW));
   const int64_t ldf = static_cast<int64_t>(P) * dp.Kp;
@@ -2044,7 +2068,7 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
 
   if (hp.variant == SRP_FD) {
     const size_t es = dsize(hp.dtype);
-    const size_t hbytes = static_cast<size_t>(dp.Jpad) * P * dp.Kp * es;
+    const size_t hbytes = static_cast<size_t>(dp.Jpad) * fd_ld(hp, dp, es) * es;
     // resident H up to 16 GiB (and within the budget); beyond, the steering
     // is generated on the fly from the FP64 TDOAs
     const bool fits = hbytes <= (size_t(16) << 30) && (budget == 0 || hbytes + dp.resident_bytes <= budget);
@@ -2061,11 +2085,11 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     try {
       upload(d_x, hp.x);
       switch (hp.dtype) {
-        case SRP_F32: launch_steering<float>(d_x, hp, dp.Kp, dp.Jpad, dp.d_H); break;
-        case SRP_BF16: launch_steering<__bf16>(d_x, hp, dp.Kp, dp.Jpad, dp.d_H); break;
-        case SRP_F16: launch_steering<_Float16>(d_x, hp, dp.Kp, dp.Jpad, dp.d_H); break;
-        case SRP_FP8_E4M3: launch_steering<fp8>(d_x, hp, dp.Kp, dp.Jpad, dp.d_H); break;
-        case SRP_F64: launch_steering<double>(d_x, hp, dp.Kp, dp.Jpad, dp.d_H); break;
+        case SRP_F32: launch_steering<float>(d_x, hp, dp.Kp, dp.Jpad, fd_ld(hp, dp, es), dp.d_H); break;
+        case SRP_BF16: launch_steering<__bf16>(d_x, hp, dp.Kp, dp.Jpad, fd_ld(hp, dp, es), dp.d_H); break;
+        case SRP_F16: launch_steering<_Float16>(d_x, hp, dp.Kp, dp.Jpad, fd_ld(hp, dp, es), dp.d_H); break;
+        case SRP_FP8_E4M3: launch_steering<fp8>(d_x, hp, dp.Kp, dp.Jpad, fd_ld(hp, dp, es), dp.d_H); break;
+        case SRP_F64: launch_steering<double>(d_x, hp, dp.Kp, dp.Jpad, fd_ld(hp, dp, es), dp.d_H); break;
       }
       HIP_OK(hipDeviceSynchronize());
     } catch (...) {
@@ -2131,7 +2155,7 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     // padded to a whole K slice of the FP32 GEMM and, for the 16-bit and
     // FP8 operands, to a multiple of four MFMA steps of the tall kernel
     const int es = static_cast<int>(dsize(hp.dtype));
-    const int elem_per_slice = std::max(BIG_BKB / es, hp.dtype == SRP_F32 ? 0 : 4 * TALL_STEP_BYTES(hp.dtype) / es);
+    const int elem_per_slice = std::max(TALL_BKB / es, hp.dtype == SRP_F32 ? 0 : 4 * TALL_STEP_BYTES(hp.dtype) / es);
     dp.Kc = static_cast<int>(round_up(static_cast<int64_t>(hp.global_fit ? 1 : P) * R, elem_per_slice));
     TmpBuf dx(hp.x.size() * sizeof(double));
     upload(dx.p, hp.x);
@@ -2358,13 +2382,13 @@ struct WsLayout {
 WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t frame_tile) {
   WsLayout w;
   w.Lc = std::max<int64_t>(1, std::min(L, frame_tile));
-  w.Lpad = round_up(w.Lc, BIG_BX);
+  w.Lpad = round_up(w.Lc, LPAD_ROWS);
   size_t off = 0;
   w.psi = off;
-  if (hp.variant == SRP_FD) off = align256(off + static_cast<size_t>(w.Lpad) * hp.P * dp.Kp * dsize(hp.dtype));
+  if (hp.variant == SRP_FD) off = align256(off + static_cast<size_t>(w.Lpad) * fd_ld(hp, dp, dsize(hp.dtype)) * dsize(hp.dtype));
   if (hp.variant == SRP_LR) {
     // FP32 cross-spectra, the FP32 fat-stage output and its narrowed copy
-    off = align256(off + static_cast<size_t>(w.Lpad) * hp.P * dp.Kp * 4);
+    off = align256(off + static_cast<size_t>(w.Lpad) * fd_ld(hp, dp, 4) * 4);
     w.g32 = off;
     off = align256(off + static_cast<size_t>(w.Lpad) * dp.Kc * 4);
     w.g = off;
@@ -2405,7 +2429,7 @@ void launch_phat(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t
 
 void phat_dispatch(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L,
                    void* out, int dtype, hipStream_t st) {
-  const int64_t ld_l = static_cast<int64_t>(hp.P) * dp.Kp;
+  const int64_t ld_l = fd_ld(hp, dp, dsize(dtype));
   const int kslots = dp.Kp / 2;
   switch (dtype) {
     case SRP_F32: launch_phat<float, float>(hp, dp, frames, L, static_cast<float*>(out), ld_l, dp.Kp, kslots, st); break;
@@ -2433,7 +2457,8 @@ template <typename T>
 void launch_big_gemm(DevicePlan& dp, const char* kname, const void* X, int64_t ldx, const void* W, int64_t ldw,
                      float* C, int64_t ldc, int nx, int nw, int kdim, float alpha, int64_t Lpad,
                      hipStream_t st) {
-  launch_gemm<T, BIG_BX, BIG_BW, BIG_WGX, BIG_BKB>(dp, kname, X, ldx, W, ldw, C, ldc, nx, nw, kdim, alpha, Lpad, st);
+  launch_gemm<T, BIG_BX, BIG_BW, BIG_WGX, big_bkb<T>()>(dp, kname, X, ldx, W, ldw, C, ldc, nx, nw, kdim, alpha, Lpad,
+                                                       st);
 }
 
 // Frame splits of the tall kernel: the number of ranges per candidate tile
@@ -2466,10 +2491,10 @@ void tall_split(DevicePlan& dp, const void* kern, int threads, int njt, int ngro
 // FD with generated steering: 256-frame tiles (waves 2 x 2) for large
 // batches, 64-frame tiles (waves 1 x 4) for small ones.
 template <typename T>
-void launch_fd_gen(const HostPlan& hp, DevicePlan& dp, const void* psi, int64_t ldpsi, float* z, int64_t ldz,
-                   int64_t Lc, hipStream_t st) {
+void launch_fd_gen(const HostPlan& hp, DevicePlan& dp, const void* psi, int64_t ldpsi, int64_t kfd, float* z,
+                   int64_t ldz, int64_t Lc, hipStream_t st) {
   const int nw = static_cast<int>((hp.J + 127) / 128);
-  const int kdim = static_cast<int>(ldpsi);
+  const int kdim = static_cast<int>(kfd);
   if (Lc > 128) {
     const int nxt = static_cast<int>((Lc + 255) / 256);
     const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(nw) * nxt, 8));
@@ -2684,7 +2709,8 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
   const WsLayout lay = ws_layout(hp, dp, L, frame_tile);
   unsigned char* base = static_cast<unsigned char*>(ensure_ws(dp, ws, ws_bytes, lay.total));
   const int64_t frame_elems = static_cast<int64_t>(hp.M) * (hp.K + 1);  // complex per frame
-  const int64_t ldpsi = static_cast<int64_t>(hp.P) * dp.Kp;
+  const int64_t kfd = static_cast<int64_t>(hp.P) * dp.Kp;           // FD contraction length
+  const int64_t ldpsi = fd_ld(hp, dp, dsize(hp.dtype));              // row pitch of psi and H
   for (int64_t l0 = 0; l0 < L; l0 += lay.Lc) {
     const int64_t Lc = std::min(lay.Lc, L - l0);
     const void* fr = static_cast<const float2*>(frames) + l0 * frame_elems;
@@ -2695,8 +2721,9 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
       phat_dispatch(hp, dp, fr, Lc, psi, SRP_F32, st);
       float* g32 = reinterpret_cast<float*>(base + lay.g32);
       float* z = static_cast<float*>(maps) + l0 * ldm;
-      launch_gemm<float, BIG_BX, BIG_BW, BIG_WGX, BIG_BKB>(dp, "lr_fat", psi, ldpsi, dp.d_F, ldpsi, g32, dp.Kc,
-                                                           (int)Lc, dp.Kc, (int)ldpsi, 1.0f, lay.Lpad, st, dp.Fpad);
+      launch_gemm<float, BIG_BX, BIG_BW, BIG_WGX, big_bkb<float>()>(dp, "lr_fat", psi, fd_ld(hp, dp, 4), dp.d_F, kfd,
+                                                                   g32, dp.Kc, (int)Lc, dp.Kc, (int)kfd, 1.0f,
+                                                                   lay.Lpad, st, dp.Fpad);
       void* g = base + lay.g;
       const int64_t ng = Lc * dp.Kc;
       const dim3 cg(static_cast<unsigned>((ng + 255) / 256));
@@ -2727,25 +2754,25 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
         TRACED(dp, "gemm_fd_f64", st,
                hipLaunchKernelGGL(gemm_nt_f64, grid, dim3(256), 0, st, static_cast<const double*>(psi), ldpsi,
                                   static_cast<const double*>(dp.d_H), ldpsi, z, ldm, static_cast<int>(Lc),
-                                  static_cast<int>(hp.J), static_cast<int>(ldpsi), 2.0));
+                                  static_cast<int>(hp.J), static_cast<int>(kfd), 2.0));
         check_launch("gemm_nt_f64");
         continue;
       }
       float* z = static_cast<float*>(maps) + l0 * ldm;
       if (dp.fd_gen) {
         switch (hp.dtype) {
-          case SRP_F32: launch_fd_gen<float>(hp, dp, psi, ldpsi, z, ldm, Lc, st); break;
-          case SRP_BF16: launch_fd_gen<__bf16>(hp, dp, psi, ldpsi, z, ldm, Lc, st); break;
-          case SRP_F16: launch_fd_gen<_Float16>(hp, dp, psi, ldpsi, z, ldm, Lc, st); break;
-          case SRP_FP8_E4M3: launch_fd_gen<fp8>(hp, dp, psi, ldpsi, z, ldm, Lc, st); break;
+          case SRP_F32: launch_fd_gen<float>(hp, dp, psi, ldpsi, kfd, z, ldm, Lc, st); break;
+          case SRP_BF16: launch_fd_gen<__bf16>(hp, dp, psi, ldpsi, kfd, z, ldm, Lc, st); break;
+          case SRP_F16: launch_fd_gen<_Float16>(hp, dp, psi, ldpsi, kfd, z, ldm, Lc, st); break;
+          case SRP_FP8_E4M3: launch_fd_gen<fp8>(hp, dp, psi, ldpsi, kfd, z, ldm, Lc, st); break;
         }
         continue;
       }
       switch (hp.dtype) {
-        case SRP_F32: launch_big_gemm<float>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
-        case SRP_BF16: launch_big_gemm<__bf16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
-        case SRP_F16: launch_big_gemm<_Float16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
-        case SRP_FP8_E4M3: launch_big_gemm<fp8>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)ldpsi, 2.0f, lay.Lpad, st); break;
+        case SRP_F32: launch_big_gemm<float>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)kfd, 2.0f, lay.Lpad, st); break;
+        case SRP_BF16: launch_big_gemm<__bf16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)kfd, 2.0f, lay.Lpad, st); break;
+        case SRP_F16: launch_big_gemm<_Float16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)kfd, 2.0f, lay.Lpad, st); break;
+        case SRP_FP8_E4M3: launch_big_gemm<fp8>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)kfd, 2.0f, lay.Lpad, st); break;
       }
       continue;
     }

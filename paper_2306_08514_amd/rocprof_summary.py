@@ -31,8 +31,8 @@ COPY_BYTES = 2 ** 30  # bench.py --copy-calibration: 2^28 float32 per copy
 # short names of the hot-path kernels, matched on the (possibly mangled) name
 _TAGS = [
     (r"gemm_nt_f64", "gemm_fd_f64"),
-    (r"gemm_nt<float, 256|gemm_ntIfLi256", "gemm_fd"),
-    (r"gemm_nt<(__bf16|_Float16|srp::fp8), 256|gemm_ntI(DF16b|DF16_|NS_3fp8E)Li256", "gemm_fd"),
+    # FD (and the LR fat stage): 128 x 128 tiles; the FP32 tall fallback: 256 x 128
+    (r"gemm_nt<[^,]+, 128, 128|gemm_ntI[^L]*Li128ELi128E", "gemm_fd"),
     (r"gemm_nt", "gemm_tall"),
     (r"tall_ws", "gemm_tall"),
     (r"sspi_gather", "sspi_gather"),
