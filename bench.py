@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--forms", default="fd,slri,sspi")
     ap.add_argument("--no-disc32", action="store_true", help="skip the large-aperture leg")
+    ap.add_argument("--no-other-forms", action="store_true",
+                    help="skip the SI / TD / global / LR / far-field timing leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
     return ap.parse_args()
@@ -195,6 +197,62 @@ def fixed_error_points(cfg, Y, Yt, z_fd, fd_maps_per_s, steps):
         out[form] = found
         out["sweeps"][form] = sweep
         log(f"fixed error {form}: {found}")
+    return out
+
+
+def bench_other_forms(cfg, Yt, steps):
+    """The comparison and global forms on the same room workload (L = 1000,
+    BF16 operands): SI (44), conv. TD-SRP (23), global SLRI (R_Lambda = 224,
+    the per-pair R = 8 budget) and global SSPI (mean 4 taps per location and
+    pair); LR-SRP (R_H = 64) on the paper's near-field geometry (J = 73,084,
+    2K = 512, 128 frames), whose P (K - 1) = 1530 keeps its fit quick, and
+    FD / SLRI / SSPI on far-field directions (2-degree half-sphere, J = 8101)."""
+    import torch
+    from paper_2306_08514_amd import native, scenes
+
+    def timed(p, Y_dev):
+        L = Y_dev.shape[0]
+        z = p.empty_maps(L)
+        ws = torch.empty(p.workspace_size(L), dtype=torch.uint8, device="cuda")
+        p.compute(Y_dev, maps=z, workspace=ws)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for e0, e1 in evs:
+            e0.record()
+            p.compute(Y_dev, maps=z, workspace=ws)
+            e1.record()
+        torch.cuda.synchronize()
+        ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+        info = p.info()
+        return {"ms_per_call": ms, "maps_per_s": L / (ms / 1e3), "frames": L, "J": info["J"],
+                "rank_or_q": info["rank_or_q"], "macs_per_map": info["macs_per_map"]}
+
+    out = {}
+    L = Yt.shape[0]
+    for name, variant, rq, kw in (("si", "si", 0, {}), ("td", "td", 0, {}),
+                                  ("slri_global_R224", "slri", 224, {"global_fit": True}),
+                                  ("sspi_global_q4", "sspi", 4, {"global_fit": True})):
+        t0 = time.time()
+        p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, rq, dtype="bf16", c=cfg["c"], **kw)
+        plan_s = time.time() - t0
+        out[name] = {"workload": "uca8_room125k", "operands": "bf16", "plan_seconds": plan_s, **timed(p, Yt)}
+        p.close()
+        log(f"other form {name}: {out[name]['ms_per_call']:.3f} ms per {L} maps")
+    nf, Ynf, _ = scenes.evaluation_scene("nf4", 16, 8)
+    Ynf_t = torch.from_numpy(Ynf).cuda()
+    t0 = time.time()
+    p = native.Plan(nf["mics"], nf["grid"], nf["fs"], nf["N"], "lr", 64, dtype="bf16", c=nf["c"])
+    out["lr_R64"] = {"workload": "nf4_paper73k (J = 73,084, 2K = 512)", "operands": "bf16",
+                     "plan_seconds": time.time() - t0, **timed(p, Ynf_t)}
+    p.close()
+    ff, Yff, _ = scenes.evaluation_scene("farfield", 16, 8)
+    Yff_t = torch.from_numpy(Yff).cuda()
+    for name, variant, rq, dt in (("ff_fd", "fd", 0, "f32"), ("ff_slri_R8", "slri", 8, "bf16"),
+                                  ("ff_sspi_Q4", "sspi", 4, "bf16")):
+        p = native.Plan(ff["mics"], ff["grid"], ff["fs"], ff["N"], variant, rq, dtype=dt, c=ff["c"], far_field=True)
+        out[name] = {"workload": "uca8_farfield8k (2-degree half-sphere, J = 8101)", "operands": dt, **timed(p, Yff_t)}
+        p.close()
+    log("other forms: " + ", ".join(f"{k} {v['maps_per_s']:.3g} maps/s" for k, v in out.items()))
     return out
 
 
@@ -391,6 +449,10 @@ def main():
                     "unit": dom["unit"], "frac": dom["frac"], "traffic": dom["traffic"],
                     "kernel": dom_name, "avg_ms": dom["avg_ms"]}
 
+    others = None
+    if not args.no_other_forms:
+        others = bench_other_forms(cfg, Yt, max(5, min(args.steps, 20)))
+
     disc32 = None
     if not args.no_disc32:
         del plans, outs, wss
@@ -426,6 +488,7 @@ def main():
         "at_fixed_error": fixed,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "other_forms": others,
         "large_aperture": disc32,
     }
     print(json.dumps(rec), flush=True)

@@ -920,30 +920,35 @@ __global__ __launch_bounds__(256) void slri_fat(const float* __restrict__ xiT, i
 
 // Global SLRI fat stage g = Lambda_fat xi (eq. (57) with the stacked fit of
 // (54)): g[l][c] = scale * sum_a V[a][c] xi[l][a] over all PN stacked
-// samples, 32 columns per block row (V zero-padded to Kc columns, so the
-// padding columns come out zero).
+// samples.  A wave holds 64 consecutive frames (coalesced xi rows) and 4
+// columns per lane (one 16-byte V load, uniform over the wave); a block is
+// 64 frames x 16 columns.  V is zero-padded to Kc columns, so the padding
+// columns come out zero.
 template <typename TG>
 __global__ __launch_bounds__(256) void slri_fat_global(const float* __restrict__ xiT, int64_t ldxi, int L,
                                                        int PN, const float* __restrict__ V, int Kc,
                                                        const float* __restrict__ gscale, TG* __restrict__ g) {
-  const int64_t l = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  const int c0 = blockIdx.y * 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t l = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+  const int c0 = blockIdx.y * 16 + wave * 4;
   if (l >= L) return;
-  float acc[32];
-#pragma unroll
-  for (int r = 0; r < 32; ++r) acc[r] = 0.0f;
+  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
   const float* xs = xiT + l;
-#pragma unroll 2
+#pragma unroll 4
   for (int a = 0; a < PN; ++a) {
     const float xv = xs[static_cast<int64_t>(a) * ldxi];
-    const float* va = V + static_cast<int64_t>(a) * Kc + c0;
-#pragma unroll
-    for (int r = 0; r < 32; ++r) acc[r] = __builtin_fmaf(va[r], xv, acc[r]);
+    const f32x4 v = *reinterpret_cast<const f32x4*>(V + static_cast<int64_t>(a) * Kc + c0);
+    a0 = __builtin_fmaf(v.x, xv, a0);
+    a1 = __builtin_fmaf(v.y, xv, a1);
+    a2 = __builtin_fmaf(v.z, xv, a2);
+    a3 = __builtin_fmaf(v.w, xv, a3);
   }
   const float sc = gscale[0];
   TG* gl = g + l * Kc + c0;
-#pragma unroll
-  for (int r = 0; r < 32; ++r) gl[r] = cvt<TG>(acc[r] * sc);
+  gl[0] = cvt<TG>(a0 * sc);
+  gl[1] = cvt<TG>(a1 * sc);
+  gl[2] = cvt<TG>(a2 * sc);
+  gl[3] = cvt<TG>(a3 * sc);
 }
 
 // ====================================================== SLRI tall stream ===
@@ -2588,7 +2593,7 @@ template <typename TG>
 void launch_fat(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t ldxi, int64_t Lc, void* g,
                 hipStream_t st) {
   if (hp.global_fit) {
-    dim3 g2(static_cast<unsigned>((Lc + 255) / 256), static_cast<unsigned>(dp.Kc / 32));
+    dim3 g2(static_cast<unsigned>((Lc + 63) / 64), static_cast<unsigned>(dp.Kc / 16));
     TRACED(dp, "slri_fat", st,
            hipLaunchKernelGGL(slri_fat_global<TG>, g2, dim3(256), 0, st, xiT, ldxi, static_cast<int>(Lc), hp.PN,
                               dp.d_V, dp.Kc, dp.d_gscale, static_cast<TG*>(g)));
