@@ -1,0 +1,64 @@
+"""Host logic of the benchmark and the profile summaries (no GPU)."""
+
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+from paper_2306_08514_amd import rocprof_summary as rs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    rec = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in rec["error"] and rec["n_gpus_requested"] == 2
+
+
+def _write_counters(d, counter, rows):
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "pmc_counter_collection.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Dispatch_Id", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, disp, val in rows:
+            w.writerow({"Kernel_Name": name, "Dispatch_Id": disp, "Counter_Name": counter, "Counter_Value": val})
+
+
+def test_traffic_is_calibrated_by_the_copy_and_summed_over_instances(tmp_path):
+    """A 1 GiB copy that reads 2^19 FETCH units and writes 2^20 WRITE units
+    fixes 2048 B and 1024 B per unit; a kernel's per-dispatch value is the
+    sum of its per-instance records, and the median over dispatches is kept."""
+    copy = "__amd_rocclr_copyBuffer"
+    fd = "void srp::gemm_nt<float, 128, 128, 2, 256, false>(srp::GemmBatch const*)"
+    _write_counters(str(tmp_path / "f"), "FETCH_SIZE",
+                    [(copy, 1, 2 ** 19), (copy, 2, 2 ** 19), (fd, 3, 600.0), (fd, 3, 400.0), (fd, 4, 1000.0)])
+    _write_counters(str(tmp_path / "w"), "WRITE_SIZE",
+                    [(copy, 1, 2 ** 20), (copy, 2, 2 ** 20), (fd, 3, 100.0), (fd, 4, 100.0)])
+    rec = rs.traffic(str(tmp_path / "f"), str(tmp_path / "w"))
+    assert rec["calibration"]["fetch_bytes_per_unit"] == 2048.0
+    assert rec["calibration"]["write_bytes_per_unit"] == 1024.0
+    k = rec["kernels"]["gemm_fd"]
+    assert k["dispatches"] == 2
+    assert k["fetch_bytes"] == 1000.0 * 2048 and k["write_bytes"] == 100.0 * 1024
+    assert k["bytes_per_launch"] == 1000.0 * 2048 + 100.0 * 1024
+    assert rec["source_sha256"] == rs.source_sha256()
+
+
+def test_kernel_tags():
+    assert rs.tag("void srp::gemm_nt<float, 128, 128, 2, 256, false>(x)") == "gemm_fd"
+    assert rs.tag("void srp::gemm_nt<float, 256, 128, 2, 128, false>(x)") == "gemm_tall"
+    assert rs.tag("_ZN3srp7tall_wsIDF16bLi16ELi8EEEvPKT_liS3_lPflilfiii") == "gemm_tall"
+    assert rs.tag("void srp::sspi_gather<__bf16, 4, 32, true>(x)") == "sspi_gather"
+
+
+def test_traffic_record_round_trips_through_the_summary(tmp_path):
+    md = tmp_path / "t.md"
+    md.write_text("# x\n\n```json\n" + json.dumps({"source_sha256": "abc", "kernels": {}}) + "\n```\n")
+    assert rs.read_traffic_record(str(md)) == {"source_sha256": "abc", "kernels": {}}
+    assert rs.read_traffic_record(str(tmp_path / "missing.md")) is None
