@@ -1748,7 +1748,24 @@ inline int64_t fd_ld(const HostPlan& hp, const DevicePlan& dp, size_t es) {
   return static_cast<int64_t>(hp.P) * dp.Kp + FD_ROW_PAD_BYTES / static_cast<int64_t>(es);
 }
 constexpr int TALL_BX = 256, TALL_BW = 128, TALL_WGX = 2, TALL_BKB = 128; // SLRI tall (FP32)
+// general tall GEMM for 16-bit and FP8 operands whose rows exceed the
+// streaming kernel's 1 KB (2 m disc: 3968 columns; SI): 128 x 128 tiles with
+// 256-byte slices, 0.53 against 0.67 ms on the 2 m disc (FP32 kept the
+// 256 x 128 / 128-byte tile, which was 6 % faster there)
+constexpr int TALL16_BX = 128, TALL16_BW = 128, TALL16_WGX = 2, TALL16_BKB = 256;
+constexpr int tall_bkb(int dtype) { return dtype == SRP_F32 ? TALL_BKB : TALL16_BKB; }
 constexpr int TALL_STEP_BYTES(int dtype) { return dtype == SRP_FP8_E4M3 ? 64 : 32; }  // Mfma<T>::STEP
+// Columns Kc of the tall operands for `raw` columns of data: a multiple of
+// four MFMA steps when the 16-bit / FP8 rows fit the streaming kernel (at
+// most 1 KB), else a whole K slice of the general GEMM that runs instead.
+inline int tall_cols(int dtype, int64_t raw) {
+  const int es = static_cast<int>(dsize(dtype));
+  if (dtype != SRP_F32) {
+    const int64_t ws = round_up(raw, 4 * TALL_STEP_BYTES(dtype) / es);
+    if (ws * es <= 1024) return static_cast<int>(ws);
+  }
+  return static_cast<int>(round_up(raw, tall_bkb(dtype) / es));
+}
 constexpr int TALL_CW = 8;  // compute waves per block of the tall kernel (256 candidates)
 constexpr int SSPI_FT = 32;                       // frames per SSPI block
 
@@ -1993,9 +2010,7 @@ static void build_lr_device(HostPlan& hp, DevicePlan& dp, Alloc& A, const double
     }
   }
   // runtime operands
-  const int es = static_cast<int>(dsize(hp.dtype));
-  const int elem_per_slice = std::max(TALL_BKB / es, hp.dtype == SRP_F32 ? 0 : 4 * TALL_STEP_BYTES(hp.dtype) / es);
-  dp.Kc = static_cast<int>(round_up(2 * R, std::max(elem_per_slice, 32)));
+  dp.Kc = static_cast<int>(round_up(tall_cols(hp.dtype, 2 * R), 32));
   dp.Fpad = static_cast<int>(round_up(dp.Kc, BIG_BW));
   const int64_t ldf = static_cast<int64_t>(P) * dp.Kp;
   std::vector<float> F(static_cast<size_t>(dp.Fpad) * ldf, 0.0f);
@@ -2159,9 +2174,7 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     const int vrows = 2 * hp.max_np + 1;
     // padded to a whole K slice of the FP32 GEMM and, for the 16-bit and
     // FP8 operands, to a multiple of four MFMA steps of the tall kernel
-    const int es = static_cast<int>(dsize(hp.dtype));
-    const int elem_per_slice = std::max(TALL_BKB / es, hp.dtype == SRP_F32 ? 0 : 4 * TALL_STEP_BYTES(hp.dtype) / es);
-    dp.Kc = static_cast<int>(round_up(static_cast<int64_t>(hp.global_fit ? 1 : P) * R, elem_per_slice));
+    dp.Kc = tall_cols(hp.dtype, static_cast<int64_t>(hp.global_fit ? 1 : P) * R);
     TmpBuf dx(hp.x.size() * sizeof(double));
     upload(dx.p, hp.x);
     if (hp.global_fit) {
@@ -2548,8 +2561,12 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
 #undef SRP_WS
     }
   }
-  launch_gemm<T, TALL_BX, TALL_BW, TALL_WGX, TALL_BKB>(dp, "gemm_tall", X, ldx, W, ldw, C, ldc, nx, nw, kdim, alpha,
-                                                      Lpad, st);
+  if constexpr (std::is_same<T, float>::value)
+    launch_gemm<T, TALL_BX, TALL_BW, TALL_WGX, TALL_BKB>(dp, "gemm_tall", X, ldx, W, ldw, C, ldc, nx, nw, kdim, alpha,
+                                                        Lpad, st);
+  else
+    launch_gemm<T, TALL16_BX, TALL16_BW, TALL16_WGX, TALL16_BKB>(dp, "gemm_tall", X, ldx, W, ldw, C, ldc, nx, nw, kdim,
+                                                                alpha, Lpad, st);
 }
 
 // Sampling front end straight from the frames: spectral slices, the slice
