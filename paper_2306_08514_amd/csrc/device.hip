@@ -881,22 +881,27 @@ __global__ __launch_bounds__(256) void slice_reduce(const float* __restrict__ pa
 }
 
 // SLRI fat stage g[l][p R + r] = gscale_p sum_n V_p[n][r] xi_p[l][n]
-// (eq. (57)): one thread per frame of pair blockIdx.y; V_p is wave-uniform
-// (scalar loads) and the xi^T reads are coalesced along frames.  Pair index
-// P zero-fills g's padding columns.
+// (eq. (57)) for pair blockIdx.y: a block covers 64 frames (one per lane,
+// coalesced xi^T reads) and splits the pair's lag rows over its four waves
+// (row n to wave n mod 4), whose partial sums meet in LDS in a fixed order;
+// V_p is wave-uniform (scalar loads).  The split keeps ~4x more loads in
+// flight for pairs with hundreds of lags.  Pair index P zero-fills g's
+// padding columns.
+constexpr int SLRI_FAT_FRAMES = 64, SLRI_FAT_SPLIT = 4;
 template <typename TG, int RMAX>
-__global__ __launch_bounds__(256) void slri_fat(const float* __restrict__ xiT, int64_t ldxi, int L,
-                                                const int32_t* __restrict__ np,
-                                                const int32_t* __restrict__ off,
-                                                const float* __restrict__ V, int vrows, int R,
-                                                const float* __restrict__ gscale, int P,
-                                                TG* __restrict__ g, int Kc) {
-  const int64_t l = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+__global__ __launch_bounds__(SLRI_FAT_FRAMES * SLRI_FAT_SPLIT) void slri_fat(
+    const float* __restrict__ xiT, int64_t ldxi, int L, const int32_t* __restrict__ np,
+    const int32_t* __restrict__ off, const float* __restrict__ V, int vrows, int R,
+    const float* __restrict__ gscale, int P, TG* __restrict__ g, int Kc) {
+  __shared__ float red[SLRI_FAT_SPLIT - 1][RMAX][SLRI_FAT_FRAMES];
+  const int lane = threadIdx.x % SLRI_FAT_FRAMES, part = threadIdx.x / SLRI_FAT_FRAMES;
+  const int64_t l = static_cast<int64_t>(blockIdx.x) * SLRI_FAT_FRAMES + lane;
   const int p = blockIdx.y;
-  if (l >= L) return;
+  const bool live = l < L;
   TG* gl = g + l * Kc;
-  if (p == P) {
-    for (int c = P * R; c < Kc; ++c) gl[c] = cvt<TG>(0.0f);
+  if (p == P) {  // uniform over the block
+    if (live && part == 0)
+      for (int c = P * R; c < Kc; ++c) gl[c] = cvt<TG>(0.0f);
     return;
   }
   float acc[RMAX];
@@ -905,17 +910,31 @@ __global__ __launch_bounds__(256) void slri_fat(const float* __restrict__ xiT, i
   const int nrows = 2 * np[p] + 1;
   const float* xs = xiT + static_cast<int64_t>(off[p]) * ldxi + l;
   const float* Vp = V + static_cast<int64_t>(p) * vrows * R;
+  if (live) {
 #pragma unroll 4
-  for (int n = 0; n < nrows; ++n) {
-    const float x = xs[static_cast<int64_t>(n) * ldxi];
+    for (int n = part; n < nrows; n += SLRI_FAT_SPLIT) {
+      const float x = xs[static_cast<int64_t>(n) * ldxi];
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r)
-      if (r < R) acc[r] = __builtin_fmaf(Vp[n * R + r], x, acc[r]);
+      for (int r = 0; r < RMAX; ++r)
+        if (r < R) acc[r] = __builtin_fmaf(Vp[n * R + r], x, acc[r]);
+    }
   }
-  const float sc = gscale[p];
+  if (part > 0) {
 #pragma unroll
-  for (int r = 0; r < RMAX; ++r)
-    if (r < R) gl[p * R + r] = cvt<TG>(acc[r] * sc);
+    for (int r = 0; r < RMAX; ++r) red[part - 1][r][lane] = acc[r];
+  }
+  __syncthreads();
+  if (part == 0 && live) {
+    const float sc = gscale[p];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      if (r >= R) break;
+      float sum = acc[r];
+#pragma unroll
+      for (int q = 0; q < SLRI_FAT_SPLIT - 1; ++q) sum += red[q][r][lane];
+      gl[p * R + r] = cvt<TG>(sum * sc);
+    }
+  }
 }
 
 // Global SLRI fat stage g = Lambda_fat xi (eq. (57) with the stacked fit of
@@ -2618,10 +2637,11 @@ void launch_fat(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t ld
   }
   {
     const int vrows = 2 * hp.max_np + 1;
-    dim3 g2(static_cast<unsigned>((Lc + 255) / 256), static_cast<unsigned>(hp.P + 1));
+    dim3 g2(static_cast<unsigned>((Lc + SLRI_FAT_FRAMES - 1) / SLRI_FAT_FRAMES), static_cast<unsigned>(hp.P + 1));
 #define SRP_FAT(RM)                                                                                       \
   TRACED(dp, "slri_fat", st,                                                                              \
-         hipLaunchKernelGGL((slri_fat<TG, RM>), g2, dim3(256), 0, st, xiT, ldxi, static_cast<int>(Lc),      \
+         hipLaunchKernelGGL((slri_fat<TG, RM>), g2, dim3(SLRI_FAT_FRAMES * SLRI_FAT_SPLIT), 0, st, xiT, ldxi, \
+                            static_cast<int>(Lc),                                                         \
                             dp.d_np, dp.d_off, dp.d_V, vrows, hp.R, dp.d_gscale, hp.P, static_cast<TG*>(g), \
                             dp.Kc))
     if (hp.R <= 8)
