@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void gemm_nt(const GemmBatch* __restrict__ bat
                                                const T* __restrict__ W, int64_t ldw,
                                                float* __restrict__ C, int64_t ldc, int nw,
                                                int kdim, float alpha, int nx_single,
-                                               int nw_tiles, int nx_tiles) {
+                                               int nw_tiles, int nx_tiles, int64_t cz_rows) {
   constexpr int STEP = Mfma<T>::STEP;
   constexpr int LB = STEP / 2;   // bytes per lane per step
   constexpr int NV = LB / 16;    // 16-byte vectors per lane per step
@@ -288,7 +288,11 @@ __global__ __launch_bounds__(256) void gemm_nt(const GemmBatch* __restrict__ bat
   __shared__ __attribute__((aligned(16))) unsigned char lds[(BX + BW) * ROWB];
 
   // batched (one entry per blockIdx.z) or a single product with nx rows
-  const GemmBatch bt = batches ? batches[blockIdx.z] : GemmBatch{0, 0, 0, nx_single, 0};
+  // whose contraction is split over blockIdx.z: split z covers elements
+  // [z kdim, (z + 1) kdim) and writes rows [z cz_rows, ...) of C
+  const int64_t kz = static_cast<int64_t>(blockIdx.z) * kdim;
+  const GemmBatch bt = batches ? batches[blockIdx.z]
+                               : GemmBatch{kz, kz, static_cast<int64_t>(blockIdx.z) * cz_rows, nx_single, 0};
   const int nx = bt.nx;
   int wt, xt;
   if (!xcd_tile(nw_tiles, nx_tiles, wt, xt)) return;  // uniform over the block
@@ -2109,7 +2113,10 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     const size_t es = dsize(hp.dtype);
     const size_t hbytes = static_cast<size_t>(dp.Jpad) * fd_ld(hp, dp, es) * es;
     // resident H up to 16 GiB (and within the budget); beyond, the steering
-    // is generated on the fly from the FP64 TDOAs
+    // is generated on the fly from the FP64 TDOAs, once per call.  (A 48 GiB
+    // cap doubled the serving mix's resident bytes for no throughput: a
+    // resident 33 GB H is re-read from HBM on every small batch, which costs
+    // about what generating it does.)
     const bool fits = hbytes <= (size_t(16) << 30) && (budget == 0 || hbytes + dp.resident_bytes <= budget);
     dp.fd_gen = hp.fd_steering == 2 || (hp.fd_steering == 0 && !fits);
     if (dp.fd_gen) {
@@ -2119,6 +2126,17 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
       return;
     }
     dp.d_H = A.get(hbytes);
+    // few candidate tiles (small grids, long contractions): split the
+    // contraction over blockIdx.z so that the GEMM has ~512 blocks per frame
+    // tile; a plan constant, so a frame's map does not depend on its batch
+    const int64_t nwt = dp.Jpad / BIG_BW;
+    if (hp.dtype != SRP_F64 && nwt < 64) {
+      const int64_t slices = static_cast<int64_t>(P) * dp.Kp * static_cast<int64_t>(es) /
+                             (hp.dtype == SRP_FP8_E4M3 ? 128 : 256);
+      int ks = 1;
+      while (ks < 64 && nwt * ks * 2 <= 512 && slices % (ks * 2) == 0 && slices / (ks * 2) >= 16) ks *= 2;
+      dp.fd_ksplit = ks;
+    }
     double* d_x = nullptr;
     HIP_OK(hipMalloc(&d_x, hp.x.size() * sizeof(double)));
     try {
@@ -2423,6 +2441,11 @@ WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t 
   size_t off = 0;
   w.psi = off;
   if (hp.variant == SRP_FD) off = align256(off + static_cast<size_t>(w.Lpad) * fd_ld(hp, dp, dsize(hp.dtype)) * dsize(hp.dtype));
+  if (hp.variant == SRP_FD && dp.fd_ksplit > 1) {
+    // partial products of the split contraction, [ksplit][Lpad][Jpad]
+    w.part = off;
+    off = align256(off + static_cast<size_t>(dp.fd_ksplit) * w.Lpad * dp.Jpad * 4);
+  }
   if (hp.variant == SRP_LR) {
     // FP32 cross-spectra, the FP32 fat-stage output and its narrowed copy
     off = align256(off + static_cast<size_t>(w.Lpad) * fd_ld(hp, dp, 4) * 4);
@@ -2477,25 +2500,42 @@ void phat_dispatch(const HostPlan& hp, DevicePlan& dp, const void* frames, int64
   }
 }
 
+// C = alpha X W^T; with ksplit > 1 the contraction (kdim elements) is split
+// into ksplit equal parts whose products go to row blocks of cz_rows rows of
+// C (partial sums, reduced by the caller).
 template <typename T, int BX, int BW, int WGX, int BKB>
 void launch_gemm(DevicePlan& dp, const char* kname, const void* X, int64_t ldx, const void* W, int64_t ldw,
                  float* C, int64_t ldc, int nx, int nw, int kdim, float alpha, int64_t Lpad, hipStream_t st,
-                 int64_t wrows = 0) {
+                 int64_t wrows = 0, int ksplit = 1, int64_t cz_rows = 0) {
   const int nwt = static_cast<int>((wrows ? wrows : dp.Jpad) / BW);
   const int nxt = static_cast<int>(Lpad / BX);
   const int blocks = static_cast<int>(round_up(static_cast<int64_t>(nwt) * nxt, 8));
   TRACED(dp, kname, st,
-         hipLaunchKernelGGL((gemm_nt<T, BX, BW, WGX, BKB, false>), dim3(blocks), dim3(256), 0, st,
+         hipLaunchKernelGGL((gemm_nt<T, BX, BW, WGX, BKB, false>), dim3(blocks, 1, ksplit), dim3(256), 0, st,
                             static_cast<const GemmBatch*>(nullptr), static_cast<const T*>(X), ldx,
-                            static_cast<const T*>(W), ldw, C, ldc, nw, kdim, alpha, nx, nwt, nxt));
+                            static_cast<const T*>(W), ldw, C, ldc, nw, kdim / ksplit, alpha, nx, nwt, nxt,
+                            cz_rows));
 }
 
 template <typename T>
 void launch_big_gemm(DevicePlan& dp, const char* kname, const void* X, int64_t ldx, const void* W, int64_t ldw,
                      float* C, int64_t ldc, int nx, int nw, int kdim, float alpha, int64_t Lpad,
-                     hipStream_t st) {
+                     hipStream_t st, int ksplit = 1, int64_t cz_rows = 0) {
   launch_gemm<T, BIG_BX, BIG_BW, BIG_WGX, big_bkb<T>()>(dp, kname, X, ldx, W, ldw, C, ldc, nx, nw, kdim, alpha, Lpad,
-                                                       st);
+                                                       st, 0, ksplit, cz_rows);
+}
+
+// z[l][j] = alpha sum_s part[s][l][j] over the ksplit partial products of
+// a split FD contraction, in split order.
+__global__ __launch_bounds__(256) void split_reduce(const float* __restrict__ part, int ksplit, int64_t cz_rows,
+                                                    int64_t ldp, int L, int64_t J, float alpha,
+                                                    float* __restrict__ z, int64_t ldz) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= static_cast<int64_t>(L) * J) return;
+  const int64_t l = i / J, j = i % J;
+  float s = 0.0f;
+  for (int q = 0; q < ksplit; ++q) s += part[(q * cz_rows + l) * ldp + j];
+  z[l * ldz + j] = alpha * s;
 }
 
 // Frame splits of the tall kernel: the number of ranges per candidate tile
@@ -2810,11 +2850,26 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
         }
         continue;
       }
-      switch (hp.dtype) {
-        case SRP_F32: launch_big_gemm<float>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)kfd, 2.0f, lay.Lpad, st); break;
-        case SRP_BF16: launch_big_gemm<__bf16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)kfd, 2.0f, lay.Lpad, st); break;
-        case SRP_F16: launch_big_gemm<_Float16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)kfd, 2.0f, lay.Lpad, st); break;
-        case SRP_FP8_E4M3: launch_big_gemm<fp8>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, z, ldm, (int)Lc, (int)hp.J, (int)kfd, 2.0f, lay.Lpad, st); break;
+      {
+        // split contraction: partial products into the workspace, then a
+        // fixed-order reduction
+        const int ks = dp.fd_ksplit;
+        float* part = reinterpret_cast<float*>(base + lay.part);
+        float* c = ks > 1 ? part : z;
+        const int64_t ldc = ks > 1 ? dp.Jpad : ldm;
+        const float a = ks > 1 ? 1.0f : 2.0f;
+        switch (hp.dtype) {
+          case SRP_F32: launch_big_gemm<float>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, c, ldc, (int)Lc, (int)hp.J, (int)kfd, a, lay.Lpad, st, ks, lay.Lpad); break;
+          case SRP_BF16: launch_big_gemm<__bf16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, c, ldc, (int)Lc, (int)hp.J, (int)kfd, a, lay.Lpad, st, ks, lay.Lpad); break;
+          case SRP_F16: launch_big_gemm<_Float16>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, c, ldc, (int)Lc, (int)hp.J, (int)kfd, a, lay.Lpad, st, ks, lay.Lpad); break;
+          case SRP_FP8_E4M3: launch_big_gemm<fp8>(dp, "gemm_fd", psi, ldpsi, dp.d_H, ldpsi, c, ldc, (int)Lc, (int)hp.J, (int)kfd, a, lay.Lpad, st, ks, lay.Lpad); break;
+        }
+        if (ks > 1) {
+          const int64_t n = Lc * hp.J;
+          TRACED(dp, "split_reduce", st,
+                 hipLaunchKernelGGL(split_reduce, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, part,
+                                    ks, lay.Lpad, dp.Jpad, static_cast<int>(Lc), hp.J, 2.0f, z, ldm));
+        }
       }
       continue;
     }

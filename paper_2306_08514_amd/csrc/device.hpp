@@ -32,6 +32,7 @@ struct DevicePlan {
   // FD
   void* d_H = nullptr;       // [Jpad][P*Kp] steering (cos, -sin) in dtype
   bool fd_gen = false;       // steering generated on the fly from d_xg
+  int fd_ksplit = 1;         // contraction splits of the resident FD GEMM (few candidate tiles)
   double* d_xg = nullptr;    // [P][J] TDOAs in samples (generated steering)
   // sampling (SLRI, SSPI)
   float* d_S = nullptr;      // [2 max_np + 1 + 32][Kp] rows 2cos / -2sin
