@@ -96,14 +96,14 @@ def kernel_rooflines(cfg, prof, L, P, K, PN):
 
 def cpu_baseline(cfg, Y, forms):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload:
-    64 frames at 16,384 of the 125,000 candidates per form (plan-time work
+    64 frames at 32,768 of the 125,000 candidates per form (plan-time work
     such as the SVD and window selection excluded); per-map time scaled by
-    J/16,384."""
+    J/32,768."""
     import oracle as o
     threads = len(os.sched_getaffinity(0))
     J = cfg["grid"].shape[0]
     rng = np.random.default_rng(11)
-    cols = np.sort(rng.choice(J, 16384, replace=False))
+    cols = np.sort(rng.choice(J, 32768, replace=False))
     Ls = 64
     Ys = Y[:Ls]
     x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
