@@ -136,8 +136,11 @@ typedef struct {
   srp_variant variant;
   srp_dtype dtype;
   double mean_n;         /* N of eq. (35) */
-  double macs_per_map;   /* run-time MACs per map: C (24), C_slri (61) or
-                            C_sspi (62), sampling counted as 2PN(K-1) */
+  double macs_per_map;   /* run-time MACs per map: C (24), C_slri (61),
+                            C_sspi (62) (global forms: R_Lambda (J + PN),
+                            the kept entries Q_Lambda) or C_lr (30); the
+                            sampling term is the form that runs, 2PN(K-1)
+                            or 8PK log2(2K) (49) */
   size_t device_bytes;   /* resident device memory owned by the plan */
   double plan_seconds;   /* wall time of plan construction */
   int64_t map_pitch;     /* recommended row pitch of the maps in elements:
@@ -233,7 +236,13 @@ srp_status srp_plan_info_get(srp_plan_t plan, srp_plan_info* info);
  *                                      to 2 max_np + 1 rows with zeros
  *          "slri_s"   double [P][2 max_np + 1] singular values, descending
  *          "sspi_start" int32 [J][P]  first lag s of the window (-N_p..)
- *          "sspi_w"   double [J][P][Q] weights sinc(x - s - q)
+ *          "sspi_w"   double [J][P][Q] weights sinc(x - s - q), zero past
+ *                                      the window's taps
+ *          "lr_s"     double [R_H]   the R_H largest singular values of H
+ *                                      (LR-SRP)
+ * With global_fit, "slri_u" is [J][R_Lambda], "slri_v" [PN][R_Lambda] and
+ * "slri_s" [PN] (the stacked fit of (54)); global SSPI exports its variable
+ * windows in the same [J][P][Q] layout, Q the widest window.
  * "tdoa", "slri_u", "sspi_start" and "sspi_w" are kept only by host-only
  * plans (device = -1): a device plan fits these on the device and frees the
  * host copies.  bytes: size of dst; *needed receives the required size.  dst

@@ -140,8 +140,9 @@ class Plan:
     """An SRP-map plan: geometry-dependent operands resident on one device.
 
     mics [M, 3], grid [J, 3] in metres (host arrays, copied); fs in Hz; N the
-    DFT length; variant in {"fd", "slri", "sspi"}; rank_or_q = R per pair
-    (SLRI) or Q per (location, pair) (SSPI); dtype in {"f32", "bf16", "f16",
+    DFT length; variant in {"fd", "slri", "sspi", "si", "td", "lr"};
+    rank_or_q = R per pair (SLRI), Q per (location, pair) (SSPI) or R_H
+    (LR-SRP), ignored for FD, SI and TD; dtype in {"f32", "bf16", "f16",
     "fp8", "f64"}; device = -1 builds the host-side plan only; sampling in
     {"auto", "direct", "fft"} selects the GCC sampling form of SLRI/SSPI;
     fd_steering in {"auto", "resident", "generated"} the FD steering operand;
