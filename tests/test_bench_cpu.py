@@ -53,6 +53,10 @@ def test_traffic_is_calibrated_by_the_copy_and_summed_over_instances(tmp_path):
 def test_kernel_tags():
     assert rs.tag("void srp::gemm_nt<float, 128, 128, 2, 256, false>(x)") == "gemm_fd"
     assert rs.tag("void srp::gemm_nt<float, 256, 128, 2, 128, false>(x)") == "gemm_tall"
+    assert rs.tag("void srp::gemm_nt<__bf16, 256, 256, 2, 128, false>(x)") == "gemm_fd"
+    assert rs.tag("void srp::gemm_nt<__bf16, 128, 128, 2, 256, false>(x)") == "gemm_tall"
+    assert rs.tag("_ZN3srp7gemm_ntIDF16bLi256ELi256ELi2ELi128ELb0EEEvPKNS_9GemmBatchE") == "gemm_fd"
+    assert rs.tag("_ZN3srp7gemm_ntIDF16bLi128ELi128ELi2ELi256ELb0EEEvPKNS_9GemmBatchE") == "gemm_tall"
     assert rs.tag("_ZN3srp7tall_wsIDF16bLi16ELi8EEEvPKT_liS3_lPflilfiii") == "gemm_tall"
     assert rs.tag("void srp::sspi_gather<__bf16, 4, 32, true>(x)") == "sspi_gather"
 
