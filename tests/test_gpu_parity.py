@@ -208,6 +208,20 @@ def test_fd_generated_steering(native, sq4, room_small, dtype):
             assert (np.linalg.norm(z - zr, axis=1) / np.linalg.norm(zr, axis=1)).max() <= 1e-5
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_fd_generated_steering_large_frame_tiles(native, sq4, dtype):
+    """Generated steering with more than 128 frames per call, which runs the
+    256-frame tile (300 frames: one full tile and a ragged one)."""
+    cfg, Y = sq4
+    Y3 = np.concatenate([Y, Y[::-1], Y])                 # 300 frames
+    _announce(f"fd generated square4 L={len(Y3)} {dtype}")
+    p = _plan(native, cfg, "fd", 0, dtype, fd_steering="generated")
+    z = p.compute(torch.from_numpy(Y3).cuda()).cpu().numpy()
+    ref = _oracle_maps("fd", Y, cfg, 0)
+    _check_maps(z, np.concatenate([ref, ref[::-1], ref]), TOL[dtype], f"fd gen L=300 {dtype}")
+    p.close()
+
+
 @pytest.mark.parametrize("variant", ["si", "td"])
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 def test_si_and_td_variants(native, sq4, room_small, variant, dtype):
