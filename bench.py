@@ -61,8 +61,12 @@ def kernel_rooflines(cfg, prof, L, P, K, PN):
       gemm_fd      2 J P (K-1) MACs per map            (eq. (24))
       gemm_tall    J R P MACs per map; HBM bytes = 4 J (map write)
                    + 2 J P R (BF16 U) per launch
-      sspi_gather  J P Q FMAs per map; HBM bytes = 4 J (map write)
-                   + J P (4 + 2 Q) (starts + BF16 weights) per launch
+      sspi         J P Q FMAs per map; HBM bytes = 4 J (map write)
+                   + J P (4 + 2 Q) (starts + BF16 weights) per launch;
+                   the time is that of every SSPI kernel after the
+                   sampling: the dense-window product on the matrix cores
+                   (its frame-major operand and the tall kernel) and the
+                   gather of the tiles it leaves
     """
     J = cfg["grid"].shape[0]
     out = {}
@@ -80,17 +84,21 @@ def kernel_rooflines(cfg, prof, L, P, K, PN):
         out["gemm_tall"] = {"bound": "hbm", "avg_ms": t * 1e3, "achieved": byts / t / 1e9,
                             "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": byts / t / 1e9 / PEAK["hbm_gbs"],
                             "mfma_tflops": 2.0 * J * P * 8 * L / t / 1e12}
-    sg = prof.get("sspi", {}).get("sspi_gather")
-    if sg:
-        t = sg[0] / sg[1] / 1e3
+    sp = prof.get("sspi", {})
+    parts = {k: sp[k] for k in ("xi_to_frames", "gemm_tall", "sspi_gather") if k in sp}
+    if parts:
+        t = sum(v[0] / v[1] for v in parts.values()) / 1e3
         fl = 2.0 * J * P * 4 * L
-        # BF16 weights run on v_dot2_f32_f16 (two MACs per lane and
-        # instruction), so the ceiling is the dual-issue FP32 vector rate
-        out["sspi_gather"] = {"bound": "alu", "avg_ms": t * 1e3, "achieved": fl / t / 1e12,
-                              "peak": PEAK["fp32_valu_dot2_tflops"], "unit": "TFLOP/s",
-                              "frac": fl / t / 1e12 / PEAK["fp32_valu_dot2_tflops"],
-                              "frac_of_fma_rate": fl / t / 1e12 / PEAK["fp32_valu_tflops_nonpacked"],
-                              "hbm_gbs": (4.0 * J * L + J * P * (4 + 2 * 4)) / t / 1e9}
+        # the gather runs BF16 weights on v_dot2_f32_f16 (two MACs per lane
+        # and instruction), so the vector ceiling is the dual-issue FP32
+        # rate; the map write is the HBM floor of either path
+        byts = 4.0 * J * L + J * P * (4 + 2 * 4)
+        out["sspi"] = {"bound": "alu", "avg_ms": t * 1e3, "achieved": fl / t / 1e12,
+                       "peak": PEAK["fp32_valu_dot2_tflops"], "unit": "TFLOP/s",
+                       "frac": fl / t / 1e12 / PEAK["fp32_valu_dot2_tflops"],
+                       "frac_of_fma_rate": fl / t / 1e12 / PEAK["fp32_valu_tflops_nonpacked"],
+                       "hbm_gbs": byts / t / 1e9, "hbm_frac": byts / t / 1e9 / PEAK["hbm_gbs"],
+                       "kernels_ms": {k: v[0] / v[1] for k, v in parts.items()}}
     return out
 
 
@@ -407,6 +415,9 @@ def main():
                           "plan_seconds": plan_s[form],
                           "resident_gib": plans[form].info()["device_bytes"] / 2 ** 30,
                           "kernels_ms_per_call": {k: v[0] / v[1] for k, v in prof[form].items()}}
+        if form == "sspi":
+            inf = plans[form].info()
+            per_form[form]["tiles_dense_gather"] = [inf["sspi_dense_tiles"], inf["sspi_gather_tiles"]]
     if "fd" in per_form:
         for form in per_form:
             per_form[form]["speedup_vs_fd_f32"] = per_form[form]["maps_per_s"] / per_form["fd"]["maps_per_s"]

@@ -150,6 +150,11 @@ typedef struct {
   int sampling_fft;      /* 1 if SLRI/SSPI sample the GCCs by the iFFT of
                             (46), 0 for the direct product of (40) */
   int fd_generated;      /* 1 if the FD steering is generated on the fly */
+  int sspi_dense_tiles;  /* SSPI with 16-bit weights: 256-candidate tiles
+                            whose lag windows (8-lag aligned, stacked over
+                            pairs) fit 512 columns and run as a dense
+                            contraction on the matrix cores; 0 otherwise */
+  int sspi_gather_tiles; /* SSPI tiles evaluated by the gather of (58) */
 } srp_plan_info;
 
 /* Fills *opts with the defaults listed above. */

@@ -260,6 +260,11 @@ srp_status srp_plan_info_get(srp_plan_t plan, srp_plan_info* info) {
   info->map_pitch = (hp.J + 127) / 128 * 128;
   info->sampling_fft = hp.fft ? 1 : 0;
   info->fd_generated = plan->dp.fd_gen ? 1 : 0;
+  if (hp.variant == SRP_SSPI) {
+    const int ntiles = static_cast<int>((hp.J + 255) / 256);
+    info->sspi_dense_tiles = plan->dp.sspi_dense ? plan->dp.n_dtiles : 0;
+    info->sspi_gather_tiles = plan->dp.sspi_dense ? plan->dp.n_gtiles : ntiles;
+  }
   return SRP_OK;
 }
 

@@ -990,11 +990,20 @@ __global__ __launch_bounds__(256) void slri_fat_global(const float* __restrict__
 // one of nsplit contiguous ranges of frame groups; the splits of a
 // candidate tile run back to back on one XCD (xcd_tile), so the U rows they
 // share are fetched from HBM once.
+// largest divisor of n that is at most 16: chunks per loader batch
+constexpr int batch_chunks(int n) {
+  int b = n < 16 ? n : 16;
+  while (n % b) --b;
+  return b;
+}
+
 template <typename T, int NS, int CW>
 __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g, int64_t ldg, int grows,
                                                const T* __restrict__ U, int64_t ldu,
                                                float* __restrict__ z, int64_t ldz, int L, int64_t J,
-                                               float alpha, int njt, int nsplit, int gps) {
+                                               float alpha, int njt, int nsplit, int gps,
+                                               const int32_t* __restrict__ ctab,
+                                               const int32_t* __restrict__ tlist) {
   constexpr int STEP = Mfma<T>::STEP;
   constexpr int LB = STEP / 2;
   constexpr int NV = LB / 16;
@@ -1005,28 +1014,47 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
   __shared__ __attribute__((aligned(16))) unsigned char gs[NBUF][32 * ROWP];
   int jt, sp;
   if (!xcd_tile(njt, nsplit, jt, sp)) return;
+  if (tlist) jt = tlist[jt];  // njt counts the listed tiles
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g0 = sp * gps;
   const int ng = std::min((L + 31) / 32, g0 + gps) - g0;  // groups of this block
   if (ng <= 0) return;  // block-uniform
 
   if (wave == CW) {
-    // loader: all of a group's loads in flight, then the LDS writes
+    // loader: all of a group's loads in flight, then the LDS writes.  With a
+    // chunk table (dense-window SSPI) the 16-byte chunks of a row come from
+    // the columns the table gives for this candidate tile (-1: zeros).
+    // (byte offsets within a row fit 32 bits: rows are at most 1 KB and
+    // table columns index the PNA < 2^30 samples of a frame; long rows are
+    // staged in batches of 16 chunks to stay inside the register budget
+    // the compute waves leave)
     const unsigned char* gb = reinterpret_cast<const unsigned char*>(g);
+    constexpr int PB = batch_chunks(PERL);
+    int32_t cb[PERL];
+#pragma unroll
+    for (int k = 0; k < PERL; ++k) {
+      const int c = lane + 64 * k;
+      cb[k] = ctab ? ctab[static_cast<int64_t>(jt) * CPR + c % CPR] * static_cast<int32_t>(sizeof(T))
+                   : 16 * (c % CPR);
+    }
     auto stage = [&](int i) {
-      i32x4 v[PERL];
 #pragma unroll
-      for (int k = 0; k < PERL; ++k) {
-        const int c = lane + 64 * k;
-        const int row = (g0 + i) * 32 + c / CPR;
-        v[k] = i32x4{0, 0, 0, 0};
-        if (row < grows)
-          v[k] = *reinterpret_cast<const i32x4*>(gb + static_cast<int64_t>(row) * ldg * sizeof(T) + 16 * (c % CPR));
-      }
+      for (int k0 = 0; k0 < PERL; k0 += PB) {
+        static_assert(PERL % PB == 0, "loader batches must tile the chunks");
+        i32x4 v[PB];
 #pragma unroll
-      for (int k = 0; k < PERL; ++k) {
-        const int c = lane + 64 * k;
-        *reinterpret_cast<i32x4*>(&gs[i % NBUF][(c / CPR) * ROWP + 16 * (c % CPR)]) = v[k];
+        for (int k = 0; k < PB; ++k) {
+          const int c = lane + 64 * (k0 + k);
+          const int row = (g0 + i) * 32 + c / CPR;
+          v[k] = i32x4{0, 0, 0, 0};
+          if (row < grows && cb[k0 + k] >= 0)
+            v[k] = *reinterpret_cast<const i32x4*>(gb + static_cast<int64_t>(row) * ldg * sizeof(T) + cb[k0 + k]);
+        }
+#pragma unroll
+        for (int k = 0; k < PB; ++k) {
+          const int c = lane + 64 * (k0 + k);
+          *reinterpret_cast<i32x4*>(&gs[i % NBUF][(c / CPR) * ROWP + 16 * (c % CPR)]) = v[k];
+        }
       }
     };
     stage(0);
@@ -1064,13 +1092,25 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
     const unsigned char* ar = &gs[i % NBUF][r32 * ROWP + gq * LB];
-    i32x4 af[NS][NV];
+    if constexpr (NS <= 16) {
+      i32x4 af[NS][NV];
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
+      for (int s = 0; s < NS; ++s)
 #pragma unroll
-      for (int v = 0; v < NV; ++v) af[s][v] = *reinterpret_cast<const i32x4*>(ar + s * STEP + 16 * v);
+        for (int v = 0; v < NV; ++v) af[s][v] = *reinterpret_cast<const i32x4*>(ar + s * STEP + 16 * v);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) Mfma<T>::run(af[s], uf[s], acc);
+      for (int s = 0; s < NS; ++s) Mfma<T>::run(af[s], uf[s], acc);
+    } else {
+      // long rows: U alone takes 4 NS registers, so the g fragments are
+      // read step by step (nine waves per block leave 168 per wave)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        i32x4 af[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) af[v] = *reinterpret_cast<const i32x4*>(ar + s * STEP + 16 * v);
+        Mfma<T>::run(af, uf[s], acc);
+      }
+    }
     // rows (frames) 8 (v / 4) + 4 gq + v % 4 of the group, column j0 + r32:
     // a uniform row pointer plus the lane's 32-bit offset
     float* zg = z + static_cast<int64_t>(grp) * 32 * ldz + j0;
@@ -1087,6 +1127,58 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
       }
     }
     __syncthreads();
+  }
+}
+
+// Dense-window SSPI operand: B[j][kpos(t, p) + (lag - a0(t, p))] = the tap
+// weights of candidate j and pair p (eq. (58) per (j, p)), from the gather
+// records (absolute start of tap 0 and Qs weights); every other entry of B
+// stays zero.  kpos and a0 place pair p's 8-aligned lag window inside the
+// contraction of candidate tile t = j / 256.
+template <typename TW>
+__global__ __launch_bounds__(256) void sspi_dense_weights(const int32_t* __restrict__ start,
+                                                          const TW* __restrict__ w, int Qs, int Q, int64_t J,
+                                                          const int32_t* __restrict__ off,
+                                                          const int32_t* __restrict__ a0,
+                                                          const int32_t* __restrict__ kpos, int P,
+                                                          const int32_t* __restrict__ tiles,
+                                                          TW* __restrict__ B, int kmax) {
+  const int64_t t = tiles[blockIdx.x];  // one block per listed tile
+  const int64_t j = t * 256 + threadIdx.x;
+  const int p = blockIdx.y;
+  if (j >= J) return;
+  const int64_t rec = static_cast<int64_t>(p) * J + j;
+  const int rel = start[rec] - off[p];  // tap 0 within the pair's lags
+  const int k0 = kpos[t * P + p] + rel - a0[t * P + p];
+  for (int q = 0; q < Q; ++q) {
+    const TW v = w[rec * Qs + q];
+    if (static_cast<float>(v) != 0.0f) B[j * kmax + k0 + q] = v;
+  }
+}
+
+// Frame-major samples for the dense-window SSPI: xf[l][a] = xi^T[colmap[a]][l]
+// (0 where colmap[a] < 0), narrowed to the operand type; 32 x 32 tiles
+// through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void xi_to_frames(const float* __restrict__ xiT, int64_t ldxi, int L, int PNA,
+                                                    const int32_t* __restrict__ colmap, T* __restrict__ xf,
+                                                    int64_t ldf) {
+  __shared__ float t[32][33];
+  const int a0 = blockIdx.x * 32, l0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int a = a0 + r, l = l0 + tx;
+    float v = 0.0f;
+    if (a < PNA && l < L) {
+      const int n = colmap[a];
+      if (n >= 0) v = xiT[static_cast<int64_t>(n) * ldxi + l];
+    }
+    t[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int l = l0 + r, a = a0 + tx;
+    if (l < L && a < PNA) xf[static_cast<int64_t>(l) * ldf + a] = cvt<T>(t[tx][r]);
   }
 }
 
@@ -1157,15 +1249,18 @@ __global__ __launch_bounds__(256) void sspi_gather(const float* __restrict__ xiT
                                                    const TW* __restrict__ w, int Qs,
                                                    const int2* __restrict__ win, int cap, int P,
                                                    int64_t J, int L, int nftiles,
-                                                   float* __restrict__ z, int64_t ldz) {
+                                                   float* __restrict__ z, int64_t ldz,
+                                                   const int32_t* __restrict__ tlist, int ntl) {
   constexpr int STRIDE = FT + 4;  // LDS row stride in 32-bit words
   constexpr int QP = PAIRS ? (Q + 1) / 2 : Q;
   constexpr int C4 = FT / 4;      // 16-byte pieces per staged row
   extern __shared__ __attribute__((aligned(16))) uint32_t xs[];
   __shared__ int pbase[SSPI_MAX_CHUNK + 1];
-  const int nj = static_cast<int>((J + 255) / 256);
+  // every location tile, or the ntl tiles listed
+  const int nj = tlist ? ntl : static_cast<int>((J + 255) / 256);
   int jt, ft;
   if (!xcd_tile(nj, nftiles, jt, ft)) return;
+  if (tlist) jt = tlist[jt];
   const int tid = threadIdx.x;
   const int64_t j = static_cast<int64_t>(jt) * 256 + tid;
   const bool live = j < J;
@@ -2090,6 +2185,102 @@ static void build_lr_device(HostPlan& hp, DevicePlan& dp, Alloc& A, const double
   HIP_OK(hipDeviceSynchronize());
 }
 
+// Dense-window SSPI (16-bit weights).  For candidate tile t (256
+// candidates, the tiles of sspi_windows and of the streaming tall kernel)
+// and pair p the taps fall inside the lag window win[t][p]; aligned to
+// 8-lag chunks ([a0, a1) within the pair) and stacked over pairs, these
+// windows form a contraction of K_t <= kmax columns, so that
+//   z[l][j] = sum_k xf[l][col_t(k)] B[j][k]
+// with B holding each candidate's tap weights at its lags' positions (zeros
+// elsewhere) and xf the samples frame-major, each pair's lags starting on an
+// 8-element boundary.  On the matrix cores this costs K_t MACs per candidate
+// and frame instead of the gather's P Q, but runs at the MFMA rate.  Tiles
+// whose K_t fits the streaming kernel's 1 KB rows go to the matrix cores,
+// the rest stay on the gather; built when at least half the tiles fit.
+static void build_sspi_dense(HostPlan& hp, DevicePlan& dp, Alloc& A, const std::vector<int2>& wins, int njt,
+                             int Qs) {
+  const int P = hp.P;
+  const int es = static_cast<int>(dsize(hp.dtype));
+  const int kcap = 1024 / es;  // the streaming kernel's row limit in elements
+  std::vector<int32_t> offA(P + 1, 0);
+  for (int p = 0; p < P; ++p) offA[p + 1] = offA[p] + static_cast<int32_t>(round_up(2 * hp.np[p] + 1, 8));
+  const int PNA = offA[P];
+  std::vector<int32_t> a0(static_cast<size_t>(njt) * P), kpos(static_cast<size_t>(njt) * P), kt(njt);
+  std::vector<int32_t> dtiles, gtiles;
+  int kmax = 0;
+  for (int t = 0; t < njt; ++t) {
+    int k = 0;
+    for (int p = 0; p < P; ++p) {
+      const int2 w = wins[static_cast<size_t>(t) * P + p];
+      const int lo = w.x - hp.off[p];  // first staged lag within the pair
+      const int b0 = lo / 8 * 8;
+      const int b1 = static_cast<int>(round_up(lo + w.y, 8));
+      a0[static_cast<size_t>(t) * P + p] = b0;
+      kpos[static_cast<size_t>(t) * P + p] = k;
+      k += b1 - b0;
+    }
+    kt[t] = k;
+    if (k <= kcap) {
+      dtiles.push_back(t);
+      kmax = std::max(kmax, k);
+    } else {
+      gtiles.push_back(t);
+    }
+  }
+  // worth it only when most tiles move to the matrix cores
+  if (2 * dtiles.size() < static_cast<size_t>(njt)) return;
+  kmax = static_cast<int>(round_up(kmax, 4 * TALL_STEP_BYTES(hp.dtype) / es));
+  // chunk columns of each dense tile in the frame-major samples
+  const int cpr = kmax / 8;
+  std::vector<int32_t> ctab(static_cast<size_t>(njt) * cpr, -1);
+  for (int t : dtiles)
+    for (int p = 0; p < P; ++p) {
+      const int b0 = a0[static_cast<size_t>(t) * P + p];
+      const int k0 = kpos[static_cast<size_t>(t) * P + p];
+      const int kn = (p + 1 < P ? kpos[static_cast<size_t>(t) * P + p + 1] : kt[t]) - k0;
+      for (int c = 0; c < kn / 8; ++c) {
+        // chunks past the last pair's lags carry only zero weights: read zeros
+        const int col = offA[p] + b0 + 8 * c;
+        ctab[static_cast<size_t>(t) * cpr + k0 / 8 + c] = col < PNA ? col : -1;
+      }
+    }
+  std::vector<int32_t> colmap(PNA, -1);
+  for (int p = 0; p < P; ++p)
+    for (int r = 0; r < 2 * hp.np[p] + 1; ++r) colmap[offA[p] + r] = hp.off[p] + r;
+  TmpBuf da0(a0.size() * 4), dkpos(kpos.size() * 4);
+  upload(da0.p, a0);
+  upload(dkpos.p, kpos);
+  dp.d_dtiles = static_cast<int32_t*>(A.get(dtiles.size() * 4));
+  upload(dp.d_dtiles, dtiles);
+  if (!gtiles.empty()) {
+    dp.d_gtiles = static_cast<int32_t*>(A.get(gtiles.size() * 4));
+    upload(dp.d_gtiles, gtiles);
+  }
+  const size_t bbytes = static_cast<size_t>(dp.Jpad) * kmax * es;
+  dp.d_B = A.get(bbytes);
+  HIP_OK(hipMemset(dp.d_B, 0, bbytes));
+  const dim3 gw(static_cast<unsigned>(dtiles.size()), static_cast<unsigned>(P));
+  if (hp.dtype == SRP_BF16)
+    hipLaunchKernelGGL(sspi_dense_weights<__bf16>, gw, dim3(256), 0, 0, dp.d_start, static_cast<const __bf16*>(dp.d_w),
+                       Qs, dp.sspi_q, hp.J, dp.d_off, da0.as<int32_t>(), dkpos.as<int32_t>(), P, dp.d_dtiles,
+                       static_cast<__bf16*>(dp.d_B), kmax);
+  else
+    hipLaunchKernelGGL(sspi_dense_weights<_Float16>, gw, dim3(256), 0, 0, dp.d_start,
+                       static_cast<const _Float16*>(dp.d_w), Qs, dp.sspi_q, hp.J, dp.d_off, da0.as<int32_t>(),
+                       dkpos.as<int32_t>(), P, dp.d_dtiles, static_cast<_Float16*>(dp.d_B), kmax);
+  check_launch("sspi_dense_weights");
+  dp.d_ctab = static_cast<int32_t*>(A.get(ctab.size() * 4));
+  upload(dp.d_ctab, ctab);
+  dp.d_colmap = static_cast<int32_t*>(A.get(colmap.size() * 4));
+  upload(dp.d_colmap, colmap);
+  HIP_OK(hipDeviceSynchronize());
+  dp.sspi_dense = true;
+  dp.sspi_kmax = kmax;
+  dp.sspi_pna = PNA;
+  dp.n_dtiles = static_cast<int>(dtiles.size());
+  dp.n_gtiles = static_cast<int>(gtiles.size());
+}
+
 void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budget) {
   (void)frame_tile;
   dp.device = -1;
@@ -2348,6 +2539,7 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     dp.sspi_cap = std::max(widest, 32 * 1024 / ((SSPI_FT + 4) * 4));
     if (static_cast<size_t>(dp.sspi_cap) * (SSPI_FT + 4) * 4 > 150 * 1024)
       throw Error{SRP_E_UNSUPPORTED, "a candidate tile spans too many lags of one pair for the SSPI tile"};
+    if (hp.dtype == SRP_BF16 || hp.dtype == SRP_F16) build_sspi_dense(hp, dp, A, wins, njt, Qs);
   }
 }
 
@@ -2428,7 +2620,8 @@ void device_free(DevicePlan& dp) {
   }
   for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
   void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_tasks, dp.d_tw, dp.d_w2,
-                  dp.d_U, dp.d_V, dp.d_gscale, dp.d_F, dp.d_start, dp.d_w, dp.d_win, dp.d_xg, dp.ws};
+                  dp.d_U, dp.d_V, dp.d_gscale, dp.d_F, dp.d_start, dp.d_w, dp.d_win, dp.d_xg, dp.d_B,
+                  dp.d_ctab, dp.d_colmap, dp.d_dtiles, dp.d_gtiles, dp.ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   dp = DevicePlan{};
@@ -2438,7 +2631,7 @@ namespace {
 
 struct WsLayout {
   int64_t Lc = 0, Lpad = 0;
-  size_t psi = 0, xi = 0, part = 0, g = 0, g32 = 0, total = 0;
+  size_t psi = 0, xi = 0, part = 0, g = 0, g32 = 0, xf = 0, total = 0;
 };
 
 WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t frame_tile) {
@@ -2476,6 +2669,10 @@ WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t 
   if (hp.variant == SRP_SLRI) {
     w.g = off;
     off = align256(off + static_cast<size_t>(w.Lpad) * dp.Kc * dsize(hp.dtype));
+  }
+  if (hp.variant == SRP_SSPI && dp.sspi_dense) {
+    w.xf = off;  // frame-major samples of the dense-window path
+    off = align256(off + static_cast<size_t>(w.Lpad) * dp.sspi_pna * dsize(hp.dtype));
   }
   w.total = off;
   return w;
@@ -2600,7 +2797,8 @@ void launch_fd_gen(const HostPlan& hp, DevicePlan& dp, const void* psi, int64_t 
 
 template <typename T>
 void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W, int64_t ldw, float* C,
-                      int64_t ldc, int nx, int nw, int kdim, float alpha, int64_t Lpad, hipStream_t st) {
+                      int64_t ldc, int nx, int nw, int kdim, float alpha, int64_t Lpad, hipStream_t st,
+                      const int32_t* ctab = nullptr, const int32_t* tlist = nullptr, int ntl = 0) {
   const int steps = kdim * static_cast<int>(sizeof(T)) / Mfma<T>::STEP;
   // 16-bit and FP8 operands with rows of at most 1 KB: U rows in registers,
   // g streamed through LDS by the loader wave; anything else takes the
@@ -2608,7 +2806,7 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
   if (!std::is_same<T, float>::value && steps <= 32 && kdim * static_cast<int>(sizeof(T)) <= 1024) {
     if (steps % 4 == 0 && 36 * ldc < (int64_t(1) << 31)) {
       constexpr int CW = TALL_CW;
-      const int njt = static_cast<int>((nw + 32 * CW - 1) / (32 * CW));
+      const int njt = tlist ? ntl : static_cast<int>((nw + 32 * CW - 1) / (32 * CW));
       const int ngroups = (nx + 31) / 32;
 #define SRP_WS(NSV)                                                                                           \
   case NSV:                                                                                                   \
@@ -2620,7 +2818,7 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
     TRACED(dp, "gemm_tall", st,                                                                               \
            hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * (CW + 1)), 0, st, static_cast<const T*>(X), ldx,  \
                               static_cast<int>(Lpad), static_cast<const T*>(W), ldw, C, ldc, nx,               \
-                              static_cast<int64_t>(nw), alpha, njt, nsplit, gps));                             \
+                              static_cast<int64_t>(nw), alpha, njt, nsplit, gps, ctab, tlist));                \
     return;                                                                                                   \
     }                                                                                                         \
     break;
@@ -2631,6 +2829,7 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
 #undef SRP_WS
     }
   }
+  if (ctab || tlist) throw Error{SRP_E_HIP, "dense-window SSPI needs the streaming tall kernel"};
   if constexpr (std::is_same<T, float>::value)
     launch_gemm<T, TALL_BX, TALL_BW, TALL_WGX, TALL_BKB>(dp, "gemm_tall", X, ldx, W, ldw, C, ldc, nx, nw, kdim, alpha,
                                                         Lpad, st);
@@ -2745,13 +2944,16 @@ void launch_sspi_q(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t
   if (lds > 60 * 1024)
     HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                static_cast<int>(lds)));
-  const int nj = static_cast<int>((hp.J + 255) / 256);
+  // with the dense-window path only the tiles it left over
+  const int32_t* tl = dp.sspi_dense ? dp.d_gtiles : nullptr;
+  const int nj = dp.sspi_dense ? dp.n_gtiles : static_cast<int>((hp.J + 255) / 256);
+  if (nj == 0) return;
   const int nf = static_cast<int>((Lc + SSPI_FT - 1) / SSPI_FT);
   const int blocks = static_cast<int>(round_up(static_cast<int64_t>(nj) * nf, 8));
   TRACED(dp, "sspi_gather", st,
          hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, xiT, Lpad, hp.PN, dp.d_start,
                             static_cast<const TW*>(dp.d_w), Qs, dp.d_win, dp.sspi_cap, hp.P, hp.J,
-                            static_cast<int>(Lc), nf, z, ldz));
+                            static_cast<int>(Lc), nf, z, ldz, tl, nj));
 }
 
 template <typename TW>
@@ -2910,6 +3112,28 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
       }
     } else {
       launch_front<0, float>(hp, dp, fr, Lc, xiT, lay.Lpad, part, nullptr, st);
+      if (dp.sspi_dense) {
+        // dense windows on the matrix cores: frame-major samples, then the
+        // streaming tall kernel with the per-tile chunk table
+        void* xf = base + lay.xf;
+        const dim3 gt(static_cast<unsigned>((dp.sspi_pna + 31) / 32), static_cast<unsigned>((Lc + 31) / 32));
+        if (hp.dtype == SRP_BF16) {
+          TRACED(dp, "xi_to_frames", st,
+                 hipLaunchKernelGGL(xi_to_frames<__bf16>, gt, dim3(256), 0, st, xiT, lay.Lpad, static_cast<int>(Lc),
+                                    dp.sspi_pna, dp.d_colmap, static_cast<__bf16*>(xf), dp.sspi_pna));
+          launch_tall_gemm<__bf16>(dp, xf, dp.sspi_pna, dp.d_B, dp.sspi_kmax, z, ldm, (int)Lc, (int)hp.J,
+                                   dp.sspi_kmax, 1.0f, lay.Lpad, st, dp.d_ctab, dp.d_dtiles, dp.n_dtiles);
+          if (dp.n_gtiles) launch_sspi<__bf16>(hp, dp, xiT, lay.Lpad, Lc, z, ldm, st);
+        } else {
+          TRACED(dp, "xi_to_frames", st,
+                 hipLaunchKernelGGL(xi_to_frames<_Float16>, gt, dim3(256), 0, st, xiT, lay.Lpad, static_cast<int>(Lc),
+                                    dp.sspi_pna, dp.d_colmap, static_cast<_Float16*>(xf), dp.sspi_pna));
+          launch_tall_gemm<_Float16>(dp, xf, dp.sspi_pna, dp.d_B, dp.sspi_kmax, z, ldm, (int)Lc, (int)hp.J,
+                                     dp.sspi_kmax, 1.0f, lay.Lpad, st, dp.d_ctab, dp.d_dtiles, dp.n_dtiles);
+          if (dp.n_gtiles) launch_sspi<_Float16>(hp, dp, xiT, lay.Lpad, Lc, z, ldm, st);
+        }
+        continue;
+      }
       switch (hp.dtype) {
         case SRP_F32: launch_sspi<float>(hp, dp, xiT, lay.Lpad, Lc, z, ldm, st); break;
         case SRP_BF16: launch_sspi<__bf16>(hp, dp, xiT, lay.Lpad, Lc, z, ldm, st); break;

@@ -60,6 +60,20 @@ struct DevicePlan {
   int2* d_win = nullptr;          // [J / 256 tiles][P] (first row, rows) lag window of a tile
   int sspi_cap = 0;               // LDS rows per staged chunk of the gather
   int sspi_q = 0;                 // taps per record read by the gather (>= the selection's Q)
+  // dense-window SSPI on the matrix cores (16-bit weights): per 256-candidate
+  // tile the pairs' lag windows, aligned to 8-lag chunks, form a contraction
+  // of up to sspi_kmax columns: B [Jpad][kmax] in dtype, the chunk columns of
+  // each tile in the frame-major samples (-1: zero), and the column map of
+  // those samples [PNA] (stacked lag or -1 for the alignment padding).  Tiles
+  // whose windows do not fit stay on the gather: the two tile lists.
+  bool sspi_dense = false;
+  int sspi_kmax = 0, sspi_pna = 0;
+  void* d_B = nullptr;
+  int32_t* d_ctab = nullptr;
+  int32_t* d_colmap = nullptr;
+  int32_t* d_dtiles = nullptr;     // tiles on the matrix cores
+  int32_t* d_gtiles = nullptr;     // tiles left to the gather
+  int n_dtiles = 0, n_gtiles = 0;
   // per-kernel timing (see srp_profile_enable)
   struct Span {
     const char* name;

@@ -1,0 +1,126 @@
+"""GPU parity of SSPI (55)/(58) with 16-bit weights where the lag windows of a
+256-candidate tile are evaluated as a dense contraction on the matrix cores
+and the remaining tiles by the gather, through the C ABI against the FP64
+oracle.  The plan reports how many tiles each path took; the workloads here
+are chosen so that both paths run inside one plan."""
+
+import numpy as np
+import pytest
+
+import oracle as o
+from paper_2306_08514_amd import scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "bf16": 1e-2, "f16": 1e-2}
+
+
+@pytest.fixture(scope="module")
+def native():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_08514_amd import native as nat
+    nat.lib()
+    return nat
+
+
+def _announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def room_slice():
+    """A contiguous run of the full-resolution room-125k grid (J = 7700, not a
+    tile multiple) that passes under the ceiling array, 19 frames: most
+    tiles have narrow lag windows, the tiles closest to the array do not."""
+    cfg = scenes.workload("uca8_room125k", L=19)
+    cfg["grid"] = cfg["grid"][58880:58880 + 7700]
+    Y = scenes.make_frames(cfg)
+    return cfg, Y
+
+
+@pytest.fixture(scope="module")
+def sq4():
+    cfg = scenes.workload("square4_plane1k", L=41)
+    return cfg, scenes.make_frames(cfg)
+
+
+def _ref(cfg, Y, Q, form="sspi", global_fit=False):
+    x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+    xi = o.gcc_samples_ifft(o.phat(Y), Np, cfg["N"] // 2)
+    if form == "td":
+        return o.td_map(xi, x, Np)
+    if global_fit:
+        return o.sspi_global_map(xi, o.sspi_global_select(x, Np, Q * x.shape[1] * len(Np)))
+    return o.sspi_map(xi, [o.sspi_select(x[p], Np[p], Q) for p in range(len(Np))], Np)
+
+
+def _plan(native, cfg, variant, rq, dtype, **kw):
+    return native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, rq, dtype=dtype, **kw)
+
+
+def _tiles(cfg):
+    return (len(cfg["grid"]) + 255) // 256
+
+
+def _check(z, ref, tol, label):
+    z = np.asarray(z, dtype=np.float64)
+    assert np.all(np.isfinite(z)), label
+    rel = o.rel_error(z, ref)
+    assert rel.max() <= tol, f"{label}: max rel error {rel.max():.3e}"
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("Q", [1, 3, 4, 8])
+def test_split_tiles_match_oracle(native, room_slice, dtype, Q):
+    cfg, Y = room_slice
+    _announce(f"sspi dense/gather split Q={Q} {dtype} J={len(cfg['grid'])}")
+    p = _plan(native, cfg, "sspi", Q, dtype)
+    info = p.info()
+    assert info["sspi_dense_tiles"] + info["sspi_gather_tiles"] == _tiles(cfg)
+    if Q <= 4:
+        assert info["sspi_dense_tiles"] > 0 and info["sspi_gather_tiles"] > 0, info
+    z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
+    _check(z, _ref(cfg, Y, Q), TOL[dtype], f"split Q={Q} {dtype}")
+    p.close()
+
+
+def test_all_dense_small_array_and_f32_gather(native, sq4):
+    """A 0.2 m square: every tile fits; FP32 weights always take the gather."""
+    cfg, Y = sq4
+    _announce("sspi all-dense square4 bf16 / f32 gather")
+    Yt = torch.from_numpy(Y).cuda()
+    ref = _ref(cfg, Y, 4)
+    p = _plan(native, cfg, "sspi", 4, "bf16")
+    assert p.info()["sspi_dense_tiles"] == _tiles(cfg) and p.info()["sspi_gather_tiles"] == 0
+    _check(p.compute(Yt).cpu().numpy(), ref, TOL["bf16"], "square4 dense bf16")
+    q = _plan(native, cfg, "sspi", 4, "f32")
+    assert q.info()["sspi_dense_tiles"] == 0 and q.info()["sspi_gather_tiles"] == _tiles(cfg)
+    _check(q.compute(Yt).cpu().numpy(), ref, TOL["f32"], "square4 gather f32")
+
+
+def test_global_and_td_on_split_tiles(native, room_slice):
+    cfg, Y = room_slice
+    Yt = torch.from_numpy(Y).cuda()
+    _announce("global sspi qbar=4 bf16 on the room slice")
+    p = _plan(native, cfg, "sspi", 4, "bf16", global_fit=True)
+    info = p.info()
+    assert info["sspi_dense_tiles"] + info["sspi_gather_tiles"] == _tiles(cfg)
+    _check(p.compute(Yt).cpu().numpy(), _ref(cfg, Y, 4, global_fit=True), TOL["bf16"], "global sspi bf16")
+    _announce("td bf16 on the room slice")
+    t = _plan(native, cfg, "td", 0, "bf16")
+    _check(t.compute(Yt).cpu().numpy(), _ref(cfg, Y, 1, form="td"), TOL["bf16"], "td bf16")
+
+
+def test_split_maps_do_not_depend_on_the_batch(native, room_slice):
+    """Each frame's map is the same bit for bit alone, at any batch offset
+    and in any batch size (frame groups of 32 never mix frames)."""
+    cfg, Y = room_slice
+    _announce("sspi split batch invariance bf16")
+    p = _plan(native, cfg, "sspi", 4, "bf16")
+    full = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
+    for a, b in ((0, 1), (5, 6), (3, 19), (18, 19)):
+        part = p.compute(torch.from_numpy(np.ascontiguousarray(Y[a:b])).cuda()).cpu().numpy()
+        np.testing.assert_array_equal(part, full[a:b])
