@@ -978,10 +978,13 @@ __global__ __launch_bounds__(256) void slri_fat_global(const float* __restrict__
 //
 // z[l][j] = alpha * sum_c g[l][c] U[j][c] (the tall stage of eq. (57)) for the
 // 16-bit and FP8 operands with rows of at most 1 KB.  Warp-specialised
-// streaming: one loader wave stages the g rows of the
-// next groups of 32 frames into LDS (three buffers, two groups ahead) while
-// CW compute waves (32 candidates each) multiply the current group and store
-// it.  vmcnt is
+// streaming: one loader wave stages the g rows of the next groups of 32
+// frames into LDS (three buffers, two groups ahead) while CW compute waves
+// (32 candidates each) multiply the current group and store it.  The loader
+// issues a group's loads one iteration before it writes them to LDS, so a
+// load round trip overlaps a whole group of compute instead of delaying the
+// group's barrier (rows whose chunks need separate column offsets and do not
+// fit this in registers are staged in batches).  vmcnt is
 // per wave and counts stores as well as loads, so keeping every global load
 // out of the compute waves means they never wait for their own map stores,
 // and the loader only ever waits for its loads.  The loads still queue
@@ -990,6 +993,7 @@ __global__ __launch_bounds__(256) void slri_fat_global(const float* __restrict__
 // one of nsplit contiguous ranges of frame groups; the splits of a
 // candidate tile run back to back on one XCD (xcd_tile), so the U rows they
 // share are fetched from HBM once.
+
 // largest divisor of n that is at most 16: chunks per loader batch
 constexpr int batch_chunks(int n) {
   int b = n < 16 ? n : 16;
@@ -1021,48 +1025,88 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
   if (ng <= 0) return;  // block-uniform
 
   if (wave == CW) {
-    // loader: all of a group's loads in flight, then the LDS writes.  With a
-    // chunk table (dense-window SSPI) the 16-byte chunks of a row come from
-    // the columns the table gives for this candidate tile (-1: zeros).
-    // (byte offsets within a row fit 32 bits: rows are at most 1 KB and
-    // table columns index the PNA < 2^30 samples of a frame; long rows are
-    // staged in batches of 16 chunks to stay inside the register budget
-    // the compute waves leave)
+    // loader.  With a chunk table (dense-window SSPI) the 16-byte chunks of
+    // a row come from the columns the table gives for this candidate tile
+    // (-1: zeros).  Byte offsets within a row fit 32 bits: rows are at most
+    // 1 KB and table columns index the PNA < 2^30 samples of a frame.
     const unsigned char* gb = reinterpret_cast<const unsigned char*>(g);
-    constexpr int PB = batch_chunks(PERL);
-    int32_t cb[PERL];
+    // one column offset per lane when a row's chunks tile the 64 lanes
+    constexpr bool ONE_CB = 64 % CPR == 0;
+    constexpr int NCB = ONE_CB ? 1 : PERL;
+    int32_t cb[NCB];
 #pragma unroll
-    for (int k = 0; k < PERL; ++k) {
+    for (int k = 0; k < NCB; ++k) {
       const int c = lane + 64 * k;
       cb[k] = ctab ? ctab[static_cast<int64_t>(jt) * CPR + c % CPR] * static_cast<int32_t>(sizeof(T))
                    : 16 * (c % CPR);
     }
-    auto stage = [&](int i) {
+    if constexpr (ONE_CB || PERL <= 16) {
+      // a group's loads are issued one iteration before their LDS writes,
+      // so their latency overlaps a whole group of compute
+      i32x4 v[PERL];
+      auto issue = [&](int i) {
 #pragma unroll
-      for (int k0 = 0; k0 < PERL; k0 += PB) {
-        static_assert(PERL % PB == 0, "loader batches must tile the chunks");
-        i32x4 v[PB];
-#pragma unroll
-        for (int k = 0; k < PB; ++k) {
-          const int c = lane + 64 * (k0 + k);
+        for (int k = 0; k < PERL; ++k) {
+          const int c = lane + 64 * k;
           const int row = (g0 + i) * 32 + c / CPR;
+          const int32_t o = cb[ONE_CB ? 0 : k];
           v[k] = i32x4{0, 0, 0, 0};
-          if (row < grows && cb[k0 + k] >= 0)
-            v[k] = *reinterpret_cast<const i32x4*>(gb + static_cast<int64_t>(row) * ldg * sizeof(T) + cb[k0 + k]);
+          if (row < grows && o >= 0)
+            v[k] = *reinterpret_cast<const i32x4*>(gb + static_cast<int64_t>(row) * ldg * sizeof(T) + o);
         }
+      };
+      auto commit = [&](int i) {
 #pragma unroll
-        for (int k = 0; k < PB; ++k) {
-          const int c = lane + 64 * (k0 + k);
+        for (int k = 0; k < PERL; ++k) {
+          const int c = lane + 64 * k;
           *reinterpret_cast<i32x4*>(&gs[i % NBUF][(c / CPR) * ROWP + 16 * (c % CPR)]) = v[k];
         }
+      };
+      issue(0);
+      commit(0);
+      if (ng > 1) {
+        issue(1);
+        commit(1);
       }
-    };
-    stage(0);
-    if (ng > 1) stage(1);
-    __syncthreads();
-    for (int i = 0; i < ng; ++i) {
-      if (i + 2 < ng) stage(i + 2);
+      if (ng > 2) issue(2);
       __syncthreads();
+      for (int i = 0; i < ng; ++i) {
+        // buffer (i + 2) % 3 was last read for group i - 1
+        if (i + 2 < ng) commit(i + 2);
+        if (i + 3 < ng) issue(i + 3);
+        __syncthreads();
+      }
+    } else {
+      // long rows whose offsets differ per chunk: batches of at most 16
+      // chunks, each loaded and written before the group's barrier
+      constexpr int PB = batch_chunks(PERL);
+      auto stage = [&](int i) {
+#pragma unroll
+        for (int k0 = 0; k0 < PERL; k0 += PB) {
+          static_assert(PERL % PB == 0, "loader batches must tile the chunks");
+          i32x4 v[PB];
+#pragma unroll
+          for (int k = 0; k < PB; ++k) {
+            const int c = lane + 64 * (k0 + k);
+            const int row = (g0 + i) * 32 + c / CPR;
+            v[k] = i32x4{0, 0, 0, 0};
+            if (row < grows && cb[k0 + k] >= 0)
+              v[k] = *reinterpret_cast<const i32x4*>(gb + static_cast<int64_t>(row) * ldg * sizeof(T) + cb[k0 + k]);
+          }
+#pragma unroll
+          for (int k = 0; k < PB; ++k) {
+            const int c = lane + 64 * (k0 + k);
+            *reinterpret_cast<i32x4*>(&gs[i % NBUF][(c / CPR) * ROWP + 16 * (c % CPR)]) = v[k];
+          }
+        }
+      };
+      stage(0);
+      if (ng > 1) stage(1);
+      __syncthreads();
+      for (int i = 0; i < ng; ++i) {
+        if (i + 2 < ng) stage(i + 2);
+        __syncthreads();
+      }
     }
     return;
   }
