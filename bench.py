@@ -85,7 +85,7 @@ def kernel_rooflines(cfg, prof, L, P, K, PN):
                             "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": byts / t / 1e9 / PEAK["hbm_gbs"],
                             "mfma_tflops": 2.0 * J * P * 8 * L / t / 1e12}
     sp = prof.get("sspi", {})
-    parts = {k: sp[k] for k in ("xi_to_frames", "gemm_tall", "sspi_gather") if k in sp}
+    parts = {k: sp[k] for k in ("xi_to_frames", "sspi_dense", "sspi_gather") if k in sp}
     if parts:
         t = sum(v[0] / v[1] for v in parts.values()) / 1e3
         fl = 2.0 * J * P * 4 * L

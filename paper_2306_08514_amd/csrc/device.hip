@@ -1001,7 +1001,7 @@ constexpr int batch_chunks(int n) {
   return b;
 }
 
-template <typename T, int NS, int CW>
+template <typename T, int NS, int CW, bool CT>
 __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g, int64_t ldg, int grows,
                                                const T* __restrict__ U, int64_t ldu,
                                                float* __restrict__ z, int64_t ldz, int L, int64_t J,
@@ -1025,7 +1025,7 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
   if (ng <= 0) return;  // block-uniform
 
   if (wave == CW) {
-    // loader.  With a chunk table (dense-window SSPI) the 16-byte chunks of
+    // loader.  With a chunk table (CT: dense-window SSPI) the 16-byte chunks of
     // a row come from the columns the table gives for this candidate tile
     // (-1: zeros).  Byte offsets within a row fit 32 bits: rows are at most
     // 1 KB and table columns index the PNA < 2^30 samples of a frame.
@@ -1037,8 +1037,10 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
 #pragma unroll
     for (int k = 0; k < NCB; ++k) {
       const int c = lane + 64 * k;
-      cb[k] = ctab ? ctab[static_cast<int64_t>(jt) * CPR + c % CPR] * static_cast<int32_t>(sizeof(T))
-                   : 16 * (c % CPR);
+      if constexpr (CT)
+        cb[k] = ctab[static_cast<int64_t>(jt) * CPR + c % CPR] * static_cast<int32_t>(sizeof(T));
+      else
+        cb[k] = 16 * (c % CPR);
     }
     if constexpr (ONE_CB || PERL <= 16) {
       // a group's loads are issued one iteration before their LDS writes,
@@ -2855,11 +2857,11 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
 #define SRP_WS(NSV)                                                                                           \
   case NSV:                                                                                                   \
     if constexpr (NSV * Mfma<T>::STEP <= 1024) {                                                              \
-    auto kern = &tall_ws<T, NSV, CW>;                                                                         \
+    auto kern = ctab ? &tall_ws<T, NSV, CW, true> : &tall_ws<T, NSV, CW, false>;                              \
     int nsplit, gps;                                                                                          \
     tall_split(dp, reinterpret_cast<const void*>(kern), 64 * (CW + 1), njt, ngroups, nsplit, gps);            \
     const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(njt) * nsplit, 8));          \
-    TRACED(dp, "gemm_tall", st,                                                                               \
+    TRACED(dp, ctab ? "sspi_dense" : "gemm_tall", st,                                                         \
            hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * (CW + 1)), 0, st, static_cast<const T*>(X), ldx,  \
                               static_cast<int>(Lpad), static_cast<const T*>(W), ldw, C, ldc, nx,               \
                               static_cast<int64_t>(nw), alpha, njt, nsplit, gps, ctab, tlist));                \

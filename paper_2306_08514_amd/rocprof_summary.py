@@ -35,8 +35,11 @@ _TAGS = [
     # the general tall GEMM: FP32 256 x 128, 16-bit / FP8 128 x 128
     (r"gemm_nt<float, 128, 128|gemm_ntIfLi128ELi128E|gemm_nt<[^,]+, 256, 256|gemm_ntI[^L]*Li256ELi256E", "gemm_fd"),
     (r"gemm_nt", "gemm_tall"),
+    (r"tall_ws<.*, true>|tall_wsI.*Lb1E", "sspi_dense"),
     (r"tall_ws", "gemm_tall"),
     (r"sspi_gather", "sspi_gather"),
+    (r"xi_to_frames", "xi_to_frames"),
+    (r"sspi_dense_weights", "sspi_dense_weights (plan)"),
     (r"spectral_slices", "spectral_slices"),
     (r"slice_reduce", "slice_reduce"),
     (r"slri_fat", "slri_fat"),

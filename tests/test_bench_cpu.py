@@ -57,7 +57,12 @@ def test_kernel_tags():
     assert rs.tag("void srp::gemm_nt<__bf16, 128, 128, 2, 256, false>(x)") == "gemm_tall"
     assert rs.tag("_ZN3srp7gemm_ntIDF16bLi256ELi256ELi2ELi128ELb0EEEvPKNS_9GemmBatchE") == "gemm_fd"
     assert rs.tag("_ZN3srp7gemm_ntIDF16bLi128ELi128ELi2ELi256ELb0EEEvPKNS_9GemmBatchE") == "gemm_tall"
-    assert rs.tag("_ZN3srp7tall_wsIDF16bLi16ELi8EEEvPKT_liS3_lPflilfiii") == "gemm_tall"
+    assert rs.tag("_ZN3srp7tall_wsIDF16bLi16ELi8ELb0EEEvPKT_liS3_lPflilfiiiPKiS6_") == "gemm_tall"
+    assert rs.tag("void srp::tall_ws<__bf16, 16, 8, false>(__bf16 const*, long)") == "gemm_tall"
+    # the tall kernel reading a per-tile chunk table: dense-window SSPI
+    assert rs.tag("_ZN3srp7tall_wsIDF16bLi32ELi8ELb1EEEvPKT_liS3_lPflilfiiiPKiS6_") == "sspi_dense"
+    assert rs.tag("void srp::tall_ws<__bf16, 32, 8, true>(__bf16 const*, long)") == "sspi_dense"
+    assert rs.tag("void srp::xi_to_frames<__bf16>(float const*, long)") == "xi_to_frames"
     assert rs.tag("void srp::sspi_gather<__bf16, 4, 32, true>(x)") == "sspi_gather"
 
 
