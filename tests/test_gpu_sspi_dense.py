@@ -124,3 +124,28 @@ def test_split_maps_do_not_depend_on_the_batch(native, room_slice):
     for a, b in ((0, 1), (5, 6), (3, 19), (18, 19)):
         part = p.compute(torch.from_numpy(np.ascontiguousarray(Y[a:b])).cuda()).cpu().numpy()
         np.testing.assert_array_equal(part, full[a:b])
+
+
+def test_split_tiles_across_streams_and_frame_chunks(native, room_slice):
+    """Maps of a plan with both tile kinds match across frame chunks that
+    reuse the workspace (frame tile 64 < 150 frames) and when two calls on
+    one plan run on two streams with their own workspaces."""
+    cfg, Y1 = room_slice
+    Y = np.concatenate([Y1] * 8)[:150]
+    _announce(f"sspi split frame chunks / two streams bf16 L={len(Y)}")
+    ref = _ref(cfg, Y1, 4)
+    p = _plan(native, cfg, "sspi", 4, "bf16", frame_tile=64)
+    assert p.info()["sspi_gather_tiles"] > 0
+    Yt = torch.from_numpy(Y).cuda()
+    z = p.compute(Yt).cpu().numpy()
+    for k in range(len(Y)):
+        _check(z[k:k + 1], ref[k % len(Y1):k % len(Y1) + 1], TOL["bf16"], f"chunked frame {k}")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for s, part in ((s1, Yt[:100]), (s2, Yt[40:150])):
+        with torch.cuda.stream(s):
+            ws = torch.empty(p.workspace_size(part.shape[0]), dtype=torch.uint8, device="cuda")
+            outs.append((p.compute(part, workspace=ws, stream=s), ws))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(outs[0][0].cpu().numpy(), z[:100])
+    np.testing.assert_array_equal(outs[1][0].cpu().numpy(), z[40:150])
