@@ -151,9 +151,10 @@ typedef struct {
                             (46), 0 for the direct product of (40) */
   int fd_generated;      /* 1 if the FD steering is generated on the fly */
   int sspi_dense_tiles;  /* SSPI with 16-bit weights: 256-candidate tiles
-                            whose lag windows (8-lag aligned, stacked over
-                            pairs) fit 512 columns and run as a dense
-                            contraction on the matrix cores; 0 otherwise */
+                            whose lag windows (each rounded up to 8 lags,
+                            stacked over pairs) fit 512 columns and run as
+                            a dense contraction on the matrix cores; 0
+                            otherwise */
   int sspi_gather_tiles; /* SSPI tiles evaluated by the gather of (58) */
 } srp_plan_info;
 

@@ -1179,8 +1179,8 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
 // Dense-window SSPI operand: B[j][kpos(t, p) + (lag - a0(t, p))] = the tap
 // weights of candidate j and pair p (eq. (58) per (j, p)), from the gather
 // records (absolute start of tap 0 and Qs weights); every other entry of B
-// stays zero.  kpos and a0 place pair p's 8-aligned lag window inside the
-// contraction of candidate tile t = j / 256.
+// stays zero.  kpos and a0 (first lag of the window) place pair p's window
+// inside the contraction of candidate tile t = j / 256.
 template <typename TW>
 __global__ __launch_bounds__(256) void sspi_dense_weights(const int32_t* __restrict__ start,
                                                           const TW* __restrict__ w, int Qs, int Q, int64_t J,
@@ -1196,35 +1196,43 @@ __global__ __launch_bounds__(256) void sspi_dense_weights(const int32_t* __restr
   const int64_t rec = static_cast<int64_t>(p) * J + j;
   const int rel = start[rec] - off[p];  // tap 0 within the pair's lags
   const int k0 = kpos[t * P + p] + rel - a0[t * P + p];
+  // the pair's slot of the contraction ends where the next pair's begins;
+  // only zero-weighted taps (past the pair's lags) fall beyond it
+  const int kend = p + 1 < P ? kpos[t * P + p + 1] : kmax;
   for (int q = 0; q < Q; ++q) {
     const TW v = w[rec * Qs + q];
-    if (static_cast<float>(v) != 0.0f) B[j * kmax + k0 + q] = v;
+    if (static_cast<float>(v) != 0.0f && k0 + q < kend) B[j * kmax + k0 + q] = v;
   }
 }
 
-// Frame-major samples for the dense-window SSPI: xf[l][a] = xi^T[colmap[a]][l]
-// (0 where colmap[a] < 0), narrowed to the operand type; 32 x 32 tiles
-// through LDS.
+// Frame-major samples for the dense-window SSPI, in 8 copies shifted by
+// c = 0..7 columns so that every window can start on a 16-byte chunk:
+// xf[l][c XW + a] = xi^T[colmap[a - c]][l] for 0 <= a - c < PNA (0 elsewhere
+// and where colmap < 0), narrowed to the operand type; 32 x 32 tiles through
+// LDS over the 8 XW columns of a row.
 template <typename T>
 __global__ __launch_bounds__(256) void xi_to_frames(const float* __restrict__ xiT, int64_t ldxi, int L, int PNA,
-                                                    const int32_t* __restrict__ colmap, T* __restrict__ xf,
-                                                    int64_t ldf) {
+                                                    int XW, const int32_t* __restrict__ colmap,
+                                                    T* __restrict__ xf, int64_t ldf) {
   __shared__ float t[32][33];
-  const int a0 = blockIdx.x * 32, l0 = blockIdx.y * 32;
+  const int v0 = blockIdx.x * 32, l0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int r = ty; r < 32; r += 8) {
-    const int a = a0 + r, l = l0 + tx;
-    float v = 0.0f;
-    if (a < PNA && l < L) {
-      const int n = colmap[a];
-      if (n >= 0) v = xiT[static_cast<int64_t>(n) * ldxi + l];
+    const int v = v0 + r, l = l0 + tx;
+    float x = 0.0f;
+    if (v < 8 * XW && l < L) {
+      const int c = v / XW, a = v % XW - c;
+      if (a >= 0 && a < PNA) {
+        const int n = colmap[a];
+        if (n >= 0) x = xiT[static_cast<int64_t>(n) * ldxi + l];
+      }
     }
-    t[r][tx] = v;
+    t[r][tx] = x;
   }
   __syncthreads();
   for (int r = ty; r < 32; r += 8) {
-    const int l = l0 + r, a = a0 + tx;
-    if (l < L && a < PNA) xf[static_cast<int64_t>(l) * ldf + a] = cvt<T>(t[tx][r]);
+    const int l = l0 + r, v = v0 + tx;
+    if (l < L && v < 8 * XW) xf[static_cast<int64_t>(l) * ldf + v] = cvt<T>(t[tx][r]);
   }
 }
 
@@ -2233,13 +2241,16 @@ static void build_lr_device(HostPlan& hp, DevicePlan& dp, Alloc& A, const double
 
 // Dense-window SSPI (16-bit weights).  For candidate tile t (256
 // candidates, the tiles of sspi_windows and of the streaming tall kernel)
-// and pair p the taps fall inside the lag window win[t][p]; aligned to
-// 8-lag chunks ([a0, a1) within the pair) and stacked over pairs, these
-// windows form a contraction of K_t <= kmax columns, so that
+// and pair p the taps fall inside the lag window win[t][p]; rounded up to
+// whole 8-lag chunks and stacked over pairs, these windows form a
+// contraction of K_t <= kmax columns, so that
 //   z[l][j] = sum_k xf[l][col_t(k)] B[j][k]
 // with B holding each candidate's tap weights at its lags' positions (zeros
 // elsewhere) and xf the samples frame-major, each pair's lags starting on an
-// 8-element boundary.  On the matrix cores this costs K_t MACs per candidate
+// 8-element boundary, in 8 copies shifted by 0..7 columns so that a window
+// starting at any lag is read in whole 16-byte chunks from one of them (the
+// lags a chunk reads past the window meet zero weights).  On the matrix
+// cores this costs K_t MACs per candidate
 // and frame instead of the gather's P Q, but runs at the MFMA rate.  Tiles
 // whose K_t fits the streaming kernel's 1 KB rows go to the matrix cores,
 // the rest stay on the gather; built when at least half the tiles fit.
@@ -2259,11 +2270,12 @@ static void build_sspi_dense(HostPlan& hp, DevicePlan& dp, Alloc& A, const std::
     for (int p = 0; p < P; ++p) {
       const int2 w = wins[static_cast<size_t>(t) * P + p];
       const int lo = w.x - hp.off[p];  // first staged lag within the pair
-      const int b0 = lo / 8 * 8;
-      const int b1 = static_cast<int>(round_up(lo + w.y, 8));
-      a0[static_cast<size_t>(t) * P + p] = b0;
+      // taps past the pair's 2 N_p + 1 lags (a gather width above the lag
+      // count) carry zero weight and are left out
+      const int len = std::max(0, std::min(w.y, 2 * hp.np[p] + 1 - lo));
+      a0[static_cast<size_t>(t) * P + p] = lo;
       kpos[static_cast<size_t>(t) * P + p] = k;
-      k += b1 - b0;
+      k += static_cast<int>(round_up(len, 8));
     }
     kt[t] = k;
     if (k <= kcap) {
@@ -2276,18 +2288,23 @@ static void build_sspi_dense(HostPlan& hp, DevicePlan& dp, Alloc& A, const std::
   // worth it only when most tiles move to the matrix cores
   if (2 * dtiles.size() < static_cast<size_t>(njt)) return;
   kmax = static_cast<int>(round_up(kmax, 4 * TALL_STEP_BYTES(hp.dtype) / es));
-  // chunk columns of each dense tile in the frame-major samples
+  // chunk columns of each dense tile in the frame-major samples: the window
+  // of pair p starting at lag lo is read from the copy shifted by
+  // c = (8 - lo % 8) % 8, where it starts on a chunk boundary; its last chunk
+  // ends before column offA[p + 1] + 14 <= XW of that copy
+  const int XW = PNA + 16;
   const int cpr = kmax / 8;
   std::vector<int32_t> ctab(static_cast<size_t>(njt) * cpr, -1);
   for (int t : dtiles)
     for (int p = 0; p < P; ++p) {
-      const int b0 = a0[static_cast<size_t>(t) * P + p];
+      const int lo = a0[static_cast<size_t>(t) * P + p];
       const int k0 = kpos[static_cast<size_t>(t) * P + p];
       const int kn = (p + 1 < P ? kpos[static_cast<size_t>(t) * P + p + 1] : kt[t]) - k0;
-      for (int c = 0; c < kn / 8; ++c) {
-        // chunks past the last pair's lags carry only zero weights: read zeros
-        const int col = offA[p] + b0 + 8 * c;
-        ctab[static_cast<size_t>(t) * cpr + k0 / 8 + c] = col < PNA ? col : -1;
+      const int c = (8 - lo % 8) % 8;
+      for (int m = 0; m < kn / 8; ++m) {
+        const int col = offA[p] + lo + c + 8 * m;
+        if (col % 8 != 0 || col + 8 > XW) throw Error{SRP_E_HIP, "dense-window SSPI: chunk outside its copy"};
+        ctab[static_cast<size_t>(t) * cpr + k0 / 8 + m] = c * XW + col;
       }
     }
   std::vector<int32_t> colmap(PNA, -1);
@@ -2323,6 +2340,7 @@ static void build_sspi_dense(HostPlan& hp, DevicePlan& dp, Alloc& A, const std::
   dp.sspi_dense = true;
   dp.sspi_kmax = kmax;
   dp.sspi_pna = PNA;
+  dp.sspi_xw = XW;
   dp.n_dtiles = static_cast<int>(dtiles.size());
   dp.n_gtiles = static_cast<int>(gtiles.size());
 }
@@ -2717,8 +2735,8 @@ WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t 
     off = align256(off + static_cast<size_t>(w.Lpad) * dp.Kc * dsize(hp.dtype));
   }
   if (hp.variant == SRP_SSPI && dp.sspi_dense) {
-    w.xf = off;  // frame-major samples of the dense-window path
-    off = align256(off + static_cast<size_t>(w.Lpad) * dp.sspi_pna * dsize(hp.dtype));
+    w.xf = off;  // frame-major samples of the dense-window path (8 shifted copies)
+    off = align256(off + static_cast<size_t>(w.Lpad) * 8 * dp.sspi_xw * dsize(hp.dtype));
   }
   w.total = off;
   return w;
@@ -3162,19 +3180,20 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
         // dense windows on the matrix cores: frame-major samples, then the
         // streaming tall kernel with the per-tile chunk table
         void* xf = base + lay.xf;
-        const dim3 gt(static_cast<unsigned>((dp.sspi_pna + 31) / 32), static_cast<unsigned>((Lc + 31) / 32));
+        const int64_t ldf = 8 * static_cast<int64_t>(dp.sspi_xw);
+        const dim3 gt(static_cast<unsigned>((ldf + 31) / 32), static_cast<unsigned>((Lc + 31) / 32));
         if (hp.dtype == SRP_BF16) {
           TRACED(dp, "xi_to_frames", st,
                  hipLaunchKernelGGL(xi_to_frames<__bf16>, gt, dim3(256), 0, st, xiT, lay.Lpad, static_cast<int>(Lc),
-                                    dp.sspi_pna, dp.d_colmap, static_cast<__bf16*>(xf), dp.sspi_pna));
-          launch_tall_gemm<__bf16>(dp, xf, dp.sspi_pna, dp.d_B, dp.sspi_kmax, z, ldm, (int)Lc, (int)hp.J,
+                                    dp.sspi_pna, dp.sspi_xw, dp.d_colmap, static_cast<__bf16*>(xf), ldf));
+          launch_tall_gemm<__bf16>(dp, xf, ldf, dp.d_B, dp.sspi_kmax, z, ldm, (int)Lc, (int)hp.J,
                                    dp.sspi_kmax, 1.0f, lay.Lpad, st, dp.d_ctab, dp.d_dtiles, dp.n_dtiles);
           if (dp.n_gtiles) launch_sspi<__bf16>(hp, dp, xiT, lay.Lpad, Lc, z, ldm, st);
         } else {
           TRACED(dp, "xi_to_frames", st,
                  hipLaunchKernelGGL(xi_to_frames<_Float16>, gt, dim3(256), 0, st, xiT, lay.Lpad, static_cast<int>(Lc),
-                                    dp.sspi_pna, dp.d_colmap, static_cast<_Float16*>(xf), dp.sspi_pna));
-          launch_tall_gemm<_Float16>(dp, xf, dp.sspi_pna, dp.d_B, dp.sspi_kmax, z, ldm, (int)Lc, (int)hp.J,
+                                    dp.sspi_pna, dp.sspi_xw, dp.d_colmap, static_cast<_Float16*>(xf), ldf));
+          launch_tall_gemm<_Float16>(dp, xf, ldf, dp.d_B, dp.sspi_kmax, z, ldm, (int)Lc, (int)hp.J,
                                      dp.sspi_kmax, 1.0f, lay.Lpad, st, dp.d_ctab, dp.d_dtiles, dp.n_dtiles);
           if (dp.n_gtiles) launch_sspi<_Float16>(hp, dp, xiT, lay.Lpad, Lc, z, ldm, st);
         }

@@ -61,13 +61,14 @@ struct DevicePlan {
   int sspi_cap = 0;               // LDS rows per staged chunk of the gather
   int sspi_q = 0;                 // taps per record read by the gather (>= the selection's Q)
   // dense-window SSPI on the matrix cores (16-bit weights): per 256-candidate
-  // tile the pairs' lag windows, aligned to 8-lag chunks, form a contraction
+  // tile the pairs' lag windows, each rounded up to 8-lag chunks, form a contraction
   // of up to sspi_kmax columns: B [Jpad][kmax] in dtype, the chunk columns of
   // each tile in the frame-major samples (-1: zero), and the column map of
   // those samples [PNA] (stacked lag or -1 for the alignment padding).  Tiles
   // whose windows do not fit stay on the gather: the two tile lists.
   bool sspi_dense = false;
   int sspi_kmax = 0, sspi_pna = 0;
+  int sspi_xw = 0;                 // width of one shifted copy of the frame-major samples (PNA + 16)
   void* d_B = nullptr;
   int32_t* d_ctab = nullptr;
   int32_t* d_colmap = nullptr;

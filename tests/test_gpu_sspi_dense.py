@@ -80,8 +80,11 @@ def test_split_tiles_match_oracle(native, room_slice, dtype, Q):
     p = _plan(native, cfg, "sspi", Q, dtype)
     info = p.info()
     assert info["sspi_dense_tiles"] + info["sspi_gather_tiles"] == _tiles(cfg)
-    if Q <= 4:
-        assert info["sspi_dense_tiles"] > 0 and info["sspi_gather_tiles"] > 0, info
+    # the windows widen with Q: one tap fits every tile here; from three
+    # taps on, the tiles right under the array stay on the gather
+    assert info["sspi_dense_tiles"] > 0, info
+    if Q >= 3:
+        assert info["sspi_gather_tiles"] > 0, (info["sspi_dense_tiles"], info["sspi_gather_tiles"])
     z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
     _check(z, _ref(cfg, Y, Q), TOL[dtype], f"split Q={Q} {dtype}")
     p.close()
