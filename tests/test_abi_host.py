@@ -308,3 +308,16 @@ def test_host_only_plan_refuses_compute_and_export_of_missing_data():
     with pytest.raises(native.SrpError):
         p.export("slri_u")
     L.srp_destroy(None)   # safe on NULL
+
+
+def test_host_plans_report_the_sspi_tile_split():
+    """Host-only plans run no kernels: an SSPI plan reports every candidate
+    tile on the gather and none on the matrix cores; other forms report
+    neither."""
+    _lib_or_skip()
+    p, cfg = _host_plan("sspi", 4, name="uca8_room125k", stride=3, dtype="bf16")
+    info = p.info()
+    assert info["sspi_dense_tiles"] == 0
+    assert info["sspi_gather_tiles"] == (len(cfg["grid"]) + 255) // 256
+    q, _ = _host_plan("slri", 4)
+    assert q.info()["sspi_dense_tiles"] == 0 and q.info()["sspi_gather_tiles"] == 0
