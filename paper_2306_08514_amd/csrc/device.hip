@@ -1208,32 +1208,34 @@ __global__ __launch_bounds__(256) void sspi_dense_weights(const int32_t* __restr
 // Frame-major samples for the dense-window SSPI, in 8 copies shifted by
 // c = 0..7 columns so that every window can start on a 16-byte chunk:
 // xf[l][c XW + a] = xi^T[colmap[a - c]][l] for 0 <= a - c < PNA (0 elsewhere
-// and where colmap < 0), narrowed to the operand type; 32 x 32 tiles through
-// LDS over the 8 XW columns of a row.
+// and where colmap < 0), narrowed to the operand type.  A block owns 32
+// columns a of every copy and 32 frames: it stages the 39 source columns
+// those reach (a - 7 .. a + 31) once in LDS and writes all 8 copies.
 template <typename T>
 __global__ __launch_bounds__(256) void xi_to_frames(const float* __restrict__ xiT, int64_t ldxi, int L, int PNA,
                                                     int XW, const int32_t* __restrict__ colmap,
                                                     T* __restrict__ xf, int64_t ldf) {
-  __shared__ float t[32][33];
-  const int v0 = blockIdx.x * 32, l0 = blockIdx.y * 32;
+  __shared__ float t[39][33];
+  const int a0 = blockIdx.x * 32, l0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int r = ty; r < 32; r += 8) {
-    const int v = v0 + r, l = l0 + tx;
+  for (int r = ty; r < 39; r += 8) {
+    const int a = a0 - 7 + r, l = l0 + tx;
     float x = 0.0f;
-    if (v < 8 * XW && l < L) {
-      const int c = v / XW, a = v % XW - c;
-      if (a >= 0 && a < PNA) {
-        const int n = colmap[a];
-        if (n >= 0) x = xiT[static_cast<int64_t>(n) * ldxi + l];
-      }
+    if (a >= 0 && a < PNA && l < L) {
+      const int n = colmap[a];
+      if (n >= 0) x = xiT[static_cast<int64_t>(n) * ldxi + l];
     }
     t[r][tx] = x;
   }
   __syncthreads();
-  for (int r = ty; r < 32; r += 8) {
-    const int l = l0 + r, v = v0 + tx;
-    if (l < L && v < 8 * XW) xf[static_cast<int64_t>(l) * ldf + v] = cvt<T>(t[tx][r]);
-  }
+  const int a = a0 + tx;
+  if (a >= XW) return;
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    for (int r = ty; r < 32; r += 8) {
+      const int l = l0 + r;
+      if (l < L) xf[static_cast<int64_t>(l) * ldf + c * XW + a] = cvt<T>(t[tx + 7 - c][r]);
+    }
 }
 
 // ========================================================= SSPI gather ===
@@ -2303,7 +2305,8 @@ static void build_sspi_dense(HostPlan& hp, DevicePlan& dp, Alloc& A, const std::
       const int c = (8 - lo % 8) % 8;
       for (int m = 0; m < kn / 8; ++m) {
         const int col = offA[p] + lo + c + 8 * m;
-        if (col % 8 != 0 || col + 8 > XW) throw Error{SRP_E_HIP, "dense-window SSPI: chunk outside its copy"};
+        if (col % 8 != 0 || col + 8 > XW)
+          throw Error{SRP_E_UNSUPPORTED, "dense-window SSPI: chunk outside its copy"};
         ctab[static_cast<size_t>(t) * cpr + k0 / 8 + m] = c * XW + col;
       }
     }
@@ -2893,7 +2896,7 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
 #undef SRP_WS
     }
   }
-  if (ctab || tlist) throw Error{SRP_E_HIP, "dense-window SSPI needs the streaming tall kernel"};
+  if (ctab || tlist) throw Error{SRP_E_UNSUPPORTED, "dense-window SSPI needs the streaming tall kernel"};
   if constexpr (std::is_same<T, float>::value)
     launch_gemm<T, TALL_BX, TALL_BW, TALL_WGX, TALL_BKB>(dp, "gemm_tall", X, ldx, W, ldw, C, ldc, nx, nw, kdim, alpha,
                                                         Lpad, st);
@@ -3181,7 +3184,7 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
         // streaming tall kernel with the per-tile chunk table
         void* xf = base + lay.xf;
         const int64_t ldf = 8 * static_cast<int64_t>(dp.sspi_xw);
-        const dim3 gt(static_cast<unsigned>((ldf + 31) / 32), static_cast<unsigned>((Lc + 31) / 32));
+        const dim3 gt(static_cast<unsigned>((dp.sspi_xw + 31) / 32), static_cast<unsigned>((Lc + 31) / 32));
         if (hp.dtype == SRP_BF16) {
           TRACED(dp, "xi_to_frames", st,
                  hipLaunchKernelGGL(xi_to_frames<__bf16>, gt, dim3(256), 0, st, xiT, lay.Lpad, static_cast<int>(Lc),
