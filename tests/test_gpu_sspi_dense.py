@@ -152,3 +152,30 @@ def test_split_tiles_across_streams_and_frame_chunks(native, room_slice):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(outs[0][0].cpu().numpy(), z[:100])
     np.testing.assert_array_equal(outs[1][0].cpu().numpy(), z[40:150])
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_dense_path_small_shapes(native, sq4, dtype):
+    """One pair and one candidate, one ragged tile (J = 300), a single frame
+    and an empty batch on the dense-window path."""
+    cfg, Y = sq4
+    _announce(f"sspi dense small shapes {dtype}")
+    cfg2 = dict(cfg)
+    cfg2["mics"] = cfg["mics"][:2]
+    cfg2["grid"] = cfg["grid"][5:6]
+    Y2 = np.ascontiguousarray(Y[:5, :2])
+    q = _plan(native, cfg2, "sspi", 2, dtype)
+    assert q.info()["sspi_dense_tiles"] == 1
+    z = q.compute(torch.from_numpy(Y2).cuda()).cpu().numpy().astype(np.float64)
+    ref2 = _ref(cfg2, Y2, 2)
+    # one value per map: the error against the largest of the five frames
+    assert np.abs(z - ref2).max() <= TOL[dtype] * np.abs(ref2).max(), "M=2 J=1"
+    cfg3 = dict(cfg)
+    cfg3["grid"] = cfg["grid"][:300]
+    p = _plan(native, cfg3, "sspi", 4, dtype)
+    assert p.info()["sspi_dense_tiles"] == 2
+    ref = _ref(cfg3, Y, 4)
+    _check(p.compute(torch.from_numpy(Y).cuda()).cpu().numpy(), ref, TOL[dtype], "J=300")
+    _check(p.compute(torch.from_numpy(Y[7:8]).cuda()).cpu().numpy(), ref[7:8], TOL[dtype], "L=1")
+    empty = torch.empty((0,) + Y.shape[1:], dtype=torch.complex64, device="cuda")
+    assert p.compute(empty).shape == (0, 300)
