@@ -285,11 +285,14 @@ def si_map(xi_list, x, Np):
 
 def td_map(xi_list, x, Np):
     """conv. TD-SRP map, (23): the GCC read at the TDOA rounded to the nearest
-    sample.  Rounding half away from zero."""
+    sample.  Rounding half away from zero; the lag is kept in the sampled
+    range [-N_p, N_p] (with N_aux = 0 an endfire TDOA can round to N_p + 1,
+    which the sampling of (46)-(48) does not hold)."""
     L = xi_list[0].shape[0]
     z = np.zeros((L, x.shape[1]))
     for p, n_p in enumerate(Np):
         n = np.sign(x[p]) * np.floor(np.abs(x[p]) + 0.5)
+        n = np.clip(n, -n_p, n_p)
         idx = (n + n_p).astype(np.int64)
         z += xi_list[p][:, idx]
     return z

@@ -1369,8 +1369,8 @@ __global__ __launch_bounds__(256) void sspi_gather(const float* __restrict__ xiT
           }
           const int n = wt[p0 + lo].x + (row - pbase[lo]);
           const float* src = xiT + static_cast<int64_t>(n) * ldxi + l0 + 4 * c4;
-          if (n < PN) a[u] = *reinterpret_cast<const f32x4*>(src);
-          if (PAIRS && n + 1 < PN) bb[u] = *reinterpret_cast<const f32x4*>(src + ldxi);
+          if (n >= 0 && n < PN) a[u] = *reinterpret_cast<const f32x4*>(src);
+          if (PAIRS && n + 1 >= 0 && n + 1 < PN) bb[u] = *reinterpret_cast<const f32x4*>(src + ldxi);
           dst[u] = row * STRIDE + 4 * c4;
         }
       }
@@ -1739,8 +1739,11 @@ __global__ __launch_bounds__(256) void sspi_windows(const double* __restrict__ x
     const int64_t rec = static_cast<int64_t>(p) * J + j;
     double s = ceil(xv - 0.5 * q);
     s = fmin(fmax(s, static_cast<double>(-npp)), static_cast<double>(npp - q + 1));
-    // conv. TD-SRP (23): the lag nearest to x, half away from zero
-    if (td) s = copysign(floor(fabs(xv) + 0.5), xv);
+    // conv. TD-SRP (23): the lag nearest to x, half away from zero, kept in
+    // the sampled range [-N_p, N_p] (with N_aux = 0 an endfire candidate can
+    // round to N_p + 1)
+    if (td) s = fmin(fmax(copysign(floor(fabs(xv) + 0.5), xv), static_cast<double>(-npp)),
+                     static_cast<double>(npp));
     // global selection: the window chosen on the host
     if (gstart) {
       s = gstart[rec];

@@ -495,8 +495,9 @@ void build_sspi(HostPlan& hp, int Q, int threads) {
         double* w = &hp.w[(static_cast<size_t>(j) * hp.P + p) * hp.Q];
         if (hp.form == SRP_TD) {
           // conv. TD-SRP (23): the lag nearest to x (half away from zero),
-          // unit weight
-          const double r = std::copysign(std::floor(std::fabs(x) + 0.5), x);
+          // unit weight, kept in the sampled range [-N_p, N_p]
+          const double r = std::min(std::max(std::copysign(std::floor(std::fabs(x) + 0.5), x),
+                                             static_cast<double>(-n_p)), static_cast<double>(n_p));
           hp.start[static_cast<size_t>(j) * hp.P + p] = static_cast<int>(r);
           w[0] = 1.0;
           continue;

@@ -321,3 +321,23 @@ def test_host_plans_report_the_sspi_tile_split():
     assert info["sspi_gather_tiles"] == (len(cfg["grid"]) + 255) // 256
     q, _ = _host_plan("slri", 4)
     assert q.info()["sspi_dense_tiles"] == 0 and q.info()["sspi_gather_tiles"] == 0
+
+def test_td_endfire_candidates_stay_in_the_sampled_range():
+    """With N_aux = 0, N_p = floor(d fs / c): a candidate on a pair's axis
+    beyond the array has |x_p| = d fs / c, which rounds to N_p + 1 when its
+    fraction is at least 1/2.  The TD plan's lag must stay at +-N_p (the
+    end of the sampled range), as in the oracle."""
+    _lib_or_skip()
+    fs, c = 16000.0, 343.0
+    d = 0.212                                   # d fs / c = 9.889: N_p = 9
+    mics = np.array([[0.0, 0.0, 0.0], [d, 0.0, 0.0]])
+    grid = np.array([[3.0, 0.0, 0.0], [-3.0, 0.0, 0.0], [0.05, 1.0, 0.0], [d + 1.0, 0.0, 0.0]])
+    x = o.tdoa_samples(mics, grid, fs, c)
+    Np = o.max_lags(mics, fs, c, 0)
+    assert Np[0] == 9 and np.abs(x[0, [0, 1, 3]]).min() > 9.5
+    p = native.Plan(mics, grid, fs, 64, "td", 0, n_aux=0, device=-1)
+    start = p.export("sspi_start").astype(np.int64).reshape(len(grid), 1)[:, 0]
+    n = np.clip(np.sign(x[0]) * np.floor(np.abs(x[0]) + 0.5), -9, 9)
+    np.testing.assert_array_equal(start, n)
+    assert start[0] == -9 and start[1] == 9 and start[3] == -9
+    p.close()

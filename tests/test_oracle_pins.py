@@ -314,12 +314,15 @@ def test_integer_tdoas_si_td_fd_agree():
 
 
 def test_td_map_rounds_to_nearest_lag():
-    K = 16
+    """(23) reads the GCC at the nearest lag: exact halves go away from zero
+    (so a banker's rounding, 0.5 -> 0 and 2.5 -> 2, fails), and a TDOA past
+    the sampled range [-N_p, N_p] (possible only with N_aux = 0) reads the
+    end lag."""
     Np = [5]
-    x = np.array([[0.4, 0.6, -1.6, 2.49, -2.51]])
+    x = np.array([[0.4, 0.6, -1.6, 2.49, -2.51, 0.5, -0.5, 2.5, -2.5, 4.5, 5.4, 5.5, -5.7]])
     xi = [np.arange(-5, 6, dtype=float)[None] * 10.0]      # xi[n] = 10 n
-    np.testing.assert_allclose(o.td_map(xi, x, Np)[0], [0, 10, -20, 20, -30])
-    del K
+    np.testing.assert_array_equal(o.td_map(xi, x, Np)[0],
+                                  [0, 10, -20, 20, -30, 10, -10, 30, -30, 50, 50, 50, -50])
 
 
 # ------------------------------------------------------------ P10 SLRI ---
