@@ -405,7 +405,13 @@ __global__ __launch_bounds__(256) void gemm_nt(const GemmBatch* __restrict__ bat
 // FP64 value by one rotation of BPS bins (at most K / BPS rotations, error
 // ~1e-15); within a slice the bins follow by FP32 rotation by
 // exp(+i pi x / K), a chain of at most BINS - 1 steps.
-template <typename T, int BX, int WGX>
+//
+// FLUSH (FP32 operands): each pair's products are summed in accumulators of
+// their own and added to the running total at the next pair.  One FP32
+// accumulator over the whole contraction (2 P (K - 1) terms, 1.0e6 on the
+// 2 m disc) drifts by about eps sqrt(n / 2) relative (4.6e-5 measured); per
+// pair the drift is that of 2 (K - 1) terms plus a P-term outer sum.
+template <typename T, int BX, int WGX, bool FLUSH = false>
 __global__ __launch_bounds__(256) void fd_gen(const T* __restrict__ X, int64_t ldx,
                                               const double* __restrict__ xg, int64_t J, int K, int Kp,
                                               float* __restrict__ C, int64_t ldc, int nx, int kdim, float alpha,
@@ -457,19 +463,40 @@ __global__ __launch_bounds__(256) void fd_gen(const T* __restrict__ X, int64_t l
     }
   };
 
-  f32x16 acc[NBX][NBW];
+  f32x16 acc[NBX][NBW], tot[FLUSH ? NBX : 1][FLUSH ? NBW : 1];
 #pragma unroll
   for (int a = 0; a < NBX; ++a)
 #pragma unroll
     for (int b = 0; b < NBW; ++b)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
+  if constexpr (FLUSH) {
+#pragma unroll
+    for (int a = 0; a < NBX; ++a)
+#pragma unroll
+      for (int b = 0; b < NBW; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) tot[a][b][v] = 0.0f;
+  }
 
   const int kbytes = kdim * static_cast<int>(sizeof(T));
   double gx = 0.0, gs_c = 1.0, gs_s = 0.0, gadv_c = 1.0, gadv_s = 0.0;  // generator state
   float gstep_c = 1.0f, gstep_s = 0.0f;
   gload(0);
   for (int kb = 0; kb < kbytes; kb += BKB) {
+    if constexpr (FLUSH) {
+      if (kb > 0 && (kb / static_cast<int>(sizeof(T))) % Kp == 0) {  // a new pair: uniform over the block
+#pragma unroll
+        for (int a = 0; a < NBX; ++a)
+#pragma unroll
+          for (int b = 0; b < NBW; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              tot[a][b][v] += acc[a][b][v];
+              acc[a][b][v] = 0.0f;
+            }
+      }
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
@@ -545,6 +572,14 @@ __global__ __launch_bounds__(256) void fd_gen(const T* __restrict__ X, int64_t l
 #pragma unroll
         for (int b = 0; b < NBW; ++b) Mfma<T>::run(fa[a], fb[b], acc[a][b]);
     }
+  }
+  if constexpr (FLUSH) {
+#pragma unroll
+    for (int a = 0; a < NBX; ++a)
+#pragma unroll
+      for (int b = 0; b < NBW; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[a][b][v] += tot[a][b][v];
   }
   // 32 x 32 accumulator layout: register v of lane i holds row
   // 8 (v / 4) + 4 (i / 32) + v % 4 and column i % 32
@@ -2850,6 +2885,16 @@ void launch_fd_gen(const HostPlan& hp, DevicePlan& dp, const void* psi, int64_t 
                    int64_t ldz, int64_t Lc, hipStream_t st) {
   const int nw = static_cast<int>((hp.J + 255) / 256);  // fd_gen's 256-candidate tiles
   const int kdim = static_cast<int>(kfd);
+  if constexpr (std::is_same<T, float>::value) {
+    // FP32: 64-frame tiles at every batch size, with per-pair accumulators
+    // (the FP32 matrix cores, not the tile's operand reuse, bound this form)
+    const int nxt = static_cast<int>((Lc + 63) / 64);
+    const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(nw) * nxt, 8));
+    TRACED(dp, "fd_gen", st,
+           hipLaunchKernelGGL((fd_gen<T, 64, 1, true>), dim3(blocks), dim3(256), 0, st, static_cast<const T*>(psi),
+                              ldpsi, dp.d_xg, hp.J, hp.K, dp.Kp, z, ldz, static_cast<int>(Lc), kdim, 2.0f, nw, nxt));
+    return;
+  }
   if (Lc > 128) {
     const int nxt = static_cast<int>((Lc + 255) / 256);
     const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(nw) * nxt, 8));
