@@ -1,17 +1,25 @@
 #!/usr/bin/env python3
 """SRP-map benchmark on one MI355X.
 
-Workload: M = 8 microphones (0.3 m UCA), J = 125,000 candidates (50 x 50 x 50
-over a 5 x 5 x 2.5 m room), fs = 16 kHz, N = 1024, L = 1000 STFT frames of a
-reverberant 1/f-noise scene (seeded synthetic frames, resident in HBM before
-timing starts).
+Workload (the metric's configuration): M = 8 microphones (0.3 m UCA),
+J = 125,000 candidates (50 x 50 x 50 over a 5 x 5 x 2.5 m room),
+fs = 16 kHz, N = 1024, L = 1000 STFT frames of a reverberant 1/f-noise
+scene (seeded synthetic frames, resident in HBM before timing starts).
+
+The metric compares reduced forms with FP32 conv. FD-SRP at a fixed map
+error.  Before the timed region the benchmark finds, for each reduced form
+with BF16 operands (per-pair SLRI, per-pair SSPI, and the paper's global
+SLRI and SSPI fits), the smallest rank or tap count whose median eps_z
+against the FP64 FD oracle is at most -20 dB (16 frames x 4096 sampled
+candidates).
 
 One step is one pass of the whole hot path over the 1000 frames: PHAT
-cross-spectra, conv. FD-SRP with FP32 operands (the reference form),
-GCC sampling, SLRI (R = 8 per pair, BF16 tall factor) and SSPI (Q = 4 per
-location and pair, BF16 weights); every form writes its 1000 maps.  `value`
-counts every map the step writes (3 L per step).  Per-form rates, p50/p99
-call latencies and each form's speed-up over FP32 FD are reported beside it.
+cross-spectra and conv. FD-SRP with FP32 operands (the reference form),
+then GCC sampling and each reduced form at its fixed-error setting; every
+form writes its 1000 maps.  `value` is the maps/s of the fastest reduced
+form at the fixed error (named in `config.headline`), from HIP events
+around its calls in the timed steps; FP32 FD maps/s and the speed-up stand
+beside it, and `step_maps_per_s` counts every map a step writes.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -27,11 +35,20 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32_mfma_tflops": 157.3, "bf16_mfma_tflops": 2500.0, "hbm_gbs": 8000.0,
+PEAK = {"fp32_mfma_tflops": 157.3, "bf16_mfma_tflops": 2500.0, "fp8_mfma_tflops": 5000.0, "hbm_gbs": 8000.0,
         "fp32_valu_tflops_nonpacked": 78.6, "fp32_valu_dot2_tflops": 157.3}
 METRIC = "SRP maps/sec (M=8, J=125k) vs FP32 conv FD-SRP at fixed error; p50/p99 ms"
+EPS_Z_TARGET_DB = -20.0
 
-FORMS = [("fd", 0, "f32"), ("slri", 8, "bf16"), ("sspi", 4, "bf16")]
+# reduced forms swept for the fixed-error point, BF16 operands:
+# (name, variant, settings in increasing cost, plan keywords)
+SWEEPS = [
+    ("slri", "slri", list(range(8, 33)), {}),
+    ("sspi", "sspi", list(range(2, 17)), {}),
+    ("slri_global", "slri", [56, 84, 112, 140, 168, 196, 224, 252, 280, 336, 392, 448, 504, 560, 660],
+     {"global_fit": True}),
+    ("sspi_global", "sspi", list(range(1, 9)), {"global_fit": True}),
+]
 
 
 def parse():
@@ -41,11 +58,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=None, help="override L (default 1000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--forms", default="fd,slri,sspi")
+    ap.add_argument("--no-precision", action="store_true", help="skip the configured-R/Q precision leg")
     ap.add_argument("--no-disc32", action="store_true", help="skip the large-aperture leg")
     ap.add_argument("--no-other-forms", action="store_true",
-                    help="skip the SI / TD / global / LR / far-field timing leg")
+                    help="skip the SI / TD / LR / far-field timing leg")
+    ap.add_argument("--fixed", default=None,
+                    help="skip the sweep: comma list name=setting, e.g. slri=21,sspi=3,slri_global=224,sspi_global=2")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
     return ap.parse_args()
@@ -55,58 +73,132 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_rooflines(cfg, prof, L, P, K, PN):
-    """Achieved rates of the main kernels from live HIP-event spans.
-    Algorithmic work per launch (one launch covers L frames):
-      gemm_fd      2 J P (K-1) MACs per map            (eq. (24))
-      gemm_tall    J R P MACs per map; HBM bytes = 4 J (map write)
-                   + 2 J P R (BF16 U) per launch
-      sspi         J P Q FMAs per map; HBM bytes = 4 J (map write)
-                   + J P (4 + 2 Q) (starts + BF16 weights) per launch;
-                   the time is that of every SSPI kernel after the
-                   sampling: the dense-window product on the matrix cores
-                   (its frame-major operand and the tall kernel) and the
-                   gather of the tiles it leaves
+def algorithmic_bytes(form, rq, J, L, M, K, P, op_bytes=2):
+    """HBM bytes one call must move: the frames in, the maps out and the
+    plan operand read once per call (intermediates such as psi, xi and g
+    are implementation traffic and not counted)."""
+    frames = 8.0 * M * (K + 1) * L
+    maps = 4.0 * J * L
+    if form == "fd":
+        plan = op_bytes * J * P * 2.0 * (K - 1)
+    elif form == "slri":
+        plan = op_bytes * J * P * rq
+    elif form == "slri_global":
+        plan = op_bytes * J * rq
+    elif form == "sspi":
+        plan = J * P * (4.0 + op_bytes * rq)
+    elif form == "sspi_global":
+        plan = J * P * 4.0 + op_bytes * rq * J * P
+    else:
+        raise ValueError(form)
+    return frames + maps + plan
+
+
+def timed_calls(p, Yt, steps, z=None):
+    import torch
+    L = Yt.shape[0]
+    z = p.empty_maps(L) if z is None else z
+    ws = torch.empty(max(1, p.workspace_size(L)), dtype=torch.uint8, device="cuda")
+    p.compute(Yt, maps=z, workspace=ws)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in evs:
+        e0.record()
+        p.compute(Yt, maps=z, workspace=ws)
+        e1.record()
+    torch.cuda.synchronize()
+    lat = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    return z, lat
+
+
+def fixed_error_sweep(cfg, Y, Yt, fixed=None):
+    """For each reduced form of SWEEPS (BF16 operands), the smallest setting
+    whose median eps_z against the FP64 FD oracle is <= -20 dB on 16 frames x
+    4096 sampled candidates; the eps_z of every setting tried."""
+    import torch
+    import oracle as o
+    from paper_2306_08514_amd import native
+    L, J = Y.shape[0], cfg["grid"].shape[0]
+    rng = np.random.default_rng(6)
+    fr = np.sort(rng.choice(L, 16, replace=False))
+    cols = np.sort(rng.choice(J, 4096, replace=False))
+    x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    t0 = time.time()
+    ref = o.fd_map(o.phat(Y[fr]), x[:, cols], cfg["N"] // 2)
+    log(f"FP64 FD oracle for the sweep in {time.time() - t0:.1f} s")
+    fr_t, cols_t = torch.from_numpy(fr).cuda(), torch.from_numpy(cols).cuda()
+    out = {}
+    for name, variant, values, kw in SWEEPS:
+        if fixed is not None:
+            if name not in fixed:
+                continue
+            values = [fixed[name]]
+        sweep, found = [], None
+        for rq in values:
+            p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, rq, dtype="bf16", c=cfg["c"],
+                            **kw)
+            z = p.compute(Yt)
+            eps = float(np.median(o.eps_z_db(z[fr_t][:, cols_t].cpu().numpy(), ref)))
+            p.close()
+            del z
+            sweep.append((rq, round(eps, 2)))
+            if eps <= EPS_Z_TARGET_DB or fixed is not None:
+                found = {"rank_or_q": rq, "eps_z_db_median": eps}
+                break
+        torch.cuda.empty_cache()
+        out[name] = {"setting": found, "sweep": sweep}
+        log(f"fixed error {name}: {found} after {len(sweep)} settings")
+    return out
+
+
+def kernel_rooflines(prof, calls, J, L, P, K, M, forms):
+    """Achieved rates of the main kernels from live HIP-event spans over the
+    timed steps (each span on the stream the kernel runs on).
+      gemm_fd   FP32 FD GEMM: 4 J P (K-1) L FLOP per launch (eq. (24), two
+                FLOP per MAC), against the FP32 matrix-core peak
+      <form>    every kernel of one reduced-form call together: the call's
+                algorithmic HBM bytes (frames, maps, BF16 plan operand once)
+                against the HBM peak; the SSPI entry also gives its J P Q
+                FMAs against the dot2 vector ceiling
     """
-    J = cfg["grid"].shape[0]
     out = {}
     fd = prof.get("fd", {}).get("gemm_fd")
     if fd:
         t = fd[0] / fd[1] / 1e3
-        flops = 2.0 * 2.0 * J * P * (K - 1) * L
+        flops = 4.0 * J * P * (K - 1) * L
         out["gemm_fd"] = {"bound": "mfma", "avg_ms": t * 1e3, "achieved": flops / t / 1e12,
                           "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
                           "frac": flops / t / 1e12 / PEAK["fp32_mfma_tflops"]}
-    tall = prof.get("slri", {}).get("gemm_tall")
-    if tall:
-        t = tall[0] / tall[1] / 1e3
-        byts = 4.0 * J * L + 2.0 * J * P * 8
-        out["gemm_tall"] = {"bound": "hbm", "avg_ms": t * 1e3, "achieved": byts / t / 1e9,
-                            "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": byts / t / 1e9 / PEAK["hbm_gbs"],
-                            "mfma_tflops": 2.0 * J * P * 8 * L / t / 1e12}
-    sp = prof.get("sspi", {})
-    parts = {k: sp[k] for k in ("xi_to_frames", "sspi_dense", "sspi_gather") if k in sp}
-    if parts:
-        t = sum(v[0] / v[1] for v in parts.values()) / 1e3
-        fl = 2.0 * J * P * 4 * L
-        # the gather runs BF16 weights on v_dot2_f32_f16 (two MACs per lane
-        # and instruction), so the vector ceiling is the dual-issue FP32
-        # rate; the map write is the HBM floor of either path
-        byts = 4.0 * J * L + J * P * (4 + 2 * 4)
-        out["sspi"] = {"bound": "alu", "avg_ms": t * 1e3, "achieved": fl / t / 1e12,
-                       "peak": PEAK["fp32_valu_dot2_tflops"], "unit": "TFLOP/s",
-                       "frac": fl / t / 1e12 / PEAK["fp32_valu_dot2_tflops"],
-                       "frac_of_fma_rate": fl / t / 1e12 / PEAK["fp32_valu_tflops_nonpacked"],
-                       "hbm_gbs": byts / t / 1e9, "hbm_frac": byts / t / 1e9 / PEAK["hbm_gbs"],
-                       "kernels_ms": {k: v[0] / v[1] for k, v in parts.items()}}
+    for name, rq in forms:
+        spans = prof.get(name)
+        if not spans:
+            continue
+        # per call: a kernel may run several launches per call (one per
+        # width class of the dense-window SSPI tiles)
+        t = sum(v[0] for v in spans.values()) / calls / 1e3
+        byts = algorithmic_bytes(name, rq, J, L, M, K, P)
+        rec = {"bound": "hbm", "avg_ms": t * 1e3, "achieved": byts / t / 1e9, "peak": PEAK["hbm_gbs"],
+               "unit": "GB/s", "frac": byts / t / 1e9 / PEAK["hbm_gbs"], "algorithmic_bytes": byts,
+               "kernels_ms": {k: v[0] / calls for k, v in spans.items()},
+               "launches_per_call": {k: v[1] / calls for k, v in spans.items()}}
+        if name == "sspi":
+            fl = 2.0 * J * P * rq * L
+            rec["valu_tflops"] = fl / t / 1e12
+            rec["valu_frac_dot2"] = fl / t / 1e12 / PEAK["fp32_valu_dot2_tflops"]
+        tall = spans.get("gemm_tall")
+        if tall:
+            tt = tall[0] / calls / 1e3
+            rec["stream_kernel_gbs"] = (4.0 * J * L) / tt / 1e9
+        out[name] = rec
     return out
 
 
-def cpu_baseline(cfg, Y, forms):
+def cpu_baseline(cfg, Y, head_name, head_rq):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload:
-    64 frames at 32,768 of the 125,000 candidates per form (plan-time work
-    such as the SVD and window selection excluded); per-map time scaled by
-    J/32,768."""
+    64 frames at 32,768 of the 125,000 candidates for conv. FD-SRP and for the
+    headline form at its fixed-error setting (plan-time work such as the
+    SVD, the global fits and window selection excluded); per-map time
+    scaled by J / 32,768."""
     import oracle as o
     threads = len(os.sched_getaffinity(0))
     J = cfg["grid"].shape[0]
@@ -118,133 +210,102 @@ def cpu_baseline(cfg, Y, forms):
     Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
     K = cfg["N"] // 2
     per_map = {}
-    for form, rq, _ in forms:
-        if form == "slri":
-            fac = o.slri_factors(x, Np, rq)
-            fac = [(U[cols], V, s) for (U, V, s) in fac]
-        elif form == "sspi":
+    for name in ("fd", head_name):
+        if name == "slri":
+            fac = [(U[cols], V, s) for (U, V, s) in o.slri_factors(x, Np, head_rq)]
+        elif name == "slri_global":
+            tall, fat = o.slri_global_factors(x, Np, head_rq)
+            tall = tall[cols]
+        elif name == "sspi":
             xs = x[:, cols]
-            sel = [o.sspi_select(xs[p], Np[p], rq) for p in range(len(Np))]
+            sel = [o.sspi_select(xs[p], Np[p], head_rq) for p in range(len(Np))]
+        elif name == "sspi_global":
+            # the selection is global over the whole grid (plan time); the
+            # map is timed on the sampled rows
+            gsel = o.sspi_global_select(x, Np, head_rq * J * len(Np))[cols]
         t0 = time.perf_counter()
         psi = o.phat(Ys)
-        if form == "fd":
+        if name == "fd":
             o.fd_map(psi, x[:, cols], K)
         else:
             xi = o.gcc_samples_ifft(psi, Np, K)
-            if form == "slri":
+            if name == "slri":
                 o.slri_map(xi, fac)
-            else:
+            elif name == "slri_global":
+                o.slri_global_map(xi, tall, fat)
+            elif name == "sspi":
                 o.sspi_map(xi, sel, Np)
+            else:
+                o.sspi_global_map(xi, gsel)
         dt = time.perf_counter() - t0
-        per_map[form] = dt * (J / len(cols)) / Ls
-    total = sum(per_map.values())
+        per_map[name] = dt * (J / len(cols)) / Ls
     try:
         model = [ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")][0]
     except Exception:
         model = "unknown"
-    return {"value": len(per_map) / total, "unit": "maps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{Ls} frames x {len(cols)} of {J} candidates per form, per-map time scaled by "
-                      f"J/{len(cols)}; one map per form per frame",
+    sample = (f"{Ls} frames x {len(cols)} of {J} candidates for fd and {head_name}, per-map time scaled by "
+              f"J/{len(cols)}")
+    return {"value": 1.0 / per_map[head_name], "unit": "maps/s", "cores": threads, "kind": "oracle",
+            "form": head_name, "rank_or_q": head_rq, "sample": sample,
             "per_form_maps_per_s": {k: 1.0 / v for k, v in per_map.items()},
-            "cpu_model": model,
-            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+            "cpu_model": model, "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
-EPS_Z_TARGET_DB = -20.0
-
-
-def fixed_error_points(cfg, Y, Yt, z_fd, fd_maps_per_s, steps):
-    """The smallest per-pair R (SLRI) and Q (SSPI), BF16 operands, whose
-    median eps_z against the FP64 FD oracle is <= -20 dB on 16 frames x
-    4096 sampled candidates; their maps/s at L = 1000 and speed-up over FP32
-    FD, with argmax and localisation agreement against FP32 FD on every
-    frame and the full grid (localisation: picks within 0.25 m)."""
+def precision_leg(cfg, Y, Yt, fd_maps_per_s, steps):
+    """The configured R = 8 / Q = 4 in FP32 and BF16 and conv. FD-SRP with
+    BF16 and FP8 operands (resident steering): maps/s from HIP events, median
+    eps_z against the FP64 FD oracle on 8 frames x 2000 candidates and
+    against each form's own FP64 oracle is covered by the parity tests."""
     import torch
     import oracle as o
     from paper_2306_08514_amd import native
     L, J = Y.shape[0], cfg["grid"].shape[0]
-    rng = np.random.default_rng(6)
-    fr = np.sort(rng.choice(L, 16, replace=False))
-    cols = np.sort(rng.choice(J, 4096, replace=False))
+    rng = np.random.default_rng(5)
+    fr = np.sort(rng.choice(L, 8, replace=False))
+    cols = np.sort(rng.choice(J, 2000, replace=False))
     x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
     ref = o.fd_map(o.phat(Y[fr]), x[:, cols], cfg["N"] // 2)
     fr_t, cols_t = torch.from_numpy(fr).cuda(), torch.from_numpy(cols).cuda()
-    am_fd, _ = native.argmax(z_fd)
-    grid_t = torch.from_numpy(cfg["grid"]).cuda()
-    out = {"criterion": "median eps_z <= -20 dB vs FP64 FD (16 frames x 4096 candidates)",
-           "sweeps": {}}
-    for form, values in (("slri", range(8, 32)), ("sspi", range(2, 17))):
-        found = None
-        sweep = []
-        for rq in values:
-            p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], form, rq, dtype="bf16", c=cfg["c"])
-            z = p.compute(Yt)
-            zs = z[fr_t][:, cols_t].cpu().numpy()
-            eps = float(np.median(o.eps_z_db(zs, ref)))
-            sweep.append((rq, round(eps, 2)))
-            if eps <= EPS_Z_TARGET_DB:
-                am, _ = native.argmax(z)
-                d = torch.linalg.norm(grid_t[am] - grid_t[am_fd], dim=1)
-                ws = torch.empty(p.workspace_size(L), dtype=torch.uint8, device="cuda")
-                p.compute(Yt, maps=z, workspace=ws)
-                evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                       for _ in range(steps)]
-                for e0, e1 in evs:
-                    e0.record()
-                    p.compute(Yt, maps=z, workspace=ws)
-                    e1.record()
-                torch.cuda.synchronize()
-                ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
-                found = {"rank_or_q": rq, "operands": "bf16", "eps_z_db_median": eps,
-                         "maps_per_s": L / (ms / 1e3), "ms_per_call": ms,
-                         "speedup_vs_fd_f32": L / (ms / 1e3) / fd_maps_per_s,
-                         "argmax_agreement_with_fd_f32": float((am == am_fd).float().mean()),
-                         "localisation_agreement_0p25m": float((d <= 0.25).float().mean())}
-                del ws
-            p.close()
-            del z
-            if found:
-                break
-        out[form] = found
-        out["sweeps"][form] = sweep
-        log(f"fixed error {form}: {found}")
+    out = {}
+    for variant, rq, dt in (("slri", 8, "f32"), ("sspi", 4, "f32"), ("slri", 8, "bf16"), ("sspi", 4, "bf16"),
+                            ("fd", 0, "bf16"), ("fd", 0, "fp8")):
+        p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, rq, dtype=dt, c=cfg["c"])
+        n = steps if variant != "fd" else max(3, steps // 4)
+        z, lat = timed_calls(p, Yt, n)
+        eps = float(np.median(o.eps_z_db(z[fr_t][:, cols_t].cpu().numpy(), ref)))
+        key = f"{variant}_{dt}" + (f"_{'R' if variant == 'slri' else 'Q'}{rq}" if rq else "")
+        out[key] = {"operands": dt, "rank_or_q": rq, "ms_per_call": float(lat.mean()),
+                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                    "maps_per_s": L / (lat.mean() / 1e3), "speedup_vs_fd_f32": L / (lat.mean() / 1e3) / fd_maps_per_s,
+                    "eps_z_db_vs_fp64_fd_median": eps}
+        p.close()
+        del z
+        torch.cuda.empty_cache()
+        log(f"precision {key}: {lat.mean():.3f} ms per {L} maps, eps_z {eps:.1f} dB")
     return out
 
 
 def bench_other_forms(cfg, Yt, steps):
-    """The comparison and global forms on the same room workload (L = 1000,
-    BF16 operands): SI (44), conv. TD-SRP (23), global SLRI (R_Lambda = 224,
-    the per-pair R = 8 budget) and global SSPI (mean 4 taps per location and
-    pair); LR-SRP (R_H = 64) on the paper's near-field geometry (J = 73,084,
-    2K = 512, 128 frames), whose P (K - 1) = 1530 keeps its fit quick, and
-    FD / SLRI / SSPI on far-field directions (2-degree half-sphere, J = 8101)."""
-    import torch
+    """The comparison forms on the same room workload (L = 1000, BF16
+    operands): SI (44) and conv. TD-SRP (23); LR-SRP (R_H = 64) on the
+    paper's near-field geometry (J = 73,084, 2K = 512, 128 frames), whose
+    P (K - 1) = 1530 keeps its fit quick; FD / SLRI / SSPI on far-field
+    directions (2-degree half-sphere, J = 8101)."""
     from paper_2306_08514_amd import native, scenes
 
     def timed(p, Y_dev):
-        L = Y_dev.shape[0]
-        z = p.empty_maps(L)
-        ws = torch.empty(p.workspace_size(L), dtype=torch.uint8, device="cuda")
-        p.compute(Y_dev, maps=z, workspace=ws)
-        torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        for e0, e1 in evs:
-            e0.record()
-            p.compute(Y_dev, maps=z, workspace=ws)
-            e1.record()
-        torch.cuda.synchronize()
-        ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+        _, lat = timed_calls(p, Y_dev, steps)
         info = p.info()
-        return {"ms_per_call": ms, "maps_per_s": L / (ms / 1e3), "frames": L, "J": info["J"],
-                "rank_or_q": info["rank_or_q"], "macs_per_map": info["macs_per_map"]}
+        L = Y_dev.shape[0]
+        return {"ms_per_call": float(lat.mean()), "maps_per_s": L / (lat.mean() / 1e3), "frames": L,
+                "J": info["J"], "rank_or_q": info["rank_or_q"], "macs_per_map": info["macs_per_map"]}
 
+    import torch
     out = {}
     L = Yt.shape[0]
-    for name, variant, rq, kw in (("si", "si", 0, {}), ("td", "td", 0, {}),
-                                  ("slri_global_R224", "slri", 224, {"global_fit": True}),
-                                  ("sspi_global_q4", "sspi", 4, {"global_fit": True})):
+    for name, variant, rq in (("si", "si", 0), ("td", "td", 0)):
         t0 = time.time()
-        p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, rq, dtype="bf16", c=cfg["c"], **kw)
+        p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, rq, dtype="bf16", c=cfg["c"])
         plan_s = time.time() - t0
         out[name] = {"workload": "uca8_room125k", "operands": "bf16", "plan_seconds": plan_s, **timed(p, Yt)}
         p.close()
@@ -270,7 +331,9 @@ def bench_other_forms(cfg, Yt, steps):
 def bench_disc32(steps):
     """Large-aperture leg: disc32_box200k (M = 32, 496 pairs, up to 499 lags,
     J = 200,000, fs 48 kHz, N = 2048, L = 256), SLRI R = 8 and SSPI Q = 4
-    with BF16 operands; maps at the recommended pitch, frames resident."""
+    with BF16 operands, and conv. FD-SRP with generated BF16 steering (a
+    resident operand would take 406 GB); maps at the recommended pitch,
+    frames resident."""
     import torch
     from paper_2306_08514_amd import native, scenes
     t0 = time.time()
@@ -280,17 +343,17 @@ def bench_disc32(steps):
     L, J = Y.shape[0], cfg["grid"].shape[0]
     log(f"disc32 frames in {time.time() - t0:.1f} s")
     out = {"workload": f"disc32_box200k: M=32 disc 2 m aperture, J={J}, fs=48 kHz, N=2048, L={L}", "forms": {}}
-    for form, rq, dt in (("slri", 8, "bf16"), ("sspi", 4, "bf16")):
+    for form, rq, dt in (("slri", 8, "bf16"), ("sspi", 4, "bf16"), ("fd", 0, "bf16")):
         t1 = time.time()
         p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], form, rq, dtype=dt, c=cfg["c"])
         plan_s = time.time() - t1
         z = p.empty_maps(L)
-        ws = torch.empty(p.workspace_size(L), dtype=torch.uint8, device="cuda")
-        for _ in range(2):
-            p.compute(Yt, maps=z, workspace=ws)
+        ws = torch.empty(max(1, p.workspace_size(L)), dtype=torch.uint8, device="cuda")
+        p.compute(Yt, maps=z, workspace=ws)
         torch.cuda.synchronize()
         p.profile(True)
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        n = steps if form != "fd" else 3
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
         for e0, e1 in evs:
             e0.record()
             p.compute(Yt, maps=z, workspace=ws)
@@ -305,7 +368,11 @@ def bench_disc32(steps):
                               "p99_ms": float(np.percentile(lat, 99)), "plan_seconds": plan_s,
                               "resident_gib": info["device_bytes"] / 2 ** 30,
                               "sampling": "ifft" if info["sampling_fft"] else "direct",
-                              "kernels_ms_per_call": {k: v[0] / v[1] for k, v in prof.items()}}
+                              "kernels_ms_per_call": {k: v[0] / n for k, v in prof.items()}}
+        if form == "fd":
+            fl = 4.0 * J * info["P"] * (info["K"] - 1) * L
+            out["forms"][form]["mfma_tflops"] = fl / (lat.mean() / 1e3) / 1e12
+            out["forms"][form]["frac_bf16_peak"] = fl / (lat.mean() / 1e3) / 1e12 / PEAK["bf16_mfma_tflops"]
         log(f"disc32 {form}/{dt}: plan {plan_s:.1f} s, {lat.mean():.3f} ms per {L} maps")
         del p, z, ws
         torch.cuda.empty_cache()
@@ -325,7 +392,6 @@ def main():
     from paper_2306_08514_amd import native, scenes
     native.lib()  # fails loudly when the HIP library is missing
 
-    forms = [f for f in FORMS if f[0] in args.forms.split(",")]
     t0 = time.time()
     cfg = scenes.workload("uca8_room125k", L=args.frames)
     Y = scenes.make_frames(cfg)
@@ -335,38 +401,47 @@ def main():
     dev = torch.device("cuda:0")
     Yt = torch.from_numpy(Y).to(dev)
 
+    fixed = None
+    if args.fixed:
+        fixed = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in args.fixed.split(",")}
+    sweep = fixed_error_sweep(cfg, Y, Yt, fixed)
+    forms = [("fd", "fd", 0, "f32", {})]
+    for name, variant, _, kw in SWEEPS:
+        st = sweep.get(name, {}).get("setting")
+        if st:
+            forms.append((name, variant, st["rank_or_q"], "bf16", kw))
+
     plans, outs, wss, plan_s = {}, {}, {}, {}
-    for form, rq, dt in forms:
+    for name, variant, rq, dt, kw in forms:
         t1 = time.time()
-        plans[form] = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], form, rq, dtype=dt,
-                                  c=cfg["c"], device=0)
-        plan_s[form] = time.time() - t1
+        plans[name] = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, rq, dtype=dt,
+                                  c=cfg["c"], device=0, **kw)
+        plan_s[name] = time.time() - t1
         # maps at the plan's row pitch (J rounded up to 128: rows on 512-byte
         # boundaries); the dense pitch J is timed separately below
-        outs[form] = plans[form].empty_maps(L, dev)
-        wss[form] = torch.empty(plans[form].workspace_size(L), dtype=torch.uint8, device=dev)
-        log(f"plan {form}/{dt} built in {plan_s[form]:.2f} s, resident "
-            f"{plans[form].info()['device_bytes'] / 2**30:.2f} GiB")
-    info = plans[forms[0][0]].info()
-    map_pitch = plans[forms[0][0]].map_pitch
+        outs[name] = plans[name].empty_maps(L, dev)
+        wss[name] = torch.empty(max(1, plans[name].workspace_size(L)), dtype=torch.uint8, device=dev)
+        log(f"plan {name}/{dt} ({rq}) built in {plan_s[name]:.2f} s, resident "
+            f"{plans[name].info()['device_bytes'] / 2**30:.2f} GiB")
+    info = plans["fd"].info()
+    map_pitch = plans["fd"].map_pitch
     P, K = info["P"], info["K"]
-    PN = info["PN"]
 
     def step(ev=None):
-        for form, _, _ in forms:
+        for name in plans:
             if ev is not None:
-                ev[form][0].record()
-            plans[form].compute(Yt, maps=outs[form], workspace=wss[form])
+                ev[name][0].record()
+            plans[name].compute(Yt, maps=outs[name], workspace=wss[name])
             if ev is not None:
-                ev[form][1].record()
+                ev[name][1].record()
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     log("warmup done")
 
-    for form in plans:
-        plans[form].profile(True)
+    for name in plans:
+        plans[name].profile(True)
     events = [{f: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for f in plans} for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -378,90 +453,79 @@ def main():
     log(f"timed {args.steps} steps in {wall:.3f} s")
 
     prof = {}
-    for form in plans:
-        prof[form] = plans[form].profile_collect()
-        plans[form].profile(False)
+    for name in plans:
+        prof[name] = plans[name].profile_collect()
+        plans[name].profile(False)
 
     # the same calls writing dense [L][J] maps (row pitch J), timed the same
-    # way (events around each call)
+    # way; their maps must equal the pitched ones bitwise
     dense_ms = {}
-    for form in plans:
+    for name in plans:
         zd = torch.empty((L, J), dtype=torch.float32, device=dev)
-        n = 2 if form == "fd" else 10
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
-        plans[form].compute(Yt, maps=zd, workspace=wss[form])
-        for e0, e1 in evs:
-            e0.record()
-            plans[form].compute(Yt, maps=zd, workspace=wss[form])
-            e1.record()
-        torch.cuda.synchronize()
-        dense_ms[form] = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
-        if not torch.equal(zd, outs[form]):
-            raise RuntimeError(f"{form}: maps at pitch J differ from maps at the padded pitch")
+        _, lat_d = timed_calls(plans[name], Yt, 2 if name == "fd" else 10, z=zd)
+        dense_ms[name] = float(lat_d.mean())
+        if not torch.equal(zd, outs[name]):
+            raise RuntimeError(f"{name}: maps at pitch J differ from maps at the padded pitch")
         del zd
 
     lat = {f: np.array([events[k][f][0].elapsed_time(events[k][f][1]) for k in range(args.steps)]) for f in plans}
     ms_per_step = wall / args.steps * 1e3
     maps_per_step = L * len(plans)
-    value = maps_per_step / (ms_per_step / 1e3)
     per_form = {}
-    for form, rq, dt in forms:
-        ms = float(np.mean(lat[form]))
-        per_form[form] = {"operands": dt, "rank_or_q": rq, "maps_per_s": L / (ms / 1e3),
-                          "ms_per_call": ms, "p50_ms": float(np.percentile(lat[form], 50)),
-                          "p99_ms": float(np.percentile(lat[form], 99)),
-                          "ms_per_call_dense_pitch": dense_ms[form],
-                          "maps_per_s_dense_pitch": L / (dense_ms[form] / 1e3),
-                          "plan_seconds": plan_s[form],
-                          "resident_gib": plans[form].info()["device_bytes"] / 2 ** 30,
-                          "kernels_ms_per_call": {k: v[0] / v[1] for k, v in prof[form].items()}}
-        if form == "sspi":
-            inf = plans[form].info()
-            per_form[form]["tiles_dense_gather"] = [inf["sspi_dense_tiles"], inf["sspi_gather_tiles"]]
-    if "fd" in per_form:
-        for form in per_form:
-            per_form[form]["speedup_vs_fd_f32"] = per_form[form]["maps_per_s"] / per_form["fd"]["maps_per_s"]
+    for name, variant, rq, dt, kw in forms:
+        ms = float(np.mean(lat[name]))
+        per_form[name] = {"variant": variant, "operands": dt, "rank_or_q": rq, "maps_per_s": L / (ms / 1e3),
+                          "ms_per_call": ms, "p50_ms": float(np.percentile(lat[name], 50)),
+                          "p99_ms": float(np.percentile(lat[name], 99)),
+                          "ms_per_call_dense_pitch": dense_ms[name],
+                          "maps_per_s_dense_pitch": L / (dense_ms[name] / 1e3),
+                          "plan_seconds": plan_s[name],
+                          "resident_gib": plans[name].info()["device_bytes"] / 2 ** 30,
+                          "kernels_ms_per_call": {k: v[0] / args.steps for k, v in prof[name].items()}}
+        if name != "fd":
+            per_form[name]["eps_z_db_vs_fp64_fd_median"] = sweep[name]["setting"]["eps_z_db_median"]
+        if variant == "sspi":
+            inf = plans[name].info()
+            per_form[name]["tiles_dense_gather"] = [inf["sspi_dense_tiles"], inf["sspi_gather_tiles"]]
+    fd_rate = per_form["fd"]["maps_per_s"]
+    for name in per_form:
+        per_form[name]["speedup_vs_fd_f32"] = per_form[name]["maps_per_s"] / fd_rate
+    reduced = [n for n in per_form if n != "fd"]
+    if not reduced:
+        raise RuntimeError("no reduced form reached the fixed error")
+    head = max(reduced, key=lambda n: per_form[n]["maps_per_s"])
 
-    # accuracy at the configured R, Q: epsilon_z against the FP64 FD oracle on
-    # 8 frames x 2000 sampled candidates; argmax agreement with FP32 FD over
-    # every frame and the full grid
-    accuracy = None
-    if not args.no_accuracy and "fd" in plans:
-        import oracle as o
-        rng = np.random.default_rng(5)
-        fr = np.sort(rng.choice(L, 8, replace=False))
-        cols = np.sort(rng.choice(J, 2000, replace=False))
-        x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
-        ref = o.fd_map(o.phat(Y[fr]), x[:, cols], cfg["N"] // 2)
-        am_fd = torch.argmax(outs["fd"], dim=1)
-        accuracy = {}
-        for form in plans:
-            zs = outs[form][torch.from_numpy(fr).to(dev)][:, torch.from_numpy(cols).to(dev)].cpu().numpy()
-            eps = o.eps_z_db(zs, ref)
-            agree = float((torch.argmax(outs[form], dim=1) == am_fd).float().mean())
-            accuracy[form] = {"eps_z_db_vs_fp64_fd_median": float(np.median(eps)),
-                              "argmax_agreement_with_fd_f32": agree}
+    # argmax and localisation agreement with FP32 FD on every frame and the
+    # full grid (localisation: picks within 0.25 m)
+    am_fd, _ = native.argmax(outs["fd"])
+    grid_t = torch.from_numpy(cfg["grid"]).to(dev)
+    for name in reduced:
+        am, _ = native.argmax(outs[name])
+        d = torch.linalg.norm(grid_t[am] - grid_t[am_fd], dim=1)
+        per_form[name]["argmax_agreement_with_fd_f32"] = float((am == am_fd).float().mean())
+        per_form[name]["localisation_agreement_0p25m"] = float((d <= 0.25).float().mean())
 
-    fixed = None
-    if accuracy is not None:
-        fixed = fixed_error_points(cfg, Y, Yt, outs["fd"], per_form["fd"]["maps_per_s"], args.steps)
-
-    rl = kernel_rooflines(cfg, prof, L, P, K, PN)
+    rl = kernel_rooflines(prof, args.steps, J, L, P, K, M, [(n, per_form[n]["rank_or_q"]) for n in reduced])
     # measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-
     # calibrated), valid only while the kernel source is the one profiled
     from paper_2306_08514_amd import rocprof_summary as rs
     rec = rs.read_traffic_record(os.path.join(ROOT, "profiles", "hbm_traffic_uca8_room125k.md"))
     traffic_ok = rec is not None and rec.get("source_sha256") == rs.source_sha256()
     for kname, k in rl.items():
-        t = rec["kernels"].get(kname, {}).get("bytes_per_launch") if traffic_ok else None
-        k["traffic"] = t
-    dom_name = "gemm_fd" if "gemm_fd" in rl else next(iter(rl), None)
-    roofline = None
-    if dom_name:
-        dom = rl[dom_name]
-        roofline = {"bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
-                    "unit": dom["unit"], "frac": dom["frac"], "traffic": dom["traffic"],
-                    "kernel": dom_name, "avg_ms": dom["avg_ms"]}
+        k["traffic"] = rec["kernels"].get(kname, {}).get("bytes_per_launch") if traffic_ok else None
+    dom = rl["gemm_fd"]
+    roofline = {"bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"], "unit": dom["unit"],
+                "frac": dom["frac"], "traffic": dom["traffic"], "kernel": "gemm_fd", "avg_ms": dom["avg_ms"]}
+    hr = rl.get(head)
+    roofline_headline = None
+    if hr:
+        roofline_headline = {"bound": hr["bound"], "achieved": hr["achieved"], "peak": hr["peak"],
+                             "unit": hr["unit"], "frac": hr["frac"], "form": head, "avg_ms": hr["avg_ms"],
+                             "kernels_ms": hr["kernels_ms"]}
+
+    precision = None
+    if not args.no_precision:
+        precision = precision_leg(cfg, Y, Yt, fd_rate, max(5, min(args.steps, 20)))
 
     others = None
     if not args.no_other_forms:
@@ -476,7 +540,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         t2 = time.time()
-        cpu = cpu_baseline(cfg, Y, forms)
+        cpu = cpu_baseline(cfg, Y, head, per_form[head]["rank_or_q"])
         log(f"cpu baseline in {time.time() - t2:.1f} s")
 
     if args.copy_calibration:
@@ -486,22 +550,32 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
+    hf = per_form[head]
     rec = {
-        "metric": METRIC, "value": value, "unit": "maps/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC, "value": hf["maps_per_s"], "unit": "maps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "p50_ms": hf["p50_ms"], "p99_ms": hf["p99_ms"],
+        "fd_f32_maps_per_s": fd_rate, "speedup_vs_fd_f32": hf["speedup_vs_fd_f32"],
+        "step_maps_per_s": maps_per_step / (ms_per_step / 1e3),
         "config": {"workload": f"uca8_room125k: M=8 UCA 0.3 m, J={J} (50x50x50 over 5x5x2.5 m), "
-                               f"fs=16 kHz, N=1024, L={L} frames per step; forms "
-                               + ", ".join(f"{f}({dt}{'' if not rq else ', ' + ('R' if f == 'slri' else 'Q') + '=' + str(rq)})"
-                                           for f, rq, dt in forms),
-                   "maps_per_step": maps_per_step, "accumulate": "f32",
-                   "map_row_pitch": map_pitch},
+                               f"fs=16 kHz, N=1024, L={L} frames per step",
+                   "headline": {"form": head, "variant": hf["variant"], "rank_or_q": hf["rank_or_q"],
+                                "operands": "bf16", "accumulate": "f32",
+                                "eps_z_db_vs_fp64_fd_median": hf["eps_z_db_vs_fp64_fd_median"],
+                                "criterion": f"median eps_z <= {EPS_Z_TARGET_DB:g} dB vs FP64 FD "
+                                             "(16 frames x 4096 candidates)"},
+                   "step_forms": [f"{n}({per_form[n]['operands']}"
+                                  + (f", {per_form[n]['rank_or_q']}" if per_form[n]['rank_or_q'] else "") + ")"
+                                  for n in per_form],
+                   "maps_per_step": maps_per_step, "map_row_pitch": map_pitch},
         "forms": per_form,
+        "fixed_error_sweeps": {k: v["sweep"] for k, v in sweep.items()},
         "kernels": rl,
-        "accuracy": accuracy,
-        "at_fixed_error": fixed,
         "roofline": roofline,
+        "roofline_headline": roofline_headline,
         "cpu_baseline": cpu,
+        "precision": precision,
         "other_forms": others,
         "large_aperture": disc32,
     }

@@ -81,9 +81,16 @@ typedef enum {
 
 /* Operand precision of the dominant contraction (steering matrix for FD, the
  * tall factor U for SLRI, the interpolation weights for SSPI).  Accumulation
- * is FP32 (FP64 for SRP_F64); cross-spectra, GCC samples and the SLRI fat
- * stage are FP32 for every dtype except SRP_F64.  FP8 is OCP E4M3 with
- * per-pair scales folded into the activations (SLRI) or weights (SSPI). */
+ * is FP32 (FP64 for SRP_F64).  Cross-spectra, GCC samples and the SLRI fat
+ * stage are computed in FP32 for every dtype; the SLRI fat stage's output g
+ * is then narrowed to the operand type.  SSPI with 16-bit or FP8 weights
+ * reads the GCC samples narrowed to 16 bits: BF16 (BF16 weights) or FP16
+ * (FP16 weights) frame-major copies where a candidate tile runs on the
+ * matrix cores, FP16 sample pairs in the gather.  FP8 is OCP E4M3: SLRI
+ * scales U per pair by a power of two (undone in the fat stage) and g by
+ * one activation scale; SSPI stores its weights (|w| <= 1, the same bound
+ * for every pair) times 2^8, undone exactly on the sums, so taps down to
+ * 2^-14 stay normal; FD steering (|h| <= 1) is unscaled. */
 typedef enum {
   SRP_F32 = 0,
   SRP_BF16 = 1,
@@ -206,6 +213,7 @@ srp_status srp_workspace_size(srp_plan_t plan, int64_t L, size_t* bytes);
 srp_status srp_compute(srp_plan_t plan, const void* frames, int64_t L,
                        void* maps, int64_t ld_maps, void* workspace,
                        size_t ws_bytes, void* stream);
+
 
 /* Peak picking of (10)-(11) on the device: for each of L maps (row pitch
  * ld_maps >= J elements, float32 or float64 as given by dtype = SRP_F32 or

@@ -3,9 +3,9 @@
 // Hot path per frame tile (one map per STFT frame):
 //   phat_kernel      PHAT-weighted cross-spectra psi_p[l, k] (FD)      eq. (2)
 //   gemm_nt (FD)     z = 2 Re[H psi] as a real MFMA GEMM              eq. (22)
-//   spectral_slices  PHAT + xi_p = 2 Re[S_p psi_p] per spectral slice    eqs. (2), (40)
-//   slice_reduce     sum of the slices' partial GCC samples
-//   slri_fat         g_p = V_p^T xi_p                                   eq. (57)
+//   gcc_direct       PHAT + xi_p = 2 Re[S_p psi_p]                      eqs. (2), (40)
+//   gcc_fft          PHAT + xi_p by the iFFT                            eq. (46)
+//   slri_fat_mfma    g_p = V_p^T xi_p                                   eq. (57)
 //   tall_ws          z = sum_p U_p g_p                                  eq. (57)
 //   sspi_gather      z = sum_p sum_q w[j,p,q] xi_p[s(j,p) + q]          eq. (58)
 #include <hip/hip_runtime.h>
@@ -97,6 +97,15 @@ __device__ inline double cvt64<double>(double v) { return v; }
       throw Error{e_ == hipErrorOutOfMemory ? SRP_E_NOMEM : SRP_E_HIP,                   \
                   std::string(#expr) + ": " + hipGetErrorString(e_)};                    \
   } while (0)
+
+// Power-of-two scale of the stored SSPI weights: 2^8 for FP8 E4M3, whose
+// normal range starts at 2^-6 (|w| <= 1 becomes |w| <= 256 < 448, and taps
+// down to 2^-14 stay normal); 1 for the other types.  The gather multiplies
+// its sums by the inverse, exactly.
+template <typename TW>
+__host__ __device__ constexpr float sspi_wscale() {
+  return std::is_same<TW, fp8>::value ? 256.0f : 1.0f;
+}
 
 static void check_launch(const char* what) {
   hipError_t e = hipGetLastError();
@@ -649,18 +658,9 @@ __global__ __launch_bounds__(256) void gemm_nt_f64(const double* __restrict__ X,
 
 // =============================================== sampling front end ======
 //
-// PHAT cross-spectra (eq. (2)) and GCC sampling xi_p[n] = sum_k S[n][k]
-// psi_p[k] (eq. (40)) for every pair, straight from the frames.
-// spectral_slices: a block owns 32 frames and one 64-bin slice of the
-// single-sided spectrum.  It stages u_m = y_m / |y_m| of every microphone
-// for chunks of CB bins in LDS (normalised once per (frame, mic, bin),
-// loaded coalesced along bins), and each wave accumulates up to 8 tasks
-// (pair, 32-lag tile) on v_mfma_f32_32x32x2_f32: the A-operand is the
-// shared iDFT table S (rows 2 cos / -2 sin (pi k n / K)), the B-operand is
-// psi_p = u_m conj(u_m') formed in registers.  The slice's partial tiles go
-// to part[slice][stacked lag][frame]; slice_reduce sums the slices in a
-// fixed order (deterministic) and writes xi^T (SSPI) or applies the SLRI fat
-// stage g_p = V_p^T xi_p (eq. (57)) and writes g in the tall operand type.
+// PHAT cross-spectra (eq. (2)) and GCC sampling (eq. (40)), straight from
+// the frames: the direct product in gcc_direct (below), the iFFT of (46)
+// in gcc_fft.
 
 // y / |y| (0 for y = 0) with the hardware reciprocal square root; squared
 // magnitudes outside [2^-100, 2^100] are rescaled first so that neither
@@ -680,145 +680,6 @@ __device__ inline float2 unit_phase(float2 y) {
   }
   const float r = __builtin_amdgcn_rsqf(n2);
   return make_float2(a * r, b * r);
-}
-
-constexpr int SLICE_BINS = 64;  // bins per spectral slice
-constexpr int SLICE_TPW = 8;    // tasks per wave per pass
-
-// LDS layout of one chunk buffer: u [M][32 frames][CB complex] rows padded to
-// CB * 8 + 16 bytes, then the S-table columns of the chunk [srows][2 CB]
-// padded to 2 CB + 4 floats.
-template <int CB>
-__device__ __host__ inline int slice_buf_bytes(int M, int srows) {
-  return M * 32 * (CB * 8 + 16) + srows * (2 * CB + 4) * 4;
-}
-
-template <int CB>
-__global__ __launch_bounds__(256) void spectral_slices(
-    const float2* __restrict__ Y, int M, int K, int L, const int32_t* __restrict__ pm,
-    const int32_t* __restrict__ pmp, const int32_t* __restrict__ np,
-    const int32_t* __restrict__ off, int max_np, const float* __restrict__ S, int Kp, int srows,
-    const int2* __restrict__ tasks, int ntasks, float* __restrict__ part, int64_t ldp, int PN) {
-  constexpr int RB = CB * 8 + 16;  // bytes per (mic, frame) row of u
-  constexpr int SR = 2 * CB + 4;   // floats per S row in LDS
-  // CB is chosen so that M * 32 * CB <= 4096 (CB = 16, 8, 4 for M <= 8, 16, 32)
-  constexpr int UPER = 4096 / 256;  // u items per thread
-  extern __shared__ __attribute__((aligned(16))) unsigned char slds[];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r32 = lane & 31, gq = lane >> 5;
-  const int64_t fbase = static_cast<int64_t>(blockIdx.x) * 32;
-  const int ks = blockIdx.y;
-  const int kb0 = ks * SLICE_BINS + 1;                           // first bin of the slice
-  const int nb = std::min(SLICE_BINS, K - 1 - ks * SLICE_BINS);  // bins in the slice
-  const int nch = (nb + CB - 1) / CB;
-  const int bufb = slice_buf_bytes<CB>(M, srows);
-  const int uitems = M * 32 * CB;          // complex values of u per chunk
-  const int sitems = srows * (CB / 2);     // 16-byte pieces of S per chunk
-
-  float2 pu[UPER];
-  f32x4 psv[4];  // S pieces per thread (the host checks srows * CB / 2 <= 1024)
-  auto gload = [&](int c) {
-#pragma unroll
-    for (int i = 0; i < UPER; ++i) {
-      const int e = tid + 256 * i;
-      pu[i] = make_float2(0.f, 0.f);
-      if (e < uitems) {
-        const int b = e % CB, row = e / CB;
-        const int mic = row / 32, fl = row % 32;
-        const int k = kb0 + c * CB + b;
-        const int64_t f = std::min<int64_t>(fbase + fl, L - 1);
-        if (k <= K - 1) pu[i] = Y[(f * M + mic) * (K + 1) + k];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = tid + 256 * i;
-      if (e < sitems) {
-        const int row = e / (CB / 2), q = e % (CB / 2);
-        psv[i] = *reinterpret_cast<const f32x4*>(S + static_cast<int64_t>(row) * Kp + 2 * (kb0 - 1 + c * CB) + 4 * q);
-      }
-    }
-  };
-  auto lstore = [&](unsigned char* buf) {
-#pragma unroll
-    for (int i = 0; i < UPER; ++i) {
-      const int e = tid + 256 * i;
-      if (e < uitems) {
-        const int b = e % CB, row = e / CB;
-        *reinterpret_cast<float2*>(buf + row * RB + 8 * b) = unit_phase(pu[i]);
-      }
-    }
-    float* sb = reinterpret_cast<float*>(buf + M * 32 * RB);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = tid + 256 * i;
-      if (e < sitems) {
-        const int row = e / (CB / 2), q = e % (CB / 2);
-        *reinterpret_cast<f32x4*>(sb + row * SR + 4 * q) = psv[i];
-      }
-    }
-  };
-
-  for (int pass = 0; pass * 4 * SLICE_TPW < ntasks; ++pass) {
-    f32x16 acc[SLICE_TPW];
-    int tp[SLICE_TPW], tt[SLICE_TPW];
-#pragma unroll
-    for (int i = 0; i < SLICE_TPW; ++i) {
-      const int id = pass * 4 * SLICE_TPW + wave + 4 * i;
-      tp[i] = id < ntasks ? tasks[id].x : -1;
-      tt[i] = id < ntasks ? tasks[id].y : 0;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[i][v] = 0.0f;
-    }
-    __syncthreads();
-    gload(0);
-    lstore(slds);
-    __syncthreads();
-    for (int c = 0; c < nch; ++c) {
-      const unsigned char* cur = slds + (c & 1) * bufb;
-      const float* sb = reinterpret_cast<const float*>(cur + M * 32 * RB);
-      if (c + 1 < nch) gload(c + 1);
-#pragma unroll
-      for (int i = 0; i < SLICE_TPW; ++i) {
-        if (tp[i] < 0) continue;  // wave-uniform
-        const int p = tp[i];
-        const unsigned char* um = cur + (pm[p] * 32 + r32) * RB + 16 * gq;
-        const unsigned char* uq = cur + (pmp[p] * 32 + r32) * RB + 16 * gq;
-        const float* srow = sb + (max_np - np[p] + 32 * tt[i] + r32) * SR + 4 * gq;
-#pragma unroll
-        for (int st = 0; st < CB / 4; ++st) {
-          const f32x4 a = *reinterpret_cast<const f32x4*>(srow + 8 * st);
-          const f32x4 x = *reinterpret_cast<const f32x4*>(um + 32 * st);  // u_m bins 2gq, 2gq+1
-          const f32x4 y = *reinterpret_cast<const f32x4*>(uq + 32 * st);  // u_m'
-          // psi = u_m conj(u_m')
-          const float b0 = __builtin_fmaf(x.x, y.x, x.y * y.y), b1 = __builtin_fmaf(x.y, y.x, -(x.x * y.y));
-          const float b2 = __builtin_fmaf(x.z, y.z, x.w * y.w), b3 = __builtin_fmaf(x.w, y.z, -(x.z * y.w));
-          acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b0, acc[i], 0, 0, 0);
-          acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b1, acc[i], 0, 0, 0);
-          acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b2, acc[i], 0, 0, 0);
-          acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b3, acc[i], 0, 0, 0);
-        }
-      }
-      if (c + 1 < nch) lstore(slds + ((c + 1) & 1) * bufb);
-      __syncthreads();
-    }
-    // accumulator layout: register v of lane i holds lag row
-    // 32 t + 8 (v / 4) + 4 (i / 32) + v % 4 of frame column i % 32
-    const int64_t frame = fbase + r32;
-    if (frame < L) {
-#pragma unroll
-      for (int i = 0; i < SLICE_TPW; ++i) {
-        if (tp[i] < 0) continue;
-        const int nrows = 2 * np[tp[i]] + 1;
-        float* dst = part + (static_cast<int64_t>(ks) * PN + off[tp[i]]) * ldp + frame;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int lag = 32 * tt[i] + 8 * (v / 4) + 4 * gq + (v % 4);
-          if (lag < nrows) dst[static_cast<int64_t>(lag) * ldp] = acc[i][v];
-        }
-      }
-    }
-  }
 }
 
 // iFFT sampling (46): xi_p[n] for n = -N_p..N_p as samples of the unscaled
@@ -907,16 +768,224 @@ __global__ __launch_bounds__(256) void transpose_lp(const float* __restrict__ xi
   }
 }
 
-// xi^T[n][l] = sum of the slices' partial samples, in slice order.
-__global__ __launch_bounds__(256) void slice_reduce(const float* __restrict__ part, int nslices,
-                                                    int64_t ldp, int PN, int L,
-                                                    float* __restrict__ xiT) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  const int64_t n = i / L, l = i % L;
-  if (n >= PN) return;
-  float s = 0.0f;
-  for (int k = 0; k < nslices; ++k) s += part[(static_cast<int64_t>(k) * PN + n) * ldp + l];
-  xiT[n * ldp + l] = s;
+// ========================================================= direct sampling ===
+//
+// xi_p[l][n] = sum_{k=1}^{K-1} S[n][k] . psi_p[l, k] (eq. (40)) with the
+// real pairing S . psi = S_re Re psi + S_im Im psi, S[n][k] = (2 cos,
+// -2 sin)(pi k n / K), as one product whose rows are the (frame, pair)
+// combinations and whose columns are the lags -max_np..max_np of the table
+// S that every pair shares (each pair keeps its own 2 N_p + 1 lags).
+// A block owns `ft` frames (ft P rows, in tiles of 32) and up to GD_TILES
+// (row tile, 32-lag column tile) products.  Per chunk of GD_CB bins it
+// stages u = y / |y| of its frames' microphones (each (frame, mic, bin)
+// normalised once) and the chunk's table columns in LDS; wave w multiplies
+// tiles w and w + 4 on v_mfma_f32_32x32x2_f32, whose k slots 0 and 1 of
+// step b are Re and Im of bin b, each lane forming psi_p = u_m conj(u_m')
+// of its row.  The frames and the table are read once per block (the
+// table is shared by every pair), and the next chunk is loaded into
+// registers while the current one is multiplied.  Every frame runs the same
+// instruction sequence, so its samples do not depend on the batch.
+constexpr int GD_CB = 64;                 // bins per chunk
+constexpr int GD_ROWB = GD_CB * 8 + 16;   // bytes per LDS row (a (frame, mic) or a table row)
+constexpr int GD_FM = 64;                 // max frames x microphones per block
+constexpr int GD_TILES = 4;               // products per block (each split over two waves)
+constexpr int GD_NCT = 4;                 // max 32-lag column tiles (2 max_np + 1 <= 128)
+
+template <int NCT>
+__global__ __launch_bounds__(512) void gcc_direct(const float2* __restrict__ Y, int M, int K, int L, int P,
+                                                  const int32_t* __restrict__ pm, const int32_t* __restrict__ pmp,
+                                                  const int32_t* __restrict__ np, const int32_t* __restrict__ off,
+                                                  int max_np, const float* __restrict__ S, int Kb, int ft, int nrt,
+                                                  int nct, float* __restrict__ xiT, int64_t ldxi) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char gd_lds[];
+  unsigned char* u_lds = gd_lds;                                 // [ft M + 1 zero row][GD_ROWB]
+  unsigned char* s_lds = gd_lds + (GD_FM + 1) * GD_ROWB;        // [NCT 32][GD_ROWB]
+  constexpr int NT = 512;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r32 = lane & 31, kq = lane >> 5;
+  const int64_t fbase = static_cast<int64_t>(blockIdx.x) * ft;
+  const int fm_rows = ft * M;
+  const int ntiles = nrt * nct;
+  // wave w: product (tile) w % 4 of the block's group, bins of half w / 4 of
+  // every chunk; the two halves' partial tiles are added in LDS at the end
+  const int t = blockIdx.y * GD_TILES + (wave & 3);
+  const int half = wave >> 2;
+  const bool tlive = t < ntiles;  // uniform over the wave
+  int ta, tb, tcol;
+  {
+    const int rt = tlive ? t / nct : 0, ct = tlive ? t % nct : 0;
+    const int rho = rt * 32 + r32;
+    const int fl = rho / P, p = rho % P;
+    const bool ok = tlive && rho < ft * P && fbase + fl < L;
+    // this lane's row: LDS offsets of u_m and u_m' (the zero row for padding
+    // rows and frames past L) and of its lag's table row
+    ta = (ok ? fl * M + pm[p] : fm_rows) * GD_ROWB + half * (GD_CB / 2) * 8;
+    tb = (ok ? fl * M + pmp[p] : fm_rows) * GD_ROWB + half * (GD_CB / 2) * 8;
+    tcol = (ct * 32 + r32) * GD_ROWB + half * (GD_CB / 2) * 8;
+  }
+  for (int e = tid; e < GD_ROWB / 16; e += NT)
+    *reinterpret_cast<f32x4*>(u_lds + fm_rows * GD_ROWB + 16 * e) = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  constexpr int UPT = GD_FM * (GD_CB / 2) / NT;     // bin pairs of u per thread
+  constexpr int SPT = NCT * 32 * (GD_CB / 2) / NT;  // 16-byte table pieces per thread
+  f32x4 uy[UPT], sv[SPT];
+  const int uitems = fm_rows * (GD_CB / 2);
+  constexpr int sitems = NCT * 32 * (GD_CB / 2);  // rows past nct 32 are zero in the table
+  const int nchunks = Kb / GD_CB;
+
+  auto gload = [&](int c) {
+#pragma unroll
+    for (int i = 0; i < UPT; ++i) {
+      const int e = tid + NT * i;
+      uy[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (e < uitems) {
+        const int row = e / (GD_CB / 2), b2 = e % (GD_CB / 2);
+        const int fl = row / M, m = row % M;
+        const int k = c * GD_CB + 2 * b2 + 1;  // bins k, k + 1
+        const int64_t f = fbase + fl;
+        if (f < L) {
+          const float2* yr = Y + (f * M + m) * (K + 1);
+          if (k + 1 <= K - 1) {
+            const float2 a0 = yr[k], a1 = yr[k + 1];
+            uy[i] = f32x4{a0.x, a0.y, a1.x, a1.y};
+          } else if (k <= K - 1) {
+            const float2 a0 = yr[k];
+            uy[i] = f32x4{a0.x, a0.y, 0.f, 0.f};
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) {
+      const int e = tid + NT * i;
+      const int row = e / (GD_CB / 2), q = e % (GD_CB / 2);
+      sv[i] = *reinterpret_cast<const f32x4*>(S + static_cast<int64_t>(row) * (2 * Kb) + 2 * c * GD_CB + 4 * q);
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int i = 0; i < UPT; ++i) {
+      const int e = tid + NT * i;
+      if (e < uitems) {
+        const int row = e / (GD_CB / 2), b2 = e % (GD_CB / 2);
+        const float2 u0 = unit_phase(make_float2(uy[i].x, uy[i].y)), u1 = unit_phase(make_float2(uy[i].z, uy[i].w));
+        *reinterpret_cast<f32x4*>(u_lds + row * GD_ROWB + 16 * b2) = f32x4{u0.x, u0.y, u1.x, u1.y};
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) {
+      const int e = tid + NT * i;
+      const int row = e / (GD_CB / 2), q = e % (GD_CB / 2);
+      *reinterpret_cast<f32x4*>(s_lds + row * GD_ROWB + 16 * q) = sv[i];
+    }
+  };
+  static_assert(sitems % NT == 0, "table pieces must tile the threads");
+
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  gload(0);
+  for (int c = 0; c < nchunks; ++c) {
+    __syncthreads();  // the previous chunk's reads are done
+    lstore();
+    __syncthreads();
+    if (c + 1 < nchunks) gload(c + 1);
+    if (tlive) {
+#pragma unroll 8
+      for (int b = 0; b < GD_CB / 2; b += 2) {
+        // bins b, b + 1 of this wave's half: u_m, u_m' and the lag's table
+        const f32x4 x = *reinterpret_cast<const f32x4*>(u_lds + ta + 8 * b);
+        const f32x4 y = *reinterpret_cast<const f32x4*>(u_lds + tb + 8 * b);
+        const f32x4 sc = *reinterpret_cast<const f32x4*>(s_lds + tcol + 8 * b);
+        // psi = u_m conj(u_m'): Re for k slot 0, Im for slot 1
+        const float re0 = __builtin_fmaf(x.x, y.x, x.y * y.y), im0 = __builtin_fmaf(x.y, y.x, -(x.x * y.y));
+        const float re1 = __builtin_fmaf(x.z, y.z, x.w * y.w), im1 = __builtin_fmaf(x.w, y.z, -(x.z * y.w));
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(kq ? im0 : re0, kq ? sc.y : sc.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(kq ? im1 : re1, kq ? sc.w : sc.z, acc, 0, 0, 0);
+      }
+    }
+  }
+  // second-half partial tiles through LDS (the u buffer is free now)
+  __syncthreads();
+  f32x16* red = reinterpret_cast<f32x16*>(gd_lds);
+  if (half == 1 && tlive) red[(wave & 3) * 64 + lane] = acc;
+  __syncthreads();
+  if (half == 1 || !tlive) return;
+  {
+    const f32x16 o = red[wave * 64 + lane];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] += o[v];
+  }
+  // 32 x 32 accumulator layout: register v of lane i holds row
+  // 8 (v / 4) + 4 (i / 32) + v % 4 and column i % 32
+  const int rt = t / nct, ct = t % nct;
+  const int n = ct * 32 + r32 - max_np;  // lag of this lane's column
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int rho = rt * 32 + 8 * (v / 4) + 4 * kq + (v % 4);
+    if (rho >= ft * P) continue;
+    const int fl = rho / P, p = rho % P;
+    const int64_t f = fbase + fl;
+    const int npp = np[p];
+    if (f < L && n >= -npp && n <= npp) xiT[static_cast<int64_t>(off[p] + n + npp) * ldxi + f] = acc[v];
+  }
+}
+
+// Per-pair SLRI fat stage on the matrix cores, g[l][p R + r] = gscale_p
+// sum_n V_p[n][r] xi_p[l][n] (eq. (57)): one wave per (pair, 16 frames, 16
+// columns of R) on v_mfma_f32_16x16x4_f32, A = xi^T rows of the pair's lags
+// (frames contiguous), B = V_p; eight steps of loads are issued ahead of
+// their products.  Block = four waves, the pair's next four frame tiles;
+// pair index P zero-fills g's padding columns.
+template <typename TG>
+__global__ __launch_bounds__(256) void slri_fat_mfma(const float* __restrict__ xiT, int64_t ldxi, int L,
+                                                     const int32_t* __restrict__ np, const int32_t* __restrict__ off,
+                                                     const float* __restrict__ V, int vrows, int R,
+                                                     const float* __restrict__ gscale, int P, TG* __restrict__ g,
+                                                     int Kc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = blockIdx.y;
+  const int64_t l0 = static_cast<int64_t>(blockIdx.x) * 64 + wave * 16;
+  if (p == P) {  // uniform over the block
+    const int pad = Kc - P * R;
+    for (int e = lane; e < 16 * pad; e += 64) {
+      const int64_t l = l0 + e / pad;
+      if (l < L) g[l * Kc + P * R + e % pad] = cvt<TG>(0.0f);
+    }
+    return;
+  }
+  const int r16 = lane & 15, kk = lane >> 4;
+  const int nrows = 2 * np[p] + 1;
+  const float* xs = xiT + static_cast<int64_t>(off[p]) * ldxi + l0 + r16;
+  const float* Vp = V + static_cast<int64_t>(p) * vrows * R;
+  const float sc = gscale[p];
+  const int nsteps = (nrows + 3) / 4;
+  for (int c0 = 0; c0 < R; c0 += 16) {
+    const int col = c0 + r16;
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    constexpr int U = 8;
+    for (int s0 = 0; s0 < nsteps; s0 += U) {
+      float a[U], b[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int n = 4 * (s0 + u) + kk;
+        const bool ok = n < nrows;
+        a[u] = ok ? xs[static_cast<int64_t>(n) * ldxi] : 0.0f;
+        b[u] = ok && col < R ? Vp[n * R + col] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc, 0, 0, 0);
+    }
+    // 16 x 16 accumulator layout: register v of lane i holds row (frame)
+    // 4 (i / 16) + v and column i % 16
+    if (col < R) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t l = l0 + 4 * kk + v;
+        if (l < L) g[l * Kc + p * R + col] = cvt<TG>(acc[v] * sc);
+      }
+    }
+  }
 }
 
 // SLRI fat stage g[l][p R + r] = gscale_p sum_n V_p[n][r] xi_p[l][n]
@@ -1007,6 +1076,58 @@ __global__ __launch_bounds__(256) void slri_fat_global(const float* __restrict__
   gl[1] = cvt<TG>(a1 * sc);
   gl[2] = cvt<TG>(a2 * sc);
   gl[3] = cvt<TG>(a3 * sc);
+}
+
+// The same product on the matrix cores: a block owns 32 frames x 32
+// columns of g; its four waves take the lag pairs (a, a + 1) of every
+// fourth v_mfma_f32_32x32x2_f32 step (a = 8 t + 2 w), reading xi^T rows
+// (frames contiguous) and V rows (columns contiguous) straight from memory
+// eight steps ahead, and the four partial tiles are added in LDS in wave
+// order (deterministic).  Lags past PN read as zero.
+template <typename TG>
+__global__ __launch_bounds__(256) void slri_fat_global_mfma(const float* __restrict__ xiT, int64_t ldxi, int L,
+                                                            int PN, const float* __restrict__ V, int Kc,
+                                                            const float* __restrict__ gscale, TG* __restrict__ g) {
+  __shared__ f32x16 red[3][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r32 = lane & 31, kq = lane >> 5;
+  const int64_t l0 = static_cast<int64_t>(blockIdx.x) * 32;
+  const int c0 = blockIdx.y * 32;
+  const float* xs = xiT + l0 + r32;
+  const float* vs = V + c0 + r32;
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  constexpr int U = 8;
+  const int nsteps = (PN + 1) / 2;
+  for (int s0 = wave; s0 < nsteps; s0 += 4 * U) {
+    float a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int a_ = 2 * (s0 + 4 * u) + kq;
+      const bool ok = s0 + 4 * u < nsteps && a_ < PN;
+      a[u] = ok ? xs[static_cast<int64_t>(a_) * ldxi] : 0.0f;
+      b[u] = ok ? vs[static_cast<int64_t>(a_) * Kc] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u], b[u], acc, 0, 0, 0);
+  }
+  if (wave > 0) red[wave - 1][lane] = acc;
+  __syncthreads();
+  if (wave != 0) return;
+  for (int q = 0; q < 3; ++q) {
+    const f32x16 o = red[q][lane];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] += o[v];
+  }
+  // accumulator layout: register v of lane i holds row (frame)
+  // 8 (v / 4) + 4 (i / 32) + v % 4 and column i % 32
+  const float sc = gscale[0];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int64_t l = l0 + 8 * (v / 4) + 4 * kq + (v % 4);
+    if (l < L) g[l * Kc + c0 + r32] = cvt<TG>(acc[v] * sc);
+  }
 }
 
 // ====================================================== SLRI tall stream ===
@@ -1496,10 +1617,11 @@ __global__ __launch_bounds__(256) void sspi_gather(const float* __restrict__ xiT
     p0 = p1;
   }
   if (!live) return;
+  constexpr float zs = 1.0f / sspi_wscale<TW>();
 #pragma unroll
   for (int f = 0; f < FT; ++f) {
     const int64_t l = l0 + f;
-    if (l < L) z[l * ldz + j] = acc[f];
+    if (l < L) z[l * ldz + j] = acc[f] * zs;
   }
 }
 
@@ -1792,7 +1914,7 @@ __global__ __launch_bounds__(256) void sspi_windows(const double* __restrict__ x
     for (int t2 = 0; t2 < Qs; ++t2) {
       float v = t2 < q ? static_cast<float>(sinc_red(xv, k0, sr, si + t2)) : 0.0f;
       if (td) v = t2 == 0 ? 1.0f : 0.0f;
-      w[rec * Qs + t2] = cvt<TW>(v);
+      w[rec * Qs + t2] = cvt<TW>(v * sspi_wscale<TW>());
     }
   }
   rlo[threadIdx.x] = sabs_lo;
@@ -2373,6 +2495,10 @@ static void build_sspi_dense(HostPlan& hp, DevicePlan& dp, Alloc& A, const std::
                        static_cast<const _Float16*>(dp.d_w), Qs, dp.sspi_q, hp.J, dp.d_off, da0.as<int32_t>(),
                        dkpos.as<int32_t>(), P, dp.d_dtiles, static_cast<_Float16*>(dp.d_B), kmax);
   check_launch("sspi_dense_weights");
+  // one launch over every dense tile at the widest contraction (tiles in
+  // width classes of 64 columns, one launch each, measured slower: 0.253
+  // against 0.215 ms per 1000 maps at Q = 3, the launches' tails cost more
+  // than the narrower classes save)
   dp.d_ctab = static_cast<int32_t*>(A.get(ctab.size() * 4));
   upload(dp.d_ctab, ctab);
   dp.d_colmap = static_cast<int32_t*>(A.get(colmap.size() * 4));
@@ -2460,10 +2586,6 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     return;
   }
 
-  // sampling table: row n + max_np holds 2 cos(pi k n / K), -2 sin(pi k n / K)
-  // in slots 2 (k - 1), 2 (k - 1) + 1; the angle pi (k n mod 2K) / K is
-  // reduced exactly in integers, then evaluated in FP64
-  dp.samp_rows = 2 * hp.max_np + 1;
   if (hp.fft) {
     // iFFT sampling (46): twiddles of the length-K complex inverse FFT and
     // the factors exp(i pi k / K) that fold the length-2K real transform
@@ -2482,30 +2604,30 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     dp.d_w2 = static_cast<float2*>(A.get(w2.size() * sizeof(float2)));
     upload(dp.d_w2, w2);
   } else {
-    const int rows = dp.samp_rows + 32;  // zero rows past the last lag tile
-    std::vector<float> S(static_cast<size_t>(rows) * dp.Kp, 0.0f);
-    for (int i = 0; i < dp.samp_rows; ++i) {
+    // the iDFT table shared by every pair: row j holds lag n = j - max_np,
+    // (2 cos, -2 sin)(pi k n / K) in slots 2 (k - 1), 2 (k - 1) + 1, the
+    // angle pi (k n mod 2K) / K reduced exactly in integers, then evaluated
+    // in FP64; rows past 2 max_np + 1 and bins past K - 1 are zero
+    dp.gd_kb = static_cast<int>(round_up(hp.K - 1, GD_CB));
+    dp.gd_nct = (2 * hp.max_np + 1 + 31) / 32;
+    if (dp.gd_nct > GD_NCT) throw Error{SRP_E_UNSUPPORTED, "too many lags for the direct sampling kernel"};
+    if (dp.gd_nct == 3) dp.gd_nct = 4;  // the kernel stages 32, 64 or 128 table rows
+    std::vector<float> S(static_cast<size_t>(dp.gd_nct) * 32 * 2 * dp.gd_kb, 0.0f);
+    for (int i = 0; i < 2 * hp.max_np + 1; ++i) {
       const int64_t n = i - hp.max_np;
       for (int k = 1; k < hp.K; ++k) {
         int64_t m = (static_cast<int64_t>(k) * n) % (2 * hp.K);
         if (m < 0) m += 2 * hp.K;
         const double ang = M_PI * static_cast<double>(m) / hp.K;
-        S[static_cast<size_t>(i) * dp.Kp + 2 * (k - 1)] = static_cast<float>(2.0 * std::cos(ang));
-        S[static_cast<size_t>(i) * dp.Kp + 2 * (k - 1) + 1] = static_cast<float>(-2.0 * std::sin(ang));
+        S[static_cast<size_t>(i) * 2 * dp.gd_kb + 2 * (k - 1)] = static_cast<float>(2.0 * std::cos(ang));
+        S[static_cast<size_t>(i) * 2 * dp.gd_kb + 2 * (k - 1) + 1] = static_cast<float>(-2.0 * std::sin(ang));
       }
     }
     dp.d_S = static_cast<float*>(A.get(S.size() * 4));
     upload(dp.d_S, S);
-    // sampling tasks: (pair, 32-lag tile)
-    std::vector<int32_t> tk;
-    for (int p = 0; p < P; ++p)
-      for (int t = 0; 32 * t < 2 * hp.np[p] + 1; ++t) {
-        tk.push_back(p);
-        tk.push_back(t);
-      }
-    dp.ntasks = static_cast<int>(tk.size() / 2);
-    dp.d_tasks = static_cast<int32_t*>(A.get(tk.size() * 4));
-    upload(dp.d_tasks, tk);
+    // frames per block: about four 32-row tiles of (frame, pair) rows, at
+    // most GD_FM (frame, microphone) rows of u in LDS
+    dp.gd_ft = std::max(1, std::min(128 / P, GD_FM / hp.M));
   }
 
   if (hp.variant == SRP_SLRI) {
@@ -2724,7 +2846,7 @@ void device_free(DevicePlan& dp) {
     (void)hipEventDestroy(sp.stop);
   }
   for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
-  void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_tasks, dp.d_tw, dp.d_w2,
+  void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_tw, dp.d_w2,
                   dp.d_U, dp.d_V, dp.d_gscale, dp.d_F, dp.d_start, dp.d_w, dp.d_win, dp.d_xg, dp.d_B,
                   dp.d_ctab, dp.d_colmap, dp.d_dtiles, dp.d_gtiles, dp.ws};
   for (void* p : ptrs)
@@ -2763,13 +2885,8 @@ WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t 
     w.xi = off;
     off = align256(off + static_cast<size_t>(hp.PN) * w.Lpad * 4);
     w.part = off;
-    if (hp.fft) {
-      // frame-major samples of the iFFT kernel, [Lc][PN]
-      off = align256(off + static_cast<size_t>(w.Lc) * hp.PN * 4);
-    } else {
-      const size_t nsl = static_cast<size_t>((hp.K - 1 + SLICE_BINS - 1) / SLICE_BINS);
-      off = align256(off + nsl * static_cast<size_t>(hp.PN) * w.Lpad * 4);
-    }
+    // frame-major samples of the iFFT kernel, [Lc][PN]
+    if (hp.fft) off = align256(off + static_cast<size_t>(w.Lc) * hp.PN * 4);
   }
   if (hp.variant == SRP_SLRI) {
     w.g = off;
@@ -2857,13 +2974,16 @@ __global__ __launch_bounds__(256) void split_reduce(const float* __restrict__ pa
 // last, partial round leaves slots idle) and the 2 stands for a block's
 // fixed cost (its U rows and the first staged groups).
 void tall_split(DevicePlan& dp, const void* kern, int threads, int njt, int ngroups, int& nsplit, int& gps) {
-  if (dp.tall_slots == 0) {
+  int slots = 0;
+  for (const auto& ks : dp.tall_slots)
+    if (ks.first == kern) slots = ks.second;
+  if (slots == 0) {
     int per_cu = 0, cus = 0;
     HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0));
     HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dp.device));
-    dp.tall_slots = std::max(1, per_cu) * std::max(1, cus);
+    slots = std::max(1, per_cu) * std::max(1, cus);
+    dp.tall_slots.emplace_back(kern, slots);
   }
-  const int slots = dp.tall_slots;
   nsplit = 1;
   int64_t best = -1;
   for (int s = 1; s <= 8 && (s == 1 || ngroups / s >= 4); ++s) {
@@ -2953,51 +3073,59 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
                                                                 alpha, Lpad, st);
 }
 
-// Sampling front end straight from the frames: spectral slices, the slice
-// reduction into xi^T, and for SLRI (MODE 1) the fat stage into g.
+// Direct GCC sampling (40) straight from the frames into xi^T [PN][ldxi].
 void launch_slices(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t Lc, float* xiT, int64_t ldxi,
-                   float* part, hipStream_t st) {
-  const int nslices = (hp.K - 1 + SLICE_BINS - 1) / SLICE_BINS;
-  dim3 grid(static_cast<unsigned>((Lc + 31) / 32), static_cast<unsigned>(nslices));
-  const int CB = hp.M <= 8 ? 16 : (hp.M <= 16 ? 8 : 4);
-  const int srows = dp.samp_rows + 32;  // every S row a task can touch
-  if (srows * (CB / 2) > 1024) throw Error{SRP_E_UNSUPPORTED, "too many lags for the sampling tile"};
-#define SRP_SLICES(CBV)                                                                                       \
+                   hipStream_t st) {
+  const int ft = dp.gd_ft;
+  const int nrt = (ft * hp.P + 31) / 32;
+  const int ntiles = nrt * dp.gd_nct;
+  const dim3 grid(static_cast<unsigned>((Lc + ft - 1) / ft), static_cast<unsigned>((ntiles + GD_TILES - 1) / GD_TILES));
+  const int NCT = dp.gd_nct <= 1 ? 1 : (dp.gd_nct <= 2 ? 2 : 4);
+  const size_t lds = static_cast<size_t>(GD_FM + 1 + 32 * NCT) * GD_ROWB;
+#define SRP_GD(NC)                                                                                            \
   do {                                                                                                        \
-    auto kern = &spectral_slices<CBV>;                                                                        \
-    const size_t lds = 2 * static_cast<size_t>(slice_buf_bytes<CBV>(hp.M, srows));                            \
-    if (lds > 160 * 1024) throw Error{SRP_E_UNSUPPORTED, "sampling tile exceeds the LDS"};                    \
+    auto kern = &gcc_direct<NC>;                                                                              \
     if (lds > 65536)                                                                                          \
       HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),                                         \
                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));         \
-    TRACED(dp, "spectral_slices", st,                                                                         \
-           hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, static_cast<const float2*>(frames), hp.M, hp.K,  \
-                              static_cast<int>(Lc), dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, hp.max_np, dp.d_S,  \
-                              dp.Kp, srows, reinterpret_cast<const int2*>(dp.d_tasks), dp.ntasks, part, ldxi, \
-                              hp.PN));                                                                        \
+    TRACED(dp, "gcc_direct", st,                                                                              \
+           hipLaunchKernelGGL(kern, grid, dim3(512), lds, st, static_cast<const float2*>(frames), hp.M, hp.K,  \
+                              static_cast<int>(Lc), hp.P, dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, hp.max_np,    \
+                              dp.d_S, dp.gd_kb, ft, nrt, dp.gd_nct, xiT, ldxi));                              \
   } while (0)
-  if (CB == 16)
-    SRP_SLICES(16);
-  else if (CB == 8)
-    SRP_SLICES(8);
+  if (NCT == 1)
+    SRP_GD(1);
+  else if (NCT == 2)
+    SRP_GD(2);
   else
-    SRP_SLICES(4);
-#undef SRP_SLICES
-  const int64_t n = static_cast<int64_t>(hp.PN) * Lc;
-  TRACED(dp, "slice_reduce", st,
-         hipLaunchKernelGGL(slice_reduce, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, part,
-                            nslices, ldxi, hp.PN, static_cast<int>(Lc), xiT));
+    SRP_GD(4);
+#undef SRP_GD
 }
 
 // SLRI fat stage g_p = V_p^T xi_p (eq. (57)) for every frame of the tile.
 template <typename TG>
 void launch_fat(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t ldxi, int64_t Lc, void* g,
                 hipStream_t st) {
+  if (hp.global_fit && dp.Kc % 32 == 0) {
+    const dim3 g2(static_cast<unsigned>((Lc + 31) / 32), static_cast<unsigned>(dp.Kc / 32));
+    TRACED(dp, "slri_fat", st,
+           hipLaunchKernelGGL(slri_fat_global_mfma<TG>, g2, dim3(256), 0, st, xiT, ldxi, static_cast<int>(Lc),
+                              hp.PN, dp.d_V, dp.Kc, dp.d_gscale, static_cast<TG*>(g)));
+    return;
+  }
   if (hp.global_fit) {
     dim3 g2(static_cast<unsigned>((Lc + 63) / 64), static_cast<unsigned>(dp.Kc / 16));
     TRACED(dp, "slri_fat", st,
            hipLaunchKernelGGL(slri_fat_global<TG>, g2, dim3(256), 0, st, xiT, ldxi, static_cast<int>(Lc), hp.PN,
                               dp.d_V, dp.Kc, dp.d_gscale, static_cast<TG*>(g)));
+    return;
+  }
+  if (hp.R <= 32) {
+    const int vrows = 2 * hp.max_np + 1;
+    const dim3 g2(static_cast<unsigned>((Lc + 63) / 64), static_cast<unsigned>(hp.P + 1));
+    TRACED(dp, "slri_fat", st,
+           hipLaunchKernelGGL(slri_fat_mfma<TG>, g2, dim3(256), 0, st, xiT, ldxi, static_cast<int>(Lc), dp.d_np,
+                              dp.d_off, dp.d_V, vrows, hp.R, dp.d_gscale, hp.P, static_cast<TG*>(g), dp.Kc));
     return;
   }
   {
@@ -3042,9 +3170,11 @@ void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_
            hipLaunchKernelGGL(transpose_lp, tgrid, dim3(256), 0, st, part, static_cast<int64_t>(hp.PN),
                               static_cast<int>(Lc), hp.PN, xiT, ldxi));
   } else {
-    launch_slices(hp, dp, frames, Lc, xiT, ldxi, part, st);
+    launch_slices(hp, dp, frames, Lc, xiT, ldxi, st);
   }
-  if constexpr (MODE == 1) launch_fat<TG>(hp, dp, xiT, ldxi, Lc, g, st);
+  if constexpr (MODE == 1) {
+    launch_fat<TG>(hp, dp, xiT, ldxi, Lc, g, st);
+  }
 }
 
 
@@ -3238,14 +3368,14 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
                  hipLaunchKernelGGL(xi_to_frames<__bf16>, gt, dim3(256), 0, st, xiT, lay.Lpad, static_cast<int>(Lc),
                                     dp.sspi_pna, dp.sspi_xw, dp.d_colmap, static_cast<__bf16*>(xf), ldf));
           launch_tall_gemm<__bf16>(dp, xf, ldf, dp.d_B, dp.sspi_kmax, z, ldm, (int)Lc, (int)hp.J,
-                                   dp.sspi_kmax, 1.0f, lay.Lpad, st, dp.d_ctab, dp.d_dtiles, dp.n_dtiles);
+                                 dp.sspi_kmax, 1.0f, lay.Lpad, st, dp.d_ctab, dp.d_dtiles, dp.n_dtiles);
           if (dp.n_gtiles) launch_sspi<__bf16>(hp, dp, xiT, lay.Lpad, Lc, z, ldm, st);
         } else {
           TRACED(dp, "xi_to_frames", st,
                  hipLaunchKernelGGL(xi_to_frames<_Float16>, gt, dim3(256), 0, st, xiT, lay.Lpad, static_cast<int>(Lc),
                                     dp.sspi_pna, dp.sspi_xw, dp.d_colmap, static_cast<_Float16*>(xf), ldf));
           launch_tall_gemm<_Float16>(dp, xf, ldf, dp.d_B, dp.sspi_kmax, z, ldm, (int)Lc, (int)hp.J,
-                                     dp.sspi_kmax, 1.0f, lay.Lpad, st, dp.d_ctab, dp.d_dtiles, dp.n_dtiles);
+                                 dp.sspi_kmax, 1.0f, lay.Lpad, st, dp.d_ctab, dp.d_dtiles, dp.n_dtiles);
           if (dp.n_gtiles) launch_sspi<_Float16>(hp, dp, xiT, lay.Lpad, Lc, z, ldm, st);
         }
         continue;

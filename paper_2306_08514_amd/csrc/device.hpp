@@ -35,10 +35,10 @@ struct DevicePlan {
   int fd_ksplit = 1;         // contraction splits of the resident FD GEMM (few candidate tiles)
   double* d_xg = nullptr;    // [P][J] TDOAs in samples (generated steering)
   // sampling (SLRI, SSPI)
-  float* d_S = nullptr;      // [2 max_np + 1 + 32][Kp] rows 2cos / -2sin
-  int samp_rows = 0;         // 2 max_np + 1
-  int32_t* d_tasks = nullptr;  // sampling tasks (pair, 32-lag tile)
-  int ntasks = 0;
+  float* d_S = nullptr;       // direct sampling: iDFT table [gd_nct 32][2 gd_kb], rows 2 cos / -2 sin
+  int gd_kb = 0;              // bins per table row: K - 1 rounded up to the kernel's chunk
+  int gd_nct = 0;             // 32-lag column tiles of the table
+  int gd_ft = 0;              // frames per block of the direct sampling kernel
   float2* d_tw = nullptr;      // iFFT sampling: exp(+2 pi i t / K), t < K/2
   float2* d_w2 = nullptr;      // iFFT sampling: exp(+i pi k / K), k < K
   int logk = 0;                // log2 K
@@ -48,7 +48,7 @@ struct DevicePlan {
   float* d_V = nullptr;      // [P][2 max_np + 1][R]
   float* d_gscale = nullptr; // [P] activation scale of pair p in the fat stage
   float tall_alpha = 1.0f;   // undoes the activation scale in the tall GEMM
-  int tall_slots = 0;        // resident blocks of the tall kernel on the device (0 = not yet queried)
+  std::vector<std::pair<const void*, int>> tall_slots;  // resident blocks of each streaming-kernel variant
   // LR-SRP: fat operand F [Fpad][P*Kp] FP32 (rows 2r, 2r+1 give Re, Im of
   // (H_fat psi)_r), tall operand in d_U (columns 2 Re T, -2 Im T)
   float* d_F = nullptr;

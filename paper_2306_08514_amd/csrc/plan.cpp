@@ -654,10 +654,9 @@ void choose_sampling(HostPlan& hp, int mode) {
   const double ifft = 8.0 * hp.P * hp.K * std::log2(2.0 * hp.K);
   if (mode == 2 && !pow2)
     throw Error{SRP_E_UNSUPPORTED, "iFFT sampling needs N a power of two, at most 4096"};
-  // the direct kernel stages the table rows of every lag a 32-lag tile can
-  // touch in LDS; past its capacity only the iFFT form runs
-  const int cb = hp.M <= 8 ? 16 : (hp.M <= 16 ? 8 : 4);
-  const bool direct_fits = (2 * hp.max_np + 1 + 32) * (cb / 2) <= 1024;
+  // the direct kernel holds the table rows of every lag in LDS: at most
+  // 128 lags per pair; past that only the iFFT form runs
+  const bool direct_fits = 2 * hp.max_np + 1 <= 128;
   if (mode == 1 && !direct_fits)
     throw Error{SRP_E_UNSUPPORTED, "too many lags for the direct sampling kernel; use the iFFT form"};
   hp.fft = mode == 2 || (mode == 0 && pow2 && (ifft < direct || !direct_fits));

@@ -10,10 +10,15 @@ R_H of LR-SRP) a plan is built on the device and every frame mapped once.
 Reported per setting:
   C_rel   the plan's run-time MAC count over conv. FD-SRP's 2 J P (K - 1);
   eps_z   10 log10 ||z_type - z||^2 / ||z||^2 per frame against conv. FD-SRP
-          in FP32 (median and 10th / 90th percentiles);
-  eps_H   for LR-SRP, 10 log10 of the discarded energy of H: since every
-          entry of H has unit modulus, ||H||_F^2 = J P (K - 1) and
-          ||H - H_lr||_F^2 = ||H||_F^2 - sum_{r <= R_H} sigma_r^2;
+          computed by the library in FP64 (median and 10th / 90th
+          percentiles);
+  eps_H   10 log10 ||H_type - H||_F^2 / ||H||_F^2 of (64), H the single-sided
+          steering matrix (19).  For SI, TD, SLRI and SSPI, H_type = Lambda_type
+          S with the sampling rows S_n[k] = exp(j pi k n / K), evaluated per
+          (location, pair) from the plan's FP64 fit without forming H (see
+          eps_h_db); for LR-SRP from the singular values: every entry of H
+          has unit modulus, so ||H||_F^2 = J P (K - 1) and ||H - H_lr||_F^2 =
+          ||H||_F^2 - sum_{r <= R_H} sigma_r^2;
   rho_s   the fraction of frames whose peak lies within eps_th of the true
           source (distance, near field) or direction (angle, far field),
           at 4, 8 and 16 cm or 3 degrees.
@@ -57,6 +62,75 @@ def accuracy(eps_s, thresholds):
     return {f"{t:g}": float(np.mean(eps_s <= t)) for t in thresholds}
 
 
+def dirichlet_sum(t, K):
+    """sum_{k=1}^{K-1} cos(pi k t / K) = sin((K - 1/2) pi t / K) /
+    (2 sin(pi t / (2K))) - 1/2, and K - 1 at t = 0 (mod 2K)."""
+    t = np.asarray(t, dtype=np.float64)
+    th = np.pi * t / K
+    sh = np.sin(th / 2.0)
+    small = np.abs(sh) < 1e-12
+    out = np.empty_like(t)
+    out[~small] = np.sin((K - 0.5) * th[~small]) / (2.0 * sh[~small]) - 0.5
+    out[small] = K - 1.0
+    return out
+
+
+def row_errors(lags, lam, x, K):
+    """sum_{k=1}^{K-1} |sum_n lam_n exp(j pi k n / K) - exp(j pi k x / K)|^2 for
+    rows of interpolation weights lam at integer lags (arrays [..., n], x
+    [...]), in closed form: with G(d) = sum_k cos(pi k d / K) = K - 1 (d = 0),
+    -1 (d even), 0 (d odd) for |d| < 2K, the weights' own energy is
+    K sum lam^2 - (sum over even lags)^2 - (sum over odd lags)^2; the steering
+    row has energy K - 1; the cross term is sum_n lam_n D(n - x)."""
+    lags = np.asarray(lags)
+    lam = np.asarray(lam, dtype=np.float64)
+    even = (lags % 2) == 0
+    e_sum = np.sum(np.where(even, lam, 0.0), axis=-1)
+    o_sum = np.sum(np.where(even, 0.0, lam), axis=-1)
+    own = K * np.sum(lam * lam, axis=-1) - e_sum ** 2 - o_sum ** 2
+    cross = np.sum(lam * dirichlet_sum(lags - np.asarray(x)[..., None], K), axis=-1)
+    return (K - 1.0) + own - 2.0 * cross
+
+
+def eps_h_db(native, cfg, variant, rq, far_field=False, global_fit=False, chunk=8192):
+    """eps_H of (64) for SI, TD, SLRI or SSPI from a host-only plan's FP64
+    fit (the same fit the device plan uses), summed over (location, pair)
+    blocks by row_errors."""
+    p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, rq, device=-1, c=cfg["c"],
+                    far_field=far_field, global_fit=global_fit)
+    info = p.info()
+    P, K, J = info["P"], info["K"], info["J"]
+    x = p.export("tdoa").reshape(P, J)
+    Np = p.export("np").astype(np.int64)
+    off = np.concatenate([[0], np.cumsum(2 * Np + 1)])
+    num = 0.0
+    if variant in ("slri", "si") and global_fit:
+        U = p.export("slri_u").reshape(J, -1)
+        V = p.export("slri_v").reshape(int(off[-1]), -1)
+        for j0 in range(0, J, chunk):
+            lam = U[j0:j0 + chunk] @ V.T                     # rows of the stacked fit
+            for q in range(P):
+                lags = np.arange(-Np[q], Np[q] + 1)
+                num += np.sum(row_errors(lags, lam[:, off[q]:off[q + 1]], x[q, j0:j0 + chunk], K))
+    elif variant in ("slri", "si"):
+        U = p.export("slri_u").reshape(P, J, -1)
+        R = U.shape[2]
+        V = p.export("slri_v").reshape(P, -1, R)
+        for q in range(P):
+            lags = np.arange(-Np[q], Np[q] + 1)
+            Vq = V[q, :2 * Np[q] + 1]
+            for j0 in range(0, J, chunk):
+                lam = U[q, j0:j0 + chunk] @ Vq.T
+                num += np.sum(row_errors(lags, lam, x[q, j0:j0 + chunk], K))
+    else:
+        start = p.export("sspi_start").reshape(J, P)
+        w = p.export("sspi_w").reshape(J, P, -1)
+        lags = start[:, :, None] + np.arange(w.shape[2])[None, None, :]
+        num = float(np.sum(row_errors(lags, w, x.T, K)))
+    p.close()
+    return 10.0 * np.log10(max(num, 1e-300) / (J * P * (K - 1.0)))
+
+
 def map_error_db(z, z_ref):
     """eps_z of Sec. V-A per frame (rows), in dB; -inf where the maps agree."""
     num = np.sum((z - z_ref) ** 2, axis=1)
@@ -82,7 +156,7 @@ def run(scene="nf4", n_sources=16, frames=8, dtype="f32", forms=None, seed=0, lo
         return native.Plan(cfg["mics"], grid, cfg["fs"], cfg["N"], variant, rq, dtype=dt, c=cfg["c"],
                            far_field=far, **kw)
 
-    ref_plan = plan("fd")
+    ref_plan = plan("fd", dt="f64")
     z_ref = ref_plan.compute(Yt)
     info = ref_plan.info()
     C = 2.0 * J * info["P"] * (info["K"] - 1)
@@ -109,6 +183,7 @@ def run(scene="nf4", n_sources=16, frames=8, dtype="f32", forms=None, seed=0, lo
                 # SI (44) is global SLRI at full rank R_Lambda = PN, which
                 # has no per-pair lag limit
                 p = plan("slri", info["PN"], dtype, global_fit=True)
+                variant, rq, kw = "slri", info["PN"], {"global_fit": True}
             plan_s = time.time() - t1
             z = p.compute(Yt)
             idx, _ = native.argmax(z)
@@ -127,6 +202,8 @@ def run(scene="nf4", n_sources=16, frames=8, dtype="f32", forms=None, seed=0, lo
                 sv = p.export("lr_s")
                 frac = max(1.0 - float(np.sum(sv ** 2)) / C * 2.0, 1e-16)  # C / 2 = J P (K - 1) = ||H||_F^2
                 row["eps_H_db"] = 10.0 * np.log10(frac)
+            elif variant != "fd":
+                row["eps_H_db"] = eps_h_db(native, cfg, variant, rq, far, kw.get("global_fit", False))
             rows.append(row)
             p.close()
             del z
@@ -141,16 +218,17 @@ def markdown(res):
     unit = "deg" if res["far_field"] else "m"
     lines = [f"scene {res['scene']}: J = {res['J']}, {res['frames']} frames from {res['sources']} sources, "
              f"{res['dtype']} operands", "",
-             "| form | setting | C_rel | median eps_z dB (p10, p90) | " +
+             "| form | setting | C_rel | eps_H dB | median eps_z dB (p10, p90) | " +
              " | ".join(f"rho_s @ {t:g} {unit}" for t in th) + " |",
-             "|---|---:|---:|---|" + "---:|" * len(th)]
+             "|---|---:|---:|---:|---|" + "---:|" * len(th)]
     for r in res["rows"]:
         if "skipped" in r:
-            lines.append(f"| {r['form']} | {r['setting']} | — | skipped: {r['skipped'][:60]} |" + " |" * len(th))
+            lines.append(f"| {r['form']} | {r['setting']} | — | — | skipped: {r['skipped'][:60]} |" + " |" * len(th))
             continue
         e = r["eps_z_db"]
         es = "reference" if e is None else f"{e['median']:.1f} ({e['p10']:.1f}, {e['p90']:.1f})"
-        lines.append(f"| {r['form']} | {r['setting']} | {r['C_rel']:.2e} | {es} | " +
+        eh = f"{r['eps_H_db']:.1f}" if "eps_H_db" in r else "—"
+        lines.append(f"| {r['form']} | {r['setting']} | {r['C_rel']:.2e} | {eh} | {es} | " +
                      " | ".join(f"{r['rho_s'][f'{t:g}']:.2f}" for t in th) + " |")
     return "\n".join(lines) + "\n"
 

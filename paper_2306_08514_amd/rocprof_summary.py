@@ -4,8 +4,13 @@ the SRP hot path, and the HBM-traffic record the benchmark reads back.
     python -m paper_2306_08514_amd.rocprof_summary trace DIR TITLE CMD... > out.md
     python -m paper_2306_08514_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR TITLE CMD... > out.md
 
+    python -m paper_2306_08514_amd.rocprof_summary counters TITLE DIR... -- CMD... > out.md
+
 `trace` turns a `--kernel-trace --stats` run into a table of per-kernel
-calls and durations.  `traffic` reads two `--pmc FETCH_SIZE` /
+calls and durations.  `counters` tabulates the per-dispatch medians of
+every counter found in one or more `--pmc` runs, per kernel, with the
+ratios derived from them (matrix-core and LDS busy fractions, L2 hit
+rate).  `traffic` reads two `--pmc FETCH_SIZE` /
 `--pmc WRITE_SIZE` runs of the same program, calibrates both counters with
 the 1 GiB device-to-device copies that `bench.py --copy-calibration` issues
 (the factor that maps the counter of a copy of known size onto its bytes),
@@ -40,8 +45,7 @@ _TAGS = [
     (r"sspi_gather", "sspi_gather"),
     (r"xi_to_frames", "xi_to_frames"),
     (r"sspi_dense_weights", "sspi_dense_weights (plan)"),
-    (r"spectral_slices", "spectral_slices"),
-    (r"slice_reduce", "slice_reduce"),
+    (r"gcc_direct", "gcc_direct"),
     (r"slri_fat", "slri_fat"),
     (r"phat_kernel", "phat"),
     (r"build_steering", "build_steering (plan)"),
@@ -175,6 +179,74 @@ def _md_traffic(fd, wd, title, cmd):
     return "\n".join(lines) + "\n"
 
 
+# derived ratios of the counters summary; the cycle counters are summed by
+# rocprofv3 over their instances: SQ_VALU_MFMA_BUSY_CYCLES over the SIMDs,
+# SQ_LDS_IDX_ACTIVE and SQ_BUSY_CU_CYCLES over the CUs, GRBM_GUI_ACTIVE over
+# the XCDs (so GRBM_GUI_ACTIVE / XCDS is the kernel's length in cycles)
+XCDS, CUS, SIMDS = 8, 256, 1024
+DERIVED = [
+    ("mfma busy", ("SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE"), lambda m, g: m / (SIMDS * g / XCDS)),
+    ("lds active", ("SQ_LDS_IDX_ACTIVE", "GRBM_GUI_ACTIVE"), lambda a, g: a / (CUS * g / XCDS)),
+    ("cu busy", ("SQ_BUSY_CU_CYCLES", "GRBM_GUI_ACTIVE"), lambda b, g: b / (CUS * g / XCDS)),
+    ("lds bank conflict / active", ("SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE"), lambda c, a: c / a if a else 0.0),
+    ("L2 hit", ("TCC_HIT_sum", "TCC_MISS_sum"), lambda h, m: h / (h + m) if h + m else 0.0),
+]
+
+
+def counters(dirs):
+    """{tag: {"name", "dispatches", counter: median per dispatch}} over every
+    counter of the *_counter_collection.csv files under dirs."""
+    names = set()
+    for d in dirs:
+        for path in _find(d, "counter_collection.csv"):
+            with open(path, newline="") as f:
+                for r in csv.DictReader(f):
+                    names.add(r["Counter_Name"])
+    out = {}
+    for d in dirs:
+        for cname in sorted(names):
+            try:
+                vals = counter_values(d, cname)
+            except FileNotFoundError:
+                continue
+            for kname, vs in vals.items():
+                t = tag(kname)
+                rec = out.setdefault(t, {"name": kname, "dispatches": len(vs)})
+                rec[cname] = statistics.median(vs)
+    for rec in out.values():
+        for label, (a, b), fn in DERIVED:
+            if a in rec and b in rec and rec[b]:
+                rec[label] = fn(rec[a], rec[b])
+    return out
+
+
+def _md_counters(title, dirs, cmd):
+    rec = counters(dirs)
+    cnames = sorted({k for r in rec.values() for k in r if k.isupper() or k.startswith(("SQ_", "TCC_", "GRBM_",
+                                                                                           "TCP_", "TA_", "TD_"))})
+    labels = [lab for lab, _, _ in DERIVED if any(lab in r for r in rec.values())]
+    lines = [f"# {title}", "", "Commands (repository root; rocprofv3 from /tmp with TMPDIR=/tmp; one run per",
+             "counter group):", "", "```", cmd,
+             "python -m paper_2306_08514_amd.rocprof_summary counters <title> <dirs> -- <command>", "```", "",
+             f"Kernel source SHA-256: `{source_sha256()}`", "",
+             "Derived ratios: matrix-core busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 "
+             "XCDs); LDS active and CU busy = SQ_LDS_IDX_ACTIVE or SQ_BUSY_CU_CYCLES / (256 CUs x "
+             "GRBM_GUI_ACTIVE / 8); L2 hit = TCC_HIT / (TCC_HIT + TCC_MISS).  Medians per dispatch.", "",
+             "| kernel | dispatches | " + " | ".join(labels) + " |", "|---|---:|" + "---:|" * len(labels)]
+    for t, r in sorted(rec.items()):
+        if t in ("copy", "torch (bench checks)") or t.endswith("(plan)"):
+            continue
+        lines.append(f"| {t} | {r['dispatches']} | " +
+                     " | ".join(f"{100 * r[lab]:.1f} %" if lab in r else "—" for lab in labels) + " |")
+    lines += ["", "Raw medians per dispatch:", "", "| kernel | " + " | ".join(cnames) + " |",
+              "|---|" + "---:|" * len(cnames)]
+    for t, r in sorted(rec.items()):
+        if t in ("copy", "torch (bench checks)") or t.endswith("(plan)"):
+            continue
+        lines.append(f"| {t} | " + " | ".join(f"{r[c]:.4g}" if c in r else "—" for c in cnames) + " |")
+    return "\n".join(lines) + "\n"
+
+
 def read_traffic_record(md_path):
     """The JSON record embedded in a traffic summary, or None."""
     try:
@@ -190,6 +262,9 @@ def main(argv):
         sys.stdout.write(_md_trace(argv[1], argv[2], " ".join(argv[3:])))
     elif len(argv) >= 4 and argv[0] == "traffic":
         sys.stdout.write(_md_traffic(argv[1], argv[2], argv[3], " ".join(argv[4:])))
+    elif len(argv) >= 4 and argv[0] == "counters" and "--" in argv:
+        i = argv.index("--")
+        sys.stdout.write(_md_counters(argv[1], argv[2:i], " ".join(argv[i + 1:])))
     else:
         sys.stderr.write(__doc__)
         return 2

@@ -64,6 +64,9 @@ def test_kernel_tags():
     assert rs.tag("void srp::tall_ws<__bf16, 32, 8, true>(__bf16 const*, long)") == "sspi_dense"
     assert rs.tag("void srp::xi_to_frames<__bf16>(float const*, long)") == "xi_to_frames"
     assert rs.tag("void srp::sspi_gather<__bf16, 4, 32, true>(x)") == "sspi_gather"
+    assert rs.tag("void srp::gcc_direct<1>(HIP_vector_type<float, 2u> const*, int)") == "gcc_direct"
+    assert rs.tag("_ZN3srp13slri_fat_mfmaIDF16bEEvPKfliPKiS4_S2_iiS2_iPT_i") == "slri_fat"
+    assert rs.tag("_ZN3srp20slri_fat_global_mfmaIDF16bEEvPKfliiS2_iS2_PT_") == "slri_fat"
 
 
 def test_traffic_record_round_trips_through_the_summary(tmp_path):

@@ -35,3 +35,58 @@ def test_harness_on_paper_near_field_scene():
         rho = [r["rho_s"][k] for k in ("0.04", "0.08", "0.16")] if "rho_s" in r else []
         assert rho == sorted(rho) and all(0.0 <= v <= 1.0 for v in rho)
     print(ev.markdown(res))
+
+
+def test_harness_measures_match_the_oracle():
+    """eps_z (against the library's FP64 FD) and eps_H of the harness on the
+    square-array scene, against the oracle's own maps and dense matrices:
+    eps_z from the FP64 oracle forms vs the FP64 oracle FD, eps_H from
+    Lambda_type S vs H."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle as o
+    from paper_2306_08514_amd import evaluate as ev
+    from paper_2306_08514_amd import scenes
+    print("[gpu-case] evaluate square scene vs oracle", flush=True)
+    res = ev.run("square", n_sources=2, frames=3, dtype="f32", forms=["fd", "si", "td", "slri", "sspi"])
+    cfg, Y, _ = scenes.evaluation_scene("square", 2, 3)
+    x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    Np = o.max_lags(cfg["mics"], cfg["fs"], cfg["c"], 2)
+    K = cfg["N"] // 2
+    psi = o.phat(Y)
+    xi = o.gcc_samples_ifft(psi, Np, K)
+    z_fd = o.fd_map(psi, x, K)
+    for r in res["rows"]:
+        if r["form"] == "fd" or "skipped" in r:
+            continue
+        rq = r["setting"]
+        if r["form"] == "si":
+            z = o.si_map(xi, x, Np)
+            lam = [o.interp_matrix(x[p], Np[p]) for p in range(len(Np))]
+        elif r["form"] == "td":
+            z = o.td_map(xi, x, Np)
+            lam = []
+            for p in range(len(Np)):
+                n_p = int(Np[p])
+                m = np.zeros((x.shape[1], 2 * n_p + 1))
+                n = np.clip(np.sign(x[p]) * np.floor(np.abs(x[p]) + 0.5), -n_p, n_p).astype(int)
+                m[np.arange(x.shape[1]), n + n_p] = 1.0
+                lam.append(m)
+        elif r["form"] == "slri":
+            fac = o.slri_factors(x, Np, rq)
+            z = o.slri_map(xi, fac)
+            lam = [U @ V.T for (U, V, _) in fac]
+        else:
+            sel = [o.sspi_select(x[p], Np[p], rq) for p in range(len(Np))]
+            z = o.sspi_map(xi, sel, Np)
+            lam = []
+            for p, (lags, wts) in enumerate(sel):
+                m = np.zeros((x.shape[1], 2 * int(Np[p]) + 1))
+                np.add.at(m, (np.repeat(np.arange(x.shape[1]), lags.shape[1]), (lags + Np[p]).ravel()), wts.ravel())
+                lam.append(m)
+        eps_z = o.eps_z_db(z, z_fd)
+        assert abs(np.median(eps_z) - r["eps_z_db"]["median"]) <= 0.05, (r["form"], rq)
+        H = o.steering_matrix(x, K)
+        Ht = np.concatenate([lam[p] @ np.exp(1j * np.pi * np.outer(np.arange(-Np[p], Np[p] + 1), np.arange(1, K)) / K)
+                             for p in range(len(Np))], axis=1)
+        assert abs(o.eps_h_db(Ht, H) - r["eps_H_db"]) <= 1e-6 * max(1.0, abs(r["eps_H_db"])), (r["form"], rq)
