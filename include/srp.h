@@ -214,6 +214,26 @@ srp_status srp_compute(srp_plan_t plan, const void* frames, int64_t L,
                        void* maps, int64_t ld_maps, void* workspace,
                        size_t ws_bytes, void* stream);
 
+/* srp_compute for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same maps, bit for bit, with no workspace argument and no allocation.
+ * The workspace is a static scratch array of SRP_STATIC_SCRATCH_BYTES in
+ * device memory, one per GPU, held until the process ends; the frames are
+ * processed in the largest frame tile (at most the plan's frame_tile)
+ * whose workspace fits it.
+ *   frames, L, maps, ld_maps, stream  as for srp_compute
+ * SRP_STATIC_SCRATCH_BYTES is 128 MiB.  Returns SRP_E_UNSUPPORTED when
+ * even the smallest frame tile (256 frames of workspace rows) needs more
+ * than the scratch (e.g. FD on 496 pairs with 2048-point frames: 520 MB of
+ * BF16 cross-spectra), SRP_E_INVALID as srp_compute does.  Every call on one GPU shares
+ * that GPU's scratch: calls that overlap in time on one GPU (other streams,
+ * other threads, other plans) race and must be serialised by the caller.
+ * The scratch keeps the last call's contents; nothing read from it needs
+ * to start at zero.  With profiling on (srp_profile_enable) the spans
+ * create HIP events. */
+#define SRP_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+srp_status srp_compute_static(srp_plan_t plan, const void* frames, int64_t L,
+                              void* maps, int64_t ld_maps, void* stream);
 
 /* Peak picking of (10)-(11) on the device: for each of L maps (row pitch
  * ld_maps >= J elements, float32 or float64 as given by dtype = SRP_F32 or

@@ -199,6 +199,23 @@ srp_status srp_compute(srp_plan_t plan, const void* frames, int64_t L, void* map
   })
 }
 
+srp_status srp_compute_static(srp_plan_t plan, const void* frames, int64_t L, void* maps, int64_t ld_maps,
+                              void* stream) {
+  if (!plan) return fail(SRP_E_INVALID, "NULL plan");
+  if (L < 0) return fail(SRP_E_INVALID, "L must be >= 0");
+  if (ld_maps == 0) ld_maps = plan->hp.J;
+  if (ld_maps < plan->hp.J) return fail(SRP_E_INVALID, "ld_maps must be 0 or >= J");
+  if (L == 0) return SRP_OK;
+  if (!frames || !maps) return fail(SRP_E_INVALID, "frames and maps must be device pointers");
+  if (!plan->has_device) return fail(SRP_E_INVALID, "host-only plan cannot compute");
+  SRP_GUARD({
+    DeviceGuard g(plan->dp.device);
+    srp::device_compute_static(plan->hp, plan->dp, frames, L, maps, ld_maps, plan->opts.frame_tile,
+                               static_cast<hipStream_t>(stream));
+    return SRP_OK;
+  })
+}
+
 srp_status srp_argmax(const void* maps, srp_dtype dtype, int64_t L, int64_t J, int64_t ld_maps,
                       int64_t* idx, double* val, void* stream) {
   if (L < 0 || J < 1) return fail(SRP_E_INVALID, "need L >= 0 and J >= 1");

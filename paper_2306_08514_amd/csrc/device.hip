@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -3394,6 +3395,50 @@ void device_crossspec(const HostPlan& hp, DevicePlan& dp, const void* frames, in
                       hipStream_t st) {
   const int64_t ld_p = 2 * (hp.K - 1);
   launch_phat<float, float>(hp, dp, frames, L, static_cast<float*>(psi), hp.P * ld_p, ld_p, hp.K - 1, st);
+}
+
+// ------------------------------------------------ static scratch workspace --
+//
+// The workspace of srp_compute_static: a fixed array in device memory, one
+// copy per GPU (held until the process ends).  Host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device
+// address): its device address comes from hipGetSymbolAddress, taken once
+// per device with that device current, and is kept per device.
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+static void* scratch_address(int device) {
+  static std::mutex mu;
+  static std::vector<void*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0) throw Error{SRP_E_INVALID, "static scratch needs a device plan"};
+  if (static_cast<size_t>(device) >= addr.size()) addr.resize(device + 1, nullptr);
+  if (!addr[device]) {
+    int cur = -1;
+    HIP_OK(hipGetDevice(&cur));
+    if (cur != device) HIP_OK(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      throw Error{SRP_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+    addr[device] = p;
+  }
+  return addr[device];
+}
+
+void device_compute_static(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L, void* maps,
+                           int64_t ldm, int64_t frame_tile, hipStream_t st) {
+  if (L <= 0) return;
+  // the largest frame tile (at most the plan's) whose workspace fits; below
+  // the row padding of the workspace a smaller tile saves nothing
+  int64_t tile = std::min(L, frame_tile);
+  while (tile > LPAD_ROWS && workspace_bytes(hp, dp, tile, tile) > STATIC_SCRATCH_BYTES) tile = (tile + 1) / 2;
+  const size_t need = workspace_bytes(hp, dp, tile, tile);
+  if (need > STATIC_SCRATCH_BYTES)
+    throw Error{SRP_E_UNSUPPORTED, "workspace of " + std::to_string(need) + " bytes for a " + std::to_string(tile) +
+                                       "-frame tile exceeds the static scratch of " +
+                                       std::to_string(STATIC_SCRATCH_BYTES) + " bytes; use srp_compute"};
+  device_compute(hp, dp, frames, L, maps, ldm, scratch_address(dp.device), STATIC_SCRATCH_BYTES, tile, st);
 }
 
 void device_gcc_samples(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L, float* xi,

@@ -104,6 +104,15 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
                     void* maps, int64_t ld_maps, void* ws, size_t ws_bytes, int64_t frame_tile,
                     hipStream_t stream);
 
+// Bytes of the per-device static scratch workspace of srp_compute_static.
+constexpr size_t STATIC_SCRATCH_BYTES = SRP_STATIC_SCRATCH_BYTES;
+
+// device_compute with the static scratch as its workspace and the largest
+// frame tile (at most frame_tile) whose workspace fits it; throws
+// SRP_E_UNSUPPORTED when even the smallest tile does not fit.
+void device_compute_static(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L,
+                           void* maps, int64_t ld_maps, int64_t frame_tile, hipStream_t stream);
+
 // Waits for the recorded spans and accumulates them per kernel name.
 void device_profile_collect(DevicePlan& dp, std::vector<std::pair<std::string, std::pair<double, int64_t>>>& out);
 

@@ -20,9 +20,12 @@ STATUS = {0: "SRP_OK", -1: "SRP_E_INVALID", -2: "SRP_E_NOMEM", -3: "SRP_E_UNSUPP
           -4: "SRP_E_HIP", -5: "SRP_E_BUDGET"}
 
 # every function declared in include/srp.h
-EXPORTS = ["srp_default_opts", "srp_plan", "srp_workspace_size", "srp_compute",
+EXPORTS = ["srp_default_opts", "srp_plan", "srp_workspace_size", "srp_compute", "srp_compute_static",
            "srp_crossspec", "srp_gcc_samples", "srp_plan_info_get", "srp_plan_export",
            "srp_profile_enable", "srp_profile_collect", "srp_destroy", "srp_last_error", "srp_argmax"]
+
+
+STATIC_SCRATCH_BYTES = 128 << 20  # SRP_STATIC_SCRATCH_BYTES of include/srp.h
 
 
 class SrpError(RuntimeError):
@@ -77,6 +80,8 @@ def lib():
     L.srp_workspace_size.restype = ctypes.c_int
     L.srp_compute.argtypes = [vp, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
     L.srp_compute.restype = ctypes.c_int
+    L.srp_compute_static.argtypes = [vp, vp, i64, vp, i64, vp]
+    L.srp_compute_static.restype = ctypes.c_int
     L.srp_crossspec.argtypes = [vp, vp, i64, vp, vp]
     L.srp_crossspec.restype = ctypes.c_int
     L.srp_gcc_samples.argtypes = [vp, vp, i64, vp, vp]
@@ -238,6 +243,22 @@ class Plan:
         ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
         _check(lib().srp_compute(self._h, _ptr(frames), L, _ptr(maps), ld, _ptr(workspace), ws_bytes,
                                  _stream_handle(stream)))
+        return maps
+
+    def compute_static(self, frames, maps, stream=None):
+        """srp_compute_static: the maps of compute() into the given [L, J]
+        view (same layout rules), with the library's static per-GPU scratch
+        as the workspace and no allocation."""
+        import torch
+        self._check_frames(frames)
+        L = frames.shape[0]
+        odt = torch.float64 if self.dtype == "f64" else torch.float32
+        if (maps.dtype != odt or tuple(maps.shape) != (L, self.J) or not maps.is_cuda
+                or (L > 0 and self.J > 1 and maps.stride(1) != 1) or (L > 1 and maps.stride(0) < self.J)):
+            raise ValueError("maps must be an [L, J] CUDA tensor of the plan's output dtype with unit "
+                             "column stride and row stride >= J")
+        ld = maps.stride(0) if L > 1 else self.J
+        _check(lib().srp_compute_static(self._h, _ptr(frames), L, _ptr(maps), ld, _stream_handle(stream)))
         return maps
 
     def crossspec(self, frames, stream=None):

@@ -1,0 +1,102 @@
+"""srp_compute_static (no allocation, static per-GPU scratch) against
+srp_compute with a caller workspace, through the C ABI: bitwise equal maps
+for FD, SLRI and SSPI plans on two calls in a row, the second with fewer
+frames, and a clear refusal where the smallest frame tile's workspace
+exceeds the scratch."""
+
+import numpy as np
+import pytest
+
+from paper_2306_08514_amd import scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def native():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_08514_amd import native as nat
+    nat.lib()
+    return nat
+
+
+def _announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def room():
+    # the room geometry on a 17^3 subgrid (J = 4913), 300 frames: more than
+    # one 256-frame tile where the scratch forces smaller tiles
+    cfg = scenes.workload("uca8_room125k", L=300, grid_stride=3)
+    return cfg, torch.from_numpy(scenes.make_frames(cfg)).cuda()
+
+
+@pytest.mark.parametrize("variant,rq,dtype", [("fd", 0, "f32"), ("fd", 0, "bf16"), ("slri", 8, "bf16"),
+                                              ("slri", 8, "f32"), ("sspi", 4, "bf16"), ("sspi", 4, "f32"),
+                                              ("si", 0, "bf16")])
+def test_static_scratch_matches_workspace_call(native, room, variant, rq, dtype):
+    cfg, Yt = room
+    _announce(f"compute_static room-subgrid {variant} {rq} {dtype}")
+    p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, rq, dtype=dtype)
+    if (variant, dtype) == ("fd", "f32"):
+        # 20 candidate tiles: the FD contraction is split into partial
+        # products, and 300 frames need more than the scratch, so the static
+        # call runs 150-frame tiles
+        assert p.workspace_size(300) > native.STATIC_SCRATCH_BYTES >= p.workspace_size(150)
+    for L in (300, 37):                      # two calls in a row, the second smaller
+        Y = Yt[:L].contiguous()
+        ref = p.compute(Y, workspace=torch.empty(p.workspace_size(L), dtype=torch.uint8, device="cuda"))
+        out = torch.full((L, p.map_pitch), float("nan"), dtype=torch.float32, device="cuda")[:, :p.J]
+        p.compute_static(Y, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), (variant, dtype, L)
+    p.close()
+
+
+@pytest.mark.parametrize("variant,rq,dtype", [("fd", 0, "f32"), ("slri", 8, "bf16"), ("sspi", 4, "bf16")])
+def test_static_scratch_full_room_grid(native, variant, rq, dtype):
+    """The full 125,000-candidate room grid with 1000 frames, the launch
+    configuration of the benchmark: FP32 FD needs 117 MB of cross-spectra,
+    which still fits the scratch."""
+    cfg = scenes.workload("uca8_room125k")
+    _announce(f"compute_static room125k {variant} {dtype} L=1000")
+    Yt = torch.from_numpy(scenes.make_frames(cfg)).cuda()
+    p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], variant, rq, dtype=dtype)
+    ref = p.compute(Yt)
+    out = p.empty_maps(Yt.shape[0])
+    p.compute_static(Yt, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    p.close()
+    del ref, out
+    torch.cuda.empty_cache()
+
+
+def test_static_scratch_refuses_oversized_workspace(native):
+    """The 496 pairs of the 2 m disc array with 2048-point frames: FD's
+    cross-spectra for one 256-row tile take 520 MB in BF16, more than the
+    scratch, so the call is refused (and the workspace entry point still
+    runs); SSPI's GCC samples (116,492 lags) take 121 MB and fit."""
+    cfg = scenes.workload("disc32_box200k", L=4, grid_stride=10)
+    Yt = torch.from_numpy(scenes.make_frames(cfg)).cuda()
+    _announce("compute_static disc32 subgrid fd (refused)")
+    p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], "fd", 0, dtype="bf16")
+    assert p.workspace_size(4) > native.STATIC_SCRATCH_BYTES
+    out = p.empty_maps(4)
+    with pytest.raises(native.SrpError, match="static scratch"):
+        p.compute_static(Yt, out)
+    z = p.compute(Yt).cpu().numpy()
+    assert np.all(np.isfinite(z))
+    p.close()
+    _announce("compute_static disc32 subgrid sspi")
+    p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], "sspi", 4, dtype="bf16")
+    assert p.workspace_size(4) <= native.STATIC_SCRATCH_BYTES
+    ref = p.compute(Yt)
+    out = p.empty_maps(4)
+    p.compute_static(Yt, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    p.close()
