@@ -779,10 +779,11 @@ __global__ __launch_bounds__(256) void transpose_lp(const float* __restrict__ xi
 // A block owns `ft` frames (ft P rows, in tiles of 32) and up to GD_TILES
 // (row tile, 32-lag column tile) products.  Per chunk of GD_CB bins it
 // stages u = y / |y| of its frames' microphones (each (frame, mic, bin)
-// normalised once) and the chunk's table columns in LDS; wave w multiplies
-// tiles w and w + 4 on v_mfma_f32_32x32x2_f32, whose k slots 0 and 1 of
-// step b are Re and Im of bin b, each lane forming psi_p = u_m conj(u_m')
-// of its row.  The frames and the table are read once per block (the
+// normalised once) and the chunk's table columns in LDS; its eight waves
+// multiply the four products, each over one half of the chunk's bins, on
+// v_mfma_f32_32x32x2_f32 (k slot 0 walks the even bin pairs, slot 1 the odd
+// ones, Re then Im), each lane forming psi_p = u_m conj(u_m') of its row,
+// and the halves are added in LDS.  The frames and the table are read once per block (the
 // table is shared by every pair), and the next chunk is loaded into
 // registers while the current one is multiplied.  Every frame runs the same
 // instruction sequence, so its samples do not depend on the batch.
@@ -892,17 +893,22 @@ __global__ __launch_bounds__(512) void gcc_direct(const float2* __restrict__ Y, 
     __syncthreads();
     if (c + 1 < nchunks) gload(c + 1);
     if (tlive) {
+      // k slot kq of four steps covers bins b + 2 kq and b + 2 kq + 1 (Re,
+      // then Im of each): a lane reads its own two bins of u_m, u_m' and of
+      // its lag's table row, 16 bytes each per four products
+      const int kb = 16 * kq;
 #pragma unroll 8
-      for (int b = 0; b < GD_CB / 2; b += 2) {
-        // bins b, b + 1 of this wave's half: u_m, u_m' and the lag's table
-        const f32x4 x = *reinterpret_cast<const f32x4*>(u_lds + ta + 8 * b);
-        const f32x4 y = *reinterpret_cast<const f32x4*>(u_lds + tb + 8 * b);
-        const f32x4 sc = *reinterpret_cast<const f32x4*>(s_lds + tcol + 8 * b);
-        // psi = u_m conj(u_m'): Re for k slot 0, Im for slot 1
+      for (int b = 0; b < GD_CB / 2; b += 4) {
+        const f32x4 x = *reinterpret_cast<const f32x4*>(u_lds + ta + 8 * b + kb);
+        const f32x4 y = *reinterpret_cast<const f32x4*>(u_lds + tb + 8 * b + kb);
+        const f32x4 sc = *reinterpret_cast<const f32x4*>(s_lds + tcol + 8 * b + kb);
+        // psi = u_m conj(u_m')
         const float re0 = __builtin_fmaf(x.x, y.x, x.y * y.y), im0 = __builtin_fmaf(x.y, y.x, -(x.x * y.y));
         const float re1 = __builtin_fmaf(x.z, y.z, x.w * y.w), im1 = __builtin_fmaf(x.w, y.z, -(x.z * y.w));
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(kq ? im0 : re0, kq ? sc.y : sc.x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(kq ? im1 : re1, kq ? sc.w : sc.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(re0, sc.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(im0, sc.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(re1, sc.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(im1, sc.w, acc, 0, 0, 0);
       }
     }
   }
@@ -1080,16 +1086,17 @@ __global__ __launch_bounds__(256) void slri_fat_global(const float* __restrict__
 }
 
 // The same product on the matrix cores: a block owns 32 frames x 32
-// columns of g; its four waves take the lag pairs (a, a + 1) of every
-// fourth v_mfma_f32_32x32x2_f32 step (a = 8 t + 2 w), reading xi^T rows
+// columns of g; its eight waves take the lag pairs (a, a + 1) of every
+// eighth v_mfma_f32_32x32x2_f32 step (a = 16 t + 2 w), reading xi^T rows
 // (frames contiguous) and V rows (columns contiguous) straight from memory
-// eight steps ahead, and the four partial tiles are added in LDS in wave
+// twelve steps ahead, and the eight partial tiles are added in LDS in wave
 // order (deterministic).  Lags past PN read as zero.
 template <typename TG>
-__global__ __launch_bounds__(256) void slri_fat_global_mfma(const float* __restrict__ xiT, int64_t ldxi, int L,
+__global__ __launch_bounds__(512) void slri_fat_global_mfma(const float* __restrict__ xiT, int64_t ldxi, int L,
                                                             int PN, const float* __restrict__ V, int Kc,
                                                             const float* __restrict__ gscale, TG* __restrict__ g) {
-  __shared__ f32x16 red[3][64];
+  constexpr int NW = 8;
+  __shared__ f32x16 red[NW - 1][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r32 = lane & 31, kq = lane >> 5;
   const int64_t l0 = static_cast<int64_t>(blockIdx.x) * 32;
@@ -1099,14 +1106,14 @@ __global__ __launch_bounds__(256) void slri_fat_global_mfma(const float* __restr
   f32x16 acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-  constexpr int U = 8;
+  constexpr int U = 12;
   const int nsteps = (PN + 1) / 2;
-  for (int s0 = wave; s0 < nsteps; s0 += 4 * U) {
+  for (int s0 = wave; s0 < nsteps; s0 += NW * U) {
     float a[U], b[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int a_ = 2 * (s0 + 4 * u) + kq;
-      const bool ok = s0 + 4 * u < nsteps && a_ < PN;
+      const int a_ = 2 * (s0 + NW * u) + kq;
+      const bool ok = s0 + NW * u < nsteps && a_ < PN;
       a[u] = ok ? xs[static_cast<int64_t>(a_) * ldxi] : 0.0f;
       b[u] = ok ? vs[static_cast<int64_t>(a_) * Kc] : 0.0f;
     }
@@ -1116,7 +1123,7 @@ __global__ __launch_bounds__(256) void slri_fat_global_mfma(const float* __restr
   if (wave > 0) red[wave - 1][lane] = acc;
   __syncthreads();
   if (wave != 0) return;
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < NW - 1; ++q) {
     const f32x16 o = red[q][lane];
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] += o[v];
@@ -3110,7 +3117,7 @@ void launch_fat(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t ld
   if (hp.global_fit && dp.Kc % 32 == 0) {
     const dim3 g2(static_cast<unsigned>((Lc + 31) / 32), static_cast<unsigned>(dp.Kc / 32));
     TRACED(dp, "slri_fat", st,
-           hipLaunchKernelGGL(slri_fat_global_mfma<TG>, g2, dim3(256), 0, st, xiT, ldxi, static_cast<int>(Lc),
+           hipLaunchKernelGGL(slri_fat_global_mfma<TG>, g2, dim3(512), 0, st, xiT, ldxi, static_cast<int>(Lc),
                               hp.PN, dp.d_V, dp.Kc, dp.d_gscale, static_cast<TG*>(g)));
     return;
   }
