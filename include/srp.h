@@ -67,7 +67,7 @@ typedef enum {
   SRP_SLRI = 1,  /* SLRI-SRP, eq. (57) */
   SRP_SSPI = 2,  /* SSPI-SRP, eq. (58) */
   SRP_SI = 3,    /* SI-SRP, eq. (44): every lag of every pair interpolated;
-                    rank_or_q ignored (at most 32 lags per pair) */
+                    rank_or_q ignored */
   SRP_TD = 4,    /* conv. TD-SRP, eq. (23): the GCC read at the TDOA rounded
                     to the nearest sample (half away from zero); rank_or_q
                     ignored */

@@ -147,7 +147,6 @@ srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J, do
       if (rank_or_q > std::min<int64_t>(hp.J, n)) throw srp::Error{SRP_E_INVALID, "R_H exceeds min(J, P (K - 1))"};
       hp.RH = rank_or_q;
     }
-    if (variant == SRP_SI && hp.R > 32) throw srp::Error{SRP_E_UNSUPPORTED, "SI with more than 32 lags per pair is not built"};
     srp::count_macs(hp);
     if (o.device >= 0) {
       DeviceGuard g(o.device);

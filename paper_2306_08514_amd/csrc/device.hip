@@ -5,7 +5,7 @@
 //   gemm_nt (FD)     z = 2 Re[H psi] as a real MFMA GEMM              eq. (22)
 //   gcc_direct       PHAT + xi_p = 2 Re[S_p psi_p]                      eqs. (2), (40)
 //   gcc_fft          PHAT + xi_p by the iFFT                            eq. (46)
-//   slri_fat_mfma    g_p = V_p^T xi_p                                   eq. (57)
+//   slri_fat_mfma    g_p = V_p^T xi_p (global fit: slri_fat_global_mfma) eq. (57)
 //   tall_ws          z = sum_p U_p g_p                                  eq. (57)
 //   sspi_gather      z = sum_p sum_q w[j,p,q] xi_p[s(j,p) + q]          eq. (58)
 #include <hip/hip_runtime.h>
@@ -995,96 +995,12 @@ __global__ __launch_bounds__(256) void slri_fat_mfma(const float* __restrict__ x
   }
 }
 
-// SLRI fat stage g[l][p R + r] = gscale_p sum_n V_p[n][r] xi_p[l][n]
-// (eq. (57)) for pair blockIdx.y: a block covers 64 frames (one per lane,
-// coalesced xi^T reads) and splits the pair's lag rows over its four waves
-// (row n to wave n mod 4), whose partial sums meet in LDS in a fixed order;
-// V_p is wave-uniform (scalar loads).  The split keeps ~4x more loads in
-// flight for pairs with hundreds of lags.  Pair index P zero-fills g's
-// padding columns.
-constexpr int SLRI_FAT_FRAMES = 64, SLRI_FAT_SPLIT = 4;
-template <typename TG, int RMAX>
-__global__ __launch_bounds__(SLRI_FAT_FRAMES * SLRI_FAT_SPLIT) void slri_fat(
-    const float* __restrict__ xiT, int64_t ldxi, int L, const int32_t* __restrict__ np,
-    const int32_t* __restrict__ off, const float* __restrict__ V, int vrows, int R,
-    const float* __restrict__ gscale, int P, TG* __restrict__ g, int Kc) {
-  __shared__ float red[SLRI_FAT_SPLIT - 1][RMAX][SLRI_FAT_FRAMES];
-  const int lane = threadIdx.x % SLRI_FAT_FRAMES, part = threadIdx.x / SLRI_FAT_FRAMES;
-  const int64_t l = static_cast<int64_t>(blockIdx.x) * SLRI_FAT_FRAMES + lane;
-  const int p = blockIdx.y;
-  const bool live = l < L;
-  TG* gl = g + l * Kc;
-  if (p == P) {  // uniform over the block
-    if (live && part == 0)
-      for (int c = P * R; c < Kc; ++c) gl[c] = cvt<TG>(0.0f);
-    return;
-  }
-  float acc[RMAX];
-#pragma unroll
-  for (int r = 0; r < RMAX; ++r) acc[r] = 0.0f;
-  const int nrows = 2 * np[p] + 1;
-  const float* xs = xiT + static_cast<int64_t>(off[p]) * ldxi + l;
-  const float* Vp = V + static_cast<int64_t>(p) * vrows * R;
-  if (live) {
-#pragma unroll 4
-    for (int n = part; n < nrows; n += SLRI_FAT_SPLIT) {
-      const float x = xs[static_cast<int64_t>(n) * ldxi];
-#pragma unroll
-      for (int r = 0; r < RMAX; ++r)
-        if (r < R) acc[r] = __builtin_fmaf(Vp[n * R + r], x, acc[r]);
-    }
-  }
-  if (part > 0) {
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) red[part - 1][r][lane] = acc[r];
-  }
-  __syncthreads();
-  if (part == 0 && live) {
-    const float sc = gscale[p];
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      if (r >= R) break;
-      float sum = acc[r];
-#pragma unroll
-      for (int q = 0; q < SLRI_FAT_SPLIT - 1; ++q) sum += red[q][r][lane];
-      gl[p * R + r] = cvt<TG>(sum * sc);
-    }
-  }
-}
-
 // Global SLRI fat stage g = Lambda_fat xi (eq. (57) with the stacked fit of
 // (54)): g[l][c] = scale * sum_a V[a][c] xi[l][a] over all PN stacked
 // samples.  A wave holds 64 consecutive frames (coalesced xi rows) and 4
 // columns per lane (one 16-byte V load, uniform over the wave); a block is
 // 64 frames x 16 columns.  V is zero-padded to Kc columns, so the padding
 // columns come out zero.
-template <typename TG>
-__global__ __launch_bounds__(256) void slri_fat_global(const float* __restrict__ xiT, int64_t ldxi, int L,
-                                                       int PN, const float* __restrict__ V, int Kc,
-                                                       const float* __restrict__ gscale, TG* __restrict__ g) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t l = static_cast<int64_t>(blockIdx.x) * 64 + lane;
-  const int c0 = blockIdx.y * 16 + wave * 4;
-  if (l >= L) return;
-  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-  const float* xs = xiT + l;
-#pragma unroll 4
-  for (int a = 0; a < PN; ++a) {
-    const float xv = xs[static_cast<int64_t>(a) * ldxi];
-    const f32x4 v = *reinterpret_cast<const f32x4*>(V + static_cast<int64_t>(a) * Kc + c0);
-    a0 = __builtin_fmaf(v.x, xv, a0);
-    a1 = __builtin_fmaf(v.y, xv, a1);
-    a2 = __builtin_fmaf(v.z, xv, a2);
-    a3 = __builtin_fmaf(v.w, xv, a3);
-  }
-  const float sc = gscale[0];
-  TG* gl = g + l * Kc + c0;
-  gl[0] = cvt<TG>(a0 * sc);
-  gl[1] = cvt<TG>(a1 * sc);
-  gl[2] = cvt<TG>(a2 * sc);
-  gl[3] = cvt<TG>(a3 * sc);
-}
-
 // The same product on the matrix cores: a block owns 32 frames x 32
 // columns of g; its eight waves take the lag pairs (a, a + 1) of every
 // eighth v_mfma_f32_32x32x2_f32 step (a = 16 t + 2 w), reading xi^T rows
@@ -3114,45 +3030,19 @@ void launch_slices(const HostPlan& hp, DevicePlan& dp, const void* frames, int64
 template <typename TG>
 void launch_fat(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t ldxi, int64_t Lc, void* g,
                 hipStream_t st) {
-  if (hp.global_fit && dp.Kc % 32 == 0) {
+  if (hp.global_fit) {
+    if (dp.Kc % 32 != 0) throw Error{SRP_E_UNSUPPORTED, "global SLRI needs the tall width in 32-column tiles"};
     const dim3 g2(static_cast<unsigned>((Lc + 31) / 32), static_cast<unsigned>(dp.Kc / 32));
     TRACED(dp, "slri_fat", st,
            hipLaunchKernelGGL(slri_fat_global_mfma<TG>, g2, dim3(512), 0, st, xiT, ldxi, static_cast<int>(Lc),
                               hp.PN, dp.d_V, dp.Kc, dp.d_gscale, static_cast<TG*>(g)));
     return;
   }
-  if (hp.global_fit) {
-    dim3 g2(static_cast<unsigned>((Lc + 63) / 64), static_cast<unsigned>(dp.Kc / 16));
-    TRACED(dp, "slri_fat", st,
-           hipLaunchKernelGGL(slri_fat_global<TG>, g2, dim3(256), 0, st, xiT, ldxi, static_cast<int>(Lc), hp.PN,
-                              dp.d_V, dp.Kc, dp.d_gscale, static_cast<TG*>(g)));
-    return;
-  }
-  if (hp.R <= 32) {
-    const int vrows = 2 * hp.max_np + 1;
-    const dim3 g2(static_cast<unsigned>((Lc + 63) / 64), static_cast<unsigned>(hp.P + 1));
-    TRACED(dp, "slri_fat", st,
-           hipLaunchKernelGGL(slri_fat_mfma<TG>, g2, dim3(256), 0, st, xiT, ldxi, static_cast<int>(Lc), dp.d_np,
-                              dp.d_off, dp.d_V, vrows, hp.R, dp.d_gscale, hp.P, static_cast<TG*>(g), dp.Kc));
-    return;
-  }
-  {
-    const int vrows = 2 * hp.max_np + 1;
-    dim3 g2(static_cast<unsigned>((Lc + SLRI_FAT_FRAMES - 1) / SLRI_FAT_FRAMES), static_cast<unsigned>(hp.P + 1));
-#define SRP_FAT(RM)                                                                                       \
-  TRACED(dp, "slri_fat", st,                                                                              \
-         hipLaunchKernelGGL((slri_fat<TG, RM>), g2, dim3(SLRI_FAT_FRAMES * SLRI_FAT_SPLIT), 0, st, xiT, ldxi, \
-                            static_cast<int>(Lc),                                                         \
-                            dp.d_np, dp.d_off, dp.d_V, vrows, hp.R, dp.d_gscale, hp.P, static_cast<TG*>(g), \
-                            dp.Kc))
-    if (hp.R <= 8)
-      SRP_FAT(8);
-    else if (hp.R <= 16)
-      SRP_FAT(16);
-    else
-      SRP_FAT(32);
-#undef SRP_FAT
-  }
+  const int vrows = 2 * hp.max_np + 1;
+  const dim3 g2(static_cast<unsigned>((Lc + 63) / 64), static_cast<unsigned>(hp.P + 1));
+  TRACED(dp, "slri_fat", st,
+         hipLaunchKernelGGL(slri_fat_mfma<TG>, g2, dim3(256), 0, st, xiT, ldxi, static_cast<int>(Lc), dp.d_np,
+                            dp.d_off, dp.d_V, vrows, hp.R, dp.d_gscale, hp.P, static_cast<TG*>(g), dp.Kc));
 }
 
 template <int MODE, typename TG>

@@ -180,8 +180,9 @@ def run(scene="nf4", n_sources=16, frames=8, dtype="f32", forms=None, seed=0, lo
                 if variant != "si":
                     rows.append({"form": form, "setting": rq, "skipped": str(e)})
                     continue
-                # SI (44) is global SLRI at full rank R_Lambda = PN, which
-                # has no per-pair lag limit
+                # SI (44) is also global SLRI at full rank R_Lambda = PN,
+                # whose tall operand (J x PN) is smaller than the per-pair
+                # form's (J x P max_p (2 N_p + 1)) when the lag counts differ
                 p = plan("slri", info["PN"], dtype, global_fit=True)
                 variant, rq, kw = "slri", info["PN"], {"global_fit": True}
             plan_s = time.time() - t1

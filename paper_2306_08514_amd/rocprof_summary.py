@@ -46,9 +46,12 @@ _TAGS = [
     (r"xi_to_frames", "xi_to_frames"),
     (r"sspi_dense_weights", "sspi_dense_weights (plan)"),
     (r"gcc_direct", "gcc_direct"),
+    (r"slri_fat_global", "slri_fat_global"),
     (r"slri_fat", "slri_fat"),
     (r"phat_kernel", "phat"),
     (r"build_steering", "build_steering (plan)"),
+    (r"gram_global_f64", "gram_global_f64 (plan)"),
+    (r"slri_u_global_f64", "slri_u_global_f64 (plan)"),
     (r"gram_f64", "gram_f64 (plan)"),
     (r"slri_u_f64", "slri_u_f64 (plan)"),
     (r"sspi_windows", "sspi_windows (plan)"),
@@ -74,6 +77,30 @@ def tag(name):
         if re.search(pat, name):
             return t
     return name[:60]
+
+
+def _targs(name):
+    """Template arguments of a (possibly mangled) kernel name, for telling
+    instances of one kernel apart: '<...>' when demangled, else the integer
+    arguments 'Li<n>E' of the mangled name."""
+    m = re.search(r"<([^()]*)>\(", name)
+    if m:
+        return m.group(1)
+    ints = re.findall(r"Li(\d+)E", name)
+    return ",".join(ints) if ints else name[:24]
+
+
+def unique_tags(names):
+    """{name: tag}, where kernels that share a tag get their template
+    arguments appended."""
+    by = {}
+    for n in names:
+        by.setdefault(tag(n), []).append(n)
+    out = {}
+    for t, ns in by.items():
+        for n in ns:
+            out[n] = t if len(ns) == 1 else f"{t} <{_targs(n)}>"
+    return out
 
 
 def _find(d, suffix):
@@ -127,9 +154,11 @@ def traffic(fetch_dir, write_dir):
     fcal, fcopy = _calibration(fv)
     wcal, wcopy = _calibration(wv)
     kernels = {}
-    for name in sorted(set(fv) | set(wv)):
-        t = tag(name)
-        if t == "copy":
+    names = sorted(set(fv) | set(wv))
+    tags = unique_tags(names)
+    for name in names:
+        t = tags[name]
+        if tag(name) in ("copy", "torch (bench checks)"):
             continue
         f = statistics.median(fv[name]) if name in fv else None
         w = statistics.median(wv[name]) if name in wv else None
@@ -152,8 +181,12 @@ def _md_trace(d, title, cmd):
              f"Kernel source SHA-256: `{source_sha256()}`", "",
              "| kernel | calls | total ms | avg us | min us | max us | full name |",
              "|---|---:|---:|---:|---:|---:|---|"]
-    for t, name, calls, tot, avg, mn, mx in kernel_stats(d):
-        lines.append(f"| {t} | {calls} | {tot / 1e6:.3f} | {avg / 1e3:.2f} | {mn / 1e3:.2f} | {mx / 1e3:.2f} | "
+    rows = kernel_stats(d)
+    tags = unique_tags([r[1] for r in rows])
+    for tg, name, calls, tot, avg, mn, mx in rows:
+        if tg == "torch (bench checks)":
+            continue
+        lines.append(f"| {tags[name]} | {calls} | {tot / 1e6:.3f} | {avg / 1e3:.2f} | {mn / 1e3:.2f} | {mx / 1e3:.2f} | "
                      f"`{name[:110]}` |")
     return "\n".join(lines) + "\n"
 
@@ -203,14 +236,18 @@ def counters(dirs):
                 for r in csv.DictReader(f):
                     names.add(r["Counter_Name"])
     out = {}
+    per = {}
     for d in dirs:
         for cname in sorted(names):
             try:
-                vals = counter_values(d, cname)
+                per[(d, cname)] = counter_values(d, cname)
             except FileNotFoundError:
                 continue
+    tags = unique_tags({k for vals in per.values() for k in vals})
+    for (d, cname), vals in per.items():
+        if True:
             for kname, vs in vals.items():
-                t = tag(kname)
+                t = tags[kname]
                 rec = out.setdefault(t, {"name": kname, "dispatches": len(vs)})
                 rec[cname] = statistics.median(vs)
     for rec in out.values():
@@ -234,14 +271,14 @@ def _md_counters(title, dirs, cmd):
              "GRBM_GUI_ACTIVE / 8); L2 hit = TCC_HIT / (TCC_HIT + TCC_MISS).  Medians per dispatch.", "",
              "| kernel | dispatches | " + " | ".join(labels) + " |", "|---|---:|" + "---:|" * len(labels)]
     for t, r in sorted(rec.items()):
-        if t in ("copy", "torch (bench checks)") or t.endswith("(plan)"):
+        if t.startswith(("copy", "torch (bench checks)")) or t.endswith("(plan)"):
             continue
         lines.append(f"| {t} | {r['dispatches']} | " +
                      " | ".join(f"{100 * r[lab]:.1f} %" if lab in r else "—" for lab in labels) + " |")
     lines += ["", "Raw medians per dispatch:", "", "| kernel | " + " | ".join(cnames) + " |",
               "|---|" + "---:|" * len(cnames)]
     for t, r in sorted(rec.items()):
-        if t in ("copy", "torch (bench checks)") or t.endswith("(plan)"):
+        if t.startswith(("copy", "torch (bench checks)")) or t.endswith("(plan)"):
             continue
         lines.append(f"| {t} | " + " | ".join(f"{r[c]:.4g}" if c in r else "—" for c in cnames) + " |")
     return "\n".join(lines) + "\n"

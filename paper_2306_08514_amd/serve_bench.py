@@ -11,6 +11,11 @@ synthetic frames.  The continuous-batching server coalesces and overlaps
 them; per rate the benchmark reports the offered and achieved load, p50/p99
 latency from submission to maps ready, and batching statistics.
 
+Before the runs every plan is timed alone (32- and 256-frame batches): the
+cost model gives the offered load of each rate in device-seconds per
+second and the rate at which the mix would fill the device; past it the
+queue grows without bound and p99 with the run's length.
+
     python -m paper_2306_08514_amd.serve_bench [--rates 500,1000,2000] [--duration 10]
 """
 
@@ -39,6 +44,50 @@ def build_catalogue(srv, pools, log):
                     keys.append(key)
             log(f"registered M={M} J={J}: {len(keys)} plans, resident {srv.resident_bytes() / 2**30:.1f} GiB")
     return keys, t_kind
+
+
+def cost_model(ex, keys, pools, log, frames=(32, 256)):
+    """Device milliseconds per map of every plan, each alone on the device,
+    for batches of 32 frames (about the mean request, 32.5 frames) and of
+    256 frames (the largest coalesced batch); from HIP events around
+    three calls after one warm-up call."""
+    import torch
+    out = {}
+    for key in keys:
+        p = ex.plan(key)
+        row = {}
+        for n in frames:
+            fr = pools[key[0]][:n].contiguous()
+            z = p.empty_maps(n)
+            ws = torch.empty(max(1, p.workspace_size(n)), dtype=torch.uint8, device="cuda")
+            p.compute(fr, maps=z, workspace=ws)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                p.compute(fr, maps=z, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            row[n] = e0.elapsed_time(e1) / 3 / n
+            del z, ws
+        out[key] = row
+    torch.cuda.empty_cache()
+    log(f"cost model: {len(out)} plans timed")
+    return out
+
+
+def offered_load(costs, rate, frames_mean=32.5, batch=32):
+    """Device seconds per second that requests at `rate` per second bring, in
+    the mix's proportions (M, J and the form uniform, R or Q uniform in
+    their ranges), each map at its plan's cost for `batch`-frame batches."""
+    from . import scenes
+    tot = 0.0
+    nM, nJ = len(scenes.SERVING_M), len(scenes.SERVING_J)
+    for M in scenes.SERVING_M:
+        for J in scenes.SERVING_J:
+            for variant, params in (("fd", [0]), ("slri", range(4, 17)), ("sspi", range(2, 9))):
+                c = np.mean([costs[(M, J, variant, rq)][batch] for rq in params])
+                tot += c / (nM * nJ * 3)
+    return rate * frames_mean * tot / 1e3
 
 
 def run_rate(srv, pools, rate, duration, rng, log):
@@ -122,11 +171,23 @@ def main(argv=None):
     for k in keys:
         srv.submit(k, pools[k[0]][:4])
     srv.drain(timeout=600)
+    costs = cost_model(ex, keys, pools, log)
+    # the rate at which the mix would occupy the device fully (offered load
+    # 1 device-second per second) with 32-frame and with 256-frame batches
+    cap32 = 1.0 / offered_load(costs, 1.0, batch=32)
+    cap256 = 1.0 / offered_load(costs, 1.0, batch=256)
+    log(f"cost model: the mix fills the device at {cap32:.0f} req/s (32-frame batches), "
+        f"{cap256:.0f} req/s (256-frame batches)")
+    by_class = {}
+    for (M, J, variant, rq), c in costs.items():
+        by_class.setdefault(f"{variant} M={M} J={J}", []).append(c[32])
     rng = np.random.default_rng(2306085144 + args.seed)
     results = {}
     for rate in [float(r) for r in args.rates.split(",")]:
         ex.busy = {}
         results[f"{rate:g}"] = run_rate(srv, pools, rate, args.duration, rng, log)
+        results[f"{rate:g}"]["offered_load_cost_model"] = {"batch32": offered_load(costs, rate, batch=32),
+                                                           "batch256": offered_load(costs, rate, batch=256)}
         # batch spans (start to done on the slot's stream, overlapping other
         # slots) by plan class, largest first
         spans = sorted(ex.busy.items(), key=lambda kv: -kv[1][0])
@@ -139,6 +200,9 @@ def main(argv=None):
            "plans": len(keys), "resident_gib": srv.resident_bytes() / 2 ** 30,
            "registration_seconds": t_reg, "registration_seconds_by_form": t_kind,
            "slots": args.slots, "max_batch_frames": args.max_batch_frames, "duration_s": args.duration,
+           "cost_model": {"capacity_req_per_s_batch32": cap32, "capacity_req_per_s_batch256": cap256,
+                          "ms_per_map_batch32_by_class": {k: float(np.mean(v)) for k, v in
+                                                          sorted(by_class.items(), key=lambda kv: -np.mean(kv[1]))}},
            "rates": results}
     print(json.dumps(out), flush=True)
 

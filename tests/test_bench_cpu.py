@@ -66,7 +66,11 @@ def test_kernel_tags():
     assert rs.tag("void srp::sspi_gather<__bf16, 4, 32, true>(x)") == "sspi_gather"
     assert rs.tag("void srp::gcc_direct<1>(HIP_vector_type<float, 2u> const*, int)") == "gcc_direct"
     assert rs.tag("_ZN3srp13slri_fat_mfmaIDF16bEEvPKfliPKiS4_S2_iiS2_iPT_i") == "slri_fat"
-    assert rs.tag("_ZN3srp20slri_fat_global_mfmaIDF16bEEvPKfliiS2_iS2_PT_") == "slri_fat"
+    assert rs.tag("_ZN3srp20slri_fat_global_mfmaIDF16bEEvPKfliiS2_iS2_PT_") == "slri_fat_global"
+    tags = rs.unique_tags(["void srp::sspi_gather<__bf16, 3, 32, true>(float const*)",
+                           "void srp::sspi_gather<__bf16, 5, 32, true>(float const*)", "srp::gcc_direct<1>(x)"])
+    assert tags["srp::gcc_direct<1>(x)"] == "gcc_direct"
+    assert tags["void srp::sspi_gather<__bf16, 3, 32, true>(float const*)"] == "sspi_gather <__bf16, 3, 32, true>"
 
 
 def test_traffic_record_round_trips_through_the_summary(tmp_path):

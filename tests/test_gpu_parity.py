@@ -225,6 +225,23 @@ def test_si_and_td_variants(native, sq4, room_small, variant, dtype):
         _check_maps(z, _oracle_maps(variant, Y, cfg, 0), TOL[dtype], f"{variant} {cfg['name']} {dtype}")
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_si_more_than_32_lags_per_pair(native, dtype):
+    """SI on the 16-microphone 0.5 m UCA at 16 kHz: 120 pairs with up to 51
+    lags each (a tall stage of 6120 columns)."""
+    mics, fs, N = scenes.serving_array(16)
+    g = np.linspace(-2.0, 2.0, 20)
+    cfg = {"mics": mics, "grid": scenes.box_grid(g, g, np.array([-1.0])), "fs": fs, "N": N, "c": scenes.C_SOUND}
+    Y = scenes.serving_frames(16, L=9)
+    Np = o.max_lags(mics, fs, cfg["c"], 2)
+    assert (2 * Np + 1).max() > 32
+    _announce(f"si M=16 {dtype} (51 lags)")
+    p = _plan(native, cfg, "si", 0, dtype)
+    z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
+    _check_maps(z, _oracle_maps("si", Y, cfg, 0), TOL[dtype], f"si M=16 {dtype}")
+    p.close()
+
+
 # ---------------------------------------------------------- edge cases ----
 
 @pytest.mark.parametrize("R,dtype", [(8, "f32"), (64, "f32"), (224, "f32"), (224, "bf16"), (224, "f16"),
