@@ -44,7 +44,7 @@ struct DeviceGuard {
     }
   }
   ~DeviceGuard() {
-    if (changed && prev >= 0) hipSetDevice(prev);
+    if (changed && prev >= 0) (void)hipSetDevice(prev);
   }
 };
 

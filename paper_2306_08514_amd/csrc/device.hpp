@@ -8,6 +8,7 @@
 #include <utility>
 #include <vector>
 
+#include "../../include/srp.h"
 #include "plan.hpp"
 
 namespace srp {
