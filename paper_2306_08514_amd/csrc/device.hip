@@ -779,22 +779,25 @@ __global__ __launch_bounds__(256) void transpose_lp(const float* __restrict__ xi
 // A block owns `ft` frames (ft P rows, in tiles of 32) and up to GD_TILES
 // (row tile, 32-lag column tile) products.  Per chunk of GD_CB bins it
 // stages u = y / |y| of its frames' microphones (each (frame, mic, bin)
-// normalised once) and the chunk's table columns in LDS; its eight waves
-// multiply the four products, each over one half of the chunk's bins, on
+// normalised once) and the chunk's table columns in LDS; its sixteen waves
+// multiply the four products, each over one quarter of the chunk's bins, on
 // v_mfma_f32_32x32x2_f32 (k slot 0 walks the even bin pairs, slot 1 the odd
 // ones, Re then Im), each lane forming psi_p = u_m conj(u_m') of its row,
-// and the halves are added in LDS.  The frames and the table are read once per block (the
+// and the quarters are added in LDS.  Four waves per product hide the LDS
+// latency that one wave per SIMD left exposed (measured: 44 us against 49
+// with two waves per product and 55 with four loader waves feeding eight
+// multiplying ones, room workload, 125,000 candidates).  The frames and the table are read once per block (the
 // table is shared by every pair), and the next chunk is loaded into
 // registers while the current one is multiplied.  Every frame runs the same
 // instruction sequence, so its samples do not depend on the batch.
 constexpr int GD_CB = 64;                 // bins per chunk
 constexpr int GD_ROWB = GD_CB * 8 + 16;   // bytes per LDS row (a (frame, mic) or a table row)
 constexpr int GD_FM = 64;                 // max frames x microphones per block
-constexpr int GD_TILES = 4;               // products per block (each split over two waves)
+constexpr int GD_TILES = 4;               // products per block (each split over four waves)
 constexpr int GD_NCT = 4;                 // max 32-lag column tiles (2 max_np + 1 <= 128)
 
 template <int NCT>
-__global__ __launch_bounds__(512) void gcc_direct(const float2* __restrict__ Y, int M, int K, int L, int P,
+__global__ __launch_bounds__(1024) void gcc_direct(const float2* __restrict__ Y, int M, int K, int L, int P,
                                                   const int32_t* __restrict__ pm, const int32_t* __restrict__ pmp,
                                                   const int32_t* __restrict__ np, const int32_t* __restrict__ off,
                                                   int max_np, const float* __restrict__ S, int Kb, int ft, int nrt,
@@ -802,16 +805,16 @@ __global__ __launch_bounds__(512) void gcc_direct(const float2* __restrict__ Y, 
   extern __shared__ __attribute__((aligned(16))) unsigned char gd_lds[];
   unsigned char* u_lds = gd_lds;                                 // [ft M + 1 zero row][GD_ROWB]
   unsigned char* s_lds = gd_lds + (GD_FM + 1) * GD_ROWB;        // [NCT 32][GD_ROWB]
-  constexpr int NT = 512;
+  constexpr int NT = 1024;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r32 = lane & 31, kq = lane >> 5;
   const int64_t fbase = static_cast<int64_t>(blockIdx.x) * ft;
   const int fm_rows = ft * M;
   const int ntiles = nrt * nct;
-  // wave w: product (tile) w % 4 of the block's group, bins of half w / 4 of
-  // every chunk; the two halves' partial tiles are added in LDS at the end
+  // wave w: product (tile) w % 4 of the block's group, bins of quarter w / 4
+  // of every chunk; the quarters' partial tiles are added in LDS at the end
   const int t = blockIdx.y * GD_TILES + (wave & 3);
-  const int half = wave >> 2;
+  const int half = wave >> 2;  // quarter of the chunk's bins (0..3)
   const bool tlive = t < ntiles;  // uniform over the wave
   int ta, tb, tcol;
   {
@@ -821,9 +824,9 @@ __global__ __launch_bounds__(512) void gcc_direct(const float2* __restrict__ Y, 
     const bool ok = tlive && rho < ft * P && fbase + fl < L;
     // this lane's row: LDS offsets of u_m and u_m' (the zero row for padding
     // rows and frames past L) and of its lag's table row
-    ta = (ok ? fl * M + pm[p] : fm_rows) * GD_ROWB + half * (GD_CB / 2) * 8;
-    tb = (ok ? fl * M + pmp[p] : fm_rows) * GD_ROWB + half * (GD_CB / 2) * 8;
-    tcol = (ct * 32 + r32) * GD_ROWB + half * (GD_CB / 2) * 8;
+    ta = (ok ? fl * M + pm[p] : fm_rows) * GD_ROWB + half * (GD_CB / 4) * 8;
+    tb = (ok ? fl * M + pmp[p] : fm_rows) * GD_ROWB + half * (GD_CB / 4) * 8;
+    tcol = (ct * 32 + r32) * GD_ROWB + half * (GD_CB / 4) * 8;
   }
   for (int e = tid; e < GD_ROWB / 16; e += NT)
     *reinterpret_cast<f32x4*>(u_lds + fm_rows * GD_ROWB + 16 * e) = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -898,7 +901,7 @@ __global__ __launch_bounds__(512) void gcc_direct(const float2* __restrict__ Y, 
       // its lag's table row, 16 bytes each per four products
       const int kb = 16 * kq;
 #pragma unroll 8
-      for (int b = 0; b < GD_CB / 2; b += 4) {
+      for (int b = 0; b < GD_CB / 4; b += 4) {
         const f32x4 x = *reinterpret_cast<const f32x4*>(u_lds + ta + 8 * b + kb);
         const f32x4 y = *reinterpret_cast<const f32x4*>(u_lds + tb + 8 * b + kb);
         const f32x4 sc = *reinterpret_cast<const f32x4*>(s_lds + tcol + 8 * b + kb);
@@ -912,14 +915,14 @@ __global__ __launch_bounds__(512) void gcc_direct(const float2* __restrict__ Y, 
       }
     }
   }
-  // second-half partial tiles through LDS (the u buffer is free now)
+  // the other quarters' partial tiles through LDS (the u buffer is free now)
   __syncthreads();
   f32x16* red = reinterpret_cast<f32x16*>(gd_lds);
-  if (half == 1 && tlive) red[(wave & 3) * 64 + lane] = acc;
+  if (half >= 1 && tlive) red[((half - 1) * 4 + (wave & 3)) * 64 + lane] = acc;
   __syncthreads();
-  if (half == 1 || !tlive) return;
-  {
-    const f32x16 o = red[wave * 64 + lane];
+  if (half >= 1 || !tlive) return;
+  for (int q = 0; q < 3; ++q) {
+    const f32x16 o = red[(q * 4 + wave) * 64 + lane];
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] += o[v];
   }
@@ -1019,9 +1022,11 @@ __global__ __launch_bounds__(512) void slri_fat_global_mfma(const float* __restr
   const int c0 = blockIdx.y * 32;
   const float* xs = xiT + l0 + r32;
   const float* vs = V + c0 + r32;
-  f32x16 acc;
+  // two accumulators (even and odd steps) so consecutive products are
+  // independent; added at the end
+  f32x16 acc, acc1;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  for (int v = 0; v < 16; ++v) acc[v] = acc1[v] = 0.0f;
   constexpr int U = 12;
   const int nsteps = (PN + 1) / 2;
   for (int s0 = wave; s0 < nsteps; s0 += NW * U) {
@@ -1034,8 +1039,13 @@ __global__ __launch_bounds__(512) void slri_fat_global_mfma(const float* __restr
       b[u] = ok ? vs[static_cast<int64_t>(a_) * Kc] : 0.0f;
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u], b[u], acc, 0, 0, 0);
+    for (int u = 0; u < U; u += 2) {
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u], b[u], acc, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u + 1], b[u + 1], acc1, 0, 0, 0);
+    }
   }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] += acc1[v];
   if (wave > 0) red[wave - 1][lane] = acc;
   __syncthreads();
   if (wave != 0) return;
@@ -3013,7 +3023,7 @@ void launch_slices(const HostPlan& hp, DevicePlan& dp, const void* frames, int64
       HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),                                         \
                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));         \
     TRACED(dp, "gcc_direct", st,                                                                              \
-           hipLaunchKernelGGL(kern, grid, dim3(512), lds, st, static_cast<const float2*>(frames), hp.M, hp.K,  \
+           hipLaunchKernelGGL(kern, grid, dim3(1024), lds, st, static_cast<const float2*>(frames), hp.M, hp.K,  \
                               static_cast<int>(Lc), hp.P, dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, hp.max_np,    \
                               dp.d_S, dp.gd_kb, ft, nrt, dp.gd_nct, xiT, ldxi));                              \
   } while (0)
