@@ -526,7 +526,8 @@ def main():
             per_form[name]["eps_z_db_vs_fp64_fd_median"] = sweep[name]["setting"]["eps_z_db_median"]
         if variant == "sspi":
             inf = plans[name].info()
-            per_form[name]["tiles_dense_gather"] = [inf["sspi_dense_tiles"], inf["sspi_gather_tiles"]]
+            per_form[name]["tiles_dense_gather_band"] = [inf["sspi_dense_tiles"], inf["sspi_gather_tiles"],
+                                                         inf["sspi_band_tiles"]]
     fd_rate = per_form["fd"]["maps_per_s"]
     for name in per_form:
         per_form[name]["speedup_vs_fd_f32"] = per_form[name]["maps_per_s"] / fd_rate

@@ -163,6 +163,10 @@ typedef struct {
                             a dense contraction on the matrix cores; 0
                             otherwise */
   int sspi_gather_tiles; /* SSPI tiles evaluated by the gather of (58) */
+  int sspi_band_tiles;   /* SSPI with 16-bit weights and at most 8 taps when
+                            the dense windows do not fit (large apertures):
+                            256-candidate tiles run as the band product of
+                            (58) on the matrix cores (every tile, or none) */
 } srp_plan_info;
 
 /* Fills *opts with the defaults listed above. */

@@ -279,7 +279,8 @@ srp_status srp_plan_info_get(srp_plan_t plan, srp_plan_info* info) {
   if (hp.variant == SRP_SSPI) {
     const int ntiles = static_cast<int>((hp.J + 255) / 256);
     info->sspi_dense_tiles = plan->dp.sspi_dense ? plan->dp.n_dtiles : 0;
-    info->sspi_gather_tiles = plan->dp.sspi_dense ? plan->dp.n_gtiles : ntiles;
+    info->sspi_band_tiles = plan->dp.sspi_band ? ntiles : 0;
+    info->sspi_gather_tiles = plan->dp.sspi_dense ? plan->dp.n_gtiles : (plan->dp.sspi_band ? 0 : ntiles);
   }
   return SRP_OK;
 }

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <memory>
 #include <mutex>
 #include <cmath>
@@ -1559,6 +1560,345 @@ __global__ __launch_bounds__(256) void sspi_gather(const float* __restrict__ xiT
   }
 }
 
+// ===================================================== SSPI band product ===
+//
+// z[l][j] = sum_p sum_{q < Q} w[p][j][q] xi[start(p, j) + q][l] (eq. (58))
+// on the matrix cores, for apertures whose per-tile lag windows are too wide
+// for the dense-window contraction.  For 256-candidate tile t and pair p the
+// taps of the tile's candidates fall in the band of columns
+// [A_tp, A_tp + W_tp) of the frame-major FP16 samples xb[l][n] (A_tp on a
+// multiple of 8, n the stacked lag index), and those of 32-candidate
+// subtile s in the narrower band [A_tp + o_tps, A_tp + o_tps + 16 k_tps).
+// Tiles and subtiles are runs of a compact candidate order (balanced k-d
+// splits of the grid, weighted by how fast the TDOAs change along each
+// axis), which narrows the bands; the maps are written through that order.
+// A block owns one tile and 128 frames (64 when a band is too wide for
+// that).  Pairs go in passes (precomputed per
+// tile) whose bands and records fit SB_LDS: a pass's bands for the 64
+// frames, its candidates' tap records (tile-major copies made at plan time)
+// and the next pass's band descriptors are loaded straight from global
+// memory into LDS, every load in flight at once.  Wave s then multiplies,
+// pair by pair, its subtile's band on v_mfma_f32_32x32x16_f16: A = 16 band
+// columns of 32 frames, B = the 16 x 32 matrix holding each candidate's Q
+// FP16 tap weights at its own rows and zeros elsewhere.  A lane shifts its
+// packed taps once per pair into the two 8-row blocks they can touch and
+// selects its block for each step; every frame group of the block uses it.  Every frame row goes through the same sequence of products, so
+// a frame's map does not depend on the other frames of the block.
+constexpr int SB_LDS = 72 * 1024;  // bands and records of one pass (two blocks per CU)
+constexpr int SB_MAXPP = 32;    // pairs per pass at most (one descriptor load)
+
+// Band descriptor of (tile, pair): the band (A, W) and per subtile s the
+// offset o / 8 and 16-column steps k as sub[s] = (o / 8) | (k << 8)
+// (k = 0: no live candidate).
+struct BandDesc {
+  int32_t A, W;
+  uint16_t sub[8];
+  uint32_t pad[2];
+};
+static_assert(sizeof(BandDesc) == 32, "two descriptors per 64-byte load pair");
+
+// LDS row of a staged band of W columns, in 16-byte units: W + 16 columns
+// (a subtile's steps reach up to 16 columns past W), made odd so that the 32
+// rows of one read spread over the banks; every unit holds staged samples
+// (the band is read that many columns wide)
+__host__ __device__ constexpr int band_units(int W) { return ((W + 16) / 8) | 1; }
+
+// LDS bytes of one pair in a pass: its band for the block's FR frames, the
+// starts and the taps (QW 32-bit words) of the tile's 256 candidates
+__host__ __device__ constexpr int band_pair_bytes(int W, int QW, int FR) {
+  return FR * 16 * band_units(W) + 256 * 4 * (1 + QW);
+}
+
+typedef unsigned long long u64;
+
+// One candidate's column of B holds its taps (packed FP16, tap i at bits
+// 16 i of the 128-bit lo:hi) at rows rel .. rel + Q - 1 and zeros elsewhere,
+// so only the 8-row blocks rel / 8 and rel / 8 + 1 can be non-zero: the tap
+// vector shifted by 16 (rel % 8) bits, low 128 bits in f0, the rest in f1.
+// Explicit selects for shifts of 64 bits and more (the hardware takes
+// 64-bit shift amounts modulo 64).
+__device__ inline void band_blocks(u64 lo, u64 hi, int d, i32x4& f0, i32x4& f1) {
+  const int sh = 16 * d;  // 0 .. 112
+  u64 a, b, c, e;
+  if (sh == 0) {
+    a = lo;
+    b = hi;
+    c = e = 0;
+  } else if (sh < 64) {
+    a = lo << sh;
+    b = (hi << sh) | (lo >> (64 - sh));
+    c = hi >> (64 - sh);
+    e = 0;
+  } else if (sh == 64) {
+    a = 0;
+    b = lo;
+    c = hi;
+    e = 0;
+  } else {
+    a = 0;
+    b = lo << (sh - 64);
+    c = (hi << (sh - 64)) | (lo >> (128 - sh));
+    e = hi >> (128 - sh);
+  }
+  f0 = i32x4{static_cast<int>(a), static_cast<int>(a >> 32), static_cast<int>(b), static_cast<int>(b >> 32)};
+  f1 = i32x4{static_cast<int>(c), static_cast<int>(c >> 32), static_cast<int>(e), static_cast<int>(e >> 32)};
+}
+
+__device__ inline void lds_dma16(const void* src, unsigned char* dst) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                   (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+}
+
+template <int QW, int FR>
+__global__ __launch_bounds__(512) void sspi_band(const _Float16* __restrict__ xb, int64_t ldb, int Lrows,
+                                                 const int32_t* __restrict__ rstart,
+                                                 const uint32_t* __restrict__ rtaps,
+                                                 const BandDesc* __restrict__ desc,
+                                                 const uint16_t* __restrict__ bnext,
+                                                 const int32_t* __restrict__ order, int P, int64_t J, int L,
+                                                 int nftiles, float* __restrict__ z, int64_t ldz) {
+  static_assert(QW == 2 || QW == 4, "taps are packed in two or four words");
+  static_assert(FR == 64 || FR == 128, "two or four frame groups of 32");
+  constexpr int NG = FR / 32;
+  extern __shared__ __attribute__((aligned(16))) unsigned char sb_lds[];
+  unsigned char* dbuf = sb_lds;                              // [2][SB_MAXPP] descriptors
+  unsigned char* region = sb_lds + 2 * SB_MAXPP * sizeof(BandDesc);
+  const int njt = static_cast<int>((J + 255) / 256);
+  int jt, ft;
+  if (!xcd_tile(njt, nftiles, jt, ft)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r32 = lane & 31, kq = lane >> 5;
+  const int cand = wave * 32 + r32;
+  const int64_t pos = static_cast<int64_t>(jt) * 256 + cand;  // position in the compact order
+  const bool live = pos < J;
+  const int64_t l0 = static_cast<int64_t>(ft) * FR;
+  const int64_t tp0 = static_cast<int64_t>(jt) * P;  // (tile, pair 0)
+  const int64_t ndesc = static_cast<int64_t>(njt) * P;
+  const uint16_t* nx = bnext + tp0;
+  // descriptors of the first pass
+  if (wave == 0 && 2 * tp0 + lane < 2 * ndesc)
+    lds_dma16(reinterpret_cast<const unsigned char*>(desc + tp0) + 16 * lane, dbuf);
+
+  f32x16 acc[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[g][v] = 0.0f;
+  int cur = 0;
+  for (int p0 = 0; p0 < P; cur ^= 1) {
+    const int p1 = nx[p0];
+    const int np = p1 - p0;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();  // the previous pass's reads are done; this pass's descriptors are in
+    const BandDesc* dc = reinterpret_cast<const BandDesc*>(dbuf + cur * SB_MAXPP * sizeof(BandDesc));
+    // bands: pair q's band is u 16-byte pieces per frame, item i = f u + c at
+    // byte 16 i of its part of the region; each wave issues every 8th chunk
+    // of 64 items
+    int off = 0;
+    for (int k = 0; k < np; ++k) {
+      const int A = dc[k].A, u = band_units(dc[k].W);
+      const int items = FR * u;
+      const float inv = 1.0f / static_cast<float>(u);
+      for (int c0 = 64 * wave; c0 < items; c0 += 512) {
+        const int i = c0 + lane;
+        // i / u exactly: i < 128 u and the quotient's fraction is >= 1 / (2 u)
+        const int f = static_cast<int>((static_cast<float>(i) + 0.5f) * inv);
+        const int c = i - f * u;
+        const int64_t row = min(l0 + f, static_cast<int64_t>(Lrows - 1));  // rows past the frames are not stored
+        if (i < items) lds_dma16(xb + row * ldb + A + 8 * c, region + off + 16 * c0);
+      }
+      off += 16 * items;
+    }
+    // records: starts (1 KB per pair) and taps (QW KB per pair), contiguous
+    // for the pass's pairs in the tile-major copies
+    unsigned char* rs = region + off;
+    unsigned char* rw = rs + 1024 * np;
+    const unsigned char* gs = reinterpret_cast<const unsigned char*>(rstart + (tp0 + p0) * 256);
+    const unsigned char* gw = reinterpret_cast<const unsigned char*>(rtaps + (tp0 + p0) * 256 * QW);
+    for (int c0 = wave; c0 < np * (1 + QW); c0 += 8) {
+      if (c0 < np)
+        lds_dma16(gs + 1024 * c0 + 16 * lane, rs + 1024 * c0);
+      else
+        lds_dma16(gw + 1024 * (c0 - np) + 16 * lane, rw + 1024 * (c0 - np));
+    }
+    // descriptors of the next pass (32, past P harmless)
+    if (wave == 0 && p1 < P && 2 * (tp0 + p1) + lane < 2 * ndesc)
+      lds_dma16(reinterpret_cast<const unsigned char*>(desc + tp0 + p1) + 16 * lane,
+                dbuf + (cur ^ 1) * SB_MAXPP * sizeof(BandDesc));
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    off = 0;
+    for (int k = 0; k < np; ++k) {
+      const int A = dc[k].A, u = band_units(dc[k].W);
+      const uint32_t e = dc[k].sub[wave];
+      const int o = 8 * static_cast<int>(e & 0xffu), ks = static_cast<int>(e >> 8);
+      const int s_c = reinterpret_cast<const int32_t*>(rs)[k * 256 + cand];
+      u64 lo = 0, hi = 0;
+      if constexpr (QW == 2) {
+        lo = reinterpret_cast<const u64*>(rw)[k * 256 + cand];
+      } else {
+        lo = reinterpret_cast<const u64*>(rw)[2 * (k * 256 + cand)];
+        hi = reinterpret_cast<const u64*>(rw)[2 * (k * 256 + cand) + 1];
+      }
+      const int rel = s_c - A - o;  // row of tap 0 in the subtile's band (>= 0)
+      i32x4 f0, f1;
+      band_blocks(lo, hi, rel & 7, f0, f1);
+      const int b0 = rel >> 3;  // the 8-row block of f0
+      const unsigned char* ar = region + off + r32 * u * 16 + (o + 8 * kq) * 2;
+      for (int kk = 0; kk < ks; ++kk) {
+        const int bi = 2 * kk + kq;  // this lane's 8-row block of the step
+        i32x4 bf;
+#pragma unroll
+        for (int e2 = 0; e2 < 4; ++e2) bf[e2] = bi == b0 ? f0[e2] : (bi == b0 + 1 ? f1[e2] : 0);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          const i32x4 af = *reinterpret_cast<const i32x4*>(ar + g * 32 * u * 16 + 32 * kk);
+          acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, af),
+                                                          __builtin_bit_cast(f16x8, bf), acc[g], 0, 0, 0);
+        }
+      }
+      off += FR * 16 * u;
+    }
+    p0 = p1;
+  }
+  if (!live) return;
+  const int64_t j = order[pos];
+  // register v of lane i: frame 8 (v / 4) + 4 (i / 32) + v % 4 of the group,
+  // candidate i % 32
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t l = l0 + 32 * g + 8 * (v / 4) + 4 * kq + (v % 4);
+      if (l < L) z[l * ldz + j] = acc[g][v];
+    }
+}
+
+// Band descriptors from the tile-major records: block (t, p), one thread per
+// candidate of tile t.  A rounded down and A + W up to multiples of 8; subtile s's taps
+// lie in [A + o, A + o + 16 k), o a multiple of 8.
+__global__ __launch_bounds__(256) void sspi_band_tables(const int32_t* __restrict__ rstart, int64_t J, int Q,
+                                                        int P, BandDesc* __restrict__ desc) {
+  __shared__ int lo_s[8], hi_s[8];
+  const int t = blockIdx.x, p = blockIdx.y;
+  const int tid = threadIdx.x;
+  const bool live = static_cast<int64_t>(t) * 256 + tid < J;
+  const int s = live ? rstart[(static_cast<int64_t>(t) * P + p) * 256 + tid] : 0;
+  int lo = live ? s : INT_MAX, hi = live ? s + Q : INT_MIN;
+  // min / max over each 32-candidate subtile
+  for (int m = 16; m >= 1; m >>= 1) {
+    lo = min(lo, __shfl_xor(lo, m, 32));
+    hi = max(hi, __shfl_xor(hi, m, 32));
+  }
+  if ((tid & 31) == 0) {
+    lo_s[tid >> 5] = lo;
+    hi_s[tid >> 5] = hi;
+  }
+  __syncthreads();
+  int blo = INT_MAX, bhi = INT_MIN;
+  for (int i = 0; i < 8; ++i) {
+    blo = min(blo, lo_s[i]);
+    bhi = max(bhi, hi_s[i]);
+  }
+  // tile t holds at least one live candidate, so blo <= bhi
+  const int A = blo - blo % 8;  // starts are >= 0
+  const int W = (bhi - A + 7) / 8 * 8;
+  BandDesc* d = desc + static_cast<int64_t>(t) * P + p;
+  if (tid == 0) {
+    d->A = A;
+    d->W = W;
+    d->pad[0] = d->pad[1] = 0u;
+  }
+  if (tid < 8) {
+    const int sl = lo_s[tid], sh = hi_s[tid];
+    uint16_t e = 0;
+    if (sl <= sh) {
+      const int o = (sl - A) / 8 * 8;
+      const int k = (sh - A - o + 15) / 16;
+      e = static_cast<uint16_t>((o / 8) | (k << 8));
+    }
+    d->sub[tid] = e;
+  }
+}
+
+// Passes of the band product: per tile, consecutive pairs (at most
+// SB_MAXPP) whose bands and records fit SB_LDS (one always does);
+// bnext[t][p0] = the first pair after the pass that starts at p0.  One
+// thread per tile.
+__global__ __launch_bounds__(256) void sspi_band_passes(const BandDesc* __restrict__ desc, int njt, int P, int QW,
+                                                        int FR, uint16_t* __restrict__ bnext) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= njt) return;
+  const BandDesc* dt = desc + static_cast<int64_t>(t) * P;
+  for (int p0 = 0; p0 < P;) {
+    int bytes = 0, p1 = p0;
+    while (p1 < P && p1 - p0 < SB_MAXPP) {
+      const int b = band_pair_bytes(dt[p1].W, QW, FR);
+      if (p1 > p0 && bytes + b > SB_LDS) break;
+      bytes += b;
+      ++p1;
+    }
+    bnext[static_cast<int64_t>(t) * P + p0] = static_cast<uint16_t>(p1);
+    p0 = p1;
+  }
+}
+
+// Tile-major records of the band product: rstart[t][p][c] and the taps as
+// packed FP16, QW words each, of candidate order[t 256 + c] (zeros for
+// positions past J and taps past Q).
+template <typename TW>
+__global__ __launch_bounds__(256) void sspi_band_records(const int32_t* __restrict__ start,
+                                                         const TW* __restrict__ w, int Qs, int Q, int64_t J,
+                                                         int P, int QW, const int32_t* __restrict__ order,
+                                                         int32_t* __restrict__ rstart,
+                                                         uint32_t* __restrict__ rtaps) {
+  const int t = blockIdx.x, p = blockIdx.y, c = threadIdx.x;
+  const int64_t pos = static_cast<int64_t>(t) * 256 + c;
+  const int64_t dst = (static_cast<int64_t>(t) * P + p) * 256 + c;
+  uint32_t v[4] = {0u, 0u, 0u, 0u};
+  int s = 0;
+  if (pos < J) {
+    const int64_t j = order[pos];
+    const int64_t rec = static_cast<int64_t>(p) * J + j;
+    s = start[rec];
+    for (int i = 0; i < Q; ++i) {
+      const _Float16 h = static_cast<_Float16>(static_cast<float>(w[rec * Qs + i]));
+      v[i / 2] |= static_cast<uint32_t>(__builtin_bit_cast(uint16_t, h)) << (16 * (i % 2));
+    }
+  }
+  rstart[dst] = s;
+  for (int k = 0; k < QW; ++k) rtaps[dst * QW + k] = v[k];
+}
+
+// xb[l][n] = xi[n][l] in FP16 for n < PN, zero for PN <= n < XB (frame-major
+// samples of the band product), from the lag-major samples xiT [PN][ldxi].
+__global__ __launch_bounds__(256) void xi_rows16(const float* __restrict__ xiT, int64_t ldxi, int L, int PN,
+                                                 int XB, _Float16* __restrict__ xb, int64_t ldb) {
+  __shared__ float t[32][33];
+  const int n0 = blockIdx.x * 32, l0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int n = n0 + r, l = l0 + tx;
+    t[r][tx] = (n < PN && l < L) ? xiT[static_cast<int64_t>(n) * ldxi + l] : 0.0f;
+  }
+  __syncthreads();
+  const int n = n0 + tx;
+  if (n >= XB) return;
+  for (int r = ty; r < 32; r += 8) {
+    const int l = l0 + r;
+    if (l < L) xb[static_cast<int64_t>(l) * ldb + n] = static_cast<_Float16>(t[tx][r]);
+  }
+}
+
+// The same from the frame-major samples of the iFFT kernel, part [L][PN].
+__global__ __launch_bounds__(256) void rows_to_f16(const float* __restrict__ part, int64_t ldp, int L, int PN,
+                                                   int XB, _Float16* __restrict__ xb, int64_t ldb) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t l = i / XB, n = i % XB;
+  if (l >= L) return;
+  xb[l * ldb + n] = n < PN ? static_cast<_Float16>(part[l * ldp + n]) : static_cast<_Float16>(0.0f);
+}
+
 // ================================================== plan-time kernels =====
 
 // sinc(x - n) for integer n with the argument reduced exactly: x = k0 + r,
@@ -2446,6 +2786,69 @@ static void build_sspi_dense(HostPlan& hp, DevicePlan& dp, Alloc& A, const std::
   dp.n_gtiles = static_cast<int>(gtiles.size());
 }
 
+// SSPI band product (the matrix cores for wide windows): descriptors and
+// passes per tile on the device, then tile-major FP16 copies of the records,
+// which replace the pair-major ones (the band product is then the only
+// consumer).  Used when every pair's band fits one pass.
+template <typename TW>
+static void build_sspi_band(HostPlan& hp, DevicePlan& dp, Alloc& A, int njt, int Qs) {
+  const int P = hp.P, Q = dp.sspi_q;
+  const int QW = Q <= 4 ? 2 : 4;
+  const size_t nd = static_cast<size_t>(njt) * P;
+  if (P > 65535) return;
+  // compact order and tile-major records
+  std::vector<int32_t> order = compact_order(hp, 256, 32);
+  order.resize(static_cast<size_t>(njt) * 256, 0);
+  const size_t nr = nd * 256;
+  std::unique_ptr<TmpBuf> ord(new TmpBuf(order.size() * 4)), rs(new TmpBuf(nr * 4)), rw(new TmpBuf(nr * 4 * QW));
+  upload(static_cast<int32_t*>(ord->p), order);
+  hipLaunchKernelGGL(sspi_band_records<TW>, dim3(static_cast<unsigned>(njt), static_cast<unsigned>(P)), dim3(256), 0,
+                     0, dp.d_start, static_cast<const TW*>(dp.d_w), Qs, Q, hp.J, P, QW, ord->as<int32_t>(),
+                     rs->as<int32_t>(), static_cast<uint32_t*>(rw->p));
+  check_launch("sspi_band_records");
+  TmpBuf dd(nd * sizeof(BandDesc));
+  hipLaunchKernelGGL(sspi_band_tables, dim3(static_cast<unsigned>(njt), static_cast<unsigned>(P)), dim3(256), 0, 0,
+                     rs->as<int32_t>(), hp.J, Q, P, static_cast<BandDesc*>(dd.p));
+  check_launch("sspi_band_tables");
+  std::vector<BandDesc> descs(nd);
+  HIP_OK(hipMemcpy(descs.data(), dd.p, nd * sizeof(BandDesc), hipMemcpyDeviceToHost));
+  int widest = 0, last = 0;
+  for (const BandDesc& d : descs) {
+    widest = std::max(widest, d.W);
+    last = std::max(last, d.A + 8 * band_units(d.W));
+  }
+  // 128 frames per block when the widest band fits a pass, else 64
+  const int FR = band_pair_bytes(widest, QW, 128) <= SB_LDS ? 128 : 64;
+  if (band_pair_bytes(widest, QW, FR) > SB_LDS) return;  // the gather takes wide bands
+  dp.d_bdesc = A.get(nd * sizeof(BandDesc));
+  HIP_OK(hipMemcpy(dp.d_bdesc, dd.p, nd * sizeof(BandDesc), hipMemcpyDeviceToDevice));
+  dp.d_bnext = static_cast<uint16_t*>(A.get(nd * sizeof(uint16_t)));
+  hipLaunchKernelGGL(sspi_band_passes, dim3(static_cast<unsigned>((njt + 255) / 256)), dim3(256), 0, 0,
+                     static_cast<const BandDesc*>(dp.d_bdesc), njt, P, QW, FR, dp.d_bnext);
+  check_launch("sspi_band_passes");
+  int32_t* rstart = static_cast<int32_t*>(A.get(nr * 4));
+  uint32_t* rtaps = static_cast<uint32_t*>(A.get(nr * 4 * QW));
+  dp.d_border = static_cast<int32_t*>(A.get(order.size() * 4));
+  HIP_OK(hipMemcpy(rstart, rs->p, nr * 4, hipMemcpyDeviceToDevice));
+  HIP_OK(hipMemcpy(rtaps, rw->p, nr * 4 * QW, hipMemcpyDeviceToDevice));
+  HIP_OK(hipMemcpy(dp.d_border, ord->p, order.size() * 4, hipMemcpyDeviceToDevice));
+  rs.reset();
+  rw.reset();
+  HIP_OK(hipDeviceSynchronize());
+  // the pair-major records are not read again
+  const size_t es = dsize(hp.dtype);
+  HIP_OK(hipFree(dp.d_start));
+  HIP_OK(hipFree(dp.d_w));
+  dp.resident_bytes -= static_cast<size_t>(hp.J) * P * 4 + static_cast<size_t>(hp.J) * P * Qs * es;
+  dp.d_start = rstart;
+  dp.d_w = rtaps;
+  dp.sspi_qw = QW;
+  dp.sspi_fr = FR;
+  // a band of W columns is staged band_units(W) pieces of 8 columns wide
+  dp.sspi_xb = static_cast<int>(round_up(std::max<int64_t>(hp.PN, last) + 32, 8));
+  dp.sspi_band = true;
+}
+
 void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budget) {
   (void)frame_tile;
   dp.device = -1;
@@ -2700,7 +3103,15 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     dp.sspi_cap = std::max(widest, 32 * 1024 / ((SSPI_FT + 4) * 4));
     if (static_cast<size_t>(dp.sspi_cap) * (SSPI_FT + 4) * 4 > 150 * 1024)
       throw Error{SRP_E_UNSUPPORTED, "a candidate tile spans too many lags of one pair for the SSPI tile"};
-    if (hp.dtype == SRP_BF16 || hp.dtype == SRP_F16) build_sspi_dense(hp, dp, A, wins, njt, Qs);
+    if (hp.dtype == SRP_BF16 || hp.dtype == SRP_F16) {
+      build_sspi_dense(hp, dp, A, wins, njt, Qs);
+      if (!dp.sspi_dense && Q <= 8) {
+        if (hp.dtype == SRP_BF16)
+          build_sspi_band<__bf16>(hp, dp, A, njt, Qs);
+        else
+          build_sspi_band<_Float16>(hp, dp, A, njt, Qs);
+      }
+    }
   }
 }
 
@@ -2782,7 +3193,7 @@ void device_free(DevicePlan& dp) {
   for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
   void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_tw, dp.d_w2,
                   dp.d_U, dp.d_V, dp.d_gscale, dp.d_F, dp.d_start, dp.d_w, dp.d_win, dp.d_xg, dp.d_B,
-                  dp.d_ctab, dp.d_colmap, dp.d_dtiles, dp.d_gtiles, dp.ws};
+                  dp.d_ctab, dp.d_colmap, dp.d_dtiles, dp.d_gtiles, dp.d_bdesc, dp.d_bnext, dp.d_border, dp.ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   dp = DevicePlan{};
@@ -2829,6 +3240,10 @@ WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t 
   if (hp.variant == SRP_SSPI && dp.sspi_dense) {
     w.xf = off;  // frame-major samples of the dense-window path (8 shifted copies)
     off = align256(off + static_cast<size_t>(w.Lpad) * 8 * dp.sspi_xw * dsize(hp.dtype));
+  }
+  if (hp.variant == SRP_SSPI && dp.sspi_band) {
+    w.xf = off;  // frame-major FP16 samples of the band product
+    off = align256(off + static_cast<size_t>(w.Lpad) * dp.sspi_xb * 2);
   }
   w.total = off;
   return w;
@@ -3057,7 +3472,7 @@ void launch_fat(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t ld
 
 template <int MODE, typename TG>
 void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t Lc, float* xiT, int64_t ldxi,
-                  float* part, void* g, hipStream_t st) {
+                  float* part, void* g, hipStream_t st, bool lag_major = true) {
   if (hp.fft) {
     const dim3 grid(static_cast<unsigned>(Lc * hp.P));
 #define SRP_FFT(LK)                                                                                           \
@@ -3073,6 +3488,7 @@ void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_
       default: throw Error{SRP_E_UNSUPPORTED, "iFFT sampling needs N a power of two, at most 4096"};
     }
 #undef SRP_FFT
+    if (!lag_major) return;  // the caller reads the frame-major samples in part
     const dim3 tgrid(static_cast<unsigned>((hp.PN + 31) / 32), static_cast<unsigned>((Lc + 31) / 32));
     TRACED(dp, "transpose_lp", st,
            hipLaunchKernelGGL(transpose_lp, tgrid, dim3(256), 0, st, part, static_cast<int64_t>(hp.PN),
@@ -3107,6 +3523,52 @@ void launch_sspi_q(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t
          hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, xiT, Lpad, hp.PN, dp.d_start,
                             static_cast<const TW*>(dp.d_w), Qs, dp.d_win, dp.sspi_cap, hp.P, hp.J,
                             static_cast<int>(Lc), nf, z, ldz, tl, nj));
+}
+
+template <int QW, int FR>
+void launch_band_qw(const HostPlan& hp, DevicePlan& dp, const _Float16* xb, int64_t Lc, float* z, int64_t ldz,
+                    hipStream_t st) {
+  auto kern = &sspi_band<QW, FR>;
+  const int lds = SB_LDS + 2 * SB_MAXPP * static_cast<int>(sizeof(BandDesc));
+  HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  const int njt = static_cast<int>((hp.J + 255) / 256);
+  const int nf = static_cast<int>((Lc + FR - 1) / FR);
+  const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(njt) * nf, 8));
+  TRACED(dp, "sspi_band", st,
+         hipLaunchKernelGGL(kern, dim3(blocks), dim3(512), lds, st, xb, static_cast<int64_t>(dp.sspi_xb),
+                            static_cast<int>(Lc), dp.d_start, static_cast<const uint32_t*>(dp.d_w),
+                            static_cast<const BandDesc*>(dp.d_bdesc), dp.d_bnext, dp.d_border, hp.P, hp.J,
+                            static_cast<int>(Lc), nf, z, ldz));
+}
+
+// SSPI band product of the frame tile: frame-major FP16 samples, then the
+// band kernel over every candidate tile.
+void launch_band(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t Lpad, const float* part,
+                 _Float16* xb, int64_t Lc, float* z, int64_t ldz, hipStream_t st) {
+  const int XB = dp.sspi_xb;
+  if (hp.fft) {
+    const int64_t n = Lc * XB;
+    TRACED(dp, "xi_to_frames", st,
+           hipLaunchKernelGGL(rows_to_f16, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, part,
+                              static_cast<int64_t>(hp.PN), static_cast<int>(Lc), hp.PN, XB, xb,
+                              static_cast<int64_t>(XB)));
+  } else {
+    const dim3 gt(static_cast<unsigned>((XB + 31) / 32), static_cast<unsigned>((Lc + 31) / 32));
+    TRACED(dp, "xi_to_frames", st,
+           hipLaunchKernelGGL(xi_rows16, gt, dim3(256), 0, st, xiT, Lpad, static_cast<int>(Lc), hp.PN, XB, xb,
+                              static_cast<int64_t>(XB)));
+  }
+  if (dp.sspi_qw == 2) {
+    if (dp.sspi_fr == 128)
+      launch_band_qw<2, 128>(hp, dp, xb, Lc, z, ldz, st);
+    else
+      launch_band_qw<2, 64>(hp, dp, xb, Lc, z, ldz, st);
+  } else {
+    if (dp.sspi_fr == 128)
+      launch_band_qw<4, 128>(hp, dp, xb, Lc, z, ldz, st);
+    else
+      launch_band_qw<4, 64>(hp, dp, xb, Lc, z, ldz, st);
+  }
 }
 
 template <typename TW>
@@ -3264,6 +3726,14 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
           break;
       }
     } else {
+      if (dp.sspi_band) {
+        // band product on the matrix cores; the iFFT's frame-major samples
+        // feed it directly
+        launch_front<0, float>(hp, dp, fr, Lc, xiT, lay.Lpad, part, nullptr, st, !hp.fft);
+        _Float16* xb = reinterpret_cast<_Float16*>(base + lay.xf);
+        launch_band(hp, dp, xiT, lay.Lpad, part, xb, Lc, z, ldm, st);
+        continue;
+      }
       launch_front<0, float>(hp, dp, fr, Lc, xiT, lay.Lpad, part, nullptr, st);
       if (dp.sspi_dense) {
         // dense windows on the matrix cores: frame-major samples, then the

@@ -56,8 +56,8 @@ struct DevicePlan {
   int Fpad = 0;
   float lr_gscale = 1.0f;    // activation scale applied when g is narrowed
   // SSPI
-  int32_t* d_start = nullptr;  // [J][P] absolute stacked lag index of tap 0
-  void* d_w = nullptr;         // [J][P][Q] in dtype (f32, bf16, f16 or fp8)
+  int32_t* d_start = nullptr;  // [P][J] absolute stacked lag index of tap 0
+  void* d_w = nullptr;         // [P][J][Q] in dtype (f32, bf16, f16 or fp8)
   int2* d_win = nullptr;          // [J / 256 tiles][P] (first row, rows) lag window of a tile
   int sspi_cap = 0;               // LDS rows per staged chunk of the gather
   int sspi_q = 0;                 // taps per record read by the gather (>= the selection's Q)
@@ -76,6 +76,20 @@ struct DevicePlan {
   int32_t* d_dtiles = nullptr;     // tiles on the matrix cores
   int32_t* d_gtiles = nullptr;     // tiles left to the gather
   int n_dtiles = 0, n_gtiles = 0;
+  // SSPI band product on the matrix cores (16-bit weights, Q <= 8, when the
+  // dense windows do not fit), over tiles of a compact candidate order: per
+  // tile and pair the band descriptor
+  // [tiles][P] and the first pair of the next LDS pass [tiles][P]; the
+  // records are then tile-major ([tiles][P][256] starts in d_start and
+  // sspi_qw words of packed FP16 taps per record in d_w); xb is the
+  // frame-major FP16 copy of the samples, sspi_xb columns wide
+  bool sspi_band = false;
+  void* d_bdesc = nullptr;
+  uint16_t* d_bnext = nullptr;
+  int32_t* d_border = nullptr;  // candidate at each position of the compact order [tiles 256]
+  int sspi_qw = 0;
+  int sspi_fr = 0;              // frames per block of the band product (64 or 128)
+  int sspi_xb = 0;
   // per-kernel timing (see srp_profile_enable)
   struct Span {
     const char* name;

@@ -690,4 +690,88 @@ void count_macs(HostPlan& hp) {
   }
 }
 
+std::vector<int32_t> compact_order(const HostPlan& hp, int tile, int sub) {
+  const int64_t J = hp.J;
+  if (J > std::numeric_limits<int32_t>::max()) fail("too many candidates for a compact order");
+  if (tile < 1 || sub < 1 || tile % sub) fail("tile must be a multiple of sub");
+  // TDOA sensitivity per axis: mean over sampled candidates and all pairs of
+  // |d x_p / d r_a| = |u_m - u_m'|_a fs / c (u: unit vector from the mic to
+  // the candidate; far field: the TDOA is linear in the direction, the
+  // gradient |r_m - r_m'|_a fs / c)
+  double sens[3] = {0.0, 0.0, 0.0};
+  const int64_t step = std::max<int64_t>(1, J / 4096);
+  int64_t ns = 0;
+  for (int64_t j = 0; j < J; j += step, ++ns) {
+    const double* r = &hp.grid[3 * j];
+    for (int p = 0; p < hp.P; ++p) {
+      const double* a = &hp.mics[3 * hp.pair_m[p]];
+      const double* b = &hp.mics[3 * hp.pair_mp[p]];
+      if (hp.far_field) {
+        for (int k = 0; k < 3; ++k) sens[k] += std::fabs(a[k] - b[k]);
+        continue;
+      }
+      double da = 0.0, db = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        da += (r[k] - a[k]) * (r[k] - a[k]);
+        db += (r[k] - b[k]) * (r[k] - b[k]);
+      }
+      da = std::sqrt(da);
+      db = std::sqrt(db);
+      for (int k = 0; k < 3; ++k) {
+        const double ua = da > 0 ? (r[k] - a[k]) / da : 0.0, ub = db > 0 ? (r[k] - b[k]) / db : 0.0;
+        sens[k] += std::fabs(ua - ub);
+      }
+    }
+  }
+  for (double& v : sens) v = v / static_cast<double>(std::max<int64_t>(ns, 1)) + 1e-12;
+  std::vector<int32_t> order(static_cast<size_t>(J));
+  for (int64_t j = 0; j < J; ++j) order[j] = static_cast<int32_t>(j);
+  auto coord = [&](int32_t j, int k) { return hp.grid[3 * static_cast<size_t>(j) + k]; };
+  // explicit stack of ranges [a, b) to split at multiples of `size`
+  struct Range {
+    int64_t a, b;
+    int size;
+  };
+  std::vector<Range> stack{{0, J, tile}};
+  while (!stack.empty()) {
+    const Range rg = stack.back();
+    stack.pop_back();
+    const int64_t n = rg.b - rg.a;
+    if (n <= rg.size) {
+      if (rg.size == tile && sub < tile) {
+        stack.push_back({rg.a, rg.b, sub});  // split the tile into subtiles
+      } else if (rg.size == sub) {
+        std::sort(order.begin() + rg.a, order.begin() + rg.b);
+      }
+      continue;
+    }
+    int axis = 0;
+    double best = -1.0;
+    for (int k = 0; k < 3; ++k) {
+      double lo = std::numeric_limits<double>::infinity(), hi = -lo;
+      for (int64_t i = rg.a; i < rg.b; ++i) {
+        lo = std::min(lo, coord(order[i], k));
+        hi = std::max(hi, coord(order[i], k));
+      }
+      const double e = (hi - lo) * sens[k];
+      if (e > best) {
+        best = e;
+        axis = k;
+      }
+    }
+    const int64_t half = (n + 2 * rg.size - 1) / (2 * rg.size) * rg.size;  // a multiple of size, >= n / 2
+    const int64_t m = rg.a + std::min(half, n - 1);
+    std::nth_element(order.begin() + rg.a, order.begin() + m, order.begin() + rg.b, [&](int32_t x, int32_t y) {
+      const double cx = coord(x, axis), cy = coord(y, axis);
+      return cx < cy || (cx == cy && x < y);
+    });
+    // the right part is split first only after the left (stack order keeps
+    // the output order: left then right)
+    stack.push_back({m, rg.b, rg.size});
+    stack.push_back({rg.a, m, rg.size});
+  }
+  return order;
+}
+
 }  // namespace srp
+

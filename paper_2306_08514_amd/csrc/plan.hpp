@@ -109,6 +109,15 @@ void build_sspi_global(HostPlan& hp, int qbar, int threads);
 // direct product, 2 PN (K-1)).
 void count_macs(HostPlan& hp);
 
+// Candidate order for tiled products: consecutive runs of `tile` candidates
+// (all but the last full) that are compact where the TDOAs change most,
+// each split the same way into runs of `sub` (tile a multiple of sub).
+// Balanced k-d splits on the grid coordinates: a range goes at a multiple
+// of `tile` (then `sub`) candidates along the axis whose extent times the
+// mean |dx_p / d axis| over the pairs is largest; a subtile's candidates are
+// in increasing index.  Returns the candidate of each position.
+std::vector<int32_t> compact_order(const HostPlan& hp, int tile, int sub);
+
 // sinc(x - n) for integer n, accurate for large |x| (argument reduced
 // exactly in FP64).
 double sinc_shift(double x, int n);

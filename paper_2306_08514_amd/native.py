@@ -50,7 +50,7 @@ class PlanInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_size_t), ("plan_seconds", ctypes.c_double),
                 ("map_pitch", ctypes.c_int64), ("sampling_fft", ctypes.c_int),
                 ("fd_generated", ctypes.c_int), ("sspi_dense_tiles", ctypes.c_int),
-                ("sspi_gather_tiles", ctypes.c_int)]
+                ("sspi_gather_tiles", ctypes.c_int), ("sspi_band_tiles", ctypes.c_int)]
 
 
 class KernelTime(ctypes.Structure):

@@ -319,8 +319,10 @@ def test_host_plans_report_the_sspi_tile_split():
     info = p.info()
     assert info["sspi_dense_tiles"] == 0
     assert info["sspi_gather_tiles"] == (len(cfg["grid"]) + 255) // 256
+    assert info["sspi_band_tiles"] == 0
     q, _ = _host_plan("slri", 4)
     assert q.info()["sspi_dense_tiles"] == 0 and q.info()["sspi_gather_tiles"] == 0
+    assert q.info()["sspi_band_tiles"] == 0
 
 def test_td_endfire_candidates_stay_in_the_sampled_range():
     """With N_aux = 0, N_p = floor(d fs / c): a candidate on a pair's axis
