@@ -1069,27 +1069,27 @@ __global__ __launch_bounds__(512) void slri_fat_global_mfma(const float* __restr
 //
 // z[l][j] = alpha * sum_c g[l][c] U[j][c] (the tall stage of eq. (57)) for the
 // 16-bit and FP8 operands with rows of at most 1 KB.  Warp-specialised
-// streaming: one loader wave stages the g rows of the next groups of 32
-// frames into LDS (three buffers, two groups ahead) while CW compute waves
-// (32 candidates each) multiply the current group and store it.  The loader
-// issues a group's loads one iteration before it writes them to LDS, so a
-// load round trip overlaps a whole group of compute instead of delaying the
-// group's barrier (rows whose chunks need separate column offsets and do not
-// fit this in registers are staged in batches).  vmcnt is
-// per wave and counts stores as well as loads, so keeping every global load
-// out of the compute waves means they never wait for their own map stores,
-// and the loader only ever waits for its loads.  The loads still queue
-// behind the CU's map stores, so a block covers 32 CW candidates to read
-// each g row as few times as possible.  Block b owns 32 CW candidates and
-// one of nsplit contiguous ranges of frame groups; the splits of a
-// candidate tile run back to back on one XCD (xcd_tile), so the U rows they
-// share are fetched from HBM once.
+// streaming: one loader wave brings the g rows of the next groups of 32
+// frames straight into LDS (global_load_lds, no register round trip) up to
+// four groups ahead, as many as the load counter and LDS hold, while CW
+// compute waves (32 candidates each) multiply the current group and store
+// it.  vmcnt is per wave and counts stores as well as loads, so keeping
+// every global load out of the compute waves means they never wait for their
+// own map stores, and the loader only ever waits for its loads; the
+// barriers are plain s_barrier (a workgroup fence would make the loader
+// drain its loads at every group).  The loads still queue behind the CU's
+// map stores, so a block covers 32 CW candidates to read each g row as few
+// times as possible.  Block b owns 32 CW candidates and one of nsplit
+// contiguous ranges of frame groups; the splits of a candidate tile run back
+// to back on one XCD (xcd_tile), so the U rows they share are fetched from
+// HBM once.
 
-// largest divisor of n that is at most 16: chunks per loader batch
-constexpr int batch_chunks(int n) {
-  int b = n < 16 ? n : 16;
-  while (n % b) --b;
-  return b;
+// s_waitcnt with vmcnt = N and no wait on the other counters (gfx9
+// encoding: vmcnt bits [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8])
+template <int N>
+__device__ inline void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
 template <typename T, int NS, int CW, bool CT>
@@ -1104,8 +1104,12 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
   constexpr int NV = LB / 16;
   constexpr int ROWP = NS * STEP + 16;  // padded LDS row (bytes)
   constexpr int CPR = NS * STEP / 16;   // 16-byte chunks per g row
-  constexpr int PERL = 32 * CPR / 64;   // chunks per loader lane and group
-  constexpr int NBUF = 3;
+  // buffers: the group being multiplied plus up to four in flight, as many
+  // as the load counter (63 loads, NI per group) and 150 KB of LDS allow
+  constexpr int NI = (32 * (CPR + 1) + 63) / 64;  // loads per group (a row's pad unit included)
+  constexpr int DV = 1 + 63 / NI;
+  constexpr int DL = (150 * 1024) / (32 * ROWP) - 1;
+  constexpr int NBUF = 1 + (DV < DL ? (DV < 4 ? DV : 4) : (DL < 4 ? DL : 4));
   __shared__ __attribute__((aligned(16))) unsigned char gs[NBUF][32 * ROWP];
   int jt, sp;
   if (!xcd_tile(njt, nsplit, jt, sp)) return;
@@ -1116,90 +1120,61 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
   if (ng <= 0) return;  // block-uniform
 
   if (wave == CW) {
-    // loader.  With a chunk table (CT: dense-window SSPI) the 16-byte chunks of
-    // a row come from the columns the table gives for this candidate tile
-    // (-1: zeros).  Byte offsets within a row fit 32 bits: rows are at most
-    // 1 KB and table columns index the PNA < 2^30 samples of a frame.
+    // loader: direct loads into LDS, D = NBUF - 1 groups in flight.  Load k
+    // of a group fills 16-byte slots 64 k .. 64 k + 63 of its buffer (lane
+    // l: slot 64 k + l).  A row's pad unit and the chunks of table entry -1
+    // are filled from the row's first chunk (finite samples; entry -1 meets
+    // zero weights), so that only lanes past the buffer are masked, every
+    // load has an active lane, each group counts exactly NI loads and the
+    // waits below are exact.
     const unsigned char* gb = reinterpret_cast<const unsigned char*>(g);
-    // one column offset per lane when a row's chunks tile the 64 lanes
-    constexpr bool ONE_CB = 64 % CPR == 0;
-    constexpr int NCB = ONE_CB ? 1 : PERL;
-    int32_t cb[NCB];
+    constexpr int SLOTS = 32 * (CPR + 1);
+    constexpr int D = NBUF - 1;
+    static_assert((D - 1) * NI < 64, "vmcnt holds at most 63 loads");
+    int32_t dcol[NI];
+    int drow[NI];
 #pragma unroll
-    for (int k = 0; k < NCB; ++k) {
-      const int c = lane + 64 * k;
-      if constexpr (CT)
-        cb[k] = ctab[static_cast<int64_t>(jt) * CPR + c % CPR] * static_cast<int32_t>(sizeof(T));
-      else
-        cb[k] = 16 * (c % CPR);
+    for (int k = 0; k < NI; ++k) {
+      const int q = 64 * k + lane;
+      const int r = q / (CPR + 1), s = q % (CPR + 1);
+      drow[k] = r;
+      dcol[k] = q < SLOTS ? 0 : -1;
+      if (q < SLOTS && s < CPR) {
+        if constexpr (CT) {
+          const int32_t cc = ctab[static_cast<int64_t>(jt) * CPR + s];
+          dcol[k] = cc >= 0 ? cc * static_cast<int32_t>(sizeof(T)) : 0;
+        } else {
+          dcol[k] = 16 * s;
+        }
+      }
     }
-    if constexpr (ONE_CB || PERL <= 16) {
-      // a group's loads are issued one iteration before their LDS writes,
-      // so their latency overlaps a whole group of compute
-      i32x4 v[PERL];
-      auto issue = [&](int i) {
+    auto issue = [&](int i) {
+      unsigned char* base = &gs[i % NBUF][0];
 #pragma unroll
-        for (int k = 0; k < PERL; ++k) {
-          const int c = lane + 64 * k;
-          const int row = (g0 + i) * 32 + c / CPR;
-          const int32_t o = cb[ONE_CB ? 0 : k];
-          v[k] = i32x4{0, 0, 0, 0};
-          if (row < grows && o >= 0)
-            v[k] = *reinterpret_cast<const i32x4*>(gb + static_cast<int64_t>(row) * ldg * sizeof(T) + o);
-        }
-      };
-      auto commit = [&](int i) {
-#pragma unroll
-        for (int k = 0; k < PERL; ++k) {
-          const int c = lane + 64 * k;
-          *reinterpret_cast<i32x4*>(&gs[i % NBUF][(c / CPR) * ROWP + 16 * (c % CPR)]) = v[k];
-        }
-      };
-      issue(0);
-      commit(0);
-      if (ng > 1) {
-        issue(1);
-        commit(1);
+      for (int k = 0; k < NI; ++k) {
+        // rows past the ones g holds repeat its last row (their frames are
+        // never stored)
+        const int row = min((g0 + i) * 32 + drow[k], grows - 1);
+        if (dcol[k] >= 0)
+          __builtin_amdgcn_global_load_lds(
+              (const __attribute__((address_space(1))) void*)(gb + static_cast<int64_t>(row) * ldg * sizeof(T) + dcol[k]),
+              (__attribute__((address_space(3))) void*)(base + 1024 * k), 16, 0, 0);
       }
-      if (ng > 2) issue(2);
-      __syncthreads();
-      for (int i = 0; i < ng; ++i) {
-        // buffer (i + 2) % 3 was last read for group i - 1
-        if (i + 2 < ng) commit(i + 2);
-        if (i + 3 < ng) issue(i + 3);
-        __syncthreads();
+    };
+    for (int i = 0; i < D && i < ng; ++i) issue(i);
+    if (ng >= D)
+      wait_vm<(D - 1) * NI>();
+    else
+      wait_vm<0>();
+    asm volatile("s_barrier" ::: "memory");
+    for (int i = 0; i < ng; ++i) {
+      if (i + D < ng) {
+        issue(i + D);
+        wait_vm<(D - 1) * NI>();  // group i + 1 has landed
+      } else {
+        wait_vm<0>();
       }
-    } else {
-      // long rows whose offsets differ per chunk: batches of at most 16
-      // chunks, each loaded and written before the group's barrier
-      constexpr int PB = batch_chunks(PERL);
-      auto stage = [&](int i) {
-#pragma unroll
-        for (int k0 = 0; k0 < PERL; k0 += PB) {
-          static_assert(PERL % PB == 0, "loader batches must tile the chunks");
-          i32x4 v[PB];
-#pragma unroll
-          for (int k = 0; k < PB; ++k) {
-            const int c = lane + 64 * (k0 + k);
-            const int row = (g0 + i) * 32 + c / CPR;
-            v[k] = i32x4{0, 0, 0, 0};
-            if (row < grows && cb[k0 + k] >= 0)
-              v[k] = *reinterpret_cast<const i32x4*>(gb + static_cast<int64_t>(row) * ldg * sizeof(T) + cb[k0 + k]);
-          }
-#pragma unroll
-          for (int k = 0; k < PB; ++k) {
-            const int c = lane + 64 * (k0 + k);
-            *reinterpret_cast<i32x4*>(&gs[i % NBUF][(c / CPR) * ROWP + 16 * (c % CPR)]) = v[k];
-          }
-        }
-      };
-      stage(0);
-      if (ng > 1) stage(1);
-      __syncthreads();
-      for (int i = 0; i < ng; ++i) {
-        if (i + 2 < ng) stage(i + 2);
-        __syncthreads();
-      }
+      asm volatile("s_barrier" ::: "memory");
     }
     return;
   }
@@ -1219,7 +1194,7 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
       for (int v = 0; v < NV; ++v)
         uf[s][v] = jok ? *reinterpret_cast<const i32x4*>(ur + s * STEP + 16 * v) : i32x4{0, 0, 0, 0};
   }
-  __syncthreads();
+  asm volatile("s_barrier" ::: "memory");
   // element offset of this lane inside a group's rows: row 4 gq, column r32
   // (the host keeps 36 ldz below 2^31)
   const uint32_t loff = static_cast<uint32_t>(4 * gq * ldz + r32);
@@ -1239,13 +1214,17 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
       for (int s = 0; s < NS; ++s) Mfma<T>::run(af[s], uf[s], acc);
     } else {
       // long rows: U alone takes 4 NS registers, so the g fragments are
-      // read step by step (nine waves per block leave 168 per wave)
+      // read CHK steps at a time
+      constexpr int CHK = NS / 2;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        i32x4 af[NV];
+      for (int s0 = 0; s0 < NS; s0 += CHK) {
+        i32x4 af[CHK][NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) af[v] = *reinterpret_cast<const i32x4*>(ar + s * STEP + 16 * v);
-        Mfma<T>::run(af, uf[s], acc);
+        for (int s = 0; s < CHK; ++s)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) af[s][v] = *reinterpret_cast<const i32x4*>(ar + (s0 + s) * STEP + 16 * v);
+#pragma unroll
+        for (int s = 0; s < CHK; ++s) Mfma<T>::run(af[s], uf[s0 + s], acc);
       }
     }
     // rows (frames) 8 (v / 4) + 4 gq + v % 4 of the group, column j0 + r32:
@@ -1263,7 +1242,7 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
         if (l < L) zg[(8 * (v / 4) + (v % 4)) * ldz + loff] = alpha * acc[v];
       }
     }
-    __syncthreads();
+    asm volatile("s_barrier" ::: "memory");
   }
 }
 
@@ -3227,8 +3206,10 @@ WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t 
     off = align256(off + static_cast<size_t>(w.Lpad) * dp.Kc * dsize(hp.dtype));
   }
   if (hp.variant != SRP_FD && hp.variant != SRP_LR) {
+    // lag-major samples [PN][Lpad] (not needed when the band product reads
+    // the iFFT's frame-major samples)
     w.xi = off;
-    off = align256(off + static_cast<size_t>(hp.PN) * w.Lpad * 4);
+    if (!(hp.variant == SRP_SSPI && dp.sspi_band && hp.fft)) off = align256(off + static_cast<size_t>(hp.PN) * w.Lpad * 4);
     w.part = off;
     // frame-major samples of the iFFT kernel, [Lc][PN]
     if (hp.fft) off = align256(off + static_cast<size_t>(w.Lc) * hp.PN * 4);
@@ -3242,8 +3223,8 @@ WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t 
     off = align256(off + static_cast<size_t>(w.Lpad) * 8 * dp.sspi_xw * dsize(hp.dtype));
   }
   if (hp.variant == SRP_SSPI && dp.sspi_band) {
-    w.xf = off;  // frame-major FP16 samples of the band product
-    off = align256(off + static_cast<size_t>(w.Lpad) * dp.sspi_xb * 2);
+    w.xf = off;  // frame-major FP16 samples of the band product, [Lc][sspi_xb]
+    off = align256(off + static_cast<size_t>(w.Lc) * dp.sspi_xb * 2);
   }
   w.total = off;
   return w;

@@ -79,7 +79,8 @@ def test_static_scratch_refuses_oversized_workspace(native):
     """The 496 pairs of the 2 m disc array with 2048-point frames: FD's
     cross-spectra for one 256-row tile take 520 MB in BF16, more than the
     scratch, so the call is refused (and the workspace entry point still
-    runs); SSPI's GCC samples (116,492 lags) take 121 MB and fit."""
+    runs); SSPI's workspace (the frame-major GCC samples of the 4 frames,
+    116,492 lags each) fits."""
     cfg = scenes.workload("disc32_box200k", L=4, grid_stride=10)
     Yt = torch.from_numpy(scenes.make_frames(cfg)).cuda()
     _announce("compute_static disc32 subgrid fd (refused)")
