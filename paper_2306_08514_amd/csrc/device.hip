@@ -417,6 +417,9 @@ __global__ __launch_bounds__(256) void gemm_nt(const GemmBatch* __restrict__ bat
 // ~1e-15); within a slice the bins follow by FP32 rotation by
 // exp(+i pi x / K), a chain of at most BINS - 1 steps.
 //
+// With blockIdx.y the contraction is split at pair boundaries (plans with
+// few candidate tiles), each split writing its partial product.
+//
 // FLUSH (FP32 operands): each pair's products are summed in accumulators of
 // their own and added to the running total at the next pair.  One FP32
 // accumulator over the whole contraction (2 P (K - 1) terms, 1.0e6 on the
@@ -426,7 +429,7 @@ template <typename T, int BX, int WGX, bool FLUSH = false>
 __global__ __launch_bounds__(256) void fd_gen(const T* __restrict__ X, int64_t ldx,
                                               const double* __restrict__ xg, int64_t J, int K, int Kp,
                                               float* __restrict__ C, int64_t ldc, int nx, int kdim, float alpha,
-                                              int nw_tiles, int nx_tiles) {
+                                              int nw_tiles, int nx_tiles, int pps, int64_t cz_rows) {
   constexpr int BW = 256, BKB = 128;  // 256 candidates: one generated row per thread (189 -> 168 ms on the 2 m disc)
   constexpr int STEP = Mfma<T>::STEP;
   constexpr int LB = STEP / 2;
@@ -490,13 +493,17 @@ __global__ __launch_bounds__(256) void fd_gen(const T* __restrict__ X, int64_t l
         for (int v = 0; v < 16; ++v) tot[a][b][v] = 0.0f;
   }
 
-  const int kbytes = kdim * static_cast<int>(sizeof(T));
+  // split blockIdx.y of the contraction: pairs [y pps, (y + 1) pps), its
+  // partial product to rows [y cz_rows, ...) of C
+  const int kb0 = static_cast<int>(blockIdx.y) * pps * Kp * static_cast<int>(sizeof(T));
+  const int kbytes = min(kdim, (static_cast<int>(blockIdx.y) + 1) * pps * Kp) * static_cast<int>(sizeof(T));
+  C += static_cast<int64_t>(blockIdx.y) * cz_rows * ldc;
   double gx = 0.0, gs_c = 1.0, gs_s = 0.0, gadv_c = 1.0, gadv_s = 0.0;  // generator state
   float gstep_c = 1.0f, gstep_s = 0.0f;
-  gload(0);
-  for (int kb = 0; kb < kbytes; kb += BKB) {
+  gload(kb0);
+  for (int kb = kb0; kb < kbytes; kb += BKB) {
     if constexpr (FLUSH) {
-      if (kb > 0 && (kb / static_cast<int>(sizeof(T))) % Kp == 0) {  // a new pair: uniform over the block
+      if (kb > kb0 && (kb / static_cast<int>(sizeof(T))) % Kp == 0) {  // a new pair: uniform over the block
 #pragma unroll
         for (int a = 0; a < NBX; ++a)
 #pragma unroll
@@ -2868,6 +2875,12 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
       if (hp.dtype == SRP_F64) throw Error{SRP_E_UNSUPPORTED, "FP64 FD needs the resident steering operand"};
       dp.d_xg = static_cast<double*>(A.get(hp.x.size() * sizeof(double)));
       upload(dp.d_xg, hp.x);
+      // few candidate tiles: split the contraction at pair boundaries so that
+      // a frame tile has ~512 blocks (up to 8 splits of at least 4 pairs)
+      const int64_t nwt = (hp.J + 255) / 256;
+      int ks = 1;
+      while (ks < 8 && nwt * ks * 2 <= 512 && P / (ks * 2) >= 4) ks *= 2;
+      dp.fd_ksplit = ks;
       return;
     }
     dp.d_H = A.get(hbytes);
@@ -3332,31 +3345,46 @@ void tall_split(DevicePlan& dp, const void* kern, int threads, int njt, int ngro
 // batches, 64-frame tiles (waves 1 x 4) for small ones.
 template <typename T>
 void launch_fd_gen(const HostPlan& hp, DevicePlan& dp, const void* psi, int64_t ldpsi, int64_t kfd, float* z,
-                   int64_t ldz, int64_t Lc, hipStream_t st) {
+                   int64_t ldz, int64_t Lc, int64_t Lpad, float* part, hipStream_t st) {
   const int nw = static_cast<int>((hp.J + 255) / 256);  // fd_gen's 256-candidate tiles
   const int kdim = static_cast<int>(kfd);
+  // split contraction (a plan constant, so a frame's map does not depend on
+  // its batch): partial products into the workspace, then a fixed-order
+  // reduction
+  const int ks = dp.fd_ksplit;
+  const int pps = (hp.P + ks - 1) / ks;
+  float* c = ks > 1 ? part : z;
+  const int64_t ldc = ks > 1 ? dp.Jpad : ldz;
+  const float alpha = ks > 1 ? 1.0f : 2.0f;
   if constexpr (std::is_same<T, float>::value) {
     // FP32: 64-frame tiles at every batch size, with per-pair accumulators
     // (the FP32 matrix cores, not the tile's operand reuse, bound this form)
     const int nxt = static_cast<int>((Lc + 63) / 64);
     const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(nw) * nxt, 8));
     TRACED(dp, "fd_gen", st,
-           hipLaunchKernelGGL((fd_gen<T, 64, 1, true>), dim3(blocks), dim3(256), 0, st, static_cast<const T*>(psi),
-                              ldpsi, dp.d_xg, hp.J, hp.K, dp.Kp, z, ldz, static_cast<int>(Lc), kdim, 2.0f, nw, nxt));
-    return;
-  }
-  if (Lc > 128) {
+           hipLaunchKernelGGL((fd_gen<T, 64, 1, true>), dim3(blocks, ks), dim3(256), 0, st,
+                              static_cast<const T*>(psi), ldpsi, dp.d_xg, hp.J, hp.K, dp.Kp, c, ldc,
+                              static_cast<int>(Lc), kdim, alpha, nw, nxt, pps, Lpad));
+  } else if (Lc > 128) {
     const int nxt = static_cast<int>((Lc + 255) / 256);
     const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(nw) * nxt, 8));
     TRACED(dp, "fd_gen", st,
-           hipLaunchKernelGGL((fd_gen<T, 256, 2>), dim3(blocks), dim3(256), 0, st, static_cast<const T*>(psi), ldpsi,
-                              dp.d_xg, hp.J, hp.K, dp.Kp, z, ldz, static_cast<int>(Lc), kdim, 2.0f, nw, nxt));
+           hipLaunchKernelGGL((fd_gen<T, 256, 2>), dim3(blocks, ks), dim3(256), 0, st, static_cast<const T*>(psi),
+                              ldpsi, dp.d_xg, hp.J, hp.K, dp.Kp, c, ldc, static_cast<int>(Lc), kdim, alpha, nw, nxt,
+                              pps, Lpad));
   } else {
     const int nxt = static_cast<int>((Lc + 63) / 64);
     const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(nw) * nxt, 8));
     TRACED(dp, "fd_gen", st,
-           hipLaunchKernelGGL((fd_gen<T, 64, 1>), dim3(blocks), dim3(256), 0, st, static_cast<const T*>(psi), ldpsi,
-                              dp.d_xg, hp.J, hp.K, dp.Kp, z, ldz, static_cast<int>(Lc), kdim, 2.0f, nw, nxt));
+           hipLaunchKernelGGL((fd_gen<T, 64, 1>), dim3(blocks, ks), dim3(256), 0, st, static_cast<const T*>(psi),
+                              ldpsi, dp.d_xg, hp.J, hp.K, dp.Kp, c, ldc, static_cast<int>(Lc), kdim, alpha, nw, nxt,
+                              pps, Lpad));
+  }
+  if (ks > 1) {
+    const int64_t n = Lc * hp.J;
+    TRACED(dp, "split_reduce", st,
+           hipLaunchKernelGGL(split_reduce, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, part, ks,
+                              Lpad, dp.Jpad, static_cast<int>(Lc), hp.J, 2.0f, z, ldz));
   }
 }
 
@@ -3651,11 +3679,12 @@ void device_compute(const HostPlan& hp, DevicePlan& dp, const void* frames, int6
       }
       float* z = static_cast<float*>(maps) + l0 * ldm;
       if (dp.fd_gen) {
+        float* part = reinterpret_cast<float*>(base + lay.part);
         switch (hp.dtype) {
-          case SRP_F32: launch_fd_gen<float>(hp, dp, psi, ldpsi, kfd, z, ldm, Lc, st); break;
-          case SRP_BF16: launch_fd_gen<__bf16>(hp, dp, psi, ldpsi, kfd, z, ldm, Lc, st); break;
-          case SRP_F16: launch_fd_gen<_Float16>(hp, dp, psi, ldpsi, kfd, z, ldm, Lc, st); break;
-          case SRP_FP8_E4M3: launch_fd_gen<fp8>(hp, dp, psi, ldpsi, kfd, z, ldm, Lc, st); break;
+          case SRP_F32: launch_fd_gen<float>(hp, dp, psi, ldpsi, kfd, z, ldm, Lc, lay.Lpad, part, st); break;
+          case SRP_BF16: launch_fd_gen<__bf16>(hp, dp, psi, ldpsi, kfd, z, ldm, Lc, lay.Lpad, part, st); break;
+          case SRP_F16: launch_fd_gen<_Float16>(hp, dp, psi, ldpsi, kfd, z, ldm, Lc, lay.Lpad, part, st); break;
+          case SRP_FP8_E4M3: launch_fd_gen<fp8>(hp, dp, psi, ldpsi, kfd, z, ldm, Lc, lay.Lpad, part, st); break;
         }
         continue;
       }

@@ -42,18 +42,22 @@ def setup():
 
 
 @pytest.mark.parametrize("M", [4, 8, 16, 32])
-@pytest.mark.parametrize("variant,rq", [("fd", 0), ("slri", 8), ("sspi", 4), ("sspi", 7)])
+@pytest.mark.parametrize("variant,rq", [("fd", 0), ("fdgen", 0), ("slri", 8), ("sspi", 4), ("sspi", 7)])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_maps_do_not_depend_on_the_frame_slot(M, variant, rq, dtype):
     """A frame's map is bitwise the same whatever its position in the batch
-    (tile slot, tile index, chunk): the property continuous batching needs."""
+    (tile slot, tile index, chunk): the property continuous batching needs.
+    fdgen: conv. FD-SRP with generated steering, whose contraction is split
+    over pairs on this small grid."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2306_08514_amd import native
     print(f"[gpu-case] slot invariance M={M} {variant} {rq} {dtype}", flush=True)
     mics, fs, N = scenes.serving_array(M)
     pool = torch.from_numpy(scenes.serving_frames(M, L=96)).cuda()
-    p = native.Plan(mics, scenes.serving_grid(1024), fs, N, variant, rq, dtype=dtype, frame_tile=64)
+    kw = {"fd_steering": "generated"} if variant == "fdgen" else {}
+    p = native.Plan(mics, scenes.serving_grid(1024), fs, N, "fd" if variant == "fdgen" else variant, rq,
+                    dtype=dtype, frame_tile=64, **kw)
     ref = p.compute(pool[10:30].contiguous())
     for lo, hi in ((0, 10), (3, 10), (17, 10), (46, 5), (0, 57)):
         # 20 frames at offset `lo` (+ `hi` more after them) in one call
