@@ -126,7 +126,11 @@ typedef struct {
                             J x PN Lambda of (43) instead of one fit per
                             pair (0, the default).  SLRI (54): one rank-R
                             truncated SVD, rank_or_q = R_Lambda, the total
-                            rank (PN <= 4096).  SSPI (55): the Q_Lambda =
+                            rank: exact through the PN x PN Gram matrix for
+                            PN <= 4096, by FP64 randomized subspace
+                            iteration on the device above (host-only plans:
+                            PN <= 4096); 2: SLRI by the randomized fit at
+                            any PN.  SSPI (55): the Q_Lambda =
                             rank_or_q * J * P largest-magnitude entries
                             (rank_or_q = mean taps per location and pair;
                             every entry at or above the Q_Lambda-th largest
@@ -279,7 +283,9 @@ srp_status srp_plan_info_get(srp_plan_t plan, srp_plan_info* info);
  *          "lr_s"     double [R_H]   the R_H largest singular values of H
  *                                      (LR-SRP)
  * With global_fit, "slri_u" is [J][R_Lambda], "slri_v" [PN][R_Lambda] and
- * "slri_s" [PN] (the stacked fit of (54)); global SSPI exports its variable
+ * "slri_s" [PN] (the stacked fit of (54); the randomized fit reports its
+ * l = R + max(16, R / 8) (rounded up to 64) leading values and zeros past
+ * them); global SSPI exports its variable
  * windows in the same [J][P][Q] layout, Q the widest window.
  * "tdoa", "slri_u", "sspi_start" and "sspi_w" are kept only by host-only
  * plans (device = -1): a device plan fits these on the device and frees the

@@ -113,9 +113,11 @@ srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J, do
   if (o.frame_tile < 1) return fail(SRP_E_INVALID, "frame_tile must be >= 1");
   if (o.sampling < 0 || o.sampling > 2) return fail(SRP_E_INVALID, "sampling must be 0, 1 or 2");
   if (o.fd_steering < 0 || o.fd_steering > 2) return fail(SRP_E_INVALID, "fd_steering must be 0, 1 or 2");
-  if (o.global_fit != 0 && o.global_fit != 1) return fail(SRP_E_INVALID, "global_fit must be 0 or 1");
+  if (o.global_fit < 0 || o.global_fit > 2) return fail(SRP_E_INVALID, "global_fit must be 0, 1 or 2");
   if (o.global_fit && variant != SRP_SLRI && variant != SRP_SSPI)
     return fail(SRP_E_INVALID, "global_fit applies to SLRI and SSPI only");
+  if (o.global_fit == 2 && variant != SRP_SLRI)
+    return fail(SRP_E_INVALID, "global_fit 2 (randomized fit) applies to SLRI only");
   if (variant == SRP_SLRI && !o.global_fit && rank_or_q > 32)
     return fail(SRP_E_UNSUPPORTED, "SLRI rank per pair above 32 is not built");
   if (variant == SRP_SSPI && rank_or_q > 16) return fail(SRP_E_UNSUPPORTED, "SSPI with Q above 16 is not built");
@@ -136,6 +138,7 @@ srp_status srp_plan(const double* mics, int M, const double* grid, int64_t J, do
     hp.device_fit = o.device >= 0;
     hp.fd_steering = o.fd_steering;
     hp.global_fit = o.global_fit != 0;
+    hp.global_rand = o.global_fit == 2;
     if (variant == SRP_SLRI && hp.global_fit) srp::build_slri_global(hp, rank_or_q, plan_threads());
     if (variant == SRP_SLRI && !hp.global_fit) srp::build_slri(hp, rank_or_q, plan_threads());
     if (variant == SRP_SI) srp::build_slri(hp, 2 * hp.max_np + 1, plan_threads());

@@ -2105,6 +2105,127 @@ __global__ __launch_bounds__(256) void slri_u_global_f64(const double* __restric
   }
 }
 
+// C = Lambda B (TR = false: M = J candidates, K = stacked lags) or
+// C = Lambda^T B (TR = true: M = stacked lags, K = candidates) in FP64 on
+// v_mfma_f64_16x16x4_f64, with Lambda[j][a] = sinc(x_p(j) - n) of (43)
+// generated in registers: the products of the randomized global fit.  The
+// stacked lag axis is padded per pair to 16-slot chunks (chunk c: pair
+// cpair[c], lags clag0[c] .. clag0[c] + 15, valid up to N_p = cnp[c];
+// padding slots are zero), so a 16-deep K chunk (TR = false) or a 16-row
+// group (TR = true) belongs to one pair.  Block = one 64 x 64 tile of C,
+// four waves of 32 x 32 (2 x 2 MFMA tiles); B rows staged through LDS per
+// 16-deep chunk.  TR = false: each lane forms x, its rounding and
+// sin(pi r) once per chunk for its two rows; TR = true: the chunk's
+// (x, k0, sin pi r) for each row group's pair and each of the 16
+// candidates are formed once in LDS.  Lane i supplies row i % 16 and k slot
+// i / 16 of each 4-deep step; accumulator register v of lane i holds row
+// 4 v + i / 16, column i % 16.  Rows of B past K hold zeros.
+template <bool TR>
+__global__ __launch_bounds__(256) void lam_gemm_f64(const double* __restrict__ x, int64_t J,
+                                                    const int32_t* __restrict__ cpair,
+                                                    const int32_t* __restrict__ clag0,
+                                                    const int32_t* __restrict__ cnp, int64_t M, int64_t Kd,
+                                                    const double* __restrict__ B, int64_t ldb,
+                                                    double* __restrict__ C, int64_t ldc, int ntn) {
+  __shared__ double bs[16][64 + 2];
+  __shared__ double gxs[4][16], gks[4][16], gss[4][16];
+  const int tn = static_cast<int>(blockIdx.x % ntn);
+  const int64_t m0 = static_cast<int64_t>(blockIdx.x / ntn) * 64;
+  const int n0 = tn * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int r16 = lane & 15, kq = lane >> 4;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.0;
+  // TR: this lane's two rows (stacked slots): pair and lag, fixed
+  int tpair[2] = {0, 0}, tlag[2] = {0, 0};
+  bool tval[2] = {false, false};
+  if constexpr (TR) {
+#pragma unroll
+    for (int ms = 0; ms < 2; ++ms) {
+      const int64_t a = m0 + wm * 32 + ms * 16 + r16;
+      if (a < M) {
+        const int64_t c = a / 16;
+        tpair[ms] = cpair[c];
+        tlag[ms] = clag0[c] + static_cast<int>(a % 16);
+        tval[ms] = tlag[ms] <= cnp[c];
+      }
+    }
+  }
+  for (int64_t k0 = 0; k0 < Kd; k0 += 16) {
+    __syncthreads();
+    {
+      const int r = tid >> 4, cc = 4 * (tid & 15);
+      const double* src = B + (k0 + r) * ldb + n0 + cc;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bs[r][cc + e] = src[e];
+    }
+    double xv[2] = {0.0, 0.0}, kr[2] = {0.0, 0.0}, sr[2] = {0.0, 0.0};
+    int lag0 = 0, npp = 0;
+    if constexpr (!TR) {
+      const int64_t c = k0 / 16;
+      const int p = cpair[c];
+      lag0 = clag0[c];
+      npp = cnp[c];
+#pragma unroll
+      for (int ms = 0; ms < 2; ++ms) {
+        const int64_t j = m0 + wm * 32 + ms * 16 + r16;
+        xv[ms] = j < J ? x[static_cast<int64_t>(p) * J + j] : 0.0;
+        kr[ms] = rint(xv[ms]);
+        sr[ms] = sin(M_PI * (xv[ms] - kr[ms]));
+      }
+    } else {
+      if (tid < 64) {
+        const int g = tid >> 4, jj = tid & 15;
+        const int64_t a = m0 + 16 * g, j = k0 + jj;
+        double v = 0.0;
+        if (a < M && j < J) v = x[static_cast<int64_t>(cpair[a / 16]) * J + j];
+        gxs[g][jj] = v;
+        gks[g][jj] = rint(v);
+        gss[g][jj] = sin(M_PI * (v - rint(v)));
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int ms = 0; ms < 2; ++ms) {
+        if constexpr (!TR) {
+          const int64_t j = m0 + wm * 32 + ms * 16 + r16;
+          const int n = lag0 + 4 * s + kq;
+          av[ms] = (j < J && n <= npp) ? sinc_red(xv[ms], kr[ms], sr[ms], n) : 0.0;
+        } else {
+          const int g = 2 * wm + ms, jj = 4 * s + kq;
+          av[ms] = (tval[ms] && k0 + jj < J) ? sinc_red(gxs[g][jj], gks[g][jj], gss[g][jj], tlag[ms]) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int ns = 0; ns < 2; ++ns) bv[ns] = bs[4 * s + kq][wn * 32 + ns * 16 + r16];
+#pragma unroll
+      for (int ms = 0; ms < 2; ++ms)
+#pragma unroll
+        for (int ns = 0; ns < 2; ++ns)
+          acc[ms][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ms], bv[ns], acc[ms][ns], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int ms = 0; ms < 2; ++ms)
+#pragma unroll
+    for (int ns = 0; ns < 2; ++ns)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = m0 + wm * 32 + ms * 16 + 4 * v + kq;
+        const int col = n0 + wn * 32 + ns * 16 + r16;
+        if (row < M) C[row * ldc + col] = acc[ms][ns][v];
+      }
+}
+
 // max |U_p| over the staged columns of pair p (per-pair FP8 scale).
 __global__ __launch_bounds__(256) void pair_absmax(const float* __restrict__ Us, int64_t J, int Kc, int R,
                                                    float* __restrict__ out) {
@@ -2408,9 +2529,24 @@ int host_threads() {
 // partial sums added on the host), its eigenvectors on the host, then
 // U = Lambda V on the device; a single FP8 weight scale and activation
 // scale, as for one pair.
+static void fit_slri_global_rand(HostPlan& hp, const double* dx);
+static void fit_slri_global_gram(HostPlan& hp, const double* dx);
+static void build_slri_global_operands(HostPlan& hp, DevicePlan& dp, Alloc& A, const double* dx);
+
 static void build_slri_global_device(HostPlan& hp, DevicePlan& dp, Alloc& A, const double* dx) {
   const int PN = hp.PN, R = hp.R, P = hp.P;
   if (2 * hp.max_np + 1 > 576) throw Error{SRP_E_UNSUPPORTED, "global SLRI stages at most 576 lags per pair"};
+  if (hp.global_rand)
+    fit_slri_global_rand(hp, dx);
+  else
+    fit_slri_global_gram(hp, dx);
+  build_slri_global_operands(hp, dp, A, dx);
+}
+
+// V and the singular values of the global fit from the PN x PN Gram matrix
+// (exact, PN <= 4096).
+static void fit_slri_global_gram(HostPlan& hp, const double* dx) {
+  const int PN = hp.PN, P = hp.P;
   std::vector<int32_t> pa(PN), la(PN);
   for (int p = 0; p < P; ++p)
     for (int i = 0; i < 2 * hp.np[p] + 1; ++i) {
@@ -2443,6 +2579,11 @@ static void build_slri_global_device(HostPlan& hp, DevicePlan& dp, Alloc& A, con
   });
   std::vector<double>().swap(gall);
   slri_fit_global(hp, G);
+}
+
+// U = Lambda V and the runtime operands of the global fit from hp.V.
+static void build_slri_global_operands(HostPlan& hp, DevicePlan& dp, Alloc& A, const double* dx) {
+  const int PN = hp.PN, R = hp.R, P = hp.P;
   // U = Lambda V, staged in FP32 as [Jpad][Kc]
   const size_t ucount = static_cast<size_t>(dp.Jpad) * dp.Kc;
   TmpBuf dv(hp.V.size() * sizeof(double));
@@ -2523,6 +2664,134 @@ struct Blas {
 static void blas_ok(rocblas_status st, const char* what) {
   if (st != rocblas_status_success)
     throw Error{SRP_E_HIP, std::string(what) + " failed: " + rocblas_status_to_string(st)};
+}
+
+// Global SLRI fit (54) by randomized subspace iteration (Halko, Martinsson
+// and Tropp, SIAM Review 53 (2011), Alg. 4.4 with the SVD of Alg. 5.1), for
+// stacked Lambda too wide for the Gram eigendecomposition: with l = R + p
+// columns (p = max(16, R / 8), l rounded up to 64), Omega Gaussian (seeded),
+//   Y = Lambda Omega, Q = orth(Y); q = 2 times: Z = orth(Lambda^T Q),
+//   Q = orth(Lambda Z); then B^T = Lambda^T Q (PN x l) and the eigenpairs
+// (W, sigma^2) of B B^T give V = B^T W sigma^-1 and the singular values.
+// Every product runs in FP64 with Lambda generated (lam_gemm_f64); orth is
+// the Householder LQ of the l x n row block (rocSOLVER dgelqf / dorglq),
+// B B^T by rocBLAS dsyrk, its eigenpairs by rocSOLVER dsyevd.  The
+// singular values past the l computed are reported as zero.
+static void fit_slri_global_rand(HostPlan& hp, const double* dx) {
+  const int P = hp.P, PN = hp.PN, R = hp.R;
+  const int64_t J = hp.J;
+  // stacked lags padded to 16-slot chunks per pair
+  std::vector<int32_t> cpair, clag0, cnp, pbase(P);
+  for (int p = 0; p < P; ++p) {
+    pbase[p] = static_cast<int32_t>(16 * cpair.size());
+    const int n = 2 * hp.np[p] + 1;
+    for (int c = 0; c < (n + 15) / 16; ++c) {
+      cpair.push_back(p);
+      clag0.push_back(-hp.np[p] + 16 * c);
+      cnp.push_back(hp.np[p]);
+    }
+  }
+  const int64_t PNA = 16 * static_cast<int64_t>(cpair.size());
+  // l sample columns: R plus oversampling, at most the rows of either side
+  const int l = static_cast<int>(
+      std::min<int64_t>(round_up(R + std::max(16, R / 8), 64), std::min<int64_t>(PNA, J) / 64 * 64));
+  if (l < R) throw Error{SRP_E_UNSUPPORTED, "randomized global SLRI needs R well below PN and J"};
+  const int64_t Jk = round_up(J, 64);  // rows of Y / Q (zeros past J)
+  TmpBuf dcp(cpair.size() * 4), dcl(clag0.size() * 4), dcn(cnp.size() * 4);
+  upload(static_cast<int32_t*>(dcp.p), cpair);
+  upload(static_cast<int32_t*>(dcl.p), clag0);
+  upload(static_cast<int32_t*>(dcn.p), cnp);
+  TmpBuf dy(static_cast<size_t>(Jk) * l * 8), dz(static_cast<size_t>(PNA) * l * 8);
+  HIP_OK(hipMemset(dy.p, 0, static_cast<size_t>(Jk) * l * 8));
+  // Omega [PNA][l]: standard normal by Box-Muller from a seeded 64-bit
+  // generator; padding rows zero
+  {
+    std::vector<double> om(static_cast<size_t>(PNA) * l, 0.0);
+    uint64_t st = 0x9E3779B97F4A7C15ull;
+    auto next = [&]() {  // splitmix64
+      st += 0x9E3779B97F4A7C15ull;
+      uint64_t zz = st;
+      zz = (zz ^ (zz >> 30)) * 0xBF58476D1CE4E5B9ull;
+      zz = (zz ^ (zz >> 27)) * 0x94D049BB133111EBull;
+      return zz ^ (zz >> 31);
+    };
+    for (int p = 0; p < P; ++p)
+      for (int i = 0; i < 2 * hp.np[p] + 1; ++i) {
+        double* row = &om[static_cast<size_t>(pbase[p] + i) * l];
+        for (int c = 0; c < l; c += 2) {
+          const double u1 = (static_cast<double>(next() >> 11) + 0.5) * 0x1p-53;
+          const double u2 = static_cast<double>(next() >> 11) * 0x1p-53;
+          const double rr = std::sqrt(-2.0 * std::log(u1));
+          row[c] = rr * std::cos(2.0 * M_PI * u2);
+          if (c + 1 < l) row[c + 1] = rr * std::sin(2.0 * M_PI * u2);
+        }
+      }
+    upload(dz.as<double>(), om);
+  }
+  const int ntn = l / 64;
+  auto lam = [&](const double* Bm, double* Cm) {  // Y = Lambda Z
+    hipLaunchKernelGGL(lam_gemm_f64<false>, dim3(static_cast<unsigned>((J + 63) / 64 * ntn)), dim3(256), 0, 0, dx, J,
+                       dcp.as<int32_t>(), dcl.as<int32_t>(), dcn.as<int32_t>(), J, PNA, Bm,
+                       static_cast<int64_t>(l), Cm, static_cast<int64_t>(l), ntn);
+    check_launch("lam_gemm_f64");
+  };
+  auto lamt = [&](const double* Bm, double* Cm) {  // Z = Lambda^T Y
+    hipLaunchKernelGGL(lam_gemm_f64<true>, dim3(static_cast<unsigned>(PNA / 64 * ntn + (PNA % 64 ? ntn : 0))),
+                       dim3(256), 0, 0, dx, J, dcp.as<int32_t>(), dcl.as<int32_t>(), dcn.as<int32_t>(), PNA,
+                       round_up(J, 16), Bm, static_cast<int64_t>(l), Cm, static_cast<int64_t>(l), ntn);
+    check_launch("lam_gemm_f64");
+  };
+  Blas blas;
+  TmpBuf tau(static_cast<size_t>(l) * 8);
+  // orthonormal basis of the column space of the n x l matrix held
+  // row-major [n][l] (= the column-major l x n matrix A): A = L Q' (LQ),
+  // Q' overwrites A
+  auto orth = [&](double* Am, int64_t n) {
+    blas_ok(rocsolver_dgelqf(blas.h, l, static_cast<rocblas_int>(n), Am, l, tau.as<double>()), "rocsolver_dgelqf");
+    blas_ok(rocsolver_dorglq(blas.h, l, static_cast<rocblas_int>(n), l, Am, l, tau.as<double>()), "rocsolver_dorglq");
+  };
+  lam(dz.as<double>(), dy.as<double>());
+  orth(dy.as<double>(), J);
+  for (int it = 0; it < 2; ++it) {
+    lamt(dy.as<double>(), dz.as<double>());
+    orth(dz.as<double>(), PNA);
+    lam(dz.as<double>(), dy.as<double>());
+    orth(dy.as<double>(), J);
+  }
+  lamt(dy.as<double>(), dz.as<double>());  // B^T = Lambda^T Q, [PNA][l]
+  TmpBuf dg(static_cast<size_t>(l) * l * 8), dd(static_cast<size_t>(l) * 8), de(static_cast<size_t>(l) * 8),
+      dinfo(sizeof(rocblas_int));
+  const double one = 1.0, zero = 0.0;
+  blas_ok(rocblas_dsyrk(blas.h, rocblas_fill_upper, rocblas_operation_none, l, static_cast<rocblas_int>(PNA), &one,
+                        dz.as<double>(), l, &zero, dg.as<double>(), l),
+          "rocblas_dsyrk");
+  blas_ok(rocsolver_dsyevd(blas.h, rocblas_evect_original, rocblas_fill_upper, l, dg.as<double>(), l,
+                           dd.as<double>(), de.as<double>(), dinfo.as<rocblas_int>()),
+          "rocsolver_dsyevd");
+  rocblas_int info = 0;
+  HIP_OK(hipMemcpy(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost));
+  if (info != 0) throw Error{SRP_E_HIP, "rocsolver_dsyevd did not converge (info " + std::to_string(info) + ")"};
+  // V^T (R x PNA, column-major) = W_R^T B^T with W_R the eigenvectors of
+  // the R largest eigenvalues (the last R columns, ascending order)
+  TmpBuf dvt(static_cast<size_t>(R) * PNA * 8);
+  blas_ok(rocblas_dgemm(blas.h, rocblas_operation_transpose, rocblas_operation_none, R,
+                        static_cast<rocblas_int>(PNA), l, &one, dg.as<double>() + static_cast<size_t>(l - R) * l, l,
+                        dz.as<double>(), l, &zero, dvt.as<double>(), R),
+          "rocblas_dgemm");
+  std::vector<double> ev(l), vt(static_cast<size_t>(R) * PNA);
+  HIP_OK(hipMemcpy(ev.data(), dd.p, ev.size() * 8, hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(vt.data(), dvt.p, vt.size() * 8, hipMemcpyDeviceToHost));
+  std::fill(hp.sv.begin(), hp.sv.end(), 0.0);
+  for (int i = 0; i < l && i < PN; ++i) hp.sv[i] = std::sqrt(std::max(0.0, ev[l - 1 - i]));
+  // column r of V (descending sigma) is row R - 1 - r of V^T, over sigma_r
+  for (int p = 0; p < P; ++p)
+    for (int i = 0; i < 2 * hp.np[p] + 1; ++i) {
+      const size_t a = static_cast<size_t>(hp.off[p] + i), ap = static_cast<size_t>(pbase[p] + i);
+      for (int r = 0; r < R; ++r) {
+        const double sg = hp.sv[r];
+        hp.V[a * R + r] = sg > 0 ? vt[ap * R + (R - 1 - r)] / sg : 0.0;
+      }
+    }
 }
 
 static void build_lr_device(HostPlan& hp, DevicePlan& dp, Alloc& A, const double* dx) {

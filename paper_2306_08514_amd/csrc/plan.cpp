@@ -418,8 +418,13 @@ void slri_fit_global(HostPlan& hp, std::vector<double>& G) {
 void build_slri_global(HostPlan& hp, int R, int threads) {
   if (R < 1) fail("rank must be >= 1");
   const int n = hp.PN;
-  if (n > 4096)
-    throw Error{SRP_E_UNSUPPORTED, "global SLRI decomposes the PN x PN Gram matrix; PN above 4096 is not built"};
+  // the exact fit decomposes the PN x PN Gram matrix; wider stacks take the
+  // randomized fit on the device
+  if (n > 4096) hp.global_rand = true;
+  if (hp.global_rand && !hp.device_fit)
+    throw Error{SRP_E_UNSUPPORTED,
+                "host-only plans fit the global SLRI through the Gram matrix (PN <= 4096); the randomized fit runs "
+                "on the device"};
   hp.R = std::min(R, n);
   hp.rp.assign(hp.P, 0);
   hp.V.assign(static_cast<size_t>(n) * hp.R, 0.0);

@@ -63,6 +63,7 @@ struct HostPlan {
   int fd_steering = 0;      // FD steering operand: 0 auto, 1 resident, 2 generated
   bool far_field = false;   // grid rows are unit directions (far-field TDOAs)
   bool global_fit = false;  // SLRI: one rank-R fit of the stacked Lambda (54); SSPI: global top-Q_Lambda (55)
+  bool global_rand = false;  // SLRI global fit by randomized subspace iteration (device plans)
 
   double macs_per_map = 0;
 };

@@ -154,7 +154,9 @@ class Plan:
     fd_steering in {"auto", "resident", "generated"} the FD steering operand;
     far_field=True reads the grid rows as unit source directions;
     global_fit=True selects the global forms: SLRI with rank_or_q = the
-    total rank R_Lambda, SSPI with Q_Lambda = rank_or_q J P kept entries."""
+    total rank R_Lambda, SSPI with Q_Lambda = rank_or_q J P kept entries;
+    global_fit="randomized" fits the global SLRI by randomized subspace
+    iteration at any PN (the form used above PN = 4096)."""
 
     SAMPLING = {"auto": 0, "direct": 1, "fft": 2}
     STEERING = {"auto": 0, "resident": 1, "generated": 2}
@@ -172,7 +174,7 @@ class Plan:
         o.sampling = self.SAMPLING[sampling]
         o.fd_steering = self.STEERING[fd_steering]
         o.far_field = 1 if far_field else 0
-        o.global_fit = 1 if global_fit else 0
+        o.global_fit = 2 if global_fit == "randomized" else (1 if global_fit else 0)
         h = ctypes.c_void_p()
         self._h = None
         self._mics_ref = mics
