@@ -69,6 +69,8 @@ def parse():
                     help="skip the sweep: comma list name=setting, e.g. slri=21,sspi=3,slri_global=224,sspi_global=2")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
+    ap.add_argument("--la-forms", default="slri,sspi,slri_global,fd",
+                    help="forms of the large-aperture leg (comma list of slri, sspi, slri_global, fd)")
     ap.add_argument("--large-aperture-only", action="store_true",
                     help="run only the large-aperture leg and print its record (for profiling)")
     return ap.parse_args()
@@ -339,12 +341,13 @@ def bench_other_forms(cfg, Yt, steps):
     return out
 
 
-def bench_disc32(steps):
+def bench_disc32(steps, forms=("slri", "sspi", "slri_global", "fd")):
     """Large-aperture leg: disc32_box200k (M = 32, 496 pairs, up to 499 lags,
-    J = 200,000, fs 48 kHz, N = 2048, L = 256), SLRI R = 8 and SSPI Q = 4
-    with BF16 operands, and conv. FD-SRP with generated BF16 steering (a
-    resident operand would take 406 GB); maps at the recommended pitch,
-    frames resident."""
+    J = 200,000, fs 48 kHz, N = 2048, L = 256), SLRI R = 8 per pair, SSPI
+    Q = 4 (band product), global SLRI R_Lambda = 1024 (randomized fit of the
+    116,492-column stacked Lambda) with BF16 operands, and conv. FD-SRP with
+    generated BF16 steering (a resident operand would take 406 GB); maps at
+    the recommended pitch, frames resident."""
     import torch
     from paper_2306_08514_amd import native, scenes
     t0 = time.time()
@@ -354,9 +357,13 @@ def bench_disc32(steps):
     L, J = Y.shape[0], cfg["grid"].shape[0]
     log(f"disc32 frames in {time.time() - t0:.1f} s")
     out = {"workload": f"disc32_box200k: M=32 disc 2 m aperture, J={J}, fs=48 kHz, N=2048, L={L}", "forms": {}}
-    for form, rq, dt in (("slri", 8, "bf16"), ("sspi", 4, "bf16"), ("fd", 0, "bf16")):
+    for name, form, rq, dt, kw in (("slri", "slri", 8, "bf16", {}), ("sspi", "sspi", 4, "bf16", {}),
+                                   ("slri_global", "slri", 1024, "bf16", {"global_fit": True}),
+                                   ("fd", "fd", 0, "bf16", {})):
+        if name not in forms:
+            continue
         t1 = time.time()
-        p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], form, rq, dtype=dt, c=cfg["c"])
+        p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], form, rq, dtype=dt, c=cfg["c"], **kw)
         plan_s = time.time() - t1
         z = p.empty_maps(L)
         ws = torch.empty(max(1, p.workspace_size(L)), dtype=torch.uint8, device="cuda")
@@ -374,7 +381,7 @@ def bench_disc32(steps):
         p.profile(False)
         lat = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
         info = p.info()
-        out["forms"][form] = {"operands": dt, "rank_or_q": rq, "maps_per_s": L / (lat.mean() / 1e3),
+        out["forms"][name] = {"operands": dt, "rank_or_q": rq, "maps_per_s": L / (lat.mean() / 1e3),
                               "ms_per_call": float(lat.mean()), "p50_ms": float(np.percentile(lat, 50)),
                               "p99_ms": float(np.percentile(lat, 99)), "plan_seconds": plan_s,
                               "resident_gib": info["device_bytes"] / 2 ** 30,
@@ -382,9 +389,14 @@ def bench_disc32(steps):
                               "kernels_ms_per_call": {k: v[0] / n for k, v in prof.items()}}
         if form == "fd":
             fl = 4.0 * J * info["P"] * (info["K"] - 1) * L
-            out["forms"][form]["mfma_tflops"] = fl / (lat.mean() / 1e3) / 1e12
-            out["forms"][form]["frac_bf16_peak"] = fl / (lat.mean() / 1e3) / 1e12 / PEAK["bf16_mfma_tflops"]
-        log(f"disc32 {form}/{dt}: plan {plan_s:.1f} s, {lat.mean():.3f} ms per {L} maps")
+            out["forms"][name]["mfma_tflops"] = fl / (lat.mean() / 1e3) / 1e12
+            out["forms"][name]["frac_bf16_peak"] = fl / (lat.mean() / 1e3) / 1e12 / PEAK["bf16_mfma_tflops"]
+        if form == "sspi":
+            out["forms"][name]["tiles_dense_gather_band"] = [info["sspi_dense_tiles"], info["sspi_gather_tiles"],
+                                                             info["sspi_band_tiles"]]
+        if kw.get("global_fit"):
+            out["forms"][name]["fit"] = "randomized subspace iteration (PN > 4096)"
+        log(f"disc32 {name}/{dt}: plan {plan_s:.1f} s, {lat.mean():.3f} ms per {L} maps")
         del p, z, ws
         torch.cuda.empty_cache()
     return out
@@ -403,7 +415,7 @@ def main():
     from paper_2306_08514_amd import native, scenes
     native.lib()  # fails loudly when the HIP library is missing
     if args.large_aperture_only:
-        rec = {"large_aperture": bench_disc32(max(3, min(args.steps, 20)))}
+        rec = {"large_aperture": bench_disc32(max(3, min(args.steps, 20)), args.la_forms.split(","))}
         if args.copy_calibration:
             a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
             b = torch.empty_like(a)
@@ -576,7 +588,7 @@ def main():
     if not args.no_disc32:
         del plans, outs, wss
         torch.cuda.empty_cache()
-        disc32 = bench_disc32(max(5, min(args.steps, 20)))
+        disc32 = bench_disc32(max(5, min(args.steps, 20)), args.la_forms.split(","))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -43,7 +43,13 @@ _TAGS = [
     (r"tall_ws<.*, true>|tall_wsI.*Lb1E", "sspi_dense"),
     (r"tall_ws", "gemm_tall"),
     (r"sspi_gather", "sspi_gather"),
-    (r"xi_to_frames", "xi_to_frames"),
+    (r"sspi_band_records", "sspi_band_records (plan)"),
+    (r"sspi_band_tables", "sspi_band_tables (plan)"),
+    (r"sspi_band_passes", "sspi_band_passes (plan)"),
+    (r"sspi_band", "sspi_band"),
+    (r"lam_gemm_f64", "lam_gemm_f64 (plan)"),
+    (r"xi_to_frames|xi_rows16|rows_to_f16", "xi_to_frames"),
+    (r"split_reduce", "split_reduce"),
     (r"sspi_dense_weights", "sspi_dense_weights (plan)"),
     (r"gcc_direct", "gcc_direct"),
     (r"slri_fat_global", "slri_fat_global"),

@@ -67,6 +67,11 @@ def test_kernel_tags():
     assert rs.tag("void srp::gcc_direct<1>(HIP_vector_type<float, 2u> const*, int)") == "gcc_direct"
     assert rs.tag("_ZN3srp13slri_fat_mfmaIDF16bEEvPKfliPKiS4_S2_iiS2_iPT_i") == "slri_fat"
     assert rs.tag("_ZN3srp20slri_fat_global_mfmaIDF16bEEvPKfliiS2_iS2_PT_") == "slri_fat_global"
+    assert rs.tag("_ZN3srp9sspi_bandILi2ELi128EEEvPKDF16_liPKiPKjPKNS_8BandDescEPKtS4_iliiPfl") == "sspi_band"
+    assert rs.tag("_ZN3srp17sspi_band_recordsIDF16bEEvPKiPKT_iiliiS2_PiPj") == "sspi_band_records (plan)"
+    assert rs.tag("_ZN3srp11rows_to_f16EPKfliiiPDF16_l") == "xi_to_frames"
+    assert rs.tag("void srp::lam_gemm_f64<true>(double const*, long)") == "lam_gemm_f64 (plan)"
+    assert rs.tag("srp::split_reduce(float const*, int, long)") == "split_reduce"
     tags = rs.unique_tags(["void srp::sspi_gather<__bf16, 3, 32, true>(float const*)",
                            "void srp::sspi_gather<__bf16, 5, 32, true>(float const*)", "srp::gcc_direct<1>(x)"])
     assert tags["srp::gcc_direct<1>(x)"] == "gcc_direct"
