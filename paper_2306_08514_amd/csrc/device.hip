@@ -145,21 +145,43 @@ static hipEvent_t take_event(DevicePlan& dp) {
     }                                                     \
   } while (0)
 
+// Tiles of the 16-bit and FP8 FD GEMM: 256 x 256 outputs, K in 64-byte
+// stages (see gemm_fd16).
+constexpr int FD16_TILE = 256, FD16_SB = 64, FD16_NBUF = 5;
+constexpr int FD16_STAGE = 2 * FD16_TILE * FD16_SB;  // 32 KB
+constexpr int FD16_NI = FD16_STAGE / 1024 / 4;       // loads per wave per stage
+
+// Bank swizzle of a stage row: its four 16-byte chunks, chunk c of row r at
+// position c ^ fd16_swz(r mod 16).
+__host__ __device__ inline int fd16_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+// Byte offset of byte kb of row j in the tile-major steering operand of the
+// 16-bit and FP8 FD GEMM: [j / 256][kb / 64][j mod 256][64 bytes], each
+// 64-byte row piece swizzled by fd16_swz, so that one stage of a 256-row
+// tile is 16 KB in the order the GEMM's LDS stage holds it.  rb = bytes per
+// row (a multiple of 64).
+__host__ __device__ inline int64_t fd16_tiled(int64_t j, int64_t kb, int64_t rb) {
+  const int64_t r = j % FD16_TILE;
+  return ((j / FD16_TILE * (rb / FD16_SB) + kb / FD16_SB) * FD16_TILE + r) * FD16_SB +
+         16 * (((kb % FD16_SB) / 16) ^ fd16_swz(static_cast<int>(r & 15))) + kb % 16;
+}
+
 // ============================================================ PHAT kernel ==
 //
 // One wave per block; a thread owns one single-sided bin k = 1 + slot of one
 // frame.  u_m = y_m / |y_m| is formed once per microphone and staged in LDS,
 // then psi_p = u_m conj(u_m') for every pair, which equals
 // y_m y_m'^* / |y_m y_m'^*| of eq. (2), and 0 where either bin is 0.
-// Output layout: out[l * ld_l + p * ld_p + 2 * slot + {re, im}]; slots in
-// [K-1, kslots) are written as zeros (row padding).
+// Output layout: out[l * ld_l + p * ld_p + 2 * slot + {re, im}], or that
+// row-major operand tile-major (fd16_tiled) for the 16-bit and FP8 FD GEMM;
+// slots in [K-1, kslots) are written as zeros (row padding).
 
 template <typename TO, typename TC>
 __global__ __launch_bounds__(64) void phat_kernel(const float2* __restrict__ Y, int M, int K,
                                                   int P, const int32_t* __restrict__ pm,
                                                   const int32_t* __restrict__ pmp,
                                                   TO* __restrict__ out, int64_t ld_l,
-                                                  int64_t ld_p, int kslots) {
+                                                  int64_t ld_p, int kslots, bool tiled) {
   extern __shared__ __attribute__((aligned(16))) unsigned char phat_lds[];
   TC* ur = reinterpret_cast<TC*>(phat_lds);  // [M][64] real
   TC* ui = ur + M * 64;                      // [M][64] imag
@@ -189,8 +211,13 @@ __global__ __launch_bounds__(64) void phat_kernel(const float2* __restrict__ Y, 
   }
   // same wave wrote and reads its own column: no barrier needed across waves
   if (slot >= kslots) return;
-  TO* o = out + l * ld_l + 2 * static_cast<int64_t>(slot);
+  const int64_t rb = ld_l * static_cast<int64_t>(sizeof(TO));
   for (int p = 0; p < P; ++p) {
+    // (re, im) share a 16-byte chunk of the tile-major layout
+    const int64_t e0 = p * ld_p + 2 * static_cast<int64_t>(slot);
+    TO* o = tiled ? reinterpret_cast<TO*>(reinterpret_cast<unsigned char*>(out) +
+                                          fd16_tiled(l, e0 * static_cast<int64_t>(sizeof(TO)), rb))
+                  : out + l * ld_l + e0;
     TC re = 0, im = 0;
     if (live) {
       const int m = pm[p], mq = pmp[p];
@@ -199,8 +226,8 @@ __global__ __launch_bounds__(64) void phat_kernel(const float2* __restrict__ Y, 
       re = std::fma(ar, br, ai * bi);  // u_m conj(u_m')
       im = std::fma(ai, br, -(ar * bi));
     }
-    o[p * ld_p] = cvt64<TO>(re);
-    o[p * ld_p + 1] = cvt64<TO>(im);
+    o[0] = cvt64<TO>(re);
+    o[1] = cvt64<TO>(im);
   }
 }
 
@@ -2315,12 +2342,13 @@ __global__ __launch_bounds__(256) void sspi_windows(const double* __restrict__ x
 }
 
 // Steering operand of conv. FD-SRP: H[j * ldh + p Kp + 2 (k-1) + {0,1}] =
-// (cos theta, -sin theta), theta = pi k x_p(j) / K (eq. (19) with (14)).  The
+// (cos theta, -sin theta), theta = pi k x_p(j) / K (eq. (19) with (14)),
+// row-major, or tile-major (fd16_tiled) for the 16-bit and FP8 GEMM.  The
 // phase is reduced in FP64: theta = 2 pi (t - rint(t)), t = k x / (2K), and
 // sin/cos come from the FP64 sincospi.  Rows j >= J and slots k >= K are 0.
 template <typename T>
 __global__ void build_steering(const double* __restrict__ x, int P, int64_t J, int K, int Kp, int64_t ldh,
-                               T* __restrict__ H) {
+                               bool tiled, T* __restrict__ H) {
   const int64_t j = blockIdx.x;
   const int slots = Kp / 2;
   const int e = blockIdx.y * 256 + threadIdx.x;
@@ -2333,7 +2361,11 @@ __global__ void build_steering(const double* __restrict__ x, int P, int64_t J, i
     const double r = t - rint(t);
     sincospi(2.0 * r, &s, &c);
   }
-  T* h = H + j * ldh + static_cast<int64_t>(p) * Kp + 2 * kk;
+  // (re, im) share a 16-byte chunk, so the tiled layout keeps them adjacent
+  const int64_t e0 = static_cast<int64_t>(p) * Kp + 2 * kk;
+  T* h = tiled ? reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(H) +
+                                      fd16_tiled(j, e0 * static_cast<int64_t>(sizeof(T)), ldh * static_cast<int64_t>(sizeof(T))))
+               : H + j * ldh + e0;
   h[0] = cvt64<T>(c);
   h[1] = cvt64<T>(-s);
 }
@@ -2394,8 +2426,12 @@ size_t dsize(int dtype) {
 
 template <typename T>
 void launch_steering(const double* d_x, const HostPlan& hp, int Kp, int64_t Jpad, int64_t ldh, void* H) {
+  // the 16-bit and FP8 GEMM (gemm_fd16) reads the tile-major layout
+  const bool tiled = sizeof(T) <= 2;
+  if (tiled && ((ldh * static_cast<int64_t>(sizeof(T))) % FD16_SB != 0 || Jpad % FD16_TILE != 0))
+    throw Error{SRP_E_UNSUPPORTED, "steering rows are not whole 64-byte stages of 256-row tiles"};
   dim3 grid(static_cast<unsigned>(Jpad), (hp.P * (Kp / 2) + 255) / 256);
-  hipLaunchKernelGGL(build_steering<T>, grid, dim3(256), 0, 0, d_x, hp.P, hp.J, hp.K, Kp, ldh,
+  hipLaunchKernelGGL(build_steering<T>, grid, dim3(256), 0, 0, d_x, hp.P, hp.J, hp.K, Kp, ldh, tiled,
                      static_cast<T*>(H));
   check_launch("build_steering");
 }
@@ -2437,6 +2473,225 @@ void upload(void* dst, const std::vector<T>& v) {
 }
 
 // tile shapes of the launch configurations
+// s_waitcnt with vmcnt = N, lgkmcnt = 0 (this wave's LDS reads are done)
+template <int N>
+__device__ inline void wait_vm_lds() {
+  static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+}
+
+// 16-bit and FP8 FD GEMM, C = alpha X W^T (X: cross-spectra rows, W: steering
+// rows, both tile-major as fd16_tiled lays them out): 256 x 256 tiles, 2 x 2 waves of 4 x 4 MFMA
+// blocks (accumulators in AccVGPRs, one block per CU).  K streams in 64-byte
+// stages straight into a ring of NBUF LDS stage buffers (global_load_lds, no
+// register staging), each refilled as soon as the barrier after its last
+// read has passed; one plain s_barrier per stage publishes it once every
+// wave has waited for its own loads of it.  A stage row holds four 16-byte
+// chunks, chunk c of row r at position c ^ f(r mod 16) with f(r) =
+// ((r >> 1) ^ (r >> 3)) & 3, so that the fragment reads of 8 or 16
+// consecutive rows at one chunk fall in distinct banks (32 or 64 banks).
+// Both operands are stored tile-major (fd16_tiled: a 256-row tile's 64-byte
+// stage pieces contiguous, already in the swizzled order), so one load is
+// 1 KB contiguous and fills 16 rows of the stage; row-major operands, whose
+// stages are scattered 64-byte pieces of rows tens of KB apart, kept the
+// loads at a fraction of the L2's rate.  The MFMA steps are software-pipelined (the next step's fragments
+// are read during the current step's MFMAs), since with one wave per SIMD
+// nothing else hides the LDS latency.  Blocks are grouped per XCD with the
+// frame tiles innermost (xcd_tile), so a steering tile is fetched from HBM
+// once.  With blockIdx.z > 0 the contraction is split: split z covers
+// elements [z kdim, (z + 1) kdim) and writes rows [z cz_rows, ...) of C.
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_fd16(const T* __restrict__ X, int64_t ldx,
+                                                 const T* __restrict__ W, int64_t ldw,
+                                                 float* __restrict__ C, int64_t ldc, int nx, int nw,
+                                                 int kdim, float alpha, int nw_tiles, int nx_tiles,
+                                                 int64_t cz_rows) {
+  constexpr int STEP = Mfma<T>::STEP;  // bytes of a row per MFMA step
+  constexpr int LB = STEP / 2;         // bytes per lane per step
+  constexpr int NV = LB / 16;
+  constexpr int KS = FD16_SB / STEP;   // MFMA steps per stage
+  static_assert(FD16_SB == 64, "four chunks per stage row");
+  static_assert(FD16_NBUF * FD16_STAGE <= 160 * 1024, "LDS");
+  static_assert((FD16_NBUF - 1) * FD16_NI < 64, "vmcnt holds at most 63 loads");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[FD16_NBUF * FD16_STAGE];
+
+  int wt, xt;
+  if (!xcd_tile(nw_tiles, nx_tiles, wt, xt)) return;  // uniform over the block
+  const int x0 = xt * FD16_TILE, w0 = wt * FD16_TILE;
+  if (x0 >= nx) return;
+  const int64_t kz = static_cast<int64_t>(blockIdx.z) * kdim * static_cast<int64_t>(sizeof(T));
+  C += static_cast<int64_t>(blockIdx.z) * cz_rows * ldc;
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (SGPR)
+  // loads: waves 0, 1 fill frame rows 128 wave .. + 127, waves 2, 3 the
+  // candidate rows 128 (wave - 2) ..; load i covers 16 of them
+  // both operands are tile-major with the swizzle applied (fd16_tiled): a
+  // load is 1 KB contiguous, lane l's 16 bytes landing at byte 16 l
+  const bool xside = wave < 2;
+  const int64_t nstg = (xside ? ldx : ldw) * static_cast<int64_t>(sizeof(T)) / FD16_SB;  // stages per full row
+  const unsigned char* src =
+      reinterpret_cast<const unsigned char*>(xside ? static_cast<const void*>(X) : static_cast<const void*>(W)) +
+      ((static_cast<int64_t>(xside ? xt : wt) * nstg + kz / FD16_SB) * FD16_TILE + (wave & 1) * 128) * FD16_SB +
+      16 * lane;
+  constexpr int64_t step16 = 1024, sstride = FD16_TILE * FD16_SB;
+  const int ns = static_cast<int>(kdim * static_cast<int64_t>(sizeof(T)) / FD16_SB);
+  // stage s >= ns reloads the last stage (a valid address) into a spent
+  // buffer, so that every wait below counts the same loads
+  auto issue = [&](int s) {
+    unsigned char* dst = lds + (s % FD16_NBUF) * FD16_STAGE + wave * FD16_NI * 1024;
+    const unsigned char* sp = src + static_cast<int64_t>(min(s, ns - 1)) * sstride;
+#pragma unroll
+    for (int i = 0; i < FD16_NI; ++i)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(sp + i * step16),
+                                       (__attribute__((address_space(3))) void*)(dst + 1024 * i), 16, 0, 0);
+  };
+
+  const int r32 = lane & 31, g = lane >> 5;
+  const int wy = wave >> 1, wx = wave & 1;
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
+
+  // fragment rows: frames wy 128 + 32 a + r32, candidates 256 + wx 128 +
+  // 32 b + r32 (all with r mod 16 = r32 mod 16); logical chunk c of step t
+  // is t STEP / 16 + g NV + v.  FP8 fragments are 8 registers (two chunks),
+  // loaded in place so that the MFMA takes them without copies.
+  using F = typename std::conditional<NV == 2, i32x8, i32x4>::type;
+  const int sw = fd16_swz(r32 & 15);
+  const int xrow = (wy * 128 + r32) * FD16_SB, wrow = (FD16_TILE + wx * 128 + r32) * FD16_SB;
+  auto ld = [&](const unsigned char* p) { return *reinterpret_cast<const i32x4*>(p); };
+  auto frags = [&](int s, auto tc, F (&fa)[4], F (&fb)[4]) {
+    constexpr int t = decltype(tc)::value;
+    const unsigned char* bs = lds + (s % FD16_NBUF) * FD16_STAGE;
+    const int p0 = 16 * (((t * STEP) / 16 + g * NV) ^ sw);
+    if constexpr (NV == 1) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) fa[a] = ld(bs + xrow + p0 + a * 32 * FD16_SB);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) fb[b] = ld(bs + wrow + p0 + b * 32 * FD16_SB);
+    } else {
+      const int p1 = 16 * (((t * STEP) / 16 + g * NV + 1) ^ sw);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        fa[a] = __builtin_shufflevector(ld(bs + xrow + p0 + a * 32 * FD16_SB), ld(bs + xrow + p1 + a * 32 * FD16_SB),
+                                        0, 1, 2, 3, 4, 5, 6, 7);
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        fb[b] = __builtin_shufflevector(ld(bs + wrow + p0 + b * 32 * FD16_SB), ld(bs + wrow + p1 + b * 32 * FD16_SB),
+                                        0, 1, 2, 3, 4, 5, 6, 7);
+    }
+  };
+  auto mfmas = [&](const F (&fa)[4], const F (&fb)[4]) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if constexpr (std::is_same<T, fp8>::value)
+          // E4M3 operands (format 0), E8M0 scales 127 = 2^0
+          acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[a], fb[b], acc[a][b], 0, 0, 0, 127, 0, 127);
+        else if constexpr (std::is_same<T, __bf16>::value)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[a]),
+                                                              __builtin_bit_cast(bf16x8, fb[b]), acc[a][b], 0, 0, 0);
+        else
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, fa[a]),
+                                                             __builtin_bit_cast(f16x8, fb[b]), acc[a][b], 0, 0, 0);
+      }
+  };
+  // MFMA step t of stage s with the fragments in (ca, cb); reads the next
+  // step's fragments into (na, nb) first.  At a stage's last step every
+  // fragment of the stage is already in registers (and this wave's reads
+  // are done): after the barrier that publishes stage s + 1, whose loads
+  // this wave has waited for (the NBUF - 2 later stages stay in flight),
+  // the buffer of stage s takes the loads of stage s + NBUF.
+  auto step = [&](int s, auto tc, F (&ca)[4], F (&cb)[4], F (&na)[4], F (&nb)[4]) {
+    constexpr int t = decltype(tc)::value;
+    constexpr int NR = 8 * NV;  // LDS reads of a step's fragments
+    // this step's fragments were read one step ago
+    __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));
+    if constexpr (t + 1 < KS) {
+      frags(s, std::integral_constant<int, t + 1>{}, na, nb);
+      mfmas(ca, cb);
+      // one MFMA, one LDS read, ...
+#pragma unroll
+      for (int i = 0; i < NR && i < 16; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+    } else {
+      // unconditional, so that the loop body is one basic block and the
+      // register sets need no copies: after the last stage the barrier,
+      // reloads and reads of a spent buffer are harmless and unused
+      wait_vm_lds<(FD16_NBUF - 2) * FD16_NI>();
+      asm volatile("s_barrier" ::: "memory");
+      issue(s + FD16_NBUF);
+      frags(s + 1, std::integral_constant<int, 0>{}, na, nb);
+      mfmas(ca, cb);
+      // the loads of stage s + NBUF and the next fragment reads interleaved
+      // with this step's MFMAs
+#pragma unroll
+      for (int i = 0; i < FD16_NI; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x004, 2, 0);  // SALU
+        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // VALU
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
+      }
+#pragma unroll
+      for (int i = 0; i < NR && i < 16 - FD16_NI; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  for (int s = 0; s < FD16_NBUF; ++s) issue(s);
+  wait_vm_lds<(FD16_NBUF - 1) * FD16_NI>();  // stage 0 has landed
+  asm volatile("s_barrier" ::: "memory");
+  F fa0[4], fb0[4], fa1[4], fb1[4];
+  frags(0, std::integral_constant<int, 0>{}, fa0, fb0);
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  // two stages per iteration so that the register sets alternate at compile
+  // time (step q = s KS + t multiplies set q & 1); ns is even
+  for (int s = 0; s < ns; s += 2) {
+    if constexpr (KS == 2) {
+      step(s, I0{}, fa0, fb0, fa1, fb1);
+      step(s, I1{}, fa1, fb1, fa0, fb0);
+      step(s + 1, I0{}, fa0, fb0, fa1, fb1);
+      step(s + 1, I1{}, fa1, fb1, fa0, fb0);
+    } else {
+      static_assert(KS == 1, "one or two MFMA steps per stage");
+      step(s, I0{}, fa0, fb0, fa1, fb1);
+      step(s + 1, I0{}, fa1, fb1, fa0, fb0);
+    }
+  }
+  wait_vm_lds<0>();  // the reloads past the last stage
+
+  // 32 x 32 accumulator layout: register v of lane i holds row
+  // 8 (v / 4) + 4 (i / 32) + v % 4 and column i % 32
+  const int rbase = x0 + wy * 128 + 4 * g;
+  float* cp = C + static_cast<int64_t>(rbase) * ldc + w0 + wx * 128 + r32;
+  const int cbase = w0 + wx * 128 + r32;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int ro = a * 32 + 8 * (v / 4) + (v % 4);
+      if (rbase + ro >= nx) continue;
+      float* rp = cp + ro * ldc;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (cbase + b * 32 < nw) rp[b * 32] = alpha * acc[a][b][v];
+    }
+}
+
 // FD GEMM: 128 frames x 128 candidates per block, 2 x 2 waves, 256-byte K
 // slices (128 bytes for FP8, whose rows are only a multiple of 128 bytes).
 // Measured against 256 x 128 tiles with 128-byte slices: 55.0 vs 58.6 ms at
@@ -3514,14 +3769,14 @@ WsLayout ws_layout(const HostPlan& hp, const DevicePlan& dp, int64_t L, int64_t 
 
 template <typename TO, typename TC>
 void launch_phat(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t L, TO* out,
-                 int64_t ld_l, int64_t ld_p, int kslots, hipStream_t st) {
+                 int64_t ld_l, int64_t ld_p, int kslots, hipStream_t st, bool tiled = false) {
   if (L == 0) return;
   dim3 grid((kslots + 63) / 64, static_cast<unsigned>(L));
   const size_t lds = 2 * static_cast<size_t>(hp.M) * 64 * sizeof(TC);
   TRACED(dp, "phat", st,
          hipLaunchKernelGGL((phat_kernel<TO, TC>), grid, dim3(64), lds, st,
                             static_cast<const float2*>(frames), hp.M, hp.K, hp.P, dp.d_pm, dp.d_pmp, out,
-                            ld_l, ld_p, kslots));
+                            ld_l, ld_p, kslots, tiled));
   check_launch("phat_kernel");
 }
 
@@ -3529,11 +3784,13 @@ void phat_dispatch(const HostPlan& hp, DevicePlan& dp, const void* frames, int64
                    void* out, int dtype, hipStream_t st) {
   const int64_t ld_l = fd_ld(hp, dp, dsize(dtype));
   const int kslots = dp.Kp / 2;
+  // the resident-steering 16-bit and FP8 GEMM (gemm_fd16) reads psi tile-major
+  const bool tiled = hp.variant == SRP_FD && !dp.fd_gen && dsize(dtype) <= 2;
   switch (dtype) {
     case SRP_F32: launch_phat<float, float>(hp, dp, frames, L, static_cast<float*>(out), ld_l, dp.Kp, kslots, st); break;
-    case SRP_BF16: launch_phat<__bf16, float>(hp, dp, frames, L, static_cast<__bf16*>(out), ld_l, dp.Kp, kslots, st); break;
-    case SRP_F16: launch_phat<_Float16, float>(hp, dp, frames, L, static_cast<_Float16*>(out), ld_l, dp.Kp, kslots, st); break;
-    case SRP_FP8_E4M3: launch_phat<fp8, float>(hp, dp, frames, L, static_cast<fp8*>(out), ld_l, dp.Kp, kslots, st); break;
+    case SRP_BF16: launch_phat<__bf16, float>(hp, dp, frames, L, static_cast<__bf16*>(out), ld_l, dp.Kp, kslots, st, tiled); break;
+    case SRP_F16: launch_phat<_Float16, float>(hp, dp, frames, L, static_cast<_Float16*>(out), ld_l, dp.Kp, kslots, st, tiled); break;
+    case SRP_FP8_E4M3: launch_phat<fp8, float>(hp, dp, frames, L, static_cast<fp8*>(out), ld_l, dp.Kp, kslots, st, tiled); break;
     case SRP_F64: launch_phat<double, double>(hp, dp, frames, L, static_cast<double*>(out), ld_l, dp.Kp, kslots, st); break;
   }
 }
@@ -3562,9 +3819,20 @@ void launch_big_gemm(DevicePlan& dp, const char* kname, const void* X, int64_t l
   if constexpr (std::is_same<T, float>::value)
     launch_gemm<T, BIG_BX, BIG_BW, BIG_WGX, big_bkb<T>()>(dp, kname, X, ldx, W, ldw, C, ldc, nx, nw, kdim, alpha,
                                                          Lpad, st, 0, ksplit, cz_rows);
-  else
-    launch_gemm<T, BIG16_BX, BIG16_BW, BIG16_WGX, BIG16_BKB>(dp, kname, X, ldx, W, ldw, C, ldc, nx, nw, kdim, alpha,
-                                                            Lpad, st, 0, ksplit, cz_rows);
+  else {
+    // rows of X and W are read up to whole 256-row tiles (Lpad, Jpad rows
+    // are allocated)
+    // the kernel takes two 64-byte stages per iteration
+    if ((static_cast<int64_t>(kdim / ksplit) * static_cast<int64_t>(sizeof(T))) % (2 * FD16_SB) != 0 || kdim % ksplit != 0)
+      throw Error{SRP_E_UNSUPPORTED, "FD contraction is not whole 128-byte rows"};
+    const int nwt = static_cast<int>(dp.Jpad / FD16_TILE);
+    const int nxt = static_cast<int>(Lpad / FD16_TILE);
+    const int blocks = static_cast<int>(round_up(static_cast<int64_t>(nwt) * nxt, 8));
+    TRACED(dp, kname, st,
+           hipLaunchKernelGGL((gemm_fd16<T>), dim3(blocks, 1, ksplit), dim3(256), 0, st, static_cast<const T*>(X),
+                              ldx, static_cast<const T*>(W), ldw, C, ldc, nx, nw, kdim / ksplit, alpha, nwt, nxt,
+                              cz_rows));
+  }
 }
 
 // z[l][j] = alpha sum_s part[s][l][j] over the ksplit partial products of
