@@ -194,11 +194,14 @@ def test_queue_bound_rejects_fast_and_recovers(frames):
     request fails at once with AdmissionError; once the queue drains, new
     requests are served again."""
     cfg, Y = frames
-    ex = FakeExecutor(per_frame_s=5e-3, fixed_s=20e-3)
+    ex = FakeExecutor(per_frame_s=5e-3, fixed_s=200e-3)
     srv = Server(ex, n_slots=1, max_batch_frames=1, max_queue=3).start()
     srv.register("a", cfg=cfg)
     first = srv.submit("a", Y[:1])
-    time.sleep(0.005)                        # the first batch is on the device
+    t0 = time.monotonic()
+    while not ex.launched and time.monotonic() - t0 < 10:
+        time.sleep(0.001)                    # until the first batch is on the device
+    assert ex.launched
     queued = [srv.submit("a", Y[i:i + 1]) for i in range(1, 4)]
     over = srv.submit("a", Y[5:6])
     with pytest.raises(AdmissionError):
