@@ -145,6 +145,21 @@ static hipEvent_t take_event(DevicePlan& dp) {
     }                                                     \
   } while (0)
 
+// s_waitcnt with vmcnt = N and no wait on the other counters (gfx9
+// encoding: vmcnt bits [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8])
+template <int N>
+__device__ inline void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// s_waitcnt with vmcnt = N, lgkmcnt = 0 (this wave's LDS reads are done)
+template <int N>
+__device__ inline void wait_vm_lds() {
+  static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+}
+
 // Tiles of the 16-bit and FP8 FD GEMM: 256 x 256 outputs, K in 64-byte
 // stages (see gemm_fd16).
 constexpr int FD16_TILE = 256, FD16_SB = 64, FD16_NBUF = 5;
@@ -642,6 +657,208 @@ __global__ __launch_bounds__(256) void fd_gen(const T* __restrict__ X, int64_t l
     }
 }
 
+// 16-bit conv. FD-SRP with generated steering for large batches: the tiles,
+// LDS stages, bank swizzle and software pipeline of gemm_fd16, with the
+// cross-spectra (tile-major, fd16_tiled) streamed through a ring of FG_NBX
+// stages and the steering stage generated into one of FG_NBH LDS buffers
+// two stages before the MFMAs read it, half a stage per MFMA step, so that
+// the generation's vector work issues between the matrix instructions.
+// Thread r generates row r (candidate w0 + r): at a pair's first stage its
+// first angle (bin 1) comes from the FP64 sincospi of the reduced phase;
+// each stage's first bin is that FP64 value advanced by a 16-bin FP64
+// rotation per stage, and the stage's 16 bins follow by FP32 rotation by
+// exp(+i pi x / K) (a chain of 15 steps); bins k > K - 1 are zero.
+// blockIdx.y splits the contraction at pair boundaries as in fd_gen.
+constexpr int FG_NBX = 6, FG_NBH = 3;
+constexpr int FG_XST = FD16_TILE * FD16_SB;  // 16 KB: one operand's stage
+
+template <typename T>
+__global__ __launch_bounds__(256) void fd_gen16(const T* __restrict__ X, int64_t ldx,
+                                                const double* __restrict__ xg, int64_t J, int K, int Kp,
+                                                float* __restrict__ C, int64_t ldc, int nx, int P, float alpha,
+                                                int nw_tiles, int nx_tiles, int pps, int64_t cz_rows) {
+  static_assert(sizeof(T) == 2, "16-bit operands");
+  constexpr int STEP = Mfma<T>::STEP, LB = STEP / 2;
+  constexpr int NL = FG_XST / 1024 / 4;  // loads per wave per stage
+  static_assert((FG_NBX - 1) * NL < 64, "vmcnt holds at most 63 loads");
+  static_assert((FG_NBX + FG_NBH) * FG_XST <= 160 * 1024, "LDS");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[(FG_NBX + FG_NBH) * FG_XST];
+  unsigned char* const hb = lds + FG_NBX * FG_XST;
+
+  int wt, xt;
+  if (!xcd_tile(nw_tiles, nx_tiles, wt, xt)) return;  // uniform over the block
+  const int x0 = xt * FD16_TILE, w0 = wt * FD16_TILE;
+  if (x0 >= nx) return;
+  const int p0 = static_cast<int>(blockIdx.y) * pps, p1 = min(P, p0 + pps);
+  if (p0 >= p1) return;
+  const int spp = Kp * 2 / FD16_SB;  // stages per pair (even)
+  const int ns = (p1 - p0) * spp;
+  C += static_cast<int64_t>(blockIdx.y) * cz_rows * ldc;
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // cross-spectra loads: wave w fills rows 64 w .. 64 w + 63 of a stage
+  const int64_t nstg = ldx * 2 / FD16_SB;
+  const unsigned char* src = reinterpret_cast<const unsigned char*>(X) +
+                             ((static_cast<int64_t>(xt) * nstg + static_cast<int64_t>(p0) * spp) * FD16_TILE + 64 * wave) *
+                                 FD16_SB +
+                             16 * lane;
+  auto issue = [&](int s) {
+    unsigned char* dst = lds + (s % FG_NBX) * FG_XST + wave * NL * 1024;
+    const unsigned char* sp = src + static_cast<int64_t>(min(s, ns - 1)) * FG_XST;
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(sp + 1024 * i),
+                                       (__attribute__((address_space(3))) void*)(dst + 1024 * i), 16, 0, 0);
+  };
+
+  // generator of row tid
+  const int64_t gj = w0 + tid;
+  const bool glive = gj < J;
+  const int gsw = fd16_swz(tid & 15);
+  double sc = 1.0, ss = 0.0, ac = 1.0, as = 0.0;  // FP64 seed (next stage's first bin) and 16-bin advance
+  float fc = 1.0f, fs = 0.0f, cc = 1.0f, cs = 0.0f;  // FP32 one-bin step and running value
+  int kfirst = 1;
+  auto seed_pair = [&](int p) {
+    const double x = glive ? xg[static_cast<int64_t>(p) * J + gj] : 0.0;
+    const double t = x / (2.0 * K);  // bin 1: theta = pi x / K
+    sincospi(2.0 * (t - rint(t)), &ss, &sc);
+    fc = static_cast<float>(sc);
+    fs = static_cast<float>(ss);
+    const double v = 16.0 * x / (2.0 * K);
+    sincospi(2.0 * (v - rint(v)), &as, &ac);
+  };
+  auto gen_begin = [&](int g) {
+    cc = static_cast<float>(sc);
+    cs = static_cast<float>(ss);
+    kfirst = (g % spp) * 16 + 1;
+    const double cn = sc * ac - ss * as;
+    ss = sc * as + ss * ac;
+    sc = cn;
+  };
+  // bins 8 h .. 8 h + 7 of stage g: chunks 2 h, 2 h + 1 of row tid
+  auto gen_half = [&](int g, int h) {
+    unsigned char* row = hb + (g % FG_NBH) * FG_XST + tid * FD16_SB;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int c = 2 * h + q;
+      uint32_t w4[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const bool ok = glive && kfirst + 4 * c + b <= K - 1;
+        const T re = cvt<T>(ok ? cc : 0.0f), im = cvt<T>(ok ? -cs : 0.0f);
+        uint16_t ur, ui;
+        __builtin_memcpy(&ur, &re, 2);
+        __builtin_memcpy(&ui, &im, 2);
+        w4[b] = static_cast<uint32_t>(ur) | (static_cast<uint32_t>(ui) << 16);
+        const float cn = __builtin_fmaf(cc, fc, -(cs * fs));
+        cs = __builtin_fmaf(cc, fs, cs * fc);
+        cc = cn;
+      }
+      *reinterpret_cast<i32x4*>(row + 16 * (c ^ gsw)) =
+          i32x4{static_cast<int>(w4[0]), static_cast<int>(w4[1]), static_cast<int>(w4[2]), static_cast<int>(w4[3])};
+    }
+  };
+
+  const int r32 = lane & 31, g = lane >> 5;
+  const int wy = wave >> 1, wx = wave & 1;
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
+  const int sw = fd16_swz(r32 & 15);
+  const int xrow = (wy * 128 + r32) * FD16_SB, wrow = (wx * 128 + r32) * FD16_SB;
+  auto frags = [&](int s, auto tc, i32x4 (&fa)[4], i32x4 (&fb)[4]) {
+    constexpr int t = decltype(tc)::value;
+    const unsigned char* bx = lds + (s % FG_NBX) * FG_XST;
+    const unsigned char* bw = hb + (s % FG_NBH) * FG_XST;
+    const int pos = 16 * (((t * STEP) / 16 + g) ^ sw);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) fa[a] = *reinterpret_cast<const i32x4*>(bx + xrow + pos + a * 32 * FD16_SB);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) fb[b] = *reinterpret_cast<const i32x4*>(bw + wrow + pos + b * 32 * FD16_SB);
+  };
+  auto mfmas = [&](const i32x4 (&fa)[4], const i32x4 (&fb)[4]) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) Mfma<T>::run(&fa[a], &fb[b], acc[a][b]);
+  };
+  // MFMA step t of consumption stage s (fragments in ca, cb) while half h = t
+  // of generation stage s + 2 is written; at t = 1 the barrier publishes
+  // stage s + 1 (its cross-spectra landed: NBX - 2 later stages may stay in
+  // flight; its steering was written during stage s - 1) and the ring slot
+  // of stage s takes stage s + NBX.
+  auto step = [&](int s, auto tc, i32x4 (&ca)[4], i32x4 (&cb)[4], i32x4 (&na)[4], i32x4 (&nb)[4]) {
+    constexpr int t = decltype(tc)::value;
+    __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));  // this step's fragments (read one step ago)
+    if constexpr (t == 0) {
+      frags(s, std::integral_constant<int, 1>{}, na, nb);
+      gen_begin(s + 2);
+      gen_half(s + 2, 0);
+    } else {
+      wait_vm_lds<(FG_NBX - 2) * NL>();
+      asm volatile("s_barrier" ::: "memory");
+      issue(s + FG_NBX);
+      frags(s + 1, std::integral_constant<int, 0>{}, na, nb);
+      gen_half(s + 2, 1);  // buffer (s + 2) mod NBH is free since the barrier of stage s
+    }
+    mfmas(ca, cb);
+    // interleave: each MFMA followed by a few vector instructions of the
+    // generation, the fragment reads and (t = 1) the loads
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+      __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);  // VALU
+      if (i < 8) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+      if (t == 1 && i < NL) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
+  for (int s = 0; s < FG_NBX; ++s) issue(s);
+  seed_pair(p0);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    gen_begin(s);
+    gen_half(s, 0);
+    gen_half(s, 1);
+  }
+  wait_vm_lds<(FG_NBX - 1) * NL>();  // stage 0 has landed
+  asm volatile("s_barrier" ::: "memory");
+  i32x4 fa0[4], fb0[4], fa1[4], fb1[4];
+  frags(0, std::integral_constant<int, 0>{}, fa0, fb0);
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  for (int s = 0; s < ns; s += 2) {
+    // the generation stages s + 2, s + 3 start a pair together (spp even)
+    if (s + 2 < ns && (s + 2) % spp == 0) seed_pair(p0 + (s + 2) / spp);
+    step(s, I0{}, fa0, fb0, fa1, fb1);
+    step(s, I1{}, fa1, fb1, fa0, fb0);
+    step(s + 1, I0{}, fa0, fb0, fa1, fb1);
+    step(s + 1, I1{}, fa1, fb1, fa0, fb0);
+  }
+  wait_vm_lds<0>();  // the reloads past the last stage
+
+  const int rbase = x0 + wy * 128 + 4 * g;
+  const int64_t cbase = static_cast<int64_t>(w0) + wx * 128 + r32;
+  float* cp = C + static_cast<int64_t>(rbase) * ldc + cbase;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int ro = a * 32 + 8 * (v / 4) + (v % 4);
+      if (rbase + ro >= nx) continue;
+      float* rp = cp + ro * ldc;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (cbase + b * 32 < J) rp[b * 32] = alpha * acc[a][b][v];
+    }
+}
+
 // FP64 variant on v_mfma_f64_16x16x4_f64: 64 x 64 tile, 4 waves of 32 x 32,
 // each 2 x 2 blocks of 16 x 16.  Lane i supplies row i % 16 and k slot i / 16
 // of each 4-deep step; accumulator register v of lane i holds row
@@ -1117,14 +1334,6 @@ __global__ __launch_bounds__(512) void slri_fat_global_mfma(const float* __restr
 // contiguous ranges of frame groups; the splits of a candidate tile run back
 // to back on one XCD (xcd_tile), so the U rows they share are fetched from
 // HBM once.
-
-// s_waitcnt with vmcnt = N and no wait on the other counters (gfx9
-// encoding: vmcnt bits [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8])
-template <int N>
-__device__ inline void wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt is six bits");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
-}
 
 template <typename T, int NS, int CW, bool CT>
 __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g, int64_t ldg, int grows,
@@ -2473,13 +2682,6 @@ void upload(void* dst, const std::vector<T>& v) {
 }
 
 // tile shapes of the launch configurations
-// s_waitcnt with vmcnt = N, lgkmcnt = 0 (this wave's LDS reads are done)
-template <int N>
-__device__ inline void wait_vm_lds() {
-  static_assert(N >= 0 && N < 64, "vmcnt is six bits");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
-}
-
 // 16-bit and FP8 FD GEMM, C = alpha X W^T (X: cross-spectra rows, W: steering
 // rows, both tile-major as fd16_tiled lays them out): 256 x 256 tiles, 2 x 2 waves of 4 x 4 MFMA
 // blocks (accumulators in AccVGPRs, one block per CU).  K streams in 64-byte
@@ -2707,11 +2909,13 @@ template <typename T>
 constexpr int big_bkb() {
   return sizeof(T) == 1 ? 128 : 256;
 }
-// 16-bit and FP8 FD: at their MFMA rates 2 x 2 blocks of 32 x 32 per wave
-// read ~16 MACs per byte of LDS fragments, which saturates LDS; 4 x 4
-// blocks per wave (256 x 256 tiles, accumulators in AccVGPRs) halve that.
-// Measured at 125,000 x 1000 x 28,672: BF16 11.2 -> 8.1 ms, FP8 5.0 -> 3.9.
-constexpr int BIG16_BX = 256, BIG16_BW = 256, BIG16_WGX = 2, BIG16_BKB = 128;
+// 16-bit and FP8 FD run gemm_fd16 (256 x 256 tiles).  At their MFMA rates
+// 2 x 2 blocks of 32 x 32 per wave read ~16 MACs per byte of LDS fragments,
+// which saturates LDS; 4 x 4 blocks per wave (accumulators in AccVGPRs)
+// halve that.  Measured at 125,000 x 1000 x 28,672, BF16 / FP8 ms per call:
+// 128 x 128 tiles 11.2 / 5.0; 256 x 256 with register-staged K slices
+// 8.1 / 3.9; direct-to-LDS stage ring with pipelined MFMA steps 7.4 / 3.75;
+// tile-major operands 6.1 / 3.2.
 // candidate rows of the resident operands are padded to the widest W tile
 constexpr int JPAD_ROWS = 256;
 // workspace frame rows are padded to whole 256-frame tiles, the largest
@@ -3412,9 +3616,9 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     // contraction over blockIdx.z so that the GEMM has ~512 blocks per frame
     // tile; a plan constant, so a frame's map does not depend on its batch
     const bool f32 = hp.dtype == SRP_F32;
-    const int64_t nwt = dp.Jpad / (f32 ? BIG_BW : BIG16_BW);
+    const int64_t nwt = dp.Jpad / (f32 ? BIG_BW : FD16_TILE);
     if (hp.dtype != SRP_F64 && nwt < 64) {
-      const int64_t slices = static_cast<int64_t>(P) * dp.Kp * static_cast<int64_t>(es) / (f32 ? 256 : BIG16_BKB);
+      const int64_t slices = static_cast<int64_t>(P) * dp.Kp * static_cast<int64_t>(es) / (f32 ? 256 : 2 * FD16_SB);
       int ks = 1;
       while (ks < 64 && nwt * ks * 2 <= 512 && slices % (ks * 2) == 0 && slices / (ks * 2) >= 16) ks *= 2;
       dp.fd_ksplit = ks;
@@ -3784,8 +3988,10 @@ void phat_dispatch(const HostPlan& hp, DevicePlan& dp, const void* frames, int64
                    void* out, int dtype, hipStream_t st) {
   const int64_t ld_l = fd_ld(hp, dp, dsize(dtype));
   const int kslots = dp.Kp / 2;
-  // the resident-steering 16-bit and FP8 GEMM (gemm_fd16) reads psi tile-major
-  const bool tiled = hp.variant == SRP_FD && !dp.fd_gen && dsize(dtype) <= 2;
+  // the resident-steering 16-bit and FP8 GEMM (gemm_fd16) and the 16-bit
+  // generated-steering kernel for large batches (fd_gen16) read psi tile-major
+  const bool tiled = hp.variant == SRP_FD && dsize(dtype) <= 2 &&
+                     (!dp.fd_gen || (dsize(dtype) == 2 && L > 128));
   switch (dtype) {
     case SRP_F32: launch_phat<float, float>(hp, dp, frames, L, static_cast<float*>(out), ld_l, dp.Kp, kslots, st); break;
     case SRP_BF16: launch_phat<__bf16, float>(hp, dp, frames, L, static_cast<__bf16*>(out), ld_l, dp.Kp, kslots, st, tiled); break;
@@ -3902,6 +4108,18 @@ void launch_fd_gen(const HostPlan& hp, DevicePlan& dp, const void* psi, int64_t 
            hipLaunchKernelGGL((fd_gen<T, 64, 1, true>), dim3(blocks, ks), dim3(256), 0, st,
                               static_cast<const T*>(psi), ldpsi, dp.d_xg, hp.J, hp.K, dp.Kp, c, ldc,
                               static_cast<int>(Lc), kdim, alpha, nw, nxt, pps, Lpad));
+  } else if (Lc > 128 && sizeof(T) == 2) {
+    // 16-bit, large batches: generation overlapped with the MFMAs
+    if constexpr (sizeof(T) == 2) {
+      const int nxt = static_cast<int>((Lc + 255) / 256);
+      const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(nw) * nxt, 8));
+      if ((static_cast<int64_t>(dp.Kp) * 2) % (2 * FD16_SB) != 0 || ldpsi * 2 % FD16_SB != 0)
+        throw Error{SRP_E_UNSUPPORTED, "FD pair slots are not whole 128-byte rows"};
+      TRACED(dp, "fd_gen", st,
+             hipLaunchKernelGGL((fd_gen16<T>), dim3(blocks, ks), dim3(256), 0, st, static_cast<const T*>(psi), ldpsi,
+                                dp.d_xg, hp.J, hp.K, dp.Kp, c, ldc, static_cast<int>(Lc), hp.P, alpha, nw, nxt, pps,
+                                Lpad));
+    }
   } else if (Lc > 128) {
     const int nxt = static_cast<int>((Lc + 255) / 256);
     const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(nw) * nxt, 8));

@@ -10,8 +10,9 @@ N = 2048.
   maps written by tests/golden/make_disc32_slri.py (oracle only);
 * conv. FD-SRP with the steering generated inside the product (the only FD
   form at this size: a resident H would take 406 GB in BF16), a
-  contraction over 2 P (K-1) = 1,014,816, on the subgrid and at sampled
-  candidates of the full grid.
+  contraction over 2 P (K-1) = 1,014,816, on the subgrid (6 and 150
+  frames: both generating kernels) and at sampled candidates of the full
+  grid.
 
 Every check bounds the relative L2 error and every element relative to the
 map's largest oracle magnitude."""
@@ -28,7 +29,7 @@ from paper_2306_08514_amd import scenes
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TOL = {"f32": 1e-5, "bf16": 1e-2}
+TOL = {"f32": 1e-5, "bf16": 1e-2, "f16": 1e-2}
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "disc32_slri_r8.npz")
 
 
@@ -121,6 +122,24 @@ def test_fd_generated_subgrid_all_outputs(native, small, dtype):
     ref = o.fd_map(o.phat(Y), x, cfg["N"] // 2)
     check_maps(z, ref, TOL[dtype], f"disc32 subgrid fd generated {dtype}")
     p.close()
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_fd_generated_subgrid_large_batch(native, dtype):
+    """More than 128 frames per call run the 16-bit kernel that generates the
+    steering between its matrix instructions; on one candidate tile the
+    contraction is also split at pair boundaries.  Every output of 150 frames
+    (one ragged frame tile) against the oracle."""
+    cfg = scenes.workload("disc32_box200k", L=150, grid_stride=10)
+    Y = scenes.make_frames(cfg)
+    _announce(f"disc32 subgrid fd generated L=150 {dtype}")
+    p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], "fd", 0, dtype=dtype,
+                    fd_steering="generated")
+    z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
+    p.close()
+    x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
+    ref = o.fd_map(o.phat(Y), x, cfg["N"] // 2)
+    check_maps(z, ref, TOL[dtype], f"disc32 subgrid fd generated L=150 {dtype}")
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
