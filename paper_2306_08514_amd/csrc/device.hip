@@ -1038,7 +1038,12 @@ __global__ __launch_bounds__(256) void transpose_lp(const float* __restrict__ xi
 // and the quarters are added in LDS.  Four waves per product hide the LDS
 // latency that one wave per SIMD left exposed (measured: 44 us against 49
 // with two waves per product and 55 with four loader waves feeding eight
-// multiplying ones, room workload, 125,000 candidates).  The frames and the table are read once per block (the
+// multiplying ones, room workload, 125,000 candidates).  SPLIT (plans with
+// 16-bit or FP8 operands, whose later stages round far coarser): the
+// products run on v_mfma_f32_32x32x16_bf16 with psi and the table split
+// into BF16 (hi, lo) halves (the table's halves precomputed: per 4 bins 16
+// bytes of hi then 16 of lo, the byte layout of the FP32 table), three
+// products per step in place of 16 FP32 ones per 8 bins.  The frames and the table are read once per block (the
 // table is shared by every pair), and the next chunk is loaded into
 // registers while the current one is multiplied.  Every frame runs the same
 // instruction sequence, so its samples do not depend on the batch.
@@ -1048,7 +1053,7 @@ constexpr int GD_FM = 64;                 // max frames x microphones per block
 constexpr int GD_TILES = 4;               // products per block (each split over four waves)
 constexpr int GD_NCT = 4;                 // max 32-lag column tiles (2 max_np + 1 <= 128)
 
-template <int NCT>
+template <int NCT, bool SPLIT>
 __global__ __launch_bounds__(1024) void gcc_direct(const float2* __restrict__ Y, int M, int K, int L, int P,
                                                   const int32_t* __restrict__ pm, const int32_t* __restrict__ pmp,
                                                   const int32_t* __restrict__ np, const int32_t* __restrict__ off,
@@ -1147,7 +1152,43 @@ __global__ __launch_bounds__(1024) void gcc_direct(const float2* __restrict__ Y,
     lstore();
     __syncthreads();
     if (c + 1 < nchunks) gload(c + 1);
-    if (tlive) {
+    if (SPLIT && tlive) {
+      // split BF16 on v_mfma_f32_32x32x16_bf16: step j covers 8 bins of the
+      // wave's quarter, k slot kq its bins 4 kq .. 4 kq + 3 (Re, Im of
+      // each); psi = ah + al and the table's (hi, lo) halves give
+      // ah th + ah tl + al th, all products exact in FP32, the dropped
+      // al tl and the rounding of al leave ~2^-16 of each term
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int o = 8 * (8 * j + 4 * kq);
+        const f32x4 x0 = *reinterpret_cast<const f32x4*>(u_lds + ta + o);
+        const f32x4 x1 = *reinterpret_cast<const f32x4*>(u_lds + ta + o + 16);
+        const f32x4 y0 = *reinterpret_cast<const f32x4*>(u_lds + tb + o);
+        const f32x4 y1 = *reinterpret_cast<const f32x4*>(u_lds + tb + o + 16);
+        const i32x4 th = *reinterpret_cast<const i32x4*>(s_lds + tcol + o);
+        const i32x4 tl = *reinterpret_cast<const i32x4*>(s_lds + tcol + o + 16);
+        float a[8];
+        // psi = u_m conj(u_m') of four bins
+        a[0] = __builtin_fmaf(x0.x, y0.x, x0.y * y0.y);
+        a[1] = __builtin_fmaf(x0.y, y0.x, -(x0.x * y0.y));
+        a[2] = __builtin_fmaf(x0.z, y0.z, x0.w * y0.w);
+        a[3] = __builtin_fmaf(x0.w, y0.z, -(x0.z * y0.w));
+        a[4] = __builtin_fmaf(x1.x, y1.x, x1.y * y1.y);
+        a[5] = __builtin_fmaf(x1.y, y1.x, -(x1.x * y1.y));
+        a[6] = __builtin_fmaf(x1.z, y1.z, x1.w * y1.w);
+        a[7] = __builtin_fmaf(x1.w, y1.z, -(x1.z * y1.w));
+        bf16x8 ah, al;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          ah[i] = static_cast<__bf16>(a[i]);
+          al[i] = static_cast<__bf16>(a[i] - static_cast<float>(ah[i]));
+        }
+        const bf16x8 bh = __builtin_bit_cast(bf16x8, th), bl = __builtin_bit_cast(bf16x8, tl);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+      }
+    } else if (tlive) {
       // k slot kq of four steps covers bins b + 2 kq and b + 2 kq + 1 (Re,
       // then Im of each): a lane reads its own two bins of u_m, u_m' and of
       // its lag's table row, 16 bytes each per four products
@@ -2676,6 +2717,19 @@ struct Alloc {
   }
 };
 
+// BF16 of an FP32 value, round to nearest even (finite inputs), and back
+inline uint16_t bf16_rne(float v) {
+  uint32_t u;
+  std::memcpy(&u, &v, 4);
+  return static_cast<uint16_t>((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+inline float bf16_float(uint16_t h) {
+  const uint32_t u = static_cast<uint32_t>(h) << 16;
+  float v;
+  std::memcpy(&v, &u, 4);
+  return v;
+}
+
 template <typename T>
 void upload(void* dst, const std::vector<T>& v) {
   HIP_OK(hipMemcpy(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -3698,6 +3752,20 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     }
     dp.d_S = static_cast<float*>(A.get(S.size() * 4));
     upload(dp.d_S, S);
+    if (hp.dtype != SRP_F32 && hp.dtype != SRP_F64) {
+      // BF16 (hi, lo) halves for the split products: per 4 bins (8 values)
+      // 16 bytes of hi then 16 of lo, the FP32 table's byte layout
+      std::vector<uint16_t> S16(S.size() * 2);
+      for (size_t q = 0; q < S.size() / 8; ++q)
+        for (int i = 0; i < 8; ++i) {
+          const float v = S[8 * q + i];
+          const uint16_t h = bf16_rne(v);
+          S16[16 * q + i] = h;
+          S16[16 * q + 8 + i] = bf16_rne(v - bf16_float(h));
+        }
+      dp.d_S16 = A.get(S16.size() * 2);
+      upload(static_cast<uint16_t*>(dp.d_S16), S16);
+    }
     // frames per block: about four 32-row tiles of (frame, pair) rows, at
     // most GD_FM (frame, microphone) rows of u in LDS
     dp.gd_ft = std::max(1, std::min(128 / P, GD_FM / hp.M));
@@ -3927,7 +3995,7 @@ void device_free(DevicePlan& dp) {
     (void)hipEventDestroy(sp.stop);
   }
   for (hipEvent_t e : dp.event_pool) (void)hipEventDestroy(e);
-  void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_tw, dp.d_w2,
+  void* ptrs[] = {dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, dp.d_H, dp.d_S, dp.d_S16, dp.d_tw, dp.d_w2,
                   dp.d_U, dp.d_V, dp.d_gscale, dp.d_F, dp.d_start, dp.d_w, dp.d_win, dp.d_xg, dp.d_B,
                   dp.d_ctab, dp.d_colmap, dp.d_dtiles, dp.d_gtiles, dp.d_bdesc, dp.d_bnext, dp.d_border, dp.ws};
   for (void* p : ptrs)
@@ -4204,7 +4272,9 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
 
 // Direct GCC sampling (40) straight from the frames into xi^T [PN][ldxi].
 void launch_slices(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t Lc, float* xiT, int64_t ldxi,
-                   hipStream_t st) {
+                   hipStream_t st, bool exact) {
+  // split BF16 products for 16-bit and FP8 plans (not for the FP32 export)
+  const bool split = !exact && dp.d_S16 != nullptr;
   const int ft = dp.gd_ft;
   const int nrt = (ft * hp.P + 31) / 32;
   const int ntiles = nrt * dp.gd_nct;
@@ -4213,14 +4283,15 @@ void launch_slices(const HostPlan& hp, DevicePlan& dp, const void* frames, int64
   const size_t lds = static_cast<size_t>(GD_FM + 1 + 32 * NCT) * GD_ROWB;
 #define SRP_GD(NC)                                                                                            \
   do {                                                                                                        \
-    auto kern = &gcc_direct<NC>;                                                                              \
+    auto kern = split ? &gcc_direct<NC, true> : &gcc_direct<NC, false>;                                      \
     if (lds > 65536)                                                                                          \
       HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),                                         \
                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));         \
     TRACED(dp, "gcc_direct", st,                                                                              \
            hipLaunchKernelGGL(kern, grid, dim3(1024), lds, st, static_cast<const float2*>(frames), hp.M, hp.K,  \
                               static_cast<int>(Lc), hp.P, dp.d_pm, dp.d_pmp, dp.d_np, dp.d_off, hp.max_np,    \
-                              dp.d_S, dp.gd_kb, ft, nrt, dp.gd_nct, xiT, ldxi));                              \
+                              split ? static_cast<const float*>(dp.d_S16) : dp.d_S, dp.gd_kb, ft, nrt,       \
+                              dp.gd_nct, xiT, ldxi));                                                         \
   } while (0)
   if (NCT == 1)
     SRP_GD(1);
@@ -4252,7 +4323,7 @@ void launch_fat(const HostPlan& hp, DevicePlan& dp, const float* xiT, int64_t ld
 
 template <int MODE, typename TG>
 void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_t Lc, float* xiT, int64_t ldxi,
-                  float* part, void* g, hipStream_t st, bool lag_major = true) {
+                  float* part, void* g, hipStream_t st, bool lag_major = true, bool exact = false) {
   if (hp.fft) {
     const dim3 grid(static_cast<unsigned>(Lc * hp.P));
 #define SRP_FFT(LK)                                                                                           \
@@ -4274,7 +4345,7 @@ void launch_front(const HostPlan& hp, DevicePlan& dp, const void* frames, int64_
            hipLaunchKernelGGL(transpose_lp, tgrid, dim3(256), 0, st, part, static_cast<int64_t>(hp.PN),
                               static_cast<int>(Lc), hp.PN, xiT, ldxi));
   } else {
-    launch_slices(hp, dp, frames, Lc, xiT, ldxi, st);
+    launch_slices(hp, dp, frames, Lc, xiT, ldxi, st, exact);
   }
   if constexpr (MODE == 1) {
     launch_fat<TG>(hp, dp, xiT, ldxi, Lc, g, st);
@@ -4610,7 +4681,7 @@ void device_gcc_samples(const HostPlan& hp, DevicePlan& dp, const void* frames, 
     const void* fr = static_cast<const float2*>(frames) + l0 * frame_elems;
     float* xiT = reinterpret_cast<float*>(base + lay.xi);
     float* part = reinterpret_cast<float*>(base + lay.part);
-    launch_front<0, float>(hp, dp, fr, Lc, xiT, lay.Lpad, part, nullptr, st);
+    launch_front<0, float>(hp, dp, fr, Lc, xiT, lay.Lpad, part, nullptr, st, true, true);  // FP32 samples
     const int64_t n = static_cast<int64_t>(hp.PN) * Lc;
     TRACED(dp, "transpose_xi", st,
            hipLaunchKernelGGL(transpose_xi, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,

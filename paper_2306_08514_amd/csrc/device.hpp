@@ -37,6 +37,7 @@ struct DevicePlan {
   double* d_xg = nullptr;    // [P][J] TDOAs in samples (generated steering)
   // sampling (SLRI, SSPI)
   float* d_S = nullptr;       // direct sampling: iDFT table [gd_nct 32][2 gd_kb], rows 2 cos / -2 sin
+  void* d_S16 = nullptr;      // its BF16 (hi, lo) halves, per 4 bins 16 B hi + 16 B lo (16-bit, FP8 plans)
   int gd_kb = 0;              // bins per table row: K - 1 rounded up to the kernel's chunk
   int gd_nct = 0;             // 32-lag column tiles of the table
   int gd_ft = 0;              // frames per block of the direct sampling kernel
