@@ -82,8 +82,12 @@ typedef enum {
 /* Operand precision of the dominant contraction (steering matrix for FD, the
  * tall factor U for SLRI, the interpolation weights for SSPI).  Accumulation
  * is FP32 (FP64 for SRP_F64).  Cross-spectra, GCC samples and the SLRI fat
- * stage are computed in FP32 for every dtype; the SLRI fat stage's output g
- * is then narrowed to the operand type.  SSPI with 16-bit or FP8 weights
+ * stage are computed in FP32 for every dtype, except that with 16-bit or FP8
+ * operands the direct sampling (40) multiplies split BF16 (hi, lo) halves of
+ * the cross-spectra and of its table on the matrix cores (FP32 accumulation,
+ * ~1e-5 relative per term; srp_gcc_samples always returns the FP32
+ * products); the SLRI fat stage's output g is then narrowed to the operand
+ * type.  SSPI with 16-bit or FP8 weights
  * reads the GCC samples narrowed to 16 bits: BF16 (BF16 weights) or FP16
  * (FP16 weights) frame-major copies where a candidate tile runs on the
  * matrix cores, FP16 sample pairs in the gather.  FP8 is OCP E4M3: SLRI
@@ -261,7 +265,8 @@ srp_status srp_crossspec(srp_plan_t plan, const void* frames, int64_t L,
                          void* psi, void* stream);
 
 /* Stage entry point: GCC samples xi_p[n], n = -N_p..N_p, of L frames
- * (eq. (40)), pairs stacked in order, lags in natural order.
+ * (eq. (40)), pairs stacked in order, lags in natural order, from FP32
+ * products whatever the plan's dtype.
  *   xi   device, float32 [L][PN]
  * Only for SLRI and SSPI plans (the sampling stage exists only there). */
 srp_status srp_gcc_samples(srp_plan_t plan, const void* frames, int64_t L,
