@@ -452,12 +452,14 @@ __global__ __launch_bounds__(256) void gemm_nt(const GemmBatch* __restrict__ bat
 // 128-byte K slice of the BW = 256 rows of H is computed into LDS instead of
 // read: slots 2 (k - 1), 2 (k - 1) + 1 of pair p hold cos theta, -sin theta,
 // theta = pi k x_p(j) / K (eq. (19) with (14)).  A thread fills the BINS
-// consecutive bins of its row in the slice: at the first slice of a pair its
-// first angle is reduced in FP64 (t = k x / 2K, theta = 2 pi (t - rint t))
-// and evaluated by sincospi; each further slice of the pair advances that
-// FP64 value by one rotation of BPS bins (at most K / BPS rotations, error
-// ~1e-15); within a slice the bins follow by FP32 rotation by
-// exp(+i pi x / K), a chain of at most BINS - 1 steps.
+// consecutive bins of its row in the slice, in groups of 16: at the first
+// slice of a pair the angle of bin 1 is reduced in FP64 (t = x / 2K,
+// theta = 2 pi (t - rint t)) and evaluated by sincospi; each further group
+// starts from that FP64 value advanced by one rotation of 16 bins per group
+// (at most K / 16 rotations, error ~1e-15), and within a group the bins
+// follow by FP32 rotation by exp(+i pi x / K), a chain of 15 steps.  This
+// is the sequence fd_gen16 generates, so that a frame's map is the same
+// whichever of the two kernels its batch size selects.
 //
 // With blockIdx.y the contraction is split at pair boundaries (plans with
 // few candidate tiles), each split writing its partial product.
@@ -574,33 +576,37 @@ __global__ __launch_bounds__(256) void fd_gen(const T* __restrict__ X, int64_t l
       const int e0 = kb / static_cast<int>(sizeof(T));  // first element of the slice in the row
       const int p = e0 / Kp;
       const int kfirst = (e0 % Kp) / 2 + 1 + gpart * BINS;  // first bin of this thread
+      static_assert(BINS % 16 == 0 && TPR == 1, "16-bin seed groups, one row per thread");
       if (glive && e0 % Kp == 0) {
+        // the pair's first slice (kfirst = 1): seed bin 1, the one-bin FP32
+        // step and the 16-bin FP64 advance, as fd_gen16 takes them
         gx = xg[static_cast<int64_t>(p) * J + gj];
-        const double t = static_cast<double>(kfirst) * gx / (2.0 * K);
+        const double t = gx / (2.0 * K);
         sincospi(2.0 * (t - rint(t)), &gs_s, &gs_c);
-        const double u = gx / (2.0 * K);
-        double su, cu;
-        sincospi(2.0 * (u - rint(u)), &su, &cu);
-        gstep_c = static_cast<float>(cu);
-        gstep_s = static_cast<float>(su);
-        const double v = static_cast<double>(BPS) * gx / (2.0 * K);
+        gstep_c = static_cast<float>(gs_c);
+        gstep_s = static_cast<float>(gs_s);
+        const double v = 16.0 * gx / (2.0 * K);
         sincospi(2.0 * (v - rint(v)), &gadv_s, &gadv_c);
-      } else if (glive) {
-        const double cn = gs_c * gadv_c - gs_s * gadv_s;
-        gs_s = gs_c * gadv_s + gs_s * gadv_c;
-        gs_c = cn;
       }
       T vals[2 * BINS];
-      float c = static_cast<float>(gs_c), sn = static_cast<float>(gs_s);
 #pragma unroll
-      for (int b = 0; b < BINS; ++b) {
-        const bool ok = glive && kfirst + b <= K - 1;
-        vals[2 * b] = cvt<T>(ok ? c : 0.0f);
-        vals[2 * b + 1] = cvt<T>(ok ? -sn : 0.0f);
-        // (c + i s) <- (c + i s)(step_c + i step_s)
-        const float cn = __builtin_fmaf(c, gstep_c, -(sn * gstep_s));
-        sn = __builtin_fmaf(c, gstep_s, sn * gstep_c);
-        c = cn;
+      for (int q = 0; q < BINS / 16; ++q) {
+        // each 16 bins start from the FP64 seed, which then advances by 16
+        // bins (explicit fma, so that fd_gen16 reproduces every value)
+        float c = static_cast<float>(gs_c), sn = static_cast<float>(gs_s);
+        const double cn = __builtin_fma(gs_c, gadv_c, -(gs_s * gadv_s));
+        gs_s = __builtin_fma(gs_c, gadv_s, gs_s * gadv_c);
+        gs_c = cn;
+#pragma unroll
+        for (int b = 16 * q; b < 16 * q + 16; ++b) {
+          const bool ok = glive && kfirst + b <= K - 1;
+          vals[2 * b] = cvt<T>(ok ? c : 0.0f);
+          vals[2 * b + 1] = cvt<T>(ok ? -sn : 0.0f);
+          // (c + i s) <- (c + i s)(step_c + i step_s)
+          const float cf = __builtin_fmaf(c, gstep_c, -(sn * gstep_s));
+          sn = __builtin_fmaf(c, gstep_s, sn * gstep_c);
+          c = cf;
+        }
       }
       unsigned char* dst = lds + (BX + gr) * ROWB + gpart * (BKB / TPR);
 #pragma unroll
@@ -732,8 +738,9 @@ __global__ __launch_bounds__(256) void fd_gen16(const T* __restrict__ X, int64_t
     cc = static_cast<float>(sc);
     cs = static_cast<float>(ss);
     kfirst = (g % spp) * 16 + 1;
-    const double cn = sc * ac - ss * as;
-    ss = sc * as + ss * ac;
+    // explicit fma: fd_gen reproduces the same seeds
+    const double cn = __builtin_fma(sc, ac, -(ss * as));
+    ss = __builtin_fma(sc, as, ss * ac);
     sc = cn;
   };
   // bins 8 h .. 8 h + 7 of stage g: chunks 2 h, 2 h + 1 of row tid
@@ -1044,7 +1051,7 @@ __global__ __launch_bounds__(256) void transpose_lp(const float* __restrict__ xi
 // into BF16 (hi, lo) halves (the table's halves precomputed: per 4 bins 16
 // bytes of hi then 16 of lo, the byte layout of the FP32 table), three
 // products per step in place of 16 FP32 ones per 8 bins.  The frames and the table are read once per block (the
-// table is shared by every pair), and the next chunk is loaded into
+// table is shared by every pair), and the chunk after next is loaded into
 // registers while the current one is multiplied.  Every frame runs the same
 // instruction sequence, so its samples do not depend on the batch.
 constexpr int GD_CB = 64;                 // bins per chunk
@@ -1090,12 +1097,13 @@ __global__ __launch_bounds__(1024) void gcc_direct(const float2* __restrict__ Y,
 
   constexpr int UPT = GD_FM * (GD_CB / 2) / NT;     // bin pairs of u per thread
   constexpr int SPT = NCT * 32 * (GD_CB / 2) / NT;  // 16-byte table pieces per thread
-  f32x4 uy[UPT], sv[SPT];
+  // two register sets: the loads run two chunks ahead of the multiplies
+  f32x4 uyA[UPT], svA[SPT], uyB[UPT], svB[SPT];
   const int uitems = fm_rows * (GD_CB / 2);
   constexpr int sitems = NCT * 32 * (GD_CB / 2);  // rows past nct 32 are zero in the table
   const int nchunks = Kb / GD_CB;
 
-  auto gload = [&](int c) {
+  auto gload = [&](int c, f32x4 (&uy)[UPT], f32x4 (&sv)[SPT]) {
 #pragma unroll
     for (int i = 0; i < UPT; ++i) {
       const int e = tid + NT * i;
@@ -1124,7 +1132,7 @@ __global__ __launch_bounds__(1024) void gcc_direct(const float2* __restrict__ Y,
       sv[i] = *reinterpret_cast<const f32x4*>(S + static_cast<int64_t>(row) * (2 * Kb) + 2 * c * GD_CB + 4 * q);
     }
   };
-  auto lstore = [&]() {
+  auto lstore = [&](const f32x4 (&uy)[UPT], const f32x4 (&sv)[SPT]) {
 #pragma unroll
     for (int i = 0; i < UPT; ++i) {
       const int e = tid + NT * i;
@@ -1146,12 +1154,7 @@ __global__ __launch_bounds__(1024) void gcc_direct(const float2* __restrict__ Y,
   f32x16 acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-  gload(0);
-  for (int c = 0; c < nchunks; ++c) {
-    __syncthreads();  // the previous chunk's reads are done
-    lstore();
-    __syncthreads();
-    if (c + 1 < nchunks) gload(c + 1);
+  auto multiply = [&]() {
     if (SPLIT && tlive) {
       // split BF16 on v_mfma_f32_32x32x16_bf16: step j covers 8 bins of the
       // wave's quarter, k slot kq its bins 4 kq .. 4 kq + 3 (Re, Im of
@@ -1206,6 +1209,22 @@ __global__ __launch_bounds__(1024) void gcc_direct(const float2* __restrict__ Y,
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(re1, sc.z, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(im1, sc.w, acc, 0, 0, 0);
       }
+    }
+  };
+  gload(0, uyA, svA);
+  if (1 < nchunks) gload(1, uyB, svB);
+  for (int c = 0; c < nchunks; c += 2) {
+    __syncthreads();  // the previous chunk's reads are done
+    lstore(uyA, svA);
+    __syncthreads();
+    if (c + 2 < nchunks) gload(c + 2, uyA, svA);
+    multiply();
+    if (c + 1 < nchunks) {
+      __syncthreads();
+      lstore(uyB, svB);
+      __syncthreads();
+      if (c + 3 < nchunks) gload(c + 3, uyB, svB);
+      multiply();
     }
   }
   // the other quarters' partial tiles through LDS (the u buffer is free now)

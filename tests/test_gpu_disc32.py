@@ -129,13 +129,19 @@ def test_fd_generated_subgrid_large_batch(native, dtype):
     """More than 128 frames per call run the 16-bit kernel that generates the
     steering between its matrix instructions; on one candidate tile the
     contraction is also split at pair boundaries.  Every output of 150 frames
-    (one ragged frame tile) against the oracle."""
+    (one ragged frame tile) against the oracle, and bitwise against the same
+    frames in batches that run the small-batch kernel."""
     cfg = scenes.workload("disc32_box200k", L=150, grid_stride=10)
     Y = scenes.make_frames(cfg)
     _announce(f"disc32 subgrid fd generated L=150 {dtype}")
     p = native.Plan(cfg["mics"], cfg["grid"], cfg["fs"], cfg["N"], "fd", 0, dtype=dtype,
                     fd_steering="generated")
     z = p.compute(torch.from_numpy(Y).cuda()).cpu().numpy()
+    # batches of at most 128 frames run the other generating kernel: the
+    # same steering values and products, so the same maps bit for bit
+    for a, b in ((0, 64), (100, 150)):
+        part = p.compute(torch.from_numpy(np.ascontiguousarray(Y[a:b])).cuda()).cpu().numpy()
+        np.testing.assert_array_equal(part, z[a:b])
     p.close()
     x = o.tdoa_samples(cfg["mics"], cfg["grid"], cfg["fs"], cfg["c"])
     ref = o.fd_map(o.phat(Y), x, cfg["N"] // 2)
