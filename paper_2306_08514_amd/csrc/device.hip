@@ -447,6 +447,23 @@ __global__ __launch_bounds__(256) void gemm_nt(const GemmBatch* __restrict__ bat
     }
 }
 
+// The generated-steering seeds of one (pair, candidate): bin 1, (cos,
+// sin)(pi x / K), and the 16-bin advance (cos, sin)(16 pi x / K), each phase
+// reduced in FP64 (t - rint t) before sincospi.  Not inlined, so that both
+// generating kernels run the same instructions (inlined, the FP64 sincospi
+// was contracted differently and a few seeds differed in the last bit).
+struct FdSeed {
+  double s1, c1, s16, c16;
+};
+__device__ __noinline__ FdSeed fd_gen_seed(double x, int K) {
+  FdSeed r;
+  const double t = x / (2.0 * K);
+  sincospi(2.0 * (t - rint(t)), &r.s1, &r.c1);
+  const double v = 16.0 * x / (2.0 * K);
+  sincospi(2.0 * (v - rint(v)), &r.s16, &r.c16);
+  return r;
+}
+
 // conv. FD-SRP with the steering operand generated on the fly (plans whose
 // H would not fit in HBM): z = alpha (psi H^T) as in gemm_nt, but each
 // 128-byte K slice of the BW = 256 rows of H is computed into LDS instead of
@@ -581,12 +598,13 @@ __global__ __launch_bounds__(256) void fd_gen(const T* __restrict__ X, int64_t l
         // the pair's first slice (kfirst = 1): seed bin 1, the one-bin FP32
         // step and the 16-bin FP64 advance, as fd_gen16 takes them
         gx = xg[static_cast<int64_t>(p) * J + gj];
-        const double t = gx / (2.0 * K);
-        sincospi(2.0 * (t - rint(t)), &gs_s, &gs_c);
+        const FdSeed sd = fd_gen_seed(gx, K);
+        gs_s = sd.s1;
+        gs_c = sd.c1;
+        gadv_s = sd.s16;
+        gadv_c = sd.c16;
         gstep_c = static_cast<float>(gs_c);
         gstep_s = static_cast<float>(gs_s);
-        const double v = 16.0 * gx / (2.0 * K);
-        sincospi(2.0 * (v - rint(v)), &gadv_s, &gadv_c);
       }
       T vals[2 * BINS];
 #pragma unroll
@@ -663,8 +681,11 @@ __global__ __launch_bounds__(256) void fd_gen(const T* __restrict__ X, int64_t l
     }
 }
 
-// 16-bit conv. FD-SRP with generated steering for large batches: the tiles,
-// LDS stages, bank swizzle and software pipeline of gemm_fd16, with the
+// 16-bit conv. FD-SRP with generated steering: the tiles (BXF = 256 frames
+// for batches of more than 128, 64 frames for smaller ones, either way 256
+// candidates and the same generation code, so a frame's map does not depend
+// on its batch), LDS stages, bank swizzle and software pipeline of gemm_fd16,
+// with the
 // cross-spectra (tile-major, fd16_tiled) streamed through a ring of FG_NBX
 // stages and the steering stage generated into one of FG_NBH LDS buffers
 // two stages before the MFMAs read it, half a stage per MFMA step, so that
@@ -678,22 +699,27 @@ __global__ __launch_bounds__(256) void fd_gen(const T* __restrict__ X, int64_t l
 constexpr int FG_NBX = 6, FG_NBH = 3;
 constexpr int FG_XST = FD16_TILE * FD16_SB;  // 16 KB: one operand's stage
 
-template <typename T>
+template <typename T, int BXF>
 __global__ __launch_bounds__(256) void fd_gen16(const T* __restrict__ X, int64_t ldx,
                                                 const double* __restrict__ xg, int64_t J, int K, int Kp,
                                                 float* __restrict__ C, int64_t ldc, int nx, int P, float alpha,
                                                 int nw_tiles, int nx_tiles, int pps, int64_t cz_rows) {
   static_assert(sizeof(T) == 2, "16-bit operands");
+  static_assert(BXF == 256 || BXF == 64, "256- or 64-frame tiles");
   constexpr int STEP = Mfma<T>::STEP, LB = STEP / 2;
-  constexpr int NL = FG_XST / 1024 / 4;  // loads per wave per stage
+  // waves: 2 x 2 of 128 x 128 (256-frame tiles) or 1 x 4 of 64 x 64
+  constexpr int WGY = BXF == 256 ? 2 : 1, WGX = 4 / WGY;
+  constexpr int NA = BXF / WGY / 32, NB = FD16_TILE / WGX / 32;  // 32 x 32 blocks per wave
+  constexpr int XST = BXF * FD16_SB;     // a cross-spectra stage
+  constexpr int NL = XST / 1024 / 4;     // its loads per wave
   static_assert((FG_NBX - 1) * NL < 64, "vmcnt holds at most 63 loads");
-  static_assert((FG_NBX + FG_NBH) * FG_XST <= 160 * 1024, "LDS");
-  __shared__ __attribute__((aligned(16))) unsigned char lds[(FG_NBX + FG_NBH) * FG_XST];
-  unsigned char* const hb = lds + FG_NBX * FG_XST;
+  static_assert(FG_NBX * XST + FG_NBH * FG_XST <= 160 * 1024, "LDS");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[FG_NBX * XST + FG_NBH * FG_XST];
+  unsigned char* const hb = lds + FG_NBX * XST;
 
   int wt, xt;
   if (!xcd_tile(nw_tiles, nx_tiles, wt, xt)) return;  // uniform over the block
-  const int x0 = xt * FD16_TILE, w0 = wt * FD16_TILE;
+  const int x0 = xt * BXF, w0 = wt * FD16_TILE;
   if (x0 >= nx) return;
   const int p0 = static_cast<int>(blockIdx.y) * pps, p1 = min(P, p0 + pps);
   if (p0 >= p1) return;
@@ -703,14 +729,18 @@ __global__ __launch_bounds__(256) void fd_gen16(const T* __restrict__ X, int64_t
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // cross-spectra loads: wave w fills rows 64 w .. 64 w + 63 of a stage
+  // cross-spectra loads: psi is tile-major in 256-row tiles (fd16_tiled), so
+  // a 64-frame tile is a contiguous quarter of each 16 KB stage; wave w
+  // fills rows 16 NL w .. 16 NL (w + 1) - 1 of the tile's stage
   const int64_t nstg = ldx * 2 / FD16_SB;
-  const unsigned char* src = reinterpret_cast<const unsigned char*>(X) +
-                             ((static_cast<int64_t>(xt) * nstg + static_cast<int64_t>(p0) * spp) * FD16_TILE + 64 * wave) *
-                                 FD16_SB +
-                             16 * lane;
+  const unsigned char* src =
+      reinterpret_cast<const unsigned char*>(X) +
+      ((static_cast<int64_t>(x0 / FD16_TILE) * nstg + static_cast<int64_t>(p0) * spp) * FD16_TILE + x0 % FD16_TILE +
+       16 * NL * wave) *
+          FD16_SB +
+      16 * lane;
   auto issue = [&](int s) {
-    unsigned char* dst = lds + (s % FG_NBX) * FG_XST + wave * NL * 1024;
+    unsigned char* dst = lds + (s % FG_NBX) * XST + wave * NL * 1024;
     const unsigned char* sp = src + static_cast<int64_t>(min(s, ns - 1)) * FG_XST;
 #pragma unroll
     for (int i = 0; i < NL; ++i)
@@ -727,12 +757,13 @@ __global__ __launch_bounds__(256) void fd_gen16(const T* __restrict__ X, int64_t
   int kfirst = 1;
   auto seed_pair = [&](int p) {
     const double x = glive ? xg[static_cast<int64_t>(p) * J + gj] : 0.0;
-    const double t = x / (2.0 * K);  // bin 1: theta = pi x / K
-    sincospi(2.0 * (t - rint(t)), &ss, &sc);
+    const FdSeed sd = fd_gen_seed(x, K);  // bin 1 (theta = pi x / K) and the 16-bin advance
+    ss = sd.s1;
+    sc = sd.c1;
+    as = sd.s16;
+    ac = sd.c16;
     fc = static_cast<float>(sc);
     fs = static_cast<float>(ss);
-    const double v = 16.0 * x / (2.0 * K);
-    sincospi(2.0 * (v - rint(v)), &as, &ac);
   };
   auto gen_begin = [&](int g) {
     cc = static_cast<float>(sc);
@@ -768,38 +799,38 @@ __global__ __launch_bounds__(256) void fd_gen16(const T* __restrict__ X, int64_t
   };
 
   const int r32 = lane & 31, g = lane >> 5;
-  const int wy = wave >> 1, wx = wave & 1;
-  f32x16 acc[4][4];
+  const int wy = wave / WGX, wx = wave % WGX;
+  f32x16 acc[NA][NB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < NA; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
   const int sw = fd16_swz(r32 & 15);
-  const int xrow = (wy * 128 + r32) * FD16_SB, wrow = (wx * 128 + r32) * FD16_SB;
-  auto frags = [&](int s, auto tc, i32x4 (&fa)[4], i32x4 (&fb)[4]) {
+  const int xrow = (wy * 32 * NA + r32) * FD16_SB, wrow = (wx * 32 * NB + r32) * FD16_SB;
+  auto frags = [&](int s, auto tc, i32x4 (&fa)[NA], i32x4 (&fb)[NB]) {
     constexpr int t = decltype(tc)::value;
-    const unsigned char* bx = lds + (s % FG_NBX) * FG_XST;
+    const unsigned char* bx = lds + (s % FG_NBX) * XST;
     const unsigned char* bw = hb + (s % FG_NBH) * FG_XST;
     const int pos = 16 * (((t * STEP) / 16 + g) ^ sw);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) fa[a] = *reinterpret_cast<const i32x4*>(bx + xrow + pos + a * 32 * FD16_SB);
+    for (int a = 0; a < NA; ++a) fa[a] = *reinterpret_cast<const i32x4*>(bx + xrow + pos + a * 32 * FD16_SB);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) fb[b] = *reinterpret_cast<const i32x4*>(bw + wrow + pos + b * 32 * FD16_SB);
+    for (int b = 0; b < NB; ++b) fb[b] = *reinterpret_cast<const i32x4*>(bw + wrow + pos + b * 32 * FD16_SB);
   };
-  auto mfmas = [&](const i32x4 (&fa)[4], const i32x4 (&fb)[4]) {
+  auto mfmas = [&](const i32x4 (&fa)[NA], const i32x4 (&fb)[NB]) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < NA; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) Mfma<T>::run(&fa[a], &fb[b], acc[a][b]);
+      for (int b = 0; b < NB; ++b) Mfma<T>::run(&fa[a], &fb[b], acc[a][b]);
   };
   // MFMA step t of consumption stage s (fragments in ca, cb) while half h = t
   // of generation stage s + 2 is written; at t = 1 the barrier publishes
   // stage s + 1 (its cross-spectra landed: NBX - 2 later stages may stay in
   // flight; its steering was written during stage s - 1) and the ring slot
   // of stage s takes stage s + NBX.
-  auto step = [&](int s, auto tc, i32x4 (&ca)[4], i32x4 (&cb)[4], i32x4 (&na)[4], i32x4 (&nb)[4]) {
+  auto step = [&](int s, auto tc, i32x4 (&ca)[NA], i32x4 (&cb)[NB], i32x4 (&na)[NA], i32x4 (&nb)[NB]) {
     constexpr int t = decltype(tc)::value;
     __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));  // this step's fragments (read one step ago)
     if constexpr (t == 0) {
@@ -817,10 +848,10 @@ __global__ __launch_bounds__(256) void fd_gen16(const T* __restrict__ X, int64_t
     // interleave: each MFMA followed by a few vector instructions of the
     // generation, the fragment reads and (t = 1) the loads
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < NA * NB; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-      __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);  // VALU
-      if (i < 8) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+      __builtin_amdgcn_sched_group_barrier(0x002, 80 / (NA * NB), 0);  // VALU
+      if (i < NA + NB) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
       if (t == 1 && i < NL) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -836,7 +867,7 @@ __global__ __launch_bounds__(256) void fd_gen16(const T* __restrict__ X, int64_t
   }
   wait_vm_lds<(FG_NBX - 1) * NL>();  // stage 0 has landed
   asm volatile("s_barrier" ::: "memory");
-  i32x4 fa0[4], fb0[4], fa1[4], fb1[4];
+  i32x4 fa0[NA], fb0[NB], fa1[NA], fb1[NB];
   frags(0, std::integral_constant<int, 0>{}, fa0, fb0);
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
@@ -850,18 +881,18 @@ __global__ __launch_bounds__(256) void fd_gen16(const T* __restrict__ X, int64_t
   }
   wait_vm_lds<0>();  // the reloads past the last stage
 
-  const int rbase = x0 + wy * 128 + 4 * g;
-  const int64_t cbase = static_cast<int64_t>(w0) + wx * 128 + r32;
+  const int rbase = x0 + wy * 32 * NA + 4 * g;
+  const int64_t cbase = static_cast<int64_t>(w0) + wx * 32 * NB + r32;
   float* cp = C + static_cast<int64_t>(rbase) * ldc + cbase;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int ro = a * 32 + 8 * (v / 4) + (v % 4);
       if (rbase + ro >= nx) continue;
       float* rp = cp + ro * ldc;
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < NB; ++b)
         if (cbase + b * 32 < J) rp[b * 32] = alpha * acc[a][b][v];
     }
 }
@@ -4093,8 +4124,7 @@ void phat_dispatch(const HostPlan& hp, DevicePlan& dp, const void* frames, int64
   const int kslots = dp.Kp / 2;
   // the resident-steering 16-bit and FP8 GEMM (gemm_fd16) and the 16-bit
   // generated-steering kernel for large batches (fd_gen16) read psi tile-major
-  const bool tiled = hp.variant == SRP_FD && dsize(dtype) <= 2 &&
-                     (!dp.fd_gen || (dsize(dtype) == 2 && L > 128));
+  const bool tiled = hp.variant == SRP_FD && dsize(dtype) <= 2 && (!dp.fd_gen || dsize(dtype) == 2);
   switch (dtype) {
     case SRP_F32: launch_phat<float, float>(hp, dp, frames, L, static_cast<float*>(out), ld_l, dp.Kp, kslots, st); break;
     case SRP_BF16: launch_phat<__bf16, float>(hp, dp, frames, L, static_cast<__bf16*>(out), ld_l, dp.Kp, kslots, st, tiled); break;
@@ -4211,17 +4241,24 @@ void launch_fd_gen(const HostPlan& hp, DevicePlan& dp, const void* psi, int64_t 
            hipLaunchKernelGGL((fd_gen<T, 64, 1, true>), dim3(blocks, ks), dim3(256), 0, st,
                               static_cast<const T*>(psi), ldpsi, dp.d_xg, hp.J, hp.K, dp.Kp, c, ldc,
                               static_cast<int>(Lc), kdim, alpha, nw, nxt, pps, Lpad));
-  } else if (Lc > 128 && sizeof(T) == 2) {
-    // 16-bit, large batches: generation overlapped with the MFMAs
+  } else if (sizeof(T) == 2) {
+    // 16-bit: generation overlapped with the MFMAs, 256- or 64-frame tiles
     if constexpr (sizeof(T) == 2) {
-      const int nxt = static_cast<int>((Lc + 255) / 256);
-      const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(nw) * nxt, 8));
       if ((static_cast<int64_t>(dp.Kp) * 2) % (2 * FD16_SB) != 0 || ldpsi * 2 % FD16_SB != 0)
         throw Error{SRP_E_UNSUPPORTED, "FD pair slots are not whole 128-byte rows"};
-      TRACED(dp, "fd_gen", st,
-             hipLaunchKernelGGL((fd_gen16<T>), dim3(blocks, ks), dim3(256), 0, st, static_cast<const T*>(psi), ldpsi,
-                                dp.d_xg, hp.J, hp.K, dp.Kp, c, ldc, static_cast<int>(Lc), hp.P, alpha, nw, nxt, pps,
-                                Lpad));
+      const int bxf = Lc > 128 ? 256 : 64;
+      const int nxt = static_cast<int>((Lc + bxf - 1) / bxf);
+      const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(nw) * nxt, 8));
+      if (bxf == 256)
+        TRACED(dp, "fd_gen", st,
+               hipLaunchKernelGGL((fd_gen16<T, 256>), dim3(blocks, ks), dim3(256), 0, st, static_cast<const T*>(psi),
+                                  ldpsi, dp.d_xg, hp.J, hp.K, dp.Kp, c, ldc, static_cast<int>(Lc), hp.P, alpha, nw, nxt,
+                                  pps, Lpad));
+      else
+        TRACED(dp, "fd_gen", st,
+               hipLaunchKernelGGL((fd_gen16<T, 64>), dim3(blocks, ks), dim3(256), 0, st, static_cast<const T*>(psi),
+                                  ldpsi, dp.d_xg, hp.J, hp.K, dp.Kp, c, ldc, static_cast<int>(Lc), hp.P, alpha, nw, nxt,
+                                  pps, Lpad));
     }
   } else if (Lc > 128) {
     const int nxt = static_cast<int>((Lc + 255) / 256);
