@@ -1081,10 +1081,12 @@ __global__ __launch_bounds__(256) void transpose_lp(const float* __restrict__ xi
 // products run on v_mfma_f32_32x32x16_bf16 with psi and the table split
 // into BF16 (hi, lo) halves (the table's halves precomputed: per 4 bins 16
 // bytes of hi then 16 of lo, the byte layout of the FP32 table), three
-// products per step in place of 16 FP32 ones per 8 bins.  The frames and the table are read once per block (the
-// table is shared by every pair), and the chunk after next is loaded into
-// registers while the current one is multiplied.  Every frame runs the same
-// instruction sequence, so its samples do not depend on the batch.
+// products per step in place of 16 FP32 ones per 8 bins (37 -> 29 us).
+// The frames and the table are read once per block (the table is shared
+// by every pair), and the next chunk is loaded into registers while the
+// current one is multiplied (two chunks ahead was slower: 35 us).  Every
+// frame runs the same instruction sequence, so its samples do not depend
+// on the batch.
 constexpr int GD_CB = 64;                 // bins per chunk
 constexpr int GD_ROWB = GD_CB * 8 + 16;   // bytes per LDS row (a (frame, mic) or a table row)
 constexpr int GD_FM = 64;                 // max frames x microphones per block
@@ -1128,8 +1130,7 @@ __global__ __launch_bounds__(1024) void gcc_direct(const float2* __restrict__ Y,
 
   constexpr int UPT = GD_FM * (GD_CB / 2) / NT;     // bin pairs of u per thread
   constexpr int SPT = NCT * 32 * (GD_CB / 2) / NT;  // 16-byte table pieces per thread
-  // two register sets: the loads run two chunks ahead of the multiplies
-  f32x4 uyA[UPT], svA[SPT], uyB[UPT], svB[SPT];
+  f32x4 uy[UPT], sv[SPT];
   const int uitems = fm_rows * (GD_CB / 2);
   constexpr int sitems = NCT * 32 * (GD_CB / 2);  // rows past nct 32 are zero in the table
   const int nchunks = Kb / GD_CB;
@@ -1242,21 +1243,13 @@ __global__ __launch_bounds__(1024) void gcc_direct(const float2* __restrict__ Y,
       }
     }
   };
-  gload(0, uyA, svA);
-  if (1 < nchunks) gload(1, uyB, svB);
-  for (int c = 0; c < nchunks; c += 2) {
+  gload(0, uy, sv);
+  for (int c = 0; c < nchunks; ++c) {
     __syncthreads();  // the previous chunk's reads are done
-    lstore(uyA, svA);
+    lstore(uy, sv);
     __syncthreads();
-    if (c + 2 < nchunks) gload(c + 2, uyA, svA);
+    if (c + 1 < nchunks) gload(c + 1, uy, sv);
     multiply();
-    if (c + 1 < nchunks) {
-      __syncthreads();
-      lstore(uyB, svB);
-      __syncthreads();
-      if (c + 3 < nchunks) gload(c + 3, uyB, svB);
-      multiply();
-    }
   }
   // the other quarters' partial tiles through LDS (the u buffer is free now)
   __syncthreads();
