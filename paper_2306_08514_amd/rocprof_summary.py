@@ -36,8 +36,9 @@ COPY_BYTES = 2 ** 30  # bench.py --copy-calibration: 2^28 float32 per copy
 # short names of the hot-path kernels, matched on the (possibly mangled) name
 _TAGS = [
     (r"gemm_nt_f64", "gemm_fd_f64"),
-    # FD: FP32 128 x 128 tiles (also the LR fat stage), 16-bit / FP8 256 x 256;
+    # FD: FP32 128 x 128 tiles (also the LR fat stage), 16-bit / FP8 gemm_fd16;
     # the general tall GEMM: FP32 256 x 128, 16-bit / FP8 128 x 128
+    (r"gemm_fd16", "gemm_fd"),
     (r"gemm_nt<float, 128, 128|gemm_ntIfLi128ELi128E|gemm_nt<[^,]+, 256, 256|gemm_ntI[^L]*Li256ELi256E", "gemm_fd"),
     (r"gemm_nt", "gemm_tall"),
     (r"tall_ws<.*, true>|tall_wsI.*Lb1E", "sspi_dense"),

@@ -72,6 +72,9 @@ def test_kernel_tags():
     assert rs.tag("_ZN3srp11rows_to_f16EPKfliiiPDF16_l") == "xi_to_frames"
     assert rs.tag("void srp::lam_gemm_f64<true>(double const*, long)") == "lam_gemm_f64 (plan)"
     assert rs.tag("srp::split_reduce(float const*, int, long)") == "split_reduce"
+    assert rs.tag("_ZN3srp12_GLOBAL__N_19gemm_fd16IDF16bEEvPKT_lS4_lPfliiifiil") == "gemm_fd"
+    assert rs.tag("_ZN3srp8fd_gen16IDF16bLi256EEEvPKT_lPKdliiPfliifiiil") == "gemm_fd_gen"
+    assert rs.tag("void srp::gcc_direct<1, true>(HIP_vector_type<float, 2u> const*, int)") == "gcc_direct"
     tags = rs.unique_tags(["void srp::sspi_gather<__bf16, 3, 32, true>(float const*)",
                            "void srp::sspi_gather<__bf16, 5, 32, true>(float const*)", "srp::gcc_direct<1>(x)"])
     assert tags["srp::gcc_direct<1>(x)"] == "gcc_direct"
