@@ -2719,8 +2719,8 @@ size_t dsize(int dtype) {
 
 template <typename T>
 void launch_steering(const double* d_x, const HostPlan& hp, int Kp, int64_t Jpad, int64_t ldh, void* H) {
-  // the 16-bit and FP8 GEMM (gemm_fd16) reads the tile-major layout
-  const bool tiled = sizeof(T) <= 2;
+  // the FP32, 16-bit and FP8 GEMM (gemm_fd16) reads the tile-major layout
+  const bool tiled = sizeof(T) <= 4;
   if (tiled && ((ldh * static_cast<int64_t>(sizeof(T))) % FD16_SB != 0 || Jpad % FD16_TILE != 0))
     throw Error{SRP_E_UNSUPPORTED, "steering rows are not whole 64-byte stages of 256-row tiles"};
   dim3 grid(static_cast<unsigned>(Jpad), (hp.P * (Kp / 2) + 255) / 256);
@@ -2890,7 +2890,9 @@ __global__ __launch_bounds__(256) void gemm_fd16(const T* __restrict__ X, int64_
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        if constexpr (std::is_same<T, fp8>::value)
+        if constexpr (std::is_same<T, float>::value)
+          Mfma<float>::run(&fa[a], &fb[b], acc[a][b]);  // four 32x32x2 steps per 16-byte chunk
+        else if constexpr (std::is_same<T, fp8>::value)
           // E4M3 operands (format 0), E8M0 scales 127 = 2^0
           acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[a], fb[b], acc[a][b], 0, 0, 0, 127, 0, 127);
         else if constexpr (std::is_same<T, __bf16>::value)
@@ -3729,9 +3731,9 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     // contraction over blockIdx.z so that the GEMM has ~512 blocks per frame
     // tile; a plan constant, so a frame's map does not depend on its batch
     const bool f32 = hp.dtype == SRP_F32;
-    const int64_t nwt = dp.Jpad / (f32 ? BIG_BW : FD16_TILE);
+    const int64_t nwt = dp.Jpad / FD16_TILE;
     if (hp.dtype != SRP_F64 && nwt < 64) {
-      const int64_t slices = static_cast<int64_t>(P) * dp.Kp * static_cast<int64_t>(es) / (f32 ? 256 : 2 * FD16_SB);
+      const int64_t slices = static_cast<int64_t>(P) * dp.Kp * static_cast<int64_t>(es) / (2 * FD16_SB);
       int ks = 1;
       while (ks < 64 && nwt * ks * 2 <= 512 && slices % (ks * 2) == 0 && slices / (ks * 2) >= 16) ks *= 2;
       dp.fd_ksplit = ks;
@@ -4115,11 +4117,11 @@ void phat_dispatch(const HostPlan& hp, DevicePlan& dp, const void* frames, int64
                    void* out, int dtype, hipStream_t st) {
   const int64_t ld_l = fd_ld(hp, dp, dsize(dtype));
   const int kslots = dp.Kp / 2;
-  // the resident-steering 16-bit and FP8 GEMM (gemm_fd16) and the 16-bit
-  // generated-steering kernel for large batches (fd_gen16) read psi tile-major
-  const bool tiled = hp.variant == SRP_FD && dsize(dtype) <= 2 && (!dp.fd_gen || dsize(dtype) == 2);
+  // the resident-steering GEMM (gemm_fd16: FP32, 16-bit, FP8) and the 16-bit
+  // generated-steering kernel (fd_gen16) read psi tile-major
+  const bool tiled = hp.variant == SRP_FD && (dp.fd_gen ? dsize(dtype) == 2 : dsize(dtype) <= 4);
   switch (dtype) {
-    case SRP_F32: launch_phat<float, float>(hp, dp, frames, L, static_cast<float*>(out), ld_l, dp.Kp, kslots, st); break;
+    case SRP_F32: launch_phat<float, float>(hp, dp, frames, L, static_cast<float*>(out), ld_l, dp.Kp, kslots, st, tiled); break;
     case SRP_BF16: launch_phat<__bf16, float>(hp, dp, frames, L, static_cast<__bf16*>(out), ld_l, dp.Kp, kslots, st, tiled); break;
     case SRP_F16: launch_phat<_Float16, float>(hp, dp, frames, L, static_cast<_Float16*>(out), ld_l, dp.Kp, kslots, st, tiled); break;
     case SRP_FP8_E4M3: launch_phat<fp8, float>(hp, dp, frames, L, static_cast<fp8*>(out), ld_l, dp.Kp, kslots, st, tiled); break;
@@ -4148,10 +4150,7 @@ template <typename T>
 void launch_big_gemm(DevicePlan& dp, const char* kname, const void* X, int64_t ldx, const void* W, int64_t ldw,
                      float* C, int64_t ldc, int nx, int nw, int kdim, float alpha, int64_t Lpad,
                      hipStream_t st, int ksplit = 1, int64_t cz_rows = 0) {
-  if constexpr (std::is_same<T, float>::value)
-    launch_gemm<T, BIG_BX, BIG_BW, BIG_WGX, big_bkb<T>()>(dp, kname, X, ldx, W, ldw, C, ldc, nx, nw, kdim, alpha,
-                                                         Lpad, st, 0, ksplit, cz_rows);
-  else {
+  {
     // rows of X and W are read up to whole 256-row tiles (Lpad, Jpad rows
     // are allocated)
     // the kernel takes two 64-byte stages per iteration
