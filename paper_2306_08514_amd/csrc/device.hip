@@ -706,7 +706,7 @@ __global__ __launch_bounds__(256) void fd_gen16(const T* __restrict__ X, int64_t
                                                 int nw_tiles, int nx_tiles, int pps, int64_t cz_rows) {
   static_assert(sizeof(T) == 2, "16-bit operands");
   static_assert(BXF == 256 || BXF == 64, "256- or 64-frame tiles");
-  constexpr int STEP = Mfma<T>::STEP, LB = STEP / 2;
+  constexpr int STEP = Mfma<T>::STEP;
   // waves: 2 x 2 of 128 x 128 (256-frame tiles) or 1 x 4 of 64 x 64
   constexpr int WGY = BXF == 256 ? 2 : 1, WGX = 4 / WGY;
   constexpr int NA = BXF / WGY / 32, NB = FD16_TILE / WGX / 32;  // 32 x 32 blocks per wave
@@ -3092,7 +3092,6 @@ static void fit_slri_global_gram(HostPlan& hp, const double* dx);
 static void build_slri_global_operands(HostPlan& hp, DevicePlan& dp, Alloc& A, const double* dx);
 
 static void build_slri_global_device(HostPlan& hp, DevicePlan& dp, Alloc& A, const double* dx) {
-  const int PN = hp.PN, R = hp.R, P = hp.P;
   if (2 * hp.max_np + 1 > 576) throw Error{SRP_E_UNSUPPORTED, "global SLRI stages at most 576 lags per pair"};
   if (hp.global_rand)
     fit_slri_global_rand(hp, dx);
@@ -3730,7 +3729,6 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
     // few candidate tiles (small grids, long contractions): split the
     // contraction over blockIdx.z so that the GEMM has ~512 blocks per frame
     // tile; a plan constant, so a frame's map does not depend on its batch
-    const bool f32 = hp.dtype == SRP_F32;
     const int64_t nwt = dp.Jpad / FD16_TILE;
     if (hp.dtype != SRP_F64 && nwt < 64) {
       const int64_t slices = static_cast<int64_t>(P) * dp.Kp * static_cast<int64_t>(es) / (2 * FD16_SB);
