@@ -1403,7 +1403,9 @@ __global__ __launch_bounds__(512) void slri_fat_global_mfma(const float* __restr
 // ====================================================== SLRI tall stream ===
 //
 // z[l][j] = alpha * sum_c g[l][c] U[j][c] (the tall stage of eq. (57)) for the
-// 16-bit and FP8 operands with rows of at most 1 KB.  Warp-specialised
+// 16-bit and FP8 operands with rows of at most 1 KB (16-bit rows up to
+// 1280 bytes on four compute waves, whose registers then hold the longer U
+// rows).  Warp-specialised
 // streaming: one loader wave brings the g rows of the next groups of 32
 // frames straight into LDS (global_load_lds, no register round trip) up to
 // four groups ahead, as many as the load counter and LDS hold, while CW
@@ -1541,8 +1543,8 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
       for (int s = 0; s < NS; ++s) Mfma<T>::run(af[s], uf[s], acc);
     } else {
       // long rows: U alone takes 4 NS registers, so the g fragments are
-      // read CHK steps at a time
-      constexpr int CHK = NS / 2;
+      // read CHK steps at a time (a quarter of the row past 1 KB)
+      constexpr int CHK = NS * STEP > 1024 ? NS / 4 : NS / 2;
 #pragma unroll
       for (int s0 = 0; s0 < NS; s0 += CHK) {
         i32x4 af[CHK][NV];
@@ -3035,6 +3037,9 @@ constexpr int TALL_BX = 256, TALL_BW = 128, TALL_WGX = 2, TALL_BKB = 128; // SLR
 constexpr int TALL16_BX = 128, TALL16_BW = 128, TALL16_WGX = 2, TALL16_BKB = 256;
 constexpr int tall_bkb(int dtype) { return dtype == SRP_F32 ? TALL_BKB : TALL16_BKB; }
 constexpr int TALL_STEP_BYTES(int dtype) { return dtype == SRP_FP8_E4M3 ? 64 : 32; }  // Mfma<T>::STEP
+// longest 16-bit U row of the streaming tall kernel (rows past 1 KB run on
+// TALL_CW_LONG compute waves)
+constexpr int TALL_ROW_MAX16 = 1280;
 // Columns Kc of the tall operands for `raw` columns of data: a multiple of
 // four MFMA steps when the 16-bit / FP8 rows fit the streaming kernel (at
 // most 1 KB), else a whole K slice of the general GEMM that runs instead.
@@ -3042,11 +3047,12 @@ inline int tall_cols(int dtype, int64_t raw) {
   const int es = static_cast<int>(dsize(dtype));
   if (dtype != SRP_F32) {
     const int64_t ws = round_up(raw, 4 * TALL_STEP_BYTES(dtype) / es);
-    if (ws * es <= 1024) return static_cast<int>(ws);
+    if (ws * es <= (es == 2 ? TALL_ROW_MAX16 : 1024)) return static_cast<int>(ws);
   }
   return static_cast<int>(round_up(raw, tall_bkb(dtype) / es));
 }
-constexpr int TALL_CW = 8;  // compute waves per block of the tall kernel (256 candidates)
+constexpr int TALL_CW = 8;       // compute waves per block of the tall kernel (256 candidates)
+constexpr int TALL_CW_LONG = 4;  // the same for 16-bit rows of 1 KB to 1280 bytes (128 candidates)
 constexpr int SSPI_FT = 32;                       // frames per SSPI block
 
 }  // namespace
@@ -4278,17 +4284,19 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
                       int64_t ldc, int nx, int nw, int kdim, float alpha, int64_t Lpad, hipStream_t st,
                       const int32_t* ctab = nullptr, const int32_t* tlist = nullptr, int ntl = 0) {
   const int steps = kdim * static_cast<int>(sizeof(T)) / Mfma<T>::STEP;
-  // 16-bit and FP8 operands with rows of at most 1 KB: U rows in registers,
-  // g streamed through LDS by the loader wave; anything else takes the
-  // general MFMA GEMM
-  if (!std::is_same<T, float>::value && steps <= 32 && kdim * static_cast<int>(sizeof(T)) <= 1024) {
-    if (steps % 4 == 0 && 36 * ldc < (int64_t(1) << 31)) {
-      constexpr int CW = TALL_CW;
-      const int njt = tlist ? ntl : static_cast<int>((nw + 32 * CW - 1) / (32 * CW));
+  const int rowb = kdim * static_cast<int>(sizeof(T));
+  // 16-bit and FP8 operands with rows of at most 1 KB (16-bit: 1280 bytes,
+  // past 1 KB on four compute waves and without tile lists): U rows in
+  // registers, g streamed through LDS by the loader wave; anything else takes
+  // the general MFMA GEMM
+  const bool longrow = sizeof(T) == 2 && rowb > 1024 && rowb <= TALL_ROW_MAX16 && !ctab && !tlist;
+  if constexpr (!std::is_same<T, float>::value) {
+    if ((rowb <= 1024 || longrow) && steps % 4 == 0 && 36 * ldc < (int64_t(1) << 31)) {
       const int ngroups = (nx + 31) / 32;
-#define SRP_WS(NSV)                                                                                           \
+#define SRP_WS(NSV, CW)                                                                                       \
   case NSV:                                                                                                   \
-    if constexpr (NSV * Mfma<T>::STEP <= 1024) {                                                              \
+    if constexpr (NSV * Mfma<T>::STEP <= (sizeof(T) == 2 ? TALL_ROW_MAX16 : 1024)) {                          \
+    const int njt = tlist ? ntl : static_cast<int>((nw + 32 * CW - 1) / (32 * CW));                           \
     auto kern = ctab ? &tall_ws<T, NSV, CW, true> : &tall_ws<T, NSV, CW, false>;                              \
     int nsplit, gps;                                                                                          \
     tall_split(dp, reinterpret_cast<const void*>(kern), 64 * (CW + 1), njt, ngroups, nsplit, gps);            \
@@ -4300,9 +4308,17 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
     return;                                                                                                   \
     }                                                                                                         \
     break;
-      switch (steps) {
-        SRP_WS(4) SRP_WS(8) SRP_WS(12) SRP_WS(16) SRP_WS(20) SRP_WS(24) SRP_WS(28) SRP_WS(32)
-        default: break;
+      if (!longrow) {
+        switch (steps) {
+          SRP_WS(4, TALL_CW) SRP_WS(8, TALL_CW) SRP_WS(12, TALL_CW) SRP_WS(16, TALL_CW) SRP_WS(20, TALL_CW)
+          SRP_WS(24, TALL_CW) SRP_WS(28, TALL_CW) SRP_WS(32, TALL_CW)
+          default: break;
+        }
+      } else {
+        switch (steps) {
+          SRP_WS(36, TALL_CW_LONG) SRP_WS(40, TALL_CW_LONG)
+          default: break;
+        }
       }
 #undef SRP_WS
     }

@@ -145,6 +145,26 @@ def test_maps_ragged_room125k_geometry(native, room_small, variant, rq):
     _check_maps(z, _oracle_maps(variant, Y, cfg, rq), TOL["f32"], f"ragged {variant} {rq}")
 
 
+@pytest.mark.parametrize("rq", [19, 21])
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_slri_u_rows_past_1kb(native, room_small, rq, dtype):
+    """Per-pair SLRI whose 16-bit U rows pass 1 KB (28 pairs x R = 19 or 21
+    columns, padded to 576 or 640: 1152 or 1280 bytes), which the tall stage
+    streams on four compute waves per 128 candidates: every output against
+    the oracle, on a grid and a batch that are not tile multiples, and a
+    frame's map is bitwise the same alone or inside the batch."""
+    cfg, Y = room_small
+    _announce(f"slri long U rows R={rq} {dtype}")
+    p = _plan(native, cfg, "slri", rq, dtype)
+    Yt = torch.from_numpy(Y).cuda()
+    full = p.compute(Yt)
+    _check_maps(full.cpu().numpy(), _oracle_maps("slri", Y, cfg, rq), TOL[dtype], f"slri R={rq} {dtype}")
+    for a, b in ((0, 1), (5, 9), (32, 37)):
+        part = p.compute(Yt[a:b].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(full[a:b], part), (a, b)
+
+
 def test_full_rank_slri_and_dense_sspi_agree_on_gpu(native, room_small):
     """R_p = Q_p = 2 N_p + 1 for every pair (max lag count 31) reproduce SI."""
     cfg, Y = room_small
