@@ -1404,7 +1404,7 @@ __global__ __launch_bounds__(512) void slri_fat_global_mfma(const float* __restr
 //
 // z[l][j] = alpha * sum_c g[l][c] U[j][c] (the tall stage of eq. (57)) for the
 // 16-bit and FP8 operands with rows of at most 1 KB (16-bit rows up to
-// 1280 bytes on four compute waves, whose registers then hold the longer U
+// 1280 bytes on six compute waves, whose registers then hold the longer U
 // rows).  Warp-specialised
 // streaming: one loader wave brings the g rows of the next groups of 32
 // frames straight into LDS (global_load_lds, no register round trip) up to
@@ -2781,8 +2781,8 @@ void upload(void* dst, const std::vector<T>& v) {
 }
 
 // tile shapes of the launch configurations
-// 16-bit and FP8 FD GEMM, C = alpha X W^T (X: cross-spectra rows, W: steering
-// rows, both tile-major as fd16_tiled lays them out): 256 x 256 tiles, 2 x 2 waves of 4 x 4 MFMA
+// FD GEMM (FP32, 16-bit and FP8), C = alpha X W^T (X: cross-spectra rows, W:
+// steering rows, both tile-major as fd16_tiled lays them out): 256 x 256 tiles, 2 x 2 waves of 4 x 4 MFMA
 // blocks (accumulators in AccVGPRs, one block per CU).  K streams in 64-byte
 // stages straight into a ring of NBUF LDS stage buffers (global_load_lds, no
 // register staging), each refilled as soon as the barrier after its last
@@ -2995,28 +2995,24 @@ __global__ __launch_bounds__(256) void gemm_fd16(const T* __restrict__ X, int64_
     }
 }
 
-// FD GEMM: 128 frames x 128 candidates per block, 2 x 2 waves, 256-byte K
-// slices (128 bytes for FP8, whose rows are only a multiple of 128 bytes).
-// Measured against 256 x 128 tiles with 128-byte slices: 55.0 vs 58.6 ms at
-// 125,000 candidates and 1000 frames (fewer barriers per MAC, two blocks
-// per CU, and twice the blocks for the last partial round of the grid).
-// The price is L2 reuse: 12 % of the reads hit L2 against 82 % with
-// 256-frame tiles, so the kernel reads ~200 GB from HBM per 1000 maps
-// instead of ~31 GB (3.7 TB/s, under half the HBM peak; the kernel stays
-// MFMA-bound).  Block order (row-major, frame-major, XCD-grouped) and row
-// padding did not restore it.
+// General FP32 GEMM tile (the LR-SRP fat product): 128 x 128 per block,
+// 2 x 2 waves, 256-byte K slices (128 bytes for FP8).  As the FP32 FD GEMM it
+// beat 256 x 128 tiles with 128-byte slices (55.0 vs 58.6 ms at 125,000
+// candidates and 1000 frames) but hit L2 on 12 % of reads and fetched ~200 GB
+// per 1000 maps; gemm_fd16's tile-major 256 x 256 tiles replaced it there
+// (52.5 ms, 23.8 GB).
 constexpr int BIG_BX = 128, BIG_BW = 128, BIG_WGX = 2;
 template <typename T>
 constexpr int big_bkb() {
   return sizeof(T) == 1 ? 128 : 256;
 }
-// 16-bit and FP8 FD run gemm_fd16 (256 x 256 tiles).  At their MFMA rates
+// FD runs gemm_fd16 (256 x 256 tiles) in FP32, 16-bit and FP8.  At 16-bit and FP8 MFMA rates
 // 2 x 2 blocks of 32 x 32 per wave read ~16 MACs per byte of LDS fragments,
 // which saturates LDS; 4 x 4 blocks per wave (accumulators in AccVGPRs)
 // halve that.  Measured at 125,000 x 1000 x 28,672, BF16 / FP8 ms per call:
 // 128 x 128 tiles 11.2 / 5.0; 256 x 256 with register-staged K slices
 // 8.1 / 3.9; direct-to-LDS stage ring with pipelined MFMA steps 7.4 / 3.75;
-// tile-major operands 6.1 / 3.2.
+// tile-major operands 6.1 / 3.2; FP32 55.0 (128 x 128 row-major tiles) -> 52.5.
 // candidate rows of the resident operands are padded to the widest W tile
 constexpr int JPAD_ROWS = 256;
 // workspace frame rows are padded to whole 256-frame tiles, the largest
@@ -3052,7 +3048,11 @@ inline int tall_cols(int dtype, int64_t raw) {
   return static_cast<int>(round_up(raw, tall_bkb(dtype) / es));
 }
 constexpr int TALL_CW = 8;       // compute waves per block of the tall kernel (256 candidates)
-constexpr int TALL_CW_LONG = 4;  // the same for 16-bit rows of 1 KB to 1280 bytes (128 candidates)
+// the same for 16-bit rows of 1 KB to 1280 bytes (192 candidates; two waves
+// per SIMD, each with 256 registers for its U rows).  Measured on per-pair
+// SLRI R = 21 at 125,000 candidates x 1000 frames: 4 / 6 / 7 compute waves
+// 0.304 / 0.279 / 0.288 ms per call (each g row feeds more candidates)
+constexpr int TALL_CW_LONG = 6;
 constexpr int SSPI_FT = 32;                       // frames per SSPI block
 
 }  // namespace
@@ -4286,7 +4286,7 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
   const int steps = kdim * static_cast<int>(sizeof(T)) / Mfma<T>::STEP;
   const int rowb = kdim * static_cast<int>(sizeof(T));
   // 16-bit and FP8 operands with rows of at most 1 KB (16-bit: 1280 bytes,
-  // past 1 KB on four compute waves and without tile lists): U rows in
+  // past 1 KB on six compute waves and without tile lists): U rows in
   // registers, g streamed through LDS by the loader wave; anything else takes
   // the general MFMA GEMM
   const bool longrow = sizeof(T) == 2 && rowb > 1024 && rowb <= TALL_ROW_MAX16 && !ctab && !tlist;
