@@ -1402,8 +1402,8 @@ __global__ __launch_bounds__(512) void slri_fat_global_mfma(const float* __restr
 
 // ====================================================== SLRI tall stream ===
 //
-// z[l][j] = alpha * sum_c g[l][c] U[j][c] (the tall stage of eq. (57)) for the
-// 16-bit and FP8 operands with rows of at most 1 KB (16-bit rows up to
+// z[l][j] = alpha * sum_c g[l][c] U[j][c] (the tall stage of eq. (57)) for
+// FP32, 16-bit and FP8 operands with rows of at most 1 KB (16-bit rows up to
 // 1280 bytes on six compute waves, whose registers then hold the longer U
 // rows).  Warp-specialised
 // streaming: one loader wave brings the g rows of the next groups of 32
@@ -4285,12 +4285,14 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
                       const int32_t* ctab = nullptr, const int32_t* tlist = nullptr, int ntl = 0) {
   const int steps = kdim * static_cast<int>(sizeof(T)) / Mfma<T>::STEP;
   const int rowb = kdim * static_cast<int>(sizeof(T));
-  // 16-bit and FP8 operands with rows of at most 1 KB (16-bit: 1280 bytes,
-  // past 1 KB on six compute waves and without tile lists): U rows in
-  // registers, g streamed through LDS by the loader wave; anything else takes
-  // the general MFMA GEMM
+  // rows of at most 1 KB (16-bit: 1280 bytes, past 1 KB on six compute waves
+  // and without tile lists): U rows in registers, g streamed through LDS by
+  // the loader wave; anything else takes the general MFMA GEMM.  FP32 rows
+  // run on v_mfma_f32_32x32x2f32 with the same sums as the general GEMM
+  // (maps bitwise equal; per-pair SLRI R = 8 at 125,000 x 1000: 0.633 ->
+  // 0.561 ms per call)
   const bool longrow = sizeof(T) == 2 && rowb > 1024 && rowb <= TALL_ROW_MAX16 && !ctab && !tlist;
-  if constexpr (!std::is_same<T, float>::value) {
+  {
     if ((rowb <= 1024 || longrow) && steps % 4 == 0 && 36 * ldc < (int64_t(1) << 31)) {
       const int ngroups = (nx + 31) / 32;
 #define SRP_WS(NSV, CW)                                                                                       \
