@@ -382,18 +382,18 @@ def test_batch_invariance_and_workspace(native, room_small):
     cfg, Y = room_small
     _announce("batch invariance")
     Yt = torch.from_numpy(Y).cuda()
-    for variant, rq in (("fd", 0), ("slri", 8), ("sspi", 4)):
-        p = _plan(native, cfg, variant, rq, "bf16" if variant != "fd" else "f32")
+    for variant, rq, dt in (("fd", 0, "f32"), ("slri", 8, "bf16"), ("slri", 8, "f32"), ("sspi", 4, "bf16")):
+        p = _plan(native, cfg, variant, rq, dt)
         full = p.compute(Yt)
         part = p.compute(Yt[5:9].contiguous())
         torch.cuda.synchronize()
-        assert torch.equal(full[5:9], part), variant
+        assert torch.equal(full[5:9], part), (variant, dt)
         ws = torch.empty(p.workspace_size(Y.shape[0]), dtype=torch.uint8, device="cuda")
         s = torch.cuda.Stream()
         with torch.cuda.stream(s):
             again = p.compute(Yt, workspace=ws, stream=s)
         s.synchronize()
-        assert torch.equal(full, again), variant
+        assert torch.equal(full, again), (variant, dt)
 
 
 def test_map_row_pitch(native, room_small):
