@@ -3714,13 +3714,15 @@ void device_build(HostPlan& hp, DevicePlan& dp, int64_t frame_tile, size_t budge
       while (ks < 8 && nwt * ks * 2 <= 512 && P / (ks * 2) >= 4) ks *= 2;
       if (ks == 1) {
         // many tiles: balance the last round of the one-block-per-CU launch
-        // (fd_gen16) by up to 4 splits of at least 4 pairs (2 m disc: 782
-        // tiles in 4 rounds, 3.06 of work; 4 splits: 13 rounds of a quarter)
+        // (fd_gen16) by up to 8 splits of at least 4 pairs (2 m disc: 782
+        // tiles in 4 rounds, 3.06 of work; 4 splits: 13 rounds of a quarter,
+        // 96.4 ms per 256 frames; 8 splits: 25 rounds of an eighth, 93.1 ms
+        // with the larger partial sums)
         int cus = 0;
         HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dp.device));
         cus = std::max(cus, 1);
         double best = std::ceil(static_cast<double>(nwt) / cus);
-        for (int k = 2; k <= 4 && P / k >= 4; ++k) {
+        for (int k = 2; k <= 8 && P / k >= 4; ++k) {
           const double cost = std::ceil(static_cast<double>(nwt) * k / cus) / k;
           if (cost < 0.99 * best) {
             best = cost;
