@@ -2,12 +2,14 @@
 //
 // Hot path per frame tile (one map per STFT frame):
 //   phat_kernel      PHAT-weighted cross-spectra psi_p[l, k] (FD)      eq. (2)
-//   gemm_nt (FD)     z = 2 Re[H psi] as a real MFMA GEMM              eq. (22)
+//   gemm_fd16        z = 2 Re[H psi] as a real MFMA GEMM (resident H)  eq. (22)
+//   fd_gen16, fd_gen the same with H generated in LDS from the TDOAs    eqs. (19), (22)
 //   gcc_direct       PHAT + xi_p = 2 Re[S_p psi_p]                      eqs. (2), (40)
 //   gcc_fft          PHAT + xi_p by the iFFT                            eq. (46)
 //   slri_fat_mfma    g_p = V_p^T xi_p (global fit: slri_fat_global_mfma) eq. (57)
 //   tall_ws          z = sum_p U_p g_p                                  eq. (57)
 //   sspi_gather      z = sum_p sum_q w[j,p,q] xi_p[s(j,p) + q]          eq. (58)
+//                    (dense-window tiles: tall_ws; large apertures: sspi_band)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -160,7 +162,7 @@ __device__ inline void wait_vm_lds() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
 }
 
-// Tiles of the 16-bit and FP8 FD GEMM: 256 x 256 outputs, K in 64-byte
+// Tiles of the FD GEMM (FP32, 16-bit, FP8): 256 x 256 outputs, K in 64-byte
 // stages (see gemm_fd16).
 constexpr int FD16_TILE = 256, FD16_SB = 64, FD16_NBUF = 5;
 constexpr int FD16_STAGE = 2 * FD16_TILE * FD16_SB;  // 32 KB
@@ -170,8 +172,8 @@ constexpr int FD16_NI = FD16_STAGE / 1024 / 4;       // loads per wave per stage
 // position c ^ fd16_swz(r mod 16).
 __host__ __device__ inline int fd16_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 
-// Byte offset of byte kb of row j in the tile-major steering operand of the
-// 16-bit and FP8 FD GEMM: [j / 256][kb / 64][j mod 256][64 bytes], each
+// Byte offset of byte kb of row j in the tile-major operands of the FD GEMM
+// (FP32, 16-bit, FP8): [j / 256][kb / 64][j mod 256][64 bytes], each
 // 64-byte row piece swizzled by fd16_swz, so that one stage of a 256-row
 // tile is 16 KB in the order the GEMM's LDS stage holds it.  rb = bytes per
 // row (a multiple of 64).
@@ -188,7 +190,8 @@ __host__ __device__ inline int64_t fd16_tiled(int64_t j, int64_t kb, int64_t rb)
 // then psi_p = u_m conj(u_m') for every pair, which equals
 // y_m y_m'^* / |y_m y_m'^*| of eq. (2), and 0 where either bin is 0.
 // Output layout: out[l * ld_l + p * ld_p + 2 * slot + {re, im}], or that
-// row-major operand tile-major (fd16_tiled) for the 16-bit and FP8 FD GEMM;
+// row-major operand tile-major (fd16_tiled) for the FD GEMM (FP32, 16-bit,
+// FP8) and the 16-bit generated-steering kernel;
 // slots in [K-1, kslots) are written as zeros (row padding).
 
 template <typename TO, typename TC>
@@ -2638,7 +2641,7 @@ __global__ __launch_bounds__(256) void sspi_windows(const double* __restrict__ x
 
 // Steering operand of conv. FD-SRP: H[j * ldh + p Kp + 2 (k-1) + {0,1}] =
 // (cos theta, -sin theta), theta = pi k x_p(j) / K (eq. (19) with (14)),
-// row-major, or tile-major (fd16_tiled) for the 16-bit and FP8 GEMM.  The
+// row-major, or tile-major (fd16_tiled) for the FD GEMM (FP32, 16-bit, FP8).  The
 // phase is reduced in FP64: theta = 2 pi (t - rint(t)), t = k x / (2K), and
 // sin/cos come from the FP64 sincospi.  Rows j >= J and slots k >= K are 0.
 template <typename T>
@@ -3025,11 +3028,12 @@ constexpr int FD_ROW_PAD_BYTES = 0;
 inline int64_t fd_ld(const HostPlan& hp, const DevicePlan& dp, size_t es) {
   return static_cast<int64_t>(hp.P) * dp.Kp + FD_ROW_PAD_BYTES / static_cast<int64_t>(es);
 }
-constexpr int TALL_BX = 256, TALL_BW = 128, TALL_WGX = 2, TALL_BKB = 128; // SLRI tall (FP32)
-// general tall GEMM for 16-bit and FP8 operands whose rows exceed the
-// streaming kernel's 1 KB (2 m disc: 3968 columns; SI): 128 x 128 tiles with
-// 256-byte slices, 0.53 against 0.67 ms on the 2 m disc (FP32 kept the
-// 256 x 128 / 128-byte tile, which was 6 % faster there)
+// general tall GEMM for FP32 rows past the streaming kernel's 1 KB
+constexpr int TALL_BX = 256, TALL_BW = 128, TALL_WGX = 2, TALL_BKB = 128;
+// the same for 16-bit and FP8 rows past the streaming kernel's limit (2 m
+// disc: 3968 columns; SI): 128 x 128 tiles with 256-byte slices, 0.53
+// against 0.67 ms on the 2 m disc (FP32 kept the 256 x 128 / 128-byte tile,
+// which was 6 % faster there)
 constexpr int TALL16_BX = 128, TALL16_BW = 128, TALL16_WGX = 2, TALL16_BKB = 256;
 constexpr int tall_bkb(int dtype) { return dtype == SRP_F32 ? TALL_BKB : TALL16_BKB; }
 constexpr int TALL_STEP_BYTES(int dtype) { return dtype == SRP_FP8_E4M3 ? 64 : 32; }  // Mfma<T>::STEP
@@ -4297,11 +4301,11 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
   {
     if ((rowb <= 1024 || longrow) && steps % 4 == 0 && 36 * ldc < (int64_t(1) << 31)) {
       const int ngroups = (nx + 31) / 32;
-#define SRP_WS(NSV, CW)                                                                                       \
+#define SRP_WS(NSV, CW, CT)                                                                                   \
   case NSV:                                                                                                   \
     if constexpr (NSV * Mfma<T>::STEP <= (sizeof(T) == 2 ? TALL_ROW_MAX16 : 1024)) {                          \
     const int njt = tlist ? ntl : static_cast<int>((nw + 32 * CW - 1) / (32 * CW));                           \
-    auto kern = ctab ? &tall_ws<T, NSV, CW, true> : &tall_ws<T, NSV, CW, false>;                              \
+    auto kern = ctab ? &tall_ws<T, NSV, CW, CT> : &tall_ws<T, NSV, CW, false>;                                \
     int nsplit, gps;                                                                                          \
     tall_split(dp, reinterpret_cast<const void*>(kern), 64 * (CW + 1), njt, ngroups, nsplit, gps);            \
     const unsigned blocks = static_cast<unsigned>(round_up(static_cast<int64_t>(njt) * nsplit, 8));          \
@@ -4312,15 +4316,18 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
     return;                                                                                                   \
     }                                                                                                         \
     break;
+      // chunk tables (dense-window SSPI) come with 16-bit operands only
+      constexpr bool CT = !std::is_same<T, float>::value;
       if (!longrow) {
         switch (steps) {
-          SRP_WS(4, TALL_CW) SRP_WS(8, TALL_CW) SRP_WS(12, TALL_CW) SRP_WS(16, TALL_CW) SRP_WS(20, TALL_CW)
-          SRP_WS(24, TALL_CW) SRP_WS(28, TALL_CW) SRP_WS(32, TALL_CW)
+          SRP_WS(4, TALL_CW, CT) SRP_WS(8, TALL_CW, CT) SRP_WS(12, TALL_CW, CT) SRP_WS(16, TALL_CW, CT)
+          SRP_WS(20, TALL_CW, CT) SRP_WS(24, TALL_CW, CT) SRP_WS(28, TALL_CW, CT) SRP_WS(32, TALL_CW, CT)
           default: break;
         }
       } else {
         switch (steps) {
-          SRP_WS(36, TALL_CW_LONG) SRP_WS(40, TALL_CW_LONG)
+          // never with a chunk table (longrow excludes it)
+          SRP_WS(36, TALL_CW_LONG, false) SRP_WS(40, TALL_CW_LONG, false)
           default: break;
         }
       }
