@@ -5,6 +5,7 @@ the SRP hot path, and the HBM-traffic record the benchmark reads back.
     python -m paper_2306_08514_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR TITLE CMD... > out.md
 
     python -m paper_2306_08514_amd.rocprof_summary counters TITLE DIR... -- CMD... > out.md
+    python -m paper_2306_08514_amd.rocprof_summary clock DIR TITLE CMD... > out.md
 
 `trace` turns a `--kernel-trace --stats` run into a table of per-kernel
 calls and durations.  `counters` tabulates the per-dispatch medians of
@@ -291,6 +292,66 @@ def _md_counters(title, dirs, cmd):
     return "\n".join(lines) + "\n"
 
 
+def clocks(d):
+    """{kernel name: [(span ns, clock GHz) per dispatch]} from a `--pmc
+    GRBM_GUI_ACTIVE` run: the counter, summed over the XCDs, divided by the
+    XCD count and by the dispatch's span gives the clock it ran at."""
+    per = {}
+    for path in _find(d, "counter_collection.csv"):
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != "GRBM_GUI_ACTIVE":
+                    continue
+                key = (r["Kernel_Name"], r.get("Dispatch_Id") or r.get("Correlation_Id"))
+                span = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+                prev = per.get(key, (0.0, span))
+                per[key] = (prev[0] + float(r["Counter_Value"]), span)
+    out = {}
+    for (name, _), (cyc, span) in per.items():
+        if span > 0:
+            out.setdefault(name, []).append((span, cyc / XCDS / span))
+    return out
+
+
+_MANGLED_TYPES = {"DF16b": "bf16", "DF16_": "f16", "f": "f32", "d": "f64", "NS_3fp8E": "fp8"}
+_DEMANGLED_TYPES = {"__bf16": "bf16", "_Float16": "f16", "float": "f32", "double": "f64", "srp::fp8": "fp8"}
+
+
+def _dtype(name):
+    """Operand type of a kernel template instance (first template argument),
+    '' when it has none."""
+    m = re.search(r"<([^,<>()]*)[,>]", name)
+    if m and m.group(1).strip() in _DEMANGLED_TYPES:
+        return _DEMANGLED_TYPES[m.group(1).strip()]
+    m = re.search(r"\d[a-z_0-9]+I(DF16b|DF16_|NS_3fp8E|f|d)", name)
+    return _MANGLED_TYPES.get(m.group(1), "") if m else ""
+
+
+def _md_clock(d, title, cmd, min_us=100.0):
+    rows = []
+    for name, vs in clocks(d).items():
+        vs = [v for v in vs if v[0] >= min_us * 1e3]
+        if not vs:
+            continue
+        ghz = sorted(v[1] for v in vs)
+        rows.append((tag(name), name, len(vs), statistics.median(v[0] for v in vs) / 1e6, statistics.median(ghz),
+                     ghz[0], ghz[-1]))
+    rows.sort(key=lambda r: -r[3])
+    lines = [f"# {title}", "", "Command (repository root; rocprofv3 from /tmp with TMPDIR=/tmp):", "",
+             "```", cmd, "python -m paper_2306_08514_amd.rocprof_summary clock <dir> ...", "```", "",
+             f"Kernel source SHA-256: `{source_sha256()}`", "",
+             f"Clock of a dispatch = GRBM_GUI_ACTIVE (summed over the {XCDS} XCDs) / {XCDS} / the dispatch's span; "
+             f"dispatches of at least {min_us:.0f} us.", "",
+             "| kernel | dispatches | median ms | median GHz | min GHz | max GHz | full name |",
+             "|---|---:|---:|---:|---:|---:|---|"]
+    for tg, name, n, ms, med, lo, hi in rows:
+        if tg == "torch (bench checks)":
+            continue
+        label = f"{tg} ({_dtype(name)})" if _dtype(name) else tg
+        lines.append(f"| {label} | {n} | {ms:.3f} | {med:.2f} | {lo:.2f} | {hi:.2f} | `{name[:90]}` |")
+    return "\n".join(lines) + "\n"
+
+
 def read_traffic_record(md_path):
     """The JSON record embedded in a traffic summary, or None."""
     try:
@@ -306,6 +367,8 @@ def main(argv):
         sys.stdout.write(_md_trace(argv[1], argv[2], " ".join(argv[3:])))
     elif len(argv) >= 4 and argv[0] == "traffic":
         sys.stdout.write(_md_traffic(argv[1], argv[2], argv[3], " ".join(argv[4:])))
+    elif len(argv) >= 3 and argv[0] == "clock":
+        sys.stdout.write(_md_clock(argv[1], argv[2], " ".join(argv[3:])))
     elif len(argv) >= 4 and argv[0] == "counters" and "--" in argv:
         i = argv.index("--")
         sys.stdout.write(_md_counters(argv[1], argv[2:i], " ".join(argv[i + 1:])))

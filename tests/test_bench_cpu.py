@@ -30,6 +30,29 @@ def _write_counters(d, counter, rows):
             w.writerow({"Kernel_Name": name, "Dispatch_Id": disp, "Counter_Name": counter, "Counter_Value": val})
 
 
+def test_clock_is_the_xcd_mean_cycle_count_over_the_dispatch_span(tmp_path):
+    """GRBM_GUI_ACTIVE is summed over the 8 XCDs (per-instance records of one
+    dispatch add up); divided by 8 and by the dispatch's span it gives the
+    clock: 8 x 2.4e6 cycles over 1 ms is 2.4 GHz."""
+    d = tmp_path / "clk"
+    os.makedirs(d)
+    fd = "_ZN3srp12_GLOBAL__N_19gemm_fd16IDF16bEEvPKT_lS4_lPfliiifiil"
+    with open(d / "pmc_counter_collection.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Dispatch_Id", "Counter_Name", "Counter_Value",
+                                          "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for disp, t0, cyc in ((1, 0, 4 * 2.4e6), (1, 0, 4 * 2.4e6), (2, 5_000_000, 8 * 1.8e6)):
+            w.writerow({"Kernel_Name": fd, "Dispatch_Id": disp, "Counter_Name": "GRBM_GUI_ACTIVE",
+                        "Counter_Value": cyc, "Start_Timestamp": t0, "End_Timestamp": t0 + 1_000_000})
+    c = rs.clocks(str(d))[fd]
+    assert sorted(round(g, 6) for _, g in c) == [1.8, 2.4]
+    assert rs._dtype(fd) == "bf16"
+    assert rs._dtype("void srp::(anonymous namespace)::gemm_fd16<float>(float const*, long)") == "f32"
+    assert rs._dtype("void srp::gemm_fd16<srp::fp8>(srp::fp8 const*)") == "fp8"
+    md = rs._md_clock(str(d), "t", "cmd")
+    assert "| gemm_fd (bf16) | 2 | 1.000 | 2.10 | 1.80 | 2.40 |" in md
+
+
 def test_traffic_is_calibrated_by_the_copy_and_summed_over_instances(tmp_path):
     """A 1 GiB copy that reads 2^19 FETCH units and writes 2^20 WRITE units
     fixes 2048 B and 1024 B per unit; a kernel's per-dispatch value is the
