@@ -1546,17 +1546,20 @@ __global__ __launch_bounds__(64 * (CW + 1)) void tall_ws(const T* __restrict__ g
       for (int s = 0; s < NS; ++s) Mfma<T>::run(af[s], uf[s], acc);
     } else {
       // long rows: U alone takes 4 NS registers, so the g fragments are
-      // read CHK steps at a time (a quarter of the row past 1 KB)
-      constexpr int CHK = NS * STEP > 1024 ? NS / 4 : NS / 2;
+      // read CHK steps at a time (a quarter of the row past 1 KB, whose step
+      // count is even but need not divide by four)
+      constexpr int CHK = NS * STEP > 1024 ? (NS + 3) / 4 : NS / 2;
 #pragma unroll
       for (int s0 = 0; s0 < NS; s0 += CHK) {
         i32x4 af[CHK][NV];
 #pragma unroll
         for (int s = 0; s < CHK; ++s)
+          if (s0 + s < NS)
 #pragma unroll
-          for (int v = 0; v < NV; ++v) af[s][v] = *reinterpret_cast<const i32x4*>(ar + (s0 + s) * STEP + 16 * v);
+            for (int v = 0; v < NV; ++v) af[s][v] = *reinterpret_cast<const i32x4*>(ar + (s0 + s) * STEP + 16 * v);
 #pragma unroll
-        for (int s = 0; s < CHK; ++s) Mfma<T>::run(af[s], uf[s0 + s], acc);
+        for (int s = 0; s < CHK; ++s)
+          if (s0 + s < NS) Mfma<T>::run(af[s], uf[s0 + s], acc);
       }
     }
     // rows (frames) 8 (v / 4) + 4 gq + v % 4 of the group, column j0 + r32:
@@ -3047,7 +3050,11 @@ inline int tall_cols(int dtype, int64_t raw) {
   const int es = static_cast<int>(dsize(dtype));
   if (dtype != SRP_F32) {
     const int64_t ws = round_up(raw, 4 * TALL_STEP_BYTES(dtype) / es);
-    if (ws * es <= (es == 2 ? TALL_ROW_MAX16 : 1024)) return static_cast<int>(ws);
+    if (ws * es <= 1024) return static_cast<int>(ws);
+    // 16-bit rows past 1 KB: pairs of MFMA steps (32 columns, the global fat
+    // stage's tile; the long-row kernel takes 34 to 40 steps)
+    const int64_t wl = round_up(raw, 2 * TALL_STEP_BYTES(dtype) / es);
+    if (es == 2 && wl * es <= TALL_ROW_MAX16) return static_cast<int>(wl);
   }
   return static_cast<int>(round_up(raw, tall_bkb(dtype) / es));
 }
@@ -4299,7 +4306,8 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
   // 0.561 ms per call)
   const bool longrow = sizeof(T) == 2 && rowb > 1024 && rowb <= TALL_ROW_MAX16 && !ctab && !tlist;
   {
-    if ((rowb <= 1024 || longrow) && steps % 4 == 0 && 36 * ldc < (int64_t(1) << 31)) {
+    if ((rowb <= 1024 || longrow) && (steps % 4 == 0 || (longrow && steps % 2 == 0)) && rowb % Mfma<T>::STEP == 0 &&
+        36 * ldc < (int64_t(1) << 31)) {
       const int ngroups = (nx + 31) / 32;
 #define SRP_WS(NSV, CW, CT)                                                                                   \
   case NSV:                                                                                                   \
@@ -4327,7 +4335,8 @@ void launch_tall_gemm(DevicePlan& dp, const void* X, int64_t ldx, const void* W,
       } else {
         switch (steps) {
           // never with a chunk table (longrow excludes it)
-          SRP_WS(36, TALL_CW_LONG, false) SRP_WS(40, TALL_CW_LONG, false)
+          SRP_WS(34, TALL_CW_LONG, false) SRP_WS(36, TALL_CW_LONG, false) SRP_WS(38, TALL_CW_LONG, false)
+          SRP_WS(40, TALL_CW_LONG, false)
           default: break;
         }
       }

@@ -149,7 +149,8 @@ def test_maps_ragged_room125k_geometry(native, room_small, variant, rq):
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
 def test_slri_u_rows_past_1kb(native, room_small, rq, dtype):
     """Per-pair SLRI whose 16-bit U rows pass 1 KB (28 pairs x R = 19 or 21
-    columns, padded to 576 or 640: 1152 or 1280 bytes), which the tall stage
+    columns, padded to 544 or 608: 1088 or 1216 bytes, 34 or 38 MFMA steps,
+    neither a multiple of four), which the tall stage
     streams on six compute waves per 192 candidates: every output against
     the oracle, on a grid and a batch that are not tile multiples, and a
     frame's map is bitwise the same alone or inside the batch."""
